@@ -1,0 +1,153 @@
+"""Throughput of the natively periodic FMM on one MI355X.
+
+Workload: N = 256 periodic mesh, uniform tree of depth L = 4 (16^3-cell
+leaves), p = 8 gridlet points per axis (512 effective masses per node), G_S1
+(Eq. 9); density = lognormal field exp(delta) - mean with delta a Gaussian
+random field of spectrum P(k) ~ k^-1.5 and sigma_delta = 2 (seed 5),
+synthetic.  One step = one pfmm_solve (every stage of the method: P2M, M2M,
+the interaction zones of levels 2..4, L2L, L2P and the near zone) with the
+density already resident in HBM.
+
+Prints one JSON line: cells/s (N^3 / time per solve), the roofline of the
+dominant kernel (the near zone) from HIP events recorded on the plan's stream
+around each stage during the timed steps, the interaction-zone (M2L) share,
+and the CPU FP64 oracle timed on a bounded sample of the same workload
+(which also checks the GPU potential: sampled cells against the reference
+FMM, the full mesh against PM with the same G).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, L, P, GREEN = 256, 4, 8, "S1"
+ALPHA, SIGMA, SEED = 1.5, 2.0, 5
+METRIC = "cells/s at 256^3 p=8 periodic FMM, L2 err<=1e-4 vs PM; M2L MFMA util"
+
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
+
+
+def algorithmic_flops(N, L, p):
+    """Flops of the two contraction steps in their block form (one multiply
+    and one add per kernel entry and source point)."""
+    s = N >> L
+    near = 27 * 2.0 * s ** 6 * 8 ** L
+    m2l = 37 * 2.0 * p ** 6 * 64 + sum(189 * 2.0 * p ** 6 * 8 ** l for l in range(3, L + 1))
+    return near, m2l
+
+
+def cpu_baseline(rho64, phi_gpu, n_side=8):
+    """The CPU FP64 oracle (reference FMM, NumPy) on the 8^3 lattice of cells
+    i_k = k N/8 + N/16 + 1, timed; the same targets check the GPU result, and
+    PM with the same G checks the full mesh."""
+    from oracle import conv, fmm as ofmm
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    k = np.arange(n_side) * (N // n_side) + N // (2 * n_side) + 1
+    tg = np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3)
+    t0 = time.perf_counter()
+    ref = ofmm.fmm(rho64, L, P, GREEN, targets=tg)
+    dt = time.perf_counter() - t0
+    got = phi_gpu[tg[:, 0], tg[:, 1], tg[:, 2]]
+    sampled = float(np.max(np.abs(got - ref)) / np.max(np.abs(phi_gpu)))
+    pm = conv.pm(rho64, GREEN)
+    a = phi_gpu - phi_gpu.mean()
+    b = pm - pm.mean()
+    acc = {
+        "sampled_max_err_vs_fp64_fmm": sampled,
+        "l2_rel_vs_pm": float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2))),
+        "lmax_rel_vs_pm": float(np.max(np.abs(a - b)) / np.max(np.abs(b))),
+    }
+    base = {"value": len(tg) / dt, "unit": "cells/s", "cores": int(cores), "kind": "oracle",
+            "sample": "reference FMM (oracle/fmm.py, FP64 NumPy) at %d cells (8^3 lattice) of "
+                      "the same 256^3 field, including its full upward pass and coarse levels; "
+                      "%.1f s" % (len(tg), dt)}
+    return base, acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); a multi-GPU "
+              "sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2011_07099_amd import fields
+    from paper_2011_07099_amd.pfmm import Plan
+
+    rho64 = fields.lognormal(N, ALPHA, SIGMA, seed=SEED)
+    rho32 = rho64.astype(np.float32)
+    dev = torch.device("cuda:0")
+    rho = torch.from_numpy(rho32).to(dev)
+    phi = torch.empty_like(rho)
+    stream = torch.cuda.current_stream(dev)
+    plan = Plan(N, L, P, GREEN, precision=args.precision, stream=stream)
+    for _ in range(args.warmup):
+        plan.solve(rho, phi)
+    plan.set_profile(True)
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record(stream)
+    for _ in range(args.steps):
+        plan.solve(rho, phi)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end) / args.steps
+    stages = plan.stage_times()
+    plan.close()
+
+    near_flops, m2l_flops = algorithmic_flops(N, L, P)
+    peak = PEAK_TFLOPS[args.precision]
+    near_ms = stages["near"][0]
+    m2l_ms = stages["m2l"][0]
+    near_tf = near_flops / (near_ms * 1e-3) / 1e12
+    m2l_tf = m2l_flops / (m2l_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": N ** 3 / (ms * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "periodic FMM, 256^3 lognormal density (P(k)~k^-1.5, "
+                               "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
+                   "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision},
+        "roofline": {"bound": "mfma", "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
+                     "frac": near_tf / peak, "traffic": None,
+                     "kernel": "near zone (%d launch/step, %.3f ms)" % (stages["near"][1], near_ms)},
+        "m2l": {"achieved": m2l_tf, "peak": peak, "unit": "TFLOP/s", "frac": m2l_tf / peak,
+                "ms": m2l_ms, "launches": stages["m2l"][1]},
+        "stages_ms": {k: v[0] for k, v in stages.items()},
+    }
+    if not args.no_cpu_baseline:
+        base, acc = cpu_baseline(rho32.astype(np.float64), phi.cpu().numpy().astype(np.float64))
+        out["cpu_baseline"] = base
+        out["accuracy"] = acc
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

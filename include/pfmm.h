@@ -1,0 +1,202 @@
+/*
+ * pfmm.h — C ABI of libpfmm, a natively periodic Fast Multipole Method for
+ * MI355X (gfx950).
+ *
+ * Method: N. Y. Gnedin, "Natively Periodic Fast Multipole Method:
+ * Approximating the Optimal Green's Function" (ApJ).  The library computes
+ * the potential of a density sampled on a uniform N^3 periodic mesh with the
+ * paper's FMM (Sec. 2): an oct-tree whose nodes carry p^3 "gridlet" effective
+ * masses (the Cartesian-multipole representation of Sec. 2, p being the
+ * paper's N_g), the upward projection of Eq. 5, the interaction-zone
+ * convolution of Eq. 6 with a periodic Green's function at level 2 and the
+ * non-periodic algorithm with periodic neighbour selection below it (Sec. 2),
+ * the downward projection of Eq. 7, and the direct 27-node near zone of a leaf.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Unit periodic box, N^3 cells of side h = 1/N, C order with x slowest:
+ *    cell (i, j, k) is element (i*N + j)*N + k.
+ *  - Green's-function normalisation G_0 = -1/(4 pi r) (Sec. 1), so that the
+ *    potential solves lap(Phi) = rho and
+ *        Phi_i  ~=  h^3 * sum_j G((x_i - x_j) wrapped) rho_j       (Eq. 4).
+ *    The FMM approximates this periodic convolution; the self term G(0) of
+ *    the real-space kinds is the potential at the centre of a uniform cube
+ *    cell, -c0/(4 pi h) with c0 = 3 ln((sqrt3+1)/(sqrt3-1)) - pi/2.
+ *  - Device pointers are HIP device addresses (e.g. a torch tensor's
+ *    data_ptr()); the caller owns them.  The plan owns its tables and
+ *    workspaces.  No entry point takes ownership of caller memory.
+ *  - Every entry point returns a pfmm_status.  Host-side argument checks run
+ *    before anything is enqueued.  Asynchronous device faults surface as
+ *    PFMM_ERR_HIP from a later call that synchronises.  pfmm_last_error()
+ *    returns a message for the calling thread's last failure.
+ */
+#ifndef PFMM_H
+#define PFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfmm_plan_s* pfmm_plan_t;
+
+typedef enum {
+  PFMM_OK = 0,
+  PFMM_ERR_INVALID_ARG = 1,   /* bad size, kind, option, pointer or handle  */
+  PFMM_ERR_UNSUPPORTED = 2,   /* valid but outside what this build handles  */
+  PFMM_ERR_OUT_OF_MEMORY = 3, /* a plan-time allocation failed              */
+  PFMM_ERR_HIP = 4            /* a HIP runtime call or a kernel failed      */
+} pfmm_status;
+
+/* Periodic Green's functions. */
+typedef enum {
+  /* "Exact-in-real-space" G_X(x) = -1/(4 pi |x wrapped|)  (Eq. 2). */
+  PFMM_GREEN_X = 0,
+  /* "Exact-in-Fourier-space" G_K, the inverse transform of -1/k^2 with the
+   * k = 0 mode removed, k = 2 pi n, n_i in [-N/2+1, N/2]  (Eq. 1).  Between
+   * mesh points it is the real even trigonometric interpolant that splits
+   * the Nyquist term equally between n_i = +N/2 and -N/2. */
+  PFMM_GREEN_K = 1,
+  /* Approximately optimal G_S1 (Eq. 9): G_X of the mapped separation
+   * x_hat = (9/(8 pi)) sin(pi x) - (1/(24 pi)) sin(3 pi x), per component. */
+  PFMM_GREEN_S1 = 2,
+  /* The one-parameter ansatz G_S of Sec. 3 with n = 1 and a free a_1
+   * (PFMM_OPT_GS_A1, default -1/8, which is G_S1). */
+  PFMM_GREEN_S = 3
+} pfmm_green;
+
+/* Arithmetic of the two contraction-heavy steps (interaction-zone
+ * convolution and near zone).  Tabulation of G always runs in FP64. */
+typedef enum {
+  /* FP32 products and FP32 accumulation. */
+  PFMM_PREC_FP32 = 0,
+  /* Split precision: each FP32 operand x is held as hi = bf16(x) and
+   * lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi on the BF16 matrix
+   * cores with FP32 accumulation. */
+  PFMM_PREC_BF16X3 = 1
+} pfmm_precision;
+
+/* Options for pfmm_plan_set. */
+typedef enum {
+  /* value: int32 pfmm_precision.  Default PFMM_PREC_FP32. */
+  PFMM_OPT_PRECISION = 1,
+  /* value: hipStream_t (pointer-sized).  The stream solve enqueues on.
+   * Default: the null stream. */
+  PFMM_OPT_STREAM = 2,
+  /* value: double a_1 of the G_S ansatz (Sec. 3); only for PFMM_GREEN_S.
+   * Re-tabulates G synchronously. */
+  PFMM_OPT_GS_A1 = 3,
+  /* value: int32 0/1.  When 1, solve records HIP events on the plan's stream
+   * around every stage (events are created at plan time; recording them
+   * allocates nothing); pfmm_plan_stage_times reads them.  Default 0. */
+  PFMM_OPT_PROFILE = 4,
+  /* value: int32 in {0, 1, 2}: keep the gridlet masses and potentials of the
+   * coarsest levels 2 .. 1+value (at most level 3) in FP64, with their M2M,
+   * interaction-zone sums and L2L in FP64.  The downward interpolation
+   * (Eq. 7) extrapolates past a parent's outermost gridlet nodes, so rounding
+   * noise in a coarse field is amplified on its way to the mesh.  Default 2. */
+  PFMM_OPT_FP64_LEVELS = 5
+} pfmm_option;
+
+/* Stages reported by pfmm_plan_stage_times (durations summed over levels). */
+typedef enum {
+  PFMM_STAGE_P2M = 0,
+  PFMM_STAGE_M2M = 1,
+  PFMM_STAGE_M2L = 2,   /* interaction zones of all levels (Eq. 6)      */
+  PFMM_STAGE_L2L = 3,
+  PFMM_STAGE_L2P = 4,
+  PFMM_STAGE_NEAR = 5,  /* direct near zone of the leaves               */
+  PFMM_STAGE_FD4 = 6,
+  PFMM_STAGE_COUNT = 7
+} pfmm_stage;
+
+/* Intermediate buffers readable with pfmm_plan_read (for testing a stage). */
+typedef enum {
+  /* Gridlet effective masses of level l: [8^l nodes][p^3], nodes and gridlet
+   * points both in C order, as float (FP64 levels are rounded).  Output of
+   * P2M (l = L) and M2M (Eq. 5). */
+  PFMM_BUF_MULTIPOLE = 0,
+  /* Gridlet potentials of level l, same layout: the interaction-zone sum of
+   * Eq. 6 plus the parent's field carried down by Eq. 7. */
+  PFMM_BUF_LOCAL = 1,
+  /* FP64 samples G(j / (2^l p)) used by the interaction-zone convolution of
+   * level l (Eq. 6 arguments), j in [-(4p-1), 4p-1]^3, C order: (8p-1)^3
+   * doubles.  `dst` is then a double*. */
+  PFMM_BUF_TABLE_LEVEL = 2,
+  /* FP64 mesh samples G(j h) of the near zone, j in [-(2s-1), 2s-1]^3 with
+   * the cube self term at j = 0: (4s-1)^3 doubles (`level` ignored). */
+  PFMM_BUF_TABLE_NEAR = 3
+} pfmm_buffer;
+
+/*
+ * Create a plan for an N^3 box, a uniform tree of depth L (levels 2..L,
+ * 2^l nodes per axis at level l, leaves of s = N/2^L cells per axis), p^3
+ * gridlet masses per node and the Green's function `green_kind`.
+ *
+ *   N     power of two, 8 <= N <= 1024
+ *   L     2 <= L, 2^L <= N, and leaf width s = N/2^L <= 16
+ *   p     1 <= p <= 10
+ *
+ * Tabulates G on the device in FP64 (plan time) and allocates every
+ * workspace, so that pfmm_solve never allocates.  Synchronises the device.
+ * On success *out receives the handle; on failure *out is set to NULL.
+ */
+pfmm_status pfmm_plan_create(int N, int L, int p, int green_kind, pfmm_plan_t* out);
+
+/*
+ * Set a plan option (pfmm_option).  `value` points to `bytes` bytes holding
+ * the option's type (see the enum).  May synchronise; never called by solve.
+ */
+pfmm_status pfmm_plan_set(pfmm_plan_t plan, int option, const void* value, size_t bytes);
+
+/*
+ * Solve: potential = FMM approximation of h^3 sum_j G(x_i - x_j) rho_j.
+ *
+ *   density    device, const float[N*N*N], C order (read only)
+ *   potential  device, float[N*N*N], overwritten
+ *   accel      device, float[3][N*N*N] (components x, y, z), overwritten with
+ *              -grad(potential) by periodic 4th-order central differences
+ *              (Sec. 3), or NULL to skip
+ *
+ * Enqueues on the plan's stream; does not allocate and does not synchronise.
+ * No mean is removed: the density normally has zero mean (G_K ignores the
+ * mean by construction).  `potential` and `accel` must not alias `density`.
+ */
+pfmm_status pfmm_solve(pfmm_plan_t plan, const float* density, float* potential, float* accel);
+
+/*
+ * Copy a plan buffer (pfmm_buffer) at tree level `level` (2..L) into the
+ * device array `dst`: 8^level * p^3 floats for the gridlet buffers of the
+ * last solve, or the FP64 tables described with the enum.  Enqueued on the
+ * plan's stream like solve.
+ */
+pfmm_status pfmm_plan_read(pfmm_plan_t plan, int buffer, int level, void* dst);
+
+/*
+ * Per-solve durations in milliseconds of each pfmm_stage, averaged over the
+ * most recent (at most 16) solves made since PFMM_OPT_PROFILE was switched
+ * on, and the kernel launches of each stage in one solve, into
+ * ms[PFMM_STAGE_COUNT] and launches[PFMM_STAGE_COUNT] (host arrays; launches
+ * may be NULL).  Waits for those solves' events.  PFMM_ERR_INVALID_ARG if no
+ * profiled solve has run.
+ */
+pfmm_status pfmm_plan_stage_times(pfmm_plan_t plan, double* ms, int* launches);
+
+/* Query plan geometry: leaf width s and the number of table entries
+ * per tree level ((8p-1)^3) into *s and *table_entries (either may be NULL). */
+pfmm_status pfmm_plan_info(pfmm_plan_t plan, int* s, int64_t* table_entries);
+
+/* Release a plan and everything it owns.  Synchronises its stream.  NULL is
+ * accepted and ignored. */
+pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char* pfmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFMM_H */

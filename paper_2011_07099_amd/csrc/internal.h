@@ -1,0 +1,83 @@
+// Internal declarations of libpfmm: plan layout, kernel argument blocks and
+// the host-side launchers of every device stage.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pfmm {
+
+// ---------------------------------------------------------------------------
+// Green's function tabulation (FP64, plan time)
+// ---------------------------------------------------------------------------
+enum GreenKind { GK_X = 0, GK_K = 1, GK_S1 = 2, GK_S = 3 };
+
+// Tabulate G(eta * j) for j in [-C, C]^3 into dst[(2C+1)^3] (FP64, C order),
+// eta = 1 / den.  `self_h` > 0 gives the value at j = 0 for the real-space
+// kinds (potential at the centre of a uniform cube cell of side self_h);
+// self_h == 0 leaves 0 there.  `N` is the mesh size (G_K frequency range).
+// G_K allocates and frees its own temporaries and synchronises `st`.
+hipError_t tabulate_green(int kind, double a1, int N, int C, int64_t den, double self_h,
+                          double* dst, hipStream_t st);
+
+// FP64 -> FP32 copy.
+hipError_t cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Block-Toeplitz operator: Y[t] (+)= sum_{d in D(class(t))} K_d X[(t+d) mod n]
+// with K_d[a, a'] = tab[a - a' - q d] (target minus source), blocks of q^3 points.  Used for the
+// interaction-zone convolution (Eq. 6; blocks = gridlets) and for the near
+// zone (blocks = leaf cells or sub-blocks of them).
+// ---------------------------------------------------------------------------
+struct ToepArgs {
+  int n;            // nodes per axis at this level (power of two)
+  int m;            // classes per axis: targets with t mod m == c share D(c)
+  int q;            // block edge
+  int noff;         // offsets per class
+  const int* offs;  // [m^3][noff] packed offsets (see pack_offset)
+  const void* tab;  // table (float or double), extent E = 2C+1 per axis, centre C
+  int C;
+  const void* X;    // sources: blocks [n^3][q^3] or (grid_in) mesh [nq]^3
+  void* Y;          // outputs: blocks or (grid_out) mesh
+  int grid_in, grid_out;
+  double xscale;    // sources are multiplied by this (h^3: density -> mass)
+  int accumulate;   // 0: overwrite Y, 1: add to Y
+  int fp64;         // 0: FP32 tab/X/Y, 1: FP64 tab/X/Y
+};
+
+inline int pack_offset(int dx, int dy, int dz) {
+  return ((dx + 128) & 255) << 16 | ((dy + 128) & 255) << 8 | ((dz + 128) & 255);
+}
+
+hipError_t launch_toeplitz(const ToepArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Upward / downward passes (tensor products of 1D Lagrange operators).
+// Gridlet buffers are FP32 or FP64 per level; `*64` flags give the type of
+// each operand (0 = float, 1 = double).  Weights are passed in both types.
+// ---------------------------------------------------------------------------
+struct Weights {
+  const float* f;
+  const double* d;
+};
+// P2M: M[b][a] = h3 * sum_c A[ax][cx] A[ay][cy] A[az][cz] rho[b s + c]
+hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int s, int p,
+                      double h3, hipStream_t st);
+// M2M (Eq. 5): Mp[B][a] = sum_o sum_a' T_o(x)T_o(x)T_o [a][a'] Mc[2B+o][a']
+hipError_t launch_m2m(const void* Mc, int c64, void* Mp, int p64, Weights T, int nparent, int p,
+                      hipStream_t st);
+// L2L (Eq. 7): Pc[2B+o][a'] = sum_a T_o[ax][a'x] T_o[ay][a'y] T_o[az][a'z] Pp[B][a]  (overwrite)
+hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int nparent, int p,
+                      hipStream_t st);
+// L2P: phi[b s + c] = sum_a A[ax][cx] A[ay][cy] A[az][cz] P[b][a]  (overwrite)
+hipError_t launch_l2p(const void* P, int p64, float* phi, Weights A, int N, int s, int p,
+                      hipStream_t st);
+// a = -grad(phi), periodic 4th-order central differences.
+hipError_t launch_fd4(const float* phi, float* acc, int N, hipStream_t st);
+// FP64 -> FP32 copy of n elements.
+hipError_t launch_cast_d2f(const double* src, float* dst, int64_t n, hipStream_t st);
+
+}  // namespace pfmm

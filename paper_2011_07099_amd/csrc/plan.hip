@@ -1,0 +1,558 @@
+// C ABI of libpfmm (declared in include/pfmm.h): plan creation, options and
+// the solve sequence of the natively periodic FMM (Sec. 2, Eqs. 5-7).
+//
+// Solve sequence, all on the plan's stream, nothing allocated:
+//   1. P2M at the leaves (level L): cell masses -> leaf gridlets.
+//   2. M2M (Eq. 5) for levels L-1 .. 2.
+//   3. Level 2: interaction zone = the 37 non-neighbour nodes of the periodic
+//      4^3 level, each once, with the periodic G (Eq. 6).
+//   4. Levels 3 .. L: L2L (Eq. 7) of the parent's field, then the 189-node
+//      interaction zone of the node's parity class (Sec. 2, Fig. 2).
+//   5. L2P at the leaves, then the direct near zone (27 leaves) added on the
+//      mesh.  A leaf wider than 8 cells is cut into sub-blocks of 8^3 cells;
+//      the 27 neighbouring leaves of a sub-block are then the (3m)^3
+//      sub-blocks around its leaf, m = s/8, and depend on the sub-block's
+//      position in its leaf.
+//   6. Optionally a = -grad(phi) by 4th-order differences (Sec. 3).
+#include "../../include/pfmm.h"
+#include "internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+using namespace pfmm;
+
+struct pfmm_plan_s {
+  int N = 0, L = 0, p = 0, s = 0, green = 0, prec = PFMM_PREC_FP32;
+  double a1 = -0.125;
+  hipStream_t stream = nullptr;
+  int qn = 0, mn = 0;  // near-zone block edge and classes per axis
+  float* dA = nullptr;  // [p][s] P2M / L2P weights
+  float* dT = nullptr;  // [2][p][p] M2M / L2L weights
+  double* dA64 = nullptr;
+  double* dT64 = nullptr;
+  int fp64_levels = 2;            // levels 2 .. 1+fp64_levels kept in FP64
+  std::vector<void*> M, P;        // gridlet masses / potentials per level
+  std::vector<double*> tab64;     // per level, (8p-1)^3
+  std::vector<float*> tab32;
+  double* ntab64 = nullptr;       // near, (4s-1)^3
+  float* ntab32 = nullptr;
+  int* offs_l2 = nullptr;         // [37]
+  int* offs_iz = nullptr;         // [8][189]
+  int* offs_near = nullptr;       // [mn^3][(3 mn)^3]
+  std::vector<void*> owned;
+  // stage timing (PFMM_OPT_PROFILE): a ring of event sets, one per solve
+  int profile = 0;
+  std::vector<hipEvent_t> ev;  // [kSlots][kMaxEvents], created at plan time
+  std::vector<int> ev_tag;     // stage of the interval ending at event k+1
+  std::vector<int> ev_used;    // events recorded per slot
+  int nprof = 0;               // profiled solves since profiling was enabled
+};
+
+namespace {
+constexpr int kMaxEvents = 64;  // per solve
+constexpr int kSlots = 16;      // most recent profiled solves kept
+}
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_mu;
+std::set<pfmm_plan_s*> g_live;
+
+pfmm_status fail(pfmm_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+pfmm_status hip_fail(hipError_t e, const char* where) {
+  return fail(PFMM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool live(pfmm_plan_s* p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return p && g_live.count(p);
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int64_t cube(int64_t v) { return v * v * v; }
+
+// 1D Lagrange basis of the gridlet nodes t_a = a + 1/2 - p/2 (units of the
+// gridlet spacing) evaluated at x: the solution of the moment-matching
+// (Vandermonde) system of Sec. 2, one axis at a time.
+double lagrange(int p, int a, double x) {
+  double v = 1.0;
+  const double ta = a + 0.5 - 0.5 * p;
+  for (int b = 0; b < p; ++b) {
+    if (b == a) continue;
+    const double tb = b + 0.5 - 0.5 * p;
+    v *= (x - tb) / (ta - tb);
+  }
+  return v;
+}
+
+template <class T>
+hipError_t dalloc(pfmm_plan_s* pl, T** ptr, size_t count) {
+  void* raw = nullptr;
+  hipError_t e = hipMalloc(&raw, count * sizeof(T));
+  if (e != hipSuccess) return e;
+  pl->owned.push_back(raw);
+  *ptr = static_cast<T*>(raw);
+  return hipSuccess;
+}
+
+void release(pfmm_plan_s* pl) {
+  for (hipEvent_t e : pl->ev)
+    if (e) hipEventDestroy(e);
+  pl->ev.clear();
+  for (void* q : pl->owned) hipFree(q);
+  pl->owned.clear();
+  delete pl;
+}
+
+// Is level l kept in FP64?  Levels 2 .. 1 + fp64_levels are, except a leaf
+// whose FP64 P2M / L2P staging would not fit in 64 KiB of LDS.
+bool level64(const pfmm_plan_s* pl, int l) {
+  if (l < 2 || l > 1 + pl->fp64_levels || l > 3) return false;
+  if (l == pl->L) {
+    const int p = pl->p, s = pl->s;
+    const size_t w1 = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
+    const size_t w2 = (size_t)(p * s + p * p * p + p * p * s + p * s * s);
+    if ((w1 > w2 ? w1 : w2) * sizeof(double) > 65536) return false;
+  }
+  return true;
+}
+
+Weights wts(const float* f, const double* d) {
+  Weights w;
+  w.f = f;
+  w.d = d;
+  return w;
+}
+
+pfmm_status tabulate_all(pfmm_plan_s* pl) {
+  const int p = pl->p;
+  const int C = 4 * p - 1;
+  const int64_t nlev = cube(2 * C + 1);
+  for (int l = 2; l <= pl->L; ++l) {
+    hipError_t e = tabulate_green(pl->green, pl->a1, pl->N, C, (int64_t(1) << l) * p, 0.0,
+                                  pl->tab64[l], pl->stream);
+    if (e == hipSuccess) e = cast_f64_f32(pl->tab64[l], pl->tab32[l], nlev, pl->stream);
+    if (e != hipSuccess) return hip_fail(e, "tabulate level table");
+  }
+  const int Cn = 2 * pl->s - 1;
+  hipError_t e = tabulate_green(pl->green, pl->a1, pl->N, Cn, pl->N, 1.0 / pl->N, pl->ntab64,
+                                pl->stream);
+  if (e == hipSuccess) e = cast_f64_f32(pl->ntab64, pl->ntab32, cube(2 * Cn + 1), pl->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) return hip_fail(e, "tabulate near table");
+  return PFMM_OK;
+}
+
+pfmm_status build(pfmm_plan_s* pl) {
+  const int N = pl->N, L = pl->L, p = pl->p, s = pl->s;
+  const int p3 = p * p * p;
+  hipError_t e = hipSuccess;
+  auto chk = [&](const char* what) -> pfmm_status {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      return fail(PFMM_ERR_OUT_OF_MEMORY, std::string("allocation failed: ") + what);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return PFMM_OK;
+  };
+  pfmm_status st;
+
+  // 1D operators in FP64 on the host, stored as FP32
+  std::vector<float> A(p * s), T(2 * p * p);
+  for (int a = 0; a < p; ++a)
+    for (int c = 0; c < s; ++c)
+      A[a * s + c] = (float)lagrange(p, a, (c + 0.5 - 0.5 * s) * ((double)p / s));
+  for (int o = 0; o < 2; ++o)
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b) {
+        const double tb = b + 0.5 - 0.5 * p;
+        T[(o * p + a) * p + b] = (float)lagrange(p, a, (o - 0.5) * 0.5 * p + 0.5 * tb);
+      }
+  e = dalloc(pl, &pl->dA, A.size());
+  if ((st = chk("P2M weights"))) return st;
+  e = dalloc(pl, &pl->dT, T.size());
+  if ((st = chk("M2M weights"))) return st;
+  e = hipMemcpy(pl->dA, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(pl->dT, T.data(), T.size() * sizeof(float), hipMemcpyHostToDevice);
+  if ((st = chk("upload weights"))) return st;
+
+  std::vector<double> A64(A.begin(), A.end()), T64(T.begin(), T.end());
+  for (int a = 0; a < p; ++a)
+    for (int c = 0; c < s; ++c) A64[a * s + c] = lagrange(p, a, (c + 0.5 - 0.5 * s) * ((double)p / s));
+  for (int o = 0; o < 2; ++o)
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b)
+        T64[(o * p + a) * p + b] = lagrange(p, a, (o - 0.5) * 0.5 * p + 0.5 * (b + 0.5 - 0.5 * p));
+  e = dalloc(pl, &pl->dA64, A64.size());
+  if (e == hipSuccess) e = dalloc(pl, &pl->dT64, T64.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->dA64, A64.data(), A64.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->dT64, T64.data(), T64.size() * sizeof(double), hipMemcpyHostToDevice);
+  if ((st = chk("FP64 weights"))) return st;
+
+  // per-level gridlet buffers (levels 2 and 3 sized for FP64) and tables
+  pl->M.assign(L + 1, nullptr);
+  pl->P.assign(L + 1, nullptr);
+  pl->tab64.assign(L + 1, nullptr);
+  pl->tab32.assign(L + 1, nullptr);
+  const int64_t nlev = cube(8 * p - 1);
+  for (int l = 2; l <= L; ++l) {
+    const size_t nodes = (size_t)1 << (3 * l);
+    const size_t wbytes = l <= 3 ? sizeof(double) : sizeof(float);
+    char* mb = nullptr;
+    e = dalloc(pl, &mb, nodes * p3 * wbytes);
+    pl->M[l] = mb;
+    if ((st = chk("multipole buffer"))) return st;
+    e = dalloc(pl, &mb, nodes * p3 * wbytes);
+    pl->P[l] = mb;
+    if ((st = chk("local buffer"))) return st;
+    e = dalloc(pl, &pl->tab64[l], nlev);
+    if ((st = chk("level table"))) return st;
+    e = dalloc(pl, &pl->tab32[l], nlev);
+    if ((st = chk("level table"))) return st;
+  }
+  const int64_t nnear = cube(4 * s - 1);
+  e = dalloc(pl, &pl->ntab64, nnear);
+  if ((st = chk("near table"))) return st;
+  e = dalloc(pl, &pl->ntab32, nnear);
+  if ((st = chk("near table"))) return st;
+
+  // zones (Sec. 2, Fig. 2)
+  std::vector<int> l2, iz, nz;
+  for (int dx = -2; dx <= 1; ++dx)
+    for (int dy = -2; dy <= 1; ++dy)
+      for (int dz = -2; dz <= 1; ++dz)
+        if (dx == -2 || dy == -2 || dz == -2) l2.push_back(pack_offset(dx, dy, dz));
+  for (int c = 0; c < 8; ++c) {
+    const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
+    for (int dx = -2 - cx; dx <= 3 - cx; ++dx)
+      for (int dy = -2 - cy; dy <= 3 - cy; ++dy)
+        for (int dz = -2 - cz; dz <= 3 - cz; ++dz)
+          if (std::abs(dx) > 1 || std::abs(dy) > 1 || std::abs(dz) > 1)
+            iz.push_back(pack_offset(dx, dy, dz));
+  }
+  pl->qn = s <= 8 ? s : 8;
+  pl->mn = s / pl->qn;
+  const int mn = pl->mn;
+  for (int c = 0; c < mn * mn * mn; ++c) {
+    const int cx = c / (mn * mn), cy = (c / mn) % mn, cz = c % mn;
+    for (int dx = -mn - cx; dx <= 2 * mn - 1 - cx; ++dx)
+      for (int dy = -mn - cy; dy <= 2 * mn - 1 - cy; ++dy)
+        for (int dz = -mn - cz; dz <= 2 * mn - 1 - cz; ++dz) nz.push_back(pack_offset(dx, dy, dz));
+  }
+  if (l2.size() != 37 || iz.size() != 8 * 189 || nz.size() != (size_t)cube(3 * mn) * cube(mn))
+    return fail(PFMM_ERR_HIP, "internal: zone sizes");
+  e = dalloc(pl, &pl->offs_l2, l2.size());
+  if (e == hipSuccess) e = dalloc(pl, &pl->offs_iz, iz.size());
+  if (e == hipSuccess) e = dalloc(pl, &pl->offs_near, nz.size());
+  if ((st = chk("zone lists"))) return st;
+  e = hipMemcpy(pl->offs_l2, l2.data(), l2.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->offs_iz, iz.data(), iz.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->offs_near, nz.data(), nz.size() * sizeof(int), hipMemcpyHostToDevice);
+  if ((st = chk("upload zone lists"))) return st;
+  (void)N;
+  pl->ev.assign(kSlots * kMaxEvents, nullptr);
+  for (auto& ev : pl->ev) {
+    e = hipEventCreate(&ev);
+    if ((st = chk("event"))) return st;
+  }
+  pl->ev_tag.assign(kSlots * kMaxEvents, 0);
+  pl->ev_used.assign(kSlots, 0);
+  return tabulate_all(pl);
+}
+
+}  // namespace
+
+extern "C" {
+
+pfmm_status pfmm_plan_create(int N, int L, int p, int green_kind, pfmm_plan_t* out) {
+  g_err.clear();
+  if (!out) return fail(PFMM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!is_pow2(N) || N < 8 || N > 1024)
+    return fail(PFMM_ERR_INVALID_ARG, "N must be a power of two in [8, 1024]");
+  if (L < 2 || (1 << L) > N) return fail(PFMM_ERR_INVALID_ARG, "need 2 <= L and 2^L <= N");
+  if (p < 1 || p > 10) return fail(PFMM_ERR_INVALID_ARG, "p must be in [1, 10]");
+  if (green_kind < PFMM_GREEN_X || green_kind > PFMM_GREEN_S)
+    return fail(PFMM_ERR_INVALID_ARG, "unknown green_kind");
+  const int s = N >> L;
+  if (s > 16) return fail(PFMM_ERR_UNSUPPORTED, "leaf width N/2^L must be <= 16");
+  pfmm_plan_s* pl = new (std::nothrow) pfmm_plan_s;
+  if (!pl) return fail(PFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  pl->N = N;
+  pl->L = L;
+  pl->p = p;
+  pl->s = s;
+  pl->green = green_kind;
+  pfmm_status st = build(pl);
+  if (st != PFMM_OK) {
+    hipDeviceSynchronize();
+    release(pl);
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.insert(pl);
+  }
+  *out = pl;
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t bytes) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!value) return fail(PFMM_ERR_INVALID_ARG, "value is NULL");
+  switch (option) {
+    case PFMM_OPT_PRECISION: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "precision is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      if (v != PFMM_PREC_FP32 && v != PFMM_PREC_BF16X3)
+        return fail(PFMM_ERR_INVALID_ARG, "unknown precision");
+      if (v != PFMM_PREC_FP32) return fail(PFMM_ERR_UNSUPPORTED, "precision not built yet");
+      pl->prec = v;
+      return PFMM_OK;
+    }
+    case PFMM_OPT_STREAM: {
+      if (bytes != sizeof(hipStream_t)) return fail(PFMM_ERR_INVALID_ARG, "stream is a hipStream_t");
+      std::memcpy(&pl->stream, value, sizeof(hipStream_t));
+      return PFMM_OK;
+    }
+    case PFMM_OPT_GS_A1: {
+      if (bytes != sizeof(double)) return fail(PFMM_ERR_INVALID_ARG, "a1 is a double");
+      if (pl->green != PFMM_GREEN_S) return fail(PFMM_ERR_INVALID_ARG, "a1 needs PFMM_GREEN_S");
+      double v;
+      std::memcpy(&v, value, sizeof v);
+      if (!std::isfinite(v)) return fail(PFMM_ERR_INVALID_ARG, "a1 must be finite");
+      pl->a1 = v;
+      return tabulate_all(pl);
+    }
+    case PFMM_OPT_FP64_LEVELS: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      if (v < 0 || v > 2) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels must be 0, 1 or 2");
+      pl->fp64_levels = v;
+      return PFMM_OK;
+    }
+    case PFMM_OPT_PROFILE: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "profile is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      pl->profile = v != 0;
+      pl->nprof = 0;
+      return PFMM_OK;
+    }
+    default:
+      return fail(PFMM_ERR_INVALID_ARG, "unknown option");
+  }
+}
+
+pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* accel) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!rho || !phi) return fail(PFMM_ERR_INVALID_ARG, "density and potential are required");
+  if ((const void*)rho == (const void*)phi || (const void*)rho == (const void*)accel ||
+      (accel && (void*)accel == (void*)phi))
+    return fail(PFMM_ERR_INVALID_ARG, "buffers must not alias");
+  const int N = pl->N, L = pl->L, p = pl->p, s = pl->s;
+  const double h3 = 1.0 / ((double)N * N * N);
+  hipStream_t st = pl->stream;
+  hipError_t e;
+  int nev = 0;
+  const int slot = pl->nprof % kSlots;
+  hipEvent_t* ev = pl->ev.data() + slot * kMaxEvents;
+  int* tag = pl->ev_tag.data() + slot * kMaxEvents;
+  // record the end of a stage's launch (profiling only)
+  auto mark = [&](int stage) -> hipError_t {
+    if (!pl->profile || nev + 1 >= kMaxEvents) return hipSuccess;
+    tag[nev] = stage;
+    return hipEventRecord(ev[++nev], st);
+  };
+  if (pl->profile) {
+    e = hipEventRecord(ev[0], st);
+    if (e != hipSuccess) return hip_fail(e, "event");
+  }
+
+  const Weights A = wts(pl->dA, pl->dA64), T = wts(pl->dT, pl->dT64);
+  auto is64 = [&](int l) { return (int)level64(pl, l); };
+
+  // upward pass
+  e = launch_p2m(rho, pl->M[L], is64(L), A, N, s, p, (double)h3, st);
+  if (e == hipSuccess) e = mark(PFMM_STAGE_P2M);
+  if (e != hipSuccess) return hip_fail(e, "P2M");
+  for (int l = L - 1; l >= 2; --l) {
+    e = launch_m2m(pl->M[l + 1], is64(l + 1), pl->M[l], is64(l), T, 1 << l, p, st);
+    if (e == hipSuccess) e = mark(PFMM_STAGE_M2M);
+    if (e != hipSuccess) return hip_fail(e, "M2M");
+  }
+
+  // interaction zones, level 2 (periodic) then 3 .. L with L2L first
+  ToepArgs a{};
+  a.q = p;
+  a.C = 4 * p - 1;
+  a.xscale = 1.0;
+  a.n = 4;
+  a.m = 1;
+  a.noff = 37;
+  a.offs = pl->offs_l2;
+  a.fp64 = is64(2);
+  a.tab = a.fp64 ? (const void*)pl->tab64[2] : (const void*)pl->tab32[2];
+  a.X = pl->M[2];
+  a.Y = pl->P[2];
+  a.accumulate = 0;
+  e = launch_toeplitz(a, st);
+  if (e == hipSuccess) e = mark(PFMM_STAGE_M2L);
+  if (e != hipSuccess) return hip_fail(e, "M2L level 2");
+  for (int l = 3; l <= L; ++l) {
+    e = launch_l2l(pl->P[l - 1], is64(l - 1), pl->P[l], is64(l), T, 1 << (l - 1), p, st);
+    if (e == hipSuccess) e = mark(PFMM_STAGE_L2L);
+    if (e != hipSuccess) return hip_fail(e, "L2L");
+    a.n = 1 << l;
+    a.m = 2;
+    a.noff = 189;
+    a.offs = pl->offs_iz;
+    a.fp64 = is64(l);
+    a.tab = a.fp64 ? (const void*)pl->tab64[l] : (const void*)pl->tab32[l];
+    a.X = pl->M[l];
+    a.Y = pl->P[l];
+    a.accumulate = 1;
+    e = launch_toeplitz(a, st);
+    if (e == hipSuccess) e = mark(PFMM_STAGE_M2L);
+    if (e != hipSuccess) return hip_fail(e, "M2L");
+  }
+
+  // downward to the mesh, then the near zone
+  e = launch_l2p(pl->P[L], is64(L), phi, A, N, s, p, st);
+  if (e == hipSuccess) e = mark(PFMM_STAGE_L2P);
+  if (e != hipSuccess) return hip_fail(e, "L2P");
+  ToepArgs nb{};
+  nb.q = pl->qn;
+  nb.m = pl->mn;
+  nb.n = N / pl->qn;
+  nb.noff = (int)cube(3 * pl->mn);
+  nb.offs = pl->offs_near;
+  nb.tab = pl->ntab32;
+  nb.C = 2 * s - 1;
+  nb.X = rho;
+  nb.Y = phi;
+  nb.grid_in = 1;
+  nb.grid_out = 1;
+  nb.xscale = 1.0 / ((double)N * N * N);
+  nb.accumulate = 1;
+  e = launch_toeplitz(nb, st);
+  if (e == hipSuccess) e = mark(PFMM_STAGE_NEAR);
+  if (e != hipSuccess) return hip_fail(e, "near zone");
+  if (accel) {
+    e = launch_fd4(phi, accel, N, st);
+    if (e == hipSuccess) e = mark(PFMM_STAGE_FD4);
+    if (e != hipSuccess) return hip_fail(e, "FD4");
+  }
+  if (pl->profile) {
+    pl->ev_used[slot] = nev;
+    ++pl->nprof;
+  }
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_plan_read(pfmm_plan_t pl, int buffer, int level, void* dst) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!dst) return fail(PFMM_ERR_INVALID_ARG, "dst is NULL");
+  const void* src = nullptr;
+  size_t bytes = 0;
+  const size_t p3 = (size_t)pl->p * pl->p * pl->p;
+  if (buffer == PFMM_BUF_TABLE_NEAR) {
+    src = pl->ntab64;
+    bytes = (size_t)cube(4 * pl->s - 1) * sizeof(double);
+  } else {
+    if (level < 2 || level > pl->L) return fail(PFMM_ERR_INVALID_ARG, "level out of range");
+    const size_t nodes = (size_t)1 << (3 * level);
+    switch (buffer) {
+      case PFMM_BUF_MULTIPOLE:
+      case PFMM_BUF_LOCAL: {
+        const void* b = buffer == PFMM_BUF_MULTIPOLE ? pl->M[level] : pl->P[level];
+        hipError_t e = level64(pl, level)
+                           ? launch_cast_d2f((const double*)b, (float*)dst, (int64_t)(nodes * p3),
+                                             pl->stream)
+                           : hipMemcpyAsync(dst, b, nodes * p3 * sizeof(float),
+                                            hipMemcpyDeviceToDevice, pl->stream);
+        if (e != hipSuccess) return hip_fail(e, "read buffer");
+        return PFMM_OK;
+      }
+      case PFMM_BUF_TABLE_LEVEL:
+        src = pl->tab64[level];
+        bytes = (size_t)cube(8 * pl->p - 1) * sizeof(double);
+        break;
+      default: return fail(PFMM_ERR_INVALID_ARG, "unknown buffer");
+    }
+  }
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, pl->stream);
+  if (e != hipSuccess) return hip_fail(e, "read buffer");
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_plan_stage_times(pfmm_plan_t pl, double* ms, int* launches) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!ms) return fail(PFMM_ERR_INVALID_ARG, "ms is NULL");
+  if (pl->nprof == 0) return fail(PFMM_ERR_INVALID_ARG, "no profiled solve");
+  for (int k = 0; k < PFMM_STAGE_COUNT; ++k) {
+    ms[k] = 0.0;
+    if (launches) launches[k] = 0;
+  }
+  const int nsol = pl->nprof < kSlots ? pl->nprof : kSlots;
+  for (int j = 0; j < nsol; ++j) {
+    const int slot = (pl->nprof - 1 - j) % kSlots;
+    hipEvent_t* ev = pl->ev.data() + slot * kMaxEvents;
+    const int* tag = pl->ev_tag.data() + slot * kMaxEvents;
+    hipError_t e = hipEventSynchronize(ev[pl->ev_used[slot]]);
+    if (e != hipSuccess) return hip_fail(e, "stage times");
+    for (int k = 0; k < pl->ev_used[slot]; ++k) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+      if (e != hipSuccess) return hip_fail(e, "stage times");
+      ms[tag[k]] += t / nsol;
+      if (launches && j == 0) launches[tag[k]] += 1;
+    }
+  }
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_plan_info(pfmm_plan_t pl, int* s, int64_t* table_entries) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (s) *s = pl->s;
+  if (table_entries) *table_entries = cube(8 * pl->p - 1);
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_plan_destroy(pfmm_plan_t pl) {
+  g_err.clear();
+  if (!pl) return PFMM_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_live.erase(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  }
+  hipError_t e = hipStreamSynchronize(pl->stream);
+  release(pl);
+  if (e != hipSuccess) return hip_fail(e, "destroy");
+  return PFMM_OK;
+}
+
+const char* pfmm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,314 @@
+// Upward and downward passes of the FMM on the uniform tree (Sec. 2):
+//   P2M  leaf cells -> leaf gridlet (effective masses with the same Cartesian
+//        moments 0 <= n_i < p; the 1D weights are the Lagrange basis of the
+//        gridlet nodes evaluated at the cell centres),
+//   M2M  Eq. 5, child gridlets -> parent gridlet,
+//   L2L  Eq. 7, parent local field -> child gridlets (the transposed operator,
+//        i.e. Lagrange interpolation),
+//   L2P  leaf gridlet -> cells (transpose of P2M),
+//   FD4  a = -grad(phi) by periodic 4th-order central differences (Sec. 3).
+// Every operator is a tensor product of 1D operators and is applied as three
+// successive 1D contractions on a block staged in LDS.  These stages move a
+// few bytes per cell and are bound by memory traffic, not arithmetic.
+//
+// Gridlet buffers of a level are FP32 or FP64 (coarse levels can be kept in
+// FP64: the interpolation of Eq. 7 extrapolates past the parent's outermost
+// gridlet nodes, so rounding noise of a parent's field is amplified in its
+// children); each kernel computes in the wider of its operand types.
+#include "internal.h"
+
+namespace pfmm {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <class W> __device__ inline const W* wsel(Weights w);
+template <> __device__ inline const float* wsel<float>(Weights w) { return w.f; }
+template <> __device__ inline const double* wsel<double>(Weights w) { return w.d; }
+
+template <class TO, class W>
+__global__ __launch_bounds__(kThreads) void k_p2m(const float* __restrict__ rho,
+                                                   TO* __restrict__ M, Weights Aw, int N, int s,
+                                                   int p, W h3) {
+  extern __shared__ __align__(8) unsigned char smraw[];
+  W* sm = reinterpret_cast<W*>(smraw);
+  W* sA = sm;              // [p][s]
+  W* sr = sA + p * s;      // [s][s][s]
+  W* t1 = sr + s * s * s;  // [cx][cy][az]
+  W* t2 = t1 + s * s * p;  // [cx][ay][az]
+  const W* A = wsel<W>(Aw);
+  const int nL = N / s;
+  const int b = blockIdx.x;
+  const int bx = b / (nL * nL), by = (b / nL) % nL, bz = b % nL;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < p * s; i += kThreads) sA[i] = A[i];
+  for (int i = tid; i < s * s * s; i += kThreads) {
+    const int cx = i / (s * s), cy = (i / s) % s, cz = i % s;
+    sr[i] = (W)rho[((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz)];
+  }
+  __syncthreads();
+  for (int i = tid; i < s * s * p; i += kThreads) {
+    const int cxy = i / p, az = i % p;
+    W acc = 0;
+    for (int cz = 0; cz < s; ++cz) acc += sA[az * s + cz] * sr[cxy * s + cz];
+    t1[i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < s * p * p; i += kThreads) {
+    const int cx = i / (p * p), ay = (i / p) % p, az = i % p;
+    W acc = 0;
+    for (int cy = 0; cy < s; ++cy) acc += sA[ay * s + cy] * t1[(cx * s + cy) * p + az];
+    t2[i] = acc;
+  }
+  __syncthreads();
+  const int p3 = p * p * p;
+  for (int i = tid; i < p3; i += kThreads) {
+    const int ax = i / (p * p), ayz = i % (p * p);
+    W acc = 0;
+    for (int cx = 0; cx < s; ++cx) acc += sA[ax * s + cx] * t2[cx * p * p + ayz];
+    M[(size_t)b * p3 + i] = (TO)(h3 * acc);
+  }
+}
+
+template <class TI, class TO, class W>
+__global__ __launch_bounds__(kThreads) void k_m2m(const TI* __restrict__ Mc,
+                                                   TO* __restrict__ Mp, Weights Tw, int np,
+                                                   int p) {
+  extern __shared__ __align__(8) unsigned char smraw[];
+  W* sm = reinterpret_cast<W*>(smraw);
+  const int p3 = p * p * p;
+  W* sT = sm;  // [o][a][a']
+  W* c = sT + 2 * p * p;
+  W* u1 = c + p3;
+  W* u2 = u1 + p3;
+  const W* T = wsel<W>(Tw);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * p * p; i += kThreads) sT[i] = T[i];
+  const int B = blockIdx.x;
+  const int Bx = B / (np * np), By = (B / np) % np, Bz = B % np;
+  const int nc = 2 * np;
+  W acc[4] = {0, 0, 0, 0};  // p^3 <= 1000 <= 4 * kThreads
+  for (int o = 0; o < 8; ++o) {
+    const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
+    const size_t child = ((size_t)(2 * Bx + ox) * nc + (2 * By + oy)) * nc + (2 * Bz + oz);
+    __syncthreads();
+    for (int i = tid; i < p3; i += kThreads) c[i] = (W)Mc[child * p3 + i];
+    __syncthreads();
+    const W* Tz = sT + oz * p * p;
+    const W* Ty = sT + oy * p * p;
+    const W* Tx = sT + ox * p * p;
+    for (int i = tid; i < p3; i += kThreads) {  // u1[a'x][a'y][az]
+      const int xy = i / p, az = i % p;
+      W v = 0;
+      for (int k = 0; k < p; ++k) v += Tz[az * p + k] * c[xy * p + k];
+      u1[i] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < p3; i += kThreads) {  // u2[a'x][ay][az]
+      const int x = i / (p * p), ay = (i / p) % p, az = i % p;
+      W v = 0;
+      for (int k = 0; k < p; ++k) v += Ty[ay * p + k] * u1[(x * p + k) * p + az];
+      u2[i] = v;
+    }
+    __syncthreads();
+    for (int i = tid, r = 0; i < p3; i += kThreads, ++r) {  // out[ax][ay][az]
+      const int ax = i / (p * p), yz = i % (p * p);
+      W v = 0;
+      for (int k = 0; k < p; ++k) v += Tx[ax * p + k] * u2[k * p * p + yz];
+      acc[r] += v;
+    }
+  }
+  for (int i = tid, r = 0; i < p3; i += kThreads, ++r) Mp[(size_t)B * p3 + i] = (TO)acc[r];
+}
+
+template <class TI, class TO, class W>
+__global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
+                                                   TO* __restrict__ Pc, Weights Tw, int np,
+                                                   int p) {
+  extern __shared__ __align__(8) unsigned char smraw[];
+  W* sm = reinterpret_cast<W*>(smraw);
+  const int p3 = p * p * p;
+  W* sT = sm;
+  W* par = sT + 2 * p * p;
+  W* v1 = par + p3;
+  W* v2 = v1 + p3;
+  const W* T = wsel<W>(Tw);
+  const int tid = threadIdx.x;
+  const int B = blockIdx.x;
+  const int Bx = B / (np * np), By = (B / np) % np, Bz = B % np;
+  const int nc = 2 * np;
+  for (int i = tid; i < 2 * p * p; i += kThreads) sT[i] = T[i];
+  for (int i = tid; i < p3; i += kThreads) par[i] = (W)Pp[(size_t)B * p3 + i];
+  for (int o = 0; o < 8; ++o) {
+    const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
+    const W* Tz = sT + oz * p * p;
+    const W* Ty = sT + oy * p * p;
+    const W* Tx = sT + ox * p * p;
+    __syncthreads();
+    for (int i = tid; i < p3; i += kThreads) {  // v1[ax][ay][a'z] = sum_az Tz[az][a'z] par
+      const int xy = i / p, bz = i % p;
+      W v = 0;
+      for (int k = 0; k < p; ++k) v += Tz[k * p + bz] * par[xy * p + k];
+      v1[i] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < p3; i += kThreads) {  // v2[ax][a'y][a'z]
+      const int x = i / (p * p), by = (i / p) % p, bz = i % p;
+      W v = 0;
+      for (int k = 0; k < p; ++k) v += Ty[k * p + by] * v1[(x * p + k) * p + bz];
+      v2[i] = v;
+    }
+    __syncthreads();
+    const size_t child = ((size_t)(2 * Bx + ox) * nc + (2 * By + oy)) * nc + (2 * Bz + oz);
+    for (int i = tid; i < p3; i += kThreads) {  // out[a'x][a'y][a'z]
+      const int bx = i / (p * p), yz = i % (p * p);
+      W v = 0;
+      for (int k = 0; k < p; ++k) v += Tx[k * p + bx] * v2[k * p * p + yz];
+      Pc[child * p3 + i] = (TO)v;
+    }
+  }
+}
+
+template <class TI, class W>
+__global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
+                                                   float* __restrict__ phi, Weights Aw, int N,
+                                                   int s, int p) {
+  extern __shared__ __align__(8) unsigned char smraw[];
+  W* sm = reinterpret_cast<W*>(smraw);
+  const int p3 = p * p * p;
+  W* sA = sm;              // [p][s]
+  W* sp = sA + p * s;      // [ax][ay][az]
+  W* w1 = sp + p3;         // [ax][ay][cz]
+  W* w2 = w1 + p * p * s;  // [ax][cy][cz]
+  const W* A = wsel<W>(Aw);
+  const int nL = N / s;
+  const int b = blockIdx.x;
+  const int bx = b / (nL * nL), by = (b / nL) % nL, bz = b % nL;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < p * s; i += kThreads) sA[i] = A[i];
+  for (int i = tid; i < p3; i += kThreads) sp[i] = (W)P[(size_t)b * p3 + i];
+  __syncthreads();
+  for (int i = tid; i < p * p * s; i += kThreads) {
+    const int xy = i / s, cz = i % s;
+    W v = 0;
+    for (int k = 0; k < p; ++k) v += sA[k * s + cz] * sp[xy * p + k];
+    w1[i] = v;
+  }
+  __syncthreads();
+  for (int i = tid; i < p * s * s; i += kThreads) {
+    const int ax = i / (s * s), cy = (i / s) % s, cz = i % s;
+    W v = 0;
+    for (int k = 0; k < p; ++k) v += sA[k * s + cy] * w1[(ax * p + k) * s + cz];
+    w2[i] = v;
+  }
+  __syncthreads();
+  for (int i = tid; i < s * s * s; i += kThreads) {
+    const int cx = i / (s * s), cyz = i % (s * s);
+    W v = 0;
+    for (int k = 0; k < p; ++k) v += sA[k * s + cx] * w2[k * s * s + cyz];
+    const int cy = cyz / s, cz = cyz % s;
+    phi[((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz)] = (float)v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fd4(const float* __restrict__ phi,
+                                                   float* __restrict__ acc, int N) {
+  const size_t n3 = (size_t)N * N * N;
+  const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n3) return;
+  const int z = (int)(i % N), y = (int)((i / N) % N), x = (int)(i / ((size_t)N * N));
+  const int mk = N - 1;
+  const float inv12h = (float)N / 12.0f;
+  auto at = [&](int xx, int yy, int zz) {
+    return phi[((size_t)(xx & mk) * N + (yy & mk)) * N + (zz & mk)];
+  };
+  const float gx = -at(x + 2, y, z) + 8.f * at(x + 1, y, z) - 8.f * at(x - 1, y, z) + at(x - 2, y, z);
+  const float gy = -at(x, y + 2, z) + 8.f * at(x, y + 1, z) - 8.f * at(x, y - 1, z) + at(x, y - 2, z);
+  const float gz = -at(x, y, z + 2) + 8.f * at(x, y, z + 1) - 8.f * at(x, y, z - 1) + at(x, y, z - 2);
+  acc[i] = -gx * inv12h;
+  acc[n3 + i] = -gy * inv12h;
+  acc[2 * n3 + i] = -gz * inv12h;
+}
+
+__global__ void k_d2f(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = (float)s[i];
+}
+
+}  // namespace
+
+hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int s, int p,
+                      double h3, hipStream_t st) {
+  const int nL = N / s;
+  const size_t words = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
+  if (m64)
+    hipLaunchKernelGGL((k_p2m<double, double>), dim3(nL * nL * nL), dim3(kThreads),
+                       words * sizeof(double), st, rho, (double*)M, A, N, s, p, h3);
+  else
+    hipLaunchKernelGGL((k_p2m<float, float>), dim3(nL * nL * nL), dim3(kThreads),
+                       words * sizeof(float), st, rho, (float*)M, A, N, s, p, (float)h3);
+  return hipGetLastError();
+}
+
+hipError_t launch_m2m(const void* Mc, int c64, void* Mp, int p64, Weights T, int np, int p,
+                      hipStream_t st) {
+  const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
+  const dim3 g(np * np * np), b(kThreads);
+  if (!c64 && !p64)
+    hipLaunchKernelGGL((k_m2m<float, float, float>), g, b, words * 4, st, (const float*)Mc,
+                       (float*)Mp, T, np, p);
+  else if (!c64 && p64)
+    hipLaunchKernelGGL((k_m2m<float, double, double>), g, b, words * 8, st, (const float*)Mc,
+                       (double*)Mp, T, np, p);
+  else if (c64 && p64)
+    hipLaunchKernelGGL((k_m2m<double, double, double>), g, b, words * 8, st, (const double*)Mc,
+                       (double*)Mp, T, np, p);
+  else
+    return hipErrorInvalidValue;  // a finer level is never wider than its parent
+  return hipGetLastError();
+}
+
+hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int np, int p,
+                      hipStream_t st) {
+  const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
+  const dim3 g(np * np * np), b(kThreads);
+  if (!p64 && !c64)
+    hipLaunchKernelGGL((k_l2l<float, float, float>), g, b, words * 4, st, (const float*)Pp,
+                       (float*)Pc, T, np, p);
+  else if (p64 && !c64)
+    hipLaunchKernelGGL((k_l2l<double, float, double>), g, b, words * 8, st, (const double*)Pp,
+                       (float*)Pc, T, np, p);
+  else if (p64 && c64)
+    hipLaunchKernelGGL((k_l2l<double, double, double>), g, b, words * 8, st, (const double*)Pp,
+                       (double*)Pc, T, np, p);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_l2p(const void* P, int p64, float* phi, Weights A, int N, int s, int p,
+                      hipStream_t st) {
+  const int nL = N / s;
+  const size_t words = (size_t)(p * s + p * p * p + p * p * s + p * s * s);
+  if (p64)
+    hipLaunchKernelGGL((k_l2p<double, double>), dim3(nL * nL * nL), dim3(kThreads),
+                       words * sizeof(double), st, (const double*)P, phi, A, N, s, p);
+  else
+    hipLaunchKernelGGL((k_l2p<float, float>), dim3(nL * nL * nL), dim3(kThreads),
+                       words * sizeof(float), st, (const float*)P, phi, A, N, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_fd4(const float* phi, float* acc, int N, hipStream_t st) {
+  const size_t n3 = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_fd4, dim3((unsigned)((n3 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     st, phi, acc, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_d2f(const double* src, float* dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace pfmm

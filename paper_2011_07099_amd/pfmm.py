@@ -1,0 +1,175 @@
+"""Thin ctypes binding of libpfmm (C ABI in include/pfmm.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  torch supplies device memory (``data_ptr()``) and streams.  The
+library is loaded from this package directory; if it is missing, every call
+raises — there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfmm.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP = range(5)
+GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3}
+PREC = {"fp32": 0, "bf16x3": 1}
+OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS = 1, 2, 3, 4, 5
+STAGES = ("p2m", "m2m", "m2l", "l2l", "l2p", "near", "fd4")
+BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
+
+# every symbol include/pfmm.h declares
+EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_plan_read",
+           "pfmm_plan_stage_times", "pfmm_plan_info", "pfmm_plan_destroy", "pfmm_last_error")
+
+_lib = None
+
+
+class PfmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("pfmm status %d: %s" % (status, msg))
+        self.status = status
+
+
+def load():
+    """Open libpfmm.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpfmm.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    lib.pfmm_plan_create.argtypes = [i32, i32, i32, i32, ctypes.POINTER(vp)]
+    lib.pfmm_plan_set.argtypes = [vp, i32, vp, sz]
+    lib.pfmm_solve.argtypes = [vp, vp, vp, vp]
+    lib.pfmm_plan_read.argtypes = [vp, i32, i32, vp]
+    lib.pfmm_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(i32)]
+    lib.pfmm_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
+    lib.pfmm_plan_destroy.argtypes = [vp]
+    lib.pfmm_last_error.restype = ctypes.c_char_p
+    for f in EXPORTS[:-1]:
+        getattr(lib, f).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != OK:
+        raise PfmmError(st, load().pfmm_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A periodic-FMM plan: ``Plan(N, L, p, green)`` then ``solve(rho, phi[, accel])``.
+
+    ``green`` is one of "X", "K", "S1", "S" (see include/pfmm.h).  ``stream``
+    is a torch.cuda.Stream (default: torch's current stream at creation).
+    """
+
+    def __init__(self, N, L, p, green="S1", precision="fp32", a1=None, stream=None,
+                 fp64_levels=None):
+        import torch
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.pfmm_plan_create(int(N), int(L), int(p), GREEN[green], ctypes.byref(h)))
+        self._h = h
+        self.N, self.L, self.p, self.green = int(N), int(L), int(p), green
+        s = ctypes.c_int()
+        _check(lib.pfmm_plan_info(self._h, ctypes.byref(s), None))
+        self.s = s.value
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.set_stream(stream)
+        if precision != "fp32":
+            self.set_precision(precision)
+        if a1 is not None:
+            self.set_a1(a1)
+        if fp64_levels is not None:
+            self.set_fp64_levels(fp64_levels)
+
+    def set_fp64_levels(self, n):
+        v = ctypes.c_int32(int(n))
+        _check(load().pfmm_plan_set(self._h, OPT_FP64_LEVELS, ctypes.byref(v), 4))
+
+    def set_stream(self, stream):
+        self.stream = stream
+        v = ctypes.c_void_p(stream.cuda_stream)
+        _check(load().pfmm_plan_set(self._h, OPT_STREAM, ctypes.byref(v), ctypes.sizeof(v)))
+
+    def set_precision(self, precision):
+        v = ctypes.c_int32(PREC[precision])
+        _check(load().pfmm_plan_set(self._h, OPT_PRECISION, ctypes.byref(v), 4))
+        self.precision = precision
+
+    def set_a1(self, a1):
+        v = ctypes.c_double(float(a1))
+        _check(load().pfmm_plan_set(self._h, OPT_GS_A1, ctypes.byref(v), 8))
+
+    def set_profile(self, on):
+        v = ctypes.c_int32(1 if on else 0)
+        _check(load().pfmm_plan_set(self._h, OPT_PROFILE, ctypes.byref(v), 4))
+
+    def stage_times(self):
+        """{stage: (ms, launches)} of the last profiled solve (synchronises)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_int * len(STAGES))()
+        _check(load().pfmm_plan_stage_times(self._h, ms, n))
+        return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+    def solve(self, rho, phi, accel=None):
+        import torch
+        n3 = self.N ** 3
+        for t, n in ((rho, n3), (phi, n3)) + (((accel, 3 * n3),) if accel is not None else ()):
+            if t.dtype != torch.float32 or t.numel() != n:
+                raise ValueError("expected float32 tensors of N^3 (accel 3 N^3) elements")
+        _check(load().pfmm_solve(self._h, _ptr(rho), _ptr(phi), _ptr(accel)))
+
+    def read(self, buffer, level, out):
+        _check(load().pfmm_plan_read(self._h, int(buffer), int(level), _ptr(out)))
+        return out
+
+    def multipoles(self, level):
+        import torch
+        out = torch.empty(8 ** level * self.p ** 3, dtype=torch.float32, device="cuda")
+        return self.read(BUF_MULTIPOLE, level, out)
+
+    def locals(self, level):
+        import torch
+        out = torch.empty(8 ** level * self.p ** 3, dtype=torch.float32, device="cuda")
+        return self.read(BUF_LOCAL, level, out)
+
+    def level_table(self, level):
+        import torch
+        out = torch.empty((8 * self.p - 1) ** 3, dtype=torch.float64, device="cuda")
+        return self.read(BUF_TABLE_LEVEL, level, out)
+
+    def near_table(self):
+        import torch
+        out = torch.empty((4 * self.s - 1) ** 3, dtype=torch.float64, device="cuda")
+        return self.read(BUF_TABLE_NEAR, 2, out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().pfmm_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

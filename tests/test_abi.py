@@ -1,0 +1,66 @@
+"""The C ABI without a GPU: the library loads, exports every symbol that
+include/pfmm.h declares, and rejects invalid arguments before touching the
+device (host-side validation only; no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pfmm.h")).read()
+    return sorted(set(re.findall(r"\b(pfmm_[a-z_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_2011_07099_amd import pfmm
+    if not os.path.exists(pfmm.LIB_PATH):
+        pytest.skip("libpfmm.so not built")
+    return pfmm.load()
+
+
+def test_header_declares_the_binding_exports():
+    from paper_2011_07099_amd import pfmm
+    assert _declared() == sorted(pfmm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("N,L,p,g", [
+    (12, 2, 4, 2),     # N not a power of two
+    (4, 2, 2, 2),      # N too small
+    (2048, 8, 4, 2),   # N too large
+    (16, 1, 4, 2),     # L < 2
+    (16, 5, 4, 2),     # 2^L > N
+    (16, 3, 0, 2),     # p < 1
+    (16, 3, 11, 2),    # p > 10
+    (16, 3, 4, 9),     # unknown Green's function
+])
+def test_invalid_plan_arguments(N, L, p, g):
+    lib = _lib()
+    h = ctypes.c_void_p(1)
+    st = lib.pfmm_plan_create(N, L, p, g, ctypes.byref(h))
+    assert st == 1 and h.value is None
+    assert lib.pfmm_last_error().decode()
+
+
+def test_unsupported_leaf_width():
+    lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.pfmm_plan_create(1024, 4, 4, 2, ctypes.byref(h)) == 2  # s = 64
+
+
+def test_bad_handles():
+    lib = _lib()
+    bogus = ctypes.c_void_p(0x1234)
+    assert lib.pfmm_solve(bogus, None, None, None) == 1
+    assert lib.pfmm_plan_destroy(bogus) == 1
+    assert lib.pfmm_plan_destroy(None) == 0
+    assert lib.pfmm_plan_create(16, 3, 4, 2, None) == 1

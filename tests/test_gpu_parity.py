@@ -1,0 +1,166 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU FP64 oracle.
+
+* tables  — FP64 device tabulation of G_X (Eq. 2), G_K (Eq. 1), G_S1 (Eq. 9)
+  and G_S (Sec. 3 ansatz) against the oracle's formulas: 1e-12 relative.
+* stages  — gridlet masses of every level (P2M, Eq. 5), gridlet potentials
+  (Eq. 6 + Eq. 7) and the potential on the mesh against the step-by-step
+  reference FMM, on the same FP32-rounded density.
+* exactness — two levels with gridlet = leaf reproduce the direct periodic
+  convolution (Sec. 3, "identical by construction").
+
+FP32 tolerance.  Every output is a sum of products of FP32-rounded operands
+(unit roundoff u = 2^-24 ~ 6e-8) over at most ~1e5 terms per level, so the
+error relative to the largest output stays within a small multiple of
+u * sqrt(#terms) * (sum |terms| / max |result|); for these zero-mean fields
+that is well under 1e-5 (FP32_TOL).  Measured values are printed.
+"""
+import numpy as np
+import pytest
+
+from oracle import conv, fd, fmm as ofmm
+from oracle import green as ogreen
+from paper_2011_07099_amd import fields
+
+from gpu_util import f32, rel_l2, rel_max, solve
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+def _white(N, seed):
+    r = np.random.default_rng(seed).standard_normal((N, N, N))
+    return r - r.mean()
+
+
+# ---------------------------------------------------------------------------
+# Green's-function tables (FP64 on the device)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,a1", [("X", None), ("S1", None), ("K", None), ("S", -0.12)])
+@pytest.mark.parametrize("N,L,p", [(16, 3, 4), (64, 3, 6), (32, 2, 3)])
+def test_tables_match_oracle(kind, a1, N, L, p):
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    a = (a1,) if a1 is not None else (-0.125,)
+    with Plan(N, L, p, kind, a1=a1) as pl:
+        for l in range(2, L + 1):
+            got = pl.level_table(l).cpu().numpy().reshape((8 * p - 1,) * 3)
+            ref, J = ofmm.m2l_table(kind, N, l, p, a)
+            assert J == 4 * p - 1
+            ok = np.isfinite(ref)
+            ok[J, J, J] = False        # the zero separation is never used by M2L
+            err = np.max(np.abs(got[ok] - ref[ok])) / np.max(np.abs(ref[ok]))
+            print(kind, N, l, p, "level table rel err", err)
+            assert err < 1e-12
+        got = pl.near_table().cpu().numpy().reshape((4 * pl.s - 1,) * 3)
+        torch.cuda.synchronize()
+    ref, J = ofmm.near_table(kind, N, N >> L, a)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(kind, N, "near table rel err", err)
+    assert err < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# stage-by-stage against the reference FMM
+# ---------------------------------------------------------------------------
+
+CASES = [
+    # (name, N, L, p, green, density)
+    ("cfg1 blobs", 16, 3, 4, "X", lambda: fields.blobs(16, 32, 0.03, seed=1)),
+    ("white s=4", 32, 3, 4, "S1", lambda: _white(32, 2)),
+    ("cfg2 p8 GX", 64, 3, 8, "X", lambda: fields.lognormal(64, 2.0, 1.0, seed=2)),
+    ("cfg2 p4 GK", 64, 3, 4, "K", lambda: fields.lognormal(64, 2.0, 1.0, seed=3)),
+    ("cfg2 p8 GK", 64, 3, 8, "K", lambda: fields.lognormal(64, 2.0, 1.0, seed=3)),
+    ("p6 GS1", 32, 3, 6, "S1", lambda: fields.lognormal(32, 2.0, 1.0, seed=4)),
+    ("s=16 near split", 64, 2, 4, "S1", lambda: _white(64, 5)),
+    ("L=4 s=8", 128, 4, 4, "S1", lambda: fields.lognormal(128, 2.0, 1.0, seed=6)),
+]
+
+
+@pytest.mark.parametrize("name,N,L,p,green,make", CASES, ids=[c[0] for c in CASES])
+def test_stages_match_reference_fmm(name, N, L, p, green, make):
+    rho = f32(make())
+    gpu = solve(rho, L, p, green, stages=True)
+    ref, st = ofmm.fmm(rho, L, p, green, stages=True)
+    for l in range(L, 1, -1):
+        e = rel_max(gpu["M"][l], st["M"][l])
+        print(name, "M level", l, e)
+        assert e < FP32_TOL
+    for l in range(2, L + 1):
+        e = rel_max(gpu["Phi"][l], st["Phi"][l])
+        print(name, "Phi level", l, e)
+        assert e < FP32_TOL
+    e1, e2 = rel_max(gpu["phi"], ref), rel_l2(gpu["phi"], ref)
+    print(name, "potential rel max", e1, "rel L2", e2)
+    assert e1 < FP32_TOL and e2 < FP32_TOL
+
+
+@pytest.mark.parametrize("green", ["X", "S1", "K"])
+@pytest.mark.parametrize("N,p", [(8, 2), (16, 4), (32, 8)])
+def test_two_levels_gridlet_equals_leaf_is_direct(green, N, p):
+    # L = 2 and s = p: near zone + level-2 zone cover every source once with
+    # exact (gridlet = cell) representation, so FMM = PM with the same G
+    rho = f32(_white(N, 7))
+    gpu = solve(rho, 2, p, green)["phi"]
+    ref = conv.pm(rho, green)
+    e = rel_max(gpu, ref)
+    print(green, N, p, "L=2 exactness", e)
+    assert e < FP32_TOL
+
+
+EDGE = [
+    ("p=1", 16, 3, 1, "S1"),
+    ("p=3 odd", 16, 2, 3, "X"),
+    ("p=5", 32, 3, 5, "S1"),
+    ("p=7", 16, 2, 7, "K"),
+    ("p=9", 32, 3, 9, "S1"),
+    ("p=10 max", 32, 3, 10, "X"),
+    ("s=1", 8, 3, 2, "S1"),
+    ("N=8 minimal", 8, 2, 2, "K"),
+    ("s<p", 32, 3, 8, "S1"),
+]
+
+
+@pytest.mark.parametrize("name,N,L,p,green", EDGE, ids=[c[0] for c in EDGE])
+def test_edge_cases_match_reference_fmm(name, N, L, p, green):
+    rho = f32(_white(N, 8))
+    gpu = solve(rho, L, p, green)["phi"]
+    ref = ofmm.fmm(rho, L, p, green)
+    e = rel_max(gpu, ref)
+    print(name, "rel max", e)
+    assert e < FP32_TOL
+
+
+def test_accel_matches_fd4_of_reference():
+    N, L, p = 32, 3, 4
+    rho = f32(fields.lognormal(N, 2.0, 1.0, seed=9))
+    gpu = solve(rho, L, p, "S1", accel=True)
+    ref = fd.accel_fd4(ofmm.fmm(rho, L, p, "S1"))
+    e = rel_max(gpu["accel"], ref)
+    print("accel rel max", e)
+    assert e < FP32_TOL
+
+
+def test_gs_a1_option_changes_tables():
+    # G_S with a1 = -1/8 is G_S1 (Sec. 3 / Eq. 9); another a1 differs
+    rho = f32(_white(16, 10))
+    a = solve(rho, 3, 4, "S", a1=-0.125)["phi"]
+    b = solve(rho, 3, 4, "S1")["phi"]
+    c = solve(rho, 3, 4, "S", a1=-0.1)["phi"]
+    assert rel_max(a, b) < 1e-6
+    assert rel_max(c, b) > 1e-4
+
+
+def test_repeated_solves_are_identical():
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    N = 32
+    rho = torch.from_numpy(_white(N, 11).astype(np.float32)).cuda()
+    outs = []
+    with Plan(N, 3, 4, "S1") as pl:
+        for _ in range(3):
+            phi = torch.full_like(rho, float("nan"))
+            pl.solve(rho, phi)
+            outs.append(phi.cpu())
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
