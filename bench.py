@@ -74,6 +74,21 @@ def cpu_baseline(rho64, phi_gpu, n_side=8):
     return base, acc
 
 
+def copy_reference():
+    """Plain streaming kernels over 1 GiB: a device-to-device copy and an
+    elementwise kernel that reads one 1 GiB array and writes another."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print("copied 2 x 2 x %d bytes" % (4 * n), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,7 +96,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run a plain 1 GiB device copy (3 times): the reference that "
+                         "scales FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
+    if args.copy_ref:
+        copy_reference()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); a multi-GPU "
               "sharding is described in DESIGN.md but not built", file=sys.stderr)
