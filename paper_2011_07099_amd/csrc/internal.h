@@ -55,6 +55,34 @@ inline int pack_offset(int dx, int dy, int dz) {
 hipError_t launch_toeplitz(const ToepArgs& a, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// Split-precision block-Toeplitz operator on the BF16 matrix cores for 8^3
+// blocks (toeplitz_mfma.hip).  Operands are held as nt in {2, 3} bf16 terms.
+// Windows of a table are precomputed per offset in [-3, 3]^3
+// (window_dwords(nt) uint32 per table); sources are nt term arrays
+// [n^3][512] laid out one after another in X.  `groups` > 1 splits each
+// class's offsets over workgroups that write `partial` [groups][n^3][512],
+// summed in order into Y.
+// ---------------------------------------------------------------------------
+struct ToepMfmaArgs {
+  int n, m, noff;
+  const int* offs;
+  const uint32_t* win;
+  const uint16_t* X;
+  float* Y;
+  int grid_out;
+  int accumulate;
+  int groups;
+  float* partial;
+};
+bool toep8_supported(int n, int m);
+size_t window_dwords(int nt);
+hipError_t make_windows(const double* tab64, int C, int nt, uint32_t* win, hipStream_t st);
+hipError_t split_blocks(const float* X, uint16_t* out, int nt, int64_t n, hipStream_t st);
+hipError_t split_mesh(const float* rho, float scale, int N, int nt, uint16_t* out,
+                      hipStream_t st);
+hipError_t launch_toep8_split(const ToepMfmaArgs& a, int nt, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // Upward / downward passes (tensor products of 1D Lagrange operators).
 // Gridlet buffers are FP32 or FP64 per level; `*64` flags give the type of
 // each operand (0 = float, 1 = double).  Weights are passed in both types.

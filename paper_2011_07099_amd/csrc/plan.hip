@@ -17,6 +17,7 @@
 #include "../../include/pfmm.h"
 #include "internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -45,6 +46,13 @@ struct pfmm_plan_s {
   int* offs_l2 = nullptr;         // [37]
   int* offs_iz = nullptr;         // [8][189]
   int* offs_near = nullptr;       // [mn^3][(3 mn)^3]
+  // split-precision matrix-core path (8^3 blocks)
+  std::vector<uint32_t*> win;     // per level: table windows (p == 8)
+  uint32_t* nwin = nullptr;       // near-table windows (8^3-cell sub-blocks)
+  uint16_t* xs = nullptr;         // bf16 source terms (up to 3 arrays of xwords)
+  size_t xwords = 0;
+  float* part = nullptr;          // split-offset partial sums
+  size_t part_floats = 0;
   std::vector<void*> owned;
   // stage timing (PFMM_OPT_PROFILE): a ring of event sets, one per solve
   int profile = 0;
@@ -55,6 +63,10 @@ struct pfmm_plan_s {
 };
 
 namespace {
+// bf16 terms per operand on the matrix-core path: interaction zones (gridlet
+// masses cancel strongly) and near zone (cell masses)
+constexpr int kM2LTerms = 3;
+constexpr int kNearTerms = 2;
 constexpr int kMaxEvents = 64;  // per solve
 constexpr int kSlots = 16;      // most recent profiled solves kept
 }
@@ -109,9 +121,9 @@ hipError_t dalloc(pfmm_plan_s* pl, T** ptr, size_t count) {
 
 void release(pfmm_plan_s* pl) {
   for (hipEvent_t e : pl->ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   pl->ev.clear();
-  for (void* q : pl->owned) hipFree(q);
+  for (void* q : pl->owned) (void)hipFree(q);
   pl->owned.clear();
   delete pl;
 }
@@ -150,9 +162,21 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
   hipError_t e = tabulate_green(pl->green, pl->a1, pl->N, Cn, pl->N, 1.0 / pl->N, pl->ntab64,
                                 pl->stream);
   if (e == hipSuccess) e = cast_f64_f32(pl->ntab64, pl->ntab32, cube(2 * Cn + 1), pl->stream);
+  for (int l = 2; l <= pl->L && e == hipSuccess; ++l)
+    if (pl->win[l]) e = make_windows(pl->tab64[l], C, kM2LTerms, pl->win[l], pl->stream);
+  if (e == hipSuccess && pl->nwin)
+    e = make_windows(pl->ntab64, Cn, kNearTerms, pl->nwin, pl->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
   if (e != hipSuccess) return hip_fail(e, "tabulate near table");
   return PFMM_OK;
+}
+
+// Offset groups of a level's matrix-core launch: enough workgroups to give
+// the 256 compute units two rounds (a level-l launch has 8^(l-2) tiles).
+int m2l_groups(int l) {
+  const int tiles = 1 << (3 * (l - 2));
+  int g = (512 + tiles - 1) / tiles;
+  return g > 37 ? 37 : g;
 }
 
 pfmm_status build(pfmm_plan_s* pl) {
@@ -228,6 +252,39 @@ pfmm_status build(pfmm_plan_s* pl) {
   e = dalloc(pl, &pl->ntab32, nnear);
   if ((st = chk("near table"))) return st;
 
+  // matrix-core path: windows, split sources and partial sums, sized for
+  // every level / near zone it can serve
+  pl->win.assign(L + 1, nullptr);
+  size_t xwords = 0;
+  if (p == 8) {
+    for (int l = 2; l <= L; ++l) {
+      if (!toep8_supported(1 << l, l == 2 ? 1 : 2)) continue;
+      e = dalloc(pl, &pl->win[l], window_dwords(kM2LTerms));
+      if ((st = chk("level windows"))) return st;
+      const size_t nodes = (size_t)1 << (3 * l);
+      xwords = std::max(xwords, nodes * 512);
+      const int G = m2l_groups(l);
+      pl->part_floats = std::max(pl->part_floats, G > 1 ? (size_t)G * nodes * 512 : (size_t)0);
+    }
+  }
+  {
+    const int qn = s <= 8 ? s : 8, mn = s / qn;
+    if (qn == 8 && toep8_supported(N / 8, mn)) {
+      e = dalloc(pl, &pl->nwin, window_dwords(kNearTerms));
+      if ((st = chk("near windows"))) return st;
+      xwords = std::max(xwords, (size_t)N * N * N);
+    }
+  }
+  if (xwords) {
+    pl->xwords = xwords;
+    e = dalloc(pl, &pl->xs, 3 * xwords);
+    if ((st = chk("split sources"))) return st;
+  }
+  if (pl->part_floats) {
+    e = dalloc(pl, &pl->part, pl->part_floats);
+    if ((st = chk("partial sums"))) return st;
+  }
+
   // zones (Sec. 2, Fig. 2)
   std::vector<int> l2, iz, nz;
   for (int dx = -2; dx <= 1; ++dx)
@@ -299,7 +356,7 @@ pfmm_status pfmm_plan_create(int N, int L, int p, int green_kind, pfmm_plan_t* o
   pl->green = green_kind;
   pfmm_status st = build(pl);
   if (st != PFMM_OK) {
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     release(pl);
     return st;
   }
@@ -322,7 +379,6 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       std::memcpy(&v, value, sizeof v);
       if (v != PFMM_PREC_FP32 && v != PFMM_PREC_BF16X3)
         return fail(PFMM_ERR_INVALID_ARG, "unknown precision");
-      if (v != PFMM_PREC_FP32) return fail(PFMM_ERR_UNSUPPORTED, "precision not built yet");
       pl->prec = v;
       return PFMM_OK;
     }
@@ -389,6 +445,26 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
 
   const Weights A = wts(pl->dA, pl->dA64), T = wts(pl->dT, pl->dT64);
   auto is64 = [&](int l) { return (int)level64(pl, l); };
+  const bool mx = pl->prec == PFMM_PREC_BF16X3;
+  // interaction zone of one level: matrix cores for FP32 levels with windows
+  auto m2l = [&](const ToepArgs& ta, int l) -> hipError_t {
+    if (!mx || ta.fp64 || !pl->win[l]) return launch_toeplitz(ta, st);
+    const size_t nodes = (size_t)1 << (3 * l);
+    hipError_t r = split_blocks((const float*)ta.X, pl->xs, kM2LTerms, (int64_t)(nodes * 512), st);
+    if (r != hipSuccess) return r;
+    ToepMfmaArgs ma{};
+    ma.n = ta.n;
+    ma.m = ta.m;
+    ma.noff = ta.noff;
+    ma.offs = ta.offs;
+    ma.win = pl->win[l];
+    ma.X = pl->xs;
+    ma.Y = (float*)ta.Y;
+    ma.accumulate = ta.accumulate;
+    ma.groups = std::min(m2l_groups(l), ta.noff);
+    ma.partial = ma.groups > 1 ? pl->part : nullptr;
+    return launch_toep8_split(ma, kM2LTerms, st);
+  };
 
   // upward pass
   e = launch_p2m(rho, pl->M[L], is64(L), A, N, s, p, (double)h3, st);
@@ -414,7 +490,7 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   a.X = pl->M[2];
   a.Y = pl->P[2];
   a.accumulate = 0;
-  e = launch_toeplitz(a, st);
+  e = m2l(a, 2);
   if (e == hipSuccess) e = mark(PFMM_STAGE_M2L);
   if (e != hipSuccess) return hip_fail(e, "M2L level 2");
   for (int l = 3; l <= L; ++l) {
@@ -430,7 +506,7 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     a.X = pl->M[l];
     a.Y = pl->P[l];
     a.accumulate = 1;
-    e = launch_toeplitz(a, st);
+    e = m2l(a, l);
     if (e == hipSuccess) e = mark(PFMM_STAGE_M2L);
     if (e != hipSuccess) return hip_fail(e, "M2L");
   }
@@ -453,7 +529,25 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   nb.grid_out = 1;
   nb.xscale = 1.0 / ((double)N * N * N);
   nb.accumulate = 1;
-  e = launch_toeplitz(nb, st);
+  if (mx && pl->nwin) {
+    e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xs, st);
+    if (e == hipSuccess) {
+      ToepMfmaArgs ma{};
+      ma.n = nb.n;
+      ma.m = nb.m;
+      ma.noff = nb.noff;
+      ma.offs = nb.offs;
+      ma.win = pl->nwin;
+      ma.X = pl->xs;
+      ma.Y = phi;
+      ma.grid_out = 1;
+      ma.accumulate = 1;
+      ma.groups = 1;
+      e = launch_toep8_split(ma, kNearTerms, st);
+    }
+  } else {
+    e = launch_toeplitz(nb, st);
+  }
   if (e == hipSuccess) e = mark(PFMM_STAGE_NEAR);
   if (e != hipSuccess) return hip_fail(e, "near zone");
   if (accel) {

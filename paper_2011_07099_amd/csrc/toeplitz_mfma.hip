@@ -1,0 +1,392 @@
+// Block-Toeplitz operator for 8^3 blocks on the BF16 matrix cores with split
+// precision: each operand is held as NT bf16 terms (x = x0 + x1 [+ x2]) and
+// the products of terms whose combined order is below NT are accumulated in
+// FP32 -- 3 MFMAs per product for NT = 2 (~2^-17 relative per product), 6 for
+// NT = 3 (~2^-24, FP32 class).  It serves the interaction-zone convolution of
+// Eq. 6 at p = 8 (blocks = gridlets; NT = 3, because the effective masses of
+// a gridlet alternate in sign and cancel by 10^2-10^3 within a sum, and the
+// downward interpolation amplifies the residue) and the leaf near zone
+// (blocks = 8^3 cells; NT = 2).
+//
+// For one class of targets (same zone) and one offset d the operation is the
+// GEMM  C[a][t] += sum_a' K_d[a][a'] X[t + d][a'],  a, a' in [0, 512),
+// K_d[a][a'] = G((a - a' - 8 d) * spacing).  Mapping onto
+// v_mfma_f32_32x32x16_bf16:
+//   * M = output points a of a block (512 = 16 tiles of 32 rows: a tile is a
+//     fixed x index, 4 y indices, all 8 z indices),
+//   * N = targets (a workgroup holds 64 targets of one class, a 4x4x4 cube),
+//   * K = source points a' (16 per step: a fixed x, 2 y, all 8 z indices).
+// The A operand is never stored densely: a lane's 8 consecutive K entries
+// are G at 8 consecutive z separations, read from a 15^3 window of the table
+// around -8d that is kept in LDS z-reversed as packed (v, v+1) bf16 pairs, so
+// every fragment is four aligned 32-bit LDS reads.  Sources are staged in LDS
+// in chunks of 128 K entries, double-buffered with the windows.
+#include "internal.h"
+
+#include <cstdint>
+
+namespace pfmm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kWinPairs = 15 * 15 * 14;   // packed pairs per window term
+constexpr int kWinPart = 3152;            // dwords per window term (padded to 16 B)
+constexpr int kTN = 64;                   // targets per workgroup
+
+__device__ inline uint16_t bf16_bits(float x) {
+  __bf16 b = (__bf16)x;
+  return __builtin_bit_cast(uint16_t, b);
+}
+__device__ inline float bf16_float(uint16_t u) { return (float)__builtin_bit_cast(__bf16, u); }
+
+__device__ inline void unpack_offset(int pk, int& dx, int& dy, int& dz) {
+  dx = ((pk >> 16) & 255) - 128;
+  dy = ((pk >> 8) & 255) - 128;
+  dz = (pk & 255) - 128;
+}
+
+// Windows of an FP64 table (centre C, extent E per axis) for the 343 offsets
+// d in [-3, 3]^3: slot = ((dx+3)*7 + (dy+3))*7 + (dz+3), nt terms per slot.
+// Local indices jx, jy in [0, 15) stand for separations jx - 7 - 8 dx; z is
+// reversed: local v stands for the z separation 7 - v - 8 dz.  Dword
+// (jx, jy, v) of a term packs the bf16 values at v (low half) and v + 1 (high
+// half), v in [0, 14).  Out-of-range windows (small tables) are zero; they
+// are never used.
+__global__ void k_make_windows(const double* __restrict__ tab, int C, int nt,
+                               uint32_t* __restrict__ win) {
+  const int slot = blockIdx.x;
+  const int dx = slot / 49 - 3, dy = (slot / 7) % 7 - 3, dz = slot % 7 - 3;
+  const int E = 2 * C + 1;
+  uint32_t* w = win + (size_t)slot * nt * kWinPart;
+  for (int i = threadIdx.x; i < nt * kWinPart; i += blockDim.x) {
+    uint32_t out = 0;
+    const int term = i / kWinPart, r = i % kWinPart;
+    if (r < kWinPairs) {
+      const int jx = r / (15 * 14), jy = (r / 14) % 15, v = r % 14;
+      const int ix = jx - 7 - 8 * dx + C, iy = jy - 7 - 8 * dy + C;
+      uint16_t h2[2];
+      for (int e = 0; e < 2; ++e) {
+        const int iz = 7 - (v + e) - 8 * dz + C;
+        double x = 0.0;
+        if (ix >= 0 && ix < E && iy >= 0 && iy < E && iz >= 0 && iz < E)
+          x = tab[((size_t)ix * E + iy) * E + iz];
+        uint16_t t = 0;
+        for (int q = 0; q <= term; ++q) {  // residual splitting x = t0 + t1 + t2
+          t = bf16_bits((float)x);
+          x -= (double)bf16_float(t);
+        }
+        h2[e] = t;
+      }
+      out = (uint32_t)h2[0] | ((uint32_t)h2[1] << 16);
+    }
+    w[i] = out;
+  }
+}
+
+// FP32 blocks [nodes][512] -> nt bf16 terms, term q at X + q * n.
+__global__ void k_split_blocks(const float* __restrict__ X, uint16_t* __restrict__ out, int nt,
+                               int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float x = X[i];
+  for (int q = 0; q < nt; ++q) {
+    const uint16_t t = bf16_bits(x);
+    out[(int64_t)q * n + i] = t;
+    x -= bf16_float(t);
+  }
+}
+
+// Mesh [N]^3 (times scale) -> 8^3-cell sub-blocks [(N/8)^3][512], nt terms.
+__global__ void k_split_mesh(const float* __restrict__ rho, float scale, int N, int nt,
+                             uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n3 = (int64_t)N * N * N;
+  if (i >= n3) return;
+  const int z = (int)(i % N), y = (int)((i / N) % N), x = (int)(i / ((int64_t)N * N));
+  const int nb = N / 8;
+  const int64_t blk = ((int64_t)(x >> 3) * nb + (y >> 3)) * nb + (z >> 3);
+  const int64_t o = blk * 512 + ((x & 7) * 64 + (y & 7) * 8 + (z & 7));
+  float v = rho[i] * scale;
+  for (int q = 0; q < nt; ++q) {
+    const uint16_t t = bf16_bits(v);
+    out[(int64_t)q * n3 + o] = t;
+    v -= bf16_float(t);
+  }
+}
+
+// Y[node][a] (+)= sum_g partial[g][node][a], groups summed in order.
+__global__ void k_reduce_groups(const float* __restrict__ part, int groups, int64_t n,
+                                float* __restrict__ Y, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = accumulate ? Y[i] : 0.f;
+  for (int g = 0; g < groups; ++g) s += part[(int64_t)g * n + i];
+  Y[i] = s;
+}
+
+struct Tile {
+  int tx, ty, tz;  // target node
+};
+
+__device__ inline Tile tile_target(int tile, int nt4, int cls, int m, int local) {
+  // tile = 4x4x4 cube of class-lattice points; nt4 tiles per axis
+  const int Tx = tile / (nt4 * nt4), Ty = (tile / nt4) % nt4, Tz = tile % nt4;
+  const int kx = 4 * Tx + (local >> 4), ky = 4 * Ty + ((local >> 2) & 3), kz = 4 * Tz + (local & 3);
+  const int cx = cls / (m * m), cy = (cls / m) % m, cz = cls % m;
+  Tile t;
+  t.tx = cx + m * kx;
+  t.ty = cy + m * ky;
+  t.tz = cz + m * kz;
+  return t;
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
+  constexpr int KCH = NT == 2 ? 128 : 64;        // source points per staged chunk
+  constexpr int NCH = 512 / KCH;                 // chunks per offset
+  constexpr int ROW = KCH + 8;                   // staged row, bf16 (padding vs bank conflicts)
+  constexpr int SEGS = KCH / 8;                  // 16-byte segments per row
+  constexpr int BV = NT * kTN * SEGS / kThreads; // 16-byte loads per thread per chunk
+  constexpr int TPR = kTN * SEGS / kThreads;     // distinct targets per thread
+  constexpr int WV = (NT * kWinPart / 4 + kThreads - 1) / kThreads;
+  __shared__ __attribute__((aligned(16))) uint32_t Aw[2][NT * kWinPart];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][NT][kTN][ROW];
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, h = l >> 5, l32 = l & 31;
+  const int m = a.m;
+  const int nk = a.n / m;                    // class lattice points per axis
+  const int nt4 = nk / 4;                    // tiles per axis
+  const int tiles_per_class = nt4 * nt4 * nt4;
+  const int nblk = tiles_per_class * m * m * m;
+  // XCD-aware order: consecutive dispatch ids go to different XCDs, so give
+  // each XCD a contiguous run of tiles (spatially close targets share sources)
+  const int b = blockIdx.x;
+  const int per = nblk / 8;
+  const int lin = (nblk % 8 == 0) ? (b % 8) * per + b / 8 : b;
+  const int cls = lin / tiles_per_class, tile = lin % tiles_per_class;
+
+  const int g = blockIdx.y;
+  const int ob = (a.noff * g) / a.groups, oe = (a.noff * (g + 1)) / a.groups;
+  const int* offs = a.offs + (size_t)cls * a.noff;
+  const int nmask = a.n - 1;
+  const size_t nterm = (size_t)a.n * a.n * a.n * 512;  // stride between source terms
+
+  // staging map: load r of a chunk covers term r / (BV/NT), target
+  // tl = (tid / SEGS) + (kThreads / SEGS) * (r % TPR), segment tid % SEGS
+  const int seg = tid % SEGS;
+  Tile st[TPR];
+#pragma unroll
+  for (int r = 0; r < TPR; ++r)
+    st[r] = tile_target(tile, nt4, cls, m, tid / SEGS + (kThreads / SEGS) * r);
+
+  u32x4 ra[WV];
+  u32x4 rb[BV];
+  auto load_A = [&](int k) {
+    int dx, dy, dz;
+    unpack_offset(offs[k], dx, dy, dz);
+    const int slot = ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
+    const u32x4* src = reinterpret_cast<const u32x4*>(a.win + (size_t)slot * NT * kWinPart);
+#pragma unroll
+    for (int r = 0; r < WV; ++r) {
+      const int i = tid + kThreads * r;
+      if (i < NT * kWinPart / 4) ra[r] = src[i];
+    }
+  };
+  auto store_A = [&](int buf) {
+    u32x4* dst = reinterpret_cast<u32x4*>(&Aw[buf][0]);
+#pragma unroll
+    for (int r = 0; r < WV; ++r) {
+      const int i = tid + kThreads * r;
+      if (i < NT * kWinPart / 4) dst[i] = ra[r];
+    }
+  };
+  auto load_B = [&](int k, int c) {
+    int dx, dy, dz;
+    unpack_offset(offs[k], dx, dy, dz);
+    size_t node[TPR];
+#pragma unroll
+    for (int r = 0; r < TPR; ++r) {
+      const int ux = (st[r].tx + dx) & nmask, uy = (st[r].ty + dy) & nmask, uz = (st[r].tz + dz) & nmask;
+      node[r] = ((size_t)ux * a.n + uy) * a.n + uz;
+    }
+#pragma unroll
+    for (int r = 0; r < BV; ++r) {
+      const int term = r / TPR;
+      rb[r] = *reinterpret_cast<const u32x4*>(a.X + term * nterm + node[r % TPR] * 512 + KCH * c + 8 * seg);
+    }
+  };
+  auto store_B = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < BV; ++r) {
+      const int tl = tid / SEGS + (kThreads / SEGS) * (r % TPR);
+      *reinterpret_cast<u32x4*>(&Bs[buf][r / TPR][tl][8 * seg]) = rb[r];
+    }
+  };
+
+  floatx16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  // per-lane parts of the A addresses: row = l32 -> (ay_loc, az)
+  const int ay_loc = l32 >> 3, az = l32 & 7;
+
+  if (ob < oe) {
+    load_A(ob);
+    load_B(ob, 0);
+    store_A(0);
+    store_B(0);
+    __syncthreads();
+    int it = 0;
+    for (int k = ob; k < oe; ++k) {
+      const uint32_t* Ak = &Aw[(k - ob) & 1][0];
+      for (int c = 0; c < NCH; ++c) {
+        const bool has_next = !(k == oe - 1 && c == NCH - 1);
+        if (has_next) {
+          if (c < NCH - 1) load_B(k, c + 1);
+          else load_B(k + 1, 0);
+          if (c == NCH - 1) load_A(k + 1);
+        }
+        const int buf = it & 1;
+#pragma unroll
+        for (int sl = 0; sl < KCH / 16; ++sl) {
+          const int s = (KCH / 16) * c + sl;  // k-step of 16 source points
+          const int bx = s >> 2, by = 2 * (s & 3) + h;
+          bf16x8 bt[NT][2];
+#pragma unroll
+          for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              bt[q][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][q][32 * j + l32][16 * sl + 8 * h]);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int I = 4 * w + i;
+            const int ax = I >> 1, ay = 4 * (I & 1) + ay_loc;
+            const int base = ((ax - bx + 7) * 15 + (ay - by + 7)) * 14 + 7 - az;
+            bf16x8 at[NT];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+              const uint32_t* Aq = Ak + q * kWinPart + base;
+              u32x4 u;
+              u[0] = Aq[0];
+              u[1] = Aq[2];
+              u[2] = Aq[4];
+              u[3] = Aq[6];
+              at[q] = __builtin_bit_cast(bf16x8, u);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              // smallest products first
+              if constexpr (NT == 3) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[2], bt[0][j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[0], bt[2][j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[1], bt[1][j], acc[i][j], 0, 0, 0);
+              }
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[1], bt[0][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[0], bt[1][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[0], bt[0][j], acc[i][j], 0, 0, 0);
+            }
+          }
+        }
+        if (has_next) {
+          store_B(buf ^ 1);
+          if (c == NCH - 1) store_A((k + 1 - ob) & 1);
+        }
+        __syncthreads();
+        ++it;
+      }
+    }
+  }
+
+  // epilogue: lane holds column l32 of each 32x32 tile, rows 8(v/4) + 4h + v%4
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const Tile t = tile_target(tile, nt4, cls, m, 32 * j + l32);
+    const size_t node = ((size_t)t.tx * a.n + t.ty) * a.n + t.tz;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int I = 4 * w + i;
+      const int ax = I >> 1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ay = 4 * (I & 1) + q;
+        const int az0 = 4 * h;
+        float4 v = make_float4(acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
+                               acc[i][j][4 * q + 3]);
+        float* dst;
+        if (a.partial) {
+          dst = a.partial + ((size_t)g * a.n * a.n * a.n + node) * 512 + ax * 64 + ay * 8 + az0;
+        } else if (a.grid_out) {
+          const size_t NN = (size_t)a.n * 8;
+          dst = a.Y + ((size_t)(t.tx * 8 + ax) * NN + (t.ty * 8 + ay)) * NN + (t.tz * 8 + az0);
+        } else {
+          dst = a.Y + node * 512 + ax * 64 + ay * 8 + az0;
+        }
+        float4* d4 = reinterpret_cast<float4*>(dst);
+        if (a.accumulate && !a.partial) {
+          const float4 o = *d4;
+          v.x += o.x;
+          v.y += o.y;
+          v.z += o.z;
+          v.w += o.w;
+        }
+        *d4 = v;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+bool toep8_supported(int n, int m) {
+  const int nk = n / m;
+  return nk >= 4 && nk % 4 == 0;
+}
+
+hipError_t make_windows(const double* tab64, int C, int nt, uint32_t* win, hipStream_t st) {
+  if (nt < 2 || nt > 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_make_windows, dim3(343), dim3(256), 0, st, tab64, C, nt, win);
+  return hipGetLastError();
+}
+
+size_t window_dwords(int nt) { return (size_t)343 * nt * kWinPart; }
+
+hipError_t split_blocks(const float* X, uint16_t* out, int nt, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_split_blocks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, out,
+                     nt, n);
+  return hipGetLastError();
+}
+
+hipError_t split_mesh(const float* rho, float scale, int N, int nt, uint16_t* out,
+                      hipStream_t st) {
+  const int64_t n3 = (int64_t)N * N * N;
+  hipLaunchKernelGGL(k_split_mesh, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, rho,
+                     scale, N, nt, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_toep8_split(const ToepMfmaArgs& a, int nt, hipStream_t st) {
+  if (!toep8_supported(a.n, a.m) || a.groups < 1 || nt < 2 || nt > 3) return hipErrorInvalidValue;
+  const int nt4 = a.n / a.m / 4;
+  const int nblk = nt4 * nt4 * nt4 * a.m * a.m * a.m;
+  if (nt == 2)
+    hipLaunchKernelGGL(k_toep8_split<2>, dim3(nblk, a.groups), dim3(kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_toep8_split<3>, dim3(nblk, a.groups), dim3(kThreads), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.partial) return e;
+  const int64_t n = (int64_t)a.n * a.n * a.n * 512;
+  hipLaunchKernelGGL(k_reduce_groups, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     a.partial, a.groups, n, a.Y, a.accumulate);
+  return hipGetLastError();
+}
+
+}  // namespace pfmm

@@ -164,3 +164,43 @@ def test_repeated_solves_are_identical():
             pl.solve(rho, phi)
             outs.append(phi.cpu())
     assert all(torch.equal(outs[0], o) for o in outs[1:])
+
+
+# ---------------------------------------------------------------------------
+# split precision (3 x BF16 on the matrix cores, 8^3 blocks)
+# ---------------------------------------------------------------------------
+# Tolerance: hi + lo bf16 represents an FP32 operand to 2^-17 relative and the
+# dropped lo*lo term is below 2^-18, so each product carries <= ~2^-16 = 1.5e-5
+# relative error; with the ~7x cancellation of zero-mean fields (sum |G m| over
+# |result|) the potential stays within 1e-4 of max |phi|.
+BF16X3_TOL = 1e-4
+
+BF_CASES = [
+    # (name, N, L, p, green, fp64_levels, density)
+    ("near q8 m1", 64, 3, 8, "S1", 2, lambda: fields.lognormal(64, 2.0, 1.0, seed=12)),
+    ("near q8 m2 (s=16)", 64, 2, 8, "X", 2, lambda: _white(64, 13)),
+    ("leaf M2L + near", 128, 4, 8, "S1", 2, lambda: fields.lognormal(128, 2.0, 1.0, seed=14)),
+    ("all levels bf16x3", 64, 3, 8, "K", 0, lambda: fields.lognormal(64, 2.0, 1.0, seed=15)),
+    ("s<p falls back", 32, 3, 8, "S1", 2, lambda: _white(32, 16)),
+    ("p=4 falls back", 64, 3, 4, "S1", 2, lambda: _white(64, 17)),
+]
+
+
+@pytest.mark.parametrize("name,N,L,p,green,f64,make", BF_CASES, ids=[c[0] for c in BF_CASES])
+def test_bf16x3_matches_reference_fmm(name, N, L, p, green, f64, make):
+    rho = f32(make())
+    gpu = solve(rho, L, p, green, precision="bf16x3", fp64_levels=f64)["phi"]
+    ref = ofmm.fmm(rho, L, p, green)
+    e1, e2 = rel_max(gpu, ref), rel_l2(gpu, ref)
+    print(name, "bf16x3 potential rel max", e1, "rel L2", e2)
+    assert e1 < BF16X3_TOL
+
+
+def test_bf16x3_repeatable_and_close_to_fp32():
+    rho = f32(fields.lognormal(64, 2.0, 1.0, seed=18))
+    a = solve(rho, 3, 8, "S1", precision="bf16x3")["phi"]
+    b = solve(rho, 3, 8, "S1", precision="bf16x3")["phi"]
+    c = solve(rho, 3, 8, "S1")["phi"]
+    assert np.array_equal(a, b)
+    print("bf16x3 vs fp32", rel_max(a, c))
+    assert rel_max(a, c) < BF16X3_TOL
