@@ -46,7 +46,12 @@ struct ToepArgs {
   double xscale;    // sources are multiplied by this (h^3: density -> mass)
   int accumulate;   // 0: overwrite Y, 1: add to Y
   int fp64;         // 0: FP32 tab/X/Y, 1: FP64 tab/X/Y
+  int groups;       // >1: offsets split over workgroups writing `partial`
+  void* partial;    // [groups][n^3][q^3] (block layout only), summed in order
 };
+
+// Workgroups of one launch of the portable kernel (before offset groups).
+int toeplitz_workgroups(int q, int fp64, int n, int m);
 
 inline int pack_offset(int dx, int dy, int dz) {
   return ((dx + 128) & 255) << 16 | ((dy + 128) & 255) << 8 | ((dz + 128) & 255);

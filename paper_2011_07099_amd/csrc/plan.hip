@@ -51,8 +51,9 @@ struct pfmm_plan_s {
   uint32_t* nwin = nullptr;       // near-table windows (8^3-cell sub-blocks)
   uint16_t* xs = nullptr;         // bf16 source terms (up to 3 arrays of xwords)
   size_t xwords = 0;
-  float* part = nullptr;          // split-offset partial sums
+  float* part = nullptr;          // split-offset partial sums (matrix-core path)
   size_t part_floats = 0;
+  void* spart = nullptr;          // split-offset partial sums (portable kernel)
   std::vector<void*> owned;
   // stage timing (PFMM_OPT_PROFILE): a ring of event sets, one per solve
   int profile = 0;
@@ -173,6 +174,14 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
 
 // Offset groups of a level's matrix-core launch: enough workgroups to give
 // the 256 compute units two rounds (a level-l launch has 8^(l-2) tiles).
+// Offset groups of a portable-kernel launch: at least 1024 workgroups.
+int scalar_groups(int q, int fp64, int n, int m, int noff) {
+  const int wg = toeplitz_workgroups(q, fp64, n, m);
+  if (wg <= 0) return 1;
+  const int g = (1024 + wg - 1) / wg;
+  return g < noff ? g : noff;
+}
+
 int m2l_groups(int l) {
   const int tiles = 1 << (3 * (l - 2));
   int g = (512 + tiles - 1) / tiles;
@@ -283,6 +292,25 @@ pfmm_status build(pfmm_plan_s* pl) {
   if (pl->part_floats) {
     e = dalloc(pl, &pl->part, pl->part_floats);
     if ((st = chk("partial sums"))) return st;
+  }
+  {
+    // portable-kernel partial sums: any level may run there (FP64 for the
+    // coarse levels), block layout only
+    size_t bytes = 0;
+    for (int l = 2; l <= L; ++l) {
+      const int n = 1 << l, m = l == 2 ? 1 : 2, noff = l == 2 ? 37 : 189;
+      for (int f64 = 0; f64 <= (l <= 3 ? 1 : 0); ++f64) {  // the FP64 level count is an option
+        const int G = scalar_groups(p, f64, n, m, noff);
+        const size_t w = f64 ? sizeof(double) : sizeof(float);
+        if (G > 1) bytes = std::max(bytes, (size_t)G * ((size_t)1 << (3 * l)) * p3 * w);
+      }
+    }
+    if (bytes) {
+      char* sp = nullptr;
+      e = dalloc(pl, &sp, bytes);
+      pl->spart = sp;
+      if ((st = chk("partial sums"))) return st;
+    }
   }
 
   // zones (Sec. 2, Fig. 2)
@@ -447,8 +475,14 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   auto is64 = [&](int l) { return (int)level64(pl, l); };
   const bool mx = pl->prec == PFMM_PREC_BF16X3;
   // interaction zone of one level: matrix cores for FP32 levels with windows
-  auto m2l = [&](const ToepArgs& ta, int l) -> hipError_t {
-    if (!mx || ta.fp64 || !pl->win[l]) return launch_toeplitz(ta, st);
+  auto m2l = [&](const ToepArgs& ta0, int l) -> hipError_t {
+    ToepArgs ta = ta0;
+    if (!mx || ta.fp64 || !pl->win[l]) {
+      ta.groups = scalar_groups(ta.q, ta.fp64, ta.n, ta.m, ta.noff);
+      ta.partial = ta.groups > 1 ? pl->spart : nullptr;
+      if (ta.groups > 1 && !ta.partial) ta.groups = 1;
+      return launch_toeplitz(ta, st);
+    }
     const size_t nodes = (size_t)1 << (3 * l);
     hipError_t r = split_blocks((const float*)ta.X, pl->xs, kM2LTerms, (int64_t)(nodes * 512), st);
     if (r != hipSuccess) return r;
@@ -529,6 +563,7 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   nb.grid_out = 1;
   nb.xscale = 1.0 / ((double)N * N * N);
   nb.accumulate = 1;
+  nb.groups = 1;
   if (mx && pl->nwin) {
     e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xs, st);
     if (e == hipSuccess) {

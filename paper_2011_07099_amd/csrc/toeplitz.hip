@@ -53,6 +53,8 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
   const int* offs = a.offs + (size_t)cls * a.noff;
   const size_t NN = (size_t)a.n * Q;  // mesh size in grid mode
   const T xscale = (T)a.xscale;
+  const int g = blockIdx.z;
+  const int ob = (a.noff * g) / a.groups, oe = (a.noff * (g + 1)) / a.groups;
 
   const int grp = tid / R, row = tid % R;
   const bool active = grp < G;
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
 #pragma unroll
     for (int j = 0; j < Q; ++j) tot[i][j] = 0.0;
 
-  for (int k = 0; k < a.noff; ++k) {
+  for (int k = ob; k < oe; ++k) {
     int dx, dy, dz;
     unpack_offset(offs[k], dx, dy, dz);
     __syncthreads();
@@ -130,6 +132,8 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
 
   if (!active) return;
   T* Y = static_cast<T*>(a.Y);
+  const bool to_part = a.groups > 1;
+  if (to_part) Y = static_cast<T*>(a.partial) + (size_t)g * a.n * a.n * a.n * Q3;
 #pragma unroll
   for (int i = 0; i < TPT; ++i) {
     const int t = t0 + grp * TPT + i;
@@ -143,9 +147,20 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
         o = ((size_t)(tx * Q + ax) * NN + (ty * Q + ay)) * NN + (tz * Q + az);
       else
         o = (((size_t)tx * a.n + ty) * a.n + tz) * Q3 + (ax * Q + ay) * Q + az;
-      Y[o] = a.accumulate ? (T)((double)Y[o] + tot[i][az]) : (T)tot[i][az];
+      Y[o] = (a.accumulate && !to_part) ? (T)((double)Y[o] + tot[i][az]) : (T)tot[i][az];
     }
   }
+}
+
+// Y (+)= sum_g partial[g], groups in order, in the operand type.
+template <class T>
+__global__ void k_reduce(const T* __restrict__ part, int groups, int64_t n, T* __restrict__ Y,
+                         int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = accumulate ? Y[i] : (T)0;
+  for (int g = 0; g < groups; ++g) s += part[(int64_t)g * n + i];
+  Y[i] = s;
 }
 
 template <int Q, int TPT, int GMAX, class T>
@@ -157,9 +172,30 @@ hipError_t launch_q(const ToepArgs& a, hipStream_t st) {
                 "LDS budget");
   const int nk = a.n / a.m;
   const int ntarg = nk * nk * nk;
-  dim3 grid((ntarg + TT - 1) / TT, a.m * a.m * a.m);
+  dim3 grid((ntarg + TT - 1) / TT, a.m * a.m * a.m, a.groups);
   hipLaunchKernelGGL((k_toeplitz<Q, TPT, GMAX, T>), grid, dim3(kThreads), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.groups <= 1) return e;
+  const int64_t n = (int64_t)a.n * a.n * a.n * Q * Q * Q;
+  hipLaunchKernelGGL((k_reduce<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const T*>(a.partial), a.groups, n, static_cast<T*>(a.Y),
+                     a.accumulate);
   return hipGetLastError();
+}
+
+template <int Q, int TPT, int GMAX, class T>
+int workgroups_q(int n, int m) {
+  constexpr int R = Q * Q;
+  constexpr int G = (kThreads / R) < GMAX ? (kThreads / R) : GMAX;
+  constexpr int TT = G * TPT;
+  const int nk = n / m;
+  return ((nk * nk * nk + TT - 1) / TT) * m * m * m;
+}
+
+template <int Q>
+int workgroups_q2(int fp64, int n, int m) {
+  if (fp64) return workgroups_q<Q, 1, (Q >= 10 ? 1 : 4), double>(n, m);
+  return workgroups_q<Q, 2, 256, float>(n, m);
 }
 
 template <int Q>
@@ -170,8 +206,25 @@ hipError_t launch_q2(const ToepArgs& a, hipStream_t st) {
 
 }  // namespace
 
+int toeplitz_workgroups(int q, int fp64, int n, int m) {
+  switch (q) {
+    case 1: return workgroups_q2<1>(fp64, n, m);
+    case 2: return workgroups_q2<2>(fp64, n, m);
+    case 3: return workgroups_q2<3>(fp64, n, m);
+    case 4: return workgroups_q2<4>(fp64, n, m);
+    case 5: return workgroups_q2<5>(fp64, n, m);
+    case 6: return workgroups_q2<6>(fp64, n, m);
+    case 7: return workgroups_q2<7>(fp64, n, m);
+    case 8: return workgroups_q2<8>(fp64, n, m);
+    case 9: return workgroups_q2<9>(fp64, n, m);
+    case 10: return workgroups_q2<10>(fp64, n, m);
+    default: return 0;
+  }
+}
+
 hipError_t launch_toeplitz(const ToepArgs& a, hipStream_t st) {
   if (a.grid_in && a.fp64) return hipErrorInvalidValue;  // the mesh is FP32
+  if (a.groups < 1 || (a.groups > 1 && (a.grid_out || !a.partial))) return hipErrorInvalidValue;
   switch (a.q) {
     case 1: return launch_q2<1>(a, st);
     case 2: return launch_q2<2>(a, st);

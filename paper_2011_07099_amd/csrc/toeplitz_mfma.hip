@@ -236,8 +236,57 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  // per-lane parts of the A addresses: row = l32 -> (ay_loc, az)
-  const int ay_loc = l32 >> 3, az = l32 & 7;
+  // A addresses: for M-tile i and k-step s the window dword is
+  //   ((ax - bx + 7) * 15 + (ay - by + 7)) * 14 + 7 - az
+  // with ax = 2w + i/2, ay = 4(i%2) + l32/8, az = l32%8, bx = s/4,
+  // by = 2(s%4) + h.  The lane part is one base; the rest is a constant.
+  const int abase = (210 * (2 * w + 7) + 14 * ((l32 >> 3) + 7 - h) + 7 - (l32 & 7));
+  // B rows: target 32j + l32, k offset 16 sl + 8h within the staged chunk
+  const int bbase = l32 * ROW + 8 * h;
+
+  struct Frags {
+    bf16x8 a[4][NT];
+    bf16x8 b[NT][2];
+  };
+  auto load_a = [&](Frags& f, const uint32_t* Ak, int s) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const uint32_t* Aq = Ak + q * kWinPart + abase + 210 * (i >> 1) + 56 * (i & 1) -
+                             210 * (s >> 2) - 28 * (s & 3);
+        u32x4 u;
+        u[0] = Aq[0];
+        u[1] = Aq[2];
+        u[2] = Aq[4];
+        u[3] = Aq[6];
+        f.a[i][q] = __builtin_bit_cast(bf16x8, u);
+      }
+  };
+  auto load_b = [&](Frags& f, const uint16_t* Bb, int sl) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        f.b[q][j] = *reinterpret_cast<const bf16x8*>(Bb + q * kTN * ROW + 32 * j * ROW + bbase +
+                                                     16 * sl);
+  };
+  auto mma = [&](const Frags& f) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // smallest products first
+        if constexpr (NT == 3) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][2], f.b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], f.b[2][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], f.b[1][j], acc[i][j], 0, 0, 0);
+        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], f.b[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], f.b[1][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], f.b[0][j], acc[i][j], 0, 0, 0);
+      }
+  };
 
   if (ob < oe) {
     load_A(ob);
@@ -245,63 +294,36 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
     store_A(0);
     store_B(0);
     __syncthreads();
-    int it = 0;
     for (int k = ob; k < oe; ++k) {
       const uint32_t* Ak = &Aw[(k - ob) & 1][0];
+      const bool last_off = (k == oe - 1);
+#pragma unroll
       for (int c = 0; c < NCH; ++c) {
-        const bool has_next = !(k == oe - 1 && c == NCH - 1);
+        // prefetch the next chunk (and at the last chunk the next window)
+        const bool has_next = !(last_off && c == NCH - 1);
         if (has_next) {
           if (c < NCH - 1) load_B(k, c + 1);
           else load_B(k + 1, 0);
           if (c == NCH - 1) load_A(k + 1);
         }
-        const int buf = it & 1;
+        const uint16_t* Bb = &Bs[c & 1][0][0][0];  // NCH is even: parity of c
+        constexpr int KS = KCH / 16;               // k-steps per chunk
+        Frags f[2];
+        load_a(f[0], Ak, KS * c);
+        load_b(f[0], Bb, 0);
 #pragma unroll
-        for (int sl = 0; sl < KCH / 16; ++sl) {
-          const int s = (KCH / 16) * c + sl;  // k-step of 16 source points
-          const int bx = s >> 2, by = 2 * (s & 3) + h;
-          bf16x8 bt[NT][2];
-#pragma unroll
-          for (int q = 0; q < NT; ++q)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-              bt[q][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][q][32 * j + l32][16 * sl + 8 * h]);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int I = 4 * w + i;
-            const int ax = I >> 1, ay = 4 * (I & 1) + ay_loc;
-            const int base = ((ax - bx + 7) * 15 + (ay - by + 7)) * 14 + 7 - az;
-            bf16x8 at[NT];
-#pragma unroll
-            for (int q = 0; q < NT; ++q) {
-              const uint32_t* Aq = Ak + q * kWinPart + base;
-              u32x4 u;
-              u[0] = Aq[0];
-              u[1] = Aq[2];
-              u[2] = Aq[4];
-              u[3] = Aq[6];
-              at[q] = __builtin_bit_cast(bf16x8, u);
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              // smallest products first
-              if constexpr (NT == 3) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[2], bt[0][j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[0], bt[2][j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[1], bt[1][j], acc[i][j], 0, 0, 0);
-              }
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[1], bt[0][j], acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[0], bt[1][j], acc[i][j], 0, 0, 0);
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at[0], bt[0][j], acc[i][j], 0, 0, 0);
-            }
+        for (int sl = 0; sl < KS; ++sl) {
+          if (sl + 1 < KS) {
+            load_a(f[(sl + 1) & 1], Ak, KS * c + sl + 1);
+            load_b(f[(sl + 1) & 1], Bb, sl + 1);
           }
+          mma(f[sl & 1]);
         }
         if (has_next) {
-          store_B(buf ^ 1);
+          store_B((c + 1) & 1);
           if (c == NCH - 1) store_A((k + 1 - ob) & 1);
         }
         __syncthreads();
-        ++it;
       }
     }
   }
