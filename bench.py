@@ -32,6 +32,22 @@ METRIC = "cells/s at 256^3 p=8 periodic FMM, L2 err<=1e-4 vs PM; M2L MFMA util"
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
 
+# HBM bytes per launch of the near-zone kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB), scaled by a plain 1 GiB copy (read x2.0, write x1.0), keyed
+# by precision and the SHA-1 prefix of the kernel source they were taken on; a
+# changed source reports null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md
+TRAFFIC = {
+    ("bf16x3", "ffb38ac75e46"): (7169124 * 2.0 + 65536 * 1.0) * 1024,
+}
+KERNEL_SRC = {"bf16x3": "toeplitz_mfma.hip", "fp32": "toeplitz.hip"}
+
+
+def traffic_bytes(precision):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2011_07099_amd", "csrc", KERNEL_SRC[precision])
+    h = hashlib.sha1(open(path, "rb").read()).hexdigest()[:12]
+    return TRAFFIC.get((precision, h))
+
 
 def algorithmic_flops(N, L, p):
     """Flops of the two contraction steps in their block form (one multiply
@@ -94,7 +110,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times): the reference that "
@@ -157,7 +173,7 @@ def main():
                                "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
                    "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
-                     "frac": near_tf / peak, "traffic": None,
+                     "frac": near_tf / peak, "traffic": traffic_bytes(args.precision),
                      "kernel": "near zone (%d launch/step, %.3f ms)" % (stages["near"][1], near_ms)},
         "m2l": {"achieved": m2l_tf, "peak": peak, "unit": "TFLOP/s", "frac": m2l_tf / peak,
                 "ms": m2l_ms, "launches": stages["m2l"][1]},
