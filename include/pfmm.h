@@ -192,6 +192,42 @@ pfmm_status pfmm_plan_info(pfmm_plan_t plan, int* s, int64_t* table_entries);
  * accepted and ignored. */
 pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
 
+/*
+ * Batches of independent fields (fields of different N and p in one solve).
+ *
+ * pfmm_batch_create binds n plans to their density and potential device
+ * arrays (density[i], potential[i] as for pfmm_solve on plans[i]), builds one
+ * pool of independent contraction work items for the whole batch (every
+ * interaction-zone level and near zone of every field: tiles of targets of
+ * one class, largest first), picks the tile width of the persistent kernel
+ * that drains the pool by timing each candidate on these inputs (or reads it
+ * from the JSON file named by the environment variable PFMM_TUNE_CACHE, which
+ * it then updates), and captures the whole batch solve -- upward passes, the
+ * single persistent launch, downward passes -- into a HIP graph on the stream
+ * of plans[0].  It allocates, runs solves and synchronises; it is plan time.
+ *
+ * Requirements: 1 <= n <= 4096; live plans on one device, p <= 8; the plans
+ * are not solved concurrently with the batch (it uses their workspaces).
+ * Each plan's FP64 coarse levels (PFMM_OPT_FP64_LEVELS at batch creation) are
+ * kept in FP64; every other contraction runs in FP32 with FP64 per-offset
+ * running totals, whatever precision the plans are set to.
+ */
+typedef struct pfmm_batch_s* pfmm_batch_t;
+pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* const* density,
+                              float* const* potential, pfmm_batch_t* out);
+
+/* Solve the whole batch: one graph launch on the stream of plans[0].  Does
+ * not allocate or synchronise.  Potentials are overwritten. */
+pfmm_status pfmm_batch_solve(pfmm_batch_t batch);
+
+/* Work items in the pool, the chosen tile width (targets per thread, 1, 2 or
+ * 4) and the timed duration in ms of the persistent launch for each candidate
+ * width 1, 2, 4 (negative when not timed; ms may be NULL). */
+pfmm_status pfmm_batch_info(pfmm_batch_t batch, int* items, int* tile_width, double* ms);
+
+/* Release a batch (not its plans). NULL is accepted and ignored. */
+pfmm_status pfmm_batch_destroy(pfmm_batch_t batch);
+
 /* Message describing the calling thread's last failure ("" if none). */
 const char* pfmm_last_error(void);
 

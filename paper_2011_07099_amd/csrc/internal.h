@@ -88,6 +88,25 @@ hipError_t split_mesh(const float* rho, float scale, int N, int nt, uint16_t* ou
 hipError_t launch_toep8_split(const ToepMfmaArgs& a, int nt, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// Batches of independent fields (batch.hip): one work item = one tile of
+// targets of one class of one interaction-zone level or near zone of one
+// field, all offsets of its zone, FP32 or FP64 operands (block edge q <= 8).
+// ---------------------------------------------------------------------------
+struct BatchItem {
+  const void* tab;  // float or (fp64) double table
+  const void* X;    // float or (fp64) double sources
+  void* Y;          // float or (fp64) double outputs
+  const int* offs;
+  int n, m, q, C, noff, cls, t0, grid;
+  float xscale;
+  int fp64;         // FP64 operands: tile width 1, FP64 sums
+};
+int batch_targets_per_item(int q, int tpt, int fp64);
+int batch_resident_grid(int tpt);
+hipError_t launch_batch_toeplitz(const BatchItem* items, int nitems, unsigned* counter, int tpt,
+                                 int grid, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // Upward / downward passes (tensor products of 1D Lagrange operators).
 // Gridlet buffers are FP32 or FP64 per level; `*64` flags give the type of
 // each operand (0 = float, 1 = double).  Weights are passed in both types.
@@ -102,12 +121,12 @@ hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int 
 // M2M (Eq. 5): Mp[B][a] = sum_o sum_a' T_o(x)T_o(x)T_o [a][a'] Mc[2B+o][a']
 hipError_t launch_m2m(const void* Mc, int c64, void* Mp, int p64, Weights T, int nparent, int p,
                       hipStream_t st);
-// L2L (Eq. 7): Pc[2B+o][a'] = sum_a T_o[ax][a'x] T_o[ay][a'y] T_o[az][a'z] Pp[B][a]  (overwrite)
+// L2L (Eq. 7): Pc[2B+o][a'] (+)= sum_a T_o[ax][a'x] T_o[ay][a'y] T_o[az][a'z] Pp[B][a]
 hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int nparent, int p,
-                      hipStream_t st);
-// L2P: phi[b s + c] = sum_a A[ax][cx] A[ay][cy] A[az][cz] P[b][a]  (overwrite)
+                      hipStream_t st, int accumulate = 0);
+// L2P: phi[b s + c] (+)= sum_a A[ax][cx] A[ay][cy] A[az][cz] P[b][a]
 hipError_t launch_l2p(const void* P, int p64, float* phi, Weights A, int N, int s, int p,
-                      hipStream_t st);
+                      hipStream_t st, int accumulate = 0);
 // a = -grad(phi), periodic 4th-order central differences.
 hipError_t launch_fd4(const float* phi, float* acc, int N, hipStream_t st);
 // FP64 -> FP32 copy of n elements.

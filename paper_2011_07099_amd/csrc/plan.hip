@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -683,5 +685,341 @@ pfmm_status pfmm_plan_destroy(pfmm_plan_t pl) {
 }
 
 const char* pfmm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent fields
+// ---------------------------------------------------------------------------
+struct pfmm_batch_s {
+  std::vector<pfmm_plan_s*> plans;
+  std::vector<const float*> rho;
+  std::vector<float*> phi;
+  hipStream_t caller = nullptr;  // stream of plans[0]; solves are ordered with it
+  hipStream_t stream = nullptr;  // the batch's own stream (captured into the graph)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  BatchItem* items = nullptr;  // device work list
+  unsigned* counter = nullptr;
+  int nitems = 0, tpt = 2, grid = 0;
+  double tuned_ms[3] = {-1.0, -1.0, -1.0};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+std::mutex g_bmu;
+std::set<pfmm_batch_s*> g_blive;
+
+bool blive(pfmm_batch_s* b) {
+  std::lock_guard<std::mutex> lk(g_bmu);
+  return b && g_blive.count(b);
+}
+
+void brelease(pfmm_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->items) (void)hipFree(b->items);
+  if (b->counter) (void)hipFree(b->counter);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+// Work items of every contraction of every field, largest first.
+std::vector<BatchItem> batch_items(const pfmm_batch_s* b, int tpt) {
+  struct Keyed {
+    double cost;
+    BatchItem it;
+  };
+  std::vector<Keyed> all;
+  auto add = [&](const BatchItem& proto) {
+    const int TT = batch_targets_per_item(proto.q, tpt, proto.fp64);
+    const int nk = proto.n / proto.m;
+    const int ntarg = nk * nk * nk;
+    const double cost = (double)proto.noff * std::min(TT, ntarg) * std::pow((double)proto.q, 6.0);
+    for (int c = 0; c < proto.m * proto.m * proto.m; ++c)
+      for (int t0 = 0; t0 < ntarg; t0 += TT) {
+        BatchItem it = proto;
+        it.cls = c;
+        it.t0 = t0;
+        all.push_back({cost, it});
+      }
+  };
+  for (size_t f = 0; f < b->plans.size(); ++f) {
+    const pfmm_plan_s* pl = b->plans[f];
+    const int p = pl->p;
+    for (int l = 2; l <= pl->L; ++l) {
+      BatchItem it{};
+      it.fp64 = level64(pl, l);
+      it.tab = it.fp64 ? (const void*)pl->tab64[l] : (const void*)pl->tab32[l];
+      it.X = pl->M[l];
+      it.Y = pl->P[l];
+      it.offs = l == 2 ? pl->offs_l2 : pl->offs_iz;
+      it.n = 1 << l;
+      it.m = l == 2 ? 1 : 2;
+      it.q = p;
+      it.C = 4 * p - 1;
+      it.noff = l == 2 ? 37 : 189;
+      it.grid = 0;
+      it.xscale = 1.0f;
+      add(it);
+    }
+    BatchItem nb{};
+    nb.fp64 = 0;
+    nb.tab = pl->ntab32;
+    nb.X = b->rho[f];
+    nb.Y = b->phi[f];
+    nb.offs = pl->offs_near;
+    nb.n = pl->N / pl->qn;
+    nb.m = pl->mn;
+    nb.q = pl->qn;
+    nb.C = 2 * pl->s - 1;
+    nb.noff = (int)cube(3 * pl->mn);
+    nb.grid = 1;
+    nb.xscale = (float)(1.0 / ((double)pl->N * pl->N * pl->N));
+    add(nb);
+  }
+  std::stable_sort(all.begin(), all.end(),
+                   [](const Keyed& a, const Keyed& c) { return a.cost > c.cost; });
+  std::vector<BatchItem> out;
+  out.reserve(all.size());
+  for (auto& k : all) out.push_back(k.it);
+  return out;
+}
+
+hipError_t batch_upload(pfmm_batch_s* b, int tpt) {
+  const std::vector<BatchItem> v = batch_items(b, tpt);
+  if (b->items) (void)hipFree(b->items);
+  b->items = nullptr;
+  hipError_t e = hipMalloc(&b->items, std::max<size_t>(1, v.size()) * sizeof(BatchItem));
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(b->items, v.data(), v.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+  b->nitems = (int)v.size();
+  b->tpt = tpt;
+  b->grid = batch_resident_grid(tpt);
+  return e;
+}
+
+// The whole batch solve, enqueued on the batch stream.  `part`: 0 = all,
+// 1 = upward passes only, 2 = the persistent contraction only, 3 = downward.
+hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
+  hipStream_t st = b->stream;
+  hipError_t e = hipSuccess;
+  if (part == 0 || part == 1) {
+    for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
+      pfmm_plan_s* pl = b->plans[f];
+      const Weights T = wts(pl->dT, pl->dT64);
+      e = launch_p2m(b->rho[f], pl->M[pl->L], level64(pl, pl->L), wts(pl->dA, pl->dA64), pl->N,
+                     pl->s, pl->p, 1.0 / ((double)pl->N * pl->N * pl->N), st);
+      for (int l = pl->L - 1; l >= 2 && e == hipSuccess; --l)
+        e = launch_m2m(pl->M[l + 1], level64(pl, l + 1), pl->M[l], level64(pl, l), T, 1 << l,
+                       pl->p, st);
+    }
+  }
+  if (e == hipSuccess && (part == 0 || part == 2))
+    e = launch_batch_toeplitz(b->items, b->nitems, b->counter, b->tpt, b->grid, st);
+  if (e == hipSuccess && (part == 0 || part == 3)) {
+    for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
+      pfmm_plan_s* pl = b->plans[f];
+      const Weights T = wts(pl->dT, pl->dT64);
+      for (int l = 3; l <= pl->L && e == hipSuccess; ++l)
+        e = launch_l2l(pl->P[l - 1], level64(pl, l - 1), pl->P[l], level64(pl, l), T,
+                       1 << (l - 1), pl->p, st, 1);
+      if (e == hipSuccess)
+        e = launch_l2p(pl->P[pl->L], level64(pl, pl->L), b->phi[f], wts(pl->dA, pl->dA64),
+                       pl->N, pl->s, pl->p, st, 1);
+    }
+  }
+  return e;
+}
+
+std::string batch_signature(const pfmm_batch_s* b) {
+  std::string sig;
+  for (const pfmm_plan_s* pl : b->plans)
+    sig += std::to_string(pl->N) + "/" + std::to_string(pl->L) + "/" + std::to_string(pl->p) + ";";
+  // hash it to keep the cache file short
+  uint64_t h = 1469598103934665603ull;
+  for (char c : sig) h = (h ^ (unsigned char)c) * 1099511628211ull;
+  char buf[32];
+  std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  return std::string(buf) + "-" + std::to_string(b->plans.size());
+}
+
+// Cache: a flat JSON object {"<signature>": tile_width, ...}.
+int cache_lookup(const char* path, const std::string& key) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return 0;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  std::fclose(f);
+  const std::string pat = "\"" + key + "\":";
+  const size_t at = txt.find(pat);
+  if (at == std::string::npos) return 0;
+  const int v = std::atoi(txt.c_str() + at + pat.size());
+  return (v == 1 || v == 2 || v == 4) ? v : 0;
+}
+
+void cache_store(const char* path, const std::string& key, int tpt) {
+  std::string txt;
+  if (FILE* f = std::fopen(path, "r")) {
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+    std::fclose(f);
+  }
+  const size_t close = txt.rfind('}');
+  std::string body = close == std::string::npos ? std::string() : txt.substr(0, close);
+  const size_t open = body.find('{');
+  body = open == std::string::npos ? std::string() : body.substr(open + 1);
+  while (!body.empty() && (body.back() == ' ' || body.back() == '\n')) body.pop_back();
+  std::string out = "{" + body + (body.empty() ? "" : ",") + "\n  \"" + key + "\": " +
+                    std::to_string(tpt) + "\n}\n";
+  if (FILE* f = std::fopen(path, "w")) {
+    std::fwrite(out.data(), 1, out.size(), f);
+    std::fclose(f);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* const* density,
+                              float* const* potential, pfmm_batch_t* out) {
+  g_err.clear();
+  if (!out) return fail(PFMM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > 4096 || !plans || !density || !potential)
+    return fail(PFMM_ERR_INVALID_ARG, "need 1 <= n <= 4096 and non-NULL arrays");
+  pfmm_batch_s* b = new (std::nothrow) pfmm_batch_s;
+  if (!b) return fail(PFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  for (int i = 0; i < n; ++i) {
+    if (!live(plans[i]) || !density[i] || !potential[i]) {
+      delete b;
+      return fail(PFMM_ERR_INVALID_ARG, "invalid plan or NULL buffer in batch");
+    }
+    if (plans[i]->p > 8) {
+      delete b;
+      return fail(PFMM_ERR_UNSUPPORTED, "batches need p <= 8");
+    }
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) {
+        delete b;
+        return fail(PFMM_ERR_INVALID_ARG, "a plan appears twice in a batch");
+      }
+    b->plans.push_back(plans[i]);
+    b->rho.push_back(density[i]);
+    b->phi.push_back(potential[i]);
+  }
+  b->caller = plans[0]->stream;
+  // default priority (no priority streams anywhere in this library)
+  hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  // inputs written on the caller's stream must be visible to the tuning runs
+  if (e == hipSuccess) e = hipStreamSynchronize(b->caller);
+  if (e == hipSuccess) e = hipMalloc(&b->counter, sizeof(unsigned));
+  if (e != hipSuccess) {
+    brelease(b);
+    return hip_fail(e, "batch counter");
+  }
+  // tile width: cache, else time each candidate on these inputs
+  const char* cache = std::getenv("PFMM_TUNE_CACHE");
+  const std::string key = batch_signature(b);
+  int tpt = cache ? cache_lookup(cache, key) : 0;
+  if (!tpt) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double best = 1e300;
+    const int cand[3] = {1, 2, 4};
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+      e = batch_upload(b, cand[c]);
+      if (e == hipSuccess) e = batch_enqueue(b, 0);  // warm up, makes the inputs valid
+      float ms = 0.f, msmin = 1e30f;
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+        e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess) e = batch_enqueue(b, 2);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        msmin = std::min(msmin, ms);
+      }
+      if (e != hipSuccess) break;
+      b->tuned_ms[c] = msmin;
+      if (msmin < best) {
+        best = msmin;
+        tpt = cand[c];
+      }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+      (void)hipDeviceSynchronize();
+      brelease(b);
+      return hip_fail(e, "batch tuning");
+    }
+    if (cache) cache_store(cache, key, tpt);
+  }
+  e = batch_upload(b, tpt);
+  // capture the whole batch solve
+  if (e == hipSuccess) e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t ee = batch_enqueue(b, 0);
+    e = hipStreamEndCapture(b->stream, &b->graph);
+    if (ee != hipSuccess) e = ee;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipDeviceSynchronize();
+    brelease(b);
+    return hip_fail(e, "batch graph");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    g_blive.insert(b);
+  }
+  *out = b;
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_batch_solve(pfmm_batch_t b) {
+  g_err.clear();
+  if (!blive(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
+  hipError_t e = hipEventRecord(b->ev_in, b->caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->caller, b->ev_out, 0);
+  if (e != hipSuccess) return hip_fail(e, "batch solve");
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_batch_info(pfmm_batch_t b, int* items, int* tile_width, double* ms) {
+  g_err.clear();
+  if (!blive(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
+  if (items) *items = b->nitems;
+  if (tile_width) *tile_width = b->tpt;
+  if (ms)
+    for (int i = 0; i < 3; ++i) ms[i] = b->tuned_ms[i];
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_batch_destroy(pfmm_batch_t b) {
+  g_err.clear();
+  if (!b) return PFMM_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_bmu);
+    if (!g_blive.erase(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
+  }
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  brelease(b);
+  if (e != hipSuccess) return hip_fail(e, "batch destroy");
+  return PFMM_OK;
+}
 
 }  // extern "C"

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void k_m2m(const TI* __restrict__ Mc,
 template <class TI, class TO, class W>
 __global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
                                                    TO* __restrict__ Pc, Weights Tw, int np,
-                                                   int p) {
+                                                   int p, int accumulate) {
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
   const int p3 = p * p * p;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
       const int bx = i / (p * p), yz = i % (p * p);
       W v = 0;
       for (int k = 0; k < p; ++k) v += Tx[k * p + bx] * v2[k * p * p + yz];
-      Pc[child * p3 + i] = (TO)v;
+      Pc[child * p3 + i] = accumulate ? (TO)((W)Pc[child * p3 + i] + v) : (TO)v;
     }
   }
 }
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
 template <class TI, class W>
 __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
                                                    float* __restrict__ phi, Weights Aw, int N,
-                                                   int s, int p) {
+                                                   int s, int p, int accumulate) {
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
   const int p3 = p * p * p;
@@ -207,7 +207,8 @@ __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
     W v = 0;
     for (int k = 0; k < p; ++k) v += sA[k * s + cx] * w2[k * s * s + cyz];
     const int cy = cyz / s, cz = cyz % s;
-    phi[((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz)] = (float)v;
+    float* o = phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz);
+    *o = accumulate ? (float)((W)*o + v) : (float)v;
   }
 }
 
@@ -269,33 +270,33 @@ hipError_t launch_m2m(const void* Mc, int c64, void* Mp, int p64, Weights T, int
 }
 
 hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int np, int p,
-                      hipStream_t st) {
+                      hipStream_t st, int accumulate) {
   const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
   const dim3 g(np * np * np), b(kThreads);
   if (!p64 && !c64)
     hipLaunchKernelGGL((k_l2l<float, float, float>), g, b, words * 4, st, (const float*)Pp,
-                       (float*)Pc, T, np, p);
+                       (float*)Pc, T, np, p, accumulate);
   else if (p64 && !c64)
     hipLaunchKernelGGL((k_l2l<double, float, double>), g, b, words * 8, st, (const double*)Pp,
-                       (float*)Pc, T, np, p);
+                       (float*)Pc, T, np, p, accumulate);
   else if (p64 && c64)
     hipLaunchKernelGGL((k_l2l<double, double, double>), g, b, words * 8, st, (const double*)Pp,
-                       (double*)Pc, T, np, p);
+                       (double*)Pc, T, np, p, accumulate);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_l2p(const void* P, int p64, float* phi, Weights A, int N, int s, int p,
-                      hipStream_t st) {
+                      hipStream_t st, int accumulate) {
   const int nL = N / s;
   const size_t words = (size_t)(p * s + p * p * p + p * p * s + p * s * s);
   if (p64)
     hipLaunchKernelGGL((k_l2p<double, double>), dim3(nL * nL * nL), dim3(kThreads),
-                       words * sizeof(double), st, (const double*)P, phi, A, N, s, p);
+                       words * sizeof(double), st, (const double*)P, phi, A, N, s, p, accumulate);
   else
     hipLaunchKernelGGL((k_l2p<float, float>), dim3(nL * nL * nL), dim3(kThreads),
-                       words * sizeof(float), st, (const float*)P, phi, A, N, s, p);
+                       words * sizeof(float), st, (const float*)P, phi, A, N, s, p, accumulate);
   return hipGetLastError();
 }
 

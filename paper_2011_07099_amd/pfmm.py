@@ -20,7 +20,9 @@ BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
 
 # every symbol include/pfmm.h declares
 EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_plan_read",
-           "pfmm_plan_stage_times", "pfmm_plan_info", "pfmm_plan_destroy", "pfmm_last_error")
+           "pfmm_plan_stage_times", "pfmm_plan_info", "pfmm_plan_destroy",
+           "pfmm_batch_create", "pfmm_batch_solve", "pfmm_batch_info", "pfmm_batch_destroy",
+           "pfmm_last_error")
 
 _lib = None
 
@@ -48,6 +50,12 @@ def load():
                                           ctypes.POINTER(i32)]
     lib.pfmm_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
     lib.pfmm_plan_destroy.argtypes = [vp]
+    lib.pfmm_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.pfmm_batch_solve.argtypes = [vp]
+    lib.pfmm_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.pfmm_batch_destroy.argtypes = [vp]
     lib.pfmm_last_error.restype = ctypes.c_char_p
     for f in EXPORTS[:-1]:
         getattr(lib, f).restype = i32
@@ -160,6 +168,58 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             _check(load().pfmm_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Many independent fields solved by one graph launch (``pfmm_batch_*``).
+
+    ``plans``: Plan objects (p <= 8); ``rhos``/``phis``: matching device
+    tensors.  Creation tunes the persistent kernel's tile width (cached in the
+    JSON file named by PFMM_TUNE_CACHE, if set) and captures the graph.
+    """
+
+    def __init__(self, plans, rhos, phis):
+        lib = load()
+        n = len(plans)
+        if not (n == len(rhos) == len(phis)) or n == 0:
+            raise ValueError("plans, rhos and phis must have the same non-zero length")
+        for pl, r, f in zip(plans, rhos, phis):
+            _ptr(r), _ptr(f)
+            if r.numel() != pl.N ** 3 or f.numel() != pl.N ** 3:
+                raise ValueError("tensor sizes must match the plans")
+        self._keep = (list(plans), list(rhos), list(phis))
+        P = (ctypes.c_void_p * n)(*[pl._h.value for pl in plans])
+        R = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+        F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in phis])
+        h = ctypes.c_void_p()
+        _check(lib.pfmm_batch_create(n, P, R, F, ctypes.byref(h)))
+        self._h = h
+
+    def solve(self):
+        _check(load().pfmm_batch_solve(self._h))
+
+    def info(self):
+        items, tw = ctypes.c_int(), ctypes.c_int()
+        ms = (ctypes.c_double * 3)()
+        _check(load().pfmm_batch_info(self._h, ctypes.byref(items), ctypes.byref(tw), ms))
+        return {"items": items.value, "tile_width": tw.value, "tuned_ms": list(ms)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().pfmm_batch_destroy(self._h))
             self._h = None
 
     def __del__(self):

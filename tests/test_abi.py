@@ -64,3 +64,14 @@ def test_bad_handles():
     assert lib.pfmm_plan_destroy(bogus) == 1
     assert lib.pfmm_plan_destroy(None) == 0
     assert lib.pfmm_plan_create(16, 3, 4, 2, None) == 1
+
+
+def test_invalid_batch_arguments():
+    lib = _lib()
+    h = ctypes.c_void_p(1)
+    assert lib.pfmm_batch_create(0, None, None, None, ctypes.byref(h)) == 1 and h.value is None
+    arr = (ctypes.c_void_p * 1)(0x1234)
+    assert lib.pfmm_batch_create(1, arr, arr, arr, ctypes.byref(h)) == 1
+    assert lib.pfmm_batch_create(1, arr, arr, arr, None) == 1
+    assert lib.pfmm_batch_solve(ctypes.c_void_p(0x1234)) == 1
+    assert lib.pfmm_batch_destroy(None) == 0
