@@ -228,6 +228,64 @@ pfmm_status pfmm_batch_info(pfmm_batch_t batch, int* items, int* tile_width, dou
 /* Release a batch (not its plans). NULL is accepted and ignored. */
 pfmm_status pfmm_batch_destroy(pfmm_batch_t batch);
 
+/*
+ * Direct periodic convolution  potential_i = h^3 sum_j G((x_i - x_j) wrapped) rho_j
+ * over the whole box with the plan's G (Eq. 4, "PM with G": the exact result
+ * the FMM approximates), by the block-Toeplitz kernel in FP32 with FP64
+ * per-offset totals.  O(N^6) work: a reference for moderate N.  Allocates
+ * its table on the first call; enqueued on the plan's stream.
+ */
+pfmm_status pfmm_plan_direct(pfmm_plan_t plan, const float* density, float* potential);
+
+/*
+ * Learned correction of the interaction-zone tables (Sec. 3 defines the
+ * optimal G_* as the G with which FMM and PM agree; Sec. 4 proposes
+ * parameterising it with many values).  A network f(|j| sorted / (4p),
+ * level / 8, p / 10) with layers 5 -> 64 -> 64 -> 1 and SiLU activations
+ * sets T_l[j] = G(eta_l j) (1 + 1e-4 f) for every interaction-zone table
+ * entry (Eq. 6); the near zone keeps G.  Weights: PFMM_MLP_PARAMS
+ * floats, W1[64][5] b1[64] W2[64][64] b2[64] W3[64] b3.
+ */
+#define PFMM_MLP_PARAMS 4609
+
+/* Set the network (host weights) and rebuild the tables by running it on the
+ * device, in BF16 with FP32 accumulation when bf16 != 0, else in FP32.
+ * weights == NULL restores the uncorrected G (the fallback).  Synchronises. */
+pfmm_status pfmm_learned_set(pfmm_plan_t plan, const float* weights, int bf16);
+
+/* Start training from the host weights with Adam step size lr (> 0).
+ * Tables follow the network in FP32 from here on.  Allocates; synchronises. */
+pfmm_status pfmm_learned_train_begin(pfmm_plan_t plan, const float* weights, double lr);
+
+/* One training field: solve `density` (device) with the current tables,
+ * compare with `target` (device, the potential to reproduce, e.g. from
+ * pfmm_plan_direct), and add the gradient of
+ *     loss = sum r^2 / sum (target - mean)^2,  r = phi - target - mean(phi - target)
+ * with respect to the weights to the plan's accumulator (adjoint sweep,
+ * table gradient, network backward pass, all on the device).  *loss
+ * receives the field's loss (may be NULL).  Synchronises. */
+pfmm_status pfmm_learned_accumulate(pfmm_plan_t plan, const float* density, const float* target,
+                                    double* loss);
+
+/* The loss above for one field with the plan's current tables, without a
+ * gradient (a forward solve and the residual).  Synchronises. */
+pfmm_status pfmm_learned_loss(pfmm_plan_t plan, const float* density, const float* target,
+                              double* loss);
+
+/* Adam step with the accumulated gradient averaged over the accumulated
+ * fields; clears the accumulator and rebuilds the tables.  Synchronises. */
+pfmm_status pfmm_learned_step(pfmm_plan_t plan);
+
+/* Current weights into the host array `weights` (PFMM_MLP_PARAMS floats). */
+pfmm_status pfmm_learned_get(pfmm_plan_t plan, float* weights);
+
+/* Gradients of the last pfmm_learned_accumulate: d loss / d T_level[j] into
+ * the host array table_grad ((8p-1)^3 doubles, same layout as
+ * PFMM_BUF_TABLE_LEVEL) and the accumulated weight gradient into weight_grad
+ * (PFMM_MLP_PARAMS floats); either may be NULL. */
+pfmm_status pfmm_learned_read_grad(pfmm_plan_t plan, int level, double* table_grad,
+                                   float* weight_grad);
+
 /* Message describing the calling thread's last failure ("" if none). */
 const char* pfmm_last_error(void);
 

@@ -16,9 +16,10 @@ Multipole Method: Approximating the Optimal Green's Function", that it follows):
   gridlet anterpolation (P2M/M2M), interaction-zone M2L, interpolation
   (L2L/L2P) and the 27-node near zone.
 * ``fd``     — periodic 4th-order finite-difference accelerations (Sec. 3).
+* ``mlp``    — FP64 network of the learned table correction (Sec. 3-4, G_*).
 
 Parity status: every function is pinned by tests in ``tests/test_oracle_*``
 (closed forms, brute force, exact special cases, invariants), except where a
 function header says "parity unpinned".
 """
-from . import green, conv, fmm, fd  # noqa: F401
+from . import green, conv, fmm, fd, mlp  # noqa: F401

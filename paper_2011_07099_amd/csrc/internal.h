@@ -107,6 +107,27 @@ hipError_t launch_batch_toeplitz(const BatchItem* items, int nitems, unsigned* c
                                  int grid, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// Learned correction of the interaction-zone tables (learned.hip)
+// ---------------------------------------------------------------------------
+constexpr int kMlpParams = 4609;  // 5 -> 64 -> 64 -> 1
+hipError_t mlp_forward(const float* theta, const float* feats, int n, int bf16, float* delta,
+                       hipStream_t st);
+hipError_t apply_correction(const double* g0, const float* delta, const int* uidx, int64_t n,
+                            double* t64, float* t32, hipStream_t st);
+hipError_t residual(const float* phi, const float* t, int64_t n, double* part, double* stats,
+                    float* r, hipStream_t st);
+size_t table_grad_partial_doubles(int m, int q, int noff);
+hipError_t table_grad(int n, int m, int q, int noff, const int* offs, const void* lam,
+                      const void* M, int fp64, int C, double* part, double* g, hipStream_t st);
+hipError_t orbit_gather(const double* g, const double* g0, const int* ptr, const int* pos, int nu,
+                        float* ddelta, hipStream_t st);
+size_t mlp_backward_partial_floats(int n);
+hipError_t mlp_backward(const float* theta, const float* feats, const float* ddelta, int n,
+                        float* part, float* grad, hipStream_t st);
+hipError_t adam_step(float* theta, float* m1, float* m2, float* grad, float count, float lr,
+                     int step, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // Upward / downward passes (tensor products of 1D Lagrange operators).
 // Gridlet buffers are FP32 or FP64 per level; `*64` flags give the type of
 // each operand (0 = float, 1 = double).  Weights are passed in both types.

@@ -56,6 +56,33 @@ struct pfmm_plan_s {
   float* part = nullptr;          // split-offset partial sums (matrix-core path)
   size_t part_floats = 0;
   void* spart = nullptr;          // split-offset partial sums (portable kernel)
+  // learned correction of the interaction-zone tables (allocated on first use)
+  int learned = 0;                // 0 none, 1 inference, 2 training
+  int nu = 0;                     // unique (|j| sorted) entries per level
+  std::vector<double*> g0;        // uncorrected FP64 level tables
+  std::vector<int*> uidx, optr, opos;
+  float* feats = nullptr;         // [(L-1) nu][5]
+  float* delta = nullptr;         // [(L-1) nu]
+  float* theta = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* wgrad = nullptr;
+  float* ddelta = nullptr;
+  float* mlp_part = nullptr;
+  float* resid = nullptr;         // mesh scratch: d loss / d phi
+  float* tphi = nullptr;          // mesh scratch: forward potential
+  double* rpart = nullptr;
+  double* rstats = nullptr;
+  std::vector<void*> lam;         // adjoint per level
+  double* tgpart = nullptr;
+  std::vector<double*> tgrad;     // table gradient per level (last accumulate)
+  int adam_t = 0, accumulated = 0;
+  double lr = 1e-3;
+  // direct periodic convolution over the whole box (allocated on first use)
+  double* dtab64 = nullptr;
+  float* dtab32 = nullptr;
+  int* doffs = nullptr;
+  int dq = 0, dC = 0, dnoff = 0;
   std::vector<void*> owned;
   // stage timing (PFMM_OPT_PROFILE): a ring of event sets, one per solve
   int profile = 0;
@@ -363,6 +390,10 @@ pfmm_status build(pfmm_plan_s* pl) {
 
 }  // namespace
 
+namespace {
+pfmm_status learned_apply(pfmm_plan_s* pl, int bf16);
+}
+
 extern "C" {
 
 pfmm_status pfmm_plan_create(int N, int L, int p, int green_kind, pfmm_plan_t* out) {
@@ -424,7 +455,16 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       std::memcpy(&v, value, sizeof v);
       if (!std::isfinite(v)) return fail(PFMM_ERR_INVALID_ARG, "a1 must be finite");
       pl->a1 = v;
-      return tabulate_all(pl);
+      pfmm_status r = tabulate_all(pl);
+      if (r != PFMM_OK || pl->g0.empty()) return r;
+      // new uncorrected tables; keep the plan's correction on top of them
+      const int64_t ntab = cube(8 * pl->p - 1);
+      for (int l = 2; l <= pl->L; ++l) {
+        const hipError_t e = hipMemcpy(pl->g0[l], pl->tab64[l], ntab * sizeof(double),
+                                       hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) return hip_fail(e, "refresh tables");
+      }
+      return pl->learned ? learned_apply(pl, 0) : PFMM_OK;
     }
     case PFMM_OPT_FP64_LEVELS: {
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels is an int32");
@@ -1019,6 +1059,345 @@ pfmm_status pfmm_batch_destroy(pfmm_batch_t b) {
   const hipError_t e = hipStreamSynchronize(b->stream);
   brelease(b);
   if (e != hipSuccess) return hip_fail(e, "batch destroy");
+  return PFMM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned correction of the interaction-zone tables, and the direct solve
+// ---------------------------------------------------------------------------
+namespace {
+
+int unique_count(int p) {  // sorted triples 4p-1 >= u1 >= u2 >= u3 >= 0
+  const int K = 4 * p;
+  return K * (K + 1) * (K + 2) / 6;
+}
+
+// Allocate the correction's index maps, features and network buffers.
+pfmm_status learned_prepare(pfmm_plan_s* pl) {
+  if (!pl->g0.empty()) return PFMM_OK;
+  const int p = pl->p, L = pl->L, C = 4 * p - 1, E = 2 * C + 1, K = 4 * p;
+  const int64_t ntab = cube(E);
+  const int nu = unique_count(p);
+  pl->nu = nu;
+  // unique index of a sorted triple
+  std::vector<int> uid((size_t)K * K * K, -1);
+  std::vector<float> fl;
+  int c = 0;
+  for (int u1 = 0; u1 < K; ++u1)
+    for (int u2 = 0; u2 <= u1; ++u2)
+      for (int u3 = 0; u3 <= u2; ++u3) uid[((size_t)u1 * K + u2) * K + u3] = c++;
+  std::vector<int> uidx((size_t)ntab);
+  std::vector<std::vector<int>> orbit(nu);
+  for (int jx = -C; jx <= C; ++jx)
+    for (int jy = -C; jy <= C; ++jy)
+      for (int jz = -C; jz <= C; ++jz) {
+        int a[3] = {std::abs(jx), std::abs(jy), std::abs(jz)};
+        std::sort(a, a + 3);
+        const int u = uid[((size_t)a[2] * K + a[1]) * K + a[0]];
+        const int64_t pos = ((int64_t)(jx + C) * E + (jy + C)) * E + (jz + C);
+        uidx[pos] = u;
+        orbit[u].push_back((int)pos);
+      }
+  std::vector<int> ptr(nu + 1, 0), pos;
+  for (int u = 0; u < nu; ++u) {
+    ptr[u + 1] = ptr[u] + (int)orbit[u].size();
+    pos.insert(pos.end(), orbit[u].begin(), orbit[u].end());
+  }
+  for (int l = 2; l <= L; ++l)
+    for (int u1 = 0; u1 < K; ++u1)
+      for (int u2 = 0; u2 <= u1; ++u2)
+        for (int u3 = 0; u3 <= u2; ++u3) {
+          fl.push_back((float)u1 / K);
+          fl.push_back((float)u2 / K);
+          fl.push_back((float)u3 / K);
+          fl.push_back((float)l / 8.f);
+          fl.push_back((float)p / 10.f);
+        }
+  const int nent = (L - 1) * nu;
+  hipError_t e = hipSuccess;
+  pl->g0.assign(L + 1, nullptr);
+  pl->uidx.assign(L + 1, nullptr);
+  pl->optr.assign(L + 1, nullptr);
+  pl->opos.assign(L + 1, nullptr);
+  pl->lam.assign(L + 1, nullptr);
+  pl->tgrad.assign(L + 1, nullptr);
+  int* d_uidx = nullptr;
+  int* d_ptr = nullptr;
+  int* d_pos = nullptr;
+  e = dalloc(pl, &d_uidx, (size_t)ntab);
+  if (e == hipSuccess) e = dalloc(pl, &d_ptr, ptr.size());
+  if (e == hipSuccess) e = dalloc(pl, &d_pos, pos.size());
+  if (e == hipSuccess) e = hipMemcpy(d_uidx, uidx.data(), uidx.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_pos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice);
+  for (int l = 2; l <= L && e == hipSuccess; ++l) {
+    pl->uidx[l] = d_uidx;
+    pl->optr[l] = d_ptr;
+    pl->opos[l] = d_pos;
+    e = dalloc(pl, &pl->g0[l], (size_t)ntab);
+    if (e == hipSuccess)
+      e = hipMemcpy(pl->g0[l], pl->tab64[l], ntab * sizeof(double), hipMemcpyDeviceToDevice);
+  }
+  if (e == hipSuccess) e = dalloc(pl, &pl->feats, fl.size());
+  if (e == hipSuccess) e = hipMemcpy(pl->feats, fl.data(), fl.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = dalloc(pl, &pl->delta, (size_t)nent);
+  if (e == hipSuccess) e = dalloc(pl, &pl->theta, (size_t)kMlpParams);
+  if (e != hipSuccess) {
+    pl->g0.clear();
+    return hip_fail(e, "learned correction buffers");
+  }
+  return PFMM_OK;
+}
+
+// Tables from the current network (or the uncorrected ones when learned == 0).
+pfmm_status learned_apply(pfmm_plan_s* pl, int bf16) {
+  const int p = pl->p, C = 4 * p - 1;
+  const int64_t ntab = cube(2 * C + 1);
+  hipStream_t st = pl->stream;
+  hipError_t e = hipSuccess;
+  if (pl->learned)
+    e = mlp_forward(pl->theta, pl->feats, (pl->L - 1) * pl->nu, bf16, pl->delta, st);
+  for (int l = 2; l <= pl->L && e == hipSuccess; ++l) {
+    if (pl->learned) {
+      e = apply_correction(pl->g0[l], pl->delta + (size_t)(l - 2) * pl->nu, pl->uidx[l], ntab,
+                           pl->tab64[l], pl->tab32[l], st);
+    } else {
+      e = hipMemcpyAsync(pl->tab64[l], pl->g0[l], ntab * sizeof(double), hipMemcpyDeviceToDevice,
+                         st);
+      if (e == hipSuccess) e = cast_f64_f32(pl->tab64[l], pl->tab32[l], ntab, st);
+    }
+    if (e == hipSuccess && pl->win[l])
+      e = make_windows(pl->tab64[l], C, kM2LTerms, pl->win[l], st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "apply learned correction");
+  return PFMM_OK;
+}
+
+pfmm_status learned_train_alloc(pfmm_plan_s* pl) {
+  if (pl->adam_m) return PFMM_OK;
+  const int N = pl->N, L = pl->L, p = pl->p;
+  const size_t n3 = (size_t)N * N * N, p3 = (size_t)p * p * p;
+  const int nent = (L - 1) * pl->nu;
+  const int64_t ntab = cube(8 * p - 1);
+  hipError_t e = dalloc(pl, &pl->adam_m, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dalloc(pl, &pl->adam_v, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dalloc(pl, &pl->wgrad, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dalloc(pl, &pl->ddelta, (size_t)nent);
+  if (e == hipSuccess) e = dalloc(pl, &pl->mlp_part, mlp_backward_partial_floats(nent));
+  if (e == hipSuccess) e = dalloc(pl, &pl->resid, n3);
+  if (e == hipSuccess) e = dalloc(pl, &pl->tphi, n3);
+  if (e == hipSuccess) e = dalloc(pl, &pl->rpart, (size_t)4 * 1024);
+  if (e == hipSuccess) e = dalloc(pl, &pl->rstats, (size_t)4);
+  size_t tg = 0;
+  for (int l = 2; l <= L && e == hipSuccess; ++l) {
+    char* b = nullptr;
+    e = dalloc(pl, &b, ((size_t)1 << (3 * l)) * p3 * (l <= 3 ? sizeof(double) : sizeof(float)));
+    pl->lam[l] = b;
+    if (e == hipSuccess) e = dalloc(pl, &pl->tgrad[l], (size_t)ntab);
+    tg = std::max(tg, table_grad_partial_doubles(l == 2 ? 1 : 2, p, l == 2 ? 37 : 189));
+  }
+  if (e == hipSuccess) e = dalloc(pl, &pl->tgpart, tg);
+  if (e == hipSuccess) e = hipMemset(pl->adam_m, 0, kMlpParams * 4);
+  if (e == hipSuccess) e = hipMemset(pl->adam_v, 0, kMlpParams * 4);
+  if (e == hipSuccess) e = hipMemset(pl->wgrad, 0, kMlpParams * 4);
+  if (e != hipSuccess) return hip_fail(e, "training buffers");
+  return PFMM_OK;
+}
+
+pfmm_status direct_prepare(pfmm_plan_s* pl) {
+  if (pl->dtab64) return PFMM_OK;
+  const int N = pl->N;
+  const int q = N >= 16 ? 8 : N / 2, n = N / q;
+  const int C = N / 2 + q - 1;
+  std::vector<int> offs;
+  for (int dx = -n / 2; dx < n / 2; ++dx)
+    for (int dy = -n / 2; dy < n / 2; ++dy)
+      for (int dz = -n / 2; dz < n / 2; ++dz) offs.push_back(pack_offset(dx, dy, dz));
+  const int64_t ntab = cube(2 * C + 1);
+  hipError_t e = dalloc(pl, &pl->dtab64, (size_t)ntab);
+  if (e == hipSuccess) e = dalloc(pl, &pl->dtab32, (size_t)ntab);
+  if (e == hipSuccess) e = dalloc(pl, &pl->doffs, offs.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->doffs, offs.data(), offs.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = tabulate_green(pl->green, pl->a1, N, C, N, 1.0 / N, pl->dtab64, pl->stream);
+  if (e == hipSuccess) e = cast_f64_f32(pl->dtab64, pl->dtab32, ntab, pl->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) {
+    pl->dtab64 = nullptr;
+    return hip_fail(e, "direct solve tables");
+  }
+  pl->dq = q;
+  pl->dC = C;
+  pl->dnoff = (int)offs.size();
+  return PFMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pfmm_status pfmm_plan_direct(pfmm_plan_t pl, const float* rho, float* phi) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!rho || !phi || (const void*)rho == (const void*)phi)
+    return fail(PFMM_ERR_INVALID_ARG, "density and potential must be distinct device arrays");
+  pfmm_status s0 = direct_prepare(pl);
+  if (s0 != PFMM_OK) return s0;
+  ToepArgs a{};
+  a.n = pl->N / pl->dq;
+  a.m = 1;
+  a.q = pl->dq;
+  a.noff = pl->dnoff;
+  a.offs = pl->doffs;
+  a.tab = pl->dtab32;
+  a.C = pl->dC;
+  a.X = rho;
+  a.Y = phi;
+  a.grid_in = 1;
+  a.grid_out = 1;
+  a.xscale = 1.0 / ((double)pl->N * pl->N * pl->N);
+  a.accumulate = 0;
+  a.groups = 1;
+  const hipError_t e = launch_toeplitz(a, pl->stream);
+  if (e != hipSuccess) return hip_fail(e, "direct solve");
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_learned_set(pfmm_plan_t pl, const float* weights, int bf16) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!weights) {
+    if (pl->g0.empty()) return PFMM_OK;  // never corrected
+    pl->learned = 0;
+    return learned_apply(pl, 0);
+  }
+  pfmm_status s0 = learned_prepare(pl);
+  if (s0 != PFMM_OK) return s0;
+  hipError_t e = hipMemcpy(pl->theta, weights, kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload weights");
+  pl->learned = 1;
+  return learned_apply(pl, bf16 ? 1 : 0);
+}
+
+pfmm_status pfmm_learned_train_begin(pfmm_plan_t pl, const float* weights, double lr) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!weights || !(lr > 0.0)) return fail(PFMM_ERR_INVALID_ARG, "need weights and lr > 0");
+  pfmm_status s0 = learned_prepare(pl);
+  if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
+  if (s0 != PFMM_OK) return s0;
+  hipError_t e = hipMemcpy(pl->theta, weights, kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(pl->adam_m, 0, kMlpParams * 4);
+  if (e == hipSuccess) e = hipMemset(pl->adam_v, 0, kMlpParams * 4);
+  if (e == hipSuccess) e = hipMemset(pl->wgrad, 0, kMlpParams * 4);
+  if (e != hipSuccess) return hip_fail(e, "training state");
+  pl->learned = 2;
+  pl->adam_t = 0;
+  pl->accumulated = 0;
+  pl->lr = lr;
+  return learned_apply(pl, 0);
+}
+
+pfmm_status pfmm_learned_accumulate(pfmm_plan_t pl, const float* rho, const float* target,
+                                    double* loss) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (pl->learned != 2) return fail(PFMM_ERR_INVALID_ARG, "call pfmm_learned_train_begin first");
+  if (!rho || !target) return fail(PFMM_ERR_INVALID_ARG, "density and target are required");
+  const int N = pl->N, L = pl->L, p = pl->p;
+  const int64_t n3 = (int64_t)N * N * N;
+  hipStream_t st = pl->stream;
+  pfmm_status s0 = pfmm_solve(pl, rho, pl->tphi, nullptr);
+  if (s0 != PFMM_OK) return s0;
+  hipError_t e = residual(pl->tphi, target, n3, pl->rpart, pl->rstats, pl->resid, st);
+  // adjoint sweep: transposes of L2P and L2L
+  if (e == hipSuccess)
+    e = launch_p2m(pl->resid, pl->lam[L], level64(pl, L), wts(pl->dA, pl->dA64), N, pl->s, p, 1.0,
+                   st);
+  for (int l = L - 1; l >= 2 && e == hipSuccess; --l)
+    e = launch_m2m(pl->lam[l + 1], level64(pl, l + 1), pl->lam[l], level64(pl, l),
+                   wts(pl->dT, pl->dT64), 1 << l, p, st);
+  const int nent = (L - 1) * pl->nu;
+  if (e == hipSuccess) e = hipMemsetAsync(pl->ddelta, 0, nent * sizeof(float), st);
+  for (int l = 2; l <= L && e == hipSuccess; ++l) {
+    const int m = l == 2 ? 1 : 2, noff = l == 2 ? 37 : 189;
+    e = table_grad(1 << l, m, p, noff, l == 2 ? pl->offs_l2 : pl->offs_iz, pl->lam[l], pl->M[l],
+                   level64(pl, l), 4 * p - 1, pl->tgpart, pl->tgrad[l], st);
+    if (e == hipSuccess)
+      e = orbit_gather(pl->tgrad[l], pl->g0[l], pl->optr[l], pl->opos[l], pl->nu,
+                       pl->ddelta + (size_t)(l - 2) * pl->nu, st);
+  }
+  if (e == hipSuccess)
+    e = mlp_backward(pl->theta, pl->feats, pl->ddelta, nent, pl->mlp_part, pl->wgrad, st);
+  double stats[3] = {0, 0, 0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(stats, pl->rstats, sizeof stats, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "learned gradient");
+  ++pl->accumulated;
+  if (loss) *loss = stats[1];
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_learned_loss(pfmm_plan_t pl, const float* rho, const float* target,
+                              double* loss) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!rho || !target || !loss) return fail(PFMM_ERR_INVALID_ARG, "NULL argument");
+  pfmm_status s0 = learned_prepare(pl);
+  if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
+  if (s0 == PFMM_OK) s0 = pfmm_solve(pl, rho, pl->tphi, nullptr);
+  if (s0 != PFMM_OK) return s0;
+  const int64_t n3 = (int64_t)pl->N * pl->N * pl->N;
+  double stats[3] = {0, 0, 0};
+  hipError_t e = residual(pl->tphi, target, n3, pl->rpart, pl->rstats, pl->resid, pl->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(stats, pl->rstats, sizeof stats, hipMemcpyDeviceToHost, pl->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) return hip_fail(e, "loss");
+  *loss = stats[1];
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_learned_step(pfmm_plan_t pl) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (pl->learned != 2 || pl->accumulated == 0)
+    return fail(PFMM_ERR_INVALID_ARG, "no accumulated gradient");
+  const hipError_t e = adam_step(pl->theta, pl->adam_m, pl->adam_v, pl->wgrad,
+                                 (float)pl->accumulated, (float)pl->lr, ++pl->adam_t, pl->stream);
+  if (e != hipSuccess) return hip_fail(e, "adam");
+  pl->accumulated = 0;
+  return learned_apply(pl, 0);
+}
+
+pfmm_status pfmm_learned_get(pfmm_plan_t pl, float* weights) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!weights || !pl->learned) return fail(PFMM_ERR_INVALID_ARG, "no network on this plan");
+  const hipError_t e =
+      hipMemcpy(weights, pl->theta, kMlpParams * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "download weights");
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_learned_read_grad(pfmm_plan_t pl, int level, double* table_grad,
+                                   float* weight_grad) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (pl->learned != 2) return fail(PFMM_ERR_INVALID_ARG, "not training");
+  if (level < 2 || level > pl->L) return fail(PFMM_ERR_INVALID_ARG, "level out of range");
+  hipError_t e = hipSuccess;
+  if (table_grad)
+    e = hipMemcpy(table_grad, pl->tgrad[level], cube(8 * pl->p - 1) * sizeof(double),
+                  hipMemcpyDeviceToHost);
+  if (e == hipSuccess && weight_grad)
+    e = hipMemcpy(weight_grad, pl->wgrad, kMlpParams * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "read gradient");
   return PFMM_OK;
 }
 

@@ -22,7 +22,10 @@ BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
 EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_plan_read",
            "pfmm_plan_stage_times", "pfmm_plan_info", "pfmm_plan_destroy",
            "pfmm_batch_create", "pfmm_batch_solve", "pfmm_batch_info", "pfmm_batch_destroy",
-           "pfmm_last_error")
+           "pfmm_plan_direct", "pfmm_learned_set", "pfmm_learned_train_begin",
+           "pfmm_learned_accumulate", "pfmm_learned_loss", "pfmm_learned_step", "pfmm_learned_get",
+           "pfmm_learned_read_grad", "pfmm_last_error")
+MLP_PARAMS = 4609
 
 _lib = None
 
@@ -56,6 +59,16 @@ def load():
     lib.pfmm_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(ctypes.c_double)]
     lib.pfmm_batch_destroy.argtypes = [vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.pfmm_plan_direct.argtypes = [vp, vp, vp]
+    lib.pfmm_learned_set.argtypes = [vp, fp, i32]
+    lib.pfmm_learned_train_begin.argtypes = [vp, fp, ctypes.c_double]
+    lib.pfmm_learned_accumulate.argtypes = [vp, vp, vp, dp]
+    lib.pfmm_learned_loss.argtypes = [vp, vp, vp, dp]
+    lib.pfmm_learned_step.argtypes = [vp]
+    lib.pfmm_learned_get.argtypes = [vp, fp]
+    lib.pfmm_learned_read_grad.argtypes = [vp, i32, dp, fp]
     lib.pfmm_last_error.restype = ctypes.c_char_p
     for f in EXPORTS[:-1]:
         getattr(lib, f).restype = i32
@@ -140,6 +153,60 @@ class Plan:
             if t.dtype != torch.float32 or t.numel() != n:
                 raise ValueError("expected float32 tensors of N^3 (accel 3 N^3) elements")
         _check(load().pfmm_solve(self._h, _ptr(rho), _ptr(phi), _ptr(accel)))
+
+    def direct(self, rho, phi):
+        """Exact periodic convolution with the plan's G on the device (O(N^6))."""
+        _check(load().pfmm_plan_direct(self._h, _ptr(rho), _ptr(phi)))
+
+    # --- learned correction of the interaction-zone tables ---------------
+    @staticmethod
+    def _f32(w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != MLP_PARAMS:
+            raise ValueError("weights must have %d entries" % MLP_PARAMS)
+        return w, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def set_learned(self, weights, bf16=True):
+        """Correct the tables with the network (None: back to the plain G)."""
+        if weights is None:
+            _check(load().pfmm_learned_set(self._h, None, 0))
+            return
+        w, ptr = self._f32(weights)
+        _check(load().pfmm_learned_set(self._h, ptr, 1 if bf16 else 0))
+
+    def train_begin(self, weights, lr):
+        w, ptr = self._f32(weights)
+        _check(load().pfmm_learned_train_begin(self._h, ptr, float(lr)))
+
+    def train_accumulate(self, rho, target):
+        loss = ctypes.c_double()
+        _check(load().pfmm_learned_accumulate(self._h, _ptr(rho), _ptr(target), ctypes.byref(loss)))
+        return loss.value
+
+    def loss(self, rho, target):
+        """Relative mean-removed squared residual against target, no gradient."""
+        v = ctypes.c_double()
+        _check(load().pfmm_learned_loss(self._h, _ptr(rho), _ptr(target), ctypes.byref(v)))
+        return v.value
+
+    def train_step(self):
+        _check(load().pfmm_learned_step(self._h))
+
+    def learned_weights(self):
+        import numpy as np
+        w = np.empty(MLP_PARAMS, np.float32)
+        _check(load().pfmm_learned_get(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return w
+
+    def learned_grads(self, level):
+        import numpy as np
+        g = np.empty((8 * self.p - 1) ** 3, np.float64)
+        w = np.empty(MLP_PARAMS, np.float32)
+        _check(load().pfmm_learned_read_grad(self._h, int(level),
+                                             g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return g.reshape((8 * self.p - 1,) * 3), w
 
     def read(self, buffer, level, out):
         _check(load().pfmm_plan_read(self._h, int(buffer), int(level), _ptr(out)))

@@ -1,0 +1,47 @@
+"""Pins of the oracle's learned-correction network: closed forms of the
+activation and of a hand-set network, zero-output fallback, symmetry."""
+import itertools
+import math
+
+import numpy as np
+
+from oracle import mlp
+
+
+def test_silu_closed_form():
+    for z in (-3.0, -0.5, 0.0, 0.7, 4.0):
+        assert abs(mlp.silu(np.array(z)) - z / (1 + math.exp(-z))) < 1e-15
+
+
+def test_zero_output_layer_is_the_plain_table():
+    rng = np.random.default_rng(0)
+    th = rng.standard_normal(mlp.N_PARAMS)
+    th[4544:4609] = 0.0
+    tab = rng.standard_normal((9, 9, 9))
+    np.testing.assert_array_equal(mlp.corrected_table(tab, 2, 3, th), tab)
+
+
+def test_hand_set_network():
+    # one path: h1_0 = silu(x0), h2_0 = silu(2 h1_0 - 1), out = 3 h2_0 + 0.5
+    th = np.zeros(mlp.N_PARAMS)
+    th[0 * 5 + 0] = 1.0            # W1[0][0]
+    th[384 + 0 * 64 + 0] = 2.0     # W2[0][0]
+    th[4480 + 0] = -1.0            # b2[0]
+    th[4544 + 0] = 3.0             # W3[0]
+    th[4608] = 0.5                 # b3
+    for x0 in (0.0, 0.3, 0.9):
+        x = np.array([x0, 0.2, 0.1, 0.25, 0.6])
+        s = lambda z: z / (1 + math.exp(-z))
+        expect = 3 * s(2 * s(x0) - 1) + 0.5
+        assert abs(mlp.forward(th, x) - expect) < 1e-14
+
+
+def test_features_cube_symmetry():
+    rng = np.random.default_rng(1)
+    j = rng.integers(-23, 24, (50, 3))
+    f = mlp.features(j, 3, 6)
+    for perm in itertools.permutations(range(3)):
+        for sg in itertools.product((1, -1), repeat=3):
+            np.testing.assert_array_equal(mlp.features(j[:, perm] * np.array(sg), 3, 6), f)
+    assert np.all(f[:, 0] >= f[:, 1]) and np.all(f[:, 1] >= f[:, 2])
+    np.testing.assert_allclose(f[:, 3:], [[3 / 8, 0.6]] * 50)
