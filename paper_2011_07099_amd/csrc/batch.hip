@@ -33,6 +33,7 @@ __device__ void item_body(const BatchItem& it, T* sl, T* xs) {
   constexpr int R = Q * Q;
   constexpr int Q3 = Q * Q * Q;
   constexpr int S = 2 * Q - 1;
+  constexpr int SY = Q == 8 ? 24 : S;  // padded slice rows per x plane (bank spread)
   constexpr int G = kThreads / R;
   constexpr int TT = G * TPT;
   const int tid = threadIdx.x;
@@ -60,10 +61,11 @@ __device__ void item_body(const BatchItem& it, T* sl, T* xs) {
     __syncthreads();
     for (int i = tid; i < S * S * S; i += kThreads) {
       const int jx = i / (S * S), jy = (i / S) % S, jz = i % S;
+      const int li = (jx * SY + jy) * S + jz;  // padded slice position
       const int ix = -Q * dx + jx - (Q - 1) + it.C;
       const int iy = -Q * dy + jy - (Q - 1) + it.C;
       const int iz = -Q * dz + jz - (Q - 1) + it.C;
-      sl[i] = static_cast<const T*>(it.tab)[((size_t)ix * E + iy) * E + iz];
+      sl[li] = static_cast<const T*>(it.tab)[((size_t)ix * E + iy) * E + iz];
     }
     for (int i = tid; i < TT * Q3; i += kThreads) {
       const int tl = i / Q3, e = i % Q3;
@@ -95,7 +97,7 @@ __device__ void item_body(const BatchItem& it, T* sl, T* xs) {
       for (int bx = 0; bx < Q; ++bx) {
         for (int by = 0; by < Q; ++by) {
           T sv[S];
-          const T* sp = sl + ((ax - bx + Q - 1) * S + (ay - by + Q - 1)) * S;
+          const T* sp = sl + ((ax - bx + Q - 1) * SY + (ay - by + Q - 1)) * S;
 #pragma unroll
           for (int j = 0; j < S; ++j) sv[j] = sp[j];
 #pragma unroll
@@ -142,7 +144,7 @@ __device__ void item_body(const BatchItem& it, T* sl, T* xs) {
 // FP32 items with tile width TPT and FP64 items with tile width 1
 template <int TPT>
 struct BatchLds {
-  static constexpr int kSlice = 15 * 15 * 15;
+  static constexpr int kSlice = 15 * 24 * 15;  // padded slice of q = 8
   static constexpr int kF32 = (kSlice + (kThreads / 64) * TPT * 512) * 4;
   static constexpr int kF64 = (kSlice + (kThreads / 64) * 512) * 8;
   static constexpr int kBytes = kF32 > kF64 ? kF32 : kF64;

@@ -87,6 +87,22 @@ hipError_t split_mesh(const float* rho, float scale, int N, int nt, uint16_t* ou
                       hipStream_t st);
 hipError_t launch_toep8_split(const ToepMfmaArgs& a, int nt, hipStream_t st);
 
+// FP64 form on the matrix cores for the FP64 coarse levels (q = 8): FP64
+// table (centre C >= 31), FP64 sources and outputs [n^3][512].
+struct ToepF64Args {
+  int n, m, noff;
+  const int* offs;
+  const double* tab;
+  int C;
+  const double* X;
+  double* Y;
+  int accumulate;
+  int groups;
+  double* partial;  // [groups][n^3][512] when groups > 1
+};
+int toep8_f64_tiles(int n, int m);
+hipError_t launch_toep8_f64(const ToepF64Args& a, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Batches of independent fields (batch.hip): one work item = one tile of
 // targets of one class of one interaction-zone level or near zone of one

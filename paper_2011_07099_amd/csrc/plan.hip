@@ -211,6 +211,13 @@ int scalar_groups(int q, int fp64, int n, int m, int noff) {
   return g < noff ? g : noff;
 }
 
+// Offset groups of an FP64 matrix-core launch: at least 512 workgroups.
+int f64_groups(int n, int m, int noff) {
+  const int tiles = toep8_f64_tiles(n, m);
+  const int g = (512 + tiles - 1) / tiles;
+  return g < noff ? g : noff;
+}
+
 int m2l_groups(int l) {
   const int tiles = 1 << (3 * (l - 2));
   int g = (512 + tiles - 1) / tiles;
@@ -329,7 +336,8 @@ pfmm_status build(pfmm_plan_s* pl) {
     for (int l = 2; l <= L; ++l) {
       const int n = 1 << l, m = l == 2 ? 1 : 2, noff = l == 2 ? 37 : 189;
       for (int f64 = 0; f64 <= (l <= 3 ? 1 : 0); ++f64) {  // the FP64 level count is an option
-        const int G = scalar_groups(p, f64, n, m, noff);
+        int G = scalar_groups(p, f64, n, m, noff);
+        if (f64 && p == 8) G = std::max(G, f64_groups(n, m, noff));
         const size_t w = f64 ? sizeof(double) : sizeof(float);
         if (G > 1) bytes = std::max(bytes, (size_t)G * ((size_t)1 << (3 * l)) * p3 * w);
       }
@@ -519,6 +527,22 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   // interaction zone of one level: matrix cores for FP32 levels with windows
   auto m2l = [&](const ToepArgs& ta0, int l) -> hipError_t {
     ToepArgs ta = ta0;
+    if (ta.fp64 && ta.q == 8 && ta.C >= 31) {  // FP64 coarse level on the matrix cores
+      ToepF64Args fa{};
+      fa.n = ta.n;
+      fa.m = ta.m;
+      fa.noff = ta.noff;
+      fa.offs = ta.offs;
+      fa.tab = (const double*)ta.tab;
+      fa.C = ta.C;
+      fa.X = (const double*)ta.X;
+      fa.Y = (double*)ta.Y;
+      fa.accumulate = ta.accumulate;
+      fa.groups = f64_groups(ta.n, ta.m, ta.noff);
+      fa.partial = fa.groups > 1 ? (double*)pl->spart : nullptr;
+      if (fa.groups > 1 && !fa.partial) fa.groups = 1;
+      return launch_toep8_f64(fa, st);
+    }
     if (!mx || ta.fp64 || !pl->win[l]) {
       ta.groups = scalar_groups(ta.q, ta.fp64, ta.n, ta.m, ta.noff);
       ta.partial = ta.groups > 1 ? pl->spart : nullptr;

@@ -35,9 +35,12 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
   constexpr int R = Q * Q;                                   // z-rows of a block
   constexpr int Q3 = Q * Q * Q;
   constexpr int S = 2 * Q - 1;                               // slice extent per axis
+  // slice rows per x plane: 24 for q = 8 spreads the 64 lanes (ax, ay) of a
+  // wave over 8 ax + ay (mod 16) bank groups (conflict-free slice reads)
+  constexpr int SY = Q == 8 ? 24 : S;
   constexpr int G = (kThreads / R) < GMAX ? (kThreads / R) : GMAX;  // thread groups
   constexpr int TT = G * TPT;                                // targets per workgroup
-  __shared__ T sl[S * S * S];
+  __shared__ T sl[S * SY * S];
   __shared__ T xs[TT * Q3];
 
   const T* tab = static_cast<const T*>(a.tab);
@@ -72,10 +75,11 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
     __syncthreads();
     for (int i = tid; i < S * S * S; i += kThreads) {
       const int jx = i / (S * S), jy = (i / S) % S, jz = i % S;
+      const int li = (jx * SY + jy) * S + jz;  // padded slice position
       const int ix = -Q * dx + jx - (Q - 1) + a.C;
       const int iy = -Q * dy + jy - (Q - 1) + a.C;
       const int iz = -Q * dz + jz - (Q - 1) + a.C;
-      sl[i] = tab[((size_t)ix * E + iy) * E + iz];
+      sl[li] = tab[((size_t)ix * E + iy) * E + iz];
     }
     for (int i = tid; i < TT * Q3; i += kThreads) {
       const int tl = i / Q3, e = i % Q3;
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
       for (int bx = 0; bx < Q; ++bx) {
         for (int by = 0; by < Q; ++by) {
           T sv[S];
-          const T* sp = sl + ((ax - bx + Q - 1) * S + (ay - by + Q - 1)) * S;
+          const T* sp = sl + ((ax - bx + Q - 1) * SY + (ay - by + Q - 1)) * S;
 #pragma unroll
           for (int j = 0; j < S; ++j) sv[j] = sp[j];
 #pragma unroll
@@ -168,7 +172,8 @@ hipError_t launch_q(const ToepArgs& a, hipStream_t st) {
   constexpr int R = Q * Q;
   constexpr int G = (kThreads / R) < GMAX ? (kThreads / R) : GMAX;
   constexpr int TT = G * TPT;
-  static_assert(((2 * Q - 1) * (2 * Q - 1) * (2 * Q - 1) + TT * Q * Q * Q) * sizeof(T) <= 65536,
+  constexpr int SY = Q == 8 ? 24 : 2 * Q - 1;
+  static_assert(((2 * Q - 1) * SY * (2 * Q - 1) + TT * Q * Q * Q) * sizeof(T) <= 65536,
                 "LDS budget");
   const int nk = a.n / a.m;
   const int ntarg = nk * nk * nk;

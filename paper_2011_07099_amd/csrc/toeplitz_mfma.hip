@@ -366,7 +366,144 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 form on v_mfma_f64_16x16x4_f64 for the FP64 coarse levels (q = 8).
+// Workgroup tile: 512 outputs x 16 consecutive targets of one class; wave w
+// holds outputs [128 w, 128 w + 128) as 8 tiles of 16 rows (a tile: fixed x,
+// 2 y, 8 z indices).  A k-step takes 4 consecutive sources a' (fixed x, y,
+// 4 z indices).  The A operand is one double per lane from the offset's FP64
+// window (15^3, double-buffered in LDS); the B operand one double per lane
+// read from the L2-resident sources with a register prefetch of 8 k-steps.
+// ---------------------------------------------------------------------------
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kW64 = 15 * 15 * 15;
+
+__global__ __launch_bounds__(256) void k_toep8_f64(ToepF64Args a) {
+  __shared__ double Wd[2][kW64];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int l16 = l & 15, kq = l >> 4;  // row / column within a tile, k lane group
+  const int m = a.m, nk = a.n / m, ntarg = nk * nk * nk;
+  const int tiles = (ntarg + 15) / 16;
+  const int cls = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const int cx = cls / (m * m), cy = (cls / m) % m, cz = cls % m;
+  const int g = blockIdx.y;
+  const int ob = (a.noff * g) / a.groups, oe = (a.noff * (g + 1)) / a.groups;
+  const int* offs = a.offs + (size_t)cls * a.noff;
+  const int E = 2 * a.C + 1, nmask = a.n - 1;
+
+  // this lane's target (B column / C column)
+  const int tk = tile * 16 + l16;
+  const bool tvalid = tk < ntarg;
+  const int tkk = tvalid ? tk : 0;
+  const int tx = cx + m * (tkk / (nk * nk)), ty = cy + m * ((tkk / nk) % nk), tz = cz + m * (tkk % nk);
+
+  double rw[14];
+  auto load_W = [&](int k) {
+    const int pk = offs[k];
+    const int dx = ((pk >> 16) & 255) - 128, dy = ((pk >> 8) & 255) - 128, dz = (pk & 255) - 128;
+#pragma unroll
+    for (int r = 0; r < 14; ++r) {
+      const int i = tid + 256 * r;
+      double v = 0.0;
+      if (i < kW64) {
+        const int jx = i / 225, jy = (i / 15) % 15, jz = i % 15;
+        v = a.tab[((size_t)(jx - 7 - 8 * dx + a.C) * E + (jy - 7 - 8 * dy + a.C)) * E +
+                  (jz - 7 - 8 * dz + a.C)];
+      }
+      rw[r] = v;
+    }
+  };
+  auto store_W = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 14; ++r) {
+      const int i = tid + 256 * r;
+      if (i < kW64) Wd[buf][i] = rw[r];
+    }
+  };
+
+  doublex4 acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  // A rows of tile i: ax = 2w + i/4, ay = 2(i%4) + l16/8, az = l16%8
+  const int azl = l16 & 7, ayl = l16 >> 3;
+  if (ob < oe) {
+    load_W(ob);
+    store_W(0);
+    __syncthreads();
+    for (int k = ob; k < oe; ++k) {
+      const double* W = &Wd[(k - ob) & 1][0];
+      const int pk = offs[k];
+      const int dx = ((pk >> 16) & 255) - 128, dy = ((pk >> 8) & 255) - 128, dz = (pk & 255) - 128;
+      const int ux = (tx + dx) & nmask, uy = (ty + dy) & nmask, uz = (tz + dz) & nmask;
+      const double* X = a.X + (((size_t)ux * a.n + uy) * a.n + uz) * 512;
+      const bool has_next = k + 1 < oe;
+      if (has_next) load_W(k + 1);
+      double b[8], bn[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[u] = tvalid ? X[4 * u + kq] : 0.0;
+      for (int blk = 0; blk < 16; ++blk) {  // 16 blocks of 8 k-steps
+        if (blk + 1 < 16) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) bn[u] = tvalid ? X[32 * (blk + 1) + 4 * u + kq] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int s = 8 * blk + u;           // k-step: sources 4s .. 4s+3
+          const int bx = s >> 4, by = (s >> 1) & 7, bz = 4 * (s & 1) + kq;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int ax = 2 * w + (i >> 2), ay = 2 * (i & 3) + ayl;
+            const double av = W[((ax - bx + 7) * 15 + (ay - by + 7)) * 15 + (azl - bz + 7)];
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[u], acc[i], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = bn[u];
+      }
+      if (has_next) store_W((k + 1 - ob) & 1);
+      __syncthreads();
+    }
+  }
+  // epilogue: lane holds rows kq + 4 v of each tile, column l16
+  if (!tvalid) return;
+  const size_t node = ((size_t)tx * a.n + ty) * a.n + tz;
+  double* Y = a.partial ? a.partial + (size_t)g * a.n * a.n * a.n * 512 : a.Y;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double* d = Y + node * 512 + 128 * w + 16 * i + kq;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      d[4 * v] = (a.accumulate && !a.partial) ? d[4 * v] + acc[i][v] : acc[i][v];
+  }
+}
+
+__global__ void k_reduce_f64(const double* __restrict__ part, int groups, int64_t n,
+                             double* __restrict__ Y, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = accumulate ? Y[i] : 0.0;
+  for (int g = 0; g < groups; ++g) s += part[(int64_t)g * n + i];
+  Y[i] = s;
+}
+
 }  // namespace
+
+int toep8_f64_tiles(int n, int m) {
+  const int nk = n / m;
+  return ((nk * nk * nk + 15) / 16) * m * m * m;
+}
+
+hipError_t launch_toep8_f64(const ToepF64Args& a, hipStream_t st) {
+  if (a.groups < 1 || (a.groups > 1 && !a.partial) || a.C < 31) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_toep8_f64, dim3(toep8_f64_tiles(a.n, a.m), a.groups), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.partial) return e;
+  const int64_t n = (int64_t)a.n * a.n * a.n * 512;
+  hipLaunchKernelGGL(k_reduce_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.partial,
+                     a.groups, n, a.Y, a.accumulate);
+  return hipGetLastError();
+}
 
 bool toep8_supported(int n, int m) {
   const int nk = n / m;
