@@ -31,6 +31,9 @@ ALPHA, SIGMA, SEED = 1.5, 2.0, 5
 METRIC = "cells/s at 256^3 p=8 periodic FMM, L2 err<=1e-4 vs PM; M2L MFMA util"
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
+# MI355X peaks (TFLOP/s) of the units each contraction runs on
+PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 157.3}
+FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 
 # HBM bytes per launch of the near-zone kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB), scaled by a plain 1 GiB copy (read x2.0, write x1.0), keyed
@@ -267,6 +270,7 @@ def main():
     torch.cuda.synchronize()
     ms = t_start.elapsed_time(t_end) / args.steps
     stages = plan.stage_times()
+    m2l_levels = plan.level_times("m2l")
     plan.close()
 
     near_flops, m2l_flops = algorithmic_flops(N, L, P)
@@ -275,6 +279,20 @@ def main():
     m2l_ms = stages["m2l"][0]
     near_tf = near_flops / (near_ms * 1e-3) / 1e12
     m2l_tf = m2l_flops / (m2l_ms * 1e-3) / 1e12
+    near_unit, near_products = ("bf16 mfma", 3) if args.precision == "bf16x3" else ("f32 valu", 1)
+    per_level = {}
+    for lv, lms in sorted(m2l_levels.items()):
+        fl = (37 if lv == 2 else 189) * 2.0 * P ** 6 * 8 ** lv
+        if lv in FP64_LEVELS:
+            unit, products = "f64 mfma", 1
+        elif args.precision == "bf16x3":
+            unit, products = "bf16 mfma", 6
+        else:
+            unit, products = "f32 valu", 1
+        tf = fl / (lms * 1e-3) / 1e12
+        per_level[str(lv)] = {"ms": lms, "unit": unit, "products": products,
+                              "achieved": tf, "issued": tf * products, "peak": PEAK_UNIT[unit],
+                              "frac": tf * products / PEAK_UNIT[unit]}
     out = {
         "metric": METRIC,
         "value": N ** 3 / (ms * 1e-3),
@@ -291,11 +309,14 @@ def main():
         "config": {"workload": "periodic FMM, 256^3 lognormal density (P(k)~k^-1.5, "
                                "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
                    "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision},
-        "roofline": {"bound": "mfma", "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma" if near_unit.endswith("mfma") else "alu",
+                     "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
                      "frac": near_tf / peak, "traffic": traffic_bytes(args.precision),
-                     "kernel": "near zone (%d launch/step, %.3f ms)" % (stages["near"][1], near_ms)},
-        "m2l": {"achieved": m2l_tf, "peak": peak, "unit": "TFLOP/s", "frac": m2l_tf / peak,
-                "ms": m2l_ms, "launches": stages["m2l"][1]},
+                     "kernel": "near zone (%d launch/step, %.3f ms)" % (stages["near"][1], near_ms),
+                     "unit_used": near_unit, "products": near_products,
+                     "issued_frac": near_tf * near_products / peak},
+        "m2l": {"achieved": m2l_tf, "unit": "TFLOP/s", "ms": m2l_ms,
+                "launches": stages["m2l"][1], "levels": per_level},
         "stages_ms": {k: v[0] for k, v in stages.items()},
     }
     if not args.no_cpu_baseline:

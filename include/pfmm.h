@@ -184,6 +184,17 @@ pfmm_status pfmm_plan_read(pfmm_plan_t plan, int buffer, int level, void* dst);
  */
 pfmm_status pfmm_plan_stage_times(pfmm_plan_t plan, double* ms, int* launches);
 
+/*
+ * Per-level split of a stage with one launch per tree level (PFMM_STAGE_M2M,
+ * PFMM_STAGE_M2L or PFMM_STAGE_L2L; Eqs. 5-7): ms[l] for l = 0..L (host
+ * array of L + 1 doubles; entries of levels without a launch are 0), averaged
+ * over the same profiled solves as pfmm_plan_stage_times.  The M2L entry of
+ * a level covers its whole interaction-zone convolution, operand splitting and
+ * group reduction included.  PFMM_ERR_INVALID_ARG for another stage or if no
+ * profiled solve has run.
+ */
+pfmm_status pfmm_plan_level_times(pfmm_plan_t plan, int stage, double* ms);
+
 /* Query plan geometry: leaf width s and the number of table entries
  * per tree level ((8p-1)^3) into *s and *table_entries (either may be NULL). */
 pfmm_status pfmm_plan_info(pfmm_plan_t plan, int* s, int64_t* table_entries);

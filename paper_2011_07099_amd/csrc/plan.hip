@@ -510,10 +510,11 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   const int slot = pl->nprof % kSlots;
   hipEvent_t* ev = pl->ev.data() + slot * kMaxEvents;
   int* tag = pl->ev_tag.data() + slot * kMaxEvents;
-  // record the end of a stage's launch (profiling only)
-  auto mark = [&](int stage) -> hipError_t {
+  // record the end of a stage's launch (profiling only); the tag holds the
+  // stage and the tree level of per-level stages
+  auto mark = [&](int stage, int level = 0) -> hipError_t {
     if (!pl->profile || nev + 1 >= kMaxEvents) return hipSuccess;
-    tag[nev] = stage;
+    tag[nev] = stage | (level << 8);
     return hipEventRecord(ev[++nev], st);
   };
   if (pl->profile) {
@@ -572,7 +573,7 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   if (e != hipSuccess) return hip_fail(e, "P2M");
   for (int l = L - 1; l >= 2; --l) {
     e = launch_m2m(pl->M[l + 1], is64(l + 1), pl->M[l], is64(l), T, 1 << l, p, st);
-    if (e == hipSuccess) e = mark(PFMM_STAGE_M2M);
+    if (e == hipSuccess) e = mark(PFMM_STAGE_M2M, l);
     if (e != hipSuccess) return hip_fail(e, "M2M");
   }
 
@@ -591,11 +592,11 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   a.Y = pl->P[2];
   a.accumulate = 0;
   e = m2l(a, 2);
-  if (e == hipSuccess) e = mark(PFMM_STAGE_M2L);
+  if (e == hipSuccess) e = mark(PFMM_STAGE_M2L, 2);
   if (e != hipSuccess) return hip_fail(e, "M2L level 2");
   for (int l = 3; l <= L; ++l) {
     e = launch_l2l(pl->P[l - 1], is64(l - 1), pl->P[l], is64(l), T, 1 << (l - 1), p, st);
-    if (e == hipSuccess) e = mark(PFMM_STAGE_L2L);
+    if (e == hipSuccess) e = mark(PFMM_STAGE_L2L, l);
     if (e != hipSuccess) return hip_fail(e, "L2L");
     a.n = 1 << l;
     a.m = 2;
@@ -607,7 +608,7 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     a.Y = pl->P[l];
     a.accumulate = 1;
     e = m2l(a, l);
-    if (e == hipSuccess) e = mark(PFMM_STAGE_M2L);
+    if (e == hipSuccess) e = mark(PFMM_STAGE_M2L, l);
     if (e != hipSuccess) return hip_fail(e, "M2L");
   }
 
@@ -720,8 +721,35 @@ pfmm_status pfmm_plan_stage_times(pfmm_plan_t pl, double* ms, int* launches) {
       float t = 0.f;
       e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
       if (e != hipSuccess) return hip_fail(e, "stage times");
-      ms[tag[k]] += t / nsol;
-      if (launches && j == 0) launches[tag[k]] += 1;
+      ms[tag[k] & 255] += t / nsol;
+      if (launches && j == 0) launches[tag[k] & 255] += 1;
+    }
+  }
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_plan_level_times(pfmm_plan_t pl, int stage, double* ms) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!ms) return fail(PFMM_ERR_INVALID_ARG, "ms is NULL");
+  if (stage != PFMM_STAGE_M2M && stage != PFMM_STAGE_M2L && stage != PFMM_STAGE_L2L)
+    return fail(PFMM_ERR_INVALID_ARG, "stage has no per-level launches");
+  if (pl->nprof == 0) return fail(PFMM_ERR_INVALID_ARG, "no profiled solve");
+  for (int l = 0; l <= pl->L; ++l) ms[l] = 0.0;
+  const int nsol = pl->nprof < kSlots ? pl->nprof : kSlots;
+  for (int j = 0; j < nsol; ++j) {
+    const int slot = (pl->nprof - 1 - j) % kSlots;
+    hipEvent_t* ev = pl->ev.data() + slot * kMaxEvents;
+    const int* tag = pl->ev_tag.data() + slot * kMaxEvents;
+    hipError_t e = hipEventSynchronize(ev[pl->ev_used[slot]]);
+    if (e != hipSuccess) return hip_fail(e, "level times");
+    for (int k = 0; k < pl->ev_used[slot]; ++k) {
+      if ((tag[k] & 255) != stage) continue;
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+      if (e != hipSuccess) return hip_fail(e, "level times");
+      const int l = tag[k] >> 8;
+      if (l >= 0 && l <= pl->L) ms[l] += t / nsol;
     }
   }
   return PFMM_OK;

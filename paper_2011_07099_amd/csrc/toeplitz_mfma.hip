@@ -378,7 +378,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int kW64 = 15 * 15 * 15;
 
-__global__ __launch_bounds__(256) void k_toep8_f64(ToepF64Args a) {
+__global__ __launch_bounds__(256, 2) void k_toep8_f64(ToepF64Args a) {
   __shared__ double Wd[2][kW64];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int l16 = l & 15, kq = l >> 4;  // row / column within a tile, k lane group

@@ -20,7 +20,7 @@ BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
 
 # every symbol include/pfmm.h declares
 EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_plan_read",
-           "pfmm_plan_stage_times", "pfmm_plan_info", "pfmm_plan_destroy",
+           "pfmm_plan_stage_times", "pfmm_plan_level_times", "pfmm_plan_info", "pfmm_plan_destroy",
            "pfmm_batch_create", "pfmm_batch_solve", "pfmm_batch_info", "pfmm_batch_destroy",
            "pfmm_plan_direct", "pfmm_learned_set", "pfmm_learned_train_begin",
            "pfmm_learned_accumulate", "pfmm_learned_loss", "pfmm_learned_step", "pfmm_learned_get",
@@ -51,6 +51,7 @@ def load():
     lib.pfmm_plan_read.argtypes = [vp, i32, i32, vp]
     lib.pfmm_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(i32)]
+    lib.pfmm_plan_level_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     lib.pfmm_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
     lib.pfmm_plan_destroy.argtypes = [vp]
     lib.pfmm_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -145,6 +146,13 @@ class Plan:
         n = (ctypes.c_int * len(STAGES))()
         _check(load().pfmm_plan_stage_times(self._h, ms, n))
         return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+    def level_times(self, stage="m2l"):
+        """{level: ms} of a per-level stage ("m2m", "m2l" or "l2l"), averaged
+        over the recent profiled solves (synchronises)."""
+        ms = (ctypes.c_double * (self.L + 1))()
+        _check(load().pfmm_plan_level_times(self._h, STAGES.index(stage), ms))
+        return {l: ms[l] for l in range(self.L + 1) if ms[l] > 0.0}
 
     def solve(self, rho, phi, accel=None):
         import torch

@@ -166,6 +166,32 @@ def test_repeated_solves_are_identical():
     assert all(torch.equal(outs[0], o) for o in outs[1:])
 
 
+def test_profiled_stage_and_level_times_are_consistent():
+    """Per-level M2L / M2M / L2L times add up to the stage totals; profiling
+    changes nothing in the result."""
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan, PfmmError
+    N, L = 64, 3
+    rho = torch.from_numpy(_white(N, 12).astype(np.float32)).cuda()
+    with Plan(N, L, 8, "S1", precision="bf16x3") as pl:
+        ref = torch.empty_like(rho)
+        pl.solve(rho, ref)
+        pl.set_profile(True)
+        phi = torch.empty_like(rho)
+        for _ in range(2):
+            pl.solve(rho, phi)
+        st = pl.stage_times()
+        m2l, m2m, l2l = pl.level_times("m2l"), pl.level_times("m2m"), pl.level_times("l2l")
+        with pytest.raises(PfmmError):
+            pl.level_times("near")
+    assert torch.equal(ref, phi)
+    assert sorted(m2l) == [2, 3] and sorted(m2m) == [2] and sorted(l2l) == [3]
+    assert st["m2l"][1] == 2 and st["near"][1] == 1
+    for name, lv in (("m2l", m2l), ("m2m", m2m), ("l2l", l2l)):
+        assert abs(sum(lv.values()) - st[name][0]) <= 1e-6 + 1e-6 * st[name][0]
+        assert all(v > 0 for v in lv.values())
+
+
 # ---------------------------------------------------------------------------
 # split precision (3 x BF16 on the matrix cores, 8^3 blocks)
 # ---------------------------------------------------------------------------
