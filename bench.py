@@ -40,7 +40,8 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 # by precision and the SHA-1 prefix of the kernel source they were taken on; a
 # changed source reports null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md
 TRAFFIC = {
-    ("bf16x3", "ffb38ac75e46"): (7169124 * 2.0 + 65536 * 1.0) * 1024,
+    ("bf16x3", "cf196215365a"): (7175845 * 2.0 + 65536 * 1.0) * 1024,
+    ("fp32", "b9bf58f895ec"): (10843808 * 2.0 + 111903 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": "toeplitz_mfma.hip", "fp32": "toeplitz.hip"}
 
