@@ -37,20 +37,20 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 
 # HBM bytes per launch of the near-zone kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB), scaled by a plain 1 GiB copy (read x2.0, write x1.0), keyed
-# by precision and the SHA-1 prefix of the kernel source they were taken on; a
-# changed source reports null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md
+# by precision and the SHA-1 prefix of the sources they were taken on (the
+# kernel and plan.hip, which sets the offset order); a changed source reports
+# null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md
 TRAFFIC = {
-    ("bf16x3", "cf196215365a"): (7175845 * 2.0 + 65536 * 1.0) * 1024,
-    ("fp32", "b9bf58f895ec"): (10843808 * 2.0 + 111903 * 1.0) * 1024,
 }
-KERNEL_SRC = {"bf16x3": "toeplitz_mfma.hip", "fp32": "toeplitz.hip"}
+KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
 
 
 def traffic_bytes(precision):
     import hashlib
-    path = os.path.join(ROOT, "paper_2011_07099_amd", "csrc", KERNEL_SRC[precision])
-    h = hashlib.sha1(open(path, "rb").read()).hexdigest()[:12]
-    return TRAFFIC.get((precision, h))
+    h = hashlib.sha1()
+    for name in KERNEL_SRC[precision]:
+        h.update(open(os.path.join(ROOT, "paper_2011_07099_amd", "csrc", name), "rb").read())
+    return TRAFFIC.get((precision, h.hexdigest()[:12]))
 
 
 def algorithmic_flops(N, L, p):

@@ -18,6 +18,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -218,6 +219,46 @@ int f64_groups(int n, int m, int noff) {
   return g < noff ? g : noff;
 }
 
+// Order one class's offsets for cache reuse and append them packed.  The
+// targets of a class lie on a lattice of step m (here 2 for the zones that
+// are split into classes), so the sources of offsets d and d + 2e overlap in
+// all but one layer of a workgroup's tile.  Offsets are grouped by parity and
+// each group is walked as a serpentine (boustrophedon) path, so consecutive
+// offsets differ by one lattice step and share most of their sources while
+// those are still in L2.  The order changes rounding only.
+void append_in_reuse_order(std::vector<std::array<int, 3>> ds, std::vector<int>& out) {
+  auto rank = [](std::vector<int> v, int x) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    return (int)(std::lower_bound(v.begin(), v.end(), x) - v.begin());
+  };
+  for (int par = 0; par < 8; ++par) {
+    std::vector<std::array<int, 3>> g;
+    for (const auto& d : ds)
+      if (((d[0] & 1) << 2 | (d[1] & 1) << 1 | (d[2] & 1)) == par) g.push_back(d);
+    std::vector<int> xs, ys, zs;
+    for (const auto& d : g) {
+      xs.push_back(d[0]);
+      ys.push_back(d[1]);
+      zs.push_back(d[2]);
+    }
+    const int ny = (int)std::set<int>(ys.begin(), ys.end()).size();
+    auto key = [&](const std::array<int, 3>& d) {
+      const int ix = rank(xs, d[0]);
+      const int iy0 = rank(ys, d[1]);
+      const int iy = (ix & 1) ? ny - 1 - iy0 : iy0;
+      const int iz0 = rank(zs, d[2]);
+      const int iz = ((ix * ny + iy) & 1) ? -iz0 : iz0;
+      return std::array<int, 3>{ix, iy, iz};
+    };
+    std::stable_sort(g.begin(), g.end(),
+                     [&](const std::array<int, 3>& a, const std::array<int, 3>& b) {
+                       return key(a) < key(b);
+                     });
+    for (const auto& d : g) out.push_back(pack_offset(d[0], d[1], d[2]));
+  }
+}
+
 int m2l_groups(int l) {
   const int tiles = 1 << (3 * (l - 2));
   int g = (512 + tiles - 1) / tiles;
@@ -350,7 +391,7 @@ pfmm_status build(pfmm_plan_s* pl) {
     }
   }
 
-  // zones (Sec. 2, Fig. 2)
+  // zones (Sec. 2, Fig. 2); the offsets of a class are listed in reuse order
   std::vector<int> l2, iz, nz;
   for (int dx = -2; dx <= 1; ++dx)
     for (int dy = -2; dy <= 1; ++dy)
@@ -358,20 +399,24 @@ pfmm_status build(pfmm_plan_s* pl) {
         if (dx == -2 || dy == -2 || dz == -2) l2.push_back(pack_offset(dx, dy, dz));
   for (int c = 0; c < 8; ++c) {
     const int cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
+    std::vector<std::array<int, 3>> cls;
     for (int dx = -2 - cx; dx <= 3 - cx; ++dx)
       for (int dy = -2 - cy; dy <= 3 - cy; ++dy)
         for (int dz = -2 - cz; dz <= 3 - cz; ++dz)
           if (std::abs(dx) > 1 || std::abs(dy) > 1 || std::abs(dz) > 1)
-            iz.push_back(pack_offset(dx, dy, dz));
+            cls.push_back({dx, dy, dz});
+    append_in_reuse_order(cls, iz);
   }
   pl->qn = s <= 8 ? s : 8;
   pl->mn = s / pl->qn;
   const int mn = pl->mn;
   for (int c = 0; c < mn * mn * mn; ++c) {
     const int cx = c / (mn * mn), cy = (c / mn) % mn, cz = c % mn;
+    std::vector<std::array<int, 3>> cls;
     for (int dx = -mn - cx; dx <= 2 * mn - 1 - cx; ++dx)
       for (int dy = -mn - cy; dy <= 2 * mn - 1 - cy; ++dy)
-        for (int dz = -mn - cz; dz <= 2 * mn - 1 - cz; ++dz) nz.push_back(pack_offset(dx, dy, dz));
+        for (int dz = -mn - cz; dz <= 2 * mn - 1 - cz; ++dz) cls.push_back({dx, dy, dz});
+    append_in_reuse_order(cls, nz);
   }
   if (l2.size() != 37 || iz.size() != 8 * 189 || nz.size() != (size_t)cube(3 * mn) * cube(mn))
     return fail(PFMM_ERR_HIP, "internal: zone sizes");
