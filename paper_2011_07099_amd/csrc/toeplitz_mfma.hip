@@ -36,6 +36,7 @@ constexpr int kThreads = 256;
 constexpr int kWinPairs = 15 * 15 * 14;   // packed pairs per window term
 constexpr int kWinPart = 3152;            // dwords per window term (padded to 16 B)
 constexpr int kTN = 64;                   // targets per workgroup
+constexpr int kMaxOffs = 216;             // offsets per class (the near zone at m = 2)
 
 __device__ inline uint16_t bf16_bits(float x) {
   __bf16 b = (__bf16)x;
@@ -144,17 +145,32 @@ __device__ inline Tile tile_target(int tile, int nt4, int cls, int m, int local)
   return t;
 }
 
+// Staged source rows hold KCH bf16 values as 16-byte slots, slot j of row r
+// holding segment j ^ swz(r): 16 consecutive rows (the lanes of one B
+// fragment read) then fall in distinct banks without row padding.
+template <int NT>
+__device__ inline int swz(int row) {
+  return NT == 2 ? (row & 15) : ((row >> 1) & 7);
+}
+
 template <int NT>
 __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
   constexpr int KCH = NT == 2 ? 128 : 64;        // source points per staged chunk
-  constexpr int NCH = 512 / KCH;                 // chunks per offset
-  constexpr int ROW = KCH + 8;                   // staged row, bf16 (padding vs bank conflicts)
-  constexpr int SEGS = KCH / 8;                  // 16-byte segments per row
-  constexpr int BV = NT * kTN * SEGS / kThreads; // 16-byte loads per thread per chunk
-  constexpr int TPR = kTN * SEGS / kThreads;     // distinct targets per thread
-  constexpr int WV = (NT * kWinPart / 4 + kThreads - 1) / kThreads;
-  __shared__ __attribute__((aligned(16))) uint32_t Aw[2][NT * kWinPart];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][NT][kTN][ROW];
+  constexpr int NCH = 512 / KCH;                 // chunks per offset (even)
+  constexpr int SLOTS = KCH / 8;                 // 16-byte slots per staged row
+  constexpr int RPI = 64 / SLOTS;                // rows per wave copy instruction
+  constexpr int IPT = 16 / RPI;                  // copy instructions per term and wave
+  constexpr int AW = (NT * kWinPart + 255) / 256 * 256;  // staged window dwords
+  constexpr int AI = AW / 256;                   // 1 KB window pieces
+  // Operands go from global memory straight into LDS (global_load_lds), so
+  // the copies of the next chunk are in flight while this chunk's MFMAs run
+  // and hold no registers.  Each buffer is its own LDS object: the copies
+  // into one never alias the reads from the other.
+  __shared__ __attribute__((aligned(16))) uint32_t Aw0[AW];
+  __shared__ __attribute__((aligned(16))) uint32_t Aw1[AW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs0[NT][kTN][KCH];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs1[NT][kTN][KCH];
+  __shared__ int Os[kMaxOffs];  // this class's offsets (read by every copy)
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, h = l >> 5, l32 = l & 31;
@@ -172,59 +188,44 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
 
   const int g = blockIdx.y;
   const int ob = (a.noff * g) / a.groups, oe = (a.noff * (g + 1)) / a.groups;
-  const int* offs = a.offs + (size_t)cls * a.noff;
   const int nmask = a.n - 1;
   const size_t nterm = (size_t)a.n * a.n * a.n * 512;  // stride between source terms
+  for (int i = tid; i < a.noff; i += kThreads) Os[i] = a.offs[(size_t)cls * a.noff + i];
+  __syncthreads();
 
-  // staging map: load r of a chunk covers term r / (BV/NT), target
-  // tl = (tid / SEGS) + (kThreads / SEGS) * (r % TPR), segment tid % SEGS
-  const int seg = tid % SEGS;
-  Tile st[TPR];
+  // copy map: instruction i of a term and wave covers rows 16w + RPI i ..
+  // + RPI - 1; lane l takes row 16w + RPI i + l / SLOTS, slot l % SLOTS
+  Tile st[IPT];
+  int seg[IPT];
 #pragma unroll
-  for (int r = 0; r < TPR; ++r)
-    st[r] = tile_target(tile, nt4, cls, m, tid / SEGS + (kThreads / SEGS) * r);
+  for (int i = 0; i < IPT; ++i) {
+    const int row = 16 * w + RPI * i + l / SLOTS;
+    st[i] = tile_target(tile, nt4, cls, m, row);
+    seg[i] = (l % SLOTS) ^ swz<NT>(row);
+  }
 
-  u32x4 ra[WV];
-  u32x4 rb[BV];
-  auto load_A = [&](int k) {
+  typedef const void __attribute__((address_space(1)))* gptr;
+  typedef void __attribute__((address_space(3)))* lptr;
+  auto copy_A = [&](uint32_t* dst, int k) {
     int dx, dy, dz;
-    unpack_offset(offs[k], dx, dy, dz);
+    unpack_offset(Os[k], dx, dy, dz);
     const int slot = ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
-    const u32x4* src = reinterpret_cast<const u32x4*>(a.win + (size_t)slot * NT * kWinPart);
-#pragma unroll
-    for (int r = 0; r < WV; ++r) {
-      const int i = tid + kThreads * r;
-      if (i < NT * kWinPart / 4) ra[r] = src[i];
-    }
+    const uint32_t* src = a.win + (size_t)slot * NT * kWinPart;
+    for (int r = w; r < AI; r += 4)
+      __builtin_amdgcn_global_load_lds((gptr)(src + 256 * r + 4 * l), (lptr)(dst + 256 * r), 16, 0,
+                                       0);
   };
-  auto store_A = [&](int buf) {
-    u32x4* dst = reinterpret_cast<u32x4*>(&Aw[buf][0]);
-#pragma unroll
-    for (int r = 0; r < WV; ++r) {
-      const int i = tid + kThreads * r;
-      if (i < NT * kWinPart / 4) dst[i] = ra[r];
-    }
-  };
-  auto load_B = [&](int k, int c) {
+  auto copy_B = [&](uint16_t (*dst)[kTN][KCH], int k, int c) {
     int dx, dy, dz;
-    unpack_offset(offs[k], dx, dy, dz);
-    size_t node[TPR];
+    unpack_offset(Os[k], dx, dy, dz);
 #pragma unroll
-    for (int r = 0; r < TPR; ++r) {
-      const int ux = (st[r].tx + dx) & nmask, uy = (st[r].ty + dy) & nmask, uz = (st[r].tz + dz) & nmask;
-      node[r] = ((size_t)ux * a.n + uy) * a.n + uz;
-    }
+    for (int i = 0; i < IPT; ++i) {
+      const int ux = (st[i].tx + dx) & nmask, uy = (st[i].ty + dy) & nmask, uz = (st[i].tz + dz) & nmask;
+      const uint16_t* src = a.X + (((size_t)ux * a.n + uy) * a.n + uz) * 512 + KCH * c + 8 * seg[i];
 #pragma unroll
-    for (int r = 0; r < BV; ++r) {
-      const int term = r / TPR;
-      rb[r] = *reinterpret_cast<const u32x4*>(a.X + term * nterm + node[r % TPR] * 512 + KCH * c + 8 * seg);
-    }
-  };
-  auto store_B = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < BV; ++r) {
-      const int tl = tid / SEGS + (kThreads / SEGS) * (r % TPR);
-      *reinterpret_cast<u32x4*>(&Bs[buf][r / TPR][tl][8 * seg]) = rb[r];
+      for (int q = 0; q < NT; ++q)
+        __builtin_amdgcn_global_load_lds((gptr)(src + q * nterm), (lptr)&dst[q][16 * w + RPI * i][0],
+                                         16, 0, 0);
     }
   };
 
@@ -241,8 +242,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
   // with ax = 2w + i/2, ay = 4(i%2) + l32/8, az = l32%8, bx = s/4,
   // by = 2(s%4) + h.  The lane part is one base; the rest is a constant.
   const int abase = (210 * (2 * w + 7) + 14 * ((l32 >> 3) + 7 - h) + 7 - (l32 & 7));
-  // B rows: target 32j + l32, k offset 16 sl + 8h within the staged chunk
-  const int bbase = l32 * ROW + 8 * h;
+  // B rows: target 32j + l32; k offset 16 sl + 8h is segment 2 sl + h
+  const int bswz = h ^ swz<NT>(l32);
 
   struct Frags {
     bf16x8 a[4][NT];
@@ -263,68 +264,68 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
         f.a[i][q] = __builtin_bit_cast(bf16x8, u);
       }
   };
-  auto load_b = [&](Frags& f, const uint16_t* Bb, int sl) {
+  auto load_b = [&](Frags& f, uint16_t (*Bb)[kTN][KCH], int sl) {
+    const int slot = (2 * sl) ^ bswz;
 #pragma unroll
     for (int q = 0; q < NT; ++q)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        f.b[q][j] = *reinterpret_cast<const bf16x8*>(Bb + q * kTN * ROW + 32 * j * ROW + bbase +
-                                                     16 * sl);
+        f.b[q][j] = *reinterpret_cast<const bf16x8*>(&Bb[q][32 * j + l32][8 * slot]);
   };
+  // products of terms (a term, b term), smallest first: the last three for
+  // NT = 2, all six for NT = 3; an accumulator is revisited only after all 8
+  // tiles, so consecutive MFMAs are independent
+  constexpr int PA[6] = {2, 0, 1, 1, 0, 0};
+  constexpr int PB[6] = {0, 2, 1, 0, 1, 0};
   auto mma = [&](const Frags& f) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int pr = (NT == 3 ? 0 : 3); pr < 6; ++pr)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        // smallest products first
-        if constexpr (NT == 3) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][2], f.b[0][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], f.b[2][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], f.b[1][j], acc[i][j], 0, 0, 0);
-        }
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][1], f.b[0][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], f.b[1][j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][0], f.b[0][j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[i][PA[pr]], f.b[PB[pr]][j],
+                                                              acc[i][j], 0, 0, 0);
+  };
+
+  // one offset: NCH chunks; copies for the next chunk (and at the last chunk
+  // the next offset's window) are issued before this chunk's MFMAs
+  auto offset_step = [&](int k, const uint32_t* Ak, uint32_t* Anext) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const bool has_next = !(k == oe - 1 && c == NCH - 1);
+      if (has_next) {
+        if (c < NCH - 1) copy_B((c & 1) ? Bs0 : Bs1, k, c + 1);
+        else copy_B(Bs0, k + 1, 0);  // NCH is even: chunk 0 uses Bs0
+        if (c == NCH - 1) copy_A(Anext, k + 1);
       }
+      // compiler-only fence (no instruction): memory operations stay on
+      // their side, so the copies are issued here and not sunk to the end
+      asm volatile("" ::: "memory");
+      uint16_t (*Bb)[kTN][KCH] = (c & 1) ? Bs1 : Bs0;
+      constexpr int KS = KCH / 16;  // k-steps per chunk
+      Frags f[2];
+      load_a(f[0], Ak, KS * c);
+      load_b(f[0], Bb, 0);
+#pragma unroll
+      for (int sl = 0; sl < KS; ++sl) {
+        if (sl + 1 < KS) {
+          load_a(f[(sl + 1) & 1], Ak, KS * c + sl + 1);
+          load_b(f[(sl + 1) & 1], Bb, sl + 1);
+        }
+        mma(f[sl & 1]);
+      }
+      __syncthreads();  // waits for this wave's copies, then for the others
+    }
   };
 
   if (ob < oe) {
-    load_A(ob);
-    load_B(ob, 0);
-    store_A(0);
-    store_B(0);
+    copy_A(Aw0, ob);
+    copy_B(Bs0, ob, 0);
     __syncthreads();
-    for (int k = ob; k < oe; ++k) {
-      const uint32_t* Ak = &Aw[(k - ob) & 1][0];
-      const bool last_off = (k == oe - 1);
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        // prefetch the next chunk (and at the last chunk the next window)
-        const bool has_next = !(last_off && c == NCH - 1);
-        if (has_next) {
-          if (c < NCH - 1) load_B(k, c + 1);
-          else load_B(k + 1, 0);
-          if (c == NCH - 1) load_A(k + 1);
-        }
-        const uint16_t* Bb = &Bs[c & 1][0][0][0];  // NCH is even: parity of c
-        constexpr int KS = KCH / 16;               // k-steps per chunk
-        Frags f[2];
-        load_a(f[0], Ak, KS * c);
-        load_b(f[0], Bb, 0);
-#pragma unroll
-        for (int sl = 0; sl < KS; ++sl) {
-          if (sl + 1 < KS) {
-            load_a(f[(sl + 1) & 1], Ak, KS * c + sl + 1);
-            load_b(f[(sl + 1) & 1], Bb, sl + 1);
-          }
-          mma(f[sl & 1]);
-        }
-        if (has_next) {
-          store_B((c + 1) & 1);
-          if (c == NCH - 1) store_A((k + 1 - ob) & 1);
-        }
-        __syncthreads();
-      }
+    for (int k = ob; k < oe; k += 2) {  // window buffers alternate by offset
+      offset_step(k, Aw0, Aw1);
+      if (k + 1 < oe) offset_step(k + 1, Aw1, Aw0);
     }
   }
 
@@ -516,7 +517,8 @@ hipError_t make_windows(const double* tab64, int C, int nt, uint32_t* win, hipSt
   return hipGetLastError();
 }
 
-size_t window_dwords(int nt) { return (size_t)343 * nt * kWinPart; }
+// (padded by 1 KB: the last window's staging copies whole 1 KB pieces)
+size_t window_dwords(int nt) { return (size_t)343 * nt * kWinPart + 256; }
 
 hipError_t split_blocks(const float* X, uint16_t* out, int nt, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_split_blocks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, out,
@@ -533,7 +535,8 @@ hipError_t split_mesh(const float* rho, float scale, int N, int nt, uint16_t* ou
 }
 
 hipError_t launch_toep8_split(const ToepMfmaArgs& a, int nt, hipStream_t st) {
-  if (!toep8_supported(a.n, a.m) || a.groups < 1 || nt < 2 || nt > 3) return hipErrorInvalidValue;
+  if (!toep8_supported(a.n, a.m) || a.groups < 1 || nt < 2 || nt > 3 || a.noff > kMaxOffs)
+    return hipErrorInvalidValue;
   const int nt4 = a.n / a.m / 4;
   const int nblk = nt4 * nt4 * nt4 * a.m * a.m * a.m;
   if (nt == 2)
