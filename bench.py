@@ -112,7 +112,9 @@ def copy_reference():
 def batch_bench(args):
     """Batch of 128 independent fields (N in {32, 64, 128}, p in {4, 6, 8},
     lognormal with alpha = 2, sigma_delta ~ U(0.5, 2), seed 1000 + i, L = 3,
-    G_S1) solved by one graph launch; fields/s over K launches."""
+    G_S1) solved by one graph launch; fields/s over K launches.  Plans are in
+    the --precision given (split: near zones with 8^3-cell sub-blocks on the
+    BF16 matrix cores)."""
     import torch
     from paper_2011_07099_amd import fields
     from paper_2011_07099_amd.pfmm import Batch, Plan
@@ -122,7 +124,7 @@ def batch_bench(args):
     for sp in specs:
         rho = fields.lognormal(sp["N"], sp["alpha"], sp["sigma_delta"], seed=sp["seed"])
         host.append(rho.astype(np.float32))
-        plans.append(Plan(sp["N"], 3, sp["p"], GREEN))
+        plans.append(Plan(sp["N"], 3, sp["p"], GREEN, precision=args.precision))
         rhos.append(torch.from_numpy(host[-1]).cuda())
         phis.append(torch.empty_like(rhos[-1]))
     torch.cuda.synchronize()
@@ -148,7 +150,7 @@ def batch_bench(args):
         "metric": "fields/s, batch of 128 mixed periodic-FMM fields in one graph launch",
         "value": len(specs) / (ms * 1e-3), "unit": "fields/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": "128 lognormal fields, N in {32,64,128}, p in {4,6,8}, "
                                "sigma_delta~U(0.5,2), alpha=2, L=3, G_S1",

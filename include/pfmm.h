@@ -207,21 +207,27 @@ pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
  * Batches of independent fields (fields of different N and p in one solve).
  *
  * pfmm_batch_create binds n plans to their density and potential device
- * arrays (density[i], potential[i] as for pfmm_solve on plans[i]), builds one
- * pool of independent contraction work items for the whole batch (every
- * interaction-zone level and near zone of every field: tiles of targets of
- * one class, largest first), picks the tile width of the persistent kernel
- * that drains the pool by timing each candidate on these inputs (or reads it
- * from the JSON file named by the environment variable PFMM_TUNE_CACHE, which
- * it then updates), and captures the whole batch solve -- upward passes, the
- * single persistent launch, downward passes -- into a HIP graph on the stream
- * of plans[0].  It allocates, runs solves and synchronises; it is plan time.
+ * arrays (density[i], potential[i] as for pfmm_solve on plans[i]) and builds
+ * work lists of independent contraction items for the whole batch (every
+ * interaction-zone level and near zone of every field, split into workgroup
+ * tiles of targets of one class):
+ *   - the near zone of a plan in PFMM_PREC_BF16X3 with 8^3-cell sub-blocks
+ *     (leaf width 8 or 16) runs on the BF16 matrix cores, 2-term split, as in
+ *     pfmm_solve;
+ *   - FP64 levels at p = 8 run on the FP64 matrix cores;
+ *   - everything else runs in the portable kernel: FP64 levels in FP64, the
+ *     rest in FP32 with FP64 per-offset running totals.
+ * Each list is drained by one persistent kernel through an atomic counter.
+ * The portable kernel's tile width is picked by timing each candidate on
+ * these inputs (or read from the JSON file named by the environment variable
+ * PFMM_TUNE_CACHE, which it then updates).  The whole batch solve -- upward
+ * passes, the persistent launches, downward passes -- is captured into a HIP
+ * graph on the batch's own stream, ordered with the stream of plans[0].  It
+ * allocates, runs solves and synchronises; it is plan time.
  *
  * Requirements: 1 <= n <= 4096; live plans on one device, p <= 8; the plans
  * are not solved concurrently with the batch (it uses their workspaces).
- * Each plan's FP64 coarse levels (PFMM_OPT_FP64_LEVELS at batch creation) are
- * kept in FP64; every other contraction runs in FP32 with FP64 per-offset
- * running totals, whatever precision the plans are set to.
+ * Precision and FP64 levels are those of each plan at batch creation.
  */
 typedef struct pfmm_batch_s* pfmm_batch_t;
 pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* const* density,
@@ -231,9 +237,10 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
  * not allocate or synchronise.  Potentials are overwritten. */
 pfmm_status pfmm_batch_solve(pfmm_batch_t batch);
 
-/* Work items in the pool, the chosen tile width (targets per thread, 1, 2 or
- * 4) and the timed duration in ms of the persistent launch for each candidate
- * width 1, 2, 4 (negative when not timed; ms may be NULL). */
+/* Work items in all lists, the chosen tile width of the portable kernel
+ * (targets per thread, 1, 2 or 4) and the timed duration in ms of the
+ * contraction launches for each candidate width 1, 2, 4 (negative when not
+ * timed; ms may be NULL). */
 pfmm_status pfmm_batch_info(pfmm_batch_t batch, int* items, int* tile_width, double* ms);
 
 /* Release a batch (not its plans). NULL is accepted and ignored. */

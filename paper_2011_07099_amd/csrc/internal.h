@@ -118,6 +118,18 @@ struct BatchItem {
   int fp64;         // FP64 operands: tile width 1, FP64 sums
 };
 int batch_targets_per_item(int q, int tpt, int fp64);
+
+// Matrix-core items of a batch (toeplitz_mfma.hip): one item = one workgroup
+// tile of one contraction, all offsets; `arg` indexes a device array of
+// ToepMfmaArgs (kind 2: split near zone, 3: split interaction zone) or
+// ToepF64Args (kind 64).  Groups and partial sums are not used (groups = 1).
+struct MmaItem {
+  int arg, tile;
+};
+int toep8_split_tiles(int n, int m);  // tiles (workgroups) of one split launch
+int batch_mma_grid(int kind);         // resident workgroups of a persistent kind
+hipError_t launch_batch_mma(int kind, const void* args, const MmaItem* items, int nitems,
+                            unsigned* counter, int grid, hipStream_t st);
 int batch_resident_grid(int tpt);
 hipError_t launch_batch_toeplitz(const BatchItem* items, int nitems, unsigned* counter, int tpt,
                                  int grid, hipStream_t st);

@@ -835,9 +835,16 @@ struct pfmm_batch_s {
   hipStream_t caller = nullptr;  // stream of plans[0]; solves are ordered with it
   hipStream_t stream = nullptr;  // the batch's own stream (captured into the graph)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  BatchItem* items = nullptr;  // device work list
-  unsigned* counter = nullptr;
+  BatchItem* items = nullptr;  // device work list (portable kernel)
+  unsigned* counter = nullptr;  // [0] portable, [1] split, [2] FP64 matrix-core list
   int nitems = 0, tpt = 2, grid = 0;
+  // matrix-core work lists: split near zones (plans in split precision) and
+  // the FP64 levels at p = 8
+  ToepMfmaArgs* sargs = nullptr;
+  ToepF64Args* fargs = nullptr;
+  MmaItem* sitems = nullptr;
+  MmaItem* fitems = nullptr;
+  int nsplit = 0, nf64 = 0, sgrid = 0, fgrid = 0;
   double tuned_ms[3] = {-1.0, -1.0, -1.0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -858,13 +865,23 @@ void brelease(pfmm_batch_s* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->items) (void)hipFree(b->items);
   if (b->counter) (void)hipFree(b->counter);
+  if (b->sargs) (void)hipFree(b->sargs);
+  if (b->fargs) (void)hipFree(b->fargs);
+  if (b->sitems) (void)hipFree(b->sitems);
+  if (b->fitems) (void)hipFree(b->fitems);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
 
-// Work items of every contraction of every field, largest first.
+// Contractions that go to the matrix-core persistent kernels: the near zone
+// of a plan in split precision with 8^3-cell sub-blocks, and FP64 levels at
+// p = 8 (the same kernels as a single solve, so the same results).
+bool batch_split_near(const pfmm_plan_s* pl) { return pl->prec == PFMM_PREC_BF16X3 && pl->nwin; }
+bool batch_f64_level(const pfmm_plan_s* pl, int l) { return level64(pl, l) && pl->p == 8; }
+
+// Work items of every other contraction of every field, largest first.
 std::vector<BatchItem> batch_items(const pfmm_batch_s* b, int tpt) {
   struct Keyed {
     double cost;
@@ -888,6 +905,7 @@ std::vector<BatchItem> batch_items(const pfmm_batch_s* b, int tpt) {
     const pfmm_plan_s* pl = b->plans[f];
     const int p = pl->p;
     for (int l = 2; l <= pl->L; ++l) {
+      if (batch_f64_level(pl, l)) continue;
       BatchItem it{};
       it.fp64 = level64(pl, l);
       it.tab = it.fp64 ? (const void*)pl->tab64[l] : (const void*)pl->tab32[l];
@@ -916,7 +934,7 @@ std::vector<BatchItem> batch_items(const pfmm_batch_s* b, int tpt) {
     nb.noff = (int)cube(3 * pl->mn);
     nb.grid = 1;
     nb.xscale = (float)(1.0 / ((double)pl->N * pl->N * pl->N));
-    add(nb);
+    if (!batch_split_near(pl)) add(nb);
   }
   std::stable_sort(all.begin(), all.end(),
                    [](const Keyed& a, const Keyed& c) { return a.cost > c.cost; });
@@ -924,6 +942,72 @@ std::vector<BatchItem> batch_items(const pfmm_batch_s* b, int tpt) {
   out.reserve(all.size());
   for (auto& k : all) out.push_back(k.it);
   return out;
+}
+
+// Argument arrays and item lists of the matrix-core kernels (one item per
+// workgroup tile, all offsets; FP64 items of the larger zone first).
+hipError_t batch_mma_upload(pfmm_batch_s* b) {
+  std::vector<ToepMfmaArgs> sa;
+  std::vector<ToepF64Args> fa;
+  std::vector<MmaItem> si, fi;
+  for (size_t f = 0; f < b->plans.size(); ++f) {
+    const pfmm_plan_s* pl = b->plans[f];
+    for (int l = 3; l >= 2; --l) {
+      if (l > pl->L || !batch_f64_level(pl, l)) continue;
+      ToepF64Args x{};
+      x.n = 1 << l;
+      x.m = l == 2 ? 1 : 2;
+      x.noff = l == 2 ? 37 : 189;
+      x.offs = l == 2 ? pl->offs_l2 : pl->offs_iz;
+      x.tab = pl->tab64[l];
+      x.C = 4 * pl->p - 1;
+      x.X = (const double*)pl->M[l];
+      x.Y = (double*)pl->P[l];
+      x.accumulate = 0;
+      x.groups = 1;
+      x.partial = nullptr;
+      const int arg = (int)fa.size();
+      fa.push_back(x);
+      for (int t = 0; t < toep8_f64_tiles(x.n, x.m); ++t) fi.push_back({arg, t});
+    }
+    if (batch_split_near(pl)) {
+      ToepMfmaArgs y{};
+      y.n = pl->N / pl->qn;
+      y.m = pl->mn;
+      y.noff = (int)cube(3 * pl->mn);
+      y.offs = pl->offs_near;
+      y.win = pl->nwin;
+      y.X = pl->xs;
+      y.Y = b->phi[f];
+      y.grid_out = 1;
+      y.accumulate = 0;
+      y.groups = 1;
+      y.partial = nullptr;
+      const int arg = (int)sa.size();
+      sa.push_back(y);
+      for (int t = 0; t < toep8_split_tiles(y.n, y.m); ++t) si.push_back({arg, t});
+    }
+  }
+  // level-3 items (189 offsets) before level-2 items (37)
+  std::stable_sort(fi.begin(), fi.end(), [&](const MmaItem& a, const MmaItem& c) {
+    return fa[a.arg].noff > fa[c.arg].noff;
+  });
+  hipError_t e = hipSuccess;
+  auto up = [&](auto** dst, const auto& v) {
+    if (e != hipSuccess || v.empty()) return;
+    e = hipMalloc(dst, v.size() * sizeof(v[0]));
+    if (e == hipSuccess)
+      e = hipMemcpy(*dst, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice);
+  };
+  up(&b->sargs, sa);
+  up(&b->fargs, fa);
+  up(&b->sitems, si);
+  up(&b->fitems, fi);
+  b->nsplit = (int)si.size();
+  b->nf64 = (int)fi.size();
+  b->sgrid = batch_mma_grid(2);
+  b->fgrid = batch_mma_grid(64);
+  return e;
 }
 
 hipError_t batch_upload(pfmm_batch_s* b, int tpt) {
@@ -953,10 +1037,17 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
       for (int l = pl->L - 1; l >= 2 && e == hipSuccess; --l)
         e = launch_m2m(pl->M[l + 1], level64(pl, l + 1), pl->M[l], level64(pl, l), T, 1 << l,
                        pl->p, st);
+      if (e == hipSuccess && batch_split_near(pl))
+        e = split_mesh(b->rho[f], (float)(1.0 / ((double)pl->N * pl->N * pl->N)), pl->N,
+                       kNearTerms, pl->xs, st);
     }
   }
   if (e == hipSuccess && (part == 0 || part == 2))
     e = launch_batch_toeplitz(b->items, b->nitems, b->counter, b->tpt, b->grid, st);
+  if (e == hipSuccess && (part == 0 || part == 2))
+    e = launch_batch_mma(2, b->sargs, b->sitems, b->nsplit, b->counter + 1, b->sgrid, st);
+  if (e == hipSuccess && (part == 0 || part == 2))
+    e = launch_batch_mma(64, b->fargs, b->fitems, b->nf64, b->counter + 2, b->fgrid, st);
   if (e == hipSuccess && (part == 0 || part == 3)) {
     for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
       pfmm_plan_s* pl = b->plans[f];
@@ -975,7 +1066,8 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
 std::string batch_signature(const pfmm_batch_s* b) {
   std::string sig;
   for (const pfmm_plan_s* pl : b->plans)
-    sig += std::to_string(pl->N) + "/" + std::to_string(pl->L) + "/" + std::to_string(pl->p) + ";";
+    sig += std::to_string(pl->N) + "/" + std::to_string(pl->L) + "/" + std::to_string(pl->p) + "/" +
+           std::to_string(pl->prec) + ";";
   // hash it to keep the cache file short
   uint64_t h = 1469598103934665603ull;
   for (char c : sig) h = (h ^ (unsigned char)c) * 1099511628211ull;
@@ -1059,10 +1151,11 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
   // inputs written on the caller's stream must be visible to the tuning runs
   if (e == hipSuccess) e = hipStreamSynchronize(b->caller);
-  if (e == hipSuccess) e = hipMalloc(&b->counter, sizeof(unsigned));
+  if (e == hipSuccess) e = hipMalloc(&b->counter, 3 * sizeof(unsigned));
+  if (e == hipSuccess) e = batch_mma_upload(b);
   if (e != hipSuccess) {
     brelease(b);
-    return hip_fail(e, "batch counter");
+    return hip_fail(e, "batch work lists");
   }
   // tile width: cache, else time each candidate on these inputs
   const char* cache = std::getenv("PFMM_TUNE_CACHE");
@@ -1139,7 +1232,7 @@ pfmm_status pfmm_batch_solve(pfmm_batch_t b) {
 pfmm_status pfmm_batch_info(pfmm_batch_t b, int* items, int* tile_width, double* ms) {
   g_err.clear();
   if (!blive(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
-  if (items) *items = b->nitems;
+  if (items) *items = b->nitems + b->nsplit + b->nf64;
   if (tile_width) *tile_width = b->tpt;
   if (ms)
     for (int i = 0; i < 3; ++i) ms[i] = b->tuned_ms[i];

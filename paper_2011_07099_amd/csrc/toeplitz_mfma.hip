@@ -154,23 +154,37 @@ __device__ inline int swz(int row) {
 }
 
 template <int NT>
-__global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
-  constexpr int KCH = NT == 2 ? 128 : 64;        // source points per staged chunk
+struct SplitCfg {
+  static constexpr int KCH = NT == 2 ? 128 : 64;              // source points per staged chunk
+  static constexpr int AW = (NT * kWinPart + 255) / 256 * 256;  // staged window dwords
+};
+
+// LDS of one workgroup of the split kernel.  Operands go from global memory
+// straight into LDS (global_load_lds), so the copies of the next chunk are in
+// flight while this chunk's MFMAs run and hold no registers.  Each buffer is
+// its own LDS object: the copies into one never alias the reads from the
+// other.
+#define PFMM_SPLIT_LDS(NT)                                                             \
+  __shared__ __attribute__((aligned(16))) uint32_t Aw0[SplitCfg<NT>::AW];              \
+  __shared__ __attribute__((aligned(16))) uint32_t Aw1[SplitCfg<NT>::AW];              \
+  __shared__ __attribute__((aligned(16))) uint16_t Bs0[NT][kTN][SplitCfg<NT>::KCH];    \
+  __shared__ __attribute__((aligned(16))) uint16_t Bs1[NT][kTN][SplitCfg<NT>::KCH];    \
+  __shared__ int Os[kMaxOffs]; /* the class's offsets (read by every copy) */
+
+// One workgroup's share of the operator: 512 outputs x 64 targets (tile
+// `lin` = class * tiles + tile) over offset group g.  Ends with a barrier, so
+// the caller may reuse the LDS at once.
+template <int NT>
+__device__ __forceinline__ void split_tile(const ToepMfmaArgs& a, int lin, int g, uint32_t* Aw0,
+                                           uint32_t* Aw1, uint16_t (*Bs0)[kTN][SplitCfg<NT>::KCH],
+                                           uint16_t (*Bs1)[kTN][SplitCfg<NT>::KCH], int* Os) {
+  constexpr int KCH = SplitCfg<NT>::KCH;
   constexpr int NCH = 512 / KCH;                 // chunks per offset (even)
   constexpr int SLOTS = KCH / 8;                 // 16-byte slots per staged row
   constexpr int RPI = 64 / SLOTS;                // rows per wave copy instruction
   constexpr int IPT = 16 / RPI;                  // copy instructions per term and wave
-  constexpr int AW = (NT * kWinPart + 255) / 256 * 256;  // staged window dwords
+  constexpr int AW = SplitCfg<NT>::AW;
   constexpr int AI = AW / 256;                   // 1 KB window pieces
-  // Operands go from global memory straight into LDS (global_load_lds), so
-  // the copies of the next chunk are in flight while this chunk's MFMAs run
-  // and hold no registers.  Each buffer is its own LDS object: the copies
-  // into one never alias the reads from the other.
-  __shared__ __attribute__((aligned(16))) uint32_t Aw0[AW];
-  __shared__ __attribute__((aligned(16))) uint32_t Aw1[AW];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs0[NT][kTN][KCH];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs1[NT][kTN][KCH];
-  __shared__ int Os[kMaxOffs];  // this class's offsets (read by every copy)
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, h = l >> 5, l32 = l & 31;
@@ -178,15 +192,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
   const int nk = a.n / m;                    // class lattice points per axis
   const int nt4 = nk / 4;                    // tiles per axis
   const int tiles_per_class = nt4 * nt4 * nt4;
-  const int nblk = tiles_per_class * m * m * m;
-  // XCD-aware order: consecutive dispatch ids go to different XCDs, so give
-  // each XCD a contiguous run of tiles (spatially close targets share sources)
-  const int b = blockIdx.x;
-  const int per = nblk / 8;
-  const int lin = (nblk % 8 == 0) ? (b % 8) * per + b / 8 : b;
   const int cls = lin / tiles_per_class, tile = lin % tiles_per_class;
 
-  const int g = blockIdx.y;
   const int ob = (a.noff * g) / a.groups, oe = (a.noff * (g + 1)) / a.groups;
   const int nmask = a.n - 1;
   const size_t nterm = (size_t)a.n * a.n * a.n * 512;  // stride between source terms
@@ -365,6 +372,42 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
       }
     }
   }
+  __syncthreads();
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
+  PFMM_SPLIT_LDS(NT)
+  const int m = a.m;
+  const int nt4 = a.n / m / 4;
+  const int nblk = nt4 * nt4 * nt4 * m * m * m;
+  // XCD-aware order: consecutive dispatch ids go to different XCDs, so give
+  // each XCD a contiguous run of tiles (spatially close targets share sources)
+  const int b = blockIdx.x;
+  const int per = nblk / 8;
+  const int lin = (nblk % 8 == 0) ? (b % 8) * per + b / 8 : b;
+  split_tile<NT>(a, lin, blockIdx.y, Aw0, Aw1, Bs0, Bs1, Os);
+}
+
+// Persistent form for batches: workgroups take (field, tile) items from an
+// atomic counter until the list is exhausted (every workgroup leaves through
+// the same uniform test).  Items cover all offsets (one group).
+template <int NT>
+__global__ __launch_bounds__(kThreads, 1) void k_batch_split(const ToepMfmaArgs* __restrict__ args,
+                                                             const MmaItem* __restrict__ items,
+                                                             int nitems, unsigned* __restrict__ counter) {
+  PFMM_SPLIT_LDS(NT)
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int idx = cur;
+    __syncthreads();  // every thread has read `cur` before thread 0 overwrites it
+    if (idx >= nitems) break;
+    const MmaItem it = items[idx];
+    const ToepMfmaArgs a = args[it.arg];
+    split_tile<NT>(a, it.tile, 0, Aw0, Aw1, Bs0, Bs1, Os);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -379,15 +422,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_toep8_split(ToepMfmaArgs a) {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int kW64 = 15 * 15 * 15;
 
-__global__ __launch_bounds__(256, 2) void k_toep8_f64(ToepF64Args a) {
-  __shared__ double Wd[2][kW64];
+// One workgroup's share: tile `blk` (= class * tiles + tile) over offset
+// group g.  Ends with a barrier, so the caller may reuse the LDS at once.
+__device__ __forceinline__ void f64_tile(const ToepF64Args& a, int blk, int g, double (*Wd)[kW64]) {
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int l16 = l & 15, kq = l >> 4;  // row / column within a tile, k lane group
   const int m = a.m, nk = a.n / m, ntarg = nk * nk * nk;
   const int tiles = (ntarg + 15) / 16;
-  const int cls = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const int cls = blk / tiles, tile = blk % tiles;
   const int cx = cls / (m * m), cy = (cls / m) % m, cz = cls % m;
-  const int g = blockIdx.y;
   const int ob = (a.noff * g) / a.groups, oe = (a.noff * (g + 1)) / a.groups;
   const int* offs = a.offs + (size_t)cls * a.noff;
   const int E = 2 * a.C + 1, nmask = a.n - 1;
@@ -467,16 +510,56 @@ __global__ __launch_bounds__(256, 2) void k_toep8_f64(ToepF64Args a) {
     }
   }
   // epilogue: lane holds rows kq + 4 v of each tile, column l16
-  if (!tvalid) return;
-  const size_t node = ((size_t)tx * a.n + ty) * a.n + tz;
-  double* Y = a.partial ? a.partial + (size_t)g * a.n * a.n * a.n * 512 : a.Y;
+  if (tvalid) {
+    const size_t node = ((size_t)tx * a.n + ty) * a.n + tz;
+    double* Y = a.partial ? a.partial + (size_t)g * a.n * a.n * a.n * 512 : a.Y;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    double* d = Y + node * 512 + 128 * w + 16 * i + kq;
+    for (int i = 0; i < 8; ++i) {
+      double* d = Y + node * 512 + 128 * w + 16 * i + kq;
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      d[4 * v] = (a.accumulate && !a.partial) ? d[4 * v] + acc[i][v] : acc[i][v];
+      for (int v = 0; v < 4; ++v)
+        d[4 * v] = (a.accumulate && !a.partial) ? d[4 * v] + acc[i][v] : acc[i][v];
+    }
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256, 2) void k_toep8_f64(ToepF64Args a) {
+  __shared__ double Wd[2][kW64];
+  f64_tile(a, blockIdx.x, blockIdx.y, Wd);
+}
+
+// Persistent form for batches (as k_batch_split): items cover all offsets.
+__global__ __launch_bounds__(256, 2) void k_batch_f64(const ToepF64Args* __restrict__ args,
+                                                      const MmaItem* __restrict__ items, int nitems,
+                                                      unsigned* __restrict__ counter) {
+  __shared__ double Wd[2][kW64];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int idx = cur;
+    __syncthreads();  // every thread has read `cur` before thread 0 overwrites it
+    if (idx >= nitems) break;
+    const MmaItem it = items[idx];
+    const ToepF64Args a = args[it.arg];
+    f64_tile(a, it.tile, 0, Wd);
+  }
+}
+
+__global__ void k_reset_counter(unsigned* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+template <class K>
+int resident(K kernel) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess)
+    return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
 }
 
 __global__ void k_reduce_f64(const double* __restrict__ part, int groups, int64_t n,
@@ -531,6 +614,41 @@ hipError_t split_mesh(const float* rho, float scale, int N, int nt, uint16_t* ou
   const int64_t n3 = (int64_t)N * N * N;
   hipLaunchKernelGGL(k_split_mesh, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, rho,
                      scale, N, nt, out);
+  return hipGetLastError();
+}
+
+int toep8_split_tiles(int n, int m) {
+  const int nt4 = n / m / 4;
+  return nt4 * nt4 * nt4 * m * m * m;
+}
+
+int batch_mma_grid(int kind) {
+  return kind == 2 ? resident(k_batch_split<2>) : kind == 3 ? resident(k_batch_split<3>)
+                                                          : resident(k_batch_f64);
+}
+
+hipError_t launch_batch_mma(int kind, const void* args, const MmaItem* items, int nitems,
+                            unsigned* counter, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (grid > nitems) grid = nitems;
+  if (grid <= 0) return hipSuccess;
+  switch (kind) {
+    case 2:
+      hipLaunchKernelGGL(k_batch_split<2>, dim3(grid), dim3(kThreads), 0, st,
+                         (const ToepMfmaArgs*)args, items, nitems, counter);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_batch_split<3>, dim3(grid), dim3(kThreads), 0, st,
+                         (const ToepMfmaArgs*)args, items, nitems, counter);
+      break;
+    case 64:
+      hipLaunchKernelGGL(k_batch_f64, dim3(grid), dim3(kThreads), 0, st, (const ToepF64Args*)args,
+                         items, nitems, counter);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

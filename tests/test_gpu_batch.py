@@ -1,9 +1,12 @@
-"""Batches of independent fields (mixed N and p) in one persistent launch
-under a captured HIP graph, against the CPU FP64 reference FMM per field.
+"""Batches of independent fields (mixed N, p, G and precision) under a
+captured HIP graph, against the CPU FP64 reference FMM per field.
 
-The batch runs every contraction in FP32 with FP64 per-offset running totals
-(coarse levels included), so the FP32 tolerance of the single-field tests
-applies with a 2x margin for the FP32 coarse levels: 2e-5 of max|phi|."""
+Work goes to three persistent kernels: the portable one (FP32 contractions
+with FP64 per-offset running totals; FP64 levels in FP64), the BF16 split
+matrix-core kernel (near zones of split-precision plans with 8^3-cell
+sub-blocks) and the FP64 matrix-core kernel (FP64 levels at p = 8).  FP32
+fields keep the single-field FP32 tolerance with a 2x margin, 2e-5 of
+max|phi|; split-precision fields the single-field split tolerance, 1e-4."""
 import os
 
 import numpy as np
@@ -17,6 +20,7 @@ from gpu_util import f32, rel_max
 pytestmark = pytest.mark.gpu
 
 BATCH_TOL = 2e-5
+SPLIT_TOL = 1e-4
 
 SPECS = [  # (N, L, p, green, seed)
     (32, 3, 4, "S1", 101), (32, 3, 8, "X", 102), (64, 3, 6, "S1", 103),
@@ -24,14 +28,15 @@ SPECS = [  # (N, L, p, green, seed)
 ]
 
 
-def _make(specs):
+def _make(specs, precision="fp32"):
     import torch
     from paper_2011_07099_amd.pfmm import Plan
     plans, rhos, phis, host = [], [], [], []
-    for N, L, p, g, seed in specs:
+    for spec in specs:
+        N, L, p, g, seed = spec[:5]
         rho = f32(fields.lognormal(N, 2.0, 1.0, seed=seed))
         host.append(rho)
-        plans.append(Plan(N, L, p, g))
+        plans.append(Plan(N, L, p, g, precision=spec[5] if len(spec) > 5 else precision))
         rhos.append(torch.from_numpy(rho.astype(np.float32)).cuda())
         phis.append(torch.full_like(rhos[-1], float("nan")))
     return plans, rhos, phis, host
@@ -56,10 +61,38 @@ def test_batch_fields_match_reference_fmm():
         pl.close()
 
 
+SPLIT_SPECS = [  # (N, L, p, green, seed, precision)
+    (64, 3, 8, "S1", 201, "bf16x3"),    # split near zone, 8^3 leaves; FP64 levels on the matrix cores
+    (128, 3, 8, "S1", 202, "bf16x3"),   # split near zone, 16^3 leaves as 2^3 sub-blocks per leaf
+    (64, 3, 6, "S1", 203, "bf16x3"),    # split near zone; p = 6 levels in the portable kernel
+    (32, 3, 8, "X", 204, "bf16x3"),     # 4^3 leaves: portable near zone
+    (64, 3, 8, "K", 205, "fp32"),       # FP32 plan in the same batch
+]
+
+
+def test_matrix_core_items_match_reference_fmm():
+    import torch
+    from paper_2011_07099_amd.pfmm import Batch
+    plans, rhos, phis, host = _make(SPLIT_SPECS)
+    with Batch(plans, rhos, phis) as b:
+        b.solve()
+        torch.cuda.synchronize()
+        info = b.info()
+    print("batch info", info)
+    for (N, L, p, g, seed, prec), phi, rho in zip(SPLIT_SPECS, phis, host):
+        ref = ofmm.fmm(rho, L, p, g)
+        e = rel_max(phi.cpu().numpy().astype(np.float64), ref)
+        print("batch field", (N, L, p, g, prec), "rel max", e)
+        assert e < (SPLIT_TOL if prec == "bf16x3" else BATCH_TOL)
+    for pl in plans:
+        pl.close()
+
+
 def test_graph_replays_match_with_eager_work_between():
     import torch
     from paper_2011_07099_amd.pfmm import Batch, Plan
-    plans, rhos, phis, host = _make(SPECS[:4])
+    specs = SPECS[:4] + SPLIT_SPECS[:1]
+    plans, rhos, phis, host = _make(specs)
     other = Plan(32, 3, 4, "S1")
     orho = torch.from_numpy(f32(fields.lognormal(32, 2.0, 1.0, seed=7)).astype(np.float32)).cuda()
     ophi = torch.empty_like(orho)
@@ -75,9 +108,10 @@ def test_graph_replays_match_with_eager_work_between():
     for r in range(1, 4):
         for a, c in zip(outs[0], outs[r]):
             assert torch.equal(a, c)
-    for (N, L, p, g, seed), phi, rho in zip(SPECS[:4], outs[0], host):
+    for spec, phi, rho in zip(specs, outs[0], host):
+        N, L, p, g = spec[:4]
         e = rel_max(phi.numpy().astype(np.float64), ofmm.fmm(rho, L, p, g))
-        assert e < BATCH_TOL
+        assert e < (SPLIT_TOL if spec[5:] == ("bf16x3",) else BATCH_TOL)
     other.close()
     for pl in plans:
         pl.close()
