@@ -41,6 +41,8 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 # kernel and plan.hip, which sets the offset order); a changed source reports
 # null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md
 TRAFFIC = {
+    ("bf16x3", "7b682194b247"): (1123215 * 2.0 + 65536 * 1.0) * 1024,
+    ("fp32", "aaa90b5c5309"): (11770157 * 2.0 + 111562 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
 
