@@ -90,7 +90,9 @@ typedef enum {
   PFMM_OPT_GS_A1 = 3,
   /* value: int32 0/1.  When 1, solve records HIP events on the plan's stream
    * around every stage (events are created at plan time; recording them
-   * allocates nothing); pfmm_plan_stage_times reads them.  Default 0. */
+   * allocates nothing); pfmm_plan_stage_times reads them.  While on, the near
+   * zone runs on the plan's stream before the tree instead of beside it.
+   * Default 0. */
   PFMM_OPT_PROFILE = 4,
   /* value: int32 in {0, 1, 2}: keep the gridlet masses and potentials of the
    * coarsest levels 2 .. 1+value (at most level 3) in FP64, with their M2M,
@@ -161,6 +163,12 @@ pfmm_status pfmm_plan_set(pfmm_plan_t plan, int option, const void* value, size_
  *              (Sec. 3), or NULL to skip
  *
  * Enqueues on the plan's stream; does not allocate and does not synchronise.
+ * The near zone (which reads only the density) runs on a second stream owned
+ * by the plan, forked from the plan's stream and joined back to it by events
+ * before the interpolation to the mesh is added, so the two parts of the
+ * potential (Sec. 2) overlap; the whole solve is still ordered on the plan's
+ * stream and may be captured into a HIP graph from it.  The order of the
+ * arithmetic, and so the result, is the same as with profiling on.
  * No mean is removed: the density normally has zero mean (G_K ignores the
  * mean by construction).  `potential` and `accel` must not alias `density`.
  */
@@ -218,9 +226,12 @@ pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
  *   - everything else runs in the portable kernel: FP64 levels in FP64, the
  *     rest in FP32 with FP64 per-offset running totals.
  * Each list is drained by one persistent kernel through an atomic counter.
- * The portable kernel's tile width is picked by timing each candidate on
- * these inputs (or read from the JSON file named by the environment variable
- * PFMM_TUNE_CACHE, which it then updates).  The whole batch solve -- upward
+ * The portable items fall into groups by block edge (p for interaction zones,
+ * min(s, 8) for near zones), FP32 or FP64 and near or interaction zone; the
+ * tile width (targets per thread: 1, 2 or 4) of each FP32 group is picked by
+ * timing the group's own items at each width (or read from the JSON file
+ * named by the environment variable PFMM_TUNE_CACHE, key "batch-q<q>-f32-
+ * <near|zone>", which it then updates).  The whole batch solve -- upward
  * passes, the persistent launches, downward passes -- is captured into a HIP
  * graph on the batch's own stream, ordered with the stream of plans[0].  It
  * allocates, runs solves and synchronises; it is plan time.
@@ -237,11 +248,16 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
  * not allocate or synchronise.  Potentials are overwritten. */
 pfmm_status pfmm_batch_solve(pfmm_batch_t batch);
 
-/* Work items in all lists, the chosen tile width of the portable kernel
- * (targets per thread, 1, 2 or 4) and the timed duration in ms of the
- * contraction launches for each candidate width 1, 2, 4 (negative when not
- * timed; ms may be NULL). */
-pfmm_status pfmm_batch_info(pfmm_batch_t batch, int* items, int* tile_width, double* ms);
+/* Work items in all lists and the number of portable item groups (either
+ * pointer may be NULL). */
+pfmm_status pfmm_batch_info(pfmm_batch_t batch, int* items, int* groups);
+
+/* Portable item group `group` (0 <= group < groups): desc[4] = {block edge q,
+ * FP64 (0/1), near zone (0/1), chosen tile width} and ms[3] = the timed
+ * launch of the group's items at widths 1, 2, 4 in ms (negative when not
+ * timed: FP64 groups, or widths read from the cache).  Either pointer may be
+ * NULL; PFMM_ERR_INVALID_ARG for a group out of range. */
+pfmm_status pfmm_batch_group(pfmm_batch_t batch, int group, int* desc, double* ms);
 
 /* Release a batch (not its plans). NULL is accepted and ignored. */
 pfmm_status pfmm_batch_destroy(pfmm_batch_t batch);

@@ -10,8 +10,9 @@
 // counter, largest items first.  No workgroup ever waits on another.
 //
 // An item applies  Y[t] = sum_{d in D(class)} tab[a - a' - q d] X[(t+d) mod n]
-// to a tile of targets; the block edge q (1..8) is a field of the item, the
-// tile width (targets per thread, TPT) a template parameter chosen by timing.
+// to a tile of targets; the block edge q (1..8) and the tile width (targets
+// per thread, TPT = 1, 2 or 4, chosen by timing per group of items) are fields
+// of the item.
 // Items of FP32 levels sum each offset's contribution in FP32 and add it to an
 // FP64 running total, as in the single-field portable kernel; items of the
 // FP64 coarse levels run the same body in FP64 with one target per thread.
@@ -29,7 +30,7 @@ __device__ inline void unpack_offset(int pk, int& dx, int& dy, int& dz) {
 }
 
 template <int Q, int TPT, class T>
-__device__ void item_body(const BatchItem& it, T* sl, T* xs) {
+__device__ __forceinline__ void item_body(const BatchItem& it, T* sl, T* xs) {
   constexpr int R = Q * Q;
   constexpr int Q3 = Q * Q * Q;
   constexpr int S = 2 * Q - 1;
@@ -151,15 +152,29 @@ struct BatchLds {
 };
 
 template <int TPT>
-__global__ __launch_bounds__(kThreads) void k_batch_toeplitz(const BatchItem* __restrict__ items,
-                                                              int nitems,
-                                                              unsigned* __restrict__ counter) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[BatchLds<TPT>::kBytes];
+__device__ __forceinline__ void run_f32(const BatchItem& it, float* slf, float* xsf) {
+  switch (it.q) {
+    case 1: item_body<1, TPT, float>(it, slf, xsf); break;
+    case 2: item_body<2, TPT, float>(it, slf, xsf); break;
+    case 3: item_body<3, TPT, float>(it, slf, xsf); break;
+    case 4: item_body<4, TPT, float>(it, slf, xsf); break;
+    case 5: item_body<5, TPT, float>(it, slf, xsf); break;
+    case 6: item_body<6, TPT, float>(it, slf, xsf); break;
+    case 7: item_body<7, TPT, float>(it, slf, xsf); break;
+    case 8: item_body<8, TPT, float>(it, slf, xsf); break;
+    default: break;
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void k_batch_toeplitz(const BatchItem* __restrict__ items,
+                                                             int nitems,
+                                                             unsigned* __restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[BatchLds<4>::kBytes];
   __shared__ int cur;
   float* slf = reinterpret_cast<float*>(lds);
-  float* xsf = slf + BatchLds<TPT>::kSlice;
+  float* xsf = slf + BatchLds<4>::kSlice;
   double* sld = reinterpret_cast<double*>(lds);
-  double* xsd = sld + BatchLds<TPT>::kSlice;
+  double* xsd = sld + BatchLds<4>::kSlice;
   for (;;) {
     if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
     __syncthreads();
@@ -179,18 +194,12 @@ __global__ __launch_bounds__(kThreads) void k_batch_toeplitz(const BatchItem* __
         case 8: item_body<8, 1, double>(it, sld, xsd); break;
         default: break;
       }
+    } else if (it.tpt == 4) {
+      run_f32<4>(it, slf, xsf);
+    } else if (it.tpt == 2) {
+      run_f32<2>(it, slf, xsf);
     } else {
-      switch (it.q) {
-        case 1: item_body<1, TPT, float>(it, slf, xsf); break;
-        case 2: item_body<2, TPT, float>(it, slf, xsf); break;
-        case 3: item_body<3, TPT, float>(it, slf, xsf); break;
-        case 4: item_body<4, TPT, float>(it, slf, xsf); break;
-        case 5: item_body<5, TPT, float>(it, slf, xsf); break;
-        case 6: item_body<6, TPT, float>(it, slf, xsf); break;
-        case 7: item_body<7, TPT, float>(it, slf, xsf); break;
-        case 8: item_body<8, TPT, float>(it, slf, xsf); break;
-        default: break;
-      }
+      run_f32<1>(it, slf, xsf);
     }
   }
 }
@@ -199,10 +208,9 @@ __global__ void k_reset_counter(unsigned* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
-template <int TPT>
 int resident_grid() {
   int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_toeplitz<TPT>, kThreads, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_toeplitz, kThreads, 0) !=
       hipSuccess)
     return 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -217,28 +225,16 @@ int batch_targets_per_item(int q, int tpt, int fp64) {
   return (kThreads / (q * q)) * (fp64 ? 1 : tpt);
 }
 
-int batch_resident_grid(int tpt) {
-  switch (tpt) {
-    case 1: return resident_grid<1>();
-    case 2: return resident_grid<2>();
-    case 4: return resident_grid<4>();
-    default: return 0;
-  }
-}
+int batch_resident_grid() { return resident_grid(); }
 
-hipError_t launch_batch_toeplitz(const BatchItem* items, int nitems, unsigned* counter, int tpt,
-                                 int grid, hipStream_t st) {
+hipError_t launch_batch_toeplitz(const BatchItem* items, int nitems, unsigned* counter, int grid,
+                                 hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (grid > nitems) grid = nitems;
   if (grid <= 0) return hipSuccess;
-  switch (tpt) {
-    case 1: hipLaunchKernelGGL(k_batch_toeplitz<1>, dim3(grid), dim3(kThreads), 0, st, items, nitems, counter); break;
-    case 2: hipLaunchKernelGGL(k_batch_toeplitz<2>, dim3(grid), dim3(kThreads), 0, st, items, nitems, counter); break;
-    case 4: hipLaunchKernelGGL(k_batch_toeplitz<4>, dim3(grid), dim3(kThreads), 0, st, items, nitems, counter); break;
-    default: return hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL(k_batch_toeplitz, dim3(grid), dim3(kThreads), 0, st, items, nitems, counter);
   return hipGetLastError();
 }
 

@@ -116,6 +116,7 @@ struct BatchItem {
   int n, m, q, C, noff, cls, t0, grid;
   float xscale;
   int fp64;         // FP64 operands: tile width 1, FP64 sums
+  int tpt;          // FP32 tile width (targets per thread): 1, 2 or 4
 };
 int batch_targets_per_item(int q, int tpt, int fp64);
 
@@ -130,9 +131,9 @@ int toep8_split_tiles(int n, int m);  // tiles (workgroups) of one split launch
 int batch_mma_grid(int kind);         // resident workgroups of a persistent kind
 hipError_t launch_batch_mma(int kind, const void* args, const MmaItem* items, int nitems,
                             unsigned* counter, int grid, hipStream_t st);
-int batch_resident_grid(int tpt);
-hipError_t launch_batch_toeplitz(const BatchItem* items, int nitems, unsigned* counter, int tpt,
-                                 int grid, hipStream_t st);
+int batch_resident_grid();
+hipError_t launch_batch_toeplitz(const BatchItem* items, int nitems, unsigned* counter, int grid,
+                                 hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Learned correction of the interaction-zone tables (learned.hip)

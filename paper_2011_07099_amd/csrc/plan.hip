@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <set>
@@ -35,6 +36,10 @@ struct pfmm_plan_s {
   int N = 0, L = 0, p = 0, s = 0, green = 0, prec = PFMM_PREC_FP32;
   double a1 = -0.125;
   hipStream_t stream = nullptr;
+  // The near zone runs on `side` while the tree runs on `stream` (fork and
+  // join by events), except when profiling
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int qn = 0, mn = 0;  // near-zone block edge and classes per axis
   float* dA = nullptr;  // [p][s] P2M / L2P weights
   float* dT = nullptr;  // [2][p][p] M2M / L2L weights
@@ -52,8 +57,9 @@ struct pfmm_plan_s {
   // split-precision matrix-core path (8^3 blocks)
   std::vector<uint32_t*> win;     // per level: table windows (p == 8)
   uint32_t* nwin = nullptr;       // near-table windows (8^3-cell sub-blocks)
-  uint16_t* xs = nullptr;         // bf16 source terms (up to 3 arrays of xwords)
+  uint16_t* xs = nullptr;         // bf16 gridlet-mass terms (3 arrays of xwords)
   size_t xwords = 0;
+  uint16_t* xsn = nullptr;        // bf16 density terms in sub-blocks (2 arrays of N^3)
   float* part = nullptr;          // split-offset partial sums (matrix-core path)
   size_t part_floats = 0;
   void* spart = nullptr;          // split-offset partial sums (portable kernel)
@@ -154,6 +160,12 @@ void release(pfmm_plan_s* pl) {
   for (hipEvent_t e : pl->ev)
     if (e) (void)hipEventDestroy(e);
   pl->ev.clear();
+  if (pl->side) {
+    (void)hipStreamSynchronize(pl->side);
+    (void)hipStreamDestroy(pl->side);
+  }
+  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+  if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
   for (void* q : pl->owned) (void)hipFree(q);
   pl->owned.clear();
   delete pl;
@@ -358,7 +370,8 @@ pfmm_status build(pfmm_plan_s* pl) {
     if (qn == 8 && toep8_supported(N / 8, mn)) {
       e = dalloc(pl, &pl->nwin, window_dwords(kNearTerms));
       if ((st = chk("near windows"))) return st;
-      xwords = std::max(xwords, (size_t)N * N * N);
+      e = dalloc(pl, &pl->xsn, (size_t)kNearTerms * N * N * N);
+      if ((st = chk("split density"))) return st;
     }
   }
   if (xwords) {
@@ -438,6 +451,12 @@ pfmm_status build(pfmm_plan_s* pl) {
   }
   pl->ev_tag.assign(kSlots * kMaxEvents, 0);
   pl->ev_used.assign(kSlots, 0);
+  // default priority (no priority streams anywhere in this library)
+  e = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking);
+  if ((st = chk("side stream"))) return st;
+  e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming);
+  if ((st = chk("fork events"))) return st;
   return tabulate_all(pl);
 }
 
@@ -612,6 +631,52 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     return launch_toep8_split(ma, kM2LTerms, st);
   };
 
+  // near zone (reads only the density): writes phi; on the side stream, so
+  // that it runs beside the tree, unless stages are being timed
+  const bool overlap = !pl->profile;
+  hipStream_t sn = overlap ? pl->side : st;
+  if (overlap) {
+    e = hipEventRecord(pl->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pl->side, pl->ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "fork");
+  }
+  ToepArgs nb{};
+  nb.q = pl->qn;
+  nb.m = pl->mn;
+  nb.n = N / pl->qn;
+  nb.noff = (int)cube(3 * pl->mn);
+  nb.offs = pl->offs_near;
+  nb.tab = pl->ntab32;
+  nb.C = 2 * s - 1;
+  nb.X = rho;
+  nb.Y = phi;
+  nb.grid_in = 1;
+  nb.grid_out = 1;
+  nb.xscale = 1.0 / ((double)N * N * N);
+  nb.accumulate = 0;
+  nb.groups = 1;
+  if (mx && pl->nwin) {
+    e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xsn, sn);
+    if (e == hipSuccess) {
+      ToepMfmaArgs ma{};
+      ma.n = nb.n;
+      ma.m = nb.m;
+      ma.noff = nb.noff;
+      ma.offs = nb.offs;
+      ma.win = pl->nwin;
+      ma.X = pl->xsn;
+      ma.Y = phi;
+      ma.grid_out = 1;
+      ma.accumulate = 0;
+      ma.groups = 1;
+      e = launch_toep8_split(ma, kNearTerms, sn);
+    }
+  } else {
+    e = launch_toeplitz(nb, sn);
+  }
+  if (e == hipSuccess) e = overlap ? hipEventRecord(pl->ev_join, pl->side) : mark(PFMM_STAGE_NEAR);
+  if (e != hipSuccess) return hip_fail(e, "near zone");
+
   // upward pass
   e = launch_p2m(rho, pl->M[L], is64(L), A, N, s, p, (double)h3, st);
   if (e == hipSuccess) e = mark(PFMM_STAGE_P2M);
@@ -657,46 +722,15 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     if (e != hipSuccess) return hip_fail(e, "M2L");
   }
 
-  // downward to the mesh, then the near zone
-  e = launch_l2p(pl->P[L], is64(L), phi, A, N, s, p, st);
+  // downward to the mesh, added to the near zone
+  if (overlap) {
+    e = hipStreamWaitEvent(st, pl->ev_join, 0);
+    if (e != hipSuccess) return hip_fail(e, "join");
+  }
+  e = launch_l2p(pl->P[L], is64(L), phi, A, N, s, p, st, 1);
   if (e == hipSuccess) e = mark(PFMM_STAGE_L2P);
   if (e != hipSuccess) return hip_fail(e, "L2P");
-  ToepArgs nb{};
-  nb.q = pl->qn;
-  nb.m = pl->mn;
-  nb.n = N / pl->qn;
-  nb.noff = (int)cube(3 * pl->mn);
-  nb.offs = pl->offs_near;
-  nb.tab = pl->ntab32;
-  nb.C = 2 * s - 1;
-  nb.X = rho;
-  nb.Y = phi;
-  nb.grid_in = 1;
-  nb.grid_out = 1;
-  nb.xscale = 1.0 / ((double)N * N * N);
-  nb.accumulate = 1;
-  nb.groups = 1;
-  if (mx && pl->nwin) {
-    e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xs, st);
-    if (e == hipSuccess) {
-      ToepMfmaArgs ma{};
-      ma.n = nb.n;
-      ma.m = nb.m;
-      ma.noff = nb.noff;
-      ma.offs = nb.offs;
-      ma.win = pl->nwin;
-      ma.X = pl->xs;
-      ma.Y = phi;
-      ma.grid_out = 1;
-      ma.accumulate = 1;
-      ma.groups = 1;
-      e = launch_toep8_split(ma, kNearTerms, st);
-    }
-  } else {
-    e = launch_toeplitz(nb, st);
-  }
-  if (e == hipSuccess) e = mark(PFMM_STAGE_NEAR);
-  if (e != hipSuccess) return hip_fail(e, "near zone");
+
   if (accel) {
     e = launch_fd4(phi, accel, N, st);
     if (e == hipSuccess) e = mark(PFMM_STAGE_FD4);
@@ -837,7 +871,7 @@ struct pfmm_batch_s {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   BatchItem* items = nullptr;  // device work list (portable kernel)
   unsigned* counter = nullptr;  // [0] portable, [1] split, [2] FP64 matrix-core list
-  int nitems = 0, tpt = 2, grid = 0;
+  int nitems = 0, grid = 0;
   // matrix-core work lists: split near zones (plans in split precision) and
   // the FP64 levels at p = 8
   ToepMfmaArgs* sargs = nullptr;
@@ -845,7 +879,14 @@ struct pfmm_batch_s {
   MmaItem* sitems = nullptr;
   MmaItem* fitems = nullptr;
   int nsplit = 0, nf64 = 0, sgrid = 0, fgrid = 0;
-  double tuned_ms[3] = {-1.0, -1.0, -1.0};
+  // portable item groups (block edge, FP64, near zone): tuned tile width and
+  // the timed launch of the group's items at widths 1, 2, 4 (-1: not timed)
+  struct Group {
+    std::string key;
+    int q, fp64, near, width;
+    double ms[3];
+  };
+  std::vector<Group> groups;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -881,15 +922,29 @@ void brelease(pfmm_batch_s* b) {
 bool batch_split_near(const pfmm_plan_s* pl) { return pl->prec == PFMM_PREC_BF16X3 && pl->nwin; }
 bool batch_f64_level(const pfmm_plan_s* pl, int l) { return level64(pl, l) && pl->p == 8; }
 
-// Work items of every other contraction of every field, largest first.
-std::vector<BatchItem> batch_items(const pfmm_batch_s* b, int tpt) {
+// Tuning group of a portable item: block edge, FP64 or FP32, near zone or
+// interaction zone (in the terms of the method: p or the leaf width s, and the
+// precision).
+std::string group_key(const BatchItem& it) {
+  return "q" + std::to_string(it.q) + (it.fp64 ? "-f64" : "-f32") + (it.grid ? "-near" : "-zone");
+}
+
+// Work items of every other contraction of every field, largest first; the
+// FP32 tile width of each group from `widths` (default 2), only the items of
+// group `only` when it is given.
+std::vector<BatchItem> batch_items(const pfmm_batch_s* b, const std::map<std::string, int>& widths,
+                                   const std::string* only = nullptr) {
   struct Keyed {
     double cost;
     BatchItem it;
   };
   std::vector<Keyed> all;
-  auto add = [&](const BatchItem& proto) {
-    const int TT = batch_targets_per_item(proto.q, tpt, proto.fp64);
+  auto add = [&](BatchItem proto) {
+    const std::string key = group_key(proto);
+    if (only && key != *only) return;
+    const auto wi = widths.find(key);
+    proto.tpt = proto.fp64 ? 1 : (wi != widths.end() ? wi->second : 2);
+    const int TT = batch_targets_per_item(proto.q, proto.tpt, proto.fp64);
     const int nk = proto.n / proto.m;
     const int ntarg = nk * nk * nk;
     const double cost = (double)proto.noff * std::min(TT, ntarg) * std::pow((double)proto.q, 6.0);
@@ -977,7 +1032,7 @@ hipError_t batch_mma_upload(pfmm_batch_s* b) {
       y.noff = (int)cube(3 * pl->mn);
       y.offs = pl->offs_near;
       y.win = pl->nwin;
-      y.X = pl->xs;
+      y.X = pl->xsn;
       y.Y = b->phi[f];
       y.grid_out = 1;
       y.accumulate = 0;
@@ -1010,21 +1065,22 @@ hipError_t batch_mma_upload(pfmm_batch_s* b) {
   return e;
 }
 
-hipError_t batch_upload(pfmm_batch_s* b, int tpt) {
-  const std::vector<BatchItem> v = batch_items(b, tpt);
+hipError_t batch_upload(pfmm_batch_s* b, const std::map<std::string, int>& widths,
+                        const std::string* only = nullptr) {
+  const std::vector<BatchItem> v = batch_items(b, widths, only);
   if (b->items) (void)hipFree(b->items);
   b->items = nullptr;
   hipError_t e = hipMalloc(&b->items, std::max<size_t>(1, v.size()) * sizeof(BatchItem));
   if (e != hipSuccess) return e;
   e = hipMemcpy(b->items, v.data(), v.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
   b->nitems = (int)v.size();
-  b->tpt = tpt;
-  b->grid = batch_resident_grid(tpt);
+  b->grid = batch_resident_grid();
   return e;
 }
 
 // The whole batch solve, enqueued on the batch stream.  `part`: 0 = all,
-// 1 = upward passes only, 2 = the persistent contraction only, 3 = downward.
+// 1 = upward passes only, 2 = the persistent contractions only, 3 = downward,
+// 4 = the portable persistent kernel only.
 hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
   hipStream_t st = b->stream;
   hipError_t e = hipSuccess;
@@ -1039,11 +1095,11 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
                        pl->p, st);
       if (e == hipSuccess && batch_split_near(pl))
         e = split_mesh(b->rho[f], (float)(1.0 / ((double)pl->N * pl->N * pl->N)), pl->N,
-                       kNearTerms, pl->xs, st);
+                       kNearTerms, pl->xsn, st);
     }
   }
-  if (e == hipSuccess && (part == 0 || part == 2))
-    e = launch_batch_toeplitz(b->items, b->nitems, b->counter, b->tpt, b->grid, st);
+  if (e == hipSuccess && (part == 0 || part == 2 || part == 4))
+    e = launch_batch_toeplitz(b->items, b->nitems, b->counter, b->grid, st);
   if (e == hipSuccess && (part == 0 || part == 2))
     e = launch_batch_mma(2, b->sargs, b->sitems, b->nsplit, b->counter + 1, b->sgrid, st);
   if (e == hipSuccess && (part == 0 || part == 2))
@@ -1063,18 +1119,6 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
   return e;
 }
 
-std::string batch_signature(const pfmm_batch_s* b) {
-  std::string sig;
-  for (const pfmm_plan_s* pl : b->plans)
-    sig += std::to_string(pl->N) + "/" + std::to_string(pl->L) + "/" + std::to_string(pl->p) + "/" +
-           std::to_string(pl->prec) + ";";
-  // hash it to keep the cache file short
-  uint64_t h = 1469598103934665603ull;
-  for (char c : sig) h = (h ^ (unsigned char)c) * 1099511628211ull;
-  char buf[32];
-  std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
-  return std::string(buf) + "-" + std::to_string(b->plans.size());
-}
 
 // Cache: a flat JSON object {"<signature>": tile_width, ...}.
 int cache_lookup(const char* path, const std::string& key) {
@@ -1157,45 +1201,65 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
     brelease(b);
     return hip_fail(e, "batch work lists");
   }
-  // tile width: cache, else time each candidate on these inputs
-  const char* cache = std::getenv("PFMM_TUNE_CACHE");
-  const std::string key = batch_signature(b);
-  int tpt = cache ? cache_lookup(cache, key) : 0;
-  if (!tpt) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    double best = 1e300;
-    const int cand[3] = {1, 2, 4};
-    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
-      e = batch_upload(b, cand[c]);
-      if (e == hipSuccess) e = batch_enqueue(b, 0);  // warm up, makes the inputs valid
-      float ms = 0.f, msmin = 1e30f;
-      for (int r = 0; r < 2 && e == hipSuccess; ++r) {
-        e = hipEventRecord(e0, b->stream);
-        if (e == hipSuccess) e = batch_enqueue(b, 2);
-        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        msmin = std::min(msmin, ms);
-      }
-      if (e != hipSuccess) break;
-      b->tuned_ms[c] = msmin;
-      if (msmin < best) {
-        best = msmin;
-        tpt = cand[c];
-      }
+  // tile width per group of portable items: cache, else time each candidate
+  // on the group's own items (after one full solve makes every input valid)
+  std::map<std::string, int> widths;
+  {
+    std::map<std::string, pfmm_batch_s::Group> found;
+    for (const BatchItem& it : batch_items(b, widths)) {
+      const std::string key = group_key(it);
+      if (!found.count(key))
+        found[key] = {key, it.q, it.fp64, it.grid, it.fp64 ? 1 : 2, {-1.0, -1.0, -1.0}};
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (e != hipSuccess) {
-      (void)hipDeviceSynchronize();
-      brelease(b);
-      return hip_fail(e, "batch tuning");
-    }
-    if (cache) cache_store(cache, key, tpt);
+    for (auto& kv : found) b->groups.push_back(kv.second);
   }
-  e = batch_upload(b, tpt);
+  const char* cache = std::getenv("PFMM_TUNE_CACHE");
+  e = batch_upload(b, widths);
+  if (e == hipSuccess) e = batch_enqueue(b, 0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const int cand[3] = {1, 2, 4};
+  for (auto& g : b->groups) {
+    if (e != hipSuccess) break;
+    if (g.fp64) continue;  // FP64 items have tile width 1
+    const std::string ckey = "batch-" + g.key;
+    int w = cache ? cache_lookup(cache, ckey) : 0;
+    if (!w) {
+      double best = 1e300;
+      for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+        std::map<std::string, int> trial = widths;
+        trial[g.key] = cand[c];
+        e = batch_upload(b, trial, &g.key);
+        float ms = 0.f, msmin = 1e30f;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {  // first run warms up
+          e = hipEventRecord(e0, b->stream);
+          if (e == hipSuccess) e = batch_enqueue(b, 4);
+          if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (r > 0) msmin = std::min(msmin, ms);
+        }
+        if (e != hipSuccess) break;
+        g.ms[c] = msmin;
+        if (msmin < best) {
+          best = msmin;
+          w = cand[c];
+        }
+      }
+      if (e == hipSuccess && cache) cache_store(cache, ckey, w);
+    }
+    g.width = w;
+    widths[g.key] = w;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e == hipSuccess) e = batch_upload(b, widths);
+  if (e != hipSuccess) {
+    (void)hipDeviceSynchronize();
+    brelease(b);
+    return hip_fail(e, "batch tuning");
+  }
   // capture the whole batch solve
   if (e == hipSuccess) e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
@@ -1229,13 +1293,28 @@ pfmm_status pfmm_batch_solve(pfmm_batch_t b) {
   return PFMM_OK;
 }
 
-pfmm_status pfmm_batch_info(pfmm_batch_t b, int* items, int* tile_width, double* ms) {
+pfmm_status pfmm_batch_info(pfmm_batch_t b, int* items, int* groups) {
   g_err.clear();
   if (!blive(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
   if (items) *items = b->nitems + b->nsplit + b->nf64;
-  if (tile_width) *tile_width = b->tpt;
+  if (groups) *groups = (int)b->groups.size();
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_batch_group(pfmm_batch_t b, int group, int* desc, double* ms) {
+  g_err.clear();
+  if (!blive(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
+  if (group < 0 || group >= (int)b->groups.size())
+    return fail(PFMM_ERR_INVALID_ARG, "group out of range");
+  const auto& g = b->groups[group];
+  if (desc) {
+    desc[0] = g.q;
+    desc[1] = g.fp64;
+    desc[2] = g.near;
+    desc[3] = g.width;
+  }
   if (ms)
-    for (int i = 0; i < 3; ++i) ms[i] = b->tuned_ms[i];
+    for (int i = 0; i < 3; ++i) ms[i] = g.ms[i];
   return PFMM_OK;
 }
 

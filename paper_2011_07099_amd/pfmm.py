@@ -21,7 +21,8 @@ BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
 # every symbol include/pfmm.h declares
 EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_plan_read",
            "pfmm_plan_stage_times", "pfmm_plan_level_times", "pfmm_plan_info", "pfmm_plan_destroy",
-           "pfmm_batch_create", "pfmm_batch_solve", "pfmm_batch_info", "pfmm_batch_destroy",
+           "pfmm_batch_create", "pfmm_batch_solve", "pfmm_batch_info", "pfmm_batch_group",
+           "pfmm_batch_destroy",
            "pfmm_plan_direct", "pfmm_learned_set", "pfmm_learned_train_begin",
            "pfmm_learned_accumulate", "pfmm_learned_loss", "pfmm_learned_step", "pfmm_learned_get",
            "pfmm_learned_read_grad", "pfmm_last_error")
@@ -57,8 +58,8 @@ def load():
     lib.pfmm_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.pfmm_batch_solve.argtypes = [vp]
-    lib.pfmm_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                    ctypes.POINTER(ctypes.c_double)]
+    lib.pfmm_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.pfmm_batch_group.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.pfmm_batch_destroy.argtypes = [vp]
     fp = ctypes.POINTER(ctypes.c_float)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -287,10 +288,19 @@ class Batch:
         _check(load().pfmm_batch_solve(self._h))
 
     def info(self):
-        items, tw = ctypes.c_int(), ctypes.c_int()
-        ms = (ctypes.c_double * 3)()
-        _check(load().pfmm_batch_info(self._h, ctypes.byref(items), ctypes.byref(tw), ms))
-        return {"items": items.value, "tile_width": tw.value, "tuned_ms": list(ms)}
+        """{"items": total work items, "groups": [{"q", "fp64", "near",
+        "width", "ms": timed ms at widths 1, 2, 4 (negative: not timed)}]}"""
+        lib = load()
+        items, ng = ctypes.c_int(), ctypes.c_int()
+        _check(lib.pfmm_batch_info(self._h, ctypes.byref(items), ctypes.byref(ng)))
+        groups = []
+        for g in range(ng.value):
+            desc = (ctypes.c_int * 4)()
+            ms = (ctypes.c_double * 3)()
+            _check(lib.pfmm_batch_group(self._h, g, desc, ms))
+            groups.append({"q": desc[0], "fp64": bool(desc[1]), "near": bool(desc[2]),
+                           "width": desc[3], "ms": list(ms)})
+        return {"items": items.value, "groups": groups}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -51,7 +51,7 @@ def test_batch_fields_match_reference_fmm():
         torch.cuda.synchronize()
         info = b.info()
     print("batch info", info)
-    assert info["tile_width"] in (1, 2, 4) and info["items"] > 0
+    assert info["items"] > 0 and all(g["width"] in (1, 2, 4) for g in info["groups"])
     for (N, L, p, g, seed), phi, rho in zip(SPECS, phis, host):
         ref = ofmm.fmm(rho, L, p, g)
         e = rel_max(phi.cpu().numpy().astype(np.float64), ref)
@@ -118,6 +118,9 @@ def test_graph_replays_match_with_eager_work_between():
 
 
 def test_tuning_cache_round_trip(tmp_path, monkeypatch):
+    """Each FP32 group of portable items is tuned on its own items; the choice
+    goes to the cache and the next batch of the same groups reads it back."""
+    import json
     import torch
     from paper_2011_07099_amd.pfmm import Batch
     path = tmp_path / "tune.json"
@@ -125,13 +128,25 @@ def test_tuning_cache_round_trip(tmp_path, monkeypatch):
     plans, rhos, phis, host = _make(SPECS[:3])
     with Batch(plans, rhos, phis) as b:
         first = b.info()
-    assert path.exists() and min(first["tuned_ms"]) > 0
+    cached = json.loads(path.read_text())
+    print("tuned", first, "cache", cached)
+    f32 = [g for g in first["groups"] if not g["fp64"]]
+    assert f32, first
+    for g in first["groups"]:
+        key = "batch-q%d-f32-%s" % (g["q"], "near" if g["near"] else "zone")
+        if g["fp64"]:
+            assert g["width"] == 1 and min(g["ms"]) < 0
+        else:
+            assert min(g["ms"]) > 0 and g["width"] in (1, 2, 4)
+            assert g["ms"][(1, 2, 4).index(g["width"])] == min(g["ms"])
+            assert cached[key] == g["width"]
     with Batch(plans, rhos, phis) as b:
         second = b.info()
         b.solve()
         torch.cuda.synchronize()
-    print("tuned", first, "cached", second, path.read_text())
-    assert second["tile_width"] == first["tile_width"]
-    assert max(second["tuned_ms"]) < 0          # taken from the cache, not timed
+    for g1, g2 in zip(first["groups"], second["groups"]):
+        assert g1["width"] == g2["width"] and (g2["fp64"] or max(g2["ms"]) < 0)
+    for (N, L, p, g, seed), phi, rho in zip(SPECS[:3], phis, host):
+        assert rel_max(phi.cpu().numpy().astype(np.float64), ofmm.fmm(rho, L, p, g)) < BATCH_TOL
     for pl in plans:
         pl.close()

@@ -1,0 +1,76 @@
+"""The edges of the operating range on the GPU, through the C ABI.
+
+* Maximum size: N = 1024 (L = 6, 16^3-cell leaves, p = 8, G_S1, split
+  precision), in the launch configuration of the headline solve.
+  - Shift by one level-2 node (N/4 cells) along each axis: the tree, the
+    parity classes of every level >= 3 and every kernel's tiling are the same
+    for the shifted problem, so each target sees the same arithmetic on the
+    same numbers and the potential shifts bit for bit.
+  - Point masses: potential differences between sampled cells against the
+    direct periodic sum of G_S1 over the sources (Eq. 4; the uniform
+    background that makes the mean zero adds the same constant to every cell,
+    which the differences cancel).  Tolerance: the method's own error for
+    point sources at p = 8, 2e-3 of the largest difference (the FMM-vs-PM
+    L_max of the 256^3 field is 2e-4).
+* Zero density: the potential and acceleration are exactly zero (every step
+  is linear).
+"""
+import numpy as np
+import pytest
+
+from oracle import green as ogreen
+
+pytestmark = pytest.mark.gpu
+
+
+def test_maximum_size_shift_exactness_and_point_masses():
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    N, L, p = 1024, 6, 8
+    h = 1.0 / N
+    rng = np.random.default_rng(77)
+    src = rng.integers(0, N, size=(8, 3))
+    bg = np.float32(-len(src) / N ** 3)
+    rho = torch.full((N, N, N), float(bg), dtype=torch.float32, device="cuda")
+    for c in src:
+        rho[c[0], c[1], c[2]] = 1.0
+    phi = torch.empty_like(rho)
+    with Plan(N, L, p, "S1", precision="bf16x3") as pl:
+        pl.solve(rho, phi)
+        for axis in range(3):
+            shifted = torch.roll(rho, N // 4, dims=axis).contiguous()
+            out = torch.empty_like(rho)
+            pl.solve(shifted, out)
+            same = torch.equal(torch.roll(phi, N // 4, dims=axis), out)
+            print("shift by N/4 along", axis, "bit-exact:", same)
+            assert same
+            del shifted, out
+        torch.cuda.synchronize()
+    tg = rng.integers(0, N, size=(64, 3))
+    got = phi[tg[:, 0], tg[:, 1], tg[:, 2]].double().cpu().numpy()
+    # direct periodic sum of the sources (their excess over the background)
+    w = np.float64(np.float32(1.0)) - np.float64(bg)
+    sep = (tg[:, None, :] - src[None, :, :]) * h
+    g = ogreen.green_s1(sep)
+    g[np.all(tg[:, None, :] == src[None, :, :], axis=-1)] = ogreen.self_value(h)
+    ref = h ** 3 * w * g.sum(axis=1)
+    d_got, d_ref = got - got[0], ref - ref[0]
+    err = np.max(np.abs(d_got - d_ref)) / np.max(np.abs(d_ref))
+    print("1024^3 point masses: max error of potential differences / max difference", err)
+    assert err < 2e-3
+    del rho, phi
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_zero_density_gives_exact_zero(precision):
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    N = 64
+    rho = torch.zeros((N, N, N), dtype=torch.float32, device="cuda")
+    phi = torch.full_like(rho, float("nan"))
+    acc = torch.full((3, N, N, N), float("nan"), dtype=torch.float32, device="cuda")
+    with Plan(N, 3, 8, "S1", precision=precision) as pl:
+        pl.solve(rho, phi, acc)
+        torch.cuda.synchronize()
+    assert torch.count_nonzero(phi).item() == 0 and torch.count_nonzero(acc).item() == 0
