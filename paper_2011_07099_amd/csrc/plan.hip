@@ -174,7 +174,7 @@ void release(pfmm_plan_s* pl) {
 // Is level l kept in FP64?  Levels 2 .. 1 + fp64_levels are, except a leaf
 // whose FP64 P2M / L2P staging would not fit in 64 KiB of LDS.
 bool level64(const pfmm_plan_s* pl, int l) {
-  if (l < 2 || l > 1 + pl->fp64_levels || l > 3) return false;
+  if (l < 2 || l > 1 + pl->fp64_levels) return false;
   if (l == pl->L) {
     const int p = pl->p, s = pl->s;
     const size_t w1 = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
@@ -331,7 +331,7 @@ pfmm_status build(pfmm_plan_s* pl) {
   const int64_t nlev = cube(8 * p - 1);
   for (int l = 2; l <= L; ++l) {
     const size_t nodes = (size_t)1 << (3 * l);
-    const size_t wbytes = l <= 3 ? sizeof(double) : sizeof(float);
+    const size_t wbytes = sizeof(double);  // any level may be kept in FP64
     char* mb = nullptr;
     e = dalloc(pl, &mb, nodes * p3 * wbytes);
     pl->M[l] = mb;
@@ -389,7 +389,7 @@ pfmm_status build(pfmm_plan_s* pl) {
     size_t bytes = 0;
     for (int l = 2; l <= L; ++l) {
       const int n = 1 << l, m = l == 2 ? 1 : 2, noff = l == 2 ? 37 : 189;
-      for (int f64 = 0; f64 <= (l <= 3 ? 1 : 0); ++f64) {  // the FP64 level count is an option
+      for (int f64 = 0; f64 <= 1; ++f64) {  // the FP64 level count is an option
         int G = scalar_groups(p, f64, n, m, noff);
         if (f64 && p == 8) G = std::max(G, f64_groups(n, m, noff));
         const size_t w = f64 ? sizeof(double) : sizeof(float);
@@ -542,7 +542,8 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels is an int32");
       int32_t v;
       std::memcpy(&v, value, sizeof v);
-      if (v < 0 || v > 2) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels must be 0, 1 or 2");
+      if (v < 0 || v > pl->L - 1)
+        return fail(PFMM_ERR_INVALID_ARG, "fp64 levels must be in [0, L - 1]");
       pl->fp64_levels = v;
       return PFMM_OK;
     }
@@ -1463,7 +1464,7 @@ pfmm_status learned_train_alloc(pfmm_plan_s* pl) {
   size_t tg = 0;
   for (int l = 2; l <= L && e == hipSuccess; ++l) {
     char* b = nullptr;
-    e = dalloc(pl, &b, ((size_t)1 << (3 * l)) * p3 * (l <= 3 ? sizeof(double) : sizeof(float)));
+    e = dalloc(pl, &b, ((size_t)1 << (3 * l)) * p3 * sizeof(double));
     pl->lam[l] = b;
     if (e == hipSuccess) e = dalloc(pl, &pl->tgrad[l], (size_t)ntab);
     tg = std::max(tg, table_grad_partial_doubles(l == 2 ? 1 : 2, p, l == 2 ? 37 : 189));

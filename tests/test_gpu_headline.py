@@ -1,12 +1,24 @@
 """Parity at the headline size: N = 256, L = 4 (16^3-cell leaves), p = 8,
 G_S1, lognormal density with P(k) ~ k^-1.5 and sigma_delta = 2 (seed 5), in
-the configuration the benchmark times.
+the configuration the benchmark times (default FP64 levels 2-3) and with the
+leaf level in FP64 as well.
 
-* Against the step-by-step FP64 reference FMM on an 8^3 lattice of sampled
-  cells i_k = k N/8 + N/16 + 1 (512 targets, one per distinct leaf).
+* Against the step-by-step FP64 reference FMM at 4096 sampled cells, one per
+  leaf of a 16^3 lattice of leaves, with the cell's position inside its leaf
+  running through all 16 values on every axis (so leaf corners are sampled).
 * Against "PM with the same G" (Eq. 4, full-mesh FFT in FP64): relative L2
   <= 1e-4 and relative L_max <= 1e-3 on the mean-removed potential, the
   accuracy the method is held to.
+
+Tolerances against the reference FMM (max error / max|phi|).  With an FP32
+leaf level, the leaf interaction-zone sums carry FP32 accumulation error of
+about 2e-6 of the locals' size (their terms cancel 10^2-10^3 fold; measured
+at 128^3 with the leaf level forced to FP32).  With s = 16 > p = 8, L2P
+extrapolates beyond the outermost gridlet nodes towards the leaf faces and
+corners, which amplifies that error about 100-fold.  Hence 2.5e-4 (split)
+and 5e-4 (FP32 VALU sums) at the default setting, against 2e-5 away from the
+faces.  With the leaf level in FP64 the remaining error is the split near
+zone's (~2e-6; tolerance 1e-5) or FP32 rounding (tolerance 1e-6).
 """
 import numpy as np
 import pytest
@@ -19,17 +31,18 @@ from gpu_util import f32, solve
 pytestmark = pytest.mark.gpu
 
 N, L, P = 256, 4, 8
+S = N >> L
 
 
 def _targets():
-    k = np.arange(8) * (N // 8) + N // 16 + 1
-    return np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3)
+    k = np.arange(N // S)
+    pos = (7 * k + 15) % S  # a permutation of 0..15 (7 is odd): every in-leaf position
+    c = S * k + pos
+    return np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
 
 
-PRECISIONS = ["fp32", "bf16x3"]
-# sampled-cell tolerance against the FP64 reference FMM, per precision (the
-# bf16x3 bound is derived with the parity tests)
-SAMPLED_TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+# (precision, FP64 levels) -> sampled-cell tolerance against the FP64 reference FMM
+CASES = {("fp32", 2): 5e-4, ("bf16x3", 2): 2.5e-4, ("fp32", 3): 1e-6, ("bf16x3", 3): 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -43,27 +56,30 @@ def reference(rho):
     return tg, ofmm.fmm(rho, L, P, "S1", targets=tg), conv.pm(rho, "S1")
 
 
-@pytest.fixture(scope="module", params=PRECISIONS)
+@pytest.fixture(scope="module", params=sorted(CASES), ids=lambda c: "%s-fp64levels%d" % c)
 def headline(request, rho):
-    return request.param, solve(rho, L, P, "S1", precision=request.param)["phi"]
+    prec, f64 = request.param
+    return request.param, solve(rho, L, P, "S1", precision=prec, fp64_levels=f64)["phi"]
 
 
 def test_headline_sampled_vs_reference_fmm(headline, reference):
-    prec, gpu = headline
+    case, gpu = headline
     tg, ref, _ = reference
     got = gpu[tg[:, 0], tg[:, 1], tg[:, 2]]
     scale = np.max(np.abs(gpu))
-    e = np.max(np.abs(got - ref)) / scale
-    print("256^3", prec, "sampled vs reference FMM: max err / max|phi| =", e)
-    assert e < SAMPLED_TOL[prec]
+    err = np.abs(got - ref) / scale
+    face = ((tg % S == 0) | (tg % S == S - 1)).any(axis=1)
+    print("256^3", case, "sampled vs reference FMM: max err / max|phi| = %.3e "
+          "(cells on a leaf face %.3e, others %.3e)" % (err.max(), err[face].max(), err[~face].max()))
+    assert err.max() < CASES[case]
 
 
 def test_headline_vs_pm_same_green(headline, reference):
-    prec, gpu = headline
+    case, gpu = headline
     pm = reference[2]
     a = gpu - gpu.mean()
     b = pm - pm.mean()
     l2 = np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2))
     lmax = np.max(np.abs(a - b)) / np.max(np.abs(b))
-    print("256^3", prec, "vs PM(G_S1): rel L2 =", l2, "rel Lmax =", lmax)
+    print("256^3", case, "vs PM(G_S1): rel L2 =", l2, "rel Lmax =", lmax)
     assert l2 <= 1e-4 and lmax <= 1e-3
