@@ -83,7 +83,9 @@ def cpu_baseline(rho64, phi_gpu, n_side=20):
     dt = time.perf_counter() - t0
     got = phi_gpu[tg[:, 0], tg[:, 1], tg[:, 2]]
     sampled = float(np.max(np.abs(got - ref)) / np.max(np.abs(phi_gpu)))
+    t1 = time.perf_counter()
     pm = conv.pm(rho64, GREEN)
+    pm_s = time.perf_counter() - t1
     a = phi_gpu - phi_gpu.mean()
     b = pm - pm.mean()
     acc = {
@@ -95,7 +97,17 @@ def cpu_baseline(rho64, phi_gpu, n_side=20):
             "sample": "reference FMM (oracle/fmm.py, FP64 NumPy) at %d cells (%d^3 lattice) of "
                       "the same 256^3 field, including its full upward pass and coarse levels; "
                       "%.1f s" % (len(tg), n_side, dt)}
-    return base, acc
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    context = {"pm_fft_s": pm_s, "pm_cells_per_s": N ** 3 / pm_s,
+               "pm_note": "PM with the same G (the FP64 FFT convolution the FMM approximates), "
+                          "NumPy FFT on the host, table included",
+               "cpu_model": cpu_model, "os_cpu_count": os.cpu_count()}
+    return base, acc, context
 
 
 def copy_reference():
@@ -332,9 +344,11 @@ def main():
         "stages_ms": {k: v[0] for k, v in stages.items()},
     }
     if not args.no_cpu_baseline:
-        base, acc = cpu_baseline(rho32.astype(np.float64), phi.cpu().numpy().astype(np.float64))
+        base, acc, context = cpu_baseline(rho32.astype(np.float64),
+                                          phi.cpu().numpy().astype(np.float64))
         out["cpu_baseline"] = base
         out["accuracy"] = acc
+        out["cpu_context"] = context
     print(json.dumps(out), flush=True)
 
 
