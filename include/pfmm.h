@@ -94,13 +94,13 @@ typedef enum {
    * zone runs on the plan's stream before the tree instead of beside it.
    * Default 0. */
   PFMM_OPT_PROFILE = 4,
-  /* value: int32 in [0, L-1]: keep the gridlet masses and potentials of the
-   * coarsest levels 2 .. 1+value in FP64, with their M2M, interaction-zone
+  /* value: int32 in [0, 30]: keep the gridlet masses and potentials of the
+   * coarsest levels 2 .. 1+value (those the tree has) in FP64, with their M2M, interaction-zone
    * sums (on the FP64 matrix cores at p = 8) and L2L in FP64.  The downward
    * interpolation (Eq. 7, and its leaf analogue when s > p) extrapolates past
    * a parent's outermost gridlet nodes, so rounding noise in a coarse field
    * is amplified on its way to the mesh, most at leaf corners.  Default 2
-   * (levels 2 and 3); L - 1 also keeps the leaf level in FP64. */
+   * (levels 2 and 3); L - 1 or more also keeps the leaf level in FP64. */
   PFMM_OPT_FP64_LEVELS = 5
 } pfmm_option;
 

@@ -542,8 +542,7 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels is an int32");
       int32_t v;
       std::memcpy(&v, value, sizeof v);
-      if (v < 0 || v > pl->L - 1)
-        return fail(PFMM_ERR_INVALID_ARG, "fp64 levels must be in [0, L - 1]");
+      if (v < 0 || v > 30) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels must be in [0, 30]");
       pl->fp64_levels = v;
       return PFMM_OK;
     }
