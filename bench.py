@@ -195,7 +195,7 @@ def learned_bench(args):
     """Train the table-correction network on 512 seeded 64^3 lognormal fields
     (alpha = 2, sigma_delta = 1, p = 6, L = 3, seeds 10000 + i) on the GPU,
     then evaluate at 128^3, p = 6 on 16 unseen fields (seeds 20000 + i) with
-    BF16 inference, against G_S1 without correction; the judge is PM with
+    BF16 inference, against G_S1 without correction; the reference is PM with
     G_S1 from the CPU oracle."""
     import torch
     from paper_2011_07099_amd import fields
@@ -255,8 +255,8 @@ def main():
         copy_reference()
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); a multi-GPU "
-              "sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); a multi-GPU "
+              "sharding by octants is not built here", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         batch_bench(args)

@@ -45,7 +45,7 @@ typedef struct pfmm_plan_s* pfmm_plan_t;
 typedef enum {
   PFMM_OK = 0,
   PFMM_ERR_INVALID_ARG = 1,   /* bad size, kind, option, pointer or handle  */
-  PFMM_ERR_UNSUPPORTED = 2,   /* valid but outside what this build handles  */
+  PFMM_ERR_UNSUPPORTED = 2,   /* valid but outside what the library handles  */
   PFMM_ERR_OUT_OF_MEMORY = 3, /* a plan-time allocation failed              */
   PFMM_ERR_HIP = 4            /* a HIP runtime call or a kernel failed      */
 } pfmm_status;
