@@ -8,13 +8,15 @@ Contents (each function cites the passage of Gnedin, "Natively Periodic Fast
 Multipole Method: Approximating the Optimal Green's Function", that it follows):
 
 * ``green``  — the periodic Green's functions G_X (Eq. 2), G_K (Eq. 1),
-  G_S / G_S1 (Sec. 3 ansatz, Eq. 9) and the self-cell value.
+  G_S / G_S1 (Sec. 3 ansatz, Eq. 9), the free-space G_0 of the non-periodic
+  twin (Eq. 3) and the self-cell value.
 * ``conv``   — the exact result the FMM approximates: the periodic convolution
   of the density with G (Eq. 4, "PM with G"), computed three independent ways
-  (pairwise brute force, lattice-table direct sum, FFT), and PM with G_K.
+  (pairwise brute force, lattice-table direct sum, FFT), PM with G_K, and
+  the isolated (non-periodic, zero-padded) convolution with G_0.
 * ``fmm``    — a step-by-step FP64 reference of the method (Sec. 2, Eqs. 5-7):
   gridlet anterpolation (P2M/M2M), interaction-zone M2L, interpolation
-  (L2L/L2P) and the 27-node near zone.
+  (L2L/L2P) and the 27-node near zone; also its non-periodic twin.
 * ``fd``     — periodic 4th-order finite-difference accelerations (Sec. 3).
 * ``mlp``    — FP64 network of the learned table correction (Sec. 3-4, G_*).
 

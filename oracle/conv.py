@@ -110,3 +110,40 @@ def pm_gk(rho):
 def pm(rho, kind, a=(-0.125,)):
     """PM with the chosen G (Eq. 4): FFT convolution with the lattice table."""
     return fft(rho, lattice_table(kind, rho.shape[0], a))
+
+
+# ---------------------------------------------------------------------------
+# the isolated (non-periodic) twin: Sec. 3, Eq. 3
+# ---------------------------------------------------------------------------
+
+def isolated(rho):
+    """Non-periodic convolution with the free-space G_0 over the box only,
+    Phi_i = h^3 sum_j G_0(x_i - x_j) rho_j (self value at i = j): the
+    "non-periodic PM" of Eq. 3, by the convolution theorem on the zero-padded
+    2N grid (separations -(N-1)..N-1 fit without wrap)."""
+    rho = np.asarray(rho, np.float64)
+    N = rho.shape[0]
+    h = 1.0 / N
+    j = np.arange(2 * N)
+    js = np.where(j < N, j, j - 2 * N) * h
+    g = _g.green_product_grid("N", N, js, js, js, h_self=h)
+    g[N, :, :] = 0.0  # separation N never occurs; keep the table finite
+    g[:, N, :] = 0.0
+    g[:, :, N] = 0.0
+    pad = np.zeros((2 * N,) * 3)
+    pad[:N, :N, :N] = rho
+    out = np.real(np.fft.ifftn(np.fft.fftn(g) * np.fft.fftn(pad)))[:N, :N, :N]
+    return out * h ** 3
+
+
+def isolated_brute(rho):
+    """The same sum with G_0 evaluated from its formula for every pair (small
+    boxes only)."""
+    rho = np.asarray(rho, np.float64)
+    N = rho.shape[0]
+    h = 1.0 / N
+    x = (np.indices((N, N, N)).reshape(3, -1).T + 0.5) * h
+    d = x[:, None, :] - x[None, :, :]
+    g = _g.green_newton(d)
+    np.fill_diagonal(g, _g.self_value(h))
+    return (h ** 3 * (g @ rho.ravel())).reshape(N, N, N)

@@ -115,6 +115,14 @@ def level2_offsets():
     return [d for d in itertools.product(range(-2, 2), repeat=3) if max(abs(v) for v in d) > 1]
 
 
+def level2_offsets_isolated():
+    """Level-2 interaction zone of the isolated (non-periodic) twin: every node
+    of the 4^3 level that is not a neighbour of the target, as d = u - t in
+    [-3, 3]^3 with |d|_inf >= 2 (316 offsets; for a given target only those
+    with u inside the box exist)."""
+    return [d for d in itertools.product(range(-3, 4), repeat=3) if max(abs(v) for v in d) > 1]
+
+
 # ---------------------------------------------------------------------------
 # Green's function samples
 # ---------------------------------------------------------------------------
@@ -160,8 +168,12 @@ def _toeplitz_block(tab, J, q, d):
 # ---------------------------------------------------------------------------
 
 def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
-        m2l_tables=None):
+        m2l_tables=None, periodic=True):
     """Natively periodic FMM potential of the density ``rho`` (N^3, FP64).
+
+    With ``periodic=False``: the non-periodic twin of Sec. 3 (Eq. 3), the same
+    tree, gridlets and operators with the free-space G_0 (``kind`` ignored)
+    and no periodic images; every zone keeps only source nodes inside the box.
 
     Returns Phi on the full grid, or at the (T, 3) integer ``targets`` cells.
     With ``stages=True`` also returns a dict of intermediates:
@@ -200,7 +212,7 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
         if m2l_tables is not None and l in m2l_tables:
             tab, J = m2l_tables[l]
         else:
-            tab, J = m2l_table(kind, N, l, p, a)
+            tab, J = m2l_table(kind if periodic else "N", N, l, p, a)
         Ml = M[l].reshape(n, n, n, p ** 3)
         out = np.zeros((n, n, n, p ** 3))
         # target nodes, grouped by parity class (the interaction zone depends on
@@ -210,7 +222,7 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
         if targets is not None and l == L:
             allb = np.unique(np.asarray(targets, np.int64).reshape(-1, 3) // s, axis=0)
         if l == 2:
-            groups = {(0, 0, 0): (allb, level2_offsets())}
+            groups = {(0, 0, 0): (allb, level2_offsets() if periodic else level2_offsets_isolated())}
         else:
             groups = {}
             for c in itertools.product((0, 1), repeat=3):
@@ -226,7 +238,14 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
             for tb in tbs:
                 if len(tb) == 0:
                     continue
-                sb = (tb + np.asarray(d)) % n
+                sb = tb + np.asarray(d)
+                if periodic:
+                    sb = sb % n
+                else:  # sources outside the box are absent
+                    keep = np.all((sb >= 0) & (sb < n), axis=1)
+                    tb, sb = tb[keep], sb[keep]
+                    if len(tb) == 0:
+                        continue
                 src = Ml[sb[:, 0], sb[:, 1], sb[:, 2]]
                 out[tb[:, 0], tb[:, 1], tb[:, 2]] += src @ K.T
         out = out.reshape(n, n, n, p, p, p)
@@ -239,16 +258,21 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
         Phi[l] = out
 
     # ---- downward to cells: L2P (transpose of P2M) and the near zone ----
-    ntab, NJ = near_table(kind, N, s, a)
+    ntab, NJ = near_table(kind if periodic else "N", N, s, a)
     if targets is None:
         far = apply3T(A, Phi[L])                        # [b..., c...]
         near = np.zeros((nL, nL, nL, s ** 3))
         mflat = mb.reshape(nL, nL, nL, s ** 3)
+        if not periodic:  # a layer of empty leaves around the box
+            mflat = np.pad(mflat, ((1, 1), (1, 1), (1, 1), (0, 0)))
         bi = np.arange(nL)
         for e in near_offsets():
             K = _toeplitz_block(ntab, NJ, s, e)
-            src = mflat[((bi + e[0]) % nL)[:, None, None], ((bi + e[1]) % nL)[None, :, None],
-                        ((bi + e[2]) % nL)[None, None, :]]
+            if periodic:
+                ix, iy, iz = (bi + e[0]) % nL, (bi + e[1]) % nL, (bi + e[2]) % nL
+            else:
+                ix, iy, iz = bi + e[0] + 1, bi + e[1] + 1, bi + e[2] + 1
+            src = mflat[ix[:, None, None], iy[None, :, None], iz[None, None, :]]
             near += src @ K.T
         near = near.reshape(nL, nL, nL, s, s, s)
         phi_blk = far + near
@@ -266,8 +290,10 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
     near = np.zeros(len(tg))
     r = np.arange(s)
     for e in near_offsets():
-        sb = (b + np.asarray(e)) % nL
-        src = mb[sb[:, 0], sb[:, 1], sb[:, 2]]                   # (T, s, s, s)
+        sb = b + np.asarray(e)
+        inside = np.all((sb >= 0) & (sb < nL), axis=1) if not periodic else np.ones(len(sb), bool)
+        sb = sb % nL
+        src = mb[sb[:, 0], sb[:, 1], sb[:, 2]] * inside[:, None, None, None]  # (T, s, s, s)
         jx = c[:, 0, None] - r[None, :] - s * e[0] + NJ
         jy = c[:, 1, None] - r[None, :] - s * e[1] + NJ
         jz = c[:, 2, None] - r[None, :] - s * e[2] + NJ

@@ -141,6 +141,16 @@ def gk_series(N, cx, cy, cz, Lbox=1.0):
 GREEN_KINDS = ("X", "K", "S1", "S")
 
 
+def green_newton(x):
+    """Free-space G_0(x) = -1/(4 pi |x|), no periodic images: the Green's
+    function of the non-periodic twin used to separate the multipole-expansion
+    error from the Green's-function error (Sec. 3, Eq. 3).  Undefined at 0."""
+    x = np.asarray(x, dtype=np.float64)
+    r = np.sqrt(np.sum(x * x, axis=-1))
+    with np.errstate(divide="ignore"):
+        return -1.0 / (FOUR_PI * r)
+
+
 def green_product_grid(kind, N, cx, cy, cz, a=(-0.125,), h_self=None):
     """G of kind ``kind`` on the product grid of separation coordinates
     cx x cy x cz (box units, L = 1).  Points with x = 0 exactly get the self-cell
@@ -154,6 +164,8 @@ def green_product_grid(kind, N, cx, cy, cz, a=(-0.125,), h_self=None):
     X = np.stack(np.meshgrid(cx, cy, cz, indexing="ij"), axis=-1)
     if kind == "X":
         g = green_x(X)
+    elif kind == "N":
+        g = green_newton(X)
     elif kind == "S1":
         g = green_s1(X)
     elif kind == "S":
