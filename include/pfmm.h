@@ -101,7 +101,18 @@ typedef enum {
    * a parent's outermost gridlet nodes, so rounding noise in a coarse field
    * is amplified on its way to the mesh, most at leaf corners.  Default 2
    * (levels 2 and 3); L - 1 or more also keeps the leaf level in FP64. */
-  PFMM_OPT_FP64_LEVELS = 5
+  PFMM_OPT_FP64_LEVELS = 5,
+  /* value: int32 0 or 1.  1 makes the plan the non-periodic twin used to
+   * separate the multipole-expansion error from the Green's-function error
+   * (Sec. 3, Eq. 3): the free-space G_0(x) = -1/(4 pi |x|) with no periodic
+   * images in every table, and every zone (level-2 zone: all non-neighbour
+   * nodes of the 4^3 level, offsets in [-3, 3]^3 \ [-1, 1]^3) keeps only
+   * source nodes inside the box.  Needs PFMM_GREEN_X and a plan without
+   * learned tables; re-tabulates (plan time).  Isolated plans are not
+   * accepted by batches, the learned-table calls or pfmm_plan_direct, and
+   * the FD4 accelerations of a solve use the periodic stencil (the two
+   * outermost cell layers of each face are not meaningful).  Default 0. */
+  PFMM_OPT_ISOLATED = 6
 } pfmm_option;
 
 /* Stages reported by pfmm_plan_stage_times (durations summed over levels). */

@@ -13,7 +13,7 @@ namespace pfmm {
 // ---------------------------------------------------------------------------
 // Green's function tabulation (FP64, plan time)
 // ---------------------------------------------------------------------------
-enum GreenKind { GK_X = 0, GK_K = 1, GK_S1 = 2, GK_S = 3 };
+enum GreenKind { GK_X = 0, GK_K = 1, GK_S1 = 2, GK_S = 3, GK_N = 4 /* free space, no wrap */ };
 
 // Tabulate G(eta * j) for j in [-C, C]^3 into dst[(2C+1)^3] (FP64, C order),
 // eta = 1 / den.  `self_h` > 0 gives the value at j = 0 for the real-space
@@ -48,6 +48,7 @@ struct ToepArgs {
   int fp64;         // 0: FP32 tab/X/Y, 1: FP64 tab/X/Y
   int groups;       // >1: offsets split over workgroups writing `partial`
   void* partial;    // [groups][n^3][q^3] (block layout only), summed in order
+  int isolated;     // 1: no periodic images, sources outside [0, n)^3 are zero
 };
 
 // Workgroups of one launch of the portable kernel (before offset groups).
@@ -78,7 +79,11 @@ struct ToepMfmaArgs {
   int accumulate;
   int groups;
   float* partial;
+  int isolated;          // 1: sources outside the box are zero (read from `zero`)
+  const uint16_t* zero;  // >= 512 zero bf16 values (isolated only)
 };
+// Most offsets per class the split kernel stages (the near zone at m = 2).
+constexpr int kSplitMaxOffs = 216;
 bool toep8_supported(int n, int m);
 size_t window_dwords(int nt);
 hipError_t make_windows(const double* tab64, int C, int nt, uint32_t* win, hipStream_t st);
@@ -99,6 +104,7 @@ struct ToepF64Args {
   int accumulate;
   int groups;
   double* partial;  // [groups][n^3][512] when groups > 1
+  int isolated;     // 1: sources outside the box are zero
 };
 int toep8_f64_tiles(int n, int m);
 hipError_t launch_toep8_f64(const ToepF64Args& a, hipStream_t st);

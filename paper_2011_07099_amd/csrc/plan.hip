@@ -51,7 +51,10 @@ struct pfmm_plan_s {
   std::vector<float*> tab32;
   double* ntab64 = nullptr;       // near, (4s-1)^3
   float* ntab32 = nullptr;
-  int* offs_l2 = nullptr;         // [37]
+  int* offs_l2 = nullptr;         // [37] periodic, [316] isolated (capacity 316)
+  int nl2 = 37;                   // level-2 offsets in use
+  int isolated = 0;               // no periodic images (PFMM_OPT_ISOLATED)
+  uint16_t* zero = nullptr;       // 512 zero bf16 values: the source outside an isolated box
   int* offs_iz = nullptr;         // [8][189]
   int* offs_near = nullptr;       // [mn^3][(3 mn)^3]
   // split-precision matrix-core path (8^3 blocks)
@@ -196,14 +199,14 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
   const int C = 4 * p - 1;
   const int64_t nlev = cube(2 * C + 1);
   for (int l = 2; l <= pl->L; ++l) {
-    hipError_t e = tabulate_green(pl->green, pl->a1, pl->N, C, (int64_t(1) << l) * p, 0.0,
-                                  pl->tab64[l], pl->stream);
+    hipError_t e = tabulate_green(pl->isolated ? GK_N : pl->green, pl->a1, pl->N, C,
+                                  (int64_t(1) << l) * p, 0.0, pl->tab64[l], pl->stream);
     if (e == hipSuccess) e = cast_f64_f32(pl->tab64[l], pl->tab32[l], nlev, pl->stream);
     if (e != hipSuccess) return hip_fail(e, "tabulate level table");
   }
   const int Cn = 2 * pl->s - 1;
-  hipError_t e = tabulate_green(pl->green, pl->a1, pl->N, Cn, pl->N, 1.0 / pl->N, pl->ntab64,
-                                pl->stream);
+  hipError_t e = tabulate_green(pl->isolated ? GK_N : pl->green, pl->a1, pl->N, Cn, pl->N,
+                                1.0 / pl->N, pl->ntab64, pl->stream);
   if (e == hipSuccess) e = cast_f64_f32(pl->ntab64, pl->ntab32, cube(2 * Cn + 1), pl->stream);
   for (int l = 2; l <= pl->L && e == hipSuccess; ++l)
     if (pl->win[l]) e = make_windows(pl->tab64[l], C, kM2LTerms, pl->win[l], pl->stream);
@@ -388,7 +391,7 @@ pfmm_status build(pfmm_plan_s* pl) {
     // coarse levels), block layout only
     size_t bytes = 0;
     for (int l = 2; l <= L; ++l) {
-      const int n = 1 << l, m = l == 2 ? 1 : 2, noff = l == 2 ? 37 : 189;
+      const int n = 1 << l, m = l == 2 ? 1 : 2, noff = l == 2 ? 316 : 189;  // 316: isolated level 2
       for (int f64 = 0; f64 <= 1; ++f64) {  // the FP64 level count is an option
         int G = scalar_groups(p, f64, n, m, noff);
         if (f64 && p == 8) G = std::max(G, f64_groups(n, m, noff));
@@ -433,7 +436,9 @@ pfmm_status build(pfmm_plan_s* pl) {
   }
   if (l2.size() != 37 || iz.size() != 8 * 189 || nz.size() != (size_t)cube(3 * mn) * cube(mn))
     return fail(PFMM_ERR_HIP, "internal: zone sizes");
-  e = dalloc(pl, &pl->offs_l2, l2.size());
+  e = dalloc(pl, &pl->offs_l2, (size_t)316);
+  if (e == hipSuccess) e = dalloc(pl, &pl->zero, (size_t)512);
+  if (e == hipSuccess) e = hipMemset(pl->zero, 0, 512 * sizeof(uint16_t));
   if (e == hipSuccess) e = dalloc(pl, &pl->offs_iz, iz.size());
   if (e == hipSuccess) e = dalloc(pl, &pl->offs_near, nz.size());
   if ((st = chk("zone lists"))) return st;
@@ -520,6 +525,30 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       std::memcpy(&pl->stream, value, sizeof(hipStream_t));
       return PFMM_OK;
     }
+    case PFMM_OPT_ISOLATED: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "isolated is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      if (v != 0 && v != 1) return fail(PFMM_ERR_INVALID_ARG, "isolated must be 0 or 1");
+      if (v && pl->green != PFMM_GREEN_X)
+        return fail(PFMM_ERR_UNSUPPORTED, "the isolated twin uses G_X without images: PFMM_GREEN_X");
+      if (!pl->g0.empty()) return fail(PFMM_ERR_UNSUPPORTED, "plan has learned tables");
+      // level-2 zone: 37 periodic representatives, or every non-neighbour
+      // node of the 4^3 level, d in [-3, 3]^3 \ [-1, 1]^3 (316)
+      std::vector<int> l2;
+      const int lo = v ? -3 : -2, hi = v ? 3 : 1;
+      for (int dx = lo; dx <= hi; ++dx)
+        for (int dy = lo; dy <= hi; ++dy)
+          for (int dz = lo; dz <= hi; ++dz)
+            if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) > 1)
+              l2.push_back(pack_offset(dx, dy, dz));
+      if (l2.size() != (v ? 316u : 37u)) return fail(PFMM_ERR_HIP, "internal: level-2 zone size");
+      hipError_t e = hipMemcpy(pl->offs_l2, l2.data(), l2.size() * sizeof(int), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "level-2 zone");
+      pl->isolated = v;
+      pl->nl2 = (int)l2.size();
+      return tabulate_all(pl);
+    }
     case PFMM_OPT_GS_A1: {
       if (bytes != sizeof(double)) return fail(PFMM_ERR_INVALID_ARG, "a1 is a double");
       if (pl->green != PFMM_GREEN_S) return fail(PFMM_ERR_INVALID_ARG, "a1 needs PFMM_GREEN_S");
@@ -604,11 +633,12 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
       fa.Y = (double*)ta.Y;
       fa.accumulate = ta.accumulate;
       fa.groups = f64_groups(ta.n, ta.m, ta.noff);
+      fa.isolated = ta.isolated;
       fa.partial = fa.groups > 1 ? (double*)pl->spart : nullptr;
       if (fa.groups > 1 && !fa.partial) fa.groups = 1;
       return launch_toep8_f64(fa, st);
     }
-    if (!mx || ta.fp64 || !pl->win[l]) {
+    if (!mx || ta.fp64 || !pl->win[l] || ta.noff > kSplitMaxOffs) {
       ta.groups = scalar_groups(ta.q, ta.fp64, ta.n, ta.m, ta.noff);
       ta.partial = ta.groups > 1 ? pl->spart : nullptr;
       if (ta.groups > 1 && !ta.partial) ta.groups = 1;
@@ -627,6 +657,8 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     ma.Y = (float*)ta.Y;
     ma.accumulate = ta.accumulate;
     ma.groups = std::min(m2l_groups(l), ta.noff);
+    ma.isolated = ta.isolated;
+    ma.zero = pl->zero;
     ma.partial = ma.groups > 1 ? pl->part : nullptr;
     return launch_toep8_split(ma, kM2LTerms, st);
   };
@@ -655,6 +687,7 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   nb.xscale = 1.0 / ((double)N * N * N);
   nb.accumulate = 0;
   nb.groups = 1;
+  nb.isolated = pl->isolated;
   if (mx && pl->nwin) {
     e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xsn, sn);
     if (e == hipSuccess) {
@@ -669,6 +702,8 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
       ma.grid_out = 1;
       ma.accumulate = 0;
       ma.groups = 1;
+      ma.isolated = pl->isolated;
+      ma.zero = pl->zero;
       e = launch_toep8_split(ma, kNearTerms, sn);
     }
   } else {
@@ -694,8 +729,9 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   a.xscale = 1.0;
   a.n = 4;
   a.m = 1;
-  a.noff = 37;
+  a.noff = pl->nl2;
   a.offs = pl->offs_l2;
+  a.isolated = pl->isolated;
   a.fp64 = is64(2);
   a.tab = a.fp64 ? (const void*)pl->tab64[2] : (const void*)pl->tab32[2];
   a.X = pl->M[2];
@@ -1179,6 +1215,10 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
       delete b;
       return fail(PFMM_ERR_UNSUPPORTED, "batches need p <= 8");
     }
+    if (plans[i]->isolated) {
+      delete b;
+      return fail(PFMM_ERR_UNSUPPORTED, "batches of isolated plans");
+    }
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) {
         delete b;
@@ -1512,6 +1552,7 @@ extern "C" {
 pfmm_status pfmm_plan_direct(pfmm_plan_t pl, const float* rho, float* phi) {
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "direct solve of an isolated plan");
   if (!rho || !phi || (const void*)rho == (const void*)phi)
     return fail(PFMM_ERR_INVALID_ARG, "density and potential must be distinct device arrays");
   pfmm_status s0 = direct_prepare(pl);
@@ -1539,6 +1580,7 @@ pfmm_status pfmm_plan_direct(pfmm_plan_t pl, const float* rho, float* phi) {
 pfmm_status pfmm_learned_set(pfmm_plan_t pl, const float* weights, int bf16) {
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
   if (!weights) {
     if (pl->g0.empty()) return PFMM_OK;  // never corrected
     pl->learned = 0;
@@ -1555,6 +1597,7 @@ pfmm_status pfmm_learned_set(pfmm_plan_t pl, const float* weights, int bf16) {
 pfmm_status pfmm_learned_train_begin(pfmm_plan_t pl, const float* weights, double lr) {
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
   if (!weights || !(lr > 0.0)) return fail(PFMM_ERR_INVALID_ARG, "need weights and lr > 0");
   pfmm_status s0 = learned_prepare(pl);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
@@ -1616,6 +1659,7 @@ pfmm_status pfmm_learned_loss(pfmm_plan_t pl, const float* rho, const float* tar
                               double* loss) {
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
   if (!rho || !target || !loss) return fail(PFMM_ERR_INVALID_ARG, "NULL argument");
   pfmm_status s0 = learned_prepare(pl);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);

@@ -5,6 +5,7 @@
 //   G_S  (Sec. 3 ansatz, n = 1): G_X of x_hat_i = xi(x_i),
 //        xi(t) = sin(pi t)/pi + a1 (sin(3 pi t)/(3 pi) - sin(pi t)/pi)
 //   G_S1 (Eq. 9):  x_hat = 9/(8 pi) sin(pi x) - 1/(24 pi) sin(3 pi x)
+//   G_0  (the non-periodic twin of Eq. 3): -1 / (4 pi |x|), no wrap
 // The zero separation takes the potential at the centre of a uniform cube
 // cell of side h: -c0/(4 pi h), c0 = 3 ln((sqrt3+1)/(sqrt3-1)) - pi/2.
 //
@@ -59,7 +60,9 @@ __global__ void tab_real_space(int kind, double a1, int C, int64_t den, double s
   } else if (kind == GK_S) {
     x = xi_s(x, a1); y = xi_s(y, a1); z = xi_s(z, a1);
   }
-  x -= rint(x); y -= rint(y); z -= rint(z);
+  if (kind != GK_N) {
+    x -= rint(x); y -= rint(y); z -= rint(z);
+  }
   dst[i] = -1.0 / (4.0 * kPi * sqrt(x * x + y * y + z * z));
 }
 

@@ -85,11 +85,12 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
       const int tl = i / Q3, e = i % Q3;
       const int t = t0 + tl;
       T v = 0;
-      if (t < ntarg) {
-        const int kx = t / (nk * nk), ky = (t / nk) % nk, kz = t % nk;
-        const int ux = (cx + m * kx + dx) & nmask;
-        const int uy = (cy + m * ky + dy) & nmask;
-        const int uz = (cz + m * kz + dz) & nmask;
+      const int kx = t / (nk * nk), ky = (t / nk) % nk, kz = t % nk;
+      const int ux0 = cx + m * kx + dx, uy0 = cy + m * ky + dy, uz0 = cz + m * kz + dz;
+      const bool inside = !a.isolated || ((unsigned)ux0 < (unsigned)a.n &&
+                                          (unsigned)uy0 < (unsigned)a.n && (unsigned)uz0 < (unsigned)a.n);
+      if (t < ntarg && inside) {
+        const int ux = ux0 & nmask, uy = uy0 & nmask, uz = uz0 & nmask;
         size_t src;
         if (a.grid_in) {
           const int ex = e / (Q * Q), ey = (e / Q) % Q, ez = e % Q;

@@ -36,7 +36,6 @@ constexpr int kThreads = 256;
 constexpr int kWinPairs = 15 * 15 * 14;   // packed pairs per window term
 constexpr int kWinPart = 3152;            // dwords per window term (padded to 16 B)
 constexpr int kTN = 64;                   // targets per workgroup
-constexpr int kMaxOffs = 216;             // offsets per class (the near zone at m = 2)
 
 __device__ inline uint16_t bf16_bits(float x) {
   __bf16 b = (__bf16)x;
@@ -169,7 +168,7 @@ struct SplitCfg {
   __shared__ __attribute__((aligned(16))) uint32_t Aw1[SplitCfg<NT>::AW];              \
   __shared__ __attribute__((aligned(16))) uint16_t Bs0[NT][kTN][SplitCfg<NT>::KCH];    \
   __shared__ __attribute__((aligned(16))) uint16_t Bs1[NT][kTN][SplitCfg<NT>::KCH];    \
-  __shared__ int Os[kMaxOffs]; /* the class's offsets (read by every copy) */
+  __shared__ int Os[kSplitMaxOffs]; /* the class's offsets (read by every copy) */
 
 // One workgroup's share of the operator: 512 outputs x 64 targets (tile
 // `lin` = class * tiles + tile) over offset group g.  Ends with a barrier, so
@@ -227,12 +226,15 @@ __device__ __forceinline__ void split_tile(const ToepMfmaArgs& a, int lin, int g
     unpack_offset(Os[k], dx, dy, dz);
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-      const int ux = (st[i].tx + dx) & nmask, uy = (st[i].ty + dy) & nmask, uz = (st[i].tz + dz) & nmask;
+      const int ux0 = st[i].tx + dx, uy0 = st[i].ty + dy, uz0 = st[i].tz + dz;
+      const bool inside = !a.isolated || ((unsigned)ux0 < (unsigned)a.n &&
+                                          (unsigned)uy0 < (unsigned)a.n && (unsigned)uz0 < (unsigned)a.n);
+      const int ux = ux0 & nmask, uy = uy0 & nmask, uz = uz0 & nmask;
       const uint16_t* src = a.X + (((size_t)ux * a.n + uy) * a.n + uz) * 512 + KCH * c + 8 * seg[i];
 #pragma unroll
-      for (int q = 0; q < NT; ++q)
-        __builtin_amdgcn_global_load_lds((gptr)(src + q * nterm), (lptr)&dst[q][16 * w + RPI * i][0],
-                                         16, 0, 0);
+      for (int q = 0; q < NT; ++q)  // a source outside an isolated box is the zero block
+        __builtin_amdgcn_global_load_lds((gptr)(inside ? src + q * nterm : a.zero + 8 * seg[i]),
+                                         (lptr)&dst[q][16 * w + RPI * i][0], 16, 0, 0);
     }
   };
 
@@ -479,17 +481,22 @@ __device__ __forceinline__ void f64_tile(const ToepF64Args& a, int blk, int g, d
       const double* W = &Wd[(k - ob) & 1][0];
       const int pk = offs[k];
       const int dx = ((pk >> 16) & 255) - 128, dy = ((pk >> 8) & 255) - 128, dz = (pk & 255) - 128;
-      const int ux = (tx + dx) & nmask, uy = (ty + dy) & nmask, uz = (tz + dz) & nmask;
+      const int ux0 = tx + dx, uy0 = ty + dy, uz0 = tz + dz;
+      // a source outside an isolated box contributes nothing
+      const bool use = tvalid && (!a.isolated || ((unsigned)ux0 < (unsigned)a.n &&
+                                                  (unsigned)uy0 < (unsigned)a.n &&
+                                                  (unsigned)uz0 < (unsigned)a.n));
+      const int ux = ux0 & nmask, uy = uy0 & nmask, uz = uz0 & nmask;
       const double* X = a.X + (((size_t)ux * a.n + uy) * a.n + uz) * 512;
       const bool has_next = k + 1 < oe;
       if (has_next) load_W(k + 1);
       double b[8], bn[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) b[u] = tvalid ? X[4 * u + kq] : 0.0;
+      for (int u = 0; u < 8; ++u) b[u] = use ? X[4 * u + kq] : 0.0;
       for (int blk = 0; blk < 16; ++blk) {  // 16 blocks of 8 k-steps
         if (blk + 1 < 16) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) bn[u] = tvalid ? X[32 * (blk + 1) + 4 * u + kq] : 0.0;
+          for (int u = 0; u < 8; ++u) bn[u] = use ? X[32 * (blk + 1) + 4 * u + kq] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -653,7 +660,8 @@ hipError_t launch_batch_mma(int kind, const void* args, const MmaItem* items, in
 }
 
 hipError_t launch_toep8_split(const ToepMfmaArgs& a, int nt, hipStream_t st) {
-  if (!toep8_supported(a.n, a.m) || a.groups < 1 || nt < 2 || nt > 3 || a.noff > kMaxOffs)
+  if (!toep8_supported(a.n, a.m) || a.groups < 1 || nt < 2 || nt > 3 || a.noff > kSplitMaxOffs ||
+      (a.isolated && !a.zero))
     return hipErrorInvalidValue;
   const int nt4 = a.n / a.m / 4;
   const int nblk = nt4 * nt4 * nt4 * a.m * a.m * a.m;

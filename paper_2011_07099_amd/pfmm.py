@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libpfmm.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP = range(5)
 GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3}
 PREC = {"fp32": 0, "bf16x3": 1}
-OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS = 1, 2, 3, 4, 5
+OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED = 1, 2, 3, 4, 5, 6
 STAGES = ("p2m", "m2m", "m2l", "l2l", "l2p", "near", "fd4")
 BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
 
@@ -99,7 +99,7 @@ class Plan:
     """
 
     def __init__(self, N, L, p, green="S1", precision="fp32", a1=None, stream=None,
-                 fp64_levels=None):
+                 fp64_levels=None, isolated=False):
         import torch
         lib = load()
         h = ctypes.c_void_p()
@@ -118,6 +118,14 @@ class Plan:
             self.set_a1(a1)
         if fp64_levels is not None:
             self.set_fp64_levels(fp64_levels)
+        if isolated:
+            self.set_isolated(True)
+
+    def set_isolated(self, on):
+        """The non-periodic twin (G_X without images, sources outside the box
+        absent); PFMM_GREEN_X plans only."""
+        v = ctypes.c_int32(1 if on else 0)
+        _check(load().pfmm_plan_set(self._h, OPT_ISOLATED, ctypes.byref(v), 4))
 
     def set_fp64_levels(self, n):
         v = ctypes.c_int32(int(n))
