@@ -16,12 +16,16 @@ Multipole Method: Approximating the Optimal Green's Function", that it follows):
   the isolated (non-periodic, zero-padded) convolution with G_0.
 * ``fmm``    — a step-by-step FP64 reference of the method (Sec. 2, Eqs. 5-7):
   gridlet anterpolation (P2M/M2M), interaction-zone M2L, interpolation
-  (L2L/L2P) and the 27-node near zone; also its non-periodic twin.
+  (L2L/L2P) and the 27-node near zone; also its non-periodic twin and the
+  accelerations taken from the expansion (Sec. 3).
 * ``fd``     — periodic 4th-order finite-difference accelerations (Sec. 3).
+* ``metric`` — the Green's-function error Delta g of Eq. 3: PM accelerations
+  of point sources, the twin's translation, L2 / L_MAX norms.
+* ``fit``    — downhill simplex (Sec. 3) for fitting the G_S coefficients.
 * ``mlp``    — FP64 network of the learned table correction (Sec. 3-4, G_*).
 
 Parity status: every function is pinned by tests in ``tests/test_oracle_*``
 (closed forms, brute force, exact special cases, invariants), except where a
 function header says "parity unpinned".
 """
-from . import green, conv, fmm, fd, mlp  # noqa: F401
+from . import green, conv, fmm, fd, mlp, metric, fit  # noqa: F401

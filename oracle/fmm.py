@@ -67,6 +67,25 @@ def p2m_1d(p, s):
     return moment_matching_weights(p, v)
 
 
+def interpolant_derivative_weights(p, v):
+    """Derivative of the gridlet interpolation weights: D[a, c] = d/dv of the
+    weight of gridlet point a at v = v_c (gridlet units).
+
+    The weights of ``moment_matching_weights`` reproduce every power v^n,
+    n < p (sum_a W[a, c] t_a^n = v_c^n), so they are the values of the
+    degree p-1 Lagrange basis polynomials at v_c; differentiating the moment
+    conditions in v_c gives sum_a D[a, c] t_a^n = n v_c^(n-1), solved with the
+    same Vandermonde matrix.  This is the gradient of the local expansion that
+    L2P evaluates (Sec. 3: FMM accelerations come from the expansion)."""
+    t = gridlet_coords(p)
+    scale = max(0.5 * p, 1.0)
+    n = np.arange(p)
+    V = (t[None, :] / scale) ** n[:, None]
+    u = np.asarray(v, np.float64)[None, :] / scale
+    dS = n[:, None] * u ** np.maximum(n[:, None] - 1, 0) / scale
+    return np.linalg.solve(V, dS)
+
+
 def m2m_1d(p):
     """1D M2M operators T[o][a, a'] of Eq. 5 for child position o in {0, 1}
     along one axis.  The child centre sits at (o - 1/2) p/2 parent-gridlet units
@@ -150,6 +169,25 @@ def near_table(kind, N, s, a=(-0.125,)):
     return _green_grid(kind, N, coords, a, h), J
 
 
+def near_accel_tables(kind, N, s, a=(-0.125,)):
+    """Near-zone acceleration kernels D_i(h j), j in [-(2s-1), 2s-1]^3, i = x, y, z:
+    minus the 4th-order central difference of the lattice G along axis i,
+        D_i(j) = -(8 (G(j + e_i) - G(j - e_i)) - (G(j + 2 e_i) - G(j - 2 e_i))) / (12 h),
+    the acceleration of a unit cell mass that PM's differencing of the
+    potential produces (Sec. 3).  Built from G on [-(2s+1), 2s+1]^3 (self value
+    at 0).  Returned as ([D_x, D_y, D_z], J)."""
+    J = 2 * s - 1
+    h = 1.0 / N
+    Gw = _green_grid(kind, N, h * np.arange(-J - 2, J + 3), a, h)
+    out = []
+    for ax in range(3):
+        def sh(k):
+            return tuple(slice(2 + k, 2 + k + 2 * J + 1) if i == ax else slice(2, 2 * J + 3)
+                         for i in range(3))
+        out.append(-(8.0 * (Gw[sh(1)] - Gw[sh(-1)]) - (Gw[sh(2)] - Gw[sh(-2)])) / (12.0 * h))
+    return out, J
+
+
 def _toeplitz_block(tab, J, q, d):
     """Dense K[(x), (y)] = tab[x - y - q d + J] for node-local points x, y in
     [0, q)^3 (flattened z-fastest): the operator coupling a node to the node at
@@ -166,6 +204,28 @@ def _toeplitz_block(tab, J, q, d):
 # ---------------------------------------------------------------------------
 # the FMM
 # ---------------------------------------------------------------------------
+
+def _near_sum(tab, J, mb, periodic):
+    """Direct near-zone sum over the 27 neighbour leaves for every cell:
+    out[b, c] = sum_{e, c'} tab[c - c' - s e + J] mb[b + e, c'], leaves wrapped
+    periodically, or absent outside the box for the isolated twin.  ``mb`` are
+    the cell masses in leaf-block layout (nL, nL, nL, s, s, s)."""
+    nL, s = mb.shape[0], mb.shape[3]
+    out = np.zeros((nL, nL, nL, s ** 3))
+    mflat = mb.reshape(nL, nL, nL, s ** 3)
+    if not periodic:  # a layer of empty leaves around the box
+        mflat = np.pad(mflat, ((1, 1), (1, 1), (1, 1), (0, 0)))
+    bi = np.arange(nL)
+    for e in near_offsets():
+        K = _toeplitz_block(tab, J, s, e)
+        if periodic:
+            ix, iy, iz = (bi + e[0]) % nL, (bi + e[1]) % nL, (bi + e[2]) % nL
+        else:
+            ix, iy, iz = bi + e[0] + 1, bi + e[1] + 1, bi + e[2] + 1
+        src = mflat[ix[:, None, None], iy[None, :, None], iz[None, None, :]]
+        out += src @ K.T
+    return out.reshape(nL, nL, nL, s, s, s)
+
 
 def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
         m2l_tables=None, periodic=True):
@@ -261,20 +321,7 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
     ntab, NJ = near_table(kind if periodic else "N", N, s, a)
     if targets is None:
         far = apply3T(A, Phi[L])                        # [b..., c...]
-        near = np.zeros((nL, nL, nL, s ** 3))
-        mflat = mb.reshape(nL, nL, nL, s ** 3)
-        if not periodic:  # a layer of empty leaves around the box
-            mflat = np.pad(mflat, ((1, 1), (1, 1), (1, 1), (0, 0)))
-        bi = np.arange(nL)
-        for e in near_offsets():
-            K = _toeplitz_block(ntab, NJ, s, e)
-            if periodic:
-                ix, iy, iz = (bi + e[0]) % nL, (bi + e[1]) % nL, (bi + e[2]) % nL
-            else:
-                ix, iy, iz = bi + e[0] + 1, bi + e[1] + 1, bi + e[2] + 1
-            src = mflat[ix[:, None, None], iy[None, :, None], iz[None, None, :]]
-            near += src @ K.T
-        near = near.reshape(nL, nL, nL, s, s, s)
+        near = _near_sum(ntab, NJ, mb, periodic)
         phi_blk = far + near
         res = phi_blk.transpose(0, 3, 1, 4, 2, 5).reshape(N, N, N)
         if stages:
@@ -303,3 +350,39 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
     if stages:
         return res, dict(M=M, Phi=Phi, far=far, near=near)
     return res
+
+
+def fmm_accel(rho, L, p, kind="S1", a=(-0.125,), periodic=True):
+    """Accelerations g = -grad(Phi) of the FMM taken from the expansion
+    (Sec. 3: PM differences its potential, the FMM differentiates its
+    expansion).  Reading adopted for the two parts of a target's field:
+
+    * far part (interaction zones of every level, carried down by Eq. 7): the
+      analytic gradient of the leaf's local expansion, i.e. of the degree p-1
+      interpolant that L2P evaluates, at the cell centre;
+    * near part (27 leaves, direct): the direct sum with the kernels of
+      ``near_accel_tables``, so that, as for the potential, the near zone
+      carries no expansion error.
+
+    Returns (g, phi): g of shape (3, N, N, N) and the potential of ``fmm``.
+    ``periodic=False`` gives the non-periodic twin."""
+    rho = np.asarray(rho, np.float64)
+    N = rho.shape[0]
+    s = N >> L
+    nL = 2 ** L
+    h = 1.0 / N
+    phi, st = fmm(rho, L, p, kind, a, stages=True, periodic=periodic)
+    A = p2m_1d(p, s)
+    v = (np.arange(s, dtype=np.float64) + 0.5 - 0.5 * s) * (p / s)
+    Ad = interpolant_derivative_weights(p, v)
+    eta = 1.0 / (nL * p)                               # leaf gridlet spacing
+    mb = (rho * h ** 3).reshape(nL, s, nL, s, nL, s).transpose(0, 2, 4, 1, 3, 5)
+    D, J = near_accel_tables(kind if periodic else "N", N, s, a)
+    g = np.empty((3, N, N, N))
+    for ax in range(3):
+        ops = [Ad if i == ax else A for i in range(3)]
+        far = -np.einsum("ai,bj,ck,...abc->...ijk", ops[0], ops[1], ops[2], st["Phi"][L],
+                         optimize=True) / eta
+        tot = far + _near_sum(D[ax], J, mb, periodic)
+        g[ax] = tot.transpose(0, 3, 1, 4, 2, 5).reshape(N, N, N)
+    return g, phi
