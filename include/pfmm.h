@@ -62,8 +62,12 @@ typedef enum {
   /* Approximately optimal G_S1 (Eq. 9): G_X of the mapped separation
    * x_hat = (9/(8 pi)) sin(pi x) - (1/(24 pi)) sin(3 pi x), per component. */
   PFMM_GREEN_S1 = 2,
-  /* The one-parameter ansatz G_S of Sec. 3 with n = 1 and a free a_1
-   * (PFMM_OPT_GS_A1, default -1/8, which is G_S1). */
+  /* The ansatz G_S of Sec. 3 with free a_1 and a_2 (n <= 2):
+   * xi(t) = sin(pi t)/pi + a_1 (sin(3 pi t)/(3 pi) - sin(pi t)/pi)
+   *                      + a_2 (sin(5 pi t)/(5 pi) - sin(pi t)/pi),
+   * set by PFMM_OPT_GS_A1 (default -1/8) and PFMM_OPT_GS_A2 (default 0).
+   * The defaults give G_S1; a_1 = -25/128, a_2 = 3/128 give the variant whose
+   * map is t + O(t^7). */
   PFMM_GREEN_S = 3
 } pfmm_green;
 
@@ -112,8 +116,32 @@ typedef enum {
    * accepted by batches, the learned-table calls or pfmm_plan_direct, and
    * the FD4 accelerations of a solve use the periodic stencil (the two
    * outermost cell layers of each face are not meaningful).  Default 0. */
-  PFMM_OPT_ISOLATED = 6
+  PFMM_OPT_ISOLATED = 6,
+  /* value: double a_2 of the G_S ansatz (Sec. 3); only for PFMM_GREEN_S.
+   * Re-tabulates G synchronously. */
+  PFMM_OPT_GS_A2 = 7,
+  /* value: int32 pfmm_accel, how pfmm_solve forms `accel`.  Switching to
+   * PFMM_ACCEL_EXPANSION allocates and tabulates its near-zone kernels
+   * (plan time; re-tabulated with G).  Default PFMM_ACCEL_FD4. */
+  PFMM_OPT_ACCEL = 8
 } pfmm_option;
+
+/* How accelerations are formed (Sec. 3: PM differences its potential, the
+ * FMM takes them from its expansion). */
+typedef enum {
+  /* -grad(potential) by periodic 4th-order central differences of the mesh
+   * potential. */
+  PFMM_ACCEL_FD4 = 0,
+  /* From the expansion: the far part is minus the analytic gradient of each
+   * leaf's local expansion (the degree p-1 interpolant that L2P evaluates) at
+   * the cell centre; the near part is the direct sum over the 27 leaves of
+   * each source cell's acceleration as PM's 4th-order difference of the
+   * potential gives it, D_i(x) = -(8 (G(x + h e_i) - G(x - h e_i))
+   * - (G(x + 2h e_i) - G(x - 2h e_i))) / (12 h).  Three more near-zone
+   * contractions (on the near zone's stream) and one gradient interpolation
+   * per component. */
+  PFMM_ACCEL_EXPANSION = 1
+} pfmm_accel;
 
 /* Stages reported by pfmm_plan_stage_times (durations summed over levels). */
 typedef enum {
@@ -172,8 +200,9 @@ pfmm_status pfmm_plan_set(pfmm_plan_t plan, int option, const void* value, size_
  *   density    device, const float[N*N*N], C order (read only)
  *   potential  device, float[N*N*N], overwritten
  *   accel      device, float[3][N*N*N] (components x, y, z), overwritten with
- *              -grad(potential) by periodic 4th-order central differences
- *              (Sec. 3), or NULL to skip
+ *              the accelerations -grad(potential) formed as PFMM_OPT_ACCEL
+ *              selects (default: periodic 4th-order central differences of
+ *              the potential, Sec. 3), or NULL to skip
  *
  * Enqueues on the plan's stream; does not allocate and does not synchronise.
  * The near zone (which reads only the density) runs on a second stream owned

@@ -20,9 +20,14 @@ enum GreenKind { GK_X = 0, GK_K = 1, GK_S1 = 2, GK_S = 3, GK_N = 4 /* free space
 // kinds (potential at the centre of a uniform cube cell of side self_h);
 // self_h == 0 leaves 0 there.  `N` is the mesh size (G_K frequency range).
 // G_K allocates and frees its own temporaries and synchronises `st`.
-hipError_t tabulate_green(int kind, double a1, int N, int C, int64_t den, double self_h,
+hipError_t tabulate_green(int kind, double a1, double a2, int N, int C, int64_t den, double self_h,
                           double* dst, hipStream_t st);
 
+// Near-zone acceleration tables d[i][j] = -(4th-order central difference of the
+// lattice G along axis i at j) for j in [-C, C]^3, i = x, y, z (FP64, device).
+// Allocates and frees a temporary table; synchronises `st`.
+hipError_t tabulate_accel(int kind, double a1, double a2, int N, int C, double* d[3],
+                          hipStream_t st);
 // FP64 -> FP32 copy.
 hipError_t cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 
@@ -183,6 +188,11 @@ hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int
 // L2P: phi[b s + c] (+)= sum_a A[ax][cx] A[ay][cy] A[az][cz] P[b][a]
 hipError_t launch_l2p(const void* P, int p64, float* phi, Weights A, int N, int s, int p,
                       hipStream_t st, int accumulate = 0);
+// acc[c][b s + cell] += scale sum_a (A or Ad per axis) P[b][a], c = x, y, z:
+// the gradient of the leaf's local expansion times `scale`, with Ad the
+// derivative of the 1D interpolation weights, on axis c.
+hipError_t launch_l2p_grad(const void* P, int p64, float* acc, Weights A, Weights Ad,
+                           double scale, int N, int s, int p, hipStream_t st);
 // a = -grad(phi), periodic 4th-order central differences.
 hipError_t launch_fd4(const float* phi, float* acc, int N, hipStream_t st);
 // FP64 -> FP32 copy of n elements.

@@ -35,6 +35,7 @@ using namespace pfmm;
 struct pfmm_plan_s {
   int N = 0, L = 0, p = 0, s = 0, green = 0, prec = PFMM_PREC_FP32;
   double a1 = -0.125;
+  double a2 = 0.0;
   hipStream_t stream = nullptr;
   // The near zone runs on `side` while the tree runs on `stream` (fork and
   // join by events), except when profiling
@@ -45,6 +46,8 @@ struct pfmm_plan_s {
   float* dT = nullptr;  // [2][p][p] M2M / L2L weights
   double* dA64 = nullptr;
   double* dT64 = nullptr;
+  float* dAd = nullptr;   // [p][s] derivative of the L2P weights
+  double* dAd64 = nullptr;
   int fp64_levels = 2;            // levels 2 .. 1+fp64_levels kept in FP64
   std::vector<void*> M, P;        // gridlet masses / potentials per level
   std::vector<double*> tab64;     // per level, (8p-1)^3
@@ -55,6 +58,11 @@ struct pfmm_plan_s {
   int nl2 = 37;                   // level-2 offsets in use
   int isolated = 0;               // no periodic images (PFMM_OPT_ISOLATED)
   uint16_t* zero = nullptr;       // 512 zero bf16 values: the source outside an isolated box
+  // accelerations from the expansion (PFMM_OPT_ACCEL; tables on first use)
+  int accel_mode = 0;
+  double* ndtab64[3] = {nullptr, nullptr, nullptr};  // near acceleration kernels, (4s-1)^3
+  float* ndtab32[3] = {nullptr, nullptr, nullptr};
+  uint32_t* ndwin[3] = {nullptr, nullptr, nullptr};  // their windows (split near zone)
   int* offs_iz = nullptr;         // [8][189]
   int* offs_near = nullptr;       // [mn^3][(3 mn)^3]
   // split-precision matrix-core path (8^3 blocks)
@@ -149,6 +157,25 @@ double lagrange(int p, int a, double x) {
   return v;
 }
 
+// Derivative of that basis polynomial: the sum over b != a of the product of
+// the other factors, with 1/(t_a - t_b) in place of the factor of b.
+double lagrange_deriv(int p, int a, double x) {
+  const double ta = a + 0.5 - 0.5 * p;
+  double sum = 0.0;
+  for (int b = 0; b < p; ++b) {
+    if (b == a) continue;
+    const double tb = b + 0.5 - 0.5 * p;
+    double v = 1.0 / (ta - tb);
+    for (int c = 0; c < p; ++c) {
+      if (c == a || c == b) continue;
+      const double tc = c + 0.5 - 0.5 * p;
+      v *= (x - tc) / (ta - tc);
+    }
+    sum += v;
+  }
+  return sum;
+}
+
 template <class T>
 hipError_t dalloc(pfmm_plan_s* pl, T** ptr, size_t count) {
   void* raw = nullptr;
@@ -181,7 +208,7 @@ bool level64(const pfmm_plan_s* pl, int l) {
   if (l == pl->L) {
     const int p = pl->p, s = pl->s;
     const size_t w1 = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
-    const size_t w2 = (size_t)(p * s + p * p * p + p * p * s + p * s * s);
+    const size_t w2 = (size_t)(3 * p * s + p * p * p + p * p * s + p * s * s);
     if ((w1 > w2 ? w1 : w2) * sizeof(double) > 65536) return false;
   }
   return true;
@@ -194,18 +221,42 @@ Weights wts(const float* f, const double* d) {
   return w;
 }
 
+// Near-zone acceleration kernels of the plan's G (allocated on first use)
+pfmm_status tabulate_accel_tables(pfmm_plan_s* pl) {
+  const int Cn = 2 * pl->s - 1;
+  const int64_t n = cube(2 * Cn + 1);
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    if (!pl->ndtab64[c]) e = dalloc(pl, &pl->ndtab64[c], n);
+    if (e == hipSuccess && !pl->ndtab32[c]) e = dalloc(pl, &pl->ndtab32[c], n);
+    if (e == hipSuccess && pl->nwin && !pl->ndwin[c])
+      e = dalloc(pl, &pl->ndwin[c], window_dwords(kNearTerms));
+  }
+  if (e == hipErrorOutOfMemory) return fail(PFMM_ERR_OUT_OF_MEMORY, "acceleration tables");
+  if (e == hipSuccess)
+    e = tabulate_accel(pl->isolated ? GK_N : pl->green, pl->a1, pl->a2, pl->N, Cn, pl->ndtab64,
+                       pl->stream);
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    e = cast_f64_f32(pl->ndtab64[c], pl->ndtab32[c], n, pl->stream);
+    if (e == hipSuccess && pl->nwin) e = make_windows(pl->ndtab64[c], Cn, kNearTerms, pl->ndwin[c], pl->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) return hip_fail(e, "acceleration tables");
+  return PFMM_OK;
+}
+
 pfmm_status tabulate_all(pfmm_plan_s* pl) {
   const int p = pl->p;
   const int C = 4 * p - 1;
   const int64_t nlev = cube(2 * C + 1);
   for (int l = 2; l <= pl->L; ++l) {
-    hipError_t e = tabulate_green(pl->isolated ? GK_N : pl->green, pl->a1, pl->N, C,
+    hipError_t e = tabulate_green(pl->isolated ? GK_N : pl->green, pl->a1, pl->a2, pl->N, C,
                                   (int64_t(1) << l) * p, 0.0, pl->tab64[l], pl->stream);
     if (e == hipSuccess) e = cast_f64_f32(pl->tab64[l], pl->tab32[l], nlev, pl->stream);
     if (e != hipSuccess) return hip_fail(e, "tabulate level table");
   }
   const int Cn = 2 * pl->s - 1;
-  hipError_t e = tabulate_green(pl->isolated ? GK_N : pl->green, pl->a1, pl->N, Cn, pl->N,
+  hipError_t e = tabulate_green(pl->isolated ? GK_N : pl->green, pl->a1, pl->a2, pl->N, Cn, pl->N,
                                 1.0 / pl->N, pl->ntab64, pl->stream);
   if (e == hipSuccess) e = cast_f64_f32(pl->ntab64, pl->ntab32, cube(2 * Cn + 1), pl->stream);
   for (int l = 2; l <= pl->L && e == hipSuccess; ++l)
@@ -214,7 +265,7 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
     e = make_windows(pl->ntab64, Cn, kNearTerms, pl->nwin, pl->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
   if (e != hipSuccess) return hip_fail(e, "tabulate near table");
-  return PFMM_OK;
+  return pl->accel_mode ? tabulate_accel_tables(pl) : PFMM_OK;
 }
 
 // Offset groups of a level's matrix-core launch: enough workgroups to give
@@ -325,6 +376,18 @@ pfmm_status build(pfmm_plan_s* pl) {
   if (e == hipSuccess)
     e = hipMemcpy(pl->dT64, T64.data(), T64.size() * sizeof(double), hipMemcpyHostToDevice);
   if ((st = chk("FP64 weights"))) return st;
+  {
+    std::vector<double> D64(p * s);
+    for (int a = 0; a < p; ++a)
+      for (int c = 0; c < s; ++c) D64[a * s + c] = lagrange_deriv(p, a, (c + 0.5 - 0.5 * s) * ((double)p / s));
+    std::vector<float> D(D64.begin(), D64.end());
+    e = dalloc(pl, &pl->dAd, D.size());
+    if (e == hipSuccess) e = dalloc(pl, &pl->dAd64, D64.size());
+    if (e == hipSuccess) e = hipMemcpy(pl->dAd, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(pl->dAd64, D64.data(), D64.size() * sizeof(double), hipMemcpyHostToDevice);
+    if ((st = chk("derivative weights"))) return st;
+  }
 
   // per-level gridlet buffers (levels 2 and 3 sized for FP64) and tables
   pl->M.assign(L + 1, nullptr);
@@ -549,13 +612,17 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       pl->nl2 = (int)l2.size();
       return tabulate_all(pl);
     }
-    case PFMM_OPT_GS_A1: {
-      if (bytes != sizeof(double)) return fail(PFMM_ERR_INVALID_ARG, "a1 is a double");
-      if (pl->green != PFMM_GREEN_S) return fail(PFMM_ERR_INVALID_ARG, "a1 needs PFMM_GREEN_S");
+    case PFMM_OPT_GS_A1:
+    case PFMM_OPT_GS_A2: {
+      const char* name = option == PFMM_OPT_GS_A1 ? "a1" : "a2";
+      if (bytes != sizeof(double))
+        return fail(PFMM_ERR_INVALID_ARG, std::string(name) + " is a double");
+      if (pl->green != PFMM_GREEN_S)
+        return fail(PFMM_ERR_INVALID_ARG, std::string(name) + " needs PFMM_GREEN_S");
       double v;
       std::memcpy(&v, value, sizeof v);
-      if (!std::isfinite(v)) return fail(PFMM_ERR_INVALID_ARG, "a1 must be finite");
-      pl->a1 = v;
+      if (!std::isfinite(v)) return fail(PFMM_ERR_INVALID_ARG, std::string(name) + " must be finite");
+      (option == PFMM_OPT_GS_A1 ? pl->a1 : pl->a2) = v;
       pfmm_status r = tabulate_all(pl);
       if (r != PFMM_OK || pl->g0.empty()) return r;
       // new uncorrected tables; keep the plan's correction on top of them
@@ -566,6 +633,18 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
         if (e != hipSuccess) return hip_fail(e, "refresh tables");
       }
       return pl->learned ? learned_apply(pl, 0) : PFMM_OK;
+    }
+    case PFMM_OPT_ACCEL: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "accel mode is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      if (v != PFMM_ACCEL_FD4 && v != PFMM_ACCEL_EXPANSION)
+        return fail(PFMM_ERR_INVALID_ARG, "unknown acceleration mode");
+      pl->accel_mode = v;
+      if (!v) return PFMM_OK;
+      const pfmm_status r = tabulate_accel_tables(pl);
+      if (r != PFMM_OK) pl->accel_mode = 0;
+      return r;
     }
     case PFMM_OPT_FP64_LEVELS: {
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels is an int32");
@@ -705,9 +784,21 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
       ma.isolated = pl->isolated;
       ma.zero = pl->zero;
       e = launch_toep8_split(ma, kNearTerms, sn);
+      // accelerations from the expansion: the near zone with the three
+      // acceleration kernels, into the three components
+      for (int c = 0; c < 3 && e == hipSuccess && accel && pl->accel_mode; ++c) {
+        ma.win = pl->ndwin[c];
+        ma.Y = accel + (size_t)c * N * N * N;
+        e = launch_toep8_split(ma, kNearTerms, sn);
+      }
     }
   } else {
     e = launch_toeplitz(nb, sn);
+    for (int c = 0; c < 3 && e == hipSuccess && accel && pl->accel_mode; ++c) {
+      nb.tab = pl->ndtab32[c];
+      nb.Y = accel + (size_t)c * N * N * N;
+      e = launch_toeplitz(nb, sn);
+    }
   }
   if (e == hipSuccess) e = overlap ? hipEventRecord(pl->ev_join, pl->side) : mark(PFMM_STAGE_NEAR);
   if (e != hipSuccess) return hip_fail(e, "near zone");
@@ -767,7 +858,13 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   if (e == hipSuccess) e = mark(PFMM_STAGE_L2P);
   if (e != hipSuccess) return hip_fail(e, "L2P");
 
-  if (accel) {
+  if (accel && pl->accel_mode) {
+    // far part: gradient of the leaf's local expansion, -d/dx = -(1/eta_L) d/dv
+    e = launch_l2p_grad(pl->P[L], is64(L), accel, A, wts(pl->dAd, pl->dAd64),
+                        -(double)(1 << L) * p, N, s, p, st);
+    if (e == hipSuccess) e = mark(PFMM_STAGE_FD4);
+    if (e != hipSuccess) return hip_fail(e, "expansion gradient");
+  } else if (accel) {
     e = launch_fd4(phi, accel, N, st);
     if (e == hipSuccess) e = mark(PFMM_STAGE_FD4);
     if (e != hipSuccess) return hip_fail(e, "FD4");
@@ -1532,7 +1629,7 @@ pfmm_status direct_prepare(pfmm_plan_s* pl) {
   if (e == hipSuccess)
     e = hipMemcpy(pl->doffs, offs.data(), offs.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = tabulate_green(pl->green, pl->a1, N, C, N, 1.0 / N, pl->dtab64, pl->stream);
+    e = tabulate_green(pl->green, pl->a1, pl->a2, N, C, N, 1.0 / N, pl->dtab64, pl->stream);
   if (e == hipSuccess) e = cast_f64_f32(pl->dtab64, pl->dtab32, ntab, pl->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
   if (e != hipSuccess) {

@@ -2,8 +2,9 @@
 //
 // Real-space kinds (one thread per entry):
 //   G_X  (Eq. 2):  -1 / (4 pi |x wrapped|),  wrap(x) = x - nint(x)
-//   G_S  (Sec. 3 ansatz, n = 1): G_X of x_hat_i = xi(x_i),
+//   G_S  (Sec. 3 ansatz, n <= 2): G_X of x_hat_i = xi(x_i),
 //        xi(t) = sin(pi t)/pi + a1 (sin(3 pi t)/(3 pi) - sin(pi t)/pi)
+//                             + a2 (sin(5 pi t)/(5 pi) - sin(pi t)/pi)
 //   G_S1 (Eq. 9):  x_hat = 9/(8 pi) sin(pi x) - 1/(24 pi) sin(3 pi x)
 //   G_0  (the non-periodic twin of Eq. 3): -1 / (4 pi |x|), no wrap
 // The zero separation takes the potential at the centre of a uniform cube
@@ -15,6 +16,11 @@
 // and 1 (n = N/2: the Nyquist term split equally between +N/2 and -N/2), and
 // evaluated as three successive 1D cosine contractions on the product grid of
 // table coordinates.  Cosines take exactly reduced rational arguments.
+//
+// For accelerations taken from the expansion, the near zone sums the
+// acceleration of each source cell with the 4th-order central difference of
+// the lattice G along each axis (what differencing the potential gives for
+// that cell), tabulated from G over a table two cells wider.
 #include "internal.h"
 
 #include <cmath>
@@ -34,13 +40,14 @@ __device__ inline double xi_s1(double t) {
   return (9.0 / (8.0 * kPi)) * sinpi(t) - (1.0 / (24.0 * kPi)) * sinpi(3.0 * t);
 }
 
-__device__ inline double xi_s(double t, double a1) {
+__device__ inline double xi_s(double t, double a1, double a2) {
   const double s1 = sinpi(t) / kPi;
   const double s3 = sinpi(3.0 * t) / (3.0 * kPi);
-  return s1 + a1 * (s3 - s1);
+  const double s5 = sinpi(5.0 * t) / (5.0 * kPi);
+  return s1 + a1 * (s3 - s1) + a2 * (s5 - s1);
 }
 
-__global__ void tab_real_space(int kind, double a1, int C, int64_t den, double self_h,
+__global__ void tab_real_space(int kind, double a1, double a2, int C, int64_t den, double self_h,
                                double* __restrict__ dst) {
   const int E = 2 * C + 1;
   const int64_t total = (int64_t)E * E * E;
@@ -58,7 +65,7 @@ __global__ void tab_real_space(int kind, double a1, int C, int64_t den, double s
   if (kind == GK_S1) {
     x = xi_s1(x); y = xi_s1(y); z = xi_s1(z);
   } else if (kind == GK_S) {
-    x = xi_s(x, a1); y = xi_s(y, a1); z = xi_s(z, a1);
+    x = xi_s(x, a1, a2); y = xi_s(y, a1, a2); z = xi_s(z, a1, a2);
   }
   if (kind != GK_N) {
     x -= rint(x); y -= rint(y); z -= rint(z);
@@ -132,15 +139,36 @@ __global__ void k_cast(const double* __restrict__ s, float* __restrict__ d, int6
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// D_i(j) = -(8 (G(j + e_i) - G(j - e_i)) - (G(j + 2 e_i) - G(j - 2 e_i))) N / 12 for
+// j in [-C, C]^3, from G on [-C-2, C+2]^3
+__global__ void k_accel_tab(const double* __restrict__ g, int C, double n12,
+                            double* __restrict__ dx, double* __restrict__ dy,
+                            double* __restrict__ dz) {
+  const int E = 2 * C + 1, Eg = 2 * C + 5;
+  const int64_t total = (int64_t)E * E * E;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int jz = (int)(i % E) + 2;
+  const int jy = (int)((i / E) % E) + 2;
+  const int jx = (int)(i / ((int64_t)E * E)) + 2;
+  auto at = [&](int x, int y, int z) { return g[((int64_t)x * Eg + y) * Eg + z]; };
+  dx[i] = -(8.0 * (at(jx + 1, jy, jz) - at(jx - 1, jy, jz)) -
+            (at(jx + 2, jy, jz) - at(jx - 2, jy, jz))) * n12;
+  dy[i] = -(8.0 * (at(jx, jy + 1, jz) - at(jx, jy - 1, jz)) -
+            (at(jx, jy + 2, jz) - at(jx, jy - 2, jz))) * n12;
+  dz[i] = -(8.0 * (at(jx, jy, jz + 1) - at(jx, jy, jz - 1)) -
+            (at(jx, jy, jz + 2) - at(jx, jy, jz - 2))) * n12;
+}
+
 }  // namespace
 
-hipError_t tabulate_green(int kind, double a1, int N, int C, int64_t den, double self_h,
+hipError_t tabulate_green(int kind, double a1, double a2, int N, int C, int64_t den, double self_h,
                           double* dst, hipStream_t st) {
   const int E = 2 * C + 1;
   const int64_t total = (int64_t)E * E * E;
   if (kind != GK_K) {
-    hipLaunchKernelGGL(tab_real_space, dim3(nblocks(total, 256)), dim3(256), 0, st, kind, a1, C,
-                       den, self_h, dst);
+    hipLaunchKernelGGL(tab_real_space, dim3(nblocks(total, 256)), dim3(256), 0, st, kind, a1, a2,
+                       C, den, self_h, dst);
     return hipGetLastError();
   }
   const int H = N / 2;
@@ -162,6 +190,24 @@ hipError_t tabulate_green(int kind, double a1, int N, int C, int64_t den, double
   if (cs) hipFree(cs);
   if (U) hipFree(U);
   if (V) hipFree(V);
+  return e;
+}
+
+hipError_t tabulate_accel(int kind, double a1, double a2, int N, int C, double* d[3],
+                          hipStream_t st) {
+  const int64_t ng = (int64_t)(2 * C + 5) * (2 * C + 5) * (2 * C + 5);
+  const int64_t total = (int64_t)(2 * C + 1) * (2 * C + 1) * (2 * C + 1);
+  double* g = nullptr;
+  hipError_t e = hipMalloc(&g, ng * sizeof(double));
+  if (e != hipSuccess) return e;
+  e = tabulate_green(kind, a1, a2, N, C + 2, N, 1.0 / N, g, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_accel_tab, dim3(nblocks(total, 256)), dim3(256), 0, st, g, C,
+                       (double)N / 12.0, d[0], d[1], d[2]);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(g);
   return e;
 }
 

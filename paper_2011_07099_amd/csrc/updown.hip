@@ -5,7 +5,9 @@
 //   M2M  Eq. 5, child gridlets -> parent gridlet,
 //   L2L  Eq. 7, parent local field -> child gridlets (the transposed operator,
 //        i.e. Lagrange interpolation),
-//   L2P  leaf gridlet -> cells (transpose of P2M),
+//   L2P  leaf gridlet -> cells (transpose of P2M); with derivative weights on
+//        one axis, the gradient of the leaf's local expansion (accelerations
+//        from the expansion, Sec. 3),
 //   FD4  a = -grad(phi) by periodic 4th-order central differences (Sec. 3).
 // Every operator is a tensor product of 1D operators and is applied as three
 // successive 1D contractions on a block staged in LDS.  These stages move a
@@ -169,43 +171,56 @@ __global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
   }
 }
 
+// out[b s + c] (+)= scale sum_a Wx[ax][cx] Wy[ay][cy] Wz[az][cz] P[b][a]: L2P
+// with Wx = Wy = Wz = A and scale 1, or one component of the gradient of the
+// leaf's local expansion with the derivative weights on that axis
 template <class TI, class W>
 __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
-                                                   float* __restrict__ phi, Weights Aw, int N,
+                                                   float* __restrict__ phi, Weights Wxw,
+                                                   Weights Wyw, Weights Wzw, W scale, int N,
                                                    int s, int p, int accumulate) {
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
   const int p3 = p * p * p;
-  W* sA = sm;              // [p][s]
-  W* sp = sA + p * s;      // [ax][ay][az]
+  W* sAx = sm;             // [p][s] per axis
+  W* sAy = sAx + p * s;
+  W* sAz = sAy + p * s;
+  W* sp = sAz + p * s;     // [ax][ay][az]
   W* w1 = sp + p3;         // [ax][ay][cz]
   W* w2 = w1 + p * p * s;  // [ax][cy][cz]
-  const W* A = wsel<W>(Aw);
+  const W* Ax = wsel<W>(Wxw);
+  const W* Ay = wsel<W>(Wyw);
+  const W* Az = wsel<W>(Wzw);
   const int nL = N / s;
   const int b = blockIdx.x;
   const int bx = b / (nL * nL), by = (b / nL) % nL, bz = b % nL;
   const int tid = threadIdx.x;
-  for (int i = tid; i < p * s; i += kThreads) sA[i] = A[i];
+  for (int i = tid; i < p * s; i += kThreads) {
+    sAx[i] = Ax[i];
+    sAy[i] = Ay[i];
+    sAz[i] = Az[i];
+  }
   for (int i = tid; i < p3; i += kThreads) sp[i] = (W)P[(size_t)b * p3 + i];
   __syncthreads();
   for (int i = tid; i < p * p * s; i += kThreads) {
     const int xy = i / s, cz = i % s;
     W v = 0;
-    for (int k = 0; k < p; ++k) v += sA[k * s + cz] * sp[xy * p + k];
+    for (int k = 0; k < p; ++k) v += sAz[k * s + cz] * sp[xy * p + k];
     w1[i] = v;
   }
   __syncthreads();
   for (int i = tid; i < p * s * s; i += kThreads) {
     const int ax = i / (s * s), cy = (i / s) % s, cz = i % s;
     W v = 0;
-    for (int k = 0; k < p; ++k) v += sA[k * s + cy] * w1[(ax * p + k) * s + cz];
+    for (int k = 0; k < p; ++k) v += sAy[k * s + cy] * w1[(ax * p + k) * s + cz];
     w2[i] = v;
   }
   __syncthreads();
   for (int i = tid; i < s * s * s; i += kThreads) {
     const int cx = i / (s * s), cyz = i % (s * s);
     W v = 0;
-    for (int k = 0; k < p; ++k) v += sA[k * s + cx] * w2[k * s * s + cyz];
+    for (int k = 0; k < p; ++k) v += sAx[k * s + cx] * w2[k * s * s + cyz];
+    v *= scale;
     const int cy = cyz / s, cz = cyz % s;
     float* o = phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz);
     *o = accumulate ? (float)((W)*o + v) : (float)v;
@@ -287,17 +302,37 @@ hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int
   return hipGetLastError();
 }
 
-hipError_t launch_l2p(const void* P, int p64, float* phi, Weights A, int N, int s, int p,
-                      hipStream_t st, int accumulate) {
+namespace {
+hipError_t l2p_axes(const void* P, int p64, float* out, Weights Wx, Weights Wy, Weights Wz,
+                    double scale, int N, int s, int p, hipStream_t st, int accumulate) {
   const int nL = N / s;
-  const size_t words = (size_t)(p * s + p * p * p + p * p * s + p * s * s);
+  const size_t words = (size_t)(3 * p * s + p * p * p + p * p * s + p * s * s);
   if (p64)
     hipLaunchKernelGGL((k_l2p<double, double>), dim3(nL * nL * nL), dim3(kThreads),
-                       words * sizeof(double), st, (const double*)P, phi, A, N, s, p, accumulate);
+                       words * sizeof(double), st, (const double*)P, out, Wx, Wy, Wz, scale, N, s,
+                       p, accumulate);
   else
     hipLaunchKernelGGL((k_l2p<float, float>), dim3(nL * nL * nL), dim3(kThreads),
-                       words * sizeof(float), st, (const float*)P, phi, A, N, s, p, accumulate);
+                       words * sizeof(float), st, (const float*)P, out, Wx, Wy, Wz, (float)scale,
+                       N, s, p, accumulate);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_l2p(const void* P, int p64, float* phi, Weights A, int N, int s, int p,
+                      hipStream_t st, int accumulate) {
+  return l2p_axes(P, p64, phi, A, A, A, 1.0, N, s, p, st, accumulate);
+}
+
+hipError_t launch_l2p_grad(const void* P, int p64, float* acc, Weights A, Weights Ad,
+                           double scale, int N, int s, int p, hipStream_t st) {
+  const size_t n3 = (size_t)N * N * N;
+  for (int c = 0; c < 3; ++c) {
+    const hipError_t e = l2p_axes(P, p64, acc + c * n3, c == 0 ? Ad : A, c == 1 ? Ad : A,
+                                  c == 2 ? Ad : A, scale, N, s, p, st, 1);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_fd4(const float* phi, float* acc, int N, hipStream_t st) {

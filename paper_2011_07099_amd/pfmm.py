@@ -14,7 +14,9 @@ LIB_PATH = os.path.join(HERE, "libpfmm.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP = range(5)
 GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3}
 PREC = {"fp32": 0, "bf16x3": 1}
-OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED = 1, 2, 3, 4, 5, 6
+OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED, OPT_GS_A2, \
+    OPT_ACCEL = 1, 2, 3, 4, 5, 6, 7, 8
+ACCEL = {"fd4": 0, "expansion": 1}
 STAGES = ("p2m", "m2m", "m2l", "l2l", "l2p", "near", "fd4")
 BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
 
@@ -99,7 +101,7 @@ class Plan:
     """
 
     def __init__(self, N, L, p, green="S1", precision="fp32", a1=None, stream=None,
-                 fp64_levels=None, isolated=False):
+                 fp64_levels=None, isolated=False, a2=None, accel="fd4"):
         import torch
         lib = load()
         h = ctypes.c_void_p()
@@ -116,10 +118,21 @@ class Plan:
             self.set_precision(precision)
         if a1 is not None:
             self.set_a1(a1)
+        if a2 is not None:
+            self.set_a2(a2)
         if fp64_levels is not None:
             self.set_fp64_levels(fp64_levels)
         if isolated:
             self.set_isolated(True)
+        if accel != "fd4":
+            self.set_accel(accel)
+
+    def set_accel(self, mode):
+        """How solve forms accelerations: "fd4" (differences of the potential)
+        or "expansion" (gradient of the local expansion plus the near zone's
+        differenced kernels)."""
+        v = ctypes.c_int32(ACCEL[mode])
+        _check(load().pfmm_plan_set(self._h, OPT_ACCEL, ctypes.byref(v), 4))
 
     def set_isolated(self, on):
         """The non-periodic twin (G_X without images, sources outside the box
@@ -144,6 +157,10 @@ class Plan:
     def set_a1(self, a1):
         v = ctypes.c_double(float(a1))
         _check(load().pfmm_plan_set(self._h, OPT_GS_A1, ctypes.byref(v), 8))
+
+    def set_a2(self, a2):
+        v = ctypes.c_double(float(a2))
+        _check(load().pfmm_plan_set(self._h, OPT_GS_A2, ctypes.byref(v), 8))
 
     def set_profile(self, on):
         v = ctypes.c_int32(1 if on else 0)
