@@ -109,7 +109,7 @@ def gk_lattice(N, Lbox=1.0):
     return np.real(np.fft.ifftn(gt)) * N ** 3 / Lbox ** 3
 
 
-def gk_series(N, cx, cy, cz, Lbox=1.0):
+def gk_series(N, cx, cy, cz, Lbox=1.0, rs=None):
     """G_K evaluated off the lattice on the product grid cx x cy x cz.
 
     The paper defines G_K only through its Fourier coefficients on the
@@ -120,6 +120,8 @@ def gk_series(N, cx, cy, cz, Lbox=1.0):
         G(x) = (1/L^3) sum_{n_i in [-N/2, N/2]} w(n) G~_K(n) prod_i cos(2 pi n_i x_i / L),
     w(n) = prod_i (1/2 if |n_i| = N/2 else 1).  At lattice points it equals the
     paper's sum.  The three 1D cosine factors are contracted one axis at a time.
+    With ``rs`` the coefficients carry the Ewald damping exp(-k^2 rs^2 / 4)
+    (the Fourier part of G_E).
     """
     n = np.arange(-(N // 2), N // 2 + 1)
     w1 = np.where(np.abs(n) == N // 2, 0.5, 1.0)
@@ -128,6 +130,8 @@ def gk_series(N, cx, cy, cz, Lbox=1.0):
     gt = np.zeros_like(k2)
     nz = k2 > 0
     gt[nz] = -1.0 / k2[nz]
+    if rs is not None:
+        gt *= np.exp(-k2 * rs * rs / 4.0)
     gt *= w1[:, None, None] * w1[None, :, None] * w1[None, None, :]
     Cx = np.cos(2.0 * np.pi * np.outer(n, np.asarray(cx, np.float64)) / Lbox)
     Cy = np.cos(2.0 * np.pi * np.outer(n, np.asarray(cy, np.float64)) / Lbox)
@@ -138,7 +142,38 @@ def gk_series(N, cx, cy, cz, Lbox=1.0):
     return np.transpose(t, (2, 1, 0)) / Lbox ** 3
 
 
-GREEN_KINDS = ("X", "K", "S1", "S")
+def ewald_constant(rs):
+    """The constant 1/(2 pi^(3/2) r_S) of G_E."""
+    return 1.0 / (2.0 * np.pi ** 1.5 * rs)
+
+
+def green_e(N, cx, cy, cz, rs, h_self=None, Lbox=1.0):
+    """Ewald G_E on the product grid cx x cy x cz (Sec. 1):
+        G_E(x) = G_X(x) erfc(r / r_S) + 1/(2 pi^(3/2) r_S) + F^-1[G~_K(k) exp(-k^2 r_S^2 / 4)],
+    with the Fourier part over the mesh frequencies as for G_K (Eq. 1; reading
+    of ``gk_series`` between mesh points) and the real-space part on the
+    nearest image (r_S << L: the other images are negligible).
+
+    Zero separation (reading, as for the real-space kinds): the Newtonian
+    -1/(4 pi r) inside G_X erfc is replaced by the self-cell value; what is
+    left of G_X erfc there is its limit erf(r/r_S)/(4 pi r) -> 1/(2 pi^(3/2) r_S).
+    NaN there when ``h_self`` is None."""
+    from scipy.special import erfc
+    cx = np.asarray(cx, np.float64)
+    cy = np.asarray(cy, np.float64)
+    cz = np.asarray(cz, np.float64)
+    X = np.stack(np.meshgrid(cx, cy, cz, indexing="ij"), axis=-1)
+    w = wrap(X, Lbox)
+    r = np.sqrt(np.sum(w * w, axis=-1))
+    c = ewald_constant(rs)
+    zero = r == 0.0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        real = -erfc(r / rs) / (FOUR_PI * r)
+    real[zero] = (np.nan if h_self is None else self_value(h_self)) + c
+    return real + c + gk_series(N, cx, cy, cz, Lbox, rs=rs)
+
+
+GREEN_KINDS = ("X", "K", "S1", "S", "E")
 
 
 def green_newton(x):
@@ -155,12 +190,15 @@ def green_product_grid(kind, N, cx, cy, cz, a=(-0.125,), h_self=None):
     """G of kind ``kind`` on the product grid of separation coordinates
     cx x cy x cz (box units, L = 1).  Points with x = 0 exactly get the self-cell
     value for the real-space kinds (``h_self`` = mesh spacing, required then);
-    for G_K the zero separation is the series value itself (Eq. 1)."""
+    for G_K the zero separation is the series value itself (Eq. 1).  ``a``
+    holds the kind's parameters: a_1.. for "S", (r_S,) for "E"."""
     cx = np.asarray(cx, np.float64)
     cy = np.asarray(cy, np.float64)
     cz = np.asarray(cz, np.float64)
     if kind == "K":
         return gk_series(N, cx, cy, cz)
+    if kind == "E":
+        return green_e(N, cx, cy, cz, a[0], h_self)
     X = np.stack(np.meshgrid(cx, cy, cz, indexing="ij"), axis=-1)
     if kind == "X":
         g = green_x(X)
