@@ -68,7 +68,15 @@ typedef enum {
    * set by PFMM_OPT_GS_A1 (default -1/8) and PFMM_OPT_GS_A2 (default 0).
    * The defaults give G_S1; a_1 = -25/128, a_2 = 3/128 give the variant whose
    * map is t + O(t^7). */
-  PFMM_GREEN_S = 3
+  PFMM_GREEN_S = 3,
+  /* The Ewald Green's function of Sec. 1:
+   *   G_E(x) = G_X(x) erfc(r/r_S) + 1/(2 pi^(3/2) r_S)
+   *            + inverse transform of -exp(-k^2 r_S^2/4)/k^2 (k != 0),
+   * the real-space part on the nearest image, the Fourier part over the mesh
+   * frequencies as for G_K.  r_S is set by PFMM_OPT_EWALD_RS (default 0.1 of
+   * the box).  At zero separation the Newtonian part of G_X erfc takes the
+   * cube self value and the rest its limit 1/(2 pi^(3/2) r_S). */
+  PFMM_GREEN_E = 4
 } pfmm_green;
 
 /* Arithmetic of the two contraction-heavy steps (interaction-zone
@@ -123,7 +131,10 @@ typedef enum {
   /* value: int32 pfmm_accel, how pfmm_solve forms `accel`.  Switching to
    * PFMM_ACCEL_EXPANSION allocates and tabulates its near-zone kernels
    * (plan time; re-tabulated with G).  Default PFMM_ACCEL_FD4. */
-  PFMM_OPT_ACCEL = 8
+  PFMM_OPT_ACCEL = 8,
+  /* value: double r_S in (0, 1/4] (box units), the Ewald splitting radius of
+   * PFMM_GREEN_E; only for that kind.  Re-tabulates G synchronously. */
+  PFMM_OPT_EWALD_RS = 9
 } pfmm_option;
 
 /* How accelerations are formed (Sec. 3: PM differences its potential, the

@@ -13,21 +13,31 @@ namespace pfmm {
 // ---------------------------------------------------------------------------
 // Green's function tabulation (FP64, plan time)
 // ---------------------------------------------------------------------------
-enum GreenKind { GK_X = 0, GK_K = 1, GK_S1 = 2, GK_S = 3, GK_N = 4 /* free space, no wrap */ };
+enum GreenKind {
+  GK_X = 0, GK_K = 1, GK_S1 = 2, GK_S = 3, GK_E = 4,  // as pfmm_green
+  GK_N = 5                                             // free space, no wrap (isolated twin)
+};
+
+// A Green's function and its parameters: a1, a2 of G_S; the splitting radius
+// rs of G_E.
+struct GreenSpec {
+  int kind;
+  double a1, a2, rs;
+};
 
 // Tabulate G(eta * j) for j in [-C, C]^3 into dst[(2C+1)^3] (FP64, C order),
 // eta = 1 / den.  `self_h` > 0 gives the value at j = 0 for the real-space
 // kinds (potential at the centre of a uniform cube cell of side self_h);
-// self_h == 0 leaves 0 there.  `N` is the mesh size (G_K frequency range).
-// G_K allocates and frees its own temporaries and synchronises `st`.
-hipError_t tabulate_green(int kind, double a1, double a2, int N, int C, int64_t den, double self_h,
+// self_h == 0 leaves 0 there.  `N` is the mesh size (frequency range of G_K
+// and of the Fourier part of G_E).  G_K and G_E allocate and free their own
+// temporaries and synchronise `st`.
+hipError_t tabulate_green(const GreenSpec& g, int N, int C, int64_t den, double self_h,
                           double* dst, hipStream_t st);
 
 // Near-zone acceleration tables d[i][j] = -(4th-order central difference of the
 // lattice G along axis i at j) for j in [-C, C]^3, i = x, y, z (FP64, device).
 // Allocates and frees a temporary table; synchronises `st`.
-hipError_t tabulate_accel(int kind, double a1, double a2, int N, int C, double* d[3],
-                          hipStream_t st);
+hipError_t tabulate_accel(const GreenSpec& g, int N, int C, double* d[3], hipStream_t st);
 // FP64 -> FP32 copy.
 hipError_t cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 

@@ -36,6 +36,7 @@ struct pfmm_plan_s {
   int N = 0, L = 0, p = 0, s = 0, green = 0, prec = PFMM_PREC_FP32;
   double a1 = -0.125;
   double a2 = 0.0;
+  double rs = 0.1;  // G_E splitting radius
   hipStream_t stream = nullptr;
   // The near zone runs on `side` while the tree runs on `stream` (fork and
   // join by events), except when profiling
@@ -221,6 +222,15 @@ Weights wts(const float* f, const double* d) {
   return w;
 }
 
+GreenSpec green_spec(const pfmm_plan_s* pl) {
+  GreenSpec g;
+  g.kind = pl->isolated ? GK_N : pl->green;
+  g.a1 = pl->a1;
+  g.a2 = pl->a2;
+  g.rs = pl->rs;
+  return g;
+}
+
 // Near-zone acceleration kernels of the plan's G (allocated on first use)
 pfmm_status tabulate_accel_tables(pfmm_plan_s* pl) {
   const int Cn = 2 * pl->s - 1;
@@ -234,8 +244,7 @@ pfmm_status tabulate_accel_tables(pfmm_plan_s* pl) {
   }
   if (e == hipErrorOutOfMemory) return fail(PFMM_ERR_OUT_OF_MEMORY, "acceleration tables");
   if (e == hipSuccess)
-    e = tabulate_accel(pl->isolated ? GK_N : pl->green, pl->a1, pl->a2, pl->N, Cn, pl->ndtab64,
-                       pl->stream);
+    e = tabulate_accel(green_spec(pl), pl->N, Cn, pl->ndtab64, pl->stream);
   for (int c = 0; c < 3 && e == hipSuccess; ++c) {
     e = cast_f64_f32(pl->ndtab64[c], pl->ndtab32[c], n, pl->stream);
     if (e == hipSuccess && pl->nwin) e = make_windows(pl->ndtab64[c], Cn, kNearTerms, pl->ndwin[c], pl->stream);
@@ -250,13 +259,13 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
   const int C = 4 * p - 1;
   const int64_t nlev = cube(2 * C + 1);
   for (int l = 2; l <= pl->L; ++l) {
-    hipError_t e = tabulate_green(pl->isolated ? GK_N : pl->green, pl->a1, pl->a2, pl->N, C,
+    hipError_t e = tabulate_green(green_spec(pl), pl->N, C,
                                   (int64_t(1) << l) * p, 0.0, pl->tab64[l], pl->stream);
     if (e == hipSuccess) e = cast_f64_f32(pl->tab64[l], pl->tab32[l], nlev, pl->stream);
     if (e != hipSuccess) return hip_fail(e, "tabulate level table");
   }
   const int Cn = 2 * pl->s - 1;
-  hipError_t e = tabulate_green(pl->isolated ? GK_N : pl->green, pl->a1, pl->a2, pl->N, Cn, pl->N,
+  hipError_t e = tabulate_green(green_spec(pl), pl->N, Cn, pl->N,
                                 1.0 / pl->N, pl->ntab64, pl->stream);
   if (e == hipSuccess) e = cast_f64_f32(pl->ntab64, pl->ntab32, cube(2 * Cn + 1), pl->stream);
   for (int l = 2; l <= pl->L && e == hipSuccess; ++l)
@@ -265,6 +274,12 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
     e = make_windows(pl->ntab64, Cn, kNearTerms, pl->nwin, pl->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
   if (e != hipSuccess) return hip_fail(e, "tabulate near table");
+  if (pl->dtab64) {  // the direct solve's table, once it exists, follows G too
+    e = tabulate_green(green_spec(pl), pl->N, pl->dC, pl->N, 1.0 / pl->N, pl->dtab64, pl->stream);
+    if (e == hipSuccess) e = cast_f64_f32(pl->dtab64, pl->dtab32, cube(2 * pl->dC + 1), pl->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) return hip_fail(e, "direct solve tables");
+  }
   return pl->accel_mode ? tabulate_accel_tables(pl) : PFMM_OK;
 }
 
@@ -544,7 +559,7 @@ pfmm_status pfmm_plan_create(int N, int L, int p, int green_kind, pfmm_plan_t* o
     return fail(PFMM_ERR_INVALID_ARG, "N must be a power of two in [8, 1024]");
   if (L < 2 || (1 << L) > N) return fail(PFMM_ERR_INVALID_ARG, "need 2 <= L and 2^L <= N");
   if (p < 1 || p > 10) return fail(PFMM_ERR_INVALID_ARG, "p must be in [1, 10]");
-  if (green_kind < PFMM_GREEN_X || green_kind > PFMM_GREEN_S)
+  if (green_kind < PFMM_GREEN_X || green_kind > PFMM_GREEN_E)
     return fail(PFMM_ERR_INVALID_ARG, "unknown green_kind");
   const int s = N >> L;
   if (s > 16) return fail(PFMM_ERR_UNSUPPORTED, "leaf width N/2^L must be <= 16");
@@ -613,16 +628,20 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       return tabulate_all(pl);
     }
     case PFMM_OPT_GS_A1:
-    case PFMM_OPT_GS_A2: {
-      const char* name = option == PFMM_OPT_GS_A1 ? "a1" : "a2";
-      if (bytes != sizeof(double))
-        return fail(PFMM_ERR_INVALID_ARG, std::string(name) + " is a double");
-      if (pl->green != PFMM_GREEN_S)
-        return fail(PFMM_ERR_INVALID_ARG, std::string(name) + " needs PFMM_GREEN_S");
+    case PFMM_OPT_GS_A2:
+    case PFMM_OPT_EWALD_RS: {
+      const bool ewald = option == PFMM_OPT_EWALD_RS;
+      const std::string name = ewald ? "r_S" : option == PFMM_OPT_GS_A1 ? "a1" : "a2";
+      if (bytes != sizeof(double)) return fail(PFMM_ERR_INVALID_ARG, name + " is a double");
+      if (pl->green != (ewald ? PFMM_GREEN_E : PFMM_GREEN_S))
+        return fail(PFMM_ERR_INVALID_ARG,
+                    name + (ewald ? " needs PFMM_GREEN_E" : " needs PFMM_GREEN_S"));
       double v;
       std::memcpy(&v, value, sizeof v);
-      if (!std::isfinite(v)) return fail(PFMM_ERR_INVALID_ARG, std::string(name) + " must be finite");
-      (option == PFMM_OPT_GS_A1 ? pl->a1 : pl->a2) = v;
+      if (!std::isfinite(v)) return fail(PFMM_ERR_INVALID_ARG, name + " must be finite");
+      if (ewald && !(v > 0.0 && v <= 0.25))
+        return fail(PFMM_ERR_INVALID_ARG, "r_S must be in (0, 1/4] of the box");
+      (ewald ? pl->rs : option == PFMM_OPT_GS_A1 ? pl->a1 : pl->a2) = v;
       pfmm_status r = tabulate_all(pl);
       if (r != PFMM_OK || pl->g0.empty()) return r;
       // new uncorrected tables; keep the plan's correction on top of them
@@ -1629,7 +1648,7 @@ pfmm_status direct_prepare(pfmm_plan_s* pl) {
   if (e == hipSuccess)
     e = hipMemcpy(pl->doffs, offs.data(), offs.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = tabulate_green(pl->green, pl->a1, pl->a2, N, C, N, 1.0 / N, pl->dtab64, pl->stream);
+    e = tabulate_green(green_spec(pl), N, C, N, 1.0 / N, pl->dtab64, pl->stream);
   if (e == hipSuccess) e = cast_f64_f32(pl->dtab64, pl->dtab32, ntab, pl->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
   if (e != hipSuccess) {

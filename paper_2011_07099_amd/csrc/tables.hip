@@ -7,6 +7,8 @@
 //                             + a2 (sin(5 pi t)/(5 pi) - sin(pi t)/pi)
 //   G_S1 (Eq. 9):  x_hat = 9/(8 pi) sin(pi x) - 1/(24 pi) sin(3 pi x)
 //   G_0  (the non-periodic twin of Eq. 3): -1 / (4 pi |x|), no wrap
+//   G_E  (Ewald, Sec. 1), real-space part: G_X(x) erfc(r / r_S) + 1/(2 pi^(3/2) r_S)
+//        on the nearest image (r_S << L), added to its Fourier part below
 // The zero separation takes the potential at the centre of a uniform cube
 // cell of side h: -c0/(4 pi h), c0 = 3 ln((sqrt3+1)/(sqrt3-1)) - pi/2.
 //
@@ -15,7 +17,10 @@
 // folded onto n_i in [0, N/2] with per-axis weights 1 (n = 0), 2 (0 < n < N/2)
 // and 1 (n = N/2: the Nyquist term split equally between +N/2 and -N/2), and
 // evaluated as three successive 1D cosine contractions on the product grid of
-// table coordinates.  Cosines take exactly reduced rational arguments.
+// table coordinates.  Cosines take exactly reduced rational arguments.  The
+// Fourier part of G_E is the same sum with -1/k^2 damped by exp(-k^2 r_S^2 / 4).
+// At zero separation G_E keeps the cube self value for its Newtonian part;
+// the rest of its real-space part tends to 1/(2 pi^(3/2) r_S) there.
 //
 // For accelerations taken from the expansion, the near zone sums the
 // acceleration of each source cell with the 4th-order central difference of
@@ -47,8 +52,8 @@ __device__ inline double xi_s(double t, double a1, double a2) {
   return s1 + a1 * (s3 - s1) + a2 * (s5 - s1);
 }
 
-__global__ void tab_real_space(int kind, double a1, double a2, int C, int64_t den, double self_h,
-                               double* __restrict__ dst) {
+__global__ void tab_real_space(int kind, double a1, double a2, double rs, int C, int64_t den,
+                               double self_h, double* __restrict__ dst) {
   const int E = 2 * C + 1;
   const int64_t total = (int64_t)E * E * E;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -56,8 +61,10 @@ __global__ void tab_real_space(int kind, double a1, double a2, int C, int64_t de
   const int jz = (int)(i % E) - C;
   const int jy = (int)((i / E) % E) - C;
   const int jx = (int)(i / ((int64_t)E * E)) - C;
+  const double ewald_c = kind == GK_E ? 1.0 / (2.0 * kPi * sqrt(kPi) * rs) : 0.0;
   if (jx == 0 && jy == 0 && jz == 0) {
-    dst[i] = self_h > 0.0 ? self_potential(self_h) : 0.0;
+    const double v = self_h > 0.0 ? self_potential(self_h) + 2.0 * ewald_c : 0.0;
+    dst[i] = kind == GK_E ? dst[i] + v : v;
     return;
   }
   const double inv = 1.0 / (double)den;
@@ -70,7 +77,11 @@ __global__ void tab_real_space(int kind, double a1, double a2, int C, int64_t de
   if (kind != GK_N) {
     x -= rint(x); y -= rint(y); z -= rint(z);
   }
-  dst[i] = -1.0 / (4.0 * kPi * sqrt(x * x + y * y + z * z));
+  const double r = sqrt(x * x + y * y + z * z);
+  if (kind == GK_E)
+    dst[i] += -erfc(r / rs) / (4.0 * kPi * r) + ewald_c;
+  else
+    dst[i] = -1.0 / (4.0 * kPi * r);
 }
 
 // CS[n][j] = w(n) cos(2 pi n j / den), n in [0, H], j in [0, C]
@@ -83,8 +94,10 @@ __global__ void gk_cos(int H, int C, int64_t den, double* __restrict__ cs) {
   cs[i] = w * cospi((double)r / (double)den);
 }
 
-// U[nx][ny][jz] = sum_nz CS[nz][jz] Gt(nx, ny, nz),  Gt = -1/(4 pi^2 |n|^2), Gt(0) = 0
-__global__ void gk_step1(int H, int C, const double* __restrict__ cs, double* __restrict__ U) {
+// U[nx][ny][jz] = sum_nz CS[nz][jz] Gt(nx, ny, nz),
+// Gt = -exp(-damp |n|^2) / (4 pi^2 |n|^2), Gt(0) = 0  (damp = pi^2 r_S^2 for G_E, else 0)
+__global__ void gk_step1(int H, int C, double damp, const double* __restrict__ cs,
+                         double* __restrict__ U) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)(H + 1) * (H + 1) * (C + 1);
   if (i >= total) return;
@@ -96,7 +109,8 @@ __global__ void gk_step1(int H, int C, const double* __restrict__ cs, double* __
   for (int nz = 0; nz <= H; ++nz) {
     const double n2 = n2xy + (double)nz * nz;
     if (n2 == 0.0) continue;
-    acc += cs[nz * (C + 1) + jz] * (-1.0 / (4.0 * kPi * kPi * n2));
+    const double w = damp > 0.0 ? exp(-damp * n2) : 1.0;
+    acc += cs[nz * (C + 1) + jz] * (-w / (4.0 * kPi * kPi * n2));
   }
   U[i] = acc;
 }
@@ -162,45 +176,46 @@ __global__ void k_accel_tab(const double* __restrict__ g, int C, double n12,
 
 }  // namespace
 
-hipError_t tabulate_green(int kind, double a1, double a2, int N, int C, int64_t den, double self_h,
+hipError_t tabulate_green(const GreenSpec& g, int N, int C, int64_t den, double self_h,
                           double* dst, hipStream_t st) {
   const int E = 2 * C + 1;
   const int64_t total = (int64_t)E * E * E;
-  if (kind != GK_K) {
-    hipLaunchKernelGGL(tab_real_space, dim3(nblocks(total, 256)), dim3(256), 0, st, kind, a1, a2,
-                       C, den, self_h, dst);
-    return hipGetLastError();
+  hipError_t e = hipSuccess;
+  if (g.kind == GK_K || g.kind == GK_E) {  // Fourier sum (the whole G_K; G_E's long-range part)
+    const int H = N / 2;
+    const double damp = g.kind == GK_E ? kPi * kPi * g.rs * g.rs : 0.0;
+    double *cs = nullptr, *U = nullptr, *V = nullptr;
+    const int64_t ncs = (int64_t)(H + 1) * (C + 1);
+    const int64_t nU = (int64_t)(H + 1) * (H + 1) * (C + 1);
+    const int64_t nV = (int64_t)(H + 1) * (C + 1) * (C + 1);
+    e = hipMalloc(&cs, ncs * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&U, nU * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&V, nV * sizeof(double));
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(gk_cos, dim3(nblocks(ncs, 256)), dim3(256), 0, st, H, C, den, cs);
+      hipLaunchKernelGGL(gk_step1, dim3(nblocks(nU, 256)), dim3(256), 0, st, H, C, damp, cs, U);
+      hipLaunchKernelGGL(gk_step2, dim3(nblocks(nV, 256)), dim3(256), 0, st, H, C, cs, U, V);
+      hipLaunchKernelGGL(gk_step3, dim3(nblocks(total, 256)), dim3(256), 0, st, H, C, cs, V, dst);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (cs) (void)hipFree(cs);
+    if (U) (void)hipFree(U);
+    if (V) (void)hipFree(V);
+    if (e != hipSuccess || g.kind == GK_K) return e;
   }
-  const int H = N / 2;
-  double *cs = nullptr, *U = nullptr, *V = nullptr;
-  const int64_t ncs = (int64_t)(H + 1) * (C + 1);
-  const int64_t nU = (int64_t)(H + 1) * (H + 1) * (C + 1);
-  const int64_t nV = (int64_t)(H + 1) * (C + 1) * (C + 1);
-  hipError_t e = hipMalloc(&cs, ncs * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&U, nU * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&V, nV * sizeof(double));
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(gk_cos, dim3(nblocks(ncs, 256)), dim3(256), 0, st, H, C, den, cs);
-    hipLaunchKernelGGL(gk_step1, dim3(nblocks(nU, 256)), dim3(256), 0, st, H, C, cs, U);
-    hipLaunchKernelGGL(gk_step2, dim3(nblocks(nV, 256)), dim3(256), 0, st, H, C, cs, U, V);
-    hipLaunchKernelGGL(gk_step3, dim3(nblocks(total, 256)), dim3(256), 0, st, H, C, cs, V, dst);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-  }
-  if (cs) hipFree(cs);
-  if (U) hipFree(U);
-  if (V) hipFree(V);
-  return e;
+  hipLaunchKernelGGL(tab_real_space, dim3(nblocks(total, 256)), dim3(256), 0, st, g.kind, g.a1,
+                     g.a2, g.rs, C, den, self_h, dst);
+  return hipGetLastError();
 }
 
-hipError_t tabulate_accel(int kind, double a1, double a2, int N, int C, double* d[3],
-                          hipStream_t st) {
+hipError_t tabulate_accel(const GreenSpec& gs, int N, int C, double* d[3], hipStream_t st) {
   const int64_t ng = (int64_t)(2 * C + 5) * (2 * C + 5) * (2 * C + 5);
   const int64_t total = (int64_t)(2 * C + 1) * (2 * C + 1) * (2 * C + 1);
   double* g = nullptr;
   hipError_t e = hipMalloc(&g, ng * sizeof(double));
   if (e != hipSuccess) return e;
-  e = tabulate_green(kind, a1, a2, N, C + 2, N, 1.0 / N, g, st);
+  e = tabulate_green(gs, N, C + 2, N, 1.0 / N, g, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_accel_tab, dim3(nblocks(total, 256)), dim3(256), 0, st, g, C,
                        (double)N / 12.0, d[0], d[1], d[2]);

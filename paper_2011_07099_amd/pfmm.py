@@ -12,10 +12,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpfmm.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP = range(5)
-GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3}
+GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3, "E": 4}
 PREC = {"fp32": 0, "bf16x3": 1}
 OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED, OPT_GS_A2, \
-    OPT_ACCEL = 1, 2, 3, 4, 5, 6, 7, 8
+    OPT_ACCEL, OPT_EWALD_RS = 1, 2, 3, 4, 5, 6, 7, 8, 9
 ACCEL = {"fd4": 0, "expansion": 1}
 STAGES = ("p2m", "m2m", "m2l", "l2l", "l2p", "near", "fd4")
 BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
@@ -101,7 +101,7 @@ class Plan:
     """
 
     def __init__(self, N, L, p, green="S1", precision="fp32", a1=None, stream=None,
-                 fp64_levels=None, isolated=False, a2=None, accel="fd4"):
+                 fp64_levels=None, isolated=False, a2=None, accel="fd4", rs=None):
         import torch
         lib = load()
         h = ctypes.c_void_p()
@@ -120,6 +120,8 @@ class Plan:
             self.set_a1(a1)
         if a2 is not None:
             self.set_a2(a2)
+        if rs is not None:
+            self.set_ewald_rs(rs)
         if fp64_levels is not None:
             self.set_fp64_levels(fp64_levels)
         if isolated:
@@ -157,6 +159,11 @@ class Plan:
     def set_a1(self, a1):
         v = ctypes.c_double(float(a1))
         _check(load().pfmm_plan_set(self._h, OPT_GS_A1, ctypes.byref(v), 8))
+
+    def set_ewald_rs(self, rs):
+        """Splitting radius r_S of the Ewald G_E (green "E")."""
+        v = ctypes.c_double(float(rs))
+        _check(load().pfmm_plan_set(self._h, OPT_EWALD_RS, ctypes.byref(v), 8))
 
     def set_a2(self, a2):
         v = ctypes.c_double(float(a2))
