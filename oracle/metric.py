@@ -20,6 +20,8 @@ image of a source have no counterpart in the twin, their expansion error stays
 in Delta g, and Delta g of the corner source comes out an order of magnitude
 above the values the paper tabulates.
 """
+import itertools
+
 import numpy as np
 
 from . import green as _g
@@ -78,3 +80,44 @@ def norms(dg):
     """(L2, L_MAX) of a per-cell error magnitude: root mean square and maximum."""
     dg = np.asarray(dg, np.float64)
     return float(np.sqrt(np.mean(dg * dg))), float(np.max(dg))
+
+
+def periodic_point_accel(N, cell=(0, 0, 0), alpha=0.1, images=1):
+    """Exact acceleration of a unit point mass at the centre of ``cell`` in the
+    periodic unit box, with the uniform background that makes the mean density
+    zero (the periodic Poisson problem the FMM solves), at every cell centre:
+    Ewald's split of -1/(4 pi r) summed over all images,
+        g = -grad[ sum_n -erfc(|x + n|/alpha) / (4 pi |x + n|) ]
+            - grad[ sum_{k != 0} -exp(-k^2 alpha^2 / 4) / k^2 cos(k . x) ],
+    the real-space sum over the (2 images + 1)^3 nearest images (alpha << 1
+    makes the rest negligible), the Fourier sum by an inverse FFT over the
+    mesh frequencies (exp(-k^2 alpha^2 / 4) is negligible beyond them for
+    alpha >> 1/N).  NaN at the source cell.  Returns (3, N, N, N).
+    This is the Newtonian force of the periodic problem, the reference for the
+    deviation of the FMM's force from the Newtonian form (Sec. 3, Fig. 6)."""
+    from scipy.special import erfc
+    h = 1.0 / N
+    j = np.arange(N)
+    out = np.zeros((3, N, N, N))
+    X = [((j - c + N // 2) % N - N // 2) * h for c in cell]   # nearest-image displacement
+    x3 = np.stack(np.meshgrid(*X, indexing="ij"))
+    for n in itertools.product(range(-images, images + 1), repeat=3):
+        y = x3 + np.asarray(n, np.float64)[:, None, None, None]
+        r = np.sqrt(np.sum(y * y, axis=0))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            dphi = erfc(r / alpha) / (4 * np.pi * r * r) \
+                + np.exp(-(r / alpha) ** 2) / (2 * np.pi ** 1.5 * alpha * r)
+            out -= dphi * y / r
+    f = np.fft.fftfreq(N, d=1.0 / N)
+    kx, ky, kz = np.meshgrid(2 * np.pi * f, 2 * np.pi * f, 2 * np.pi * f, indexing="ij")
+    k2 = kx * kx + ky * ky + kz * kz
+    c = np.zeros_like(k2)
+    nz = k2 > 0
+    c[nz] = -np.exp(-k2[nz] * alpha * alpha / 4.0) / k2[nz]
+    phase = np.exp(-1j * 2 * np.pi * (f[:, None, None] * cell[0] + f[None, :, None] * cell[1]
+                                      + f[None, None, :] * cell[2]) / N)
+    for ax, k in enumerate((kx, ky, kz)):
+        # -grad of sum c cos(k.(x - x_s)) = sum c k sin(k.(x - x_s)), as a DFT
+        out[ax] += np.real(np.fft.ifftn(-1j * k * c * phase)) * N ** 3
+    out[:, cell[0], cell[1], cell[2]] = np.nan
+    return out

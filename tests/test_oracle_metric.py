@@ -14,6 +14,9 @@ norms and the downhill simplex.
   from a source they approach the Newtonian -m x / (4 pi r^3).
 * The expansion accelerations of a smooth field converge to PM's as p grows.
 * The simplex finds known minima.
+* The exact periodic force of a point mass (Ewald summation) does not depend
+  on the splitting radius, tends to the Newtonian force plus the background's
+  +x/3 near the source, and is translation and reflection covariant.
 """
 import numpy as np
 
@@ -143,3 +146,27 @@ def test_nelder_mead_finds_known_minima():
     x, _, _ = fit.nelder_mead(lambda v: max(abs(v[0] - 0.2), abs(v[1] + 0.4)), [0, 0], 0.3,
                               xtol=1e-9, maxiter=2000)
     assert np.max(np.abs(x - [0.2, -0.4])) < 1e-7
+
+
+def test_exact_periodic_force_of_a_point_mass():
+    N = 32
+    h = 1.0 / N
+    g1 = metric.periodic_point_accel(N, (0, 0, 0), alpha=0.08)
+    g2 = metric.periodic_point_accel(N, (0, 0, 0), alpha=0.12)
+    # Ewald's split does not depend on the splitting radius
+    assert np.nanmax(np.abs(g1 - g2)) < 1e-8 * np.nanmax(np.abs(g1))
+    # near the source: Newtonian plus the background's +x/3 (the images' linear
+    # tidal terms cancel by cubic symmetry)
+    for c in [(2, 0, 0), (2, 2, 1), (1, 1, 1)]:
+        x = np.array(c) * h
+        r = np.linalg.norm(x)
+        rest = g1[:, c[0], c[1], c[2]] + x / (4 * np.pi * r ** 3)
+        assert np.max(np.abs(rest - x / 3)) < 0.05 * np.linalg.norm(x / 3)
+    # translation
+    g3 = metric.periodic_point_accel(N, (5, 7, 9), alpha=0.1)
+    g0 = metric.periodic_point_accel(N, (0, 0, 0), alpha=0.1)
+    assert np.nanmax(np.abs(np.roll(g0, (5, 7, 9), axis=(1, 2, 3)) - g3)) < 1e-12 * np.nanmax(np.abs(g0))
+    # point reflection through the source: g(-x) = -g(x)
+    flip = -np.roll(np.flip(g0, axis=(1, 2, 3)), 1, axis=(1, 2, 3))
+    m = np.isfinite(g0)
+    assert np.max(np.abs(flip[m] - g0[m])) < 1e-12 * np.nanmax(np.abs(g0))
