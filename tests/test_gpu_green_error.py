@@ -20,6 +20,16 @@ interaction zone in FP64.
   from p = 6 on, increasingly with p (L2 x1.13 at p = 6, x1.56 at p = 8, where
   L_MAX is x2.3), but better at p = 4 (L2 x0.86).  The test holds the L2 ratio
   to bands around those values.
+* Deviation of the force from the Newtonian form (Fig. 6 analogue, the
+  GADGET-4 comparison left out): the G_S1 FMM acceleration of the corner
+  source against the exact periodic Newtonian force (Ewald summation, oracle)
+  and against the nearest image's -x/(4 pi r^3), |g - g_N| / |g_N| binned by
+  distance.  The deviation is G_S1's own: PM with G_S1 gives the same curve
+  (medians agree to 5% in every bin past 4 cells), and PM with G_K matches the
+  exact periodic force to 1e-4 past 8 cells.  G_S1's force is Newtonian to a
+  few 1e-3 out to L/8 and deviates by 2e-2 at L/8 - L/4 and 0.2-0.5 beyond:
+  G_S1 is chosen to make the FMM agree with PM(G_S1), not with the periodic
+  Newtonian force.
 """
 import os
 
@@ -152,3 +162,40 @@ def test_t7_variant_against_gs1(runner):
           % (p, t7[0], t7[1], base[0], base[1], ratio, t7[1] / base[1]))
     lo, hi = T7_L2_RATIO[p]
     assert lo < ratio < hi
+
+
+BINS = [1, 2, 4, 8, 16, 32, 64, 112]
+
+
+def _binned_median(dev, r):
+    # cells where the reference force vanishes (the box's symmetry points) drop out
+    out = []
+    for lo, hi in zip(BINS[:-1], BINS[1:]):
+        v = dev[(r >= lo) & (r < hi)]
+        out.append(float(np.median(v[np.isfinite(v)])))
+    return out
+
+
+def test_deviation_from_newtonian_force(runner):
+    p = runner.p
+    runner.P.set_a1(-0.125)
+    runner.P.set_a2(0.0)
+    g = runner._accel(runner.P, [[0, 0, 0]], [1.0])
+    exact = metric.periodic_point_accel(N, (0, 0, 0))
+    j = np.arange(N)
+    d = np.minimum(j, N - j).astype(np.float64)
+    r = np.sqrt(d[:, None, None] ** 2 + d[None, :, None] ** 2 + d[None, None, :] ** 2)
+    x = np.stack(np.meshgrid(*([np.where(j < N // 2, j, j - N) / N] * 3), indexing="ij"))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        newton = -x / (4 * np.pi * np.sum(x * x, axis=0) ** 1.5)
+        dev = np.linalg.norm(g - exact, axis=0) / np.linalg.norm(exact, axis=0)
+        dev_n = np.linalg.norm(g - newton, axis=0) / np.linalg.norm(newton, axis=0)
+        pm = metric.point_sources_accel(N, [[0, 0, 0]], [1.0], "S1")
+        dev_pm = np.linalg.norm(pm - exact, axis=0) / np.linalg.norm(exact, axis=0)
+    fmm_b, newt_b, pm_b = _binned_median(dev, r), _binned_median(dev_n, r), _binned_median(dev_pm, r)
+    for (lo, hi), a, b, c in zip(zip(BINS[:-1], BINS[1:]), fmm_b, newt_b, pm_b):
+        print("p=%d r in [%3d, %3d) cells: median |g - g_N|/|g_N| vs periodic %.2e "
+              "(PM(G_S1) %.2e), vs nearest image %.2e" % (p, lo, hi, a, c, b))
+    for lo, a, c in zip(BINS[:-1], fmm_b, pm_b):
+        if lo >= 4:
+            assert abs(a - c) <= 0.05 * c
