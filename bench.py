@@ -238,6 +238,49 @@ def learned_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def m2l_bench(args):
+    """The interaction zones (Eq. 6) two ways on the headline mesh (256^3,
+    L = 4, G_S1, the same density): the block-Toeplitz GEMM of this library
+    (FP32 portable kernel, and split BF16 on the matrix cores at p = 8) and
+    the HPM form the paper runs (Sec. 2: per target node one FFT convolution
+    of its zone's effective masses with G, rocFFT), at p = 4, 6, 8.  Levels
+    2-3 are FP64 in every variant (FP64 matrix cores at p = 8, FP64
+    transforms for the FFT).  Per-level medians of the profiled stage times
+    over `steps` solves; `value` is the FFT-to-GEMM time ratio of all levels
+    at p = 8 with the default (split) precision."""
+    import torch
+    from paper_2011_07099_amd import fields
+    from paper_2011_07099_amd.pfmm import Plan
+    rho = torch.from_numpy(fields.lognormal(N, ALPHA, SIGMA, seed=SEED).astype(np.float32)).cuda()
+    phi = torch.empty_like(rho)
+    res = {}
+    for p in (4, 6, 8):
+        for m2l, prec in (("gemm", "fp32"), ("gemm", "bf16x3"), ("fft", "fp32")):
+            if prec == "bf16x3" and p != 8:
+                continue  # the split matrix-core kernel serves p = 8
+            with Plan(N, L, p, GREEN, precision=prec, m2l=m2l) as pl:
+                for _ in range(max(args.warmup, 1)):
+                    pl.solve(rho, phi)
+                pl.set_profile(True)
+                per = []
+                for _ in range(max(args.steps, 1)):
+                    pl.solve(rho, phi)
+                    per.append(pl.level_times("m2l"))
+                torch.cuda.synchronize()
+            lv = {str(l): float(np.median([x[l] for x in per])) for l in range(2, L + 1)}
+            key = "p%d %s %s" % (p, m2l, prec)
+            res[key] = {"ms_per_level": lv, "ms_total": float(sum(lv.values()))}
+            print("m2l", key, res[key], file=sys.stderr, flush=True)
+    ratio = res["p8 fft fp32"]["ms_total"] / res["p8 gemm bf16x3"]["ms_total"]
+    out = {"metric": "interaction-zone time, HPM FFT convolution / block-Toeplitz GEMM, p=8",
+           "value": ratio, "unit": "ratio", "higher_is_better": True, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+           "config": {"workload": "256^3 L=4 G_S1 lognormal (alpha=1.5, sigma_delta=2, seed 5); "
+                                  "M2L of levels 2-4, p = 4, 6, 8"},
+           "results": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,7 +288,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "learned"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "learned", "m2l"])
     ap.add_argument("--epochs", type=int, default=2, help="training epochs (learned workload)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times): the reference that "
@@ -263,6 +306,9 @@ def main():
         return
     if args.workload == "learned":
         learned_bench(args)
+        return
+    if args.workload == "m2l":
+        m2l_bench(args)
         return
 
     import torch

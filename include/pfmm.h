@@ -134,8 +134,28 @@ typedef enum {
   PFMM_OPT_ACCEL = 8,
   /* value: double r_S in (0, 1/4] (box units), the Ewald splitting radius of
    * PFMM_GREEN_E; only for that kind.  Re-tabulates G synchronously. */
-  PFMM_OPT_EWALD_RS = 9
+  PFMM_OPT_EWALD_RS = 9,
+  /* value: int32 pfmm_m2l, how the interaction zones are summed.  Switching
+   * to PFMM_M2L_FFT creates FFT plans and up to 1 GiB of grids and transforms
+   * the level tables (plan time; transformed again when G changes).  Not for
+   * isolated plans, batches or learned tables.  Default PFMM_M2L_GEMM. */
+  PFMM_OPT_M2L = 10
 } pfmm_option;
+
+/* Interaction-zone (M2L, Eq. 6) algorithm. */
+typedef enum {
+  /* Block-Toeplitz GEMM over the zone's offsets (matrix cores or the
+   * portable kernel, as PFMM_OPT_PRECISION selects). */
+  PFMM_M2L_GEMM = 0,
+  /* The Hierarchical Particle-Mesh form the paper runs (Sec. 2): per target
+   * node the effective masses of its whole zone on one uniform grid, one FFT
+   * convolution with G (rocFFT; FP64 transforms for the levels kept in FP64,
+   * PFMM_OPT_FP64_LEVELS, FP32 for the rest).  Levels >= 3: the 6^3 children of the
+   * parent's neighbours with the target's neighbours zeroed, padded to
+   * (8p)^3; level 2: the periodic (4p)^3 level.  A comparator: same sums as
+   * the GEMM up to rounding. */
+  PFMM_M2L_FFT = 1
+} pfmm_m2l;
 
 /* How accelerations are formed (Sec. 3: PM differences its potential, the
  * FMM takes them from its expansion). */

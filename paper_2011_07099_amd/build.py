@@ -2,7 +2,7 @@
 
 Usage: ``python -m paper_2011_07099_amd.build`` or ``build()`` from Python.
 Every HIP source under ``csrc/`` is compiled to an object under ``_build/``
-(in parallel) and linked into ``paper_2011_07099_amd/libpfmm.so``.  Packed
+(in parallel) and linked, with hipFFT, into ``paper_2011_07099_amd/libpfmm.so``.  Packed
 FP32 instructions are disabled for all device code.
 """
 import glob
@@ -46,7 +46,7 @@ def build(verbose=False, jobs=8):
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(one, srcs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhipfft"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr)

@@ -205,6 +205,22 @@ hipError_t launch_l2p_grad(const void* P, int p64, float* acc, Weights A, Weight
                            double scale, int N, int s, int p, hipStream_t st);
 // a = -grad(phi), periodic 4th-order central differences.
 hipError_t launch_fd4(const float* phi, float* acc, int N, hipStream_t st);
+// ---------------------------------------------------------------------------
+// Interaction zones by FFT convolution (the HPM comparator)
+// ---------------------------------------------------------------------------
+struct M2LFft;
+// Plans for levels 2 .. L at gridlet size p, batches of targets sized so that
+// their grids take at most `budget_bytes`; allocates.
+hipError_t m2l_fft_create(int L, int p, size_t budget_bytes, M2LFft** out);
+void m2l_fft_destroy(M2LFft* f);
+// Transform the kernels G(eta_l w) of every level from the FP64 level tables;
+// synchronises `st`.
+hipError_t m2l_fft_tables(M2LFft* f, const std::vector<double*>& tab64, hipStream_t st);
+// Pl (+)= the level-l interaction-zone sums of the masses Ml (FP64 buffers
+// and transforms when fp64, else FP32).
+hipError_t m2l_fft_level(M2LFft* f, int l, const void* Ml, void* Pl, int fp64, int accumulate,
+                         hipStream_t st);
+
 // FP64 -> FP32 copy of n elements.
 hipError_t launch_cast_d2f(const double* src, float* dst, int64_t n, hipStream_t st);
 

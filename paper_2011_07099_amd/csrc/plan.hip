@@ -58,6 +58,8 @@ struct pfmm_plan_s {
   int* offs_l2 = nullptr;         // [37] periodic, [316] isolated (capacity 316)
   int nl2 = 37;                   // level-2 offsets in use
   int isolated = 0;               // no periodic images (PFMM_OPT_ISOLATED)
+  int m2l_fft = 0;                // interaction zones by FFT convolution (PFMM_OPT_M2L)
+  M2LFft* fft = nullptr;          // its plans, grids and transformed kernels
   uint16_t* zero = nullptr;       // 512 zero bf16 values: the source outside an isolated box
   // accelerations from the expansion (PFMM_OPT_ACCEL; tables on first use)
   int accel_mode = 0;
@@ -188,6 +190,8 @@ hipError_t dalloc(pfmm_plan_s* pl, T** ptr, size_t count) {
 }
 
 void release(pfmm_plan_s* pl) {
+  if (pl->fft) m2l_fft_destroy(pl->fft);
+  pl->fft = nullptr;
   for (hipEvent_t e : pl->ev)
     if (e) (void)hipEventDestroy(e);
   pl->ev.clear();
@@ -279,6 +283,10 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
     if (e == hipSuccess) e = cast_f64_f32(pl->dtab64, pl->dtab32, cube(2 * pl->dC + 1), pl->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
     if (e != hipSuccess) return hip_fail(e, "direct solve tables");
+  }
+  if (pl->fft) {  // transformed kernels of the FFT interaction zones follow G
+    e = m2l_fft_tables(pl->fft, pl->tab64, pl->stream);
+    if (e != hipSuccess) return hip_fail(e, "FFT kernels");
   }
   return pl->accel_mode ? tabulate_accel_tables(pl) : PFMM_OK;
 }
@@ -611,6 +619,7 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       if (v && pl->green != PFMM_GREEN_X)
         return fail(PFMM_ERR_UNSUPPORTED, "the isolated twin uses G_X without images: PFMM_GREEN_X");
       if (!pl->g0.empty()) return fail(PFMM_ERR_UNSUPPORTED, "plan has learned tables");
+      if (v && pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "the FFT interaction zones are periodic only");
       // level-2 zone: 37 periodic representatives, or every non-neighbour
       // node of the 4^3 level, d in [-3, 3]^3 \ [-1, 1]^3 (316)
       std::vector<int> l2;
@@ -664,6 +673,28 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       const pfmm_status r = tabulate_accel_tables(pl);
       if (r != PFMM_OK) pl->accel_mode = 0;
       return r;
+    }
+    case PFMM_OPT_M2L: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "M2L mode is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      if (v != PFMM_M2L_GEMM && v != PFMM_M2L_FFT)
+        return fail(PFMM_ERR_INVALID_ARG, "unknown M2L mode");
+      if (v == PFMM_M2L_FFT) {
+        if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "the FFT interaction zones are periodic only");
+        if (!pl->g0.empty()) return fail(PFMM_ERR_UNSUPPORTED, "plan has learned tables");
+        if (!pl->fft) {
+          M2LFft* f = nullptr;
+          hipError_t e = m2l_fft_create(pl->L, pl->p, (size_t)1 << 30, &f);
+          if (e == hipErrorOutOfMemory) return fail(PFMM_ERR_OUT_OF_MEMORY, "FFT workspace");
+          if (e != hipSuccess) return hip_fail(e, "FFT plans");
+          pl->fft = f;
+          e = m2l_fft_tables(pl->fft, pl->tab64, pl->stream);
+          if (e != hipSuccess) return hip_fail(e, "FFT kernels");
+        }
+      }
+      pl->m2l_fft = v;
+      return PFMM_OK;
     }
     case PFMM_OPT_FP64_LEVELS: {
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels is an int32");
@@ -719,6 +750,8 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   // interaction zone of one level: matrix cores for FP32 levels with windows
   auto m2l = [&](const ToepArgs& ta0, int l) -> hipError_t {
     ToepArgs ta = ta0;
+    if (pl->m2l_fft)  // the FFT-convolution comparator, in the level's precision
+      return m2l_fft_level(pl->fft, l, ta.X, ta.Y, ta.fp64, ta.accumulate, st);
     if (ta.fp64 && ta.q == 8 && ta.C >= 31) {  // FP64 coarse level on the matrix cores
       ToepF64Args fa{};
       fa.n = ta.n;
@@ -1335,6 +1368,10 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
       delete b;
       return fail(PFMM_ERR_UNSUPPORTED, "batches of isolated plans");
     }
+    if (plans[i]->m2l_fft) {
+      delete b;
+      return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with FFT interaction zones");
+    }
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) {
         delete b;
@@ -1697,6 +1734,7 @@ pfmm_status pfmm_learned_set(pfmm_plan_t pl, const float* weights, int bf16) {
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
   if (!weights) {
     if (pl->g0.empty()) return PFMM_OK;  // never corrected
     pl->learned = 0;
@@ -1714,6 +1752,7 @@ pfmm_status pfmm_learned_train_begin(pfmm_plan_t pl, const float* weights, doubl
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
   if (!weights || !(lr > 0.0)) return fail(PFMM_ERR_INVALID_ARG, "need weights and lr > 0");
   pfmm_status s0 = learned_prepare(pl);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
@@ -1776,6 +1815,7 @@ pfmm_status pfmm_learned_loss(pfmm_plan_t pl, const float* rho, const float* tar
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
   if (!rho || !target || !loss) return fail(PFMM_ERR_INVALID_ARG, "NULL argument");
   pfmm_status s0 = learned_prepare(pl);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
