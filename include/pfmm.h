@@ -393,6 +393,44 @@ pfmm_status pfmm_learned_get(pfmm_plan_t plan, float* weights);
 pfmm_status pfmm_learned_read_grad(pfmm_plan_t plan, int level, double* table_grad,
                                    float* weight_grad);
 
+/*
+ * Grid-valued interaction-zone tables (Sec. 3 defines G_* by FMM = PM; Sec. 4
+ * proposes treating G_* as a grid of free values).  Every table value of
+ * Eq. 6 is free up to the 48 symmetries of the cube:
+ *     T_l[j] = G(eta_l j) (1 + delta_l[u(j)]),
+ * u(j) the orbit of the sorted |j_i|, one delta per orbit and level (levels
+ * 2 .. L).  delta[(l - 2) nu + u]: nu = orbits per level, u the position of
+ * (a >= b >= c) = sorted |j_i| in the order a = 0 .. 4p-1, b = 0 .. a,
+ * c = 0 .. b, i.e. u = a(a+1)(a+2)/6 + b(b+1)/2 + c.  The near zone keeps G.  Training uses pfmm_learned_accumulate,
+ * pfmm_learned_loss and pfmm_learned_step (Adam on delta) with the same loss
+ * and target as the network; pfmm_learned_set(plan, NULL, 0) restores G.
+ */
+
+/* Number of free values, (L - 1) x orbits per level, into *count.  Prepares
+ * the orbit tables (allocates on first use; synchronises). */
+pfmm_status pfmm_table_params(pfmm_plan_t plan, int* count);
+
+/* Set delta from the host (count floats, see pfmm_table_params) and rebuild
+ * the tables; NULL restores the uncorrected G.  Synchronises. */
+pfmm_status pfmm_table_set(pfmm_plan_t plan, const float* delta);
+
+/* Copy the current delta to the host (count floats).  Fails unless the plan
+ * holds grid-valued tables. */
+pfmm_status pfmm_table_get(pfmm_plan_t plan, float* delta);
+
+/* Start training the grid-valued tables from delta = 0 (exactly G) with Adam
+ * step size lr > 0 (a change of the relative correction per step).
+ * Allocates; synchronises. */
+pfmm_status pfmm_table_train_begin(pfmm_plan_t plan, double lr);
+
+/* Copy the gradient summed over the fields accumulated since the last step
+ * (d loss / d delta, count floats) to the host and clear it, for a driver
+ * that takes its own steps (pfmm_table_set) instead of pfmm_learned_step.
+ * The loss is exactly quadratic in delta (the FMM is linear in its tables),
+ * so a line search along any direction needs one more loss evaluation.
+ * Synchronises. */
+pfmm_status pfmm_table_grad(pfmm_plan_t plan, float* grad);
+
 /* Message describing the calling thread's last failure ("" if none). */
 const char* pfmm_last_error(void);
 

@@ -174,8 +174,10 @@ hipError_t orbit_gather(const double* g, const double* g0, const int* ptr, const
 size_t mlp_backward_partial_floats(int n);
 hipError_t mlp_backward(const float* theta, const float* feats, const float* ddelta, int n,
                         float* part, float* grad, hipStream_t st);
-hipError_t adam_step(float* theta, float* m1, float* m2, float* grad, float count, float lr,
-                     int step, hipStream_t st);
+hipError_t adam_step(float* theta, float* m1, float* m2, float* grad, int n, float count,
+                     float lr, int step, hipStream_t st);
+// dst[i] += src[i], i < n
+hipError_t add_into(float* dst, const float* src, int n, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Upward / downward passes (tensor products of 1D Lagrange operators).

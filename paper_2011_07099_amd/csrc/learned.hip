@@ -311,12 +311,13 @@ __global__ void k_sum_partials(const float* __restrict__ part, int nblk, float* 
   g[i] += s;
 }
 
-// Adam (Kingma & Ba) on the averaged gradient g / count; clears g.
+// Adam (Kingma & Ba) on the averaged gradient g / count over n parameters;
+// clears g.
 __global__ void k_adam(float* __restrict__ th, float* __restrict__ m1, float* __restrict__ m2,
-                       float* __restrict__ g, float count, float lr, float b1, float b2, float eps,
-                       int step) {
+                       float* __restrict__ g, int n, float count, float lr, float b1, float b2,
+                       float eps, int step) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kMlpParams) return;
+  if (i >= n) return;
   const float gi = g[i] / count;
   m1[i] = b1 * m1[i] + (1.f - b1) * gi;
   m2[i] = b2 * m2[i] + (1.f - b2) * gi * gi;
@@ -324,6 +325,11 @@ __global__ void k_adam(float* __restrict__ th, float* __restrict__ m1, float* __
   const float vh = m2[i] / (1.f - powf(b2, (float)step));
   th[i] -= lr * mh / (sqrtf(vh) + eps);
   g[i] = 0.f;
+}
+
+__global__ void k_add_into(float* __restrict__ dst, const float* __restrict__ src, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] += src[i];
 }
 
 inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -392,10 +398,15 @@ hipError_t mlp_backward(const float* theta, const float* feats, const float* dde
   return hipGetLastError();
 }
 
-hipError_t adam_step(float* theta, float* m1, float* m2, float* grad, float count, float lr,
-                     int step, hipStream_t st) {
-  hipLaunchKernelGGL(k_adam, dim3(nb(kMlpParams, 256)), dim3(256), 0, st, theta, m1, m2, grad,
-                     count, lr, 0.9f, 0.999f, 1e-8f, step);
+hipError_t adam_step(float* theta, float* m1, float* m2, float* grad, int n, float count,
+                     float lr, int step, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3(nb(n, 256)), dim3(256), 0, st, theta, m1, m2, grad, n, count,
+                     lr, 0.9f, 0.999f, 1e-8f, step);
+  return hipGetLastError();
+}
+
+hipError_t add_into(float* dst, const float* src, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_into, dim3(nb(n, 256)), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 

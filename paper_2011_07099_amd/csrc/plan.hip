@@ -78,7 +78,8 @@ struct pfmm_plan_s {
   size_t part_floats = 0;
   void* spart = nullptr;          // split-offset partial sums (portable kernel)
   // learned correction of the interaction-zone tables (allocated on first use)
-  int learned = 0;                // 0 none, 1 inference, 2 training
+  int learned = 0;                // 0 none, 1 network inference, 2 network training,
+                                  // 3 grid-valued tables (parameters = delta)
   int nu = 0;                     // unique (|j| sorted) entries per level
   std::vector<double*> g0;        // uncorrected FP64 level tables
   std::vector<int*> uidx, optr, opos;
@@ -90,6 +91,9 @@ struct pfmm_plan_s {
   float* wgrad = nullptr;
   float* ddelta = nullptr;
   float* mlp_part = nullptr;
+  float* gm = nullptr;            // Adam state and gradient of the grid-valued tables
+  float* gv = nullptr;
+  float* ggrad = nullptr;
   float* resid = nullptr;         // mesh scratch: d loss / d phi
   float* tphi = nullptr;          // mesh scratch: forward potential
   double* rpart = nullptr;
@@ -1619,7 +1623,7 @@ pfmm_status learned_apply(pfmm_plan_s* pl, int bf16) {
   const int64_t ntab = cube(2 * C + 1);
   hipStream_t st = pl->stream;
   hipError_t e = hipSuccess;
-  if (pl->learned)
+  if (pl->learned == 1 || pl->learned == 2)
     e = mlp_forward(pl->theta, pl->feats, (pl->L - 1) * pl->nu, bf16, pl->delta, st);
   for (int l = 2; l <= pl->L && e == hipSuccess; ++l) {
     if (pl->learned) {
@@ -1773,7 +1777,8 @@ pfmm_status pfmm_learned_accumulate(pfmm_plan_t pl, const float* rho, const floa
                                     double* loss) {
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
-  if (pl->learned != 2) return fail(PFMM_ERR_INVALID_ARG, "call pfmm_learned_train_begin first");
+  if (pl->learned != 2 && pl->learned != 3)
+    return fail(PFMM_ERR_INVALID_ARG, "call pfmm_learned_train_begin or pfmm_table_train_begin first");
   if (!rho || !target) return fail(PFMM_ERR_INVALID_ARG, "density and target are required");
   const int N = pl->N, L = pl->L, p = pl->p;
   const int64_t n3 = (int64_t)N * N * N;
@@ -1798,8 +1803,12 @@ pfmm_status pfmm_learned_accumulate(pfmm_plan_t pl, const float* rho, const floa
       e = orbit_gather(pl->tgrad[l], pl->g0[l], pl->optr[l], pl->opos[l], pl->nu,
                        pl->ddelta + (size_t)(l - 2) * pl->nu, st);
   }
-  if (e == hipSuccess)
-    e = mlp_backward(pl->theta, pl->feats, pl->ddelta, nent, pl->mlp_part, pl->wgrad, st);
+  if (e == hipSuccess) {
+    if (pl->learned == 3)  // grid-valued tables: ddelta is the parameters' gradient
+      e = add_into(pl->ggrad, pl->ddelta, nent, st);
+    else
+      e = mlp_backward(pl->theta, pl->feats, pl->ddelta, nent, pl->mlp_part, pl->wgrad, st);
+  }
   double stats[3] = {0, 0, 0};
   if (e == hipSuccess)
     e = hipMemcpyAsync(stats, pl->rstats, sizeof stats, hipMemcpyDeviceToHost, st);
@@ -1835,12 +1844,91 @@ pfmm_status pfmm_learned_loss(pfmm_plan_t pl, const float* rho, const float* tar
 pfmm_status pfmm_learned_step(pfmm_plan_t pl) {
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
-  if (pl->learned != 2 || pl->accumulated == 0)
+  if ((pl->learned != 2 && pl->learned != 3) || pl->accumulated == 0)
     return fail(PFMM_ERR_INVALID_ARG, "no accumulated gradient");
-  const hipError_t e = adam_step(pl->theta, pl->adam_m, pl->adam_v, pl->wgrad,
-                                 (float)pl->accumulated, (float)pl->lr, ++pl->adam_t, pl->stream);
+  const hipError_t e =
+      pl->learned == 3
+          ? adam_step(pl->delta, pl->gm, pl->gv, pl->ggrad, (pl->L - 1) * pl->nu,
+                      (float)pl->accumulated, (float)pl->lr, ++pl->adam_t, pl->stream)
+          : adam_step(pl->theta, pl->adam_m, pl->adam_v, pl->wgrad, kMlpParams,
+                      (float)pl->accumulated, (float)pl->lr, ++pl->adam_t, pl->stream);
   if (e != hipSuccess) return hip_fail(e, "adam");
   pl->accumulated = 0;
+  return learned_apply(pl, 0);
+}
+
+pfmm_status pfmm_table_params(pfmm_plan_t pl, int* count) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!count) return fail(PFMM_ERR_INVALID_ARG, "count is NULL");
+  if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
+  const pfmm_status s0 = learned_prepare(pl);
+  if (s0 != PFMM_OK) return s0;
+  *count = (pl->L - 1) * pl->nu;
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_table_set(pfmm_plan_t pl, const float* delta) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!delta) return pfmm_learned_set(pl, nullptr, 0);
+  int n = 0;
+  pfmm_status s0 = pfmm_table_params(pl, &n);
+  if (s0 != PFMM_OK) return s0;
+  const hipError_t e = hipMemcpy(pl->delta, delta, (size_t)n * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload table parameters");
+  pl->learned = 3;
+  pl->accumulated = 0;
+  return learned_apply(pl, 0);
+}
+
+pfmm_status pfmm_table_get(pfmm_plan_t pl, float* delta) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!delta) return fail(PFMM_ERR_INVALID_ARG, "delta is NULL");
+  if (pl->learned != 3) return fail(PFMM_ERR_INVALID_ARG, "the plan has no grid-valued tables");
+  const hipError_t e = hipMemcpy(delta, pl->delta, (size_t)(pl->L - 1) * pl->nu * sizeof(float),
+                                 hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "download table parameters");
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_table_grad(pfmm_plan_t pl, float* grad) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!grad) return fail(PFMM_ERR_INVALID_ARG, "grad is NULL");
+  if (pl->learned != 3 || !pl->ggrad)
+    return fail(PFMM_ERR_INVALID_ARG, "call pfmm_table_train_begin first");
+  const size_t n = (size_t)(pl->L - 1) * pl->nu;
+  hipError_t e = hipMemcpy(grad, pl->ggrad, n * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(pl->ggrad, 0, n * sizeof(float));
+  if (e != hipSuccess) return hip_fail(e, "table gradient");
+  pl->accumulated = 0;
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_table_train_begin(pfmm_plan_t pl, double lr) {
+  g_err.clear();
+  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  if (!(lr > 0.0)) return fail(PFMM_ERR_INVALID_ARG, "need lr > 0");
+  int n = 0;
+  pfmm_status s0 = pfmm_table_params(pl, &n);
+  if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
+  if (s0 != PFMM_OK) return s0;
+  hipError_t e = hipSuccess;
+  if (!pl->gm) e = dalloc(pl, &pl->gm, (size_t)n);
+  if (e == hipSuccess && !pl->gv) e = dalloc(pl, &pl->gv, (size_t)n);
+  if (e == hipSuccess && !pl->ggrad) e = dalloc(pl, &pl->ggrad, (size_t)n);
+  if (e == hipSuccess) e = hipMemset(pl->delta, 0, (size_t)n * 4);
+  if (e == hipSuccess) e = hipMemset(pl->gm, 0, (size_t)n * 4);
+  if (e == hipSuccess) e = hipMemset(pl->gv, 0, (size_t)n * 4);
+  if (e == hipSuccess) e = hipMemset(pl->ggrad, 0, (size_t)n * 4);
+  if (e != hipSuccess) return hip_fail(e, "table training state");
+  pl->learned = 3;
+  pl->adam_t = 0;
+  pl->accumulated = 0;
+  pl->lr = lr;
   return learned_apply(pl, 0);
 }
 

@@ -28,7 +28,8 @@ EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_plan_read",
            "pfmm_batch_destroy",
            "pfmm_plan_direct", "pfmm_learned_set", "pfmm_learned_train_begin",
            "pfmm_learned_accumulate", "pfmm_learned_loss", "pfmm_learned_step", "pfmm_learned_get",
-           "pfmm_learned_read_grad", "pfmm_last_error")
+           "pfmm_learned_read_grad", "pfmm_table_params", "pfmm_table_set", "pfmm_table_get",
+           "pfmm_table_train_begin", "pfmm_table_grad", "pfmm_last_error")
 MLP_PARAMS = 4609
 
 _lib = None
@@ -71,6 +72,11 @@ def load():
     lib.pfmm_learned_train_begin.argtypes = [vp, fp, ctypes.c_double]
     lib.pfmm_learned_accumulate.argtypes = [vp, vp, vp, dp]
     lib.pfmm_learned_loss.argtypes = [vp, vp, vp, dp]
+    lib.pfmm_table_params.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.pfmm_table_set.argtypes = [vp, fp]
+    lib.pfmm_table_get.argtypes = [vp, fp]
+    lib.pfmm_table_train_begin.argtypes = [vp, ctypes.c_double]
+    lib.pfmm_table_grad.argtypes = [vp, fp]
     lib.pfmm_learned_step.argtypes = [vp]
     lib.pfmm_learned_get.argtypes = [vp, fp]
     lib.pfmm_learned_read_grad.argtypes = [vp, i32, dp, fp]
@@ -224,6 +230,43 @@ class Plan:
             return
         w, ptr = self._f32(weights)
         _check(load().pfmm_learned_set(self._h, ptr, 1 if bf16 else 0))
+
+    def table_params(self):
+        """Number of free values of the grid-valued tables (one per cube-
+        symmetry orbit of table entries and level)."""
+        n = ctypes.c_int()
+        _check(load().pfmm_table_params(self._h, ctypes.byref(n)))
+        return n.value
+
+    def set_table(self, delta):
+        """Grid-valued tables T = G (1 + delta[orbit]) (None: back to the plain G)."""
+        import numpy as np
+        if delta is None:
+            _check(load().pfmm_table_set(self._h, None))
+            return
+        d = np.ascontiguousarray(delta, dtype=np.float32)
+        if d.size != self.table_params():
+            raise ValueError("delta must have table_params() entries")
+        _check(load().pfmm_table_set(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def table_values(self):
+        import numpy as np
+        d = np.empty(self.table_params(), np.float32)
+        _check(load().pfmm_table_get(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return d
+
+    def table_train_begin(self, lr):
+        """Train the grid-valued tables (from exactly G) with train_accumulate /
+        train_step."""
+        _check(load().pfmm_table_train_begin(self._h, float(lr)))
+
+    def table_grad(self):
+        """Gradient of the summed loss over the fields accumulated since the
+        last step, d loss / d delta (clears it)."""
+        import numpy as np
+        g = np.empty(self.table_params(), np.float32)
+        _check(load().pfmm_table_grad(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return g
 
     def train_begin(self, weights, lr):
         w, ptr = self._f32(weights)
