@@ -121,9 +121,10 @@ typedef enum {
    * nodes of the 4^3 level, offsets in [-3, 3]^3 \ [-1, 1]^3) keeps only
    * source nodes inside the box.  Needs PFMM_GREEN_X and a plan without
    * learned tables; re-tabulates (plan time).  Isolated plans are not
-   * accepted by batches, the learned-table calls or pfmm_plan_direct, and
-   * the FD4 accelerations of a solve use the periodic stencil (the two
-   * outermost cell layers of each face are not meaningful).  Default 0. */
+   * accepted by batches, the learned-table calls, pfmm_plan_direct or the
+   * FFT interaction zones.  With PFMM_ACCEL_FD4 the accelerations use the
+   * periodic stencil (the two outermost cell layers of each face are not
+   * meaningful); PFMM_ACCEL_EXPANSION gives them everywhere.  Default 0. */
   PFMM_OPT_ISOLATED = 6,
   /* value: double a_2 of the G_S ansatz (Sec. 3); only for PFMM_GREEN_S.
    * Re-tabulates G synchronously. */
