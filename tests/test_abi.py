@@ -75,3 +75,33 @@ def test_invalid_batch_arguments():
     assert lib.pfmm_batch_create(1, arr, arr, arr, None) == 1
     assert lib.pfmm_batch_solve(ctypes.c_void_p(0x1234)) == 1
     assert lib.pfmm_batch_destroy(None) == 0
+
+
+def test_header_is_plain_c_and_links():
+    """include/pfmm.h compiles as C99 on its own, and a C program that takes
+    the address of every declared function links against libpfmm.so."""
+    import shutil
+    import subprocess
+    from paper_2011_07099_amd import pfmm
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    work = os.path.join(ROOT, "_build", "abi_c")  # build scratch, ignored by git
+    os.makedirs(work, exist_ok=True)
+    src = os.path.join(work, "use.c")
+    names = _declared()
+    open(src, "w").write('#include "pfmm.h"\n#include <stdio.h>\nint main(void) {\n'
+                   "  const void* f[] = {%s};\n"
+                   '  printf("%%d\\n", (int)(sizeof f / sizeof f[0]));\n  return 0;\n}\n'
+                   % ", ".join("(const void*)&" + n for n in names))
+    inc = os.path.join(ROOT, "include")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", inc, str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    if not os.path.exists(pfmm.LIB_PATH):
+        pytest.skip("libpfmm.so not built")
+    exe = os.path.join(work, "use")
+    libdir = os.path.dirname(pfmm.LIB_PATH)
+    r = subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe), "-L", libdir,
+                        "-lpfmm", "-Wl,-rpath," + libdir], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
