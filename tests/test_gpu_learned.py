@@ -8,7 +8,7 @@
   residual of ~1e-3 |phi| at p = 4: tolerance 1e-3 relative.
 * Fallback and inference: zero output layer = plain G; NULL restores G.
 * Training: the loss falls, and the trained network lowers the FMM-vs-PM
-  error on unseen fields (PM with the same G from the oracle as the judge).
+  error on unseen fields (PM with the same G from the oracle as the reference).
 """
 import numpy as np
 import pytest
