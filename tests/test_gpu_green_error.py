@@ -18,6 +18,10 @@ interaction zone in FP64.
   multipole-expansion error (the twin's own error) for p = 4 .. 8.
 * The 4-level tree (Fig. 5, bottom row: 256^3, L = 4): the corner source's
   Green's-function and expansion errors of G_S1 for p = 4, 6, 8.
+* Figs. 3-4: with the "exact-in-real-space" G_X the corner source's error
+  exceeds 100 % of the characteristic acceleration (aliasing at half the box);
+  G_S1 lowers it by about three orders of magnitude (the colour bar of Fig. 4
+  is 100x smaller).
 * The variant whose map is t + O(t^7) (a_1 = -25/128, a_2 = 3/128): Sec. 3
   reports that it makes the error markedly worse than G_S1.  Measured: worse
   from p = 6 on, increasingly with p (L2 x1.13 at p = 6, x1.56 at p = 8, where
@@ -252,3 +256,20 @@ def test_corner_errors_on_the_four_level_tree(p):
           % (p, gf[0], gf[1], me[0], me[1]))
     # Fig. 5: the Green's-function error stays below or about the expansion error
     assert gf[0] < 2.0 * me[0]
+
+
+def test_gx_aliasing_against_gs1(runner):
+    p = runner.p
+    if p != 6:
+        pytest.skip("Figs. 3-4 use N_g = 6")
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    with Plan(N, L, p, "X", accel="expansion", fp64_levels=L - 1) as px:
+        g = runner._accel(px, [[0, 0, 0]], [1.0])
+    e_x = g - metric.point_sources_accel(N, [[0, 0, 0]], [1.0], "X")
+    gx = metric.norms(metric.delta_g(e_x, runner.corner_twin))
+    gs = metric.norms(metric.delta_g(runner.periodic_error([[0, 0, 0]], [1.0], -0.125),
+                                     runner.corner_twin))
+    print("corner, p=6: G_X L2 %.3e L_MAX %.3e | G_S1 L2 %.3e L_MAX %.3e | ratio L_MAX %.0f"
+          % (gx[0], gx[1], gs[0], gs[1], gx[1] / gs[1]))
+    assert gx[1] > 1.0 and gx[1] > 300 * gs[1]
