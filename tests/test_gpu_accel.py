@@ -52,3 +52,26 @@ def test_gs_second_coefficient_t7_variant():
     e, ep = rel_max(out["accel"], ref), rel_max(out["phi"], ref_phi)
     print("G_S t^7 variant: accel %.3e potential %.3e" % (e, ep))
     assert e < 2e-5 and ep < 2e-5
+
+
+@pytest.mark.parametrize("N,L,p,green,a", [
+    (32, 3, 8, "S1", None),    # s = 4 < p: the interpolant is evaluated between fewer cells
+    (8, 3, 2, "S1", None),     # s = 1
+    (32, 3, 5, "K", None),     # odd p, G_K
+    (32, 3, 4, "E", (0.1,)),   # Ewald G_E
+])
+def test_expansion_accel_edge_cases(N, L, p, green, a):
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    rho = f32(fields.lognormal(N, 2.0, 1.0, seed=68 + N + p))
+    r = torch.from_numpy(rho.astype(np.float32)).cuda()
+    phi = torch.empty_like(r)
+    acc = torch.empty((3, N, N, N), dtype=torch.float32, device="cuda")
+    kw = {"rs": a[0]} if green == "E" else {}
+    with Plan(N, L, p, green, accel="expansion", **kw) as pl:
+        pl.solve(r, phi, acc)
+        torch.cuda.synchronize()
+    ref, _ = ofmm.fmm_accel(rho, L, p, green, a=a if a else (-0.125,))
+    e = rel_max(acc.cpu().numpy().astype(np.float64), ref)
+    print("expansion accel edge", (N, L, p, green), "%.3e" % e)
+    assert e < 2e-5

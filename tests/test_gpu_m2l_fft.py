@@ -44,6 +44,9 @@ def _solve_stages(rho, L, p, green, m2l, fp64_levels=None):
     (64, 3, 8, "S1", None),
     (128, 4, 4, "K", None),
     (64, 2, 8, "S1", None),
+    (32, 3, 3, "X", None),     # odd p: 24^3 grids at levels >= 3
+    (32, 3, 5, "S1", 0),       # odd p, every level in FP32
+    (16, 2, 2, "K", None),     # the smallest tree
 ])
 def test_fft_zones_match_reference_and_gemm(N, L, p, green, f64):
     rho = f32(fields.lognormal(N, 2.0, 1.0, seed=81 + N + p))
