@@ -123,9 +123,9 @@ __global__ void k_reduce_groups(const float* __restrict__ part, int groups, int6
                                 float* __restrict__ Y, int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float s = accumulate ? Y[i] : 0.f;
-  for (int g = 0; g < groups; ++g) s += part[(int64_t)g * n + i];
-  Y[i] = s;
+  double s = accumulate ? (double)Y[i] : 0.0;  // the group partials are added in FP64
+  for (int g = 0; g < groups; ++g) s += (double)part[(int64_t)g * n + i];
+  Y[i] = (float)s;
 }
 
 struct Tile {
