@@ -339,6 +339,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="headline", choices=["headline", "batch", "learned", "m2l", "table"])
     ap.add_argument("--epochs", type=int, default=2, help="training epochs (learned workload)")
+    ap.add_argument("--accel", default="none", choices=["none", "fd4", "expansion"],
+                    help="also form accelerations (headline workload): by differences of "
+                         "the potential or from the expansion")
     ap.add_argument("--iters", type=int, default=20,
                     help="conjugate-gradient iterations (table workload)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -375,15 +378,18 @@ def main():
     rho = torch.from_numpy(rho32).to(dev)
     phi = torch.empty_like(rho)
     stream = torch.cuda.current_stream(dev)
-    plan = Plan(N, L, P, GREEN, precision=args.precision, stream=stream)
+    plan = Plan(N, L, P, GREEN, precision=args.precision, stream=stream,
+                accel="expansion" if args.accel == "expansion" else "fd4")
+    acc = (torch.empty((3, N, N, N), dtype=torch.float32, device=dev)
+           if args.accel != "none" else None)
     for _ in range(args.warmup):
-        plan.solve(rho, phi)
+        plan.solve(rho, phi, acc)
     torch.cuda.synchronize()
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     t_start.record(stream)
     for _ in range(args.steps):
-        plan.solve(rho, phi)
+        plan.solve(rho, phi, acc)
     t_end.record(stream)
     torch.cuda.synchronize()
     ms = t_start.elapsed_time(t_end) / args.steps
@@ -392,12 +398,14 @@ def main():
     # beside it), after the timed region
     plan.set_profile(True)
     for _ in range(min(args.steps, 10)):
-        plan.solve(rho, phi)
+        plan.solve(rho, phi, acc)
     stages = plan.stage_times()
     m2l_levels = plan.level_times("m2l")
     plan.close()
 
     near_flops, m2l_flops = algorithmic_flops(N, L, P)
+    if args.accel == "expansion":
+        near_flops *= 4  # the potential's near zone and one per acceleration component
     peak = PEAK_TFLOPS[args.precision]
     near_ms = stages["near"][0]
     m2l_ms = stages["m2l"][0]
@@ -432,11 +440,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "periodic FMM, 256^3 lognormal density (P(k)~k^-1.5, "
                                "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
-                   "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision},
+                   "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision,
+                   **({"accel": args.accel} if args.accel != "none" else {})},
         "roofline": {"bound": "mfma" if near_unit.endswith("mfma") else "alu",
                      "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
                      "frac": near_tf / peak, "traffic": traffic_bytes(args.precision),
-                     "kernel": "near zone (%d launch/step, %.3f ms)" % (stages["near"][1], near_ms),
+                     "kernel": "near zone (%d launch/step, %.3f ms)" % (
+                         4 if args.accel == "expansion" else 1, near_ms),
                      "unit_used": near_unit, "products": near_products,
                      "issued_frac": near_tf * near_products / peak},
         "m2l": {"achieved": m2l_tf, "unit": "TFLOP/s", "ms": m2l_ms,
