@@ -1068,6 +1068,10 @@ struct pfmm_batch_s {
   hipStream_t caller = nullptr;  // stream of plans[0]; solves are ordered with it
   hipStream_t stream = nullptr;  // the batch's own stream (captured into the graph)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // the matrix-core persistent kernels run beside the portable one (their
+  // outputs are disjoint): two more streams, forked and joined by events
+  hipStream_t s_split = nullptr, s_f64 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_split = nullptr, ev_f64 = nullptr;
   BatchItem* items = nullptr;  // device work list (portable kernel)
   unsigned* counter = nullptr;  // [0] portable, [1] split, [2] FP64 matrix-core list
   int nitems = 0, grid = 0;
@@ -1111,6 +1115,13 @@ void brelease(pfmm_batch_s* b) {
   if (b->fitems) (void)hipFree(b->fitems);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  for (hipEvent_t ev : {b->ev_fork, b->ev_split, b->ev_f64})
+    if (ev) (void)hipEventDestroy(ev);
+  for (hipStream_t s : {b->s_split, b->s_f64})
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
@@ -1297,12 +1308,26 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
                        kNearTerms, pl->xsn, st);
     }
   }
-  if (e == hipSuccess && (part == 0 || part == 2 || part == 4))
+  if (e == hipSuccess && (part == 0 || part == 2)) {
+    // the three persistent kernels read only the upward passes' outputs and
+    // write disjoint buffers (a field's near zone and each level go to exactly
+    // one list), so they run side by side: the tail of one fills with the
+    // others' workgroups
+    e = hipEventRecord(b->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->s_split, b->ev_fork, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->s_f64, b->ev_fork, 0);
+    if (e == hipSuccess)
+      e = launch_batch_mma(2, b->sargs, b->sitems, b->nsplit, b->counter + 1, b->sgrid, b->s_split);
+    if (e == hipSuccess)
+      e = launch_batch_mma(64, b->fargs, b->fitems, b->nf64, b->counter + 2, b->fgrid, b->s_f64);
+    if (e == hipSuccess) e = launch_batch_toeplitz(b->items, b->nitems, b->counter, b->grid, st);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_split, b->s_split);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_f64, b->s_f64);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_split, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_f64, 0);
+  } else if (e == hipSuccess && part == 4) {
     e = launch_batch_toeplitz(b->items, b->nitems, b->counter, b->grid, st);
-  if (e == hipSuccess && (part == 0 || part == 2))
-    e = launch_batch_mma(2, b->sargs, b->sitems, b->nsplit, b->counter + 1, b->sgrid, st);
-  if (e == hipSuccess && (part == 0 || part == 2))
-    e = launch_batch_mma(64, b->fargs, b->fitems, b->nf64, b->counter + 2, b->fgrid, st);
+  }
   if (e == hipSuccess && (part == 0 || part == 3)) {
     for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
       pfmm_plan_s* pl = b->plans[f];
@@ -1400,6 +1425,10 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
   hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->s_split, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->s_f64, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&b->ev_fork, &b->ev_split, &b->ev_f64})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   // inputs written on the caller's stream must be visible to the tuning runs
   if (e == hipSuccess) e = hipStreamSynchronize(b->caller);
   if (e == hipSuccess) e = hipMalloc(&b->counter, 3 * sizeof(unsigned));
