@@ -37,13 +37,14 @@ PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 157.3}
 FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 
 # HBM bytes per launch of the near-zone kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB), scaled by a plain 1 GiB copy (read x2.0, write x1.0), keyed
+# WRITE_SIZE (KiB; the mean of the two profiled solves' launches), scaled by a
+# plain 1 GiB copy (read x2.0, write x1.0), keyed
 # by precision and the SHA-1 prefix of the sources they were taken on (the
 # kernel and plan.hip, which sets the offset order); a changed source reports
 # null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md
 TRAFFIC = {
-    ("bf16x3", "9cdf73661578"): (1189339 * 2.0 + 65536 * 1.0) * 1024,
-    ("fp32", "05ab7beb0956"): (11776995 * 2.0 + 71579 * 1.0) * 1024,
+    ("bf16x3", "13cab9468dc2"): (1197910 * 2.0 + 65536 * 1.0) * 1024,
+    ("fp32", "caae94d8dbb6"): (11728392 * 2.0 + 68658 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
 
