@@ -343,6 +343,9 @@ def main():
     ap.add_argument("--accel", default="none", choices=["none", "fd4", "expansion"],
                     help="also form accelerations (headline workload): by differences of "
                          "the potential or from the expansion")
+    ap.add_argument("--near", default="direct", choices=["direct", "fft"],
+                    help="leaf near zone by direct summation or by FFT convolution "
+                         "(headline workload)")
     ap.add_argument("--iters", type=int, default=20,
                     help="conjugate-gradient iterations (table workload)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -380,7 +383,7 @@ def main():
     phi = torch.empty_like(rho)
     stream = torch.cuda.current_stream(dev)
     plan = Plan(N, L, P, GREEN, precision=args.precision, stream=stream,
-                accel="expansion" if args.accel == "expansion" else "fd4")
+                accel="expansion" if args.accel == "expansion" else "fd4", near=args.near)
     acc = (torch.empty((3, N, N, N), dtype=torch.float32, device=dev)
            if args.accel != "none" else None)
     for _ in range(args.warmup):
@@ -442,7 +445,8 @@ def main():
         "config": {"workload": "periodic FMM, 256^3 lognormal density (P(k)~k^-1.5, "
                                "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
                    "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision,
-                   **({"accel": args.accel} if args.accel != "none" else {})},
+                   **({"accel": args.accel} if args.accel != "none" else {}),
+                   **({"near": args.near} if args.near != "direct" else {})},
         "roofline": {"bound": "mfma" if near_unit.endswith("mfma") else "alu",
                      "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
                      "frac": near_tf / peak, "traffic": traffic_bytes(args.precision),

@@ -140,8 +140,30 @@ typedef enum {
    * to PFMM_M2L_FFT creates FFT plans and up to 1 GiB of grids and transforms
    * the level tables (plan time; transformed again when G changes).  Not for
    * isolated plans, batches or learned tables.  Default PFMM_M2L_GEMM. */
-  PFMM_OPT_M2L = 10
+  PFMM_OPT_M2L = 10,
+  /* value: int32 pfmm_near, how the leaf near zone is summed.  Switching to
+   * PFMM_NEAR_FFT creates FFT plans and about 100 bytes of buffers per cell
+   * and transforms the near-zone kernels (plan time; transformed again when G
+   * or PFMM_OPT_ACCEL changes).  Not for batches.  Default PFMM_NEAR_DIRECT. */
+  PFMM_OPT_NEAR = 11
 } pfmm_option;
+
+/* Leaf near-zone algorithm (the 27 neighbour leaves, Sec. 2). */
+typedef enum {
+  /* Direct summation as a block-Toeplitz GEMM over the 27 leaf offsets
+   * (matrix cores or the portable kernel, as PFMM_OPT_PRECISION selects). */
+  PFMM_NEAR_DIRECT = 0,
+  /* FFT convolution on the doubled grid, the route the paper takes (Sec. 2
+   * and 3): each leaf's cells zero-padded to (2s)^3 and transformed once
+   * (rocFFT, FP32), the 27 neighbours' transforms multiplied by the
+   * transformed kernels G(h (m - s e)) (FP64 DFT at plan time, stored FP32)
+   * and added per frequency, one inverse transform per leaf.  The cyclic
+   * convolution on 2s points equals the linear one at the target cells.
+   * Same sums as the direct route up to rounding; the precision option
+   * does not apply to it.  With PFMM_ACCEL_EXPANSION the three acceleration
+   * kernels reuse the forward transforms. */
+  PFMM_NEAR_FFT = 1
+} pfmm_near;
 
 /* Interaction-zone (M2L, Eq. 6) algorithm. */
 typedef enum {

@@ -223,6 +223,26 @@ hipError_t m2l_fft_tables(M2LFft* f, const std::vector<double*>& tab64, hipStrea
 hipError_t m2l_fft_level(M2LFft* f, int l, const void* Ml, void* Pl, int fp64, int accumulate,
                          hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Leaf near zone by FFT convolution on the doubled grid (Sec. 2-3)
+// ---------------------------------------------------------------------------
+struct NearFft;
+// Plans and buffers for N^3 cells in leaves of s^3 (about 100 bytes per cell);
+// allocates.
+hipError_t near_fft_create(int N, int s, NearFft** out);
+void near_fft_destroy(NearFft* f);
+// Transform the near-zone kernels of `ntabs` (1 .. 4) FP64 tables (centred,
+// edge 4s - 1, indexed by target minus source cell) times `scale`; allocates
+// the kernels on first use and synchronises `st`.
+hipError_t near_fft_tables(NearFft* f, const double* const* tabs, int ntabs, double scale,
+                           hipStream_t st);
+// Kernels transformed so far.
+int near_fft_kernels(const NearFft* f);
+// out[t] = the near zone of rho with kernel t, t < nout (written, not added);
+// isolated: sources outside the box are absent instead of periodic images.
+hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
+                        hipStream_t st);
+
 // FP64 -> FP32 copy of n elements.
 hipError_t launch_cast_d2f(const double* src, float* dst, int64_t n, hipStream_t st);
 

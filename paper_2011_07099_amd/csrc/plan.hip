@@ -60,6 +60,8 @@ struct pfmm_plan_s {
   int isolated = 0;               // no periodic images (PFMM_OPT_ISOLATED)
   int m2l_fft = 0;                // interaction zones by FFT convolution (PFMM_OPT_M2L)
   M2LFft* fft = nullptr;          // its plans, grids and transformed kernels
+  int near_fft = 0;               // leaf near zone by FFT convolution (PFMM_OPT_NEAR)
+  NearFft* nfft = nullptr;        // its plans, buffers and transformed kernels
   uint16_t* zero = nullptr;       // 512 zero bf16 values: the source outside an isolated box
   // accelerations from the expansion (PFMM_OPT_ACCEL; tables on first use)
   int accel_mode = 0;
@@ -196,6 +198,8 @@ hipError_t dalloc(pfmm_plan_s* pl, T** ptr, size_t count) {
 void release(pfmm_plan_s* pl) {
   if (pl->fft) m2l_fft_destroy(pl->fft);
   pl->fft = nullptr;
+  if (pl->nfft) near_fft_destroy(pl->nfft);
+  pl->nfft = nullptr;
   for (hipEvent_t e : pl->ev)
     if (e) (void)hipEventDestroy(e);
   pl->ev.clear();
@@ -239,6 +243,19 @@ GreenSpec green_spec(const pfmm_plan_s* pl) {
   return g;
 }
 
+// Transformed kernels of the FFT near zone: G, and the three acceleration
+// kernels when accelerations come from the expansion
+pfmm_status refresh_near_fft(pfmm_plan_s* pl) {
+  if (!pl->nfft) return PFMM_OK;
+  const double* tabs[4] = {pl->ntab64, pl->ndtab64[0], pl->ndtab64[1], pl->ndtab64[2]};
+  const int n = pl->accel_mode ? 4 : 1;
+  const double h3 = 1.0 / ((double)pl->N * pl->N * pl->N);
+  const hipError_t e = near_fft_tables(pl->nfft, tabs, n, h3, pl->stream);
+  if (e == hipErrorOutOfMemory) return fail(PFMM_ERR_OUT_OF_MEMORY, "FFT near-zone kernels");
+  if (e != hipSuccess) return hip_fail(e, "FFT near-zone kernels");
+  return PFMM_OK;
+}
+
 // Near-zone acceleration kernels of the plan's G (allocated on first use)
 pfmm_status tabulate_accel_tables(pfmm_plan_s* pl) {
   const int Cn = 2 * pl->s - 1;
@@ -259,7 +276,7 @@ pfmm_status tabulate_accel_tables(pfmm_plan_s* pl) {
   }
   if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
   if (e != hipSuccess) return hip_fail(e, "acceleration tables");
-  return PFMM_OK;
+  return refresh_near_fft(pl);
 }
 
 pfmm_status tabulate_all(pfmm_plan_s* pl) {
@@ -292,7 +309,7 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
     e = m2l_fft_tables(pl->fft, pl->tab64, pl->stream);
     if (e != hipSuccess) return hip_fail(e, "FFT kernels");
   }
-  return pl->accel_mode ? tabulate_accel_tables(pl) : PFMM_OK;
+  return pl->accel_mode ? tabulate_accel_tables(pl) : refresh_near_fft(pl);
 }
 
 // Offset groups of a level's matrix-core launch: enough workgroups to give
@@ -710,6 +727,28 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       pl->m2l_fft = v;
       return PFMM_OK;
     }
+    case PFMM_OPT_NEAR: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "near-zone mode is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      if (v != PFMM_NEAR_DIRECT && v != PFMM_NEAR_FFT)
+        return fail(PFMM_ERR_INVALID_ARG, "unknown near-zone mode");
+      if (v == PFMM_NEAR_FFT && !pl->nfft) {
+        NearFft* f = nullptr;
+        const hipError_t e = near_fft_create(pl->N, pl->s, &f);
+        if (e == hipErrorOutOfMemory) return fail(PFMM_ERR_OUT_OF_MEMORY, "FFT near-zone buffers");
+        if (e != hipSuccess) return hip_fail(e, "FFT near-zone plans");
+        pl->nfft = f;
+        const pfmm_status r = refresh_near_fft(pl);
+        if (r != PFMM_OK) {
+          near_fft_destroy(pl->nfft);
+          pl->nfft = nullptr;
+          return r;
+        }
+      }
+      pl->near_fft = v;
+      return PFMM_OK;
+    }
     case PFMM_OPT_FP64_LEVELS: {
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fp64 levels is an int32");
       int32_t v;
@@ -833,7 +872,13 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   nb.accumulate = 0;
   nb.groups = 1;
   nb.isolated = pl->isolated;
-  if (mx && pl->nwin) {
+  if (pl->near_fft) {
+    float* outs[4] = {phi, nullptr, nullptr, nullptr};
+    int nout = 1;
+    if (accel && pl->accel_mode)
+      for (int c = 0; c < 3; ++c) outs[nout++] = accel + (size_t)c * N * N * N;
+    e = near_fft_run(pl->nfft, rho, outs, nout, pl->isolated, sn);
+  } else if (mx && pl->nwin) {
     e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xsn, sn);
     if (e == hipSuccess) {
       ToepMfmaArgs ma{};
@@ -1410,6 +1455,10 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
     if (plans[i]->m2l_fft) {
       delete b;
       return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with FFT interaction zones");
+    }
+    if (plans[i]->near_fft) {
+      delete b;
+      return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with the FFT near zone");
     }
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) {

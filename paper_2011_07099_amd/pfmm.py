@@ -15,8 +15,9 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP = range(5)
 GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3, "E": 4}
 PREC = {"fp32": 0, "bf16x3": 1}
 OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED, OPT_GS_A2, \
-    OPT_ACCEL, OPT_EWALD_RS, OPT_M2L = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
+    OPT_ACCEL, OPT_EWALD_RS, OPT_M2L, OPT_NEAR = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
 M2L = {"gemm": 0, "fft": 1}
+NEAR = {"direct": 0, "fft": 1}
 ACCEL = {"fd4": 0, "expansion": 1}
 STAGES = ("p2m", "m2m", "m2l", "l2l", "l2p", "near", "fd4")
 BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
@@ -108,7 +109,8 @@ class Plan:
     """
 
     def __init__(self, N, L, p, green="S1", precision="fp32", a1=None, stream=None,
-                 fp64_levels=None, isolated=False, a2=None, accel="fd4", rs=None, m2l="gemm"):
+                 fp64_levels=None, isolated=False, a2=None, accel="fd4", rs=None, m2l="gemm",
+                 near="direct"):
         import torch
         lib = load()
         h = ctypes.c_void_p()
@@ -137,6 +139,14 @@ class Plan:
             self.set_accel(accel)
         if m2l != "gemm":
             self.set_m2l(m2l)
+        if near != "direct":
+            self.set_near(near)
+
+    def set_near(self, mode):
+        """Leaf near zone by "direct" summation (block Toeplitz) or "fft"
+        (convolution on the doubled grid, one transform per leaf)."""
+        v = ctypes.c_int32(NEAR[mode])
+        _check(load().pfmm_plan_set(self._h, OPT_NEAR, ctypes.byref(v), 4))
 
     def set_m2l(self, mode):
         """Interaction zones of the FP32 levels by "gemm" (block Toeplitz) or
