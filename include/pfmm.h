@@ -161,7 +161,11 @@ typedef enum {
    * convolution on 2s points equals the linear one at the target cells.
    * Same sums as the direct route up to rounding; the precision option
    * does not apply to it.  With PFMM_ACCEL_EXPANSION the three acceleration
-   * kernels reuse the forward transforms. */
+   * kernels reuse the forward transforms.  For leaf edges s = 4, 8, 16 the
+   * transforms are the library's own (one workgroup per leaf, in LDS, reading
+   * and writing the mesh directly); other s use rocFFT on zero-padded blocks.
+   * pfmm_solve then needs density, potential and accel 16-byte aligned
+   * (PFMM_ERR_INVALID_ARG otherwise). */
   PFMM_NEAR_FFT = 1
 } pfmm_near;
 

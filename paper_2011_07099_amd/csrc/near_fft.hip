@@ -17,8 +17,16 @@
 // 2 (s^3)^2 flops per leaf pair this costs O(s^3 log s) per leaf.
 //
 // The kernels are transformed once per table (plan time) by a separable
-// FP64 DFT; the per-solve transforms are rocFFT R2C / C2R in FP32.  The same
-// machinery serves the acceleration kernels D_i (they replace G).
+// FP64 DFT.  Per solve, for leaf edges s = 4, 8, 16 one workgroup per leaf
+// reads the leaf's cells straight from the mesh and transforms them in LDS,
+// skipping the zero half of every axis (only s of the 2s inputs of a forward
+// pass, and only s of the 2s outputs of an inverse pass, are ever nonzero or
+// needed), and the inverse writes the target cells straight into the mesh;
+// spectra are stored in chunks of 64 frequencies over all leaves, so that
+// the 27-point stencil of one chunk reads 64 x 8 B contiguous per leaf and
+// its whole working set (64 x 8 B x leaves: 2 MiB at 16^3 leaves) stays in
+// one XCD's L2.  Other leaf edges use rocFFT R2C / C2R on zero-padded blocks.
+// The same machinery serves the acceleration kernels D_i (they replace G).
 #include "internal.h"
 
 #include <hipfft/hipfft.h>
@@ -39,6 +47,8 @@ struct NearFft {
   float2* yhat = nullptr;    // [nleaf][F]
   float2* khat[4] = {nullptr, nullptr, nullptr, nullptr};  // [27][F] per kernel
   double2* dft[2] = {nullptr, nullptr};                    // [F] FP64 DFT passes
+  int fused = 0;             // s in {4, 8, 16}: fused LDS transforms, chunked spectra
+  int lgnb = 0;              // log2 of leaves per axis
 };
 
 namespace {
@@ -143,22 +153,267 @@ __global__ void k_unpack(const float* __restrict__ pad, int N, int s, int nb, in
   out[i] = accumulate ? out[i] + v : v;
 }
 
+// exp(-2 pi i j / 32) = cos32(j) - i sin32(j).  With the DFT loops below
+// fully unrolled, j is a compile-time constant and these fold to literals.
+__device__ constexpr float kQuarter[9] = {1.0f, 0.98078528040f, 0.92387953251f, 0.83146961230f,
+                                          0.70710678119f, 0.55557023302f, 0.38268343237f,
+                                          0.19509032202f, 0.0f};
+__device__ __forceinline__ float cos32(int j) {
+  j &= 31;
+  if (j <= 8) return kQuarter[j];
+  if (j <= 16) return -kQuarter[16 - j];
+  if (j <= 24) return -kQuarter[j - 16];
+  return kQuarter[32 - j];
+}
+__device__ __forceinline__ float sin32(int j) { return cos32(j - 8); }
+
+// Twiddle exp(-2 pi i j / M) as (cos, sin) of the positive angle, M | 32.
+template <int M>
+__device__ __forceinline__ float2 tw(int j) {
+  constexpr int r = 32 / M;
+  return make_float2(cos32(j * r), sin32(j * r));
+}
+
+// Address of frequency f of leaf `leaf` in the chunked spectrum layout:
+// [F / 64][leaves][64].
+__device__ __forceinline__ int64_t chunk_addr(int f, int64_t leaf, int64_t nleaf) {
+  return ((int64_t)(f >> 6) * nleaf + leaf) * 64 + (f & 63);
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// a exp(-2 pi i j / P) (forward) or a exp(+2 pi i j / P) (INV)
+template <int P, bool INV>
+__device__ __forceinline__ float2 twiddle(float2 a, int j) {
+  const float2 w = tw<P>(j);
+  return INV ? make_float2(a.x * w.x - a.y * w.y, a.y * w.x + a.x * w.y)
+             : make_float2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 b0 = cadd(a0, a2), b1 = csub(a0, a2), b2 = cadd(a1, a3), b3 = csub(a1, a3);
+  const float2 ib3 = make_float2(-b3.y, b3.x);
+  a0 = cadd(b0, b2);
+  a2 = csub(b0, b2);
+  a1 = INV ? cadd(b1, ib3) : csub(b1, ib3);
+  a3 = INV ? csub(b1, ib3) : cadd(b1, ib3);
+}
+
+// In-place DFT of P = 4Q values (Q = 1, 2, 4), v[m] <- sum_n v[n] exp(-+2 pi i n m / P),
+// by the split n = Q n1 + n2, m = m1 + 4 m2: length-4 DFTs over n1, twiddles
+// exp(-+2 pi i n2 m1 / P), length-Q DFTs over n2.
+template <int P, bool INV>
+__device__ __forceinline__ void dft(float2 (&v)[P]) {
+  constexpr int Q = P / 4;
+  float2 T[Q][4];
+#pragma unroll
+  for (int n2 = 0; n2 < Q; ++n2) {
+    T[n2][0] = v[n2];
+    T[n2][1] = v[Q + n2];
+    T[n2][2] = v[2 * Q + n2];
+    T[n2][3] = v[3 * Q + n2];
+    dft4<INV>(T[n2][0], T[n2][1], T[n2][2], T[n2][3]);
+#pragma unroll
+    for (int m1 = 1; m1 < 4; ++m1)
+      if (n2) T[n2][m1] = twiddle<P, INV>(T[n2][m1], n2 * m1);
+  }
+#pragma unroll
+  for (int m1 = 0; m1 < 4; ++m1) {
+    if constexpr (Q == 1) {
+      v[m1] = T[0][m1];
+    } else if constexpr (Q == 2) {
+      v[m1] = cadd(T[0][m1], T[1][m1]);
+      v[m1 + 4] = csub(T[0][m1], T[1][m1]);
+    } else {
+      float2 c0 = T[0][m1], c1 = T[1][m1], c2 = T[2][m1], c3 = T[3][m1];
+      dft4<INV>(c0, c1, c2, c3);
+      v[m1] = c0;
+      v[m1 + 4] = c1;
+      v[m1 + 8] = c2;
+      v[m1 + 12] = c3;
+    }
+  }
+}
+
+// Threads per leaf: every pass has at most s (s + 1) tasks, one per thread.
+template <int S>
+constexpr int leaf_threads() { return (S * (S + 1) + 63) / 64 * 64; }
+
+// Forward transform of one leaf: its s^3 cells (read from the mesh) on the
+// (2s)^3 cyclic grid, zero beyond s on every axis, to the half spectrum
+// X[kx][ky][kz], kz <= s, written in the chunked layout.  z: direct real DFT
+// of the s inputs to s + 1 outputs.  y and x: s inputs to 2s outputs, split
+// by output parity, X[2m] = DFT_s(u)[m] and X[2m + 1] = DFT_s(u_n w^n)[m]
+// with w = exp(-2 pi i / 2s); the y pass runs once per parity of ky so that
+// LDS holds one half of its output at a time.
+template <int S>
+__global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __restrict__ rho, int N, int lgnb,
+                                                        int64_t nleaf, float2* __restrict__ rhat) {
+  constexpr int M = 2 * S, H = S + 1;
+  __shared__ float2 A1[S * S * H];  // [x][y][kz]
+  __shared__ float2 A2[S * S * H];  // [x][m][kz], ky = 2m + parity
+  const int64_t leaf = blockIdx.x;
+  const int msk = (1 << lgnb) - 1;
+  const int bz = (int)(leaf & msk), by = (int)((leaf >> lgnb) & msk), bx = (int)(leaf >> (2 * lgnb));
+  for (int r = threadIdx.x; r < S * S; r += leaf_threads<S>()) {
+    const int x = r / S, y = r % S;
+    const float4* src = reinterpret_cast<const float4*>(
+        rho + ((int64_t)(bx * S + x) * N + (by * S + y)) * N + (int64_t)bz * S);
+    // kz = 2m: DFT_s of the row; kz = 2m + 1: DFT_s of the row times w^z
+    float2 e[S], o[S];
+#pragma unroll
+    for (int q = 0; q < S / 4; ++q) {
+      const float4 a = src[q];
+      e[4 * q] = make_float2(a.x, 0.0f);
+      e[4 * q + 1] = make_float2(a.y, 0.0f);
+      e[4 * q + 2] = make_float2(a.z, 0.0f);
+      e[4 * q + 3] = make_float2(a.w, 0.0f);
+    }
+#pragma unroll
+    for (int z = 0; z < S; ++z) o[z] = twiddle<M, false>(e[z], z);
+    dft<S, false>(e);
+    dft<S, false>(o);
+    float2* row = A1 + (x * S + y) * H;
+#pragma unroll
+    for (int m = 0; m < S / 2; ++m) {
+      row[2 * m] = e[m];
+      row[2 * m + 1] = o[m];
+    }
+    row[S] = e[S / 2];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
+      const int x = r / H, kz = r % H;
+      float2 u[S];
+#pragma unroll
+      for (int y = 0; y < S; ++y) {
+        u[y] = A1[(x * S + y) * H + kz];
+        if (h) u[y] = twiddle<M, false>(u[y], y);
+      }
+      dft<S, false>(u);
+#pragma unroll
+      for (int m = 0; m < S; ++m) A2[(x * S + m) * H + kz] = u[m];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
+      const int m = r / H, kz = r % H;
+      float2 e[S], o[S];
+#pragma unroll
+      for (int x = 0; x < S; ++x) {
+        e[x] = A2[(x * S + m) * H + kz];
+        o[x] = twiddle<M, false>(e[x], x);
+      }
+      dft<S, false>(e);
+      dft<S, false>(o);
+      const int col = (2 * m + h) * H + kz;
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        rhat[chunk_addr(2 * j * M * H + col, leaf, nleaf)] = e[j];
+        rhat[chunk_addr((2 * j + 1) * M * H + col, leaf, nleaf)] = o[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Inverse transform of one leaf's half spectrum (chunked layout), kept only
+// at the s^3 target cells and written into the mesh: x and y passes keep s
+// of the 2s outputs, v[x] = IDFT_s(Y_even)[x] + exp(2 pi i x / 2s) IDFT_s(Y_odd)[x]
+// (the y pass accumulated over the two parities of ky, one in LDS at a time);
+// the z pass is the real inverse of the half spectrum,
+//   v[z] = Re Y[0] + (-1)^z Re Y[s] + 2 sum_{0 < k < s} Re(Y[k] exp(2 pi i k z / 2s)),
+// unnormalised (the kernels carry 1 / (2s)^3).
+template <int S>
+__global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __restrict__ yhat, int N, int lgnb,
+                                                        int64_t nleaf, float* __restrict__ out) {
+  constexpr int M = 2 * S, H = S + 1;
+  __shared__ float2 B1[S * S * H];  // [x][m][kz], ky = 2m + parity
+  __shared__ float2 B2[S * S * H];  // [x][y][kz]
+  const int64_t leaf = blockIdx.x;
+  const int msk = (1 << lgnb) - 1;
+  const int bz = (int)(leaf & msk), by = (int)((leaf >> lgnb) & msk), bx = (int)(leaf >> (2 * lgnb));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
+      const int m = r / H, kz = r % H;
+      const int col = (2 * m + h) * H + kz;
+      float2 e[S], o[S];
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        e[j] = yhat[chunk_addr(2 * j * M * H + col, leaf, nleaf)];
+        o[j] = yhat[chunk_addr((2 * j + 1) * M * H + col, leaf, nleaf)];
+      }
+      dft<S, true>(e);
+      dft<S, true>(o);
+#pragma unroll
+      for (int x = 0; x < S; ++x) B1[(x * S + m) * H + kz] = cadd(e[x], twiddle<M, true>(o[x], x));
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
+      const int x = r / H, kz = r % H;
+      float2 v[S];
+#pragma unroll
+      for (int m = 0; m < S; ++m) v[m] = B1[(x * S + m) * H + kz];
+      dft<S, true>(v);
+#pragma unroll
+      for (int y = 0; y < S; ++y) {
+        float2& d = B2[(x * S + y) * H + kz];
+        d = h ? cadd(d, twiddle<M, true>(v[y], y)) : v[y];
+      }
+    }
+    __syncthreads();
+  }
+  for (int r = threadIdx.x; r < S * S; r += leaf_threads<S>()) {
+    const int x = r / S, y = r % S;
+    float2 u[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) u[k] = B2[r * H + k];
+    float v[S];
+#pragma unroll
+    for (int z = 0; z < S; ++z) {
+      const float a = u[0].x + ((z & 1) ? -u[S].x : u[S].x);
+      float b = 0.0f;
+#pragma unroll
+      for (int k = 1; k < S; ++k) {
+        const float2 w = tw<M>(k * z);
+        b += u[k].x * w.x - u[k].y * w.y;
+      }
+      v[z] = a + 2.0f * b;
+    }
+    float4* dst = reinterpret_cast<float4*>(
+        out + ((int64_t)(bx * S + x) * N + (by * S + y)) * N + (int64_t)bz * S);
+#pragma unroll
+    for (int q = 0; q < S / 4; ++q) dst[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  }
+}
+
 // yhat_b(k) = sum_e khat_e(k) rhat_{b+e}(k).  Block = 256 consecutive
 // frequencies of one pencil of leaves (bx, by), swept along z with the
 // 3 z-neighbours of each of the 9 (ex, ey) columns held in registers.  The
 // pencils of one frequency chunk go to one XCD (blocks are dealt to the 8
 // XCDs round robin), so its L2 serves the 9 column re-reads.
+template <bool CHUNKED>
 __global__ void __launch_bounds__(kThreads) k_near_mac(const float2* __restrict__ rhat,
                                                         const float2* __restrict__ khat, int nb,
                                                         int64_t F, int nchunk, int isolated,
                                                         float2* __restrict__ yhat) {
+  constexpr int W = CHUNKED ? 64 : kThreads;  // frequencies per block
   const int g = blockIdx.x;
   const int np = nb * nb;
   const int j = g >> 3;
   const int chunk = (j / np) * 8 + (g & 7);
   if (chunk >= nchunk) return;
-  const int64_t k = (int64_t)chunk * kThreads + threadIdx.x;
+  const int64_t k = (int64_t)chunk * W + threadIdx.x;
   if (k >= F) return;
+  const int64_t nleaf = (int64_t)np * nb;
+  // spectrum element of a leaf at this frequency
+  auto at = [&](int64_t leaf) -> int64_t {
+    return CHUNKED ? ((int64_t)chunk * nleaf + leaf) * 64 + threadIdx.x : leaf * F + k;
+  };
   const int pencil = j % np;
   const int bx = pencil / nb, by = pencil % nb;
   float2 kk[27];
@@ -177,17 +432,20 @@ __global__ void __launch_bounds__(kThreads) k_near_mac(const float2* __restrict_
   auto load = [&](int c, int z) -> float2 {
     if (isolated && (z < 0 || z >= nb || !ok[c])) return make_float2(0.0f, 0.0f);
     const int zw = (z + nb) % nb;
-    return rhat[(col[c] + zw) * F + k];
+    return rhat[at(col[c] + zw)];
   };
-  float2 r0[9], r1[9], r2[9];
+  // z - 1, z, z + 1 of every column; z + 2 and z + 3 are loaded ahead
+  float2 r0[9], r1[9], r2[9], r3[9], r4[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
     r0[c] = load(c, -1);
     r1[c] = load(c, 0);
+    r2[c] = load(c, 1);
+    r3[c] = load(c, 2);
   }
   for (int bz = 0; bz < nb; ++bz) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) r2[c] = load(c, bz + 1);
+    for (int c = 0; c < 9; ++c) r4[c] = load(c, bz + 3);
     float re = 0.0f, im = 0.0f;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -195,11 +453,13 @@ __global__ void __launch_bounds__(kThreads) k_near_mac(const float2* __restrict_
       re += a.x * r0[c].x - a.y * r0[c].y + b.x * r1[c].x - b.y * r1[c].y + d.x * r2[c].x - d.y * r2[c].y;
       im += a.x * r0[c].y + a.y * r0[c].x + b.x * r1[c].y + b.y * r1[c].x + d.x * r2[c].y + d.y * r2[c].x;
     }
-    yhat[(((int64_t)bx * nb + by) * nb + bz) * F + k] = make_float2(re, im);
+    yhat[at(((int64_t)bx * nb + by) * nb + bz)] = make_float2(re, im);
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       r0[c] = r1[c];
       r1[c] = r2[c];
+      r2[c] = r3[c];
+      r3[c] = r4[c];
     }
   }
 }
@@ -229,10 +489,13 @@ hipError_t near_fft_create(int N, int s, NearFft** out) {
   const int M = 2 * s;
   f->R = (int64_t)M * M * M;
   f->F = (int64_t)M * M * (s + 1);
-  hipError_t e = hipMalloc(&f->pad, (size_t)(f->nleaf * f->R) * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&f->rhat, (size_t)(f->nleaf * f->F) * sizeof(float2));
+  f->fused = s == 4 || s == 8 || s == 16;
+  while ((1 << f->lgnb) < f->nb) ++f->lgnb;
+  if ((1 << f->lgnb) != f->nb) f->fused = 0;
+  hipError_t e = hipMalloc(&f->rhat, (size_t)(f->nleaf * f->F) * sizeof(float2));
   if (e == hipSuccess) e = hipMalloc(&f->yhat, (size_t)(f->nleaf * f->F) * sizeof(float2));
-  if (e == hipSuccess) {
+  if (e == hipSuccess && !f->fused) e = hipMalloc(&f->pad, (size_t)(f->nleaf * f->R) * sizeof(float));
+  if (e == hipSuccess && !f->fused) {
     int nn[3] = {M, M, M};
     e = fft_err(hipfftPlanMany(&f->fwd, 3, nn, nullptr, 1, (int)f->R, nullptr, 1, (int)f->F,
                                HIPFFT_R2C, (int)f->nleaf));
@@ -278,9 +541,36 @@ int near_fft_kernels(const NearFft* f) {
   return n;
 }
 
+template <int S>
+hipError_t run_fused(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
+                     hipStream_t st) {
+  const unsigned leaves = (unsigned)f->nleaf;
+  k_leaf_fwd<S><<<leaves, leaf_threads<S>(), 0, st>>>(rho, f->N, f->lgnb, f->nleaf, f->rhat);
+  hipError_t e = hipGetLastError();
+  const int nchunk = (int)(f->F / 64);
+  const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * f->nb * f->nb;
+  for (int t = 0; t < nout && e == hipSuccess; ++t) {
+    k_near_mac<true><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
+                                                      isolated, f->yhat);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+      k_leaf_inv<S><<<leaves, leaf_threads<S>(), 0, st>>>(f->yhat, f->N, f->lgnb, f->nleaf, out[t]);
+      e = hipGetLastError();
+    }
+  }
+  return e;
+}
+
 hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
                         hipStream_t st) {
   if (nout < 1 || nout > near_fft_kernels(f)) return hipErrorInvalidValue;
+  if (f->fused) {
+    switch (f->s) {
+      case 4: return run_fused<4>(f, rho, out, nout, isolated, st);
+      case 8: return run_fused<8>(f, rho, out, nout, isolated, st);
+      default: return run_fused<16>(f, rho, out, nout, isolated, st);
+    }
+  }
   const int64_t total = f->nleaf * f->R;
   k_pack<<<nblk(total), kThreads, 0, st>>>(rho, f->N, f->s, f->nb, total, f->pad);
   hipError_t e = hipGetLastError();
@@ -291,8 +581,8 @@ hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nou
   const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * f->nb * f->nb;
   const int64_t N3 = (int64_t)f->N * f->N * f->N;
   for (int t = 0; t < nout && e == hipSuccess; ++t) {
-    k_near_mac<<<(unsigned)blocks, kThreads, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
-                                                     isolated, f->yhat);
+    k_near_mac<false><<<(unsigned)blocks, kThreads, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F,
+                                                            nchunk, isolated, f->yhat);
     e = hipGetLastError();
     if (e == hipSuccess) e = fft_err(hipfftExecC2R(f->inv, (hipfftComplex*)f->yhat, f->pad));
     if (e == hipSuccess) {

@@ -777,6 +777,8 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   if ((const void*)rho == (const void*)phi || (const void*)rho == (const void*)accel ||
       (accel && (void*)accel == (void*)phi))
     return fail(PFMM_ERR_INVALID_ARG, "buffers must not alias");
+  if (pl->near_fft && (((uintptr_t)rho | (uintptr_t)phi | (uintptr_t)accel) & 15))
+    return fail(PFMM_ERR_INVALID_ARG, "the FFT near zone needs 16-byte aligned density and outputs");
   const int N = pl->N, L = pl->L, p = pl->p, s = pl->s;
   const double h3 = 1.0 / ((double)N * N * N);
   hipStream_t st = pl->stream;

@@ -13,7 +13,8 @@ paper takes for a leaf's near zone, Sec. 2-3), through the C ABI.
   neighbours of a leaf are distinct wrapped leaves), a density that is a single
   cell (the transformed kernel alone, including the self value), and zero.
 * A solve with the FFT near zone captured into a HIP graph replays bit for
-  bit; batches refuse such plans.
+  bit; batches refuse such plans, and solves refuse buffers that are not
+  16-byte aligned (the leaf transforms move four cells per access).
 """
 import numpy as np
 import pytest
@@ -108,3 +109,17 @@ def test_fft_near_zone_graph_replay_and_batch_refusal():
             torch.cuda.synchronize()
         with pytest.raises(PfmmError):
             Batch([pl], [rho], [other_out])
+
+
+def test_fft_near_zone_refuses_misaligned_buffers():
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan, PfmmError
+    N = 32
+    rho = torch.zeros((N, N, N), device="cuda")
+    buf = torch.empty(N ** 3 + 1, device="cuda")
+    phi = buf[1:].view(N, N, N)   # 4 bytes past a 16-byte boundary
+    with Plan(N, 3, 4, "S1", near="fft") as pl:
+        with pytest.raises(PfmmError):
+            pl.solve(rho, phi)
+        pl.solve(rho, buf[:N ** 3].view(N, N, N))
+        torch.cuda.synchronize()
