@@ -36,25 +36,37 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
 PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 157.3}
 FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 
-# HBM bytes per launch of the near-zone kernel from rocprofv3 FETCH_SIZE and
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB; the mean of the two profiled solves' launches), scaled by a
-# plain 1 GiB copy (read x2.0, write x1.0), keyed
-# by precision and the SHA-1 prefix of the sources they were taken on (the
-# kernel and plan.hip, which sets the offset order); a changed source reports
-# null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md
+# plain 1 GiB copy (read x2.0, write x1.0), keyed by kernel, precision and the
+# SHA-1 prefix of the sources they were taken on (the kernel's file and
+# plan.hip, which sets the offset order and groups); a changed source reports
+# null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md (FFT near zone, where
+# the leaf interaction zones dominate) and profiles/near_direct_256cube_L4_p8_*.md.
 TRAFFIC = {
-    ("bf16x3", "13cab9468dc2"): (1197910 * 2.0 + 65536 * 1.0) * 1024,
-    ("fp32", "caae94d8dbb6"): (11728392 * 2.0 + 68658 * 1.0) * 1024,
+    ("near", "bf16x3", "13cab9468dc2"): (1197910 * 2.0 + 65536 * 1.0) * 1024,
+    ("near", "fp32", "caae94d8dbb6"): (11728392 * 2.0 + 68658 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
 
 
-def traffic_bytes(precision):
+def traffic_bytes(kernel, precision):
     import hashlib
     h = hashlib.sha1()
     for name in KERNEL_SRC[precision]:
         h.update(open(os.path.join(ROOT, "paper_2011_07099_amd", "csrc", name), "rb").read())
-    return TRAFFIC.get((precision, h.hexdigest()[:12]))
+    return TRAFFIC.get((kernel, precision, h.hexdigest()[:12]))
+
+
+def near_fft_bytes(N, L, kernels=1):
+    """Algorithmic HBM bytes of the FFT near zone per solve: the forward pass
+    reads the density and writes every leaf's half spectrum ((2s)^2 (s + 1)
+    complex FP32 values); per kernel (the potential's, and one per
+    acceleration component from the expansion) the 27-point stencil reads and
+    writes the spectra once and the inverse reads them and writes a mesh."""
+    s = N >> L
+    spectra = 8.0 ** L * (2 * s) ** 2 * (s + 1) * 8
+    return 4.0 * N ** 3 + spectra + kernels * (3 * spectra + 4.0 * N ** 3)
 
 
 def algorithmic_flops(N, L, p):
@@ -343,7 +355,7 @@ def main():
     ap.add_argument("--accel", default="none", choices=["none", "fd4", "expansion"],
                     help="also form accelerations (headline workload): by differences of "
                          "the potential or from the expansion")
-    ap.add_argument("--near", default="direct", choices=["direct", "fft"],
+    ap.add_argument("--near", default="fft", choices=["direct", "fft"],
                     help="leaf near zone by direct summation or by FFT convolution "
                          "(headline workload)")
     ap.add_argument("--iters", type=int, default=20,
@@ -429,6 +441,25 @@ def main():
         per_level[str(lv)] = {"ms": lms, "unit": unit, "products": products,
                               "achieved": tf, "issued": tf * products, "peak": PEAK_UNIT[unit],
                               "frac": tf * products / PEAK_UNIT[unit]}
+    if args.near == "direct":
+        # the direct near zone dominates
+        roofline = {"bound": "mfma" if near_unit.endswith("mfma") else "alu",
+                    "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
+                    "frac": near_tf / peak, "traffic": traffic_bytes("near", args.precision),
+                    "kernel": "near zone (%d launch/step, %.3f ms)" % (
+                        4 if args.accel == "expansion" else 1, near_ms),
+                    "unit_used": near_unit, "products": near_products,
+                    "issued_frac": near_tf * near_products / peak}
+    else:
+        # with the near zone by FFT the leaf level's interaction zones dominate
+        lv = per_level[str(L)]
+        roofline = {"bound": "mfma" if lv["unit"].endswith("mfma") else "alu",
+                    "achieved": lv["achieved"], "peak": PEAK_UNIT[lv["unit"]], "unit": "TFLOP/s",
+                    "frac": lv["achieved"] / PEAK_UNIT[lv["unit"]],
+                    "traffic": traffic_bytes("zones-L%d" % L, args.precision),
+                    "kernel": "level-%d interaction zones (1 launch/step, %.3f ms)" % (L, lv["ms"]),
+                    "unit_used": lv["unit"], "products": lv["products"],
+                    "issued_frac": lv["frac"]}
     out = {
         "metric": METRIC,
         "value": N ** 3 / (ms * 1e-3),
@@ -447,17 +478,18 @@ def main():
                    "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision,
                    **({"accel": args.accel} if args.accel != "none" else {}),
                    **({"near": args.near} if args.near != "direct" else {})},
-        "roofline": {"bound": "mfma" if near_unit.endswith("mfma") else "alu",
-                     "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
-                     "frac": near_tf / peak, "traffic": traffic_bytes(args.precision),
-                     "kernel": "near zone (%d launch/step, %.3f ms)" % (
-                         4 if args.accel == "expansion" else 1, near_ms),
-                     "unit_used": near_unit, "products": near_products,
-                     "issued_frac": near_tf * near_products / peak},
+        "roofline": roofline,
         "m2l": {"achieved": m2l_tf, "unit": "TFLOP/s", "ms": m2l_ms,
                 "launches": stages["m2l"][1], "levels": per_level},
         "stages_ms": {k: v[0] for k, v in stages.items()},
     }
+    if args.near == "fft":
+        nb = near_fft_bytes(N, L, 4 if args.accel == "expansion" else 1)
+        gbs = nb / (near_ms * 1e-3) / 1e9
+        out["near"] = {"method": "fft", "bound": "hbm", "achieved": gbs, "peak": 8000.0,
+                       "unit": "GB/s", "frac": gbs / 8000.0, "bytes": nb, "ms": near_ms}
+    else:
+        out["near"] = {"method": "direct", "achieved": near_tf, "unit": "TFLOP/s", "ms": near_ms}
     if not args.no_cpu_baseline:
         base, acc, context = cpu_baseline(rho32.astype(np.float64),
                                           phi.cpu().numpy().astype(np.float64))

@@ -115,11 +115,21 @@ __global__ void k_kdft_axis(const double2* __restrict__ in, int s, int axis, dou
   out[i] = make_double2(re, im);
 }
 
-__global__ void k_kdft_store(const double2* __restrict__ in, int64_t F, double scale,
+// Scaled FP32 copy of a transformed kernel.  With `fused` the frequencies
+// go to the order of the fused transforms, ky split into parity and half:
+// (kx, ky, kz) -> ((kx * 2 + ky % 2) * s + ky / 2) * (s + 1) + kz.
+__global__ void k_kdft_store(const double2* __restrict__ in, int s, int fused, double scale,
                              float2* __restrict__ out) {
+  const int M = 2 * s, H = s + 1;
+  const int64_t F = (int64_t)M * M * H;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= F) return;
-  out[i] = make_float2((float)(in[i].x * scale), (float)(in[i].y * scale));
+  int64_t d = i;
+  if (fused) {
+    const int kz = (int)(i % H), ky = (int)((i / H) % M), kx = (int)(i / ((int64_t)H * M));
+    d = ((int64_t)(kx * 2 + (ky & 1)) * s + (ky >> 1)) * H + kz;
+  }
+  out[d] = make_float2((float)(in[i].x * scale), (float)(in[i].y * scale));
 }
 
 // pad[leaf][x][y][z] = rho of the leaf's cell (x, y, z) for x, y, z < s, else 0
@@ -309,11 +319,12 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __r
       }
       dft<S, false>(e);
       dft<S, false>(o);
-      const int col = (2 * m + h) * H + kz;
+      // frequency order ((kx * 2 + parity) * s + m) * (s + 1) + kz, ky = 2m + parity:
+      // one parity's s (s + 1) frequencies of a kx plane are contiguous
 #pragma unroll
       for (int j = 0; j < S; ++j) {
-        rhat[chunk_addr(2 * j * M * H + col, leaf, nleaf)] = e[j];
-        rhat[chunk_addr((2 * j + 1) * M * H + col, leaf, nleaf)] = o[j];
+        rhat[chunk_addr((4 * j + h) * S * H + r, leaf, nleaf)] = e[j];
+        rhat[chunk_addr((4 * j + 2 + h) * S * H + r, leaf, nleaf)] = o[j];
       }
     }
     __syncthreads();
@@ -340,12 +351,11 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
   for (int h = 0; h < 2; ++h) {
     for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
       const int m = r / H, kz = r % H;
-      const int col = (2 * m + h) * H + kz;
       float2 e[S], o[S];
 #pragma unroll
       for (int j = 0; j < S; ++j) {
-        e[j] = yhat[chunk_addr(2 * j * M * H + col, leaf, nleaf)];
-        o[j] = yhat[chunk_addr((2 * j + 1) * M * H + col, leaf, nleaf)];
+        e[j] = yhat[chunk_addr((4 * j + h) * S * H + r, leaf, nleaf)];
+        o[j] = yhat[chunk_addr((4 * j + 2 + h) * S * H + r, leaf, nleaf)];
       }
       dft<S, true>(e);
       dft<S, true>(o);
@@ -391,75 +401,84 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
   }
 }
 
-// yhat_b(k) = sum_e khat_e(k) rhat_{b+e}(k).  Block = 256 consecutive
-// frequencies of one pencil of leaves (bx, by), swept along z with the
-// 3 z-neighbours of each of the 9 (ex, ey) columns held in registers.  The
-// pencils of one frequency chunk go to one XCD (blocks are dealt to the 8
-// XCDs round robin), so its L2 serves the 9 column re-reads.
+// yhat_b(k) = sum_e khat_e(k) rhat_{b+e}(k).  A thread owns one frequency
+// and a 2 x 2 block of pencils of leaves (bx, by), swept along z: the 4 x 4
+// source columns around the block are each read once per z and serve all
+// four targets (4 reads per output instead of 9), three z-neighbours held in
+// registers and the next one loaded ahead.  The pencil blocks of one
+// frequency chunk go to one XCD (blocks are dealt to the 8 XCDs round
+// robin), so its L2 serves the column re-reads between neighbouring blocks.
 template <bool CHUNKED>
-__global__ void __launch_bounds__(kThreads) k_near_mac(const float2* __restrict__ rhat,
-                                                        const float2* __restrict__ khat, int nb,
-                                                        int64_t F, int nchunk, int isolated,
-                                                        float2* __restrict__ yhat) {
+__global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
+    const float2* __restrict__ rhat, const float2* __restrict__ khat, int nb, int64_t F,
+    int nchunk, int isolated, float2* __restrict__ yhat) {
   constexpr int W = CHUNKED ? 64 : kThreads;  // frequencies per block
   const int g = blockIdx.x;
-  const int np = nb * nb;
+  const int hb = nb >> 1;
+  const int np = hb * hb;  // 2 x 2 pencil blocks
   const int j = g >> 3;
   const int chunk = (j / np) * 8 + (g & 7);
   if (chunk >= nchunk) return;
   const int64_t k = (int64_t)chunk * W + threadIdx.x;
   if (k >= F) return;
-  const int64_t nleaf = (int64_t)np * nb;
-  // spectrum element of a leaf at this frequency
-  auto at = [&](int64_t leaf) -> int64_t {
-    return CHUNKED ? ((int64_t)chunk * nleaf + leaf) * 64 + threadIdx.x : leaf * F + k;
-  };
-  const int pencil = j % np;
-  const int bx = pencil / nb, by = pencil % nb;
+  // this frequency of leaf l is at base[l * stride] (leaves per axis are a
+  // power of two, so wrapping is a mask)
+  const int64_t nleaf = (int64_t)nb * nb * nb;
+  const int64_t off = CHUNKED ? (int64_t)chunk * nleaf * 64 + threadIdx.x : k;
+  const float2* __restrict__ base = rhat + off;
+  float2* __restrict__ obase = yhat + off;
+  const int stride = CHUNKED ? 64 : (int)F;
+  const int msk = nb - 1;
+  const int blk = j % np;
+  const int bx0 = 2 * (blk / hb), by0 = 2 * (blk % hb);
   float2 kk[27];
 #pragma unroll
   for (int e = 0; e < 27; ++e) kk[e] = khat[(int64_t)e * F + k];
-  int64_t col[9];
-  bool ok[9];
+  // columns (bx0 - 1 + ix, by0 - 1 + iy), ix, iy in [0, 4)
+  int col[16];
+  bool ok[16];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    int sx = bx + c / 3 - 1, sy = by + c % 3 - 1;
+  for (int c = 0; c < 16; ++c) {
+    const int sx = bx0 - 1 + c / 4, sy = by0 - 1 + c % 4;
     ok[c] = !isolated || (sx >= 0 && sx < nb && sy >= 0 && sy < nb);
-    sx = (sx + nb) % nb;
-    sy = (sy + nb) % nb;
-    col[c] = ((int64_t)sx * nb + sy) * nb;
+    col[c] = ((sx & msk) * nb + (sy & msk)) * nb;
   }
   auto load = [&](int c, int z) -> float2 {
     if (isolated && (z < 0 || z >= nb || !ok[c])) return make_float2(0.0f, 0.0f);
-    const int zw = (z + nb) % nb;
-    return rhat[at(col[c] + zw)];
+    return base[(int64_t)(col[c] + (z & msk)) * stride];
   };
-  // z - 1, z, z + 1 of every column; z + 2 and z + 3 are loaded ahead
-  float2 r0[9], r1[9], r2[9], r3[9], r4[9];
+  // z - 1, z, z + 1 of every column; z + 2 is loaded ahead
+  float2 r0[16], r1[16], r2[16], r3[16];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
+  for (int c = 0; c < 16; ++c) {
     r0[c] = load(c, -1);
     r1[c] = load(c, 0);
     r2[c] = load(c, 1);
-    r3[c] = load(c, 2);
   }
   for (int bz = 0; bz < nb; ++bz) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) r4[c] = load(c, bz + 3);
-    float re = 0.0f, im = 0.0f;
+    for (int c = 0; c < 16; ++c) r3[c] = load(c, bz + 2);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      const float2 a = kk[3 * c], b = kk[3 * c + 1], d = kk[3 * c + 2];
-      re += a.x * r0[c].x - a.y * r0[c].y + b.x * r1[c].x - b.y * r1[c].y + d.x * r2[c].x - d.y * r2[c].y;
-      im += a.x * r0[c].y + a.y * r0[c].x + b.x * r1[c].y + b.y * r1[c].x + d.x * r2[c].y + d.y * r2[c].x;
-    }
-    yhat[at(((int64_t)bx * nb + by) * nb + bz)] = make_float2(re, im);
+    for (int tx = 0; tx < 2; ++tx)
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
+      for (int ty = 0; ty < 2; ++ty) {
+        float re = 0.0f, im = 0.0f;
+#pragma unroll
+        for (int ex = 0; ex < 3; ++ex)
+#pragma unroll
+          for (int ey = 0; ey < 3; ++ey) {
+            const int c = (tx + ex) * 4 + (ty + ey);
+            const float2 a = kk[ex * 9 + ey * 3], b = kk[ex * 9 + ey * 3 + 1], d = kk[ex * 9 + ey * 3 + 2];
+            re += a.x * r0[c].x - a.y * r0[c].y + b.x * r1[c].x - b.y * r1[c].y + d.x * r2[c].x - d.y * r2[c].y;
+            im += a.x * r0[c].y + a.y * r0[c].x + b.x * r1[c].y + b.y * r1[c].x + d.x * r2[c].y + d.y * r2[c].x;
+          }
+        obase[(int64_t)(((bx0 + tx) * nb + by0 + ty) * nb + bz) * stride] = make_float2(re, im);
+      }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
       r0[c] = r1[c];
       r1[c] = r2[c];
       r2[c] = r3[c];
-      r3[c] = r4[c];
     }
   }
 }
@@ -528,7 +547,8 @@ hipError_t near_fft_tables(NearFft* f, const double* const* tabs, int ntabs, dou
       k_kdft_z<<<nblk(f->F), kThreads, 0, st>>>(tabs[t], s, ex, ey, ez, f->dft[0]);
       k_kdft_axis<<<nblk(f->F), kThreads, 0, st>>>(f->dft[0], s, 1, f->dft[1]);
       k_kdft_axis<<<nblk(f->F), kThreads, 0, st>>>(f->dft[1], s, 0, f->dft[0]);
-      k_kdft_store<<<nblk(f->F), kThreads, 0, st>>>(f->dft[0], f->F, sc, f->khat[t] + (int64_t)ei * f->F);
+      k_kdft_store<<<nblk(f->F), kThreads, 0, st>>>(f->dft[0], s, f->fused, sc,
+                                                    f->khat[t] + (int64_t)ei * f->F);
       e = hipGetLastError();
     }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -548,7 +568,7 @@ hipError_t run_fused(NearFft* f, const float* rho, float* const* out, int nout, 
   k_leaf_fwd<S><<<leaves, leaf_threads<S>(), 0, st>>>(rho, f->N, f->lgnb, f->nleaf, f->rhat);
   hipError_t e = hipGetLastError();
   const int nchunk = (int)(f->F / 64);
-  const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * f->nb * f->nb;
+  const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * (f->nb / 2) * (f->nb / 2);
   for (int t = 0; t < nout && e == hipSuccess; ++t) {
     k_near_mac<true><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
                                                       isolated, f->yhat);
@@ -578,7 +598,7 @@ hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nou
   if (e == hipSuccess) e = fft_err(hipfftSetStream(f->inv, st));
   if (e == hipSuccess) e = fft_err(hipfftExecR2C(f->fwd, f->pad, (hipfftComplex*)f->rhat));
   const int nchunk = (int)((f->F + kThreads - 1) / kThreads);
-  const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * f->nb * f->nb;
+  const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * (f->nb / 2) * (f->nb / 2);
   const int64_t N3 = (int64_t)f->N * f->N * f->N;
   for (int t = 0; t < nout && e == hipSuccess; ++t) {
     k_near_mac<false><<<(unsigned)blocks, kThreads, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F,
