@@ -44,8 +44,10 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 # null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md (FFT near zone, where
 # the leaf interaction zones dominate) and profiles/near_direct_256cube_L4_p8_*.md.
 TRAFFIC = {
-    ("near", "bf16x3", "13cab9468dc2"): (1197910 * 2.0 + 65536 * 1.0) * 1024,
-    ("near", "fp32", "caae94d8dbb6"): (11728392 * 2.0 + 68658 * 1.0) * 1024,
+    ("zones-L4", "bf16x3", "8bed0f69fede"): (182868 * 2.0 + 262144 * 1.0) * 1024,
+    ("zones-L4", "fp32", "e30717c294e3"): (205501 * 2.0 + 16384 * 1.0) * 1024,
+    ("near", "bf16x3", "8bed0f69fede"): (1178322 * 2.0 + 65536 * 1.0) * 1024,
+    ("near", "fp32", "e30717c294e3"): (11710447 * 2.0 + 68766 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
 
