@@ -144,8 +144,9 @@ def batch_bench(args):
     """Batch of 128 independent fields (N in {32, 64, 128}, p in {4, 6, 8},
     lognormal with alpha = 2, sigma_delta ~ U(0.5, 2), seed 1000 + i, L = 3,
     G_S1) solved by one graph launch; fields/s over K launches.  Plans are in
-    the --precision given (split: near zones with 8^3-cell sub-blocks on the
-    BF16 matrix cores)."""
+    the --precision given, with the --near zone route (FFT: per-leaf
+    transforms in the graph; direct, split: near zones with 8^3-cell
+    sub-blocks on the BF16 matrix cores)."""
     import torch
     from paper_2011_07099_amd import fields
     from paper_2011_07099_amd.pfmm import Batch, Plan
@@ -155,7 +156,7 @@ def batch_bench(args):
     for sp in specs:
         rho = fields.lognormal(sp["N"], sp["alpha"], sp["sigma_delta"], seed=sp["seed"])
         host.append(rho.astype(np.float32))
-        plans.append(Plan(sp["N"], 3, sp["p"], GREEN, precision=args.precision))
+        plans.append(Plan(sp["N"], 3, sp["p"], GREEN, precision=args.precision, near=args.near))
         rhos.append(torch.from_numpy(host[-1]).cuda())
         phis.append(torch.empty_like(rhos[-1]))
     torch.cuda.synchronize()
@@ -185,7 +186,8 @@ def batch_bench(args):
         "data": "synthetic",
         "config": {"workload": "128 lognormal fields, N in {32,64,128}, p in {4,6,8}, "
                                "sigma_delta~U(0.5,2), alpha=2, L=3, G_S1",
-                   "cells": cells, "items": info["items"], "create_s": create_s},
+                   "cells": cells, "items": info["items"], "create_s": create_s,
+                   "near": args.near},
         "tuning": info["groups"],
         "achieved_tflops": flops / (ms * 1e-3) / 1e12,
     }
@@ -359,7 +361,7 @@ def main():
                          "the potential or from the expansion")
     ap.add_argument("--near", default="fft", choices=["direct", "fft"],
                     help="leaf near zone by direct summation or by FFT convolution "
-                         "(headline workload)")
+                         "(headline and batch workloads)")
     ap.add_argument("--iters", type=int, default=20,
                     help="conjugate-gradient iterations (table workload)")
     ap.add_argument("--copy-ref", action="store_true",

@@ -144,7 +144,8 @@ typedef enum {
   /* value: int32 pfmm_near, how the leaf near zone is summed.  Switching to
    * PFMM_NEAR_FFT creates FFT plans and about 100 bytes of buffers per cell
    * and transforms the near-zone kernels (plan time; transformed again when G
-   * or PFMM_OPT_ACCEL changes).  Not for batches.  Default PFMM_NEAR_DIRECT. */
+   * or PFMM_OPT_ACCEL changes).  Batches take such plans for leaf edges
+   * s = 4, 8, 16 (the library's own transforms).  Default PFMM_NEAR_DIRECT. */
   PFMM_OPT_NEAR = 11
 } pfmm_option;
 
@@ -326,6 +327,9 @@ pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
  *   - everything else runs in the portable kernel: FP64 levels in FP64, the
  *     rest in FP32 with FP64 per-offset running totals.
  * Each list is drained by one persistent kernel through an atomic counter.
+ * A plan with PFMM_NEAR_FFT (leaf edges 4, 8, 16 only) has no near-zone
+ * items: its per-leaf transforms and stencil run as their own kernels in
+ * the same graph, beside the matrix-core persistent kernels.
  * The portable items fall into groups by block edge (p for interaction zones,
  * min(s, 8) for near zones), FP32 or FP64 and near or interaction zone; the
  * tile width (targets per thread: 1, 2 or 4) of each FP32 group is picked by
@@ -337,7 +341,8 @@ pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
  * allocates, runs solves and synchronises; it is plan time.
  *
  * Requirements: 1 <= n <= 4096; live plans on one device, p <= 8; the plans
- * are not solved concurrently with the batch (it uses their workspaces).
+ * are not solved concurrently with the batch (it uses their workspaces);
+ * density and potential 16-byte aligned for plans with PFMM_NEAR_FFT.
  * Precision and FP64 levels are those of each plan at batch creation.
  */
 typedef struct pfmm_batch_s* pfmm_batch_t;

@@ -238,6 +238,9 @@ hipError_t near_fft_tables(NearFft* f, const double* const* tabs, int ntabs, dou
                            hipStream_t st);
 // Kernels transformed so far.
 int near_fft_kernels(const NearFft* f);
+// 1 when the leaf transforms are the library's own kernels (s = 4, 8, 16),
+// 0 when they go through rocFFT.
+int near_fft_fused(const NearFft* f);
 // out[t] = the near zone of rho with kernel t, t < nout (written, not added);
 // isolated: sources outside the box are absent instead of periodic images.
 hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nout, int isolated,

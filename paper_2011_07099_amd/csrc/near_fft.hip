@@ -555,6 +555,8 @@ hipError_t near_fft_tables(NearFft* f, const double* const* tabs, int ntabs, dou
   return e;
 }
 
+int near_fft_fused(const NearFft* f) { return f->fused; }
+
 int near_fft_kernels(const NearFft* f) {
   int n = 0;
   while (n < 4 && f->khat[n]) ++n;

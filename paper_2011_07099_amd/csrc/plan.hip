@@ -1176,7 +1176,9 @@ void brelease(pfmm_batch_s* b) {
 // Contractions that go to the matrix-core persistent kernels: the near zone
 // of a plan in split precision with 8^3-cell sub-blocks, and FP64 levels at
 // p = 8 (the same kernels as a single solve, so the same results).
-bool batch_split_near(const pfmm_plan_s* pl) { return pl->prec == PFMM_PREC_BF16X3 && pl->nwin; }
+bool batch_split_near(const pfmm_plan_s* pl) {
+  return !pl->near_fft && pl->prec == PFMM_PREC_BF16X3 && pl->nwin;
+}
 bool batch_f64_level(const pfmm_plan_s* pl, int l) { return level64(pl, l) && pl->p == 8; }
 
 // Tuning group of a portable item: block edge, FP64 or FP32, near zone or
@@ -1246,7 +1248,7 @@ std::vector<BatchItem> batch_items(const pfmm_batch_s* b, const std::map<std::st
     nb.noff = (int)cube(3 * pl->mn);
     nb.grid = 1;
     nb.xscale = (float)(1.0 / ((double)pl->N * pl->N * pl->N));
-    if (!batch_split_near(pl)) add(nb);
+    if (!batch_split_near(pl) && !pl->near_fft) add(nb);  // FFT near zones run on their own
   }
   std::stable_sort(all.begin(), all.end(),
                    [](const Keyed& a, const Keyed& c) { return a.cost > c.cost; });
@@ -1367,6 +1369,14 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
       e = launch_batch_mma(2, b->sargs, b->sitems, b->nsplit, b->counter + 1, b->sgrid, b->s_split);
     if (e == hipSuccess)
       e = launch_batch_mma(64, b->fargs, b->fitems, b->nf64, b->counter + 2, b->fgrid, b->s_f64);
+    // FFT near zones (their own per-leaf kernels, no work items): they write
+    // the potential before the downward passes add to it
+    for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
+      pfmm_plan_s* pl = b->plans[f];
+      if (!pl->near_fft) continue;
+      float* out[1] = {b->phi[f]};
+      e = near_fft_run(pl->nfft, b->rho[f], out, 1, 0, st);
+    }
     if (e == hipSuccess) e = launch_batch_toeplitz(b->items, b->nitems, b->counter, b->grid, st);
     if (e == hipSuccess) e = hipEventRecord(b->ev_split, b->s_split);
     if (e == hipSuccess) e = hipEventRecord(b->ev_f64, b->s_f64);
@@ -1458,9 +1468,14 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
       delete b;
       return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with FFT interaction zones");
     }
-    if (plans[i]->near_fft) {
+    if (plans[i]->near_fft && !near_fft_fused(plans[i]->nfft)) {
       delete b;
-      return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with the FFT near zone");
+      return fail(PFMM_ERR_UNSUPPORTED,
+                  "batches take the FFT near zone for leaf edges 4, 8 and 16 only");
+    }
+    if (plans[i]->near_fft && (((uintptr_t)density[i] | (uintptr_t)potential[i]) & 15)) {
+      delete b;
+      return fail(PFMM_ERR_INVALID_ARG, "the FFT near zone needs 16-byte aligned density and outputs");
     }
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) {

@@ -36,7 +36,8 @@ def _make(specs, precision="fp32"):
         N, L, p, g, seed = spec[:5]
         rho = f32(fields.lognormal(N, 2.0, 1.0, seed=seed))
         host.append(rho)
-        plans.append(Plan(N, L, p, g, precision=spec[5] if len(spec) > 5 else precision))
+        plans.append(Plan(N, L, p, g, precision=spec[5] if len(spec) > 5 else precision,
+                          near=spec[6] if len(spec) > 6 else "direct"))
         rhos.append(torch.from_numpy(rho.astype(np.float32)).cuda())
         phis.append(torch.full_like(rhos[-1], float("nan")))
     return plans, rhos, phis, host
@@ -148,5 +149,40 @@ def test_tuning_cache_round_trip(tmp_path, monkeypatch):
         assert g1["width"] == g2["width"] and (g2["fp64"] or max(g2["ms"]) < 0)
     for (N, L, p, g, seed), phi, rho in zip(SPECS[:3], phis, host):
         assert rel_max(phi.cpu().numpy().astype(np.float64), ofmm.fmm(rho, L, p, g)) < BATCH_TOL
+    for pl in plans:
+        pl.close()
+
+
+FFT_SPECS = [  # (N, L, p, green, seed, precision, near zone)
+    (64, 3, 8, "S1", 301, "bf16x3", "fft"),   # 8^3 leaves
+    (128, 3, 8, "S1", 302, "bf16x3", "fft"),  # 16^3 leaves
+    (32, 3, 4, "S1", 303, "fp32", "fft"),     # 4^3 leaves
+    (64, 3, 6, "K", 304, "fp32", "fft"),
+    (64, 3, 8, "X", 305, "bf16x3", "direct"),  # a direct near zone in the same batch
+]
+
+
+def test_fft_near_zone_fields_in_batches():
+    """Plans with the FFT near zone in a batch: their per-leaf transforms and
+    stencil run in the batch graph beside the persistent kernels; every field
+    against the reference FMM, and two graph launches bit for bit."""
+    import torch
+    from paper_2011_07099_amd.pfmm import Batch
+    plans, rhos, phis, host = _make(FFT_SPECS)
+    with Batch(plans, rhos, phis) as b:
+        outs = []
+        for r in range(2):
+            for f in phis:
+                f.fill_(float("nan"))
+            b.solve()
+            torch.cuda.synchronize()
+            outs.append([f.cpu().clone() for f in phis])
+    for a, c in zip(outs[0], outs[1]):
+        assert torch.equal(a, c)
+    for spec, phi, rho in zip(FFT_SPECS, outs[0], host):
+        N, L, p, g, seed, prec, near = spec
+        e = rel_max(phi.numpy().astype(np.float64), ofmm.fmm(rho, L, p, g))
+        print("batch field", spec, "rel max", e)
+        assert e < (SPLIT_TOL if prec == "bf16x3" else BATCH_TOL)
     for pl in plans:
         pl.close()

@@ -13,8 +13,9 @@ paper takes for a leaf's near zone, Sec. 2-3), through the C ABI.
   neighbours of a leaf are distinct wrapped leaves), a density that is a single
   cell (the transformed kernel alone, including the self value), and zero.
 * A solve with the FFT near zone captured into a HIP graph replays bit for
-  bit; batches refuse such plans, and solves refuse buffers that are not
-  16-byte aligned (the leaf transforms move four cells per access).
+  bit; batches refuse such plans when the leaf transforms would be rocFFT's
+  (s = 1, 2), and solves refuse buffers that are not 16-byte aligned (the
+  leaf transforms move four cells per access).
 """
 import numpy as np
 import pytest
@@ -107,8 +108,12 @@ def test_fft_near_zone_graph_replay_and_batch_refusal():
             assert same
             other.solve(rho, other_out)
             torch.cuda.synchronize()
+    # batches take the FFT near zone only with the library's own transforms
+    with Plan(16, 4, 2, "X", near="fft") as pl:   # one cell per leaf: rocFFT
+        r = torch.zeros((16, 16, 16), device="cuda")
+        out = torch.empty_like(r)
         with pytest.raises(PfmmError):
-            Batch([pl], [rho], [other_out])
+            Batch([pl], [r], [out])
 
 
 def test_fft_near_zone_refuses_misaligned_buffers():
