@@ -447,7 +447,9 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
     if (isolated && (z < 0 || z >= nb || !ok[c])) return make_float2(0.0f, 0.0f);
     return base[(int64_t)(col[c] + (z & msk)) * stride];
   };
-  // z - 1, z, z + 1 of every column; z + 2 is loaded ahead
+  // z - 1, z, z + 1 of every column in three register sets, z + 2 loaded
+  // into the fourth one step ahead; the sweep is unrolled by four (nb is a
+  // power of two >= 4) and rotates the roles of the sets instead of copying
   float2 r0[16], r1[16], r2[16], r3[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
@@ -455,9 +457,9 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
     r1[c] = load(c, 0);
     r2[c] = load(c, 1);
   }
-  for (int bz = 0; bz < nb; ++bz) {
+  auto step = [&](int bz, float2 (&zm)[16], float2 (&z0)[16], float2 (&zp)[16], float2 (&next)[16]) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) r3[c] = load(c, bz + 2);
+    for (int c = 0; c < 16; ++c) next[c] = load(c, bz + 2);
 #pragma unroll
     for (int tx = 0; tx < 2; ++tx)
 #pragma unroll
@@ -469,17 +471,17 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
           for (int ey = 0; ey < 3; ++ey) {
             const int c = (tx + ex) * 4 + (ty + ey);
             const float2 a = kk[ex * 9 + ey * 3], b = kk[ex * 9 + ey * 3 + 1], d = kk[ex * 9 + ey * 3 + 2];
-            re += a.x * r0[c].x - a.y * r0[c].y + b.x * r1[c].x - b.y * r1[c].y + d.x * r2[c].x - d.y * r2[c].y;
-            im += a.x * r0[c].y + a.y * r0[c].x + b.x * r1[c].y + b.y * r1[c].x + d.x * r2[c].y + d.y * r2[c].x;
+            re += a.x * zm[c].x - a.y * zm[c].y + b.x * z0[c].x - b.y * z0[c].y + d.x * zp[c].x - d.y * zp[c].y;
+            im += a.x * zm[c].y + a.y * zm[c].x + b.x * z0[c].y + b.y * z0[c].x + d.x * zp[c].y + d.y * zp[c].x;
           }
         obase[(int64_t)(((bx0 + tx) * nb + by0 + ty) * nb + bz) * stride] = make_float2(re, im);
       }
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      r0[c] = r1[c];
-      r1[c] = r2[c];
-      r2[c] = r3[c];
-    }
+  };
+  for (int bz = 0; bz < nb; bz += 4) {
+    step(bz, r0, r1, r2, r3);
+    step(bz + 1, r1, r2, r3, r0);
+    step(bz + 2, r2, r3, r0, r1);
+    step(bz + 3, r3, r0, r1, r2);
   }
 }
 
