@@ -362,6 +362,9 @@ def main():
     ap.add_argument("--near", default="fft", choices=["direct", "fft"],
                     help="leaf near zone by direct summation or by FFT convolution "
                          "(headline and batch workloads)")
+    ap.add_argument("--m2l", default="gemm", choices=["gemm", "spectral"],
+                    help="interaction zones by block-Toeplitz GEMM or spectral stencils "
+                         "(headline workload)")
     ap.add_argument("--iters", type=int, default=20,
                     help="conjugate-gradient iterations (table workload)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -399,7 +402,8 @@ def main():
     phi = torch.empty_like(rho)
     stream = torch.cuda.current_stream(dev)
     plan = Plan(N, L, P, GREEN, precision=args.precision, stream=stream,
-                accel="expansion" if args.accel == "expansion" else "fd4", near=args.near)
+                accel="expansion" if args.accel == "expansion" else "fd4", near=args.near,
+                m2l=args.m2l)
     acc = (torch.empty((3, N, N, N), dtype=torch.float32, device=dev)
            if args.accel != "none" else None)
     for _ in range(args.warmup):
@@ -481,7 +485,8 @@ def main():
                                "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
                    "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision,
                    **({"accel": args.accel} if args.accel != "none" else {}),
-                   **({"near": args.near} if args.near != "direct" else {})},
+                   **({"near": args.near} if args.near != "direct" else {}),
+                   **({"m2l": args.m2l} if args.m2l != "gemm" else {})},
         "roofline": roofline,
         "m2l": {"achieved": m2l_tf, "unit": "TFLOP/s", "ms": m2l_ms,
                 "launches": stages["m2l"][1], "levels": per_level},

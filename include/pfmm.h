@@ -182,7 +182,20 @@ typedef enum {
    * parent's neighbours with the target's neighbours zeroed, padded to
    * (8p)^3; level 2: the periodic (4p)^3 level.  A comparator: same sums as
    * the GEMM up to rounding. */
-  PFMM_M2L_FFT = 1
+  PFMM_M2L_FFT = 1,
+  /* Spectral stencils, for p = 4 and 8: every node's gridlet transformed
+   * once on its (2p)^3 cyclic grid (exact for the block convolutions of
+   * Eq. 6, whose separations |a - a'| <= p - 1 have distinct residues), the
+   * zone's offsets (189 per parity class, the level-2 zone) summed per
+   * frequency with the transformed kernels G(eta_l (m - p d)), one inverse
+   * per node.  All in FP64 on the vector ALUs, whatever
+   * PFMM_OPT_PRECISION and PFMM_OPT_FP64_LEVELS say; masses are read and
+   * potentials added in each level's precision.  Allocates about
+   * 2 (2p)^2 (p + 1) x 16 bytes per leaf-level node (0.3 GB at 16^3 nodes,
+   * p = 8) and transforms the kernels of the 343 offsets in [-3, 3]^3 per
+   * level (plan time; again when G changes).  Periodic and isolated plans;
+   * not for batches or learned tables. */
+  PFMM_M2L_SPECTRAL = 2
 } pfmm_m2l;
 
 /* How accelerations are formed (Sec. 3: PM differences its potential, the

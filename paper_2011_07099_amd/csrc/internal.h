@@ -246,6 +246,21 @@ int near_fft_fused(const NearFft* f);
 hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
                         hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Interaction zones as spectral stencils (per-node transforms, FP64)
+// ---------------------------------------------------------------------------
+struct M2LSpectral;
+// Buffers for levels 2 .. L at gridlet size p (4 or 8); allocates.
+hipError_t m2l_spectral_create(int L, int p, M2LSpectral** out);
+void m2l_spectral_destroy(M2LSpectral* f);
+// Transform the kernels of every offset in [-3, 3]^3 from the FP64 level
+// tables; synchronises `st`.
+hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64, hipStream_t st);
+// Pl (+)= the level-l zone sums of Ml over `offs` (noff per class: 8 classes
+// at levels >= 3, one at level 2); m64 / p64: the buffers hold doubles.
+hipError_t m2l_spectral_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, int p64,
+                              int accumulate, const int* offs, int noff, int isolated, hipStream_t st);
+
 // FP64 -> FP32 copy of n elements.
 hipError_t launch_cast_d2f(const double* src, float* dst, int64_t n, hipStream_t st);
 

@@ -1,0 +1,473 @@
+// Interaction zones (Eq. 6) as spectral stencils over the nodes of a level.
+//
+// Target node t, source node t + d (d in the zone of t's parity class, 189
+// offsets at levels >= 3; the periodic level-2 zone), gridlet points a, a':
+//   Phi_l[t][a] += sum_d sum_a' G(eta_l (a - a' - p d)) M_l[t + d][a'].
+// For one d this is a linear convolution of a p^3 block with the kernel
+// K_d[m] = G(eta_l (m - p d)), |m_i| <= p - 1, so, as for the leaf near zone,
+// it is exact as a cyclic convolution on 2p points per axis, and the zone's
+// offsets add per frequency:
+//   Phi_hat_t(k) = sum_{d in IZ(t)} K_hat_d(k) M_hat_{t+d}(k).
+// One forward transform per node, a stencil of 189 (37 at level 2) terms per
+// target and frequency, one inverse per node.  Against the block-Toeplitz
+// GEMM's 2 p^6 flops per target and offset this is 8 flops per frequency
+// ((2p)^2 (p + 1) of them) plus the transforms.
+//
+// Everything here is FP64 (transforms, kernel spectra, stencil), on the
+// vector ALUs; masses are read and potentials added in the level's own
+// precision.  Kernel spectra (all 343 offsets of [-3, 3]^3) are transformed
+// once per table by the same separable FP64 DFT as the near zone's.
+//
+// Layout: spectra of a level as [frequency][node], so that one stencil
+// workgroup (one frequency, one 8^3 tile of targets) reads its tile and the
+// 3-node halo from contiguous node runs.  In the stencil each wave handles
+// one parity class, so the offset, and with it the kernel value, is the same
+// across the wave.
+#include "internal.h"
+
+#include <vector>
+
+namespace pfmm {
+
+struct M2LSpectral {
+  int L = 0, p = 0;
+  int64_t F = 0;                 // (2p)^2 (p + 1) frequencies per node
+  double2* spec = nullptr;       // [F][nodes] of the level being summed
+  double2* out = nullptr;        // [F][nodes]
+  std::vector<double2*> khat;    // per level: [343][F], offsets of [-3, 3]^3
+  double2* dft[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+// cos(2 pi j / 32) for j = 0 .. 8
+__device__ constexpr double kQuarterD[9] = {1.0,
+                                            0.98078528040323044913,
+                                            0.92387953251128675613,
+                                            0.83146961230254523708,
+                                            0.70710678118654752440,
+                                            0.55557023301960222474,
+                                            0.38268343236508977173,
+                                            0.19509032201612826785,
+                                            0.0};
+__device__ __forceinline__ double cosd32(int j) {
+  j &= 31;
+  if (j <= 8) return kQuarterD[j];
+  if (j <= 16) return -kQuarterD[16 - j];
+  if (j <= 24) return -kQuarterD[j - 16];
+  return kQuarterD[32 - j];
+}
+
+// (cos, sin) of 2 pi j / M, M | 32
+template <int M>
+__device__ __forceinline__ double2 twd(int j) {
+  constexpr int r = 32 / M;
+  return make_double2(cosd32(j * r), cosd32(j * r - 8));
+}
+
+__device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// a exp(-2 pi i j / P) (forward) or a exp(+2 pi i j / P) (INV)
+template <int P, bool INV>
+__device__ __forceinline__ double2 dtwiddle(double2 a, int j) {
+  const double2 w = twd<P>(j);
+  return INV ? make_double2(a.x * w.x - a.y * w.y, a.y * w.x + a.x * w.y)
+             : make_double2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
+}
+
+template <bool INV>
+__device__ __forceinline__ void ddft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+  const double2 b0 = dadd(a0, a2), b1 = dsub(a0, a2), b2 = dadd(a1, a3), b3 = dsub(a1, a3);
+  const double2 ib3 = make_double2(-b3.y, b3.x);
+  a0 = dadd(b0, b2);
+  a2 = dsub(b0, b2);
+  a1 = INV ? dadd(b1, ib3) : dsub(b1, ib3);
+  a3 = INV ? dsub(b1, ib3) : dadd(b1, ib3);
+}
+
+// In-place DFT of P = 4Q values (Q = 1, 2), split n = Q n1 + n2, m = m1 + 4 m2
+template <int P, bool INV>
+__device__ __forceinline__ void ddft(double2 (&v)[P]) {
+  constexpr int Q = P / 4;
+  double2 T[Q][4];
+#pragma unroll
+  for (int n2 = 0; n2 < Q; ++n2) {
+    T[n2][0] = v[n2];
+    T[n2][1] = v[Q + n2];
+    T[n2][2] = v[2 * Q + n2];
+    T[n2][3] = v[3 * Q + n2];
+    ddft4<INV>(T[n2][0], T[n2][1], T[n2][2], T[n2][3]);
+#pragma unroll
+    for (int m1 = 1; m1 < 4; ++m1)
+      if (n2) T[n2][m1] = dtwiddle<P, INV>(T[n2][m1], n2 * m1);
+  }
+#pragma unroll
+  for (int m1 = 0; m1 < 4; ++m1) {
+    if constexpr (Q == 1) {
+      v[m1] = T[0][m1];
+    } else {
+      v[m1] = dadd(T[0][m1], T[1][m1]);
+      v[m1 + 4] = dsub(T[0][m1], T[1][m1]);
+    }
+  }
+}
+
+template <int P>
+constexpr int node_threads() { return (P * (P + 1) + 63) / 64 * 64; }
+
+// Node of block g: the 8 XCDs (blocks dealt round robin) take contiguous runs
+// of nodes, so that the [frequency][node] writes of neighbouring nodes meet in
+// one L2.
+__device__ __forceinline__ int64_t xcd_node(int64_t g, int64_t nn) { return (g & 7) * (nn >> 3) + (g >> 3); }
+
+// Forward transform of one node's p^3 gridlet (on the 2p cyclic grid, zero
+// beyond p) to its half spectrum; frequency order
+// ((kx * 2 + ky % 2) * p + ky / 2) * (p + 1) + kz.
+template <int P, class TIN>
+__global__ void __launch_bounds__(node_threads<P>()) k_node_fwd(const TIN* __restrict__ Ml, int64_t nn,
+                                                                double2* __restrict__ spec) {
+  constexpr int M = 2 * P, H = P + 1, NT = node_threads<P>();
+  __shared__ double2 A1[P * P * H];
+  __shared__ double2 A2[P * P * H];
+  const int64_t node = xcd_node(blockIdx.x, nn);
+  const TIN* src = Ml + node * (P * P * P);
+  for (int r = threadIdx.x; r < P * P; r += NT) {
+    double2 e[P], o[P];
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      e[z] = make_double2((double)src[r * P + z], 0.0);
+      o[z] = dtwiddle<M, false>(e[z], z);
+    }
+    ddft<P, false>(e);
+    ddft<P, false>(o);
+    double2* row = A1 + r * H;
+#pragma unroll
+    for (int m = 0; m < P / 2; ++m) {
+      row[2 * m] = e[m];
+      row[2 * m + 1] = o[m];
+    }
+    row[P] = e[P / 2];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    for (int r = threadIdx.x; r < P * H; r += NT) {
+      const int x = r / H, kz = r % H;
+      double2 u[P];
+#pragma unroll
+      for (int y = 0; y < P; ++y) {
+        u[y] = A1[(x * P + y) * H + kz];
+        if (h) u[y] = dtwiddle<M, false>(u[y], y);
+      }
+      ddft<P, false>(u);
+#pragma unroll
+      for (int m = 0; m < P; ++m) A2[(x * P + m) * H + kz] = u[m];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < P * H; r += NT) {
+      const int m = r / H, kz = r % H;
+      double2 e[P], o[P];
+#pragma unroll
+      for (int x = 0; x < P; ++x) {
+        e[x] = A2[(x * P + m) * H + kz];
+        o[x] = dtwiddle<M, false>(e[x], x);
+      }
+      ddft<P, false>(e);
+      ddft<P, false>(o);
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        spec[(int64_t)((4 * j + h) * P * H + r) * nn + node] = e[j];
+        spec[(int64_t)((4 * j + 2 + h) * P * H + r) * nn + node] = o[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Inverse of k_node_fwd at the p^3 gridlet points, added to (or written into)
+// the node's potentials; unnormalised (the kernel spectra carry 1 / (2p)^3).
+template <int P, class TOUT>
+__global__ void __launch_bounds__(node_threads<P>()) k_node_inv(const double2* __restrict__ spec,
+                                                                int64_t nn, int accumulate,
+                                                                TOUT* __restrict__ Pl) {
+  constexpr int M = 2 * P, H = P + 1, NT = node_threads<P>();
+  __shared__ double2 B1[P * P * H];
+  __shared__ double2 B2[P * P * H];
+  const int64_t node = xcd_node(blockIdx.x, nn);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    for (int r = threadIdx.x; r < P * H; r += NT) {
+      const int m = r / H, kz = r % H;
+      double2 e[P], o[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        e[j] = spec[(int64_t)((4 * j + h) * P * H + r) * nn + node];
+        o[j] = spec[(int64_t)((4 * j + 2 + h) * P * H + r) * nn + node];
+      }
+      ddft<P, true>(e);
+      ddft<P, true>(o);
+#pragma unroll
+      for (int x = 0; x < P; ++x) B1[(x * P + m) * H + kz] = dadd(e[x], dtwiddle<M, true>(o[x], x));
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < P * H; r += NT) {
+      const int x = r / H, kz = r % H;
+      double2 v[P];
+#pragma unroll
+      for (int m = 0; m < P; ++m) v[m] = B1[(x * P + m) * H + kz];
+      ddft<P, true>(v);
+#pragma unroll
+      for (int y = 0; y < P; ++y) {
+        double2& d = B2[(x * P + y) * H + kz];
+        d = h ? dadd(d, dtwiddle<M, true>(v[y], y)) : v[y];
+      }
+    }
+    __syncthreads();
+  }
+  TOUT* dst = Pl + node * (P * P * P);
+  for (int r = threadIdx.x; r < P * P; r += NT) {
+    double2 u[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) u[k] = B2[r * H + k];
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      double b = 0.0;
+#pragma unroll
+      for (int k = 1; k < P; ++k) {
+        const double2 w = twd<M>(k * z);
+        b += u[k].x * w.x - u[k].y * w.y;
+      }
+      const double v = u[0].x + ((z & 1) ? -u[P].x : u[P].x) + 2.0 * b;
+      dst[r * P + z] = accumulate ? (TOUT)((double)dst[r * P + z] + v) : (TOUT)v;
+    }
+  }
+}
+
+// out_t(k) = sum_{d in zone(class of t)} khat_d(k) spec_{t+d}(k) for one
+// frequency k (blockIdx.x) and one tile of T^3 targets (blockIdx.y); T = 8,
+// or T = n = 4 on the 4^3 level (one class).  The tile's source spectra with a
+// 3-node halo are staged in LDS (wrapped, or zero outside an isolated box).
+// Wave w handles the targets of class w (levels >= 3), so the offset list,
+// and the kernel value at k, is uniform across the wave.
+__global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ spec,
+                                                   const double2* __restrict__ khat,
+                                                   const int* __restrict__ offs, int noff, int n,
+                                                   int classes, int isolated, int64_t F,
+                                                   double2* __restrict__ out) {
+  __shared__ double2 box[14 * 14 * 14];
+  __shared__ double2 kk[343];        // this frequency's kernel values, all offsets of [-3, 3]^3
+  __shared__ int sof[8 * 316];       // the zone's offsets per class, as box steps and kernel index
+  const int T = n < 8 ? n : 8;
+  const int B = T + 6;
+  const int Bh = B / 2, H3 = Bh * Bh * Bh;  // parity-split box
+  const int64_t nn = (int64_t)n * n * n;
+  const int64_t k = blockIdx.x;
+  const int tpa = n / T;  // tiles per axis
+  const int tile = blockIdx.y;
+  const int ox = (tile / (tpa * tpa)) * T, oy = ((tile / tpa) % tpa) * T, oz = (tile % tpa) * T;
+  const double2* sk = spec + k * nn;
+  for (int i = threadIdx.x; i < 343; i += blockDim.x) kk[i] = khat[(int64_t)i * F + k];
+  // per (class, offset): the box position of the source of the class's first
+  // target (the others follow it by the lane's lattice step), and the kernel
+  for (int i = threadIdx.x; i < classes * noff; i += blockDim.x) {
+    const int pk = offs[i];
+    const int dx = ((pk >> 16) & 255) - 128, dy = ((pk >> 8) & 255) - 128, dz = (pk & 255) - 128;
+    int pos;
+    if (classes == 8) {
+      const int c = i / noff;
+      const int sx = (c >> 2) + dx + 3, sy = ((c >> 1) & 1) + dy + 3, sz = (c & 1) + dz + 3;
+      pos = (((sx & 1) * 2 + (sy & 1)) * 2 + (sz & 1)) * H3 + ((sx >> 1) * Bh + (sy >> 1)) * Bh + (sz >> 1);
+    } else {
+      pos = ((dx + 3) * B + (dy + 3)) * B + (dz + 3);
+    }
+    sof[i] = pos * 512 + ((dx + 3) * 49 + (dy + 3) * 7 + (dz + 3));
+  }
+  // With 8 classes the box is stored split by parity, [px][py][pz][hx][hy][hz]
+  // (coordinate 2h + p): for one offset, the 64 targets of a class (a 4^3
+  // lattice of step 2) then read 64 consecutive entries.  On the 4^3 level it
+  // is stored plainly.
+  for (int i = threadIdx.x; i < B * B * B; i += blockDim.x) {
+    const int bx = i / (B * B), by = (i / B) % B, bz = i % B;
+    const int x = ox + bx - 3, y = oy + by - 3, z = oz + bz - 3;
+    double2 v = make_double2(0.0, 0.0);
+    if (!isolated || ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n)) {
+      const int xw = x & (n - 1), yw = y & (n - 1), zw = z & (n - 1);
+      v = sk[((int64_t)xw * n + yw) * n + zw];
+    }
+    const int dst = classes == 8 ? (((bx & 1) * 2 + (by & 1)) * 2 + (bz & 1)) * H3 +
+                                       ((bx >> 1) * Bh + (by >> 1)) * Bh + (bz >> 1)
+                                 : i;
+    box[dst] = v;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int tx, ty, tz, cls;
+  if (classes == 8) {  // 4^3 targets of class `wave` in the 8^3 tile
+    cls = wave;
+    tx = 2 * (lane >> 4) + (cls >> 2);
+    ty = 2 * ((lane >> 2) & 3) + ((cls >> 1) & 1);
+    tz = 2 * (lane & 3) + (cls & 1);
+  } else {             // one class, the whole 4^3 level
+    cls = 0;
+    tx = lane >> 4;
+    ty = (lane >> 2) & 3;
+    tz = lane & 3;
+  }
+  const int* o = sof + cls * noff;
+  const int base = classes == 8 ? ((lane >> 4) * Bh + ((lane >> 2) & 3)) * Bh + (lane & 3)
+                                : (tx * B + ty) * B + tz;
+  double re = 0.0, im = 0.0;
+#pragma unroll 4
+  for (int i = 0; i < noff; ++i) {
+    const int w = o[i];
+    const double2 kd = kk[w & 511];
+    const double2 s = box[base + (w >> 9)];
+    re += kd.x * s.x - kd.y * s.y;
+    im += kd.x * s.y + kd.y * s.x;
+  }
+  out[k * nn + ((int64_t)(ox + tx) * n + (oy + ty)) * n + (oz + tz)] = make_double2(re, im);
+}
+
+// Kernel spectrum of offset d (FP64 separable DFT): first pass along z of
+// K_d[x][y][z] = tab[w(x) - p dx][w(y) - p dy][w(z) - p dz] (tab centred at
+// C), zero on the unused slot p; then y and x (k_sdft_axis); stored scaled in
+// the frequency order of k_node_fwd.
+__global__ void k_sdft_z(const double* __restrict__ tab, int p, int C, int dx, int dy, int dz,
+                         double2* __restrict__ A) {
+  const int M = 2 * p, H = p + 1;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= (int64_t)M * M * H) return;
+  const int kz = (int)(i % H), y = (int)((i / H) % M), x = (int)(i / ((int64_t)H * M));
+  const int E = 2 * C + 1;
+  double re = 0.0, im = 0.0;
+  if (x != p && y != p) {
+    const int jx = (x < p ? x : x - M) - p * dx, jy = (y < p ? y : y - M) - p * dy;
+    const double* row = tab + ((int64_t)(jx + C) * E + (jy + C)) * E;
+    for (int z = 0; z < M; ++z) {
+      if (z == p) continue;
+      const double v = row[(z < p ? z : z - M) - p * dz + C];
+      double sn, cs;
+      sincospi(-(double)((kz * z) % M) / p, &sn, &cs);
+      re += v * cs;
+      im += v * sn;
+    }
+  }
+  A[i] = make_double2(re, im);
+}
+
+__global__ void k_sdft_axis(const double2* __restrict__ in, int p, int axis, double2* __restrict__ out) {
+  const int M = 2 * p, H = p + 1;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= (int64_t)M * M * H) return;
+  const int kz = (int)(i % H), b = (int)((i / H) % M), a = (int)(i / ((int64_t)H * M));
+  const int kk = axis ? b : a;
+  double re = 0.0, im = 0.0;
+  for (int j = 0; j < M; ++j) {
+    const double2 v = in[axis ? ((int64_t)a * M + j) * H + kz : ((int64_t)j * M + b) * H + kz];
+    double sn, cs;
+    sincospi(-(double)((kk * j) % M) / p, &sn, &cs);
+    re += v.x * cs - v.y * sn;
+    im += v.x * sn + v.y * cs;
+  }
+  out[i] = make_double2(re, im);
+}
+
+__global__ void k_sdft_store(const double2* __restrict__ in, int p, double scale, double2* __restrict__ out) {
+  const int M = 2 * p, H = p + 1;
+  const int64_t F = (int64_t)M * M * H;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const int kz = (int)(i % H), ky = (int)((i / H) % M), kx = (int)(i / ((int64_t)H * M));
+  const int64_t d = ((int64_t)(kx * 2 + (ky & 1)) * p + (ky >> 1)) * H + kz;
+  out[d] = make_double2(in[i].x * scale, in[i].y * scale);
+}
+
+template <int P>
+hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, int p64,
+                     int accumulate, const int* offs, int noff, int isolated, hipStream_t st) {
+  const int n = 1 << l;
+  const int64_t nn = (int64_t)n * n * n;
+  constexpr int NT = node_threads<P>();
+  if (m64)
+    k_node_fwd<P, double><<<(unsigned)nn, NT, 0, st>>>((const double*)Ml, nn, f->spec);
+  else
+    k_node_fwd<P, float><<<(unsigned)nn, NT, 0, st>>>((const float*)Ml, nn, f->spec);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int T = n < 8 ? n : 8;
+  const dim3 grid((unsigned)f->F, (unsigned)((n / T) * (n / T) * (n / T)));
+  const int classes = l == 2 ? 1 : 8;
+  k_zone_spec<<<grid, classes == 8 ? 512 : 64, 0, st>>>(f->spec, f->khat[l], offs, noff, n, classes,
+                                                         isolated, f->F, f->out);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (p64)
+    k_node_inv<P, double><<<(unsigned)nn, NT, 0, st>>>(f->out, nn, accumulate, (double*)Pl);
+  else
+    k_node_inv<P, float><<<(unsigned)nn, NT, 0, st>>>(f->out, nn, accumulate, (float*)Pl);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+void m2l_spectral_destroy(M2LSpectral* f) {
+  if (!f) return;
+  (void)hipFree(f->spec);
+  (void)hipFree(f->out);
+  for (double2* k : f->khat) (void)hipFree(k);
+  for (double2* d : f->dft) (void)hipFree(d);
+  delete f;
+}
+
+hipError_t m2l_spectral_create(int L, int p, M2LSpectral** out) {
+  *out = nullptr;
+  if (p != 4 && p != 8) return hipErrorInvalidValue;
+  M2LSpectral* f = new M2LSpectral;
+  f->L = L;
+  f->p = p;
+  f->F = (int64_t)(2 * p) * (2 * p) * (p + 1);
+  const int64_t nodes = (int64_t)1 << (3 * L);
+  f->khat.assign(L + 1, nullptr);
+  hipError_t e = hipMalloc(&f->spec, (size_t)(f->F * nodes) * sizeof(double2));
+  if (e == hipSuccess) e = hipMalloc(&f->out, (size_t)(f->F * nodes) * sizeof(double2));
+  for (int d = 0; d < 2 && e == hipSuccess; ++d) e = hipMalloc(&f->dft[d], (size_t)f->F * sizeof(double2));
+  for (int l = 2; l <= L && e == hipSuccess; ++l)
+    e = hipMalloc(&f->khat[l], (size_t)(343 * f->F) * sizeof(double2));
+  if (e != hipSuccess) {
+    m2l_spectral_destroy(f);
+    return e;
+  }
+  *out = f;
+  return hipSuccess;
+}
+
+hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64, hipStream_t st) {
+  const int p = f->p, C = 4 * p - 1;
+  const double scale = 1.0 / (double)((2 * p) * (2 * p) * (2 * p));
+  hipError_t e = hipSuccess;
+  for (int l = 2; l <= f->L && e == hipSuccess; ++l)
+    for (int di = 0; di < 343 && e == hipSuccess; ++di) {
+      const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+      k_sdft_z<<<nblk(f->F), kThreads, 0, st>>>(tab64[l], p, C, dx, dy, dz, f->dft[0]);
+      k_sdft_axis<<<nblk(f->F), kThreads, 0, st>>>(f->dft[0], p, 1, f->dft[1]);
+      k_sdft_axis<<<nblk(f->F), kThreads, 0, st>>>(f->dft[1], p, 0, f->dft[0]);
+      k_sdft_store<<<nblk(f->F), kThreads, 0, st>>>(f->dft[0], p, scale, f->khat[l] + (int64_t)di * f->F);
+      e = hipGetLastError();
+    }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+hipError_t m2l_spectral_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, int p64,
+                              int accumulate, const int* offs, int noff, int isolated, hipStream_t st) {
+  if (l < 2 || l > f->L) return hipErrorInvalidValue;
+  return f->p == 4 ? run_level<4>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st)
+                   : run_level<8>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st);
+}
+
+}  // namespace pfmm

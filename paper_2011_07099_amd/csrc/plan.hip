@@ -60,6 +60,8 @@ struct pfmm_plan_s {
   int isolated = 0;               // no periodic images (PFMM_OPT_ISOLATED)
   int m2l_fft = 0;                // interaction zones by FFT convolution (PFMM_OPT_M2L)
   M2LFft* fft = nullptr;          // its plans, grids and transformed kernels
+  int m2l_spectral = 0;           // interaction zones as spectral stencils (PFMM_OPT_M2L)
+  M2LSpectral* mspec = nullptr;   // its spectra and transformed kernels
   int near_fft = 0;               // leaf near zone by FFT convolution (PFMM_OPT_NEAR)
   NearFft* nfft = nullptr;        // its plans, buffers and transformed kernels
   uint16_t* zero = nullptr;       // 512 zero bf16 values: the source outside an isolated box
@@ -200,6 +202,8 @@ void release(pfmm_plan_s* pl) {
   pl->fft = nullptr;
   if (pl->nfft) near_fft_destroy(pl->nfft);
   pl->nfft = nullptr;
+  if (pl->mspec) m2l_spectral_destroy(pl->mspec);
+  pl->mspec = nullptr;
   for (hipEvent_t e : pl->ev)
     if (e) (void)hipEventDestroy(e);
   pl->ev.clear();
@@ -308,6 +312,10 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
   if (pl->fft) {  // transformed kernels of the FFT interaction zones follow G
     e = m2l_fft_tables(pl->fft, pl->tab64, pl->stream);
     if (e != hipSuccess) return hip_fail(e, "FFT kernels");
+  }
+  if (pl->mspec) {  // and those of the spectral stencils
+    e = m2l_spectral_tables(pl->mspec, pl->tab64, pl->stream);
+    if (e != hipSuccess) return hip_fail(e, "spectral zone kernels");
   }
   return pl->accel_mode ? tabulate_accel_tables(pl) : refresh_near_fft(pl);
 }
@@ -709,8 +717,25 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "M2L mode is an int32");
       int32_t v;
       std::memcpy(&v, value, sizeof v);
-      if (v != PFMM_M2L_GEMM && v != PFMM_M2L_FFT)
+      if (v != PFMM_M2L_GEMM && v != PFMM_M2L_FFT && v != PFMM_M2L_SPECTRAL)
         return fail(PFMM_ERR_INVALID_ARG, "unknown M2L mode");
+      if (v == PFMM_M2L_SPECTRAL) {
+        if (pl->p != 4 && pl->p != 8)
+          return fail(PFMM_ERR_UNSUPPORTED, "the spectral interaction zones need p = 4 or 8");
+        if (!pl->g0.empty()) return fail(PFMM_ERR_UNSUPPORTED, "plan has learned tables");
+        if (!pl->mspec) {
+          M2LSpectral* f = nullptr;
+          hipError_t e = m2l_spectral_create(pl->L, pl->p, &f);
+          if (e == hipErrorOutOfMemory) return fail(PFMM_ERR_OUT_OF_MEMORY, "spectral zone buffers");
+          if (e != hipSuccess) return hip_fail(e, "spectral zone buffers");
+          pl->mspec = f;
+          e = m2l_spectral_tables(pl->mspec, pl->tab64, pl->stream);
+          if (e != hipSuccess) return hip_fail(e, "spectral zone kernels");
+        }
+        pl->m2l_fft = 0;
+        pl->m2l_spectral = 1;
+        return PFMM_OK;
+      }
       if (v == PFMM_M2L_FFT) {
         if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "the FFT interaction zones are periodic only");
         if (!pl->g0.empty()) return fail(PFMM_ERR_UNSUPPORTED, "plan has learned tables");
@@ -725,6 +750,7 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
         }
       }
       pl->m2l_fft = v;
+      pl->m2l_spectral = 0;
       return PFMM_OK;
     }
     case PFMM_OPT_NEAR: {
@@ -807,6 +833,9 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     ToepArgs ta = ta0;
     if (pl->m2l_fft)  // the FFT-convolution comparator, in the level's precision
       return m2l_fft_level(pl->fft, l, ta.X, ta.Y, ta.fp64, ta.accumulate, st);
+    if (pl->m2l_spectral)  // spectral stencils, FP64 throughout
+      return m2l_spectral_level(pl->mspec, l, ta.X, ta.fp64, ta.Y, ta.fp64, ta.accumulate, ta.offs,
+                                ta.noff, ta.isolated, st);
     if (ta.fp64 && ta.q == 8 && ta.C >= 31) {  // FP64 coarse level on the matrix cores
       ToepF64Args fa{};
       fa.n = ta.n;
@@ -1468,6 +1497,10 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
       delete b;
       return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with FFT interaction zones");
     }
+    if (plans[i]->m2l_spectral) {
+      delete b;
+      return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with spectral interaction zones");
+    }
     if (plans[i]->near_fft && !near_fft_fused(plans[i]->nfft)) {
       delete b;
       return fail(PFMM_ERR_UNSUPPORTED,
@@ -1843,7 +1876,8 @@ pfmm_status pfmm_learned_set(pfmm_plan_t pl, const float* weights, int bf16) {
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
-  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
+  if (pl->m2l_fft || pl->m2l_spectral)
+    return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT or spectral interaction zones");
   if (!weights) {
     if (pl->g0.empty()) return PFMM_OK;  // never corrected
     pl->learned = 0;
@@ -1861,7 +1895,8 @@ pfmm_status pfmm_learned_train_begin(pfmm_plan_t pl, const float* weights, doubl
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
-  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
+  if (pl->m2l_fft || pl->m2l_spectral)
+    return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT or spectral interaction zones");
   if (!weights || !(lr > 0.0)) return fail(PFMM_ERR_INVALID_ARG, "need weights and lr > 0");
   pfmm_status s0 = learned_prepare(pl);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
@@ -1929,7 +1964,8 @@ pfmm_status pfmm_learned_loss(pfmm_plan_t pl, const float* rho, const float* tar
   g_err.clear();
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
-  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
+  if (pl->m2l_fft || pl->m2l_spectral)
+    return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT or spectral interaction zones");
   if (!rho || !target || !loss) return fail(PFMM_ERR_INVALID_ARG, "NULL argument");
   pfmm_status s0 = learned_prepare(pl);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
@@ -1967,7 +2003,8 @@ pfmm_status pfmm_table_params(pfmm_plan_t pl, int* count) {
   if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
   if (!count) return fail(PFMM_ERR_INVALID_ARG, "count is NULL");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
-  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
+  if (pl->m2l_fft || pl->m2l_spectral)
+    return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT or spectral interaction zones");
   const pfmm_status s0 = learned_prepare(pl);
   if (s0 != PFMM_OK) return s0;
   *count = (pl->L - 1) * pl->nu;

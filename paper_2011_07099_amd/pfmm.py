@@ -16,7 +16,7 @@ GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3, "E": 4}
 PREC = {"fp32": 0, "bf16x3": 1}
 OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED, OPT_GS_A2, \
     OPT_ACCEL, OPT_EWALD_RS, OPT_M2L, OPT_NEAR = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
-M2L = {"gemm": 0, "fft": 1}
+M2L = {"gemm": 0, "fft": 1, "spectral": 2}
 NEAR = {"direct": 0, "fft": 1}
 ACCEL = {"fd4": 0, "expansion": 1}
 STAGES = ("p2m", "m2m", "m2l", "l2l", "l2p", "near", "fd4")
@@ -149,8 +149,9 @@ class Plan:
         _check(load().pfmm_plan_set(self._h, OPT_NEAR, ctypes.byref(v), 4))
 
     def set_m2l(self, mode):
-        """Interaction zones of the FP32 levels by "gemm" (block Toeplitz) or
-        "fft" (the HPM FFT convolution, a comparator)."""
+        """Interaction zones by "gemm" (block Toeplitz), "fft" (the HPM FFT
+        convolution, a comparator) or "spectral" (per-node transforms and a
+        per-frequency stencil, FP64; p = 4 or 8)."""
         v = ctypes.c_int32(M2L[mode])
         _check(load().pfmm_plan_set(self._h, OPT_M2L, ctypes.byref(v), 4))
 

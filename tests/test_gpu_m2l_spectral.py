@@ -1,0 +1,92 @@
+"""Interaction zones as spectral stencils (per-node transforms on the 2p
+cyclic grid, the zone's offsets summed per frequency, FP64), through the C
+ABI, against the oracle's step-by-step FMM and the block-Toeplitz GEMM path.
+
+* Locals of every level (Eq. 6 + Eq. 7) and the mesh potential against the
+  reference FMM, periodic and isolated, p = 4 and 8, G_S1, G_K and G_X.
+  The FP32 levels' rounding sets the tolerance, 2e-5, as for the other M2L
+  routes.  With every level kept in FP64 the spectral and GEMM locals differ
+  by FP64 rounding only: their FP32 read-backs agree to 2e-7 of max.
+* The split-precision plan with spectral zones at the 256^3 headline size is
+  covered by the headline parity test.
+* Unsupported uses are refused: p = 6, batches, learned tables.
+"""
+import numpy as np
+import pytest
+
+from oracle import fmm as ofmm
+from paper_2011_07099_amd import fields
+
+from gpu_util import f32, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve_stages(rho, L, p, green, m2l, fp64_levels=None, isolated=False, precision="fp32"):
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    N = rho.shape[0]
+    r = torch.from_numpy(np.ascontiguousarray(rho, dtype=np.float32)).cuda()
+    phi = torch.empty_like(r)
+    n = lambda l: 2 ** l
+    with Plan(N, L, p, green, fp64_levels=fp64_levels, isolated=isolated, m2l=m2l,
+              precision=precision) as pl:
+        pl.solve(r, phi)
+        Phi = {l: pl.locals(l).cpu().numpy().astype(np.float64).reshape((n(l),) * 3 + (p,) * 3)
+               for l in range(2, L + 1)}
+        torch.cuda.synchronize()
+    return phi.cpu().numpy().astype(np.float64), Phi
+
+
+@pytest.mark.parametrize("N,L,p,green,f64,iso,prec", [
+    (32, 3, 4, "S1", 0, False, "fp32"),       # every level in FP32
+    (64, 3, 8, "S1", None, False, "fp32"),    # default FP64 levels 2-3
+    (64, 3, 8, "S1", None, False, "bf16x3"),  # split near zone beside spectral zones
+    (128, 4, 4, "K", None, False, "fp32"),
+    (64, 2, 8, "S1", None, False, "fp32"),    # the smallest periodic tree
+    (32, 3, 4, "X", None, True, "fp32"),      # isolated twin (316-offset level 2)
+    (64, 3, 8, "X", None, True, "fp32"),
+])
+def test_spectral_zones_match_reference_and_gemm(N, L, p, green, f64, iso, prec):
+    rho = f32(fields.lognormal(N, 2.0, 1.0, seed=281 + N + p))
+    phi, Phi = _solve_stages(rho, L, p, green, "spectral", f64, iso, prec)
+    ref, st = ofmm.fmm(rho, L, p, green, stages=True, periodic=not iso)
+    for l in range(2, L + 1):
+        e = rel_max(Phi[l], st["Phi"][l])
+        print("spectral zones", (N, L, p, green, iso), "Phi level", l, "%.3e" % e)
+        assert e < 2e-5
+    e = rel_max(phi, ref)
+    g, _ = _solve_stages(rho, L, p, green, "gemm", f64, iso, prec)
+    eg = rel_max(phi, g)
+    print("spectral zones", (N, L, p, green, iso, prec),
+          "potential vs reference %.3e, vs GEMM path %.3e" % (e, eg))
+    tol = 2e-5 if prec == "fp32" else 1e-4
+    assert e < tol and eg < tol
+
+
+@pytest.mark.parametrize("N,L,p,green,iso", [
+    (32, 3, 4, "S1", False), (64, 3, 8, "K", False), (32, 3, 8, "X", True),
+])
+def test_spectral_zones_in_fp64_match_the_fp64_gemm(N, L, p, green, iso):
+    """Every level in FP64: the spectral and GEMM locals differ by FP64
+    rounding only, so their FP32 read-backs agree to one FP32 rounding."""
+    rho = f32(fields.lognormal(N, 2.0, 1.0, seed=291 + N + p))
+    _, Phi = _solve_stages(rho, L, p, green, "spectral", 30, iso)
+    _, G = _solve_stages(rho, L, p, green, "gemm", 30, iso)
+    for l in range(2, L + 1):
+        e = rel_max(Phi[l], G[l])
+        print("spectral vs GEMM zones, FP64 levels", (N, L, p, green, iso), "Phi level", l, "%.3e" % e)
+        assert e < 2e-7
+
+
+def test_spectral_zones_refusals():
+    import torch
+    from paper_2011_07099_amd.pfmm import Batch, Plan, PfmmError
+    with Plan(32, 3, 6, "S1") as pl:
+        with pytest.raises(PfmmError):
+            pl.set_m2l("spectral")
+    with Plan(32, 3, 4, "S1", m2l="spectral") as pl:
+        r = torch.zeros((32, 32, 32), device="cuda")
+        out = torch.empty_like(r)
+        with pytest.raises(PfmmError):
+            Batch([pl], [r], [out])
