@@ -33,7 +33,7 @@ METRIC = "cells/s at 256^3 p=8 periodic FMM, L2 err<=1e-4 vs PM; M2L MFMA util"
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
 # MI355X peaks (TFLOP/s) of the units each contraction runs on
-PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 157.3}
+PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 157.3, "f64 valu": 78.6}
 FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -41,21 +41,25 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 # plain 1 GiB copy (read x2.0, write x1.0), keyed by kernel, precision and the
 # SHA-1 prefix of the sources they were taken on (the kernel's file and
 # plan.hip, which sets the offset order and groups); a changed source reports
-# null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md (FFT near zone, where
-# the leaf interaction zones dominate) and profiles/near_direct_256cube_L4_p8_*.md.
+# null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md (the default: FFT near
+# zone, spectral interaction zones), profiles/zones_gemm_256cube_L4_p8_bf16x3.md
+# and profiles/near_direct_256cube_L4_p8_*.md.
 TRAFFIC = {
-    ("zones-L4", "bf16x3", "8bed0f69fede"): (182868 * 2.0 + 262144 * 1.0) * 1024,
-    ("zones-L4", "fp32", "e30717c294e3"): (205501 * 2.0 + 16384 * 1.0) * 1024,
-    ("near", "bf16x3", "8bed0f69fede"): (1178322 * 2.0 + 65536 * 1.0) * 1024,
-    ("near", "fp32", "e30717c294e3"): (11710447 * 2.0 + 68766 * 1.0) * 1024,
+    # the leaf level's spectral zones: node transforms, stencil and inverse together
+    ("spectral-L4", "bf16x3", "71fb86c3dfa2"): (218953 * 2.0 + 447628 * 1.0) * 1024,
+    ("spectral-L4", "fp32", "71fb86c3dfa2"): (219496 * 2.0 + 458776 * 1.0) * 1024,
+    ("zones-L4", "bf16x3", "3306028f0d67"): (182792 * 2.0 + 262144 * 1.0) * 1024,
+    ("near", "bf16x3", "3306028f0d67"): (1175903 * 2.0 + 65536 * 1.0) * 1024,
+    ("near", "fp32", "b40b63959910"): (11709836 * 2.0 + 68800 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
+SPECTRAL_SRC = ("m2l_spectral.hip", "plan.hip")
 
 
 def traffic_bytes(kernel, precision):
     import hashlib
     h = hashlib.sha1()
-    for name in KERNEL_SRC[precision]:
+    for name in (SPECTRAL_SRC if kernel.startswith("spectral") else KERNEL_SRC[precision]):
         h.update(open(os.path.join(ROOT, "paper_2011_07099_amd", "csrc", name), "rb").read())
     return TRAFFIC.get((kernel, precision, h.hexdigest()[:12]))
 
@@ -362,7 +366,7 @@ def main():
     ap.add_argument("--near", default="fft", choices=["direct", "fft"],
                     help="leaf near zone by direct summation or by FFT convolution "
                          "(headline and batch workloads)")
-    ap.add_argument("--m2l", default="gemm", choices=["gemm", "spectral"],
+    ap.add_argument("--m2l", default="spectral", choices=["gemm", "spectral"],
                     help="interaction zones by block-Toeplitz GEMM or spectral stencils "
                          "(headline workload)")
     ap.add_argument("--iters", type=int, default=20,
@@ -437,8 +441,17 @@ def main():
     m2l_tf = m2l_flops / (m2l_ms * 1e-3) / 1e12
     near_unit, near_products = ("bf16 mfma", 3) if args.precision == "bf16x3" else ("f32 valu", 1)
     per_level = {}
+    F = (2 * P) ** 2 * (P + 1)  # frequencies per node of the spectral zones
     for lv, lms in sorted(m2l_levels.items()):
         fl = (37 if lv == 2 else 189) * 2.0 * P ** 6 * 8 ** lv
+        if args.m2l == "spectral":
+            # one complex FP64 multiply-add per zone offset, target node and frequency
+            fl = (37 if lv == 2 else 189) * 8.0 * F * 8 ** lv
+            tf = fl / (lms * 1e-3) / 1e12
+            per_level[str(lv)] = {"ms": lms, "unit": "f64 valu", "products": 1, "achieved": tf,
+                                  "issued": tf, "peak": PEAK_UNIT["f64 valu"],
+                                  "frac": tf / PEAK_UNIT["f64 valu"], "flops": fl}
+            continue
         if lv in FP64_LEVELS:
             unit, products = "f64 mfma", 1
         elif args.precision == "bf16x3":
@@ -458,6 +471,15 @@ def main():
                         4 if args.accel == "expansion" else 1, near_ms),
                     "unit_used": near_unit, "products": near_products,
                     "issued_frac": near_tf * near_products / peak}
+    elif args.m2l == "spectral":
+        # the leaf level's spectral zones (transforms, stencil, inverse) dominate
+        lv = per_level[str(L)]
+        roofline = {"bound": "alu", "achieved": lv["achieved"], "peak": lv["peak"],
+                    "unit": "TFLOP/s", "frac": lv["frac"],
+                    "traffic": traffic_bytes("spectral-L%d" % L, args.precision),
+                    "kernel": "level-%d interaction zones, spectral stencil (3 launches/step: "
+                              "node transforms, stencil, inverse; %.3f ms)" % (L, lv["ms"]),
+                    "unit_used": "f64 valu", "products": 1, "issued_frac": lv["frac"]}
     else:
         # with the near zone by FFT the leaf level's interaction zones dominate
         lv = per_level[str(L)]
@@ -488,7 +510,10 @@ def main():
                    **({"near": args.near} if args.near != "direct" else {}),
                    **({"m2l": args.m2l} if args.m2l != "gemm" else {})},
         "roofline": roofline,
-        "m2l": {"achieved": m2l_tf, "unit": "TFLOP/s", "ms": m2l_ms,
+        "m2l": {"method": args.m2l,
+                "achieved": (sum(v["flops"] for v in per_level.values()) / (m2l_ms * 1e-3) / 1e12
+                             if args.m2l == "spectral" else m2l_tf),
+                "unit": "TFLOP/s", "ms": m2l_ms,
                 "launches": stages["m2l"][1], "levels": per_level},
         "stages_ms": {k: v[0] for k, v in stages.items()},
     }

@@ -249,8 +249,11 @@ __global__ void __launch_bounds__(node_threads<P>()) k_node_inv(const double2* _
 }
 
 // out_t(k) = sum_{d in zone(class of t)} khat_d(k) spec_{t+d}(k) for one
-// frequency k (blockIdx.x) and one tile of T^3 targets (blockIdx.y); T = 8,
-// or T = n = 4 on the 4^3 level (one class).  The tile's source spectra with a
+// frequency k and one tile of T^3 targets; T = 8, or T = n = 4 on the 4^3
+// level (one class).  Blocks are dealt to the 8 XCDs round robin; block g
+// takes frequency 8 (g / 8 / tiles) + g % 8 and tile (g / 8) % tiles, so each
+// XCD runs all tiles of a frequency back to back and their overlapping halos
+// come from its L2.  The tile's source spectra with a
 // 3-node halo are staged in LDS (wrapped, or zero outside an isolated box).
 // Wave w handles the targets of class w (levels >= 3), so the offset list,
 // and the kernel value at k, is uniform across the wave.
@@ -266,9 +269,11 @@ __global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ s
   const int B = T + 6;
   const int Bh = B / 2, H3 = Bh * Bh * Bh;  // parity-split box
   const int64_t nn = (int64_t)n * n * n;
-  const int64_t k = blockIdx.x;
   const int tpa = n / T;  // tiles per axis
-  const int tile = blockIdx.y;
+  const int tiles = tpa * tpa * tpa;
+  const int j = blockIdx.x >> 3;
+  const int64_t k = (int64_t)(j / tiles) * 8 + (blockIdx.x & 7);
+  const int tile = j % tiles;
   const int ox = (tile / (tpa * tpa)) * T, oy = ((tile / tpa) % tpa) * T, oz = (tile % tpa) * T;
   const double2* sk = spec + k * nn;
   for (int i = threadIdx.x; i < 343; i += blockDim.x) kk[i] = khat[(int64_t)i * F + k];
@@ -400,7 +405,7 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int T = n < 8 ? n : 8;
-  const dim3 grid((unsigned)f->F, (unsigned)((n / T) * (n / T) * (n / T)));
+  const unsigned grid = (unsigned)(f->F * (n / T) * (n / T) * (n / T));  // F is a multiple of 8
   const int classes = l == 2 ? 1 : 8;
   k_zone_spec<<<grid, classes == 8 ? 512 : 64, 0, st>>>(f->spec, f->khat[l], offs, noff, n, classes,
                                                          isolated, f->F, f->out);
