@@ -501,7 +501,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        # with the FFT near zone and spectral zones no step uses the split
+        # bf16 products: FP32 near zone and mesh transfers, FP64 zones
+        "dtype": "f32+f64" if (args.near == "fft" and args.m2l == "spectral") else args.precision,
         "data": "synthetic",
         "config": {"workload": "periodic FMM, 256^3 lognormal density (P(k)~k^-1.5, "
                                "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
