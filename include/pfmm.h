@@ -193,8 +193,9 @@ typedef enum {
    * potentials added in each level's precision.  Allocates about
    * 2 (2p)^2 (p + 1) x 16 bytes per leaf-level node (0.3 GB at 16^3 nodes,
    * p = 8) and transforms the kernels of the 343 offsets in [-3, 3]^3 per
-   * level (plan time; again when G changes).  Periodic and isolated plans;
-   * not for batches or learned tables. */
+   * level (plan time; again when G changes).  Periodic and isolated plans
+   * and batches (the zones then run as the plan's own launches in the
+   * batch graph); not with learned tables. */
   PFMM_M2L_SPECTRAL = 2
 } pfmm_m2l;
 
@@ -341,8 +342,9 @@ pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
  *     rest in FP32 with FP64 per-offset running totals.
  * Each list is drained by one persistent kernel through an atomic counter.
  * A plan with PFMM_NEAR_FFT (leaf edges 4, 8, 16 only) has no near-zone
- * items: its per-leaf transforms and stencil run as their own kernels in
- * the same graph, beside the matrix-core persistent kernels.
+ * items, and one with PFMM_M2L_SPECTRAL no interaction-zone items: their
+ * transforms and stencils run as their own kernels in the same graph,
+ * beside the matrix-core persistent kernels.
  * The portable items fall into groups by block edge (p for interaction zones,
  * min(s, 8) for near zones), FP32 or FP64 and near or interaction zone; the
  * tile width (targets per thread: 1, 2 or 4) of each FP32 group is picked by

@@ -1248,7 +1248,7 @@ std::vector<BatchItem> batch_items(const pfmm_batch_s* b, const std::map<std::st
     const pfmm_plan_s* pl = b->plans[f];
     const int p = pl->p;
     for (int l = 2; l <= pl->L; ++l) {
-      if (batch_f64_level(pl, l)) continue;
+      if (batch_f64_level(pl, l) || pl->m2l_spectral) continue;  // other lists / own launches
       BatchItem it{};
       it.fp64 = level64(pl, l);
       it.tab = it.fp64 ? (const void*)pl->tab64[l] : (const void*)pl->tab32[l];
@@ -1296,7 +1296,7 @@ hipError_t batch_mma_upload(pfmm_batch_s* b) {
   for (size_t f = 0; f < b->plans.size(); ++f) {
     const pfmm_plan_s* pl = b->plans[f];
     for (int l = 3; l >= 2; --l) {
-      if (l > pl->L || !batch_f64_level(pl, l)) continue;
+      if (l > pl->L || !batch_f64_level(pl, l) || pl->m2l_spectral) continue;
       ToepF64Args x{};
       x.n = 1 << l;
       x.m = l == 2 ? 1 : 2;
@@ -1398,13 +1398,18 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
       e = launch_batch_mma(2, b->sargs, b->sitems, b->nsplit, b->counter + 1, b->sgrid, b->s_split);
     if (e == hipSuccess)
       e = launch_batch_mma(64, b->fargs, b->fitems, b->nf64, b->counter + 2, b->fgrid, b->s_f64);
-    // FFT near zones (their own per-leaf kernels, no work items): they write
-    // the potential before the downward passes add to it
+    // FFT near zones and spectral interaction zones (their own kernels, no
+    // work items): they write the potential and each level's zone sums
+    // before the downward passes add to them
     for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
       pfmm_plan_s* pl = b->plans[f];
-      if (!pl->near_fft) continue;
-      float* out[1] = {b->phi[f]};
-      e = near_fft_run(pl->nfft, b->rho[f], out, 1, 0, st);
+      if (pl->near_fft) {
+        float* out[1] = {b->phi[f]};
+        e = near_fft_run(pl->nfft, b->rho[f], out, 1, 0, st);
+      }
+      for (int l = 2; l <= pl->L && e == hipSuccess && pl->m2l_spectral; ++l)
+        e = m2l_spectral_level(pl->mspec, l, pl->M[l], level64(pl, l), pl->P[l], level64(pl, l), 0,
+                               l == 2 ? pl->offs_l2 : pl->offs_iz, l == 2 ? pl->nl2 : 189, 0, st);
     }
     if (e == hipSuccess) e = launch_batch_toeplitz(b->items, b->nitems, b->counter, b->grid, st);
     if (e == hipSuccess) e = hipEventRecord(b->ev_split, b->s_split);
@@ -1496,10 +1501,6 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
     if (plans[i]->m2l_fft) {
       delete b;
       return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with FFT interaction zones");
-    }
-    if (plans[i]->m2l_spectral) {
-      delete b;
-      return fail(PFMM_ERR_UNSUPPORTED, "batches of plans with spectral interaction zones");
     }
     if (plans[i]->near_fft && !near_fft_fused(plans[i]->nfft)) {
       delete b;

@@ -37,7 +37,8 @@ def _make(specs, precision="fp32"):
         rho = f32(fields.lognormal(N, 2.0, 1.0, seed=seed))
         host.append(rho)
         plans.append(Plan(N, L, p, g, precision=spec[5] if len(spec) > 5 else precision,
-                          near=spec[6] if len(spec) > 6 else "direct"))
+                          near=spec[6] if len(spec) > 6 else "direct",
+                          m2l=spec[7] if len(spec) > 7 else "gemm"))
         rhos.append(torch.from_numpy(rho.astype(np.float32)).cuda())
         phis.append(torch.full_like(rhos[-1], float("nan")))
     return plans, rhos, phis, host
@@ -184,5 +185,41 @@ def test_fft_near_zone_fields_in_batches():
         e = rel_max(phi.numpy().astype(np.float64), ofmm.fmm(rho, L, p, g))
         print("batch field", spec, "rel max", e)
         assert e < (SPLIT_TOL if prec == "bf16x3" else BATCH_TOL)
+    for pl in plans:
+        pl.close()
+
+
+SPECTRAL_SPECS = [  # (N, L, p, green, seed, precision, near zone, interaction zones)
+    (64, 3, 8, "S1", 401, "bf16x3", "fft", "spectral"),
+    (128, 3, 8, "S1", 402, "fp32", "fft", "spectral"),
+    (32, 3, 4, "S1", 403, "fp32", "direct", "spectral"),
+    (64, 3, 4, "X", 405, "bf16x3", "direct", "spectral"),  # split direct near zone
+    (64, 3, 6, "K", 404, "fp32", "fft", "gemm"),            # p = 6: zones as work items
+]
+
+
+def test_spectral_zone_fields_in_batches():
+    """Plans with spectral interaction zones in a batch: their levels run as
+    the plan's own launches in the graph (zone sums written, parents added by
+    the downward passes); every field against the reference FMM, two graph
+    launches bit for bit."""
+    import torch
+    from paper_2011_07099_amd.pfmm import Batch
+    plans, rhos, phis, host = _make(SPECTRAL_SPECS)
+    with Batch(plans, rhos, phis) as b:
+        outs = []
+        for r in range(2):
+            for f in phis:
+                f.fill_(float("nan"))
+            b.solve()
+            torch.cuda.synchronize()
+            outs.append([f.cpu().clone() for f in phis])
+    for a, c in zip(outs[0], outs[1]):
+        assert torch.equal(a, c)
+    for spec, phi, rho in zip(SPECTRAL_SPECS, outs[0], host):
+        N, L, p, g, seed, prec, near, m2l = spec
+        e = rel_max(phi.numpy().astype(np.float64), ofmm.fmm(rho, L, p, g))
+        print("batch field", spec, "rel max", e)
+        assert e < (SPLIT_TOL if (prec == "bf16x3" and near == "direct") else BATCH_TOL)
     for pl in plans:
         pl.close()
