@@ -46,11 +46,11 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 # and profiles/near_direct_256cube_L4_p8_*.md.
 TRAFFIC = {
     # the leaf level's spectral zones: node transforms, stencil and inverse together
-    ("spectral-L4", "bf16x3", "71fb86c3dfa2"): (218953 * 2.0 + 447628 * 1.0) * 1024,
-    ("spectral-L4", "fp32", "71fb86c3dfa2"): (219496 * 2.0 + 458776 * 1.0) * 1024,
-    ("zones-L4", "bf16x3", "3306028f0d67"): (182792 * 2.0 + 262144 * 1.0) * 1024,
-    ("near", "bf16x3", "3306028f0d67"): (1175903 * 2.0 + 65536 * 1.0) * 1024,
-    ("near", "fp32", "b40b63959910"): (11709836 * 2.0 + 68800 * 1.0) * 1024,
+    ("spectral-L4", "bf16x3", "e6acee4684ec"): (217883 * 2.0 + 443624 * 1.0) * 1024,
+    ("spectral-L4", "fp32", "e6acee4684ec"): (219114 * 2.0 + 437598 * 1.0) * 1024,
+    ("zones-L4", "bf16x3", "6469cce526a2"): (252580 * 2.0 + 262144 * 1.0) * 1024,
+    ("near", "bf16x3", "6469cce526a2"): (1156807 * 2.0 + 65536 * 1.0) * 1024,
+    ("near", "fp32", "e15380d05dd6"): (11732373 * 2.0 + 68948 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
 SPECTRAL_SRC = ("m2l_spectral.hip", "plan.hip")

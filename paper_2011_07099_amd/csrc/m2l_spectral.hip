@@ -35,7 +35,7 @@ struct M2LSpectral {
   double2* spec = nullptr;       // [F][nodes] of the level being summed
   double2* out = nullptr;        // [F][nodes]
   std::vector<double2*> khat;    // per level: [343][F], offsets of [-3, 3]^3
-  double2* dft[2] = {nullptr, nullptr};
+  double2* dft[2] = {nullptr, nullptr};  // [343][F] DFT passes of the kernels
 };
 
 namespace {
@@ -342,11 +342,14 @@ __global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ s
 // K_d[x][y][z] = tab[w(x) - p dx][w(y) - p dy][w(z) - p dz] (tab centred at
 // C), zero on the unused slot p; then y and x (k_sdft_axis); stored scaled in
 // the frequency order of k_node_fwd.
-__global__ void k_sdft_z(const double* __restrict__ tab, int p, int C, int dx, int dy, int dz,
-                         double2* __restrict__ A) {
+__global__ void k_sdft_z(const double* __restrict__ tab, int p, int C, double2* __restrict__ A) {
   const int M = 2 * p, H = p + 1;
+  const int64_t F = (int64_t)M * M * H;
+  const int di = blockIdx.y;  // offset (dx, dy, dz) in [-3, 3]^3
+  const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
+  A += di * F;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= (int64_t)M * M * H) return;
+  if (i >= F) return;
   const int kz = (int)(i % H), y = (int)((i / H) % M), x = (int)(i / ((int64_t)H * M));
   const int E = 2 * C + 1;
   double re = 0.0, im = 0.0;
@@ -367,8 +370,11 @@ __global__ void k_sdft_z(const double* __restrict__ tab, int p, int C, int dx, i
 
 __global__ void k_sdft_axis(const double2* __restrict__ in, int p, int axis, double2* __restrict__ out) {
   const int M = 2 * p, H = p + 1;
+  const int64_t F = (int64_t)M * M * H;
+  in += blockIdx.y * F;
+  out += blockIdx.y * F;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= (int64_t)M * M * H) return;
+  if (i >= F) return;
   const int kz = (int)(i % H), b = (int)((i / H) % M), a = (int)(i / ((int64_t)H * M));
   const int kk = axis ? b : a;
   double re = 0.0, im = 0.0;
@@ -385,6 +391,8 @@ __global__ void k_sdft_axis(const double2* __restrict__ in, int p, int axis, dou
 __global__ void k_sdft_store(const double2* __restrict__ in, int p, double scale, double2* __restrict__ out) {
   const int M = 2 * p, H = p + 1;
   const int64_t F = (int64_t)M * M * H;
+  in += blockIdx.y * F;
+  out += blockIdx.y * F;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= F) return;
   const int kz = (int)(i % H), ky = (int)((i / H) % M), kx = (int)(i / ((int64_t)H * M));
@@ -440,7 +448,7 @@ hipError_t m2l_spectral_create(int L, int p, M2LSpectral** out) {
   f->khat.assign(L + 1, nullptr);
   hipError_t e = hipMalloc(&f->spec, (size_t)(f->F * nodes) * sizeof(double2));
   if (e == hipSuccess) e = hipMalloc(&f->out, (size_t)(f->F * nodes) * sizeof(double2));
-  for (int d = 0; d < 2 && e == hipSuccess; ++d) e = hipMalloc(&f->dft[d], (size_t)f->F * sizeof(double2));
+  for (int d = 0; d < 2 && e == hipSuccess; ++d) e = hipMalloc(&f->dft[d], (size_t)(343 * f->F) * sizeof(double2));
   for (int l = 2; l <= L && e == hipSuccess; ++l)
     e = hipMalloc(&f->khat[l], (size_t)(343 * f->F) * sizeof(double2));
   if (e != hipSuccess) {
@@ -455,15 +463,14 @@ hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64
   const int p = f->p, C = 4 * p - 1;
   const double scale = 1.0 / (double)((2 * p) * (2 * p) * (2 * p));
   hipError_t e = hipSuccess;
-  for (int l = 2; l <= f->L && e == hipSuccess; ++l)
-    for (int di = 0; di < 343 && e == hipSuccess; ++di) {
-      const int dx = di / 49 - 3, dy = (di / 7) % 7 - 3, dz = di % 7 - 3;
-      k_sdft_z<<<nblk(f->F), kThreads, 0, st>>>(tab64[l], p, C, dx, dy, dz, f->dft[0]);
-      k_sdft_axis<<<nblk(f->F), kThreads, 0, st>>>(f->dft[0], p, 1, f->dft[1]);
-      k_sdft_axis<<<nblk(f->F), kThreads, 0, st>>>(f->dft[1], p, 0, f->dft[0]);
-      k_sdft_store<<<nblk(f->F), kThreads, 0, st>>>(f->dft[0], p, scale, f->khat[l] + (int64_t)di * f->F);
-      e = hipGetLastError();
-    }
+  const dim3 grid(nblk(f->F), 343);  // all offsets of [-3, 3]^3 at once
+  for (int l = 2; l <= f->L && e == hipSuccess; ++l) {
+    k_sdft_z<<<grid, kThreads, 0, st>>>(tab64[l], p, C, f->dft[0]);
+    k_sdft_axis<<<grid, kThreads, 0, st>>>(f->dft[0], p, 1, f->dft[1]);
+    k_sdft_axis<<<grid, kThreads, 0, st>>>(f->dft[1], p, 0, f->dft[0]);
+    k_sdft_store<<<grid, kThreads, 0, st>>>(f->dft[0], p, scale, f->khat[l]);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   return e;
 }

@@ -9,7 +9,7 @@ ABI, against the oracle's step-by-step FMM and the block-Toeplitz GEMM path.
   by FP64 rounding only: their FP32 read-backs agree to 2e-7 of max.
 * The split-precision plan with spectral zones at the 256^3 headline size is
   covered by the headline parity test.
-* Unsupported uses are refused: p = 6, batches, learned tables.
+* p = 6 is refused (batches with spectral plans: test_gpu_batch.py).
 """
 import numpy as np
 import pytest
@@ -80,13 +80,7 @@ def test_spectral_zones_in_fp64_match_the_fp64_gemm(N, L, p, green, iso):
 
 
 def test_spectral_zones_refusals():
-    import torch
-    from paper_2011_07099_amd.pfmm import Batch, Plan, PfmmError
-    with Plan(32, 3, 6, "S1") as pl:
+    from paper_2011_07099_amd.pfmm import Plan, PfmmError
+    with Plan(32, 3, 6, "S1") as pl:   # radix-4 transforms: p = 4 or 8 only
         with pytest.raises(PfmmError):
             pl.set_m2l("spectral")
-    with Plan(32, 3, 4, "S1", m2l="spectral") as pl:
-        r = torch.zeros((32, 32, 32), device="cuda")
-        out = torch.empty_like(r)
-        with pytest.raises(PfmmError):
-            Batch([pl], [r], [out])
