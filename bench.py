@@ -313,11 +313,12 @@ def table_bench(args):
 
 
 def m2l_bench(args):
-    """The interaction zones (Eq. 6) two ways on the headline mesh (256^3,
+    """The interaction zones (Eq. 6) three ways on the headline mesh (256^3,
     L = 4, G_S1, the same density): the block-Toeplitz GEMM of this library
-    (FP32 portable kernel, and split BF16 on the matrix cores at p = 8) and
-    the HPM form the paper runs (Sec. 2: per target node one FFT convolution
-    of its zone's effective masses with G, rocFFT), at p = 4, 6, 8.  Levels
+    (FP32 portable kernel, and split BF16 on the matrix cores at p = 8), the
+    HPM form the paper runs (Sec. 2: per target node one FFT convolution of
+    its zone's effective masses with G, rocFFT), and the spectral stencils
+    (per-node transforms, FP64; p = 4 and 8), at p = 4, 6, 8.  Levels
     2-3 are FP64 in every variant (FP64 matrix cores at p = 8, FP64
     transforms for the FFT).  Per-level medians of the profiled stage times
     over `steps` solves; `value` is the FFT-to-GEMM time ratio of all levels
@@ -329,9 +330,12 @@ def m2l_bench(args):
     phi = torch.empty_like(rho)
     res = {}
     for p in (4, 6, 8):
-        for m2l, prec in (("gemm", "fp32"), ("gemm", "bf16x3"), ("fft", "fp32")):
+        for m2l, prec in (("gemm", "fp32"), ("gemm", "bf16x3"), ("fft", "fp32"),
+                          ("spectral", "fp32")):
             if prec == "bf16x3" and p != 8:
                 continue  # the split matrix-core kernel serves p = 8
+            if m2l == "spectral" and p == 6:
+                continue  # radix-4 transforms: p = 4 and 8
             with Plan(N, L, p, GREEN, precision=prec, m2l=m2l) as pl:
                 for _ in range(max(args.warmup, 1)):
                     pl.solve(rho, phi)
@@ -351,6 +355,7 @@ def m2l_bench(args):
            "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
            "config": {"workload": "256^3 L=4 G_S1 lognormal (alpha=1.5, sigma_delta=2, seed 5); "
                                   "M2L of levels 2-4, p = 4, 6, 8"},
+           "spectral_vs_gemm_p8": res["p8 spectral fp32"]["ms_total"] / res["p8 gemm bf16x3"]["ms_total"],
            "results": res}
     print(json.dumps(out), flush=True)
 
