@@ -338,6 +338,94 @@ __global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ s
   out[k * nn + ((int64_t)(ox + tx) * n + (oy + ty)) * n + (oz + tz)] = make_double2(re, im);
 }
 
+// The same sums on levels with n >= 16 nodes per axis (levels >= 4), tiles
+// of 8 x 8 x 16 targets: each lane owns two targets of its wave's class, 2
+// apart in z, and walks the zone by (dx, dy) columns.  Stored split by
+// parity, a full column (six consecutive dz) is two runs of three entries
+// per target, and the second target's runs are the first's shifted by one,
+// so four loads per parity plane serve both (8 loads for 12 multiply-adds).
+// Columns next to the target (|dx|, |dy| <= 1) keep the three dz outside the
+// near zone.  The zone of class c is {d : d_i in [-2 - c_i, 3 - c_i],
+// max |d_i| > 1} (Sec. 2), enumerated here directly.
+__global__ void __launch_bounds__(512) k_zone_spec2(const double2* __restrict__ spec,
+                                                    const double2* __restrict__ khat, int n,
+                                                    int isolated, int64_t F,
+                                                    double2* __restrict__ out) {
+  constexpr int TX = 8, TZ = 16, BX = TX + 6, BZ = TZ + 6;
+  constexpr int HX = BX / 2, HZ = BZ / 2, H3 = HX * HX * HZ;
+  __shared__ double2 box[8 * H3];
+  __shared__ double2 kk[343];
+  const int64_t nn = (int64_t)n * n * n;
+  const int tpx = n / TX, tpz = n / TZ;
+  const int tiles = tpx * tpx * tpz;
+  const int j = blockIdx.x >> 3;
+  const int64_t k = (int64_t)(j / tiles) * 8 + (blockIdx.x & 7);
+  const int tile = j % tiles;
+  const int ox = (tile / (tpx * tpz)) * TX, oy = ((tile / tpz) % tpx) * TX, oz = (tile % tpz) * TZ;
+  const double2* sk = spec + k * nn;
+  for (int i = threadIdx.x; i < 343; i += blockDim.x) kk[i] = khat[(int64_t)i * F + k];
+  for (int i = threadIdx.x; i < BX * BX * BZ; i += blockDim.x) {
+    const int bx = i / (BX * BZ), by = (i / BZ) % BX, bz = i % BZ;
+    const int x = ox + bx - 3, y = oy + by - 3, z = oz + bz - 3;
+    double2 v = make_double2(0.0, 0.0);
+    if (!isolated || ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n))
+      v = sk[((int64_t)(x & (n - 1)) * n + (y & (n - 1))) * n + (z & (n - 1))];
+    box[(((bx & 1) * 2 + (by & 1)) * 2 + (bz & 1)) * H3 + ((bx >> 1) * HX + (by >> 1)) * HZ + (bz >> 1)] = v;
+  }
+  __syncthreads();
+  const int cls = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cx = cls >> 2, cy = (cls >> 1) & 1, cz = cls & 1;
+  const int kx = lane >> 4, ky = (lane >> 2) & 3, kz = 2 * (lane & 3);
+  const int base = (kx * HX + ky) * HZ + kz;
+  double r1 = 0.0, i1 = 0.0, r2 = 0.0, i2 = 0.0;
+  const int dz0 = -2 - cz;
+  for (int dx = -2 - cx; dx <= 3 - cx; ++dx) {
+    const int sx = cx + dx + 3;
+    for (int dy = -2 - cy; dy <= 3 - cy; ++dy) {
+      const int sy = cy + dy + 3;
+      const int pxy = ((sx & 1) * 2 + (sy & 1)) * 2;
+      const int col = base + ((sx >> 1) * HX + (sy >> 1)) * HZ;
+      const double2* kc = kk + (dx + 3) * 49 + (dy + 3) * 7 + (dz0 + 3);
+      if (abs(dx) > 1 || abs(dy) > 1) {
+        // dz0 + 2m: source z 1 + 2m (odd plane, h = m); dz0 + 2m + 1: z 2 + 2m (even, h = m + 1)
+        const double2* pa = box + (pxy + 1) * H3 + col;
+        const double2* pb = box + pxy * H3 + col + 1;
+        double2 a[4], b[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          a[m] = pa[m];
+          b[m] = pb[m];
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const double2 ka = kc[2 * m], kb = kc[2 * m + 1];
+          r1 += ka.x * a[m].x - ka.y * a[m].y + kb.x * b[m].x - kb.y * b[m].y;
+          i1 += ka.x * a[m].y + ka.y * a[m].x + kb.x * b[m].y + kb.y * b[m].x;
+          r2 += ka.x * a[m + 1].x - ka.y * a[m + 1].y + kb.x * b[m + 1].x - kb.y * b[m + 1].y;
+          i2 += ka.x * a[m + 1].y + ka.y * a[m + 1].x + kb.x * b[m + 1].y + kb.y * b[m + 1].x;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const int dz = dz0 + q;
+          if (dz >= -1 && dz <= 1) continue;
+          const int sz = 1 + q;
+          const double2* ps = box + (pxy + (sz & 1)) * H3 + col + (sz >> 1);
+          const double2 kd = kc[q], s1 = ps[0], s2 = ps[1];
+          r1 += kd.x * s1.x - kd.y * s1.y;
+          i1 += kd.x * s1.y + kd.y * s1.x;
+          r2 += kd.x * s2.x - kd.y * s2.y;
+          i2 += kd.x * s2.y + kd.y * s2.x;
+        }
+      }
+    }
+  }
+  const int tx = ox + 2 * kx + cx, ty = oy + 2 * ky + cy, tz = oz + 2 * kz + cz;
+  double2* o = out + k * nn + ((int64_t)tx * n + ty) * n + tz;
+  o[0] = make_double2(r1, i1);
+  o[2] = make_double2(r2, i2);
+}
+
 // Kernel spectrum of offset d (FP64 separable DFT): first pass along z of
 // K_d[x][y][z] = tab[w(x) - p dx][w(y) - p dy][w(z) - p dz] (tab centred at
 // C), zero on the unused slot p; then y and x (k_sdft_axis); stored scaled in
@@ -412,11 +500,16 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
     k_node_fwd<P, float><<<(unsigned)nn, NT, 0, st>>>((const float*)Ml, nn, f->spec);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int T = n < 8 ? n : 8;
-  const unsigned grid = (unsigned)(f->F * (n / T) * (n / T) * (n / T));  // F is a multiple of 8
   const int classes = l == 2 ? 1 : 8;
-  k_zone_spec<<<grid, classes == 8 ? 512 : 64, 0, st>>>(f->spec, f->khat[l], offs, noff, n, classes,
-                                                         isolated, f->F, f->out);
+  if (n >= 16) {  // 8 x 8 x 16 tiles, two targets per lane
+    const unsigned grid = (unsigned)(f->F * (n / 8) * (n / 8) * (n / 16));  // F is a multiple of 8
+    k_zone_spec2<<<grid, 512, 0, st>>>(f->spec, f->khat[l], n, isolated, f->F, f->out);
+  } else {
+    const int T = n < 8 ? n : 8;
+    const unsigned grid = (unsigned)(f->F * (n / T) * (n / T) * (n / T));
+    k_zone_spec<<<grid, classes == 8 ? 512 : 64, 0, st>>>(f->spec, f->khat[l], offs, noff, n, classes,
+                                                           isolated, f->F, f->out);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (p64)
