@@ -9,6 +9,9 @@ ABI, against the oracle's step-by-step FMM and the block-Toeplitz GEMM path.
   by FP64 rounding only: their FP32 read-backs agree to 2e-7 of max.
 * The split-precision plan with spectral zones at the 256^3 headline size is
   covered by the headline parity test.
+* Both transform routes together (FFT near zone and spectral zones) with
+  accelerations from the expansion, periodic and isolated, against the
+  oracle's fmm_accel (measured 1-6e-7; tolerance 2e-5).
 * p = 6 is refused (batches with spectral plans: test_gpu_batch.py).
 """
 import numpy as np
@@ -84,3 +87,26 @@ def test_spectral_zones_refusals():
     with Plan(32, 3, 6, "S1") as pl:   # radix-4 transforms: p = 4 or 8 only
         with pytest.raises(PfmmError):
             pl.set_m2l("spectral")
+
+
+@pytest.mark.parametrize("N,L,p,iso", [(32, 3, 4, True), (64, 3, 8, False), (64, 4, 4, True)])
+def test_spectral_zones_with_fft_near_zone_and_expansion_accel(N, L, p, iso):
+    """Both transform routes together (FFT near zone, spectral zones), with
+    accelerations from the expansion: potential and accelerations against the
+    oracle's fmm_accel, periodic and isolated."""
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    green = "X" if iso else "S1"
+    rho = f32(fields.lognormal(N, 1.5, 1.0, seed=301 + N + p))
+    r = torch.from_numpy(rho.astype(np.float32)).cuda()
+    phi = torch.empty_like(r)
+    acc = torch.empty((3, N, N, N), dtype=torch.float32, device="cuda")
+    with Plan(N, L, p, green, isolated=iso, accel="expansion", near="fft", m2l="spectral") as pl:
+        pl.solve(r, phi, acc)
+        torch.cuda.synchronize()
+    ref, ref_phi = ofmm.fmm_accel(rho, L, p, green, periodic=not iso)
+    e = rel_max(acc.cpu().numpy().astype(np.float64), ref)
+    ep = rel_max(phi.cpu().numpy().astype(np.float64), ref_phi)
+    print("FFT near zone + spectral zones + expansion accel", (N, L, p, iso),
+          "max err / max|g| = %.3e, potential %.3e" % (e, ep))
+    assert e < 2e-5 and ep < 2e-5
