@@ -28,10 +28,13 @@ template <class W> __device__ inline const W* wsel(Weights w);
 template <> __device__ inline const float* wsel<float>(Weights w) { return w.f; }
 template <> __device__ inline const double* wsel<double>(Weights w) { return w.d; }
 
-template <class TO, class W>
+// S, P: leaf width and gridlet size fixed at compile time (0: the arguments),
+// so that the index arithmetic folds and the contraction loops unroll.
+template <class TO, class W, int S = 0, int P = 0>
 __global__ __launch_bounds__(kThreads) void k_p2m(const float* __restrict__ rho,
-                                                   TO* __restrict__ M, Weights Aw, int N, int s,
-                                                   int p, W h3) {
+                                                   TO* __restrict__ M, Weights Aw, int N, int s_,
+                                                   int p_, W h3) {
+  const int s = S ? S : s_, p = P ? P : p_;
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
   W* sA = sm;              // [p][s]
@@ -174,11 +177,12 @@ __global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
 // out[b s + c] (+)= scale sum_a Wx[ax][cx] Wy[ay][cy] Wz[az][cz] P[b][a]: L2P
 // with Wx = Wy = Wz = A and scale 1, or one component of the gradient of the
 // leaf's local expansion with the derivative weights on that axis
-template <class TI, class W>
+template <class TI, class W, int S = 0, int PP = 0>
 __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
                                                    float* __restrict__ phi, Weights Wxw,
                                                    Weights Wyw, Weights Wzw, W scale, int N,
-                                                   int s, int p, int accumulate) {
+                                                   int s_, int p_, int accumulate) {
+  const int s = S ? S : s_, p = PP ? PP : p_;
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
   const int p3 = p * p * p;
@@ -260,9 +264,21 @@ hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int 
   if (m64)
     hipLaunchKernelGGL((k_p2m<double, double>), dim3(nL * nL * nL), dim3(kThreads),
                        words * sizeof(double), st, rho, (double*)M, A, N, s, p, h3);
-  else
-    hipLaunchKernelGGL((k_p2m<float, float>), dim3(nL * nL * nL), dim3(kThreads),
-                       words * sizeof(float), st, rho, (float*)M, A, N, s, p, (float)h3);
+  else {
+    const dim3 g(nL * nL * nL), b(kThreads);
+    const size_t sh = words * sizeof(float);
+    const float hf = (float)h3;
+    if (s == 16 && p == 8)
+      hipLaunchKernelGGL((k_p2m<float, float, 16, 8>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
+    else if (s == 8 && p == 8)
+      hipLaunchKernelGGL((k_p2m<float, float, 8, 8>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
+    else if (s == 16 && p == 4)
+      hipLaunchKernelGGL((k_p2m<float, float, 16, 4>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
+    else if (s == 8 && p == 4)
+      hipLaunchKernelGGL((k_p2m<float, float, 8, 4>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
+    else
+      hipLaunchKernelGGL((k_p2m<float, float>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
+  }
   return hipGetLastError();
 }
 
@@ -311,10 +327,22 @@ hipError_t l2p_axes(const void* P, int p64, float* out, Weights Wx, Weights Wy, 
     hipLaunchKernelGGL((k_l2p<double, double>), dim3(nL * nL * nL), dim3(kThreads),
                        words * sizeof(double), st, (const double*)P, out, Wx, Wy, Wz, scale, N, s,
                        p, accumulate);
-  else
-    hipLaunchKernelGGL((k_l2p<float, float>), dim3(nL * nL * nL), dim3(kThreads),
-                       words * sizeof(float), st, (const float*)P, out, Wx, Wy, Wz, (float)scale,
-                       N, s, p, accumulate);
+  else {
+    const dim3 g(nL * nL * nL), b(kThreads);
+    const size_t sh = words * sizeof(float);
+    const float sc = (float)scale;
+    const float* Pf = (const float*)P;
+    if (s == 16 && p == 8)
+      hipLaunchKernelGGL((k_l2p<float, float, 16, 8>), g, b, sh, st, Pf, out, Wx, Wy, Wz, sc, N, s, p, accumulate);
+    else if (s == 8 && p == 8)
+      hipLaunchKernelGGL((k_l2p<float, float, 8, 8>), g, b, sh, st, Pf, out, Wx, Wy, Wz, sc, N, s, p, accumulate);
+    else if (s == 16 && p == 4)
+      hipLaunchKernelGGL((k_l2p<float, float, 16, 4>), g, b, sh, st, Pf, out, Wx, Wy, Wz, sc, N, s, p, accumulate);
+    else if (s == 8 && p == 4)
+      hipLaunchKernelGGL((k_l2p<float, float, 8, 4>), g, b, sh, st, Pf, out, Wx, Wy, Wz, sc, N, s, p, accumulate);
+    else
+      hipLaunchKernelGGL((k_l2p<float, float>), g, b, sh, st, Pf, out, Wx, Wy, Wz, sc, N, s, p, accumulate);
+  }
   return hipGetLastError();
 }
 }  // namespace
