@@ -75,10 +75,11 @@ __global__ __launch_bounds__(kThreads) void k_p2m(const float* __restrict__ rho,
   }
 }
 
-template <class TI, class TO, class W>
+template <class TI, class TO, class W, int PP = 0>
 __global__ __launch_bounds__(kThreads) void k_m2m(const TI* __restrict__ Mc,
                                                    TO* __restrict__ Mp, Weights Tw, int np,
-                                                   int p) {
+                                                   int p_) {
+  const int p = PP ? PP : p_;
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
   const int p3 = p * p * p;
@@ -126,10 +127,11 @@ __global__ __launch_bounds__(kThreads) void k_m2m(const TI* __restrict__ Mc,
   for (int i = tid, r = 0; i < p3; i += kThreads, ++r) Mp[(size_t)B * p3 + i] = (TO)acc[r];
 }
 
-template <class TI, class TO, class W>
+template <class TI, class TO, class W, int PP = 0>
 __global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
                                                    TO* __restrict__ Pc, Weights Tw, int np,
-                                                   int p, int accumulate) {
+                                                   int p_, int accumulate) {
+  const int p = PP ? PP : p_;
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
   const int p3 = p * p * p;
@@ -282,19 +284,29 @@ hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int 
   return hipGetLastError();
 }
 
+// M2M / L2L instance with the gridlet size fixed at compile time for p = 4
+// and 8 (index arithmetic folded, loops unrolled), else the generic one.
+#define PFMM_BY_P(KERNEL, TI, TO, W, ...)                        \
+  do {                                                            \
+    if (p == 8)                                                   \
+      hipLaunchKernelGGL((KERNEL<TI, TO, W, 8>), __VA_ARGS__);    \
+    else if (p == 4)                                              \
+      hipLaunchKernelGGL((KERNEL<TI, TO, W, 4>), __VA_ARGS__);    \
+    else                                                          \
+      hipLaunchKernelGGL((KERNEL<TI, TO, W>), __VA_ARGS__);       \
+  } while (0)
+
 hipError_t launch_m2m(const void* Mc, int c64, void* Mp, int p64, Weights T, int np, int p,
                       hipStream_t st) {
   const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
   const dim3 g(np * np * np), b(kThreads);
   if (!c64 && !p64)
-    hipLaunchKernelGGL((k_m2m<float, float, float>), g, b, words * 4, st, (const float*)Mc,
-                       (float*)Mp, T, np, p);
+    PFMM_BY_P(k_m2m, float, float, float, g, b, words * 4, st, (const float*)Mc, (float*)Mp, T, np, p);
   else if (!c64 && p64)
-    hipLaunchKernelGGL((k_m2m<float, double, double>), g, b, words * 8, st, (const float*)Mc,
-                       (double*)Mp, T, np, p);
+    PFMM_BY_P(k_m2m, float, double, double, g, b, words * 8, st, (const float*)Mc, (double*)Mp, T, np, p);
   else if (c64 && p64)
-    hipLaunchKernelGGL((k_m2m<double, double, double>), g, b, words * 8, st, (const double*)Mc,
-                       (double*)Mp, T, np, p);
+    PFMM_BY_P(k_m2m, double, double, double, g, b, words * 8, st, (const double*)Mc, (double*)Mp, T,
+              np, p);
   else
     return hipErrorInvalidValue;  // a finer level is never wider than its parent
   return hipGetLastError();
@@ -305,18 +317,19 @@ hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int
   const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
   const dim3 g(np * np * np), b(kThreads);
   if (!p64 && !c64)
-    hipLaunchKernelGGL((k_l2l<float, float, float>), g, b, words * 4, st, (const float*)Pp,
-                       (float*)Pc, T, np, p, accumulate);
+    PFMM_BY_P(k_l2l, float, float, float, g, b, words * 4, st, (const float*)Pp, (float*)Pc, T, np, p,
+              accumulate);
   else if (p64 && !c64)
-    hipLaunchKernelGGL((k_l2l<double, float, double>), g, b, words * 8, st, (const double*)Pp,
-                       (float*)Pc, T, np, p, accumulate);
+    PFMM_BY_P(k_l2l, double, float, double, g, b, words * 8, st, (const double*)Pp, (float*)Pc, T, np,
+              p, accumulate);
   else if (p64 && c64)
-    hipLaunchKernelGGL((k_l2l<double, double, double>), g, b, words * 8, st, (const double*)Pp,
-                       (double*)Pc, T, np, p, accumulate);
+    PFMM_BY_P(k_l2l, double, double, double, g, b, words * 8, st, (const double*)Pp, (double*)Pc, T,
+              np, p, accumulate);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
+#undef PFMM_BY_P
 
 namespace {
 hipError_t l2p_axes(const void* P, int p64, float* out, Weights Wx, Weights Wy, Weights Wz,
