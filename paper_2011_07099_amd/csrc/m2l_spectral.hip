@@ -18,9 +18,10 @@
 // precision.  Kernel spectra (all 343 offsets of [-3, 3]^3) are transformed
 // once per table by the same separable FP64 DFT as the near zone's.
 //
-// Layout: spectra of a level as [frequency][node], so that one stencil
-// workgroup (one frequency, one 8^3 tile of targets) reads its tile and the
-// 3-node halo from contiguous node runs.  In the stencil each wave handles
+// Layout: spectra of a level as [frequency / 8][node][frequency % 8]: a
+// node's transform writes (and its inverse reads) 128-byte runs, and the 8
+// frequencies of a chunk, whose stencil workgroups run on one XCD, share
+// every line of it.  In the stencil each wave handles
 // one parity class, so the offset, and with it the kernel value, is the same
 // across the wave.
 #include "internal.h"
@@ -125,6 +126,21 @@ constexpr int node_threads() { return (P * (P + 1) + 63) / 64 * 64; }
 // one L2.
 __device__ __forceinline__ int64_t xcd_node(int64_t g, int64_t nn) { return (g & 7) * (nn >> 3) + (g >> 3); }
 
+// Spectrum element (frequency f, node) of a level with nn nodes.
+__device__ __forceinline__ int64_t sidx(int f, int64_t node, int64_t nn) {
+  return ((int64_t)(f >> 3) * nn + node) * 8 + (f & 7);
+}
+
+// Stencil block g of F x tiles: the 8 XCDs (blocks dealt round robin) take
+// whole 8-frequency chunks, all of a chunk's frequencies and tiles back to
+// back (F is a multiple of 64).
+__device__ __forceinline__ void zone_block(int g, int tiles, int& k, int& tile) {
+  const int j = g >> 3;
+  const int chunk = (j / (8 * tiles)) * 8 + (g & 7);
+  k = chunk * 8 + (j / tiles) % 8;
+  tile = j % tiles;
+}
+
 // Forward transform of one node's p^3 gridlet (on the 2p cyclic grid, zero
 // beyond p) to its half spectrum; frequency order
 // ((kx * 2 + ky % 2) * p + ky / 2) * (p + 1) + kz.
@@ -181,8 +197,8 @@ __global__ void __launch_bounds__(node_threads<P>()) k_node_fwd(const TIN* __res
       ddft<P, false>(o);
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        spec[(int64_t)((4 * j + h) * P * H + r) * nn + node] = e[j];
-        spec[(int64_t)((4 * j + 2 + h) * P * H + r) * nn + node] = o[j];
+        spec[sidx((4 * j + h) * P * H + r, node, nn)] = e[j];
+        spec[sidx((4 * j + 2 + h) * P * H + r, node, nn)] = o[j];
       }
     }
     __syncthreads();
@@ -206,8 +222,8 @@ __global__ void __launch_bounds__(node_threads<P>()) k_node_inv(const double2* _
       double2 e[P], o[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        e[j] = spec[(int64_t)((4 * j + h) * P * H + r) * nn + node];
-        o[j] = spec[(int64_t)((4 * j + 2 + h) * P * H + r) * nn + node];
+        e[j] = spec[sidx((4 * j + h) * P * H + r, node, nn)];
+        o[j] = spec[sidx((4 * j + 2 + h) * P * H + r, node, nn)];
       }
       ddft<P, true>(e);
       ddft<P, true>(o);
@@ -271,11 +287,10 @@ __global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ s
   const int64_t nn = (int64_t)n * n * n;
   const int tpa = n / T;  // tiles per axis
   const int tiles = tpa * tpa * tpa;
-  const int j = blockIdx.x >> 3;
-  const int64_t k = (int64_t)(j / tiles) * 8 + (blockIdx.x & 7);
-  const int tile = j % tiles;
+  int k, tile;
+  zone_block(blockIdx.x, tiles, k, tile);
   const int ox = (tile / (tpa * tpa)) * T, oy = ((tile / tpa) % tpa) * T, oz = (tile % tpa) * T;
-  const double2* sk = spec + k * nn;
+  const double2* sk = spec + sidx(k, 0, nn);  // node v at sk[8 v]
   for (int i = threadIdx.x; i < 343; i += blockDim.x) kk[i] = khat[(int64_t)i * F + k];
   // per (class, offset): the box position of the source of the class's first
   // target (the others follow it by the lane's lattice step), and the kernel
@@ -302,7 +317,7 @@ __global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ s
     double2 v = make_double2(0.0, 0.0);
     if (!isolated || ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n)) {
       const int xw = x & (n - 1), yw = y & (n - 1), zw = z & (n - 1);
-      v = sk[((int64_t)xw * n + yw) * n + zw];
+      v = sk[(((int64_t)xw * n + yw) * n + zw) * 8];
     }
     const int dst = classes == 8 ? (((bx & 1) * 2 + (by & 1)) * 2 + (bz & 1)) * H3 +
                                        ((bx >> 1) * Bh + (by >> 1)) * Bh + (bz >> 1)
@@ -335,7 +350,7 @@ __global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ s
     re += kd.x * s.x - kd.y * s.y;
     im += kd.x * s.y + kd.y * s.x;
   }
-  out[k * nn + ((int64_t)(ox + tx) * n + (oy + ty)) * n + (oz + tz)] = make_double2(re, im);
+  out[sidx(k, ((int64_t)(ox + tx) * n + (oy + ty)) * n + (oz + tz), nn)] = make_double2(re, im);
 }
 
 // The same sums on levels with n >= 16 nodes per axis (levels >= 4), tiles
@@ -358,18 +373,17 @@ __global__ void __launch_bounds__(512) k_zone_spec2(const double2* __restrict__ 
   const int64_t nn = (int64_t)n * n * n;
   const int tpx = n / TX, tpz = n / TZ;
   const int tiles = tpx * tpx * tpz;
-  const int j = blockIdx.x >> 3;
-  const int64_t k = (int64_t)(j / tiles) * 8 + (blockIdx.x & 7);
-  const int tile = j % tiles;
+  int k, tile;
+  zone_block(blockIdx.x, tiles, k, tile);
   const int ox = (tile / (tpx * tpz)) * TX, oy = ((tile / tpz) % tpx) * TX, oz = (tile % tpz) * TZ;
-  const double2* sk = spec + k * nn;
+  const double2* sk = spec + sidx(k, 0, nn);  // node v at sk[8 v]
   for (int i = threadIdx.x; i < 343; i += blockDim.x) kk[i] = khat[(int64_t)i * F + k];
   for (int i = threadIdx.x; i < BX * BX * BZ; i += blockDim.x) {
     const int bx = i / (BX * BZ), by = (i / BZ) % BX, bz = i % BZ;
     const int x = ox + bx - 3, y = oy + by - 3, z = oz + bz - 3;
     double2 v = make_double2(0.0, 0.0);
     if (!isolated || ((unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n))
-      v = sk[((int64_t)(x & (n - 1)) * n + (y & (n - 1))) * n + (z & (n - 1))];
+      v = sk[(((int64_t)(x & (n - 1)) * n + (y & (n - 1))) * n + (z & (n - 1))) * 8];
     box[(((bx & 1) * 2 + (by & 1)) * 2 + (bz & 1)) * H3 + ((bx >> 1) * HX + (by >> 1)) * HZ + (bz >> 1)] = v;
   }
   __syncthreads();
@@ -421,9 +435,9 @@ __global__ void __launch_bounds__(512) k_zone_spec2(const double2* __restrict__ 
     }
   }
   const int tx = ox + 2 * kx + cx, ty = oy + 2 * ky + cy, tz = oz + 2 * kz + cz;
-  double2* o = out + k * nn + ((int64_t)tx * n + ty) * n + tz;
+  double2* o = out + sidx(k, ((int64_t)tx * n + ty) * n + tz, nn);
   o[0] = make_double2(r1, i1);
-  o[2] = make_double2(r2, i2);
+  o[16] = make_double2(r2, i2);  // node tz + 2
 }
 
 // Kernel spectrum of offset d (FP64 separable DFT): first pass along z of
