@@ -353,20 +353,25 @@ __global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ s
   out[sidx(k, ((int64_t)(ox + tx) * n + (oy + ty)) * n + (oz + tz), nn)] = make_double2(re, im);
 }
 
-// The same sums on levels with n >= 16 nodes per axis (levels >= 4), tiles
-// of 8 x 8 x 16 targets: each lane owns two targets of its wave's class, 2
-// apart in z, and walks the zone by (dx, dy) columns.  Stored split by
+// The same sums on levels with n >= 8 nodes per axis (levels >= 3), tiles
+// of 8 x 8 x TZ targets (TZ = 16, or 8 on the 8^3 level): each lane owns two
+// targets of its class, 2 apart in z, and walks the zone by (dx, dy)
+// columns.  With TZ = 16 a wave is one class; with TZ = 8 a wave holds two
+// classes that differ only in z parity, so the column loops stay uniform.  Stored split by
 // parity, a full column (six consecutive dz) is two runs of three entries
 // per target, and the second target's runs are the first's shifted by one,
 // so four loads per parity plane serve both (8 loads for 12 multiply-adds).
 // Columns next to the target (|dx|, |dy| <= 1) keep the three dz outside the
 // near zone.  The zone of class c is {d : d_i in [-2 - c_i, 3 - c_i],
 // max |d_i| > 1} (Sec. 2), enumerated here directly.
-__global__ void __launch_bounds__(512) k_zone_spec2(const double2* __restrict__ spec,
-                                                    const double2* __restrict__ khat, int n,
-                                                    int isolated, int64_t F,
-                                                    double2* __restrict__ out) {
-  constexpr int TX = 8, TZ = 16, BX = TX + 6, BZ = TZ + 6;
+template <int TZ>
+__global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restrict__ spec,
+                                                        const double2* __restrict__ khat, int n,
+                                                        int isolated, int64_t F,
+                                                        double2* __restrict__ out) {
+  constexpr int TX = 8, BX = TX + 6, BZ = TZ + 6;
+  constexpr int KZ = TZ / 4;       // target pairs along z per class and (x, y)
+  constexpr int LPC = 16 * KZ;     // lanes per class
   constexpr int HX = BX / 2, HZ = BZ / 2, H3 = HX * HX * HZ;
   __shared__ double2 box[8 * H3];
   __shared__ double2 kk[343];
@@ -387,9 +392,9 @@ __global__ void __launch_bounds__(512) k_zone_spec2(const double2* __restrict__ 
     box[(((bx & 1) * 2 + (by & 1)) * 2 + (bz & 1)) * H3 + ((bx >> 1) * HX + (by >> 1)) * HZ + (bz >> 1)] = v;
   }
   __syncthreads();
-  const int cls = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cls = threadIdx.x / LPC, lane = threadIdx.x % LPC;
   const int cx = cls >> 2, cy = (cls >> 1) & 1, cz = cls & 1;
-  const int kx = lane >> 4, ky = (lane >> 2) & 3, kz = 2 * (lane & 3);
+  const int kx = lane / (4 * KZ), ky = (lane / KZ) % 4, kz = 2 * (lane % KZ);
   const int base = (kx * HX + ky) * HZ + kz;
   double r1 = 0.0, i1 = 0.0, r2 = 0.0, i2 = 0.0;
   const int dz0 = -2 - cz;
@@ -516,8 +521,10 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
   if (e != hipSuccess) return e;
   const int classes = l == 2 ? 1 : 8;
   if (n >= 16) {  // 8 x 8 x 16 tiles, two targets per lane
-    const unsigned grid = (unsigned)(f->F * (n / 8) * (n / 8) * (n / 16));  // F is a multiple of 8
-    k_zone_spec2<<<grid, 512, 0, st>>>(f->spec, f->khat[l], n, isolated, f->F, f->out);
+    const unsigned grid = (unsigned)(f->F * (n / 8) * (n / 8) * (n / 16));  // F is a multiple of 64
+    k_zone_spec2<16><<<grid, 512, 0, st>>>(f->spec, f->khat[l], n, isolated, f->F, f->out);
+  } else if (n == 8) {  // the 8^3 level as one tile, two targets per lane
+    k_zone_spec2<8><<<(unsigned)f->F, 256, 0, st>>>(f->spec, f->khat[l], n, isolated, f->F, f->out);
   } else {
     const int T = n < 8 ? n : 8;
     const unsigned grid = (unsigned)(f->F * (n / T) * (n / T) * (n / T));
