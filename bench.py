@@ -46,8 +46,8 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 # and profiles/near_direct_256cube_L4_p8_*.md.
 TRAFFIC = {
     # the leaf level's spectral zones: node transforms, stencil and inverse together
-    ("spectral-L4", "bf16x3", "69f89f5e1568"): (162060 * 2.0 + 303332 * 1.0) * 1024,
-    ("spectral-L4", "fp32", "69f89f5e1568"): (162064 * 2.0 + 303328 * 1.0) * 1024,
+    ("spectral-L4", "bf16x3", "23ad275584d6"): (162065 * 2.0 + 303309 * 1.0) * 1024,
+    ("spectral-L4", "fp32", "23ad275584d6"): (162058 * 2.0 + 303289 * 1.0) * 1024,
     ("zones-L4", "bf16x3", "6469cce526a2"): (252580 * 2.0 + 262144 * 1.0) * 1024,
     ("near", "bf16x3", "6469cce526a2"): (1156807 * 2.0 + 65536 * 1.0) * 1024,
     ("near", "fp32", "e15380d05dd6"): (11732373 * 2.0 + 68948 * 1.0) * 1024,
