@@ -112,7 +112,10 @@ typedef enum {
    * interpolation (Eq. 7, and its leaf analogue when s > p) extrapolates past
    * a parent's outermost gridlet nodes, so rounding noise in a coarse field
    * is amplified on its way to the mesh, most at leaf corners.  Default 2
-   * (levels 2 and 3); L - 1 or more also keeps the leaf level in FP64. */
+   * (levels 2 and 3), which keeps every level above the leaf in FP64 for
+   * L = 4; deeper trees want L - 2 (at 512^3, L = 5, an FP32 level 4 leaves
+   * 1e-4 of max|phi|, FP64 storage 7e-7); L - 1 or more also keeps the leaf
+   * level in FP64. */
   PFMM_OPT_FP64_LEVELS = 5,
   /* value: int32 0 or 1.  1 makes the plan the non-periodic twin used to
    * separate the multipole-expansion error from the Green's-function error

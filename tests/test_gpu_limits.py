@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 from oracle import green as ogreen
+from paper_2011_07099_amd import fields
 
 pytestmark = pytest.mark.gpu
 
@@ -74,3 +75,36 @@ def test_zero_density_gives_exact_zero(precision):
         pl.solve(rho, phi, acc)
         torch.cuda.synchronize()
     assert torch.count_nonzero(phi).item() == 0 and torch.count_nonzero(acc).item() == 0
+
+
+def test_transform_routes_on_a_five_level_tree():
+    """512^3, L = 5 (a 32^3 leaf level, 16^3-cell leaves), p = 8: the FFT near
+    zone with spectral interaction zones against the FP32 direct near zone
+    with GEMM zones, every level stored in FP64 on both sides, both on the
+    GPU.  The spectral stencil's 8 x 8 x 16 tiles then tile a level four deep
+    in z, and the near zone's stencil runs on 16^2 pencil blocks.  Measured
+    7e-7 of max|phi| (the two near zones' FP32 rounding); tolerance 1e-5.
+    Also printed: the spectral route with the default storage (levels 2-3 in
+    FP64).  At L = 5 that leaves the intermediate level 4 in FP32, whose
+    rounding two interpolations amplify on the way down (1e-4 of max|phi|
+    here, whatever the zone route), so deep trees want PFMM_OPT_FP64_LEVELS
+    >= L - 2."""
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    N, L, p = 512, 5, 8
+    rho = torch.from_numpy(fields.lognormal(N, 1.5, 2.0, seed=17).astype(np.float32)).cuda()
+    a = torch.empty_like(rho)
+    b = torch.empty_like(rho)
+    with Plan(N, L, p, "S1", fp64_levels=L - 1) as pl:
+        pl.solve(rho, b)                  # FP32 direct near zone, GEMM zones
+        torch.cuda.synchronize()
+    scale = float(b.abs().max())
+    errs = {}
+    for f64 in (L - 1, 2):
+        with Plan(N, L, p, "S1", near="fft", m2l="spectral", fp64_levels=f64) as pl:
+            pl.solve(rho, a)
+            torch.cuda.synchronize()
+        errs[f64] = float((a - b).abs().max()) / scale
+        print("512^3 L=5: FFT near zone + spectral zones (FP64 levels 2-%d) vs direct near zone + "
+              "GEMM zones (all FP64): max diff / max|phi| = %.3e" % (1 + f64, errs[f64]))
+    assert errs[L - 1] < 1e-5
