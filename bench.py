@@ -161,7 +161,7 @@ def batch_bench(args):
         rho = fields.lognormal(sp["N"], sp["alpha"], sp["sigma_delta"], seed=sp["seed"])
         host.append(rho.astype(np.float32))
         plans.append(Plan(sp["N"], 3, sp["p"], GREEN, precision=args.precision, near=args.near,
-                          m2l=args.m2l if sp["p"] in (4, 8) else "gemm"))
+                          m2l=args.m2l))
         rhos.append(torch.from_numpy(host[-1]).cuda())
         phis.append(torch.empty_like(rhos[-1]))
     torch.cuda.synchronize()
@@ -188,14 +188,13 @@ def batch_bench(args):
         "value": len(specs) / (ms * 1e-3), "unit": "fields/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        # FFT near zones and spectral zones use no split bf16 products; the
-        # p = 6 fields' zones are the portable kernel's FP32 / FP64 items
+        # FFT near zones and spectral zones use no split bf16 products
         "dtype": "f32+f64" if (args.near == "fft" and args.m2l == "spectral") else args.precision,
         "data": "synthetic",
         "config": {"workload": "128 lognormal fields, N in {32,64,128}, p in {4,6,8}, "
                                "sigma_delta~U(0.5,2), alpha=2, L=3, G_S1",
                    "cells": cells, "items": info["items"], "create_s": create_s,
-                   "near": args.near, "m2l": args.m2l + " (p = 4, 8; gemm for p = 6)"},
+                   "near": args.near, "m2l": args.m2l},
         "tuning": info["groups"],
         "achieved_tflops": flops / (ms * 1e-3) / 1e12,
     }
@@ -318,7 +317,7 @@ def m2l_bench(args):
     (FP32 portable kernel, and split BF16 on the matrix cores at p = 8), the
     HPM form the paper runs (Sec. 2: per target node one FFT convolution of
     its zone's effective masses with G, rocFFT), and the spectral stencils
-    (per-node transforms, FP64; p = 4 and 8), at p = 4, 6, 8.  Levels
+    (per-node transforms, FP64), at p = 4, 6, 8.  Levels
     2-3 are FP64 in every variant (FP64 matrix cores at p = 8, FP64
     transforms for the FFT).  Per-level medians of the profiled stage times
     over `steps` solves; `value` is the FFT-to-GEMM time ratio of all levels
@@ -334,8 +333,6 @@ def m2l_bench(args):
                           ("spectral", "fp32")):
             if prec == "bf16x3" and p != 8:
                 continue  # the split matrix-core kernel serves p = 8
-            if m2l == "spectral" and p == 6:
-                continue  # radix-4 transforms: p = 4 and 8
             with Plan(N, L, p, GREEN, precision=prec, m2l=m2l) as pl:
                 for _ in range(max(args.warmup, 1)):
                     pl.solve(rho, phi)

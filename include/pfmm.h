@@ -186,7 +186,7 @@ typedef enum {
    * (8p)^3; level 2: the periodic (4p)^3 level.  A comparator: same sums as
    * the GEMM up to rounding. */
   PFMM_M2L_FFT = 1,
-  /* Spectral stencils, for p = 4 and 8: every node's gridlet transformed
+  /* Spectral stencils, for p = 4, 6 and 8: every node's gridlet transformed
    * once on its (2p)^3 cyclic grid (exact for the block convolutions of
    * Eq. 6, whose separations |a - a'| <= p - 1 have distinct residues), the
    * zone's offsets (189 per parity class, the level-2 zone) summed per

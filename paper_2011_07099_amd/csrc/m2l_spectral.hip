@@ -45,29 +45,31 @@ constexpr int kThreads = 256;
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-// cos(2 pi j / 32) for j = 0 .. 8
-__device__ constexpr double kQuarterD[9] = {1.0,
-                                            0.98078528040323044913,
-                                            0.92387953251128675613,
-                                            0.83146961230254523708,
-                                            0.70710678118654752440,
-                                            0.55557023301960222474,
-                                            0.38268343236508977173,
-                                            0.19509032201612826785,
-                                            0.0};
-__device__ __forceinline__ double cosd32(int j) {
-  j &= 31;
-  if (j <= 8) return kQuarterD[j];
-  if (j <= 16) return -kQuarterD[16 - j];
-  if (j <= 24) return -kQuarterD[j - 16];
-  return kQuarterD[32 - j];
+// cos(2 pi j / 96) for j = 0 .. 24 (96 = lcm of the grid sizes 2p = 8, 12, 16)
+__device__ constexpr double kQuarterD[25] = {
+    1.0,                    0.997858923238603506738, 0.991444861373810411145,
+    0.980785280403230449126, 0.96592582628906828675,  0.946930129495105664256,
+    0.923879532511286756128, 0.896872741532688303894, 0.866025403784438646764,
+    0.831469612302545237079, 0.79335334029123516458,  0.751839807478977396408,
+    0.707106781186547524401, 0.659345815100068868425, 0.608761429008720639416,
+    0.555570233019602224743, 0.5,                     0.442288690219001281995,
+    0.382683432365089771728, 0.321439465303161580701, 0.258819045102520762349,
+    0.195090322016128267848, 0.130526192220051591548, 0.0654031292301430668153,
+    0.0};
+__device__ __forceinline__ double cosd96(int j) {
+  j %= 96;
+  if (j < 0) j += 96;
+  if (j <= 24) return kQuarterD[j];
+  if (j <= 48) return -kQuarterD[48 - j];
+  if (j <= 72) return -kQuarterD[j - 48];
+  return kQuarterD[96 - j];
 }
 
-// (cos, sin) of 2 pi j / M, M | 32
+// (cos, sin) of 2 pi j / M, M | 96
 template <int M>
 __device__ __forceinline__ double2 twd(int j) {
-  constexpr int r = 32 / M;
-  return make_double2(cosd32(j * r), cosd32(j * r - 8));
+  constexpr int r = 96 / M;
+  return make_double2(cosd96(j * r), cosd96(j * r - 24));
 }
 
 __device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -91,9 +93,23 @@ __device__ __forceinline__ void ddft4(double2& a0, double2& a1, double2& a2, dou
   a3 = INV ? dsub(b1, ib3) : dadd(b1, ib3);
 }
 
-// In-place DFT of P = 4Q values (Q = 1, 2), split n = Q n1 + n2, m = m1 + 4 m2
+// In-place DFT of P values: P = 4Q (Q = 1, 2) by the split n = Q n1 + n2,
+// m = m1 + 4 m2; P = 6 directly.
 template <int P, bool INV>
 __device__ __forceinline__ void ddft(double2 (&v)[P]) {
+  if constexpr (P == 6) {
+    double2 u[6];
+#pragma unroll
+    for (int n = 0; n < 6; ++n) u[n] = v[n];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      double2 acc = u[0];
+#pragma unroll
+      for (int n = 1; n < 6; ++n) acc = dadd(acc, dtwiddle<6, INV>(u[n], n * m));
+      v[m] = acc;
+    }
+    return;
+  }
   constexpr int Q = P / 4;
   double2 T[Q][4];
 #pragma unroll
@@ -131,14 +147,16 @@ __device__ __forceinline__ int64_t sidx(int f, int64_t node, int64_t nn) {
   return ((int64_t)(f >> 3) * nn + node) * 8 + (f & 7);
 }
 
-// Stencil block g of F x tiles: the 8 XCDs (blocks dealt round robin) take
-// whole 8-frequency chunks, all of a chunk's frequencies and tiles back to
-// back (F is a multiple of 64).
-__device__ __forceinline__ void zone_block(int g, int tiles, int& k, int& tile) {
+// Stencil block g: the 8 XCDs (blocks dealt round robin) take whole
+// 8-frequency chunks, all of a chunk's frequencies and tiles back to back.
+// The grid covers the chunks rounded up to a multiple of 8; false for the
+// blocks beyond the last chunk.
+__device__ __forceinline__ bool zone_block(int g, int tiles, int nchunk, int& k, int& tile) {
   const int j = g >> 3;
   const int chunk = (j / (8 * tiles)) * 8 + (g & 7);
   k = chunk * 8 + (j / tiles) % 8;
   tile = j % tiles;
+  return chunk < nchunk;
 }
 
 // Forward transform of one node's p^3 gridlet (on the 2p cyclic grid, zero
@@ -288,7 +306,7 @@ __global__ void __launch_bounds__(512) k_zone_spec(const double2* __restrict__ s
   const int tpa = n / T;  // tiles per axis
   const int tiles = tpa * tpa * tpa;
   int k, tile;
-  zone_block(blockIdx.x, tiles, k, tile);
+  if (!zone_block(blockIdx.x, tiles, (int)(F >> 3), k, tile)) return;
   const int ox = (tile / (tpa * tpa)) * T, oy = ((tile / tpa) % tpa) * T, oz = (tile % tpa) * T;
   const double2* sk = spec + sidx(k, 0, nn);  // node v at sk[8 v]
   for (int i = threadIdx.x; i < 343; i += blockDim.x) kk[i] = khat[(int64_t)i * F + k];
@@ -379,7 +397,7 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
   const int tpx = n / TX, tpz = n / TZ;
   const int tiles = tpx * tpx * tpz;
   int k, tile;
-  zone_block(blockIdx.x, tiles, k, tile);
+  if (!zone_block(blockIdx.x, tiles, (int)(F >> 3), k, tile)) return;
   const int ox = (tile / (tpx * tpz)) * TX, oy = ((tile / tpz) % tpx) * TX, oz = (tile % tpz) * TZ;
   const double2* sk = spec + sidx(k, 0, nn);  // node v at sk[8 v]
   for (int i = threadIdx.x; i < 343; i += blockDim.x) kk[i] = khat[(int64_t)i * F + k];
@@ -520,14 +538,16 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int classes = l == 2 ? 1 : 8;
+  // blocks per tile: the 8-frequency chunks rounded up to a multiple of 8, times 8
+  const int64_t per_tile = (f->F / 8 + 7) / 8 * 64;
   if (n >= 16) {  // 8 x 8 x 16 tiles, two targets per lane
-    const unsigned grid = (unsigned)(f->F * (n / 8) * (n / 8) * (n / 16));  // F is a multiple of 64
+    const unsigned grid = (unsigned)(per_tile * (n / 8) * (n / 8) * (n / 16));
     k_zone_spec2<16><<<grid, 512, 0, st>>>(f->spec, f->khat[l], n, isolated, f->F, f->out);
   } else if (n == 8) {  // the 8^3 level as one tile, two targets per lane
-    k_zone_spec2<8><<<(unsigned)f->F, 256, 0, st>>>(f->spec, f->khat[l], n, isolated, f->F, f->out);
+    k_zone_spec2<8><<<(unsigned)per_tile, 256, 0, st>>>(f->spec, f->khat[l], n, isolated, f->F, f->out);
   } else {
     const int T = n < 8 ? n : 8;
-    const unsigned grid = (unsigned)(f->F * (n / T) * (n / T) * (n / T));
+    const unsigned grid = (unsigned)(per_tile * (n / T) * (n / T) * (n / T));
     k_zone_spec<<<grid, classes == 8 ? 512 : 64, 0, st>>>(f->spec, f->khat[l], offs, noff, n, classes,
                                                            isolated, f->F, f->out);
   }
@@ -553,7 +573,7 @@ void m2l_spectral_destroy(M2LSpectral* f) {
 
 hipError_t m2l_spectral_create(int L, int p, M2LSpectral** out) {
   *out = nullptr;
-  if (p != 4 && p != 8) return hipErrorInvalidValue;
+  if (p != 4 && p != 6 && p != 8) return hipErrorInvalidValue;
   M2LSpectral* f = new M2LSpectral;
   f->L = L;
   f->p = p;
@@ -592,8 +612,9 @@ hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64
 hipError_t m2l_spectral_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, int p64,
                               int accumulate, const int* offs, int noff, int isolated, hipStream_t st) {
   if (l < 2 || l > f->L) return hipErrorInvalidValue;
-  return f->p == 4 ? run_level<4>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st)
-                   : run_level<8>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st);
+  if (f->p == 4) return run_level<4>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st);
+  if (f->p == 6) return run_level<6>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st);
+  return run_level<8>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st);
 }
 
 }  // namespace pfmm

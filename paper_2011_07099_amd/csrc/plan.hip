@@ -720,8 +720,8 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       if (v != PFMM_M2L_GEMM && v != PFMM_M2L_FFT && v != PFMM_M2L_SPECTRAL)
         return fail(PFMM_ERR_INVALID_ARG, "unknown M2L mode");
       if (v == PFMM_M2L_SPECTRAL) {
-        if (pl->p != 4 && pl->p != 8)
-          return fail(PFMM_ERR_UNSUPPORTED, "the spectral interaction zones need p = 4 or 8");
+        if (pl->p != 4 && pl->p != 6 && pl->p != 8)
+          return fail(PFMM_ERR_UNSUPPORTED, "the spectral interaction zones need p = 4, 6 or 8");
         if (!pl->g0.empty()) return fail(PFMM_ERR_UNSUPPORTED, "plan has learned tables");
         if (!pl->mspec) {
           M2LSpectral* f = nullptr;

@@ -151,7 +151,7 @@ class Plan:
     def set_m2l(self, mode):
         """Interaction zones by "gemm" (block Toeplitz), "fft" (the HPM FFT
         convolution, a comparator) or "spectral" (per-node transforms and a
-        per-frequency stencil, FP64; p = 4 or 8)."""
+        per-frequency stencil, FP64; p = 4, 6 or 8)."""
         v = ctypes.c_int32(M2L[mode])
         _check(load().pfmm_plan_set(self._h, OPT_M2L, ctypes.byref(v), 4))
 

@@ -194,7 +194,8 @@ SPECTRAL_SPECS = [  # (N, L, p, green, seed, precision, near zone, interaction z
     (128, 3, 8, "S1", 402, "fp32", "fft", "spectral"),
     (32, 3, 4, "S1", 403, "fp32", "direct", "spectral"),
     (64, 3, 4, "X", 405, "bf16x3", "direct", "spectral"),  # split direct near zone
-    (64, 3, 6, "K", 404, "fp32", "fft", "gemm"),            # p = 6: zones as work items
+    (64, 3, 6, "K", 404, "fp32", "fft", "gemm"),            # zones as work items
+    (32, 3, 6, "S1", 406, "fp32", "fft", "spectral"),      # p = 6 spectral
 ]
 
 

@@ -3,7 +3,7 @@ cyclic grid, the zone's offsets summed per frequency, FP64), through the C
 ABI, against the oracle's step-by-step FMM and the block-Toeplitz GEMM path.
 
 * Locals of every level (Eq. 6 + Eq. 7) and the mesh potential against the
-  reference FMM, periodic and isolated, p = 4 and 8, G_S1, G_K and G_X.
+  reference FMM, periodic and isolated, p = 4, 6 and 8, G_S1, G_K and G_X.
   The FP32 levels' rounding sets the tolerance, 2e-5, as for the other M2L
   routes.  With every level kept in FP64 the spectral and GEMM locals differ
   by FP64 rounding only: their FP32 read-backs agree to 2e-7 of max.
@@ -12,7 +12,8 @@ ABI, against the oracle's step-by-step FMM and the block-Toeplitz GEMM path.
 * Both transform routes together (FFT near zone and spectral zones) with
   accelerations from the expansion, periodic and isolated, against the
   oracle's fmm_accel (measured 1-6e-7; tolerance 2e-5).
-* p = 6 is refused (batches with spectral plans: test_gpu_batch.py).
+* p = 5 is refused (p = 4, 6, 8 only; batches with spectral plans:
+  test_gpu_batch.py).
 """
 import numpy as np
 import pytest
@@ -49,6 +50,8 @@ def _solve_stages(rho, L, p, green, m2l, fp64_levels=None, isolated=False, preci
     (64, 2, 8, "S1", None, False, "fp32"),    # the smallest periodic tree
     (32, 3, 4, "X", None, True, "fp32"),      # isolated twin (316-offset level 2)
     (64, 3, 8, "X", None, True, "fp32"),
+    (64, 3, 6, "S1", None, False, "fp32"),    # p = 6: 12-point transforms, 1008 frequencies
+    (128, 4, 6, "X", None, True, "fp32"),     # p = 6 isolated, a 16^3 leaf level
 ])
 def test_spectral_zones_match_reference_and_gemm(N, L, p, green, f64, iso, prec):
     rho = f32(fields.lognormal(N, 2.0, 1.0, seed=281 + N + p))
@@ -84,7 +87,7 @@ def test_spectral_zones_in_fp64_match_the_fp64_gemm(N, L, p, green, iso):
 
 def test_spectral_zones_refusals():
     from paper_2011_07099_amd.pfmm import Plan, PfmmError
-    with Plan(32, 3, 6, "S1") as pl:   # radix-4 transforms: p = 4 or 8 only
+    with Plan(64, 3, 5, "S1") as pl:   # transforms for p = 4, 6, 8 only
         with pytest.raises(PfmmError):
             pl.set_m2l("spectral")
 
