@@ -46,11 +46,11 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
 # and profiles/near_direct_256cube_L4_p8_*.md.
 TRAFFIC = {
     # the leaf level's spectral zones: node transforms, stencil and inverse together
-    ("spectral-L4", "bf16x3", "23ad275584d6"): (162065 * 2.0 + 303309 * 1.0) * 1024,
-    ("spectral-L4", "fp32", "23ad275584d6"): (162058 * 2.0 + 303289 * 1.0) * 1024,
-    ("zones-L4", "bf16x3", "6469cce526a2"): (252580 * 2.0 + 262144 * 1.0) * 1024,
-    ("near", "bf16x3", "6469cce526a2"): (1156807 * 2.0 + 65536 * 1.0) * 1024,
-    ("near", "fp32", "e15380d05dd6"): (11732373 * 2.0 + 68948 * 1.0) * 1024,
+    ("spectral-L4", "bf16x3", "9df7fc67c4f5"): (162065 * 2.0 + 303326 * 1.0) * 1024,
+    ("spectral-L4", "fp32", "9df7fc67c4f5"): (162066 * 2.0 + 303328 * 1.0) * 1024,
+    ("zones-L4", "bf16x3", "b7aef9891b13"): (252926 * 2.0 + 262144 * 1.0) * 1024,
+    ("near", "bf16x3", "b7aef9891b13"): (1188392 * 2.0 + 65536 * 1.0) * 1024,
+    ("near", "fp32", "1503ffb456c4"): (11731340 * 2.0 + 68856 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
 SPECTRAL_SRC = ("m2l_spectral.hip", "plan.hip")
