@@ -50,16 +50,22 @@ TRAFFIC = {
     ("spectral-L4", "fp32", "9df7fc67c4f5"): (162066 * 2.0 + 303328 * 1.0) * 1024,
     ("zones-L4", "bf16x3", "b7aef9891b13"): (252926 * 2.0 + 262144 * 1.0) * 1024,
     ("near", "bf16x3", "b7aef9891b13"): (1188392 * 2.0 + 65536 * 1.0) * 1024,
+    # the FFT near zone: leaf transforms, stencil and inverse together
+    ("near-fft", "bf16x3", "e64dd98b8f1f"): (677175 * 2.0 + 1179669 * 1.0) * 1024,
+    ("near-fft", "fp32", "e64dd98b8f1f"): (677120 * 2.0 + 1179648 * 1.0) * 1024,
     ("near", "fp32", "1503ffb456c4"): (11731340 * 2.0 + 68856 * 1.0) * 1024,
 }
 KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
 SPECTRAL_SRC = ("m2l_spectral.hip", "plan.hip")
+NEAR_FFT_SRC = ("near_fft.hip", "plan.hip")
 
 
 def traffic_bytes(kernel, precision):
     import hashlib
     h = hashlib.sha1()
-    for name in (SPECTRAL_SRC if kernel.startswith("spectral") else KERNEL_SRC[precision]):
+    srcs = (SPECTRAL_SRC if kernel.startswith("spectral") else
+            NEAR_FFT_SRC if kernel == "near-fft" else KERNEL_SRC[precision])
+    for name in srcs:
         h.update(open(os.path.join(ROOT, "paper_2011_07099_amd", "csrc", name), "rb").read())
     return TRAFFIC.get((kernel, precision, h.hexdigest()[:12]))
 
@@ -477,6 +483,17 @@ def main():
                         4 if args.accel == "expansion" else 1, near_ms),
                     "unit_used": near_unit, "products": near_products,
                     "issued_frac": near_tf * near_products / peak}
+    elif args.near == "fft" and near_ms > per_level[str(L)]["ms"]:
+        # the FFT near zone (leaf transforms, stencil, inverse) is the longest stage
+        nbytes = near_fft_bytes(N, L, 4 if args.accel == "expansion" else 1)
+        gbs = nbytes / (near_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                    "frac": gbs / 8000.0,
+                    "traffic": traffic_bytes("near-fft", args.precision) if args.accel != "expansion"
+                    else None,
+                    "kernel": "near zone by FFT (3 launches/step: leaf transforms, stencil, "
+                              "inverse; %.3f ms)" % near_ms,
+                    "algorithmic_bytes": nbytes}
     elif args.m2l == "spectral":
         # the leaf level's spectral zones (transforms, stencil, inverse) dominate
         lv = per_level[str(L)]
