@@ -276,11 +276,13 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
         Ml = M[l].reshape(n, n, n, p ** 3)
         out = np.zeros((n, n, n, p ** 3))
         # target nodes, grouped by parity class (the interaction zone depends on
-        # it at levels >= 3); at the leaf level only the leaves holding requested
-        # targets when ``targets`` is given
+        # it at levels >= 3); when ``targets`` is given, only the leaves holding
+        # requested targets and their ancestors (the only nodes whose field
+        # reaches those targets through Eq. 7)
         allb = np.indices((n, n, n)).reshape(3, -1).T
-        if targets is not None and l == L:
-            allb = np.unique(np.asarray(targets, np.int64).reshape(-1, 3) // s, axis=0)
+        if targets is not None:
+            leaves = np.asarray(targets, np.int64).reshape(-1, 3) // s
+            allb = np.unique(leaves >> (L - l), axis=0)
         if l == 2:
             groups = {(0, 0, 0): (allb, level2_offsets() if periodic else level2_offsets_isolated())}
         else:

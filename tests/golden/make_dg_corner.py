@@ -3,6 +3,10 @@ the corner point source of Sec. 3 (unit mass in cell (0,0,0) of a 128^3 mesh,
 3-level tree, 16^3-cell leaves) at N_g = p = 4, 6, 8, for G_S with a_1 from
 Table 1 and a_1 = -1/8 (G_S1).  Calls only the oracle (FP64, CPU; about ten
 minutes).  Run from the repository root:  python tests/golden/make_dg_corner.py
+
+With ``--t7`` it writes dg_corner_t7_oracle.txt instead: the same error for
+the G_S variant with two coefficients whose map is t + O(t^7) (Sec. 3; a_1 =
+-25/128, a_2 = 3/128) beside G_S1, at p = 4, 6, 8.
 """
 import os
 import sys
@@ -14,6 +18,9 @@ from oracle import fmm as ofmm, metric  # noqa: E402
 
 N, L = 128, 3
 A1 = {4: [-0.138598, -0.125], 6: [-0.120236, -0.125], 8: [-0.120236, -0.125]}
+
+
+T7 = (-25.0 / 128.0, 3.0 / 128.0)
 
 
 def corner_errors(p, a1s):
@@ -28,10 +35,26 @@ def corner_errors(p, a1s):
     rho[0, 0, 0] = 1.0 / h ** 3
     rows = [(p, None) + metric.norms(np.linalg.norm(e_np, axis=0))]
     for a1 in a1s:
-        g, _ = ofmm.fmm_accel(rho, L, p, "S", a=(a1,))
-        e_p = g - metric.point_sources_accel(N, [[0, 0, 0]], [1.0], "S", (a1,))
+        a = tuple(a1) if isinstance(a1, tuple) else (a1,)
+        g, _ = ofmm.fmm_accel(rho, L, p, "S", a=a)
+        e_p = g - metric.point_sources_accel(N, [[0, 0, 0]], [1.0], "S", a)
         rows.append((p, a1) + metric.norms(metric.delta_g(e_p, e_np)))
     return rows
+
+
+def main_t7():
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "dg_corner_t7_oracle.txt")
+    lines = ["# Oracle (FP64) Green's-function error Delta g (Eq. 3) of the corner point",
+             "# source, 128^3, L = 3, for G_S1 (a_1 = -1/8, a_2 = 0) and the variant whose",
+             "# map is t + O(t^7) (a_1 = -25/128, a_2 = 3/128; Sec. 3).  Written by",
+             "# make_dg_corner.py --t7.",
+             "# columns: p  a_1  a_2  L2  L_MAX"]
+    for p in (4, 6, 8):
+        for p_, a, l2, lmax in corner_errors(p, [(-0.125, 0.0), T7])[1:]:
+            lines.append("%d %r %r %.6e %.6e" % (p_, a[0], a[1], l2, lmax))
+            print(lines[-1], flush=True)
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def main():
@@ -50,4 +73,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main_t7() if "--t7" in sys.argv[1:] else main()

@@ -23,10 +23,11 @@ interaction zone in FP64.
   G_S1 lowers it by about three orders of magnitude (the colour bar of Fig. 4
   is 100x smaller).
 * The variant whose map is t + O(t^7) (a_1 = -25/128, a_2 = 3/128): Sec. 3
-  reports that it makes the error markedly worse than G_S1.  Measured: worse
-  from p = 6 on, increasingly with p (L2 x1.13 at p = 6, x1.56 at p = 8, where
-  L_MAX is x2.3), but better at p = 4 (L2 x0.86).  The test holds the L2 ratio
-  to bands around those values.
+  reports that it makes the error markedly worse than G_S1.  The GPU's error
+  of the variant, and its ratio to G_S1's, against the oracle's
+  (tests/golden/dg_corner_t7_oracle.txt, written by make_dg_corner.py --t7
+  from the oracle alone).  The oracle finds the variant worse from p = 6 on,
+  increasingly with p, and better at p = 4.
 * Deviation of the force from the Newtonian form (Fig. 6 analogue, the
   GADGET-4 comparison left out): the G_S1 FMM acceleration of the corner
   source against the exact periodic Newtonian force (Ewald summation, oracle)
@@ -147,8 +148,11 @@ def test_corner_fit_of_a1(runner):
 
     xm, lm, nevm = fit.nelder_mead(lmax_of, [-0.125], 0.005, xtol=2e-4, maxiter=60)
     print("fit of L_MAX p=%d: a1 = %.5f, L_MAX %.3e, %d evaluations" % (p, xm[0], lm, nevm))
-    # measured: -0.153 / -0.133 / -0.127 against the L2 fit's -0.124 / -0.126 / -0.124
-    assert abs(xm[0] - x[0]) < 0.05 and lm <= lmax * (1 + 1e-9)
+    # Sec. 3 reports little change of a_1 with the norm; measured here:
+    # -0.153 / -0.133 / -0.127 against the L2 fit's -0.124 / -0.126 / -0.124
+    # (printed, not held to a window).  What a minimum guarantees: the L_MAX
+    # fit's L_MAX is no larger than L_MAX at the L2 fit's a_1.
+    assert lm <= lmax * (1 + 1e-9)
 
     # two coefficients (a_1, a_2): Sec. 3 finds the second term of little use
     def l2_of2(v):
@@ -177,20 +181,25 @@ def test_ten_random_sources_gf_and_me_error(runner):
     assert gf[0] < 3.0 * me[0]
 
 
-T7_L2_RATIO = {4: (0.7, 1.0), 6: (1.0, 1.3), 8: (1.3, 2.0)}
-
-
 def test_t7_variant_against_gs1(runner):
     p = runner.p
+    rows = {(r[1], r[2]): r[3:] for r in _rows("dg_corner_t7_oracle.txt") if int(r[0]) == p}
+    ref_s1, ref_t7 = rows[(-0.125, 0.0)], rows[(-25.0 / 128.0, 3.0 / 128.0)]
     base = metric.norms(metric.delta_g(runner.periodic_error([[0, 0, 0]], [1.0], -0.125),
                                        runner.corner_twin))
     t7 = metric.norms(metric.delta_g(
         runner.periodic_error([[0, 0, 0]], [1.0], -25.0 / 128.0, 3.0 / 128.0), runner.corner_twin))
-    ratio = t7[0] / base[0]
-    print("t^7 variant p=%d: L2 %.3e L_MAX %.3e | G_S1 L2 %.3e L_MAX %.3e | ratio L2 %.2f L_MAX %.2f"
-          % (p, t7[0], t7[1], base[0], base[1], ratio, t7[1] / base[1]))
-    lo, hi = T7_L2_RATIO[p]
-    assert lo < ratio < hi
+    ratio, ref_ratio = t7[0] / base[0], ref_t7[0] / ref_s1[0]
+    print("t^7 variant p=%d: L2 %.3e (oracle %.3e) L_MAX %.3e (oracle %.3e) | ratio to G_S1: "
+          "L2 %.3f (oracle %.3f), L_MAX %.3f (oracle %.3f)"
+          % (p, t7[0], ref_t7[0], t7[1], ref_t7[1], ratio, ref_ratio, t7[1] / base[1],
+             ref_t7[1] / ref_s1[1]))
+    # the GPU's FP32 arithmetic: 1% in L2, 2% in L_MAX, as for the other rows
+    assert abs(t7[0] / ref_t7[0] - 1) < 0.01 and abs(t7[1] / ref_t7[1] - 1) < 0.02
+    assert abs(ratio / ref_ratio - 1) < 0.02
+    # the direction Sec. 3 reports holds wherever the oracle finds it
+    if ref_ratio > 1:
+        assert ratio > 1
 
 
 BINS = [1, 2, 4, 8, 16, 32, 64, 112]
@@ -258,18 +267,20 @@ def test_corner_errors_on_the_four_level_tree(p):
     assert gf[0] < 2.0 * me[0]
 
 
-def test_gx_aliasing_against_gs1(runner):
-    p = runner.p
-    if p != 6:
-        pytest.skip("Figs. 3-4 use N_g = 6")
-    import torch
+def test_gx_aliasing_against_gs1():
+    # Figs. 3-4 use N_g = 6
     from paper_2011_07099_amd.pfmm import Plan
-    with Plan(N, L, p, "X", accel="expansion", fp64_levels=L - 1) as px:
-        g = runner._accel(px, [[0, 0, 0]], [1.0])
-    e_x = g - metric.point_sources_accel(N, [[0, 0, 0]], [1.0], "X")
-    gx = metric.norms(metric.delta_g(e_x, runner.corner_twin))
-    gs = metric.norms(metric.delta_g(runner.periodic_error([[0, 0, 0]], [1.0], -0.125),
-                                     runner.corner_twin))
+    p = 6
+    r = _Runner(p)
+    try:
+        twin = r.twin_error([[0, 0, 0]], [1.0])
+        with Plan(N, L, p, "X", accel="expansion", fp64_levels=L - 1) as px:
+            g = r._accel(px, [[0, 0, 0]], [1.0])
+        e_x = g - metric.point_sources_accel(N, [[0, 0, 0]], [1.0], "X")
+        gx = metric.norms(metric.delta_g(e_x, twin))
+        gs = metric.norms(metric.delta_g(r.periodic_error([[0, 0, 0]], [1.0], -0.125), twin))
+    finally:
+        r.close()
     print("corner, p=6: G_X L2 %.3e L_MAX %.3e | G_S1 L2 %.3e L_MAX %.3e | ratio L_MAX %.0f"
           % (gx[0], gx[1], gs[0], gs[1], gx[1] / gs[1]))
     assert gx[1] > 1.0 and gx[1] > 300 * gs[1]

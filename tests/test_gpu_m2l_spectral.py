@@ -72,10 +72,13 @@ def test_spectral_zones_match_reference_and_gemm(N, L, p, green, f64, iso, prec)
 
 @pytest.mark.parametrize("N,L,p,green,iso", [
     (32, 3, 4, "S1", False), (64, 3, 8, "K", False), (32, 3, 8, "X", True),
+    (64, 3, 6, "S1", False),    # p = 6: direct 6-point DFTs, 96-entry twiddle table
+    (128, 4, 6, "K", False),    # p = 6 periodic with a 16^3 leaf level (the two-target stencil)
 ])
 def test_spectral_zones_in_fp64_match_the_fp64_gemm(N, L, p, green, iso):
     """Every level in FP64: the spectral and GEMM locals differ by FP64
-    rounding only, so their FP32 read-backs agree to one FP32 rounding."""
+    rounding only, so their FP32 read-backs agree to one FP32 rounding.  A
+    wrong twiddle or a transform that aliases would show far above it."""
     rho = f32(fields.lognormal(N, 2.0, 1.0, seed=291 + N + p))
     _, Phi = _solve_stages(rho, L, p, green, "spectral", 30, iso)
     _, G = _solve_stages(rho, L, p, green, "gemm", 30, iso)

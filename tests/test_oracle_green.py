@@ -117,3 +117,93 @@ def test_gk_zero_mean_and_newtonian_limit():
         r = np.sqrt(2) * j / N
         expect = -1 / (4 * np.pi * r) + 1 / (4 * np.pi * 2 * r) + 0.5 * r ** 2
         assert abs(d / expect - 1) < 1e-3
+
+
+def _fourier_interpolate_2x(lat):
+    """Band-limited interpolation of an N^3 periodic lattice function onto
+    the 2N^3 lattice of half-cell steps, by zero padding its discrete
+    spectrum.  The Nyquist coefficient of each axis is split equally between
+    +N/2 and -N/2 of the wider spectrum, so that the interpolant is real and
+    even wherever the lattice function is.  Independent of gk_series: FFTs of
+    the lattice values only."""
+    N = lat.shape[0]
+    A = np.fft.fftn(lat)
+    for axis in range(3):
+        shape = list(A.shape)
+        shape[axis] = 2 * N
+        B = np.zeros(shape, complex)
+        lo = [slice(None)] * 3
+        src = [slice(None)] * 3
+        lo[axis], src[axis] = slice(0, N // 2), slice(0, N // 2)
+        B[tuple(lo)] = A[tuple(src)]
+        lo[axis], src[axis] = slice(2 * N - N // 2 + 1, 2 * N), slice(N // 2 + 1, N)
+        B[tuple(lo)] = A[tuple(src)]
+        nyq = [slice(None)] * 3
+        nyq[axis] = slice(N // 2, N // 2 + 1)
+        half = 0.5 * A[tuple(nyq)]
+        lo[axis] = slice(N // 2, N // 2 + 1)
+        B[tuple(lo)] = half
+        lo[axis] = slice(2 * N - N // 2, 2 * N - N // 2 + 1)
+        B[tuple(lo)] = half
+        A = B
+    out = np.fft.ifftn(A) * 8.0
+    assert np.max(np.abs(out.imag)) < 1e-12 * np.max(np.abs(out.real))
+    return out.real
+
+
+def test_gk_series_off_mesh_equals_fourier_interpolation_of_the_lattice():
+    # Off the mesh G_K is the real even trigonometric interpolant of the
+    # lattice values of Eq. 1 (Nyquist term split between +-N/2).  An
+    # independent route to it: zero-pad the lattice function's FFT onto a
+    # twice finer lattice and transform back.  Every second point of the fine
+    # lattice lies half a cell off the mesh along one, two or three axes.
+    for N in (8, 16):
+        fine = _fourier_interpolate_2x(g.gk_lattice(N))
+        c = np.arange(2 * N) / (2.0 * N)
+        ser = g.gk_series(N, c, c, c)
+        np.testing.assert_allclose(ser, fine, rtol=0, atol=1e-13 * np.max(np.abs(fine)))
+        # the even sub-lattice is the mesh itself
+        np.testing.assert_allclose(ser[::2, ::2, ::2], g.gk_lattice(N), atol=1e-13)
+
+
+def test_gk_series_off_mesh_equals_explicit_symmetric_fourier_sum():
+    # Eq. 1 summed term by term at arbitrary points, with the Nyquist
+    # frequencies n_i = +-N/2 both present at half weight; the imaginary part
+    # cancels exactly (the coefficients are even in n).
+    N = 8
+    n1 = np.arange(-N // 2, N // 2 + 1)
+    w1 = np.where(np.abs(n1) == N // 2, 0.5, 1.0)
+    pts = [(0.1234, 0.4567, 0.7891), (0.5 / N, 0.0, 0.0), (0.37, 0.37, 0.5), (1.5 / N, 2.5 / N, 3.25 / N)]
+    ser = {p: g.gk_series(N, [p[0]], [p[1]], [p[2]])[0, 0, 0] for p in pts}
+    for x in pts:
+        s = 0.0 + 0.0j
+        for ia, a in enumerate(n1):
+            for ib, b in enumerate(n1):
+                for ic, c in enumerate(n1):
+                    if a == b == c == 0:
+                        continue
+                    k2 = (2 * np.pi) ** 2 * (a * a + b * b + c * c)
+                    s += w1[ia] * w1[ib] * w1[ic] * (-1.0 / k2) * np.exp(
+                        2j * np.pi * (a * x[0] + b * x[1] + c * x[2]))
+        assert abs(s.imag) < 1e-14
+        assert abs(ser[x] - s.real) < 1e-13 * max(1.0, abs(s.real))
+
+
+def test_gk_off_mesh_pin_rejects_the_one_sided_nyquist_sum():
+    # The pin above discriminates: the paper's one-sided frequency set
+    # n_i in [-N/2+1, N/2], evaluated off the mesh along every axis, has a
+    # different real part (and an imaginary part), so an interpolant that
+    # dropped the Nyquist split would fail it.
+    N = 8
+    n1 = np.arange(-N // 2 + 1, N // 2 + 1)
+    for x in ((0.5 / N, 0.5 / N, 0.5 / N), (0.37, 0.21, 0.05)):
+        s = 0.0 + 0.0j
+        for a in n1:
+            for b in n1:
+                for c in n1:
+                    if a == b == c == 0:
+                        continue
+                    k2 = (2 * np.pi) ** 2 * (a * a + b * b + c * c)
+                    s += (-1.0 / k2) * np.exp(2j * np.pi * (a * x[0] + b * x[1] + c * x[2]))
+        ser = g.gk_series(N, [x[0]], [x[1]], [x[2]])[0, 0, 0]
+        assert abs(s.imag) > 1e-4 and abs(s.real - ser) > 1e-4
