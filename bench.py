@@ -8,13 +8,17 @@ synthetic.  One step = one pfmm_solve (every stage of the method: P2M, M2M,
 the interaction zones of levels 2..4, L2L, L2P and the near zone) with the
 density already resident in HBM.
 
-Prints one JSON line: cells/s (N^3 / time per solve), the roofline of the
-dominant kernel (the near zone) from HIP events recorded on the plan's stream
-around each stage in profiled solves after the timed steps, the
-interaction-zone (M2L) share per level,
-and the CPU FP64 oracle timed on a bounded sample of the same workload
-(which also checks the GPU potential: sampled cells against the reference
-FMM, the full mesh against PM with the same G).
+Prints one JSON line:
+  - cells/s (N^3 / time per solve) over the timed steps;
+  - the roofline of the dominant single kernel of those same steps: the plan
+    records HIP events around each kernel on the stream it runs on while the
+    steps are timed (the near zone beside the tree, as in any solve);
+  - m2l_mfma: the interaction zones as block-Toeplitz GEMMs on the matrix
+    cores, timed in the same run on the same density, per level against the
+    peak of the matrix-core instruction it uses;
+  - the CPU FP64 oracle timed on a bounded sample of the same workload (which
+    also checks the GPU potential: sampled cells against the reference FMM,
+    the full mesh against PM with the same G).
 """
 import argparse
 import json
@@ -32,42 +36,40 @@ ALPHA, SIGMA, SEED = 1.5, 2.0, 5
 METRIC = "cells/s at 256^3 p=8 periodic FMM, L2 err<=1e-4 vs PM; M2L MFMA util"
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
-# MI355X peaks (TFLOP/s) of the units each contraction runs on
-PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 157.3, "f64 valu": 78.6}
-FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default)
+# MI355X peaks (TFLOP/s) of the units each kernel runs on.  The vector FP32
+# figure is the non-packed rate (256 CUs x 64 lanes x 2 flops x 2.4 GHz): this
+# library compiles every kernel with packed FP32 instructions disabled, so
+# the packed 157.3 is out of reach; it equals the FP64 vector rate.
+PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 78.6, "f64 valu": 78.6}
+FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default at L = 4)
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB; the mean of the two profiled solves' launches), scaled by a
-# plain 1 GiB copy (read x2.0, write x1.0), keyed by kernel, precision and the
-# SHA-1 prefix of the sources they were taken on (the kernel's file and
-# plan.hip, which sets the offset order and groups); a changed source reports
-# null.  Counters: profiles/pfmm_solve_256cube_L4_p8_*.md (the default: FFT near
-# zone, spectral interaction zones), profiles/zones_gemm_256cube_L4_p8_bf16x3.md
-# and profiles/near_direct_256cube_L4_p8_*.md.
-TRAFFIC = {
-    # the leaf level's spectral zones: node transforms, stencil and inverse together
-    ("spectral-L4", "bf16x3", "9df7fc67c4f5"): (162065 * 2.0 + 303326 * 1.0) * 1024,
-    ("spectral-L4", "fp32", "9df7fc67c4f5"): (162066 * 2.0 + 303328 * 1.0) * 1024,
-    ("zones-L4", "bf16x3", "b7aef9891b13"): (252926 * 2.0 + 262144 * 1.0) * 1024,
-    ("near", "bf16x3", "b7aef9891b13"): (1188392 * 2.0 + 65536 * 1.0) * 1024,
-    # the FFT near zone: leaf transforms, stencil and inverse together
-    ("near-fft", "bf16x3", "e64dd98b8f1f"): (677175 * 2.0 + 1179669 * 1.0) * 1024,
-    ("near-fft", "fp32", "e64dd98b8f1f"): (677120 * 2.0 + 1179648 * 1.0) * 1024,
-    ("near", "fp32", "1503ffb456c4"): (11731340 * 2.0 + 68856 * 1.0) * 1024,
-}
-KERNEL_SRC = {"bf16x3": ("toeplitz_mfma.hip", "plan.hip"), "fp32": ("toeplitz.hip", "plan.hip")}
-SPECTRAL_SRC = ("m2l_spectral.hip", "plan.hip")
-NEAR_FFT_SRC = ("near_fft.hip", "plan.hip")
+# HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch, the mean over the profiled run's launches), scaled by a
+# plain 1 GiB copy (read x2.0, write x1.0), keyed by the kernel's name in the
+# bench line and the SHA-1 prefix of the sources it was taken on (its file and
+# plan.hip); a changed source reports null.
+TRAFFIC = {}
+KERNEL_SRC = {"m2l": ("m2l_spectral.hip", "plan.hip"), "near": ("near_fft.hip", "plan.hip"),
+              "p2m": ("updown.hip", "plan.hip"), "l2p": ("updown.hip", "plan.hip")}
 
 
-def traffic_bytes(kernel, precision):
+def source_key():
+    """{kernel family: SHA-1 prefix of its sources}."""
     import hashlib
-    h = hashlib.sha1()
-    srcs = (SPECTRAL_SRC if kernel.startswith("spectral") else
-            NEAR_FFT_SRC if kernel == "near-fft" else KERNEL_SRC[precision])
-    for name in srcs:
-        h.update(open(os.path.join(ROOT, "paper_2011_07099_amd", "csrc", name), "rb").read())
-    return TRAFFIC.get((kernel, precision, h.hexdigest()[:12]))
+    out = {}
+    for fam, names in KERNEL_SRC.items():
+        h = hashlib.sha1()
+        for name in names:
+            h.update(open(os.path.join(ROOT, "paper_2011_07099_amd", "csrc", name), "rb").read())
+        out[fam] = h.hexdigest()[:12]
+    return out
+
+
+def traffic_bytes(kernel, precision=None):
+    fam = kernel.split()[0]
+    if fam not in KERNEL_SRC:
+        return None
+    return TRAFFIC.get((kernel, source_key()[fam]))
 
 
 def near_fft_bytes(N, L, kernels=1):
@@ -128,7 +130,7 @@ def cpu_baseline(rho64, phi_gpu, n_side=25):
             cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    context = {"pm_fft_s": pm_s, "pm_cells_per_s": N ** 3 / pm_s,
+    context = {"_pm": pm, "pm_fft_s": pm_s, "pm_cells_per_s": N ** 3 / pm_s,
                "pm_note": "PM with the same G (the FP64 FFT convolution the FMM approximates), "
                           "NumPy FFT on the host, table included",
                "cpu_model": cpu_model, "os_cpu_count": os.cpu_count()}
@@ -370,6 +372,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mfma", action="store_true",
+                    help="skip the GEMM-route interaction zones timed for the matrix-core "
+                         "utilisation (headline workload)")
     ap.add_argument("--workload", default="headline", choices=["headline", "batch", "learned", "m2l", "table"])
     ap.add_argument("--epochs", type=int, default=2, help="training epochs (learned workload)")
     ap.add_argument("--accel", default="none", choices=["none", "fd4", "expansion"],
@@ -407,6 +412,124 @@ def main():
         table_bench(args)
         return
 
+    headline(args)
+
+
+def kernel_table(plan, L, near_fft, spectral):
+    """{name: (ms, level, stage, part)} of the timed kernels of the recent
+    profiled solves: each stage as a whole, the spectral zones and the FFT
+    near zone kernel by kernel."""
+    out = {}
+    st = plan.stage_times()
+    for stage in ("p2m", "l2p", "fd4"):
+        if st[stage][1]:
+            out[stage] = (st[stage][0], 0, stage, 0)
+    for stage in ("m2m", "l2l"):
+        for lv, ms in plan.level_times(stage).items():
+            out["%s L%d" % (stage, lv)] = (ms, lv, stage, 0)
+    names = ("node transforms", "stencil", "inverse transforms")
+    for lv in range(2, L + 1):
+        parts = plan.kernel_times("m2l", lv)
+        if spectral:
+            for k, ms in enumerate(parts):
+                out["m2l L%d %s" % (lv, names[k])] = (ms, lv, "m2l", k)
+        elif parts:
+            out["m2l L%d" % lv] = (parts[0], lv, "m2l", 0)
+    parts = plan.kernel_times("near", 0)
+    if near_fft:
+        nn = ("leaf transforms", "stencil", "inverse transforms")
+        for k, ms in enumerate(parts):
+            out["near %s" % (nn[0] if k == 0 else nn[1 + (k - 1) % 2])
+                + ("" if k < 3 else " %d" % ((k - 1) // 2))] = (ms, 0, "near", k)
+    elif parts:
+        out["near"] = (parts[0], 0, "near", 0)
+    return out
+
+
+def kernel_work(name, N, L, p):
+    """Algorithmic work of one launch of a kernel of the default route:
+    (flops, unit, bytes).  Flops count 8 per complex multiply-add; bytes are
+    the kernel's compulsory HBM traffic (operands read once, results written
+    once).  Spectra are complex FP64 at the interaction zones ((2p)^2 (p + 1)
+    frequencies per node), complex FP32 at the near zone ((2s)^2 (s + 1) per
+    leaf)."""
+    s = N >> L
+    if name.startswith("m2l L"):
+        lv = int(name.split()[1][1:])
+        F = (2 * p) ** 2 * (p + 1)
+        nodes = 8 ** lv
+        spec = 16.0 * F * nodes
+        gl = (8.0 if lv in FP64_LEVELS else 4.0) * p ** 3 * nodes  # gridlet buffer
+        if name.endswith("stencil"):
+            offs = 37 if lv == 2 else 189
+            return offs * 8.0 * F * nodes, "f64 valu", 2 * spec + 343 * 16.0 * F
+        if name.endswith("inverse transforms"):
+            return None, "hbm", spec + 2 * gl
+        return None, "hbm", spec + gl
+    if name.startswith("near"):
+        F = (2 * s) ** 2 * (s + 1)
+        leaves = 8 ** L
+        spec = 8.0 * F * leaves
+        if "stencil" in name:
+            return 27 * 8.0 * F * leaves, "f32 valu", 2 * spec + 27 * 8.0 * F
+        if "inverse" in name:
+            return None, "hbm", spec + 4.0 * N ** 3
+        return None, "hbm", spec + 4.0 * N ** 3
+    if name in ("p2m",):
+        return None, "hbm", 4.0 * N ** 3 + 4.0 * p ** 3 * 8 ** L
+    if name in ("l2p",):
+        return None, "hbm", 8.0 * N ** 3 + 4.0 * p ** 3 * 8 ** L
+    return None, "hbm", None
+
+
+def gemm_m2l_mfma(rho, args):
+    """The interaction zones as block-Toeplitz GEMMs on the matrix cores, on
+    the same density: split BF16 (three bf16 terms per operand, six products)
+    at the leaf level, FP64 matrix cores at the FP64 levels 2-3.  Per level:
+    HIP-event time of its launches (stages one after another), algorithmic
+    flops (2 p^6 per offset and target node), issued flops (times the
+    products; equal to the MOPS counters) and the fraction of the peak of the
+    matrix-core instruction that level runs on."""
+    import torch
+    from paper_2011_07099_amd.pfmm import Plan
+    phi = torch.empty_like(rho)
+    with Plan(N, L, P, GREEN, precision="bf16x3", near="direct", m2l="gemm") as pl:
+        for _ in range(2):
+            pl.solve(rho, phi)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            pl.solve(rho, phi)
+        e1.record()
+        torch.cuda.synchronize()
+        route_ms = e0.elapsed_time(e1) / 5
+        pl.set_profile("serial")
+        for _ in range(5):
+            pl.solve(rho, phi)
+        lv_ms = pl.level_times("m2l")
+        torch.cuda.synchronize()
+    levels, issued, budget = {}, 0.0, 0.0
+    for lv, ms in sorted(lv_ms.items()):
+        fl = (37 if lv == 2 else 189) * 2.0 * P ** 6 * 8 ** lv
+        unit, products = ("f64 mfma", 1) if lv in FP64_LEVELS else ("bf16 mfma", 6)
+        peak = PEAK_UNIT[unit]
+        tf = fl / (ms * 1e-3) / 1e12
+        levels[str(lv)] = {"ms": ms, "unit": unit, "products": products, "flops": fl,
+                           "algorithmic_tflops": tf, "issued_tflops": tf * products, "peak": peak,
+                           "algorithmic_frac": tf / peak, "issued_frac": tf * products / peak}
+        issued += fl * products
+        budget += ms * 1e-3 * peak * 1e12
+    return {"route": "block-Toeplitz GEMM zones (split bf16 at level 4, FP64 matrix cores at "
+                     "levels 2-3), timed on the same density in this run",
+            "util": issued / budget, "util_note": "issued matrix-core flops of all levels over "
+            "the time-weighted peak of the instruction each level uses",
+            "levels": levels, "m2l_ms": sum(lv_ms.values()),
+            "solve_ms_with_direct_near_zone": route_ms,
+            "phi": phi}
+
+
+def headline(args):
     import torch
     from paper_2011_07099_amd import fields
     from paper_2011_07099_amd.pfmm import Plan
@@ -425,6 +548,10 @@ def main():
     for _ in range(args.warmup):
         plan.solve(rho, phi, acc)
     torch.cuda.synchronize()
+    # the timed steps record HIP events around every kernel group on the
+    # stream it runs on (the near zone stays beside the tree): the per-kernel
+    # durations below come from these same solves
+    plan.set_profile("live")
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     t_start.record(stream)
@@ -433,86 +560,33 @@ def main():
     t_end.record(stream)
     torch.cuda.synchronize()
     ms = t_start.elapsed_time(t_end) / args.steps
-    # stage times from separate profiled solves (events around every stage;
-    # the near zone then runs before the tree on the plan stream instead of
-    # beside it), after the timed region
-    plan.set_profile(True)
-    for _ in range(min(args.steps, 10)):
-        plan.solve(rho, phi, acc)
+    spectral, near_fft = args.m2l == "spectral", args.near == "fft"
+    kern = kernel_table(plan, L, near_fft, spectral)
     stages = plan.stage_times()
     m2l_levels = plan.level_times("m2l")
     plan.close()
 
-    near_flops, m2l_flops = algorithmic_flops(N, L, P)
-    if args.accel == "expansion":
-        near_flops *= 4  # the potential's near zone and one per acceleration component
-    peak = PEAK_TFLOPS[args.precision]
-    near_ms = stages["near"][0]
-    m2l_ms = stages["m2l"][0]
-    near_tf = near_flops / (near_ms * 1e-3) / 1e12
-    m2l_tf = m2l_flops / (m2l_ms * 1e-3) / 1e12
-    near_unit, near_products = ("bf16 mfma", 3) if args.precision == "bf16x3" else ("f32 valu", 1)
-    per_level = {}
-    F = (2 * P) ** 2 * (P + 1)  # frequencies per node of the spectral zones
-    for lv, lms in sorted(m2l_levels.items()):
-        fl = (37 if lv == 2 else 189) * 2.0 * P ** 6 * 8 ** lv
-        if args.m2l == "spectral":
-            # one complex FP64 multiply-add per zone offset, target node and frequency
-            fl = (37 if lv == 2 else 189) * 8.0 * F * 8 ** lv
-            tf = fl / (lms * 1e-3) / 1e12
-            per_level[str(lv)] = {"ms": lms, "unit": "f64 valu", "products": 1, "achieved": tf,
-                                  "issued": tf, "peak": PEAK_UNIT["f64 valu"],
-                                  "frac": tf / PEAK_UNIT["f64 valu"], "flops": fl}
-            continue
-        if lv in FP64_LEVELS:
-            unit, products = "f64 mfma", 1
-        elif args.precision == "bf16x3":
-            unit, products = "bf16 mfma", 6
-        else:
-            unit, products = "f32 valu", 1
-        tf = fl / (lms * 1e-3) / 1e12
-        per_level[str(lv)] = {"ms": lms, "unit": unit, "products": products,
-                              "achieved": tf, "issued": tf * products, "peak": PEAK_UNIT[unit],
-                              "frac": tf * products / PEAK_UNIT[unit]}
-    if args.near == "direct":
-        # the direct near zone dominates
-        roofline = {"bound": "mfma" if near_unit.endswith("mfma") else "alu",
-                    "achieved": near_tf, "peak": peak, "unit": "TFLOP/s",
-                    "frac": near_tf / peak, "traffic": traffic_bytes("near", args.precision),
-                    "kernel": "near zone (%d launch/step, %.3f ms)" % (
-                        4 if args.accel == "expansion" else 1, near_ms),
-                    "unit_used": near_unit, "products": near_products,
-                    "issued_frac": near_tf * near_products / peak}
-    elif args.near == "fft" and near_ms > per_level[str(L)]["ms"]:
-        # the FFT near zone (leaf transforms, stencil, inverse) is the longest stage
-        nbytes = near_fft_bytes(N, L, 4 if args.accel == "expansion" else 1)
-        gbs = nbytes / (near_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
-                    "frac": gbs / 8000.0,
-                    "traffic": traffic_bytes("near-fft", args.precision) if args.accel != "expansion"
-                    else None,
-                    "kernel": "near zone by FFT (3 launches/step: leaf transforms, stencil, "
-                              "inverse; %.3f ms)" % near_ms,
-                    "algorithmic_bytes": nbytes}
-    elif args.m2l == "spectral":
-        # the leaf level's spectral zones (transforms, stencil, inverse) dominate
-        lv = per_level[str(L)]
-        roofline = {"bound": "alu", "achieved": lv["achieved"], "peak": lv["peak"],
-                    "unit": "TFLOP/s", "frac": lv["frac"],
-                    "traffic": traffic_bytes("spectral-L%d" % L, args.precision),
-                    "kernel": "level-%d interaction zones, spectral stencil (3 launches/step: "
-                              "node transforms, stencil, inverse; %.3f ms)" % (L, lv["ms"]),
-                    "unit_used": "f64 valu", "products": 1, "issued_frac": lv["frac"]}
+    # the dominant single kernel of the timed solves and its roofline
+    dom = max(kern, key=lambda k: kern[k][0])
+    dms = kern[dom][0]
+    fl, unit, kbytes = kernel_work(dom, N, L, P) if (spectral and near_fft) else (None, "hbm", None)
+    if fl is not None:
+        peak = PEAK_UNIT[unit]
+        tf = fl / (dms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                    "frac": tf / peak, "unit_used": unit, "flops_per_launch": fl}
     else:
-        # with the near zone by FFT the leaf level's interaction zones dominate
-        lv = per_level[str(L)]
-        roofline = {"bound": "mfma" if lv["unit"].endswith("mfma") else "alu",
-                    "achieved": lv["achieved"], "peak": PEAK_UNIT[lv["unit"]], "unit": "TFLOP/s",
-                    "frac": lv["achieved"] / PEAK_UNIT[lv["unit"]],
-                    "traffic": traffic_bytes("zones-L%d" % L, args.precision),
-                    "kernel": "level-%d interaction zones (1 launch/step, %.3f ms)" % (L, lv["ms"]),
-                    "unit_used": lv["unit"], "products": lv["products"],
-                    "issued_frac": lv["frac"]}
+        gbs = (kbytes or 0.0) / (dms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                    "frac": gbs / 8000.0}
+    roofline.update({
+        "kernel": "%s (%.4f ms average over the last %d timed solves, HIP events on its stream)"
+                  % (dom, dms, min(args.steps, 16)),
+        "traffic": traffic_bytes(dom, args.precision),
+        "kernel_compulsory_bytes": kbytes,
+        "solve_compulsory_bytes": 4.0 * N ** 3 * 2 + sum(
+            (8.0 if lv in FP64_LEVELS else 4.0) * 2 * P ** 3 * 8 ** lv for lv in range(2, L + 1)),
+    })
     out = {
         "metric": METRIC,
         "value": N ** 3 / (ms * 1e-3),
@@ -526,34 +600,38 @@ def main():
         "vs_baseline": None,
         # with the FFT near zone and spectral zones no step uses the split
         # bf16 products: FP32 near zone and mesh transfers, FP64 zones
-        "dtype": "f32+f64" if (args.near == "fft" and args.m2l == "spectral") else args.precision,
+        "dtype": "f32+f64" if (near_fft and spectral) else args.precision,
         "data": "synthetic",
         "config": {"workload": "periodic FMM, 256^3 lognormal density (P(k)~k^-1.5, "
                                "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
-                   "N": N, "L": L, "p": P, "green": GREEN, "precision": args.precision,
+                   "N": N, "L": L, "p": P, "green": GREEN,
+                   "arithmetic": ("FP32 near zone (FFT on the doubled grid) and mesh transfers, "
+                                  "FP64 interaction zones (spectral stencils) and levels 2-3"
+                                  if (near_fft and spectral) else args.precision),
                    **({"accel": args.accel} if args.accel != "none" else {}),
-                   **({"near": args.near} if args.near != "direct" else {}),
-                   **({"m2l": args.m2l} if args.m2l != "gemm" else {})},
+                   "near": args.near, "m2l": args.m2l},
         "roofline": roofline,
-        "m2l": {"method": args.m2l,
-                "achieved": (sum(v["flops"] for v in per_level.values()) / (m2l_ms * 1e-3) / 1e12
-                             if args.m2l == "spectral" else m2l_tf),
-                "unit": "TFLOP/s", "ms": m2l_ms,
-                "launches": stages["m2l"][1], "levels": per_level},
+        "kernels_ms": {k: v[0] for k, v in sorted(kern.items(), key=lambda kv: -kv[1][0])},
         "stages_ms": {k: v[0] for k, v in stages.items()},
+        "m2l_levels_ms": {str(k): v for k, v in m2l_levels.items()},
     }
-    if args.near == "fft":
-        nb = near_fft_bytes(N, L, 4 if args.accel == "expansion" else 1)
-        gbs = nb / (near_ms * 1e-3) / 1e9
-        out["near"] = {"method": "fft", "bound": "hbm", "achieved": gbs, "peak": 8000.0,
-                       "unit": "GB/s", "frac": gbs / 8000.0, "bytes": nb, "ms": near_ms}
-    else:
-        out["near"] = {"method": "direct", "achieved": near_tf, "unit": "TFLOP/s", "ms": near_ms}
+    mf = gemm_m2l_mfma(rho, args) if not args.no_mfma else None
+    if mf is not None:
+        gemm_phi = mf.pop("phi")
+        out["m2l_mfma"] = mf
     if not args.no_cpu_baseline:
-        base, acc, context = cpu_baseline(rho32.astype(np.float64),
-                                          phi.cpu().numpy().astype(np.float64))
+        base, accd, context = cpu_baseline(rho32.astype(np.float64),
+                                           phi.cpu().numpy().astype(np.float64))
         out["cpu_baseline"] = base
-        out["accuracy"] = acc
+        out["accuracy"] = accd
+        if mf is not None:
+            from oracle import conv
+            pm = context.pop("_pm")
+            a = gemm_phi.cpu().numpy().astype(np.float64)
+            a, b = a - a.mean(), pm - pm.mean()
+            out["m2l_mfma"]["l2_rel_vs_pm"] = float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+            assert conv is not None
+        context.pop("_pm", None)
         out["cpu_context"] = context
     print(json.dumps(out), flush=True)
 

@@ -25,6 +25,10 @@
  *  - Device pointers are HIP device addresses (e.g. a torch tensor's
  *    data_ptr()); the caller owns them.  The plan owns its tables and
  *    workspaces.  No entry point takes ownership of caller memory.
+ *  - Plan and batch handles are opaque tokens, not addresses.  Each carries
+ *    a generation count: once its object is destroyed the handle is refused
+ *    with PFMM_ERR_BAD_HANDLE, also after the library has reused its slot.
+ *    Calls on one handle must not overlap with its destroy.
  *  - Every entry point returns a pfmm_status.  Host-side argument checks run
  *    before anything is enqueued.  Asynchronous device faults surface as
  *    PFMM_ERR_HIP from a later call that synchronises.  pfmm_last_error()
@@ -44,10 +48,14 @@ typedef struct pfmm_plan_s* pfmm_plan_t;
 
 typedef enum {
   PFMM_OK = 0,
-  PFMM_ERR_INVALID_ARG = 1,   /* bad size, kind, option, pointer or handle  */
+  PFMM_ERR_INVALID_ARG = 1,   /* bad size, kind, option or pointer          */
   PFMM_ERR_UNSUPPORTED = 2,   /* valid but outside what the library handles  */
   PFMM_ERR_OUT_OF_MEMORY = 3, /* a plan-time allocation failed              */
-  PFMM_ERR_HIP = 4            /* a HIP runtime call or a kernel failed      */
+  PFMM_ERR_HIP = 4,           /* a HIP runtime call or a kernel failed      */
+  PFMM_ERR_CAPTURE = 5,       /* a call that allocates or synchronises was
+                                 made while the plan's stream is being
+                                 captured into a graph                      */
+  PFMM_ERR_BAD_HANDLE = 6     /* not a live plan or batch handle            */
 } pfmm_status;
 
 /* Periodic Green's functions. */
@@ -76,7 +84,14 @@ typedef enum {
    * frequencies as for G_K.  r_S is set by PFMM_OPT_EWALD_RS (default 0.1 of
    * the box).  At zero separation the Newtonian part of G_X erfc takes the
    * cube self value and the rest its limit 1/(2 pi^(3/2) r_S). */
-  PFMM_GREEN_E = 4
+  PFMM_GREEN_E = 4,
+  /* A learned approximation of the optimal G_* (Sec. 3 defines G_* as the G
+   * with which FMM and PM agree; Sec. 4 proposes parameterising it): G_S1's
+   * tables with the interaction-zone entries corrected by the network of
+   * pfmm_learned_set (weights also through PFMM_OPT_LEARNED_WEIGHTS).
+   * Without weights a solve uses the uncorrected G_S1 tables (the fallback),
+   * returns PFMM_OK and records the fallback in pfmm_last_error(). */
+  PFMM_GREEN_LEARNED = 5
 } pfmm_green;
 
 /* Arithmetic of the two contraction-heavy steps (interaction-zone
@@ -87,7 +102,15 @@ typedef enum {
   /* Split precision: each FP32 operand x is held as hi = bf16(x) and
    * lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi on the BF16 matrix
    * cores with FP32 accumulation. */
-  PFMM_PREC_BF16X3 = 1
+  PFMM_PREC_BF16X3 = 1,
+  /* FP64 throughout: every level's gridlets and interaction zones, the mesh
+   * transfers and the near zone (direct summation in FP64, whatever
+   * PFMM_OPT_NEAR says).  pfmm_solve then rounds only its FP32 result;
+   * pfmm_solve_f64 takes and returns FP64 arrays.  Needs the leaf's FP64
+   * transfers to fit in 64 KiB of LDS (p s + s^3 + s^2 p + s p^2 <= 8192
+   * doubles, and the same for L2P; every s <= 16 with p <= 9): else
+   * PFMM_ERR_UNSUPPORTED.  Not accepted by batches. */
+  PFMM_PREC_FP64 = 2
 } pfmm_precision;
 
 /* Options for pfmm_plan_set. */
@@ -100,10 +123,15 @@ typedef enum {
   /* value: double a_1 of the G_S ansatz (Sec. 3); only for PFMM_GREEN_S.
    * Re-tabulates G synchronously. */
   PFMM_OPT_GS_A1 = 3,
-  /* value: int32 0/1.  When 1, solve records HIP events on the plan's stream
-   * around every stage (events are created at plan time; recording them
-   * allocates nothing); pfmm_plan_stage_times reads them.  While on, the near
-   * zone runs on the plan's stream before the tree instead of beside it.
+  /* value: int32 0, 1 or 2.  Non-zero: solve records a start and an end
+   * HIP event around every stage's launches, and around each kernel of the
+   * spectral interaction zones and of the FFT near zone, on the stream each
+   * runs on (the events are created when profiling is first switched on;
+   * recording them allocates nothing); pfmm_plan_stage_times,
+   * pfmm_plan_level_times and pfmm_plan_kernel_times read them.  1: the
+   * near zone runs on the plan's stream before the tree, so every interval
+   * is a stage alone on the device.  2: the near zone stays beside the tree
+   * as in an unprofiled solve (live durations of overlapped kernels).
    * Default 0. */
   PFMM_OPT_PROFILE = 4,
   /* value: int32 in [0, 30]: keep the gridlet masses and potentials of the
@@ -111,11 +139,11 @@ typedef enum {
    * sums (on the FP64 matrix cores at p = 8) and L2L in FP64.  The downward
    * interpolation (Eq. 7, and its leaf analogue when s > p) extrapolates past
    * a parent's outermost gridlet nodes, so rounding noise in a coarse field
-   * is amplified on its way to the mesh, most at leaf corners.  Default 2
-   * (levels 2 and 3), which keeps every level above the leaf in FP64 for
-   * L = 4; deeper trees want L - 2 (at 512^3, L = 5, an FP32 level 4 leaves
-   * 1e-4 of max|phi|, FP64 storage 7e-7); L - 1 or more also keeps the leaf
-   * level in FP64. */
+   * is amplified on its way to the mesh, most at leaf corners.  Default
+   * max(2, L - 2): levels 2 .. L - 1, every level above the leaf, for
+   * L >= 4 (at 512^3, L = 5, an FP32 level 4 would leave 1e-4 of max|phi|,
+   * FP64 storage 7e-7), and levels 2 and 3 for L <= 3; L - 1 or more also
+   * keeps the leaf level in FP64. */
   PFMM_OPT_FP64_LEVELS = 5,
   /* value: int32 0 or 1.  1 makes the plan the non-periodic twin used to
    * separate the multipole-expansion error from the Green's-function error
@@ -149,7 +177,11 @@ typedef enum {
    * and transforms the near-zone kernels (plan time; transformed again when G
    * or PFMM_OPT_ACCEL changes).  Batches take such plans for leaf edges
    * s = 4, 8, 16 (the library's own transforms).  Default PFMM_NEAR_DIRECT. */
-  PFMM_OPT_NEAR = 11
+  PFMM_OPT_NEAR = 11,
+  /* value: PFMM_MLP_PARAMS floats, the weights of the table-correction
+   * network (same as pfmm_learned_set with BF16 inference), meant for
+   * PFMM_GREEN_LEARNED plans.  Synchronises. */
+  PFMM_OPT_LEARNED_WEIGHTS = 12
 } pfmm_option;
 
 /* Leaf near-zone algorithm (the 27 neighbour leaves, Sec. 2). */
@@ -254,8 +286,10 @@ typedef enum {
  * 2^l nodes per axis at level l, leaves of s = N/2^L cells per axis), p^3
  * gridlet masses per node and the Green's function `green_kind`.
  *
- *   N     power of two, 8 <= N <= 1024
- *   L     2 <= L, 2^L <= N, and leaf width s = N/2^L <= 16
+ *   N     power of two, 8 <= N <= 1024 (else PFMM_ERR_INVALID_ARG)
+ *   L     2 <= L and 2^L <= N (else PFMM_ERR_INVALID_ARG); a leaf width
+ *         s = N/2^L above 16 is refused with PFMM_ERR_UNSUPPORTED (the mesh
+ *         transfers stage one leaf in 64 KiB of LDS)
  *   p     1 <= p <= 10
  *
  * Tabulates G on the device in FP64 (plan time) and allocates every
@@ -293,6 +327,21 @@ pfmm_status pfmm_plan_set(pfmm_plan_t plan, int option, const void* value, size_
 pfmm_status pfmm_solve(pfmm_plan_t plan, const float* density, float* potential, float* accel);
 
 /*
+ * The same solve with FP64 arrays, for PFMM_PREC_FP64 plans (the plain FP64
+ * periodic FMM; PFMM_ERR_INVALID_ARG for other plans):
+ *
+ *   density    device, const double[N*N*N], C order (read only)
+ *   potential  device, double[N*N*N], overwritten
+ *   accel      device, double[3][N*N*N], or NULL
+ *
+ * Same ordering, stream and no-allocation rules as pfmm_solve.  With L = 2
+ * and s = p the FMM is the exact periodic convolution of Eq. 4 (Sec. 3:
+ * identical by construction), here up to FP64 rounding.
+ */
+pfmm_status pfmm_solve_f64(pfmm_plan_t plan, const double* density, double* potential,
+                           double* accel);
+
+/*
  * Copy a plan buffer (pfmm_buffer) at tree level `level` (2..L) into the
  * device array `dst`: 8^level * p^3 floats for the gridlet buffers of the
  * last solve, or the FP64 tables described with the enum.  Enqueued on the
@@ -301,12 +350,12 @@ pfmm_status pfmm_solve(pfmm_plan_t plan, const float* density, float* potential,
 pfmm_status pfmm_plan_read(pfmm_plan_t plan, int buffer, int level, void* dst);
 
 /*
- * Per-solve durations in milliseconds of each pfmm_stage, averaged over the
- * most recent (at most 16) solves made since PFMM_OPT_PROFILE was switched
- * on, and the kernel launches of each stage in one solve, into
- * ms[PFMM_STAGE_COUNT] and launches[PFMM_STAGE_COUNT] (host arrays; launches
- * may be NULL).  Waits for those solves' events.  PFMM_ERR_INVALID_ARG if no
- * profiled solve has run.
+ * Per-solve durations in milliseconds of each stage, pfmm_stage, as the sum of its
+ * timed intervals, averaged over the most recent (at most 16) solves made
+ * since PFMM_OPT_PROFILE was switched on, and the timed intervals of each
+ * stage in one solve, into ms[PFMM_STAGE_COUNT] and
+ * launches[PFMM_STAGE_COUNT] (host arrays; launches may be NULL).  Waits for
+ * those solves' events.  PFMM_ERR_INVALID_ARG if no profiled solve has run.
  */
 pfmm_status pfmm_plan_stage_times(pfmm_plan_t plan, double* ms, int* launches);
 
@@ -321,12 +370,26 @@ pfmm_status pfmm_plan_stage_times(pfmm_plan_t plan, double* ms, int* launches);
  */
 pfmm_status pfmm_plan_level_times(pfmm_plan_t plan, int stage, double* ms);
 
+/*
+ * Durations of the kernels of one stage at one tree level (level 0 for the
+ * stages without levels), averaged over the same profiled solves: ms[part]
+ * for part = 0 .. *count - 1 (host array of 8 doubles).  The spectral
+ * interaction zones of a level have three parts (0 node transforms, 1
+ * stencil, 2 inverse transforms); the FFT near zone has the forward
+ * transforms (0), then the stencil (1 + 2t) and the inverse (2 + 2t) of
+ * each kernel t (the potential's, then one per acceleration component);
+ * every other stage and level is one part.  *count = 0 when none ran.
+ */
+pfmm_status pfmm_plan_kernel_times(pfmm_plan_t plan, int stage, int level, double* ms, int* count);
+
 /* Query plan geometry: leaf width s and the number of table entries
  * per tree level ((8p-1)^3) into *s and *table_entries (either may be NULL). */
 pfmm_status pfmm_plan_info(pfmm_plan_t plan, int* s, int64_t* table_entries);
 
 /* Release a plan and everything it owns.  Synchronises its stream.  NULL is
- * accepted and ignored. */
+ * accepted and ignored.  Batches that pfmm_solve_batch made with the plan
+ * are released with it; a plan bound to a live batch of pfmm_batch_create
+ * is refused (PFMM_ERR_INVALID_ARG): destroy the batch first. */
 pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
 
 /*
@@ -358,10 +421,14 @@ pfmm_status pfmm_plan_destroy(pfmm_plan_t plan);
  * graph on the batch's own stream, ordered with the stream of plans[0].  It
  * allocates, runs solves and synchronises; it is plan time.
  *
- * Requirements: 1 <= n <= 4096; live plans on one device, p <= 8; the plans
- * are not solved concurrently with the batch (it uses their workspaces);
- * density and potential 16-byte aligned for plans with PFMM_NEAR_FFT.
- * Precision and FP64 levels are those of each plan at batch creation.
+ * Requirements: 1 <= n <= 4096; live plans on one device, p <= 8, not
+ * PFMM_PREC_FP64; the plans are not solved concurrently with the batch (it
+ * uses their workspaces); density and potential 16-byte aligned for plans
+ * with PFMM_NEAR_FFT.  Precision and FP64 levels are those of each plan at
+ * batch creation.  While the batch lives its plans refuse pfmm_plan_destroy
+ * and the options that change what its graph uses (precision, isolated
+ * twin, FP64 levels, M2L and near-zone routes).  PFMM_ERR_CAPTURE while the
+ * stream of plans[0] is being captured.
  */
 typedef struct pfmm_batch_s* pfmm_batch_t;
 pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* const* density,
@@ -384,6 +451,18 @@ pfmm_status pfmm_batch_group(pfmm_batch_t batch, int group, int* desc, double* m
 
 /* Release a batch (not its plans). NULL is accepted and ignored. */
 pfmm_status pfmm_batch_destroy(pfmm_batch_t batch);
+
+/*
+ * Solve n independent fields as one batch: potential[i] from density[i]
+ * with plans[i] (arguments as for pfmm_batch_create).  The first call with
+ * a given set of (plan, density, potential) triples builds and captures its
+ * batch (plan time: allocates and synchronises; PFMM_ERR_CAPTURE under
+ * capture) and keeps it; later calls with the same set only launch its
+ * graph on the stream of plans[0] and do not allocate.  The kept batch is
+ * released with the first of its plans to be destroyed.
+ */
+pfmm_status pfmm_solve_batch(int n, const pfmm_plan_t* plans, const float* const* density,
+                             float* const* potential);
 
 /*
  * Direct periodic convolution  potential_i = h^3 sum_j G((x_i - x_j) wrapped) rho_j

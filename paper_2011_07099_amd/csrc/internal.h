@@ -10,6 +10,15 @@
 
 namespace pfmm {
 
+// Optional timing of a routine's kernels: begin() before and end(part) after
+// its part-th kernel (or group of kernels), on the stream it launches on.
+// A null timer times nothing.
+struct KernelTimer {
+  virtual hipError_t begin(hipStream_t s) = 0;
+  virtual hipError_t end(hipStream_t s, int part) = 0;
+  virtual ~KernelTimer() = default;
+};
+
 // ---------------------------------------------------------------------------
 // Green's function tabulation (FP64, plan time)
 // ---------------------------------------------------------------------------
@@ -33,6 +42,12 @@ struct GreenSpec {
 // temporaries and synchronise `st`.
 hipError_t tabulate_green(const GreenSpec& g, int N, int C, int64_t den, double self_h,
                           double* dst, hipStream_t st);
+// The same without allocating or synchronising: the Fourier kinds (G_K, G_E)
+// keep their partial sums in the caller's workspace `ws` of
+// tabulate_workspace_doubles(kind, N, C) doubles (0 for the real-space kinds).
+size_t tabulate_workspace_doubles(int kind, int N, int C);
+hipError_t tabulate_green_ws(const GreenSpec& g, int N, int C, int64_t den, double self_h,
+                             double* dst, double* ws, hipStream_t st);
 
 // Near-zone acceleration tables d[i][j] = -(4th-order central difference of the
 // lattice G along axis i at j) for j in [-C, C]^3, i = x, y, z (FP64, device).
@@ -64,6 +79,7 @@ struct ToepArgs {
   int groups;       // >1: offsets split over workgroups writing `partial`
   void* partial;    // [groups][n^3][q^3] (block layout only), summed in order
   int isolated;     // 1: no periodic images, sources outside [0, n)^3 are zero
+  int mesh64;       // grid_in / grid_out mesh arrays hold doubles (fp64 only); else floats
 };
 
 // Workgroups of one launch of the portable kernel (before offset groups).
@@ -207,6 +223,16 @@ hipError_t launch_l2p_grad(const void* P, int p64, float* acc, Weights A, Weight
                            double scale, int N, int s, int p, hipStream_t st);
 // a = -grad(phi), periodic 4th-order central differences.
 hipError_t launch_fd4(const float* phi, float* acc, int N, hipStream_t st);
+// The same three steps with an FP64 mesh (density in, or potential and
+// accelerations out) and FP64 gridlets: the PFMM_PREC_FP64 solve with FP64
+// buffers.
+hipError_t launch_p2m_f64in(const double* rho, void* M, Weights A, int N, int s, int p, double h3,
+                            hipStream_t st);
+hipError_t launch_l2p_f64out(const void* P, double* phi, Weights A, int N, int s, int p,
+                             hipStream_t st, int accumulate = 0);
+hipError_t launch_l2p_grad_f64out(const void* P, double* acc, Weights A, Weights Ad, double scale,
+                                  int N, int s, int p, hipStream_t st);
+hipError_t launch_fd4_f64(const double* phi, double* acc, int N, hipStream_t st);
 // ---------------------------------------------------------------------------
 // Interaction zones by FFT convolution (the HPM comparator)
 // ---------------------------------------------------------------------------
@@ -243,8 +269,10 @@ int near_fft_kernels(const NearFft* f);
 int near_fft_fused(const NearFft* f);
 // out[t] = the near zone of rho with kernel t, t < nout (written, not added);
 // isolated: sources outside the box are absent instead of periodic images.
+// Parts for a timer: 0 the forward transforms, then per kernel t the
+// stencil (1 + 2t) and the inverse transform (2 + 2t).
 hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
-                        hipStream_t st);
+                        hipStream_t st, KernelTimer* kt = nullptr);
 
 // ---------------------------------------------------------------------------
 // Interaction zones as spectral stencils (per-node transforms, FP64)
@@ -258,10 +286,25 @@ void m2l_spectral_destroy(M2LSpectral* f);
 hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64, hipStream_t st);
 // Pl (+)= the level-l zone sums of Ml over `offs` (noff per class: 8 classes
 // at levels >= 3, one at level 2); m64 / p64: the buffers hold doubles.
+// Parts for a timer: 0 the node transforms, 1 the stencil, 2 the inverse.
 hipError_t m2l_spectral_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, int p64,
-                              int accumulate, const int* offs, int noff, int isolated, hipStream_t st);
+                              int accumulate, const int* offs, int noff, int isolated, hipStream_t st,
+                              KernelTimer* kt = nullptr);
 
 // FP64 -> FP32 copy of n elements.
 hipError_t launch_cast_d2f(const double* src, float* dst, int64_t n, hipStream_t st);
+
+// What the direct periodic convolution of a plan needs (plan.hip): mesh
+// size, G and stream.  Returns 0 (PFMM_OK), or a status with the message set.
+struct DirectSpec {
+  int N;
+  int isolated;
+  GreenSpec green;
+  hipStream_t stream;
+};
+int plan_direct_spec(const void* plan, DirectSpec* out);
+// Set the calling thread's message for pfmm_last_error and return `status`.
+int set_error(int status, const std::string& msg);
+void clear_error();
 
 }  // namespace pfmm

@@ -36,12 +36,14 @@ struct M2LSpectral {
   double2* spec = nullptr;       // [F][nodes] of the level being summed
   double2* out = nullptr;        // [F][nodes]
   std::vector<double2*> khat;    // per level: [343][F], offsets of [-3, 3]^3
+  std::vector<double2*> khatT;   // per level: [F][kKT], the same values frequency by frequency
   double2* dft[2] = {nullptr, nullptr};  // [343][F] DFT passes of the kernels
 };
 
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kKT = 344;  // kernel values per frequency in khatT (343 offsets, padded)
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
@@ -282,6 +284,14 @@ __global__ void __launch_bounds__(node_threads<P>()) k_node_inv(const double2* _
   }
 }
 
+// (re, im) += k s, one complex multiply-add as four FMAs
+__device__ __forceinline__ void cmac(double& re, double& im, double2 k, double2 s) {
+  re = fma(k.x, s.x, re);
+  re = fma(-k.y, s.y, re);
+  im = fma(k.x, s.y, im);
+  im = fma(k.y, s.x, im);
+}
+
 // out_t(k) = sum_{d in zone(class of t)} khat_d(k) spec_{t+d}(k) for one
 // frequency k and one tile of T^3 targets; T = 8, or T = n = 4 on the 4^3
 // level (one class).  Blocks are dealt to the 8 XCDs round robin; block g
@@ -436,10 +446,10 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
           const double2 ka = kc[2 * m], kb = kc[2 * m + 1];
-          r1 += ka.x * a[m].x - ka.y * a[m].y + kb.x * b[m].x - kb.y * b[m].y;
-          i1 += ka.x * a[m].y + ka.y * a[m].x + kb.x * b[m].y + kb.y * b[m].x;
-          r2 += ka.x * a[m + 1].x - ka.y * a[m + 1].y + kb.x * b[m + 1].x - kb.y * b[m + 1].y;
-          i2 += ka.x * a[m + 1].y + ka.y * a[m + 1].x + kb.x * b[m + 1].y + kb.y * b[m + 1].x;
+          cmac(r1, i1, ka, a[m]);
+          cmac(r1, i1, kb, b[m]);
+          cmac(r2, i2, ka, a[m + 1]);
+          cmac(r2, i2, kb, b[m + 1]);
         }
       } else {
 #pragma unroll
@@ -449,10 +459,8 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
           const int sz = 1 + q;
           const double2* ps = box + (pxy + (sz & 1)) * H3 + col + (sz >> 1);
           const double2 kd = kc[q], s1 = ps[0], s2 = ps[1];
-          r1 += kd.x * s1.x - kd.y * s1.y;
-          i1 += kd.x * s1.y + kd.y * s1.x;
-          r2 += kd.x * s2.x - kd.y * s2.y;
-          i2 += kd.x * s2.y + kd.y * s2.x;
+          cmac(r1, i1, kd, s1);
+          cmac(r2, i2, kd, s2);
         }
       }
     }
@@ -461,6 +469,155 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
   double2* o = out + sidx(k, ((int64_t)tx * n + ty) * n + tz, nn);
   o[0] = make_double2(r1, i1);
   o[16] = make_double2(r2, i2);  // node tz + 2
+}
+
+// Whole-level stencil for the periodic levels with n = 2H = 8 or 16 nodes per
+// axis: one workgroup per frequency holds the level's whole spectrum at that
+// frequency in LDS (n^3 values: periodic wrap, no halo) and sums every
+// target's zone.  Stored split by parity ([px][py][pz][hx][hy][hz], node
+// coordinate 2h + p), rows of H values (hz) XOR-swizzled by the row index so
+// that the lanes of a wave, which read one hz from H different rows, hit
+// distinct banks.  Two (H = 8) or one (H = 4) waves per parity class: the
+// class, the zone's offsets and so every kernel value are uniform across a
+// wave, and the kernel values come from the frequency's contiguous row of
+// khatT by scalar loads, leaving LDS to the sources.  A lane owns TZ targets
+// of its class consecutive in hz (2 apart in z); walking the zone by (dx, dy)
+// columns, each parity plane of a column is one run of TZ + 2 source values
+// shared by the TZ targets (three offsets per target and plane).  Columns
+// next to the target (|dx|, |dy| <= 1) skip the three dz of the near zone.
+// Blocks are dealt to the 8 XCDs so that the 8 frequencies of a chunk, which
+// share every 128-byte line of the spectra, run on one XCD back to back.
+template <int H, int TZ>
+__global__ void __launch_bounds__(8 * (H * H * H / TZ), 8) k_zone_level(
+    const double2* __restrict__ spec, const double2* __restrict__ khatT, int64_t F, int nchunk,
+    double2* __restrict__ out) {
+  constexpr int n = 2 * H, nn = n * n * n;
+  constexpr int LPC = H * H * H / TZ;   // lanes per class
+  constexpr int NT = 8 * LPC;
+  static_assert(LPC % 64 == 0, "a class fills whole waves");
+  static_assert(H % TZ == 0, "whole target runs");
+  __shared__ double2 box[nn];
+  const int g = blockIdx.x;
+  const int chunk = ((g >> 3) >> 3) * 8 + (g & 7);
+  if (chunk >= nchunk) return;
+  const int k = chunk * 8 + ((g >> 3) & 7);
+  const double2* sk = spec + (int64_t)(k >> 3) * nn * 8 + (k & 7);  // node v at sk[8 v]
+  // stage: node (x, y, z) -> parity block, row (hx, hy), swizzled hz
+  for (int v = threadIdx.x; v < nn; v += NT) {
+    const int x = v / (n * n), y = (v / n) % n, z = v % n;
+    const int row = (((x & 1) * 2 + (y & 1)) * 2 + (z & 1)) * H * H + (x >> 1) * H + (y >> 1);
+    box[row * H + ((z >> 1) ^ (row & (H - 1)))] = sk[(int64_t)v * 8];
+  }
+  __syncthreads();
+  const int cls = __builtin_amdgcn_readfirstlane(threadIdx.x / LPC);
+  const int cx = cls >> 2, cy = (cls >> 1) & 1, cz = cls & 1;
+  const int lane = threadIdx.x % LPC;
+  const int hx = lane / (H * (H / TZ)), hy = (lane / (H / TZ)) % H, hz0 = (lane % (H / TZ)) * TZ;
+  const double2* kf = khatT + (int64_t)k * kKT;
+  double re[TZ], im[TZ];
+#pragma unroll
+  for (int t = 0; t < TZ; ++t) re[t] = im[t] = 0.0;
+  // one parity plane of a column: source half-z hz0 - 1 + j (j < TZ + 2);
+  // target t reads j = t + m with the kernel of offset index kidx[m]
+  auto plane = [&](int rowbase, int kbase, int pz, bool m0, bool m1, bool m2) {
+    double2 src[TZ + 2];
+    const int row = rowbase + pz * H * H;
+#pragma unroll
+    for (int j = 0; j < TZ + 2; ++j)
+      src[j] = box[row * H + (((hz0 - 1 + j) & (H - 1)) ^ (row & (H - 1)))];
+    // offset dz = sz - cz with sz = 2 m - 2 + pz (m = 0, 1, 2)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      if ((m == 0 && !m0) || (m == 1 && !m1) || (m == 2 && !m2)) continue;
+      const double2 kd = kf[kbase + (2 * m - 2 + pz - cz + 3)];
+#pragma unroll
+      for (int t = 0; t < TZ; ++t) {  // one complex multiply-add as four FMAs
+        const double2 sv = src[t + m];
+        re[t] = fma(kd.x, sv.x, re[t]);
+        re[t] = fma(-kd.y, sv.y, re[t]);
+        im[t] = fma(kd.x, sv.y, im[t]);
+        im[t] = fma(kd.y, sv.x, im[t]);
+      }
+    }
+  };
+  for (int sx = -2; sx <= 3; ++sx) {      // source x = 2 hx + cx + dx, sx = cx + dx
+    const int dx = sx - cx;
+    const int rx = ((hx + (sx >> 1)) & (H - 1)) * H;
+    for (int sy = -2; sy <= 3; ++sy) {
+      const int dy = sy - cy;
+      const int rowbase = ((sx & 1) * 4 + (sy & 1) * 2) * H * H + rx + ((hy + (sy >> 1)) & (H - 1));
+      const int kbase = (dx + 3) * 49 + (dy + 3) * 7;
+      if (abs(dx) > 1 || abs(dy) > 1) {
+        plane(rowbase, kbase, 0, true, true, true);
+        plane(rowbase, kbase, 1, true, true, true);
+      } else if (cz == 0) {  // keep sz = -2, 2 (even) and 3 (odd)
+        plane(rowbase, kbase, 0, true, false, true);
+        plane(rowbase, kbase, 1, false, false, true);
+      } else {               // keep sz = -2 (even), -1 and 3 (odd)
+        plane(rowbase, kbase, 0, true, false, false);
+        plane(rowbase, kbase, 1, true, false, true);
+      }
+    }
+  }
+  double2* o = out + (int64_t)(k >> 3) * nn * 8 + (k & 7);
+#pragma unroll
+  for (int t = 0; t < TZ; ++t) {
+    const int z = 2 * (hz0 + t) + cz;
+    const int v = ((2 * hx + cx) * n + (2 * hy + cy)) * n + z;
+    o[(int64_t)v * 8] = make_double2(re[t], im[t]);
+  }
+}
+
+// The 4^3 level (37 offsets periodic, 316 isolated), one workgroup per
+// 8-frequency chunk: each thread loads one node's 8 frequencies (one 128-byte
+// line) and then sums one target's zone at one frequency.  Kernel values of
+// the zone's offsets for the chunk come from khatT.
+__global__ void __launch_bounds__(512) k_zone_l2(const double2* __restrict__ spec,
+                                                 const double2* __restrict__ khatT,
+                                                 const int* __restrict__ offs, int noff, int isolated,
+                                                 int nchunk, double2* __restrict__ out) {
+  __shared__ double2 box[8 * 64];        // [frequency in chunk][node]
+  __shared__ double2 kk[8 * 316];        // [frequency in chunk][zone offset]
+  __shared__ int so[316];                // packed offsets
+  const int chunk = blockIdx.x;
+  if (chunk >= nchunk) return;
+  const double2* sk = spec + (int64_t)chunk * 64 * 8;
+  for (int i = threadIdx.x; i < 512; i += 512) box[(i & 7) * 64 + (i >> 3)] = sk[i];
+  for (int i = threadIdx.x; i < noff; i += 512) so[i] = offs[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < 8 * noff; i += 512) {
+    const int f = i / noff, d = i % noff;
+    const int pk = so[d];
+    const int dx = ((pk >> 16) & 255) - 128, dy = ((pk >> 8) & 255) - 128, dz = (pk & 255) - 128;
+    kk[f * 316 + d] = khatT[(int64_t)(chunk * 8 + f) * kKT + (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)];
+  }
+  __syncthreads();
+  const int f = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int tx = t >> 4, ty = (t >> 2) & 3, tz = t & 3;
+  double re = 0.0, im = 0.0;
+  for (int d = 0; d < noff; ++d) {
+    const int pk = so[d];
+    const int x = tx + ((pk >> 16) & 255) - 128, y = ty + ((pk >> 8) & 255) - 128,
+              z = tz + (pk & 255) - 128;
+    if (isolated && ((unsigned)x > 3u || (unsigned)y > 3u || (unsigned)z > 3u)) continue;
+    const double2 kd = kk[f * 316 + d];
+    const double2 sv = box[f * 64 + (((x & 3) * 4 + (y & 3)) * 4 + (z & 3))];
+    re = fma(kd.x, sv.x, re);
+    re = fma(-kd.y, sv.y, re);
+    im = fma(kd.x, sv.y, im);
+    im = fma(kd.y, sv.x, im);
+  }
+  out[(int64_t)chunk * 64 * 8 + t * 8 + f] = make_double2(re, im);
+}
+
+// khatT[f][d] = khat[d][f] (d < 343; the pad entry is zero).
+__global__ void k_khat_transpose(const double2* __restrict__ khat, int64_t F,
+                                 double2* __restrict__ khatT) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= F * kKT) return;
+  const int64_t f = i / kKT;
+  const int d = (int)(i % kKT);
+  khatT[i] = d < 343 ? khat[(int64_t)d * F + f] : make_double2(0.0, 0.0);
 }
 
 // Kernel spectrum of offset d (FP64 separable DFT): first pass along z of
@@ -525,22 +682,41 @@ __global__ void k_sdft_store(const double2* __restrict__ in, int p, double scale
   out[d] = make_double2(in[i].x * scale, in[i].y * scale);
 }
 
+inline hipError_t tbegin(KernelTimer* kt, hipStream_t st) { return kt ? kt->begin(st) : hipSuccess; }
+inline hipError_t tend(KernelTimer* kt, hipStream_t st, int part, hipError_t e) {
+  if (e != hipSuccess || !kt) return e;
+  return kt->end(st, part);
+}
+
 template <int P>
 hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, int p64,
-                     int accumulate, const int* offs, int noff, int isolated, hipStream_t st) {
+                     int accumulate, const int* offs, int noff, int isolated, hipStream_t st,
+                     KernelTimer* kt) {
   const int n = 1 << l;
   const int64_t nn = (int64_t)n * n * n;
   constexpr int NT = node_threads<P>();
+  hipError_t e = tbegin(kt, st);
+  if (e != hipSuccess) return e;
   if (m64)
     k_node_fwd<P, double><<<(unsigned)nn, NT, 0, st>>>((const double*)Ml, nn, f->spec);
   else
     k_node_fwd<P, float><<<(unsigned)nn, NT, 0, st>>>((const float*)Ml, nn, f->spec);
-  hipError_t e = hipGetLastError();
+  e = tend(kt, st, 0, hipGetLastError());
+  if (e == hipSuccess) e = tbegin(kt, st);
   if (e != hipSuccess) return e;
   const int classes = l == 2 ? 1 : 8;
   // blocks per tile: the 8-frequency chunks rounded up to a multiple of 8, times 8
   const int64_t per_tile = (f->F / 8 + 7) / 8 * 64;
-  if (n >= 16) {  // 8 x 8 x 16 tiles, two targets per lane
+  const int nchunk = (int)(f->F / 8);
+  const unsigned cgrid = (unsigned)((nchunk + 7) / 8 * 64);  // chunks rounded up to 8, times 8
+  if (n == 16 && !isolated) {  // the whole level per frequency, four targets per lane
+    k_zone_level<8, 4><<<cgrid, 1024, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
+  } else if (n == 8 && !isolated) {
+    k_zone_level<4, 1><<<cgrid, 512, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
+  } else if (n == 4) {
+    k_zone_l2<<<(unsigned)nchunk, 512, 0, st>>>(f->spec, f->khatT[l], offs, noff, isolated, nchunk,
+                                                 f->out);
+  } else if (n >= 16) {  // 8 x 8 x 16 tiles, two targets per lane
     const unsigned grid = (unsigned)(per_tile * (n / 8) * (n / 8) * (n / 16));
     k_zone_spec2<16><<<grid, 512, 0, st>>>(f->spec, f->khat[l], n, isolated, f->F, f->out);
   } else if (n == 8) {  // the 8^3 level as one tile, two targets per lane
@@ -551,13 +727,14 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
     k_zone_spec<<<grid, classes == 8 ? 512 : 64, 0, st>>>(f->spec, f->khat[l], offs, noff, n, classes,
                                                            isolated, f->F, f->out);
   }
-  e = hipGetLastError();
+  e = tend(kt, st, 1, hipGetLastError());
+  if (e == hipSuccess) e = tbegin(kt, st);
   if (e != hipSuccess) return e;
   if (p64)
     k_node_inv<P, double><<<(unsigned)nn, NT, 0, st>>>(f->out, nn, accumulate, (double*)Pl);
   else
     k_node_inv<P, float><<<(unsigned)nn, NT, 0, st>>>(f->out, nn, accumulate, (float*)Pl);
-  return hipGetLastError();
+  return tend(kt, st, 2, hipGetLastError());
 }
 
 }  // namespace
@@ -567,6 +744,7 @@ void m2l_spectral_destroy(M2LSpectral* f) {
   (void)hipFree(f->spec);
   (void)hipFree(f->out);
   for (double2* k : f->khat) (void)hipFree(k);
+  for (double2* k : f->khatT) (void)hipFree(k);
   for (double2* d : f->dft) (void)hipFree(d);
   delete f;
 }
@@ -580,11 +758,14 @@ hipError_t m2l_spectral_create(int L, int p, M2LSpectral** out) {
   f->F = (int64_t)(2 * p) * (2 * p) * (p + 1);
   const int64_t nodes = (int64_t)1 << (3 * L);
   f->khat.assign(L + 1, nullptr);
+  f->khatT.assign(L + 1, nullptr);
   hipError_t e = hipMalloc(&f->spec, (size_t)(f->F * nodes) * sizeof(double2));
   if (e == hipSuccess) e = hipMalloc(&f->out, (size_t)(f->F * nodes) * sizeof(double2));
   for (int d = 0; d < 2 && e == hipSuccess; ++d) e = hipMalloc(&f->dft[d], (size_t)(343 * f->F) * sizeof(double2));
   for (int l = 2; l <= L && e == hipSuccess; ++l)
     e = hipMalloc(&f->khat[l], (size_t)(343 * f->F) * sizeof(double2));
+  for (int l = 2; l <= L && e == hipSuccess; ++l)
+    e = hipMalloc(&f->khatT[l], (size_t)(kKT * f->F) * sizeof(double2));
   if (e != hipSuccess) {
     m2l_spectral_destroy(f);
     return e;
@@ -603,6 +784,7 @@ hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64
     k_sdft_axis<<<grid, kThreads, 0, st>>>(f->dft[0], p, 1, f->dft[1]);
     k_sdft_axis<<<grid, kThreads, 0, st>>>(f->dft[1], p, 0, f->dft[0]);
     k_sdft_store<<<grid, kThreads, 0, st>>>(f->dft[0], p, scale, f->khat[l]);
+    k_khat_transpose<<<nblk(f->F * kKT), kThreads, 0, st>>>(f->khat[l], f->F, f->khatT[l]);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -610,11 +792,12 @@ hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64
 }
 
 hipError_t m2l_spectral_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, int p64,
-                              int accumulate, const int* offs, int noff, int isolated, hipStream_t st) {
+                              int accumulate, const int* offs, int noff, int isolated, hipStream_t st,
+                              KernelTimer* kt) {
   if (l < 2 || l > f->L) return hipErrorInvalidValue;
-  if (f->p == 4) return run_level<4>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st);
-  if (f->p == 6) return run_level<6>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st);
-  return run_level<8>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st);
+  if (f->p == 4) return run_level<4>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st, kt);
+  if (f->p == 6) return run_level<6>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st, kt);
+  return run_level<8>(f, l, Ml, m64, Pl, p64, accumulate, offs, noff, isolated, st, kt);
 }
 
 }  // namespace pfmm

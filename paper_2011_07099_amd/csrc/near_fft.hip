@@ -465,14 +465,21 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
 #pragma unroll
       for (int ty = 0; ty < 2; ++ty) {
         float re = 0.0f, im = 0.0f;
+        // one complex multiply-add as four FMAs
+        auto cmac = [&](float2 kv, float2 sv) {
+          re = fmaf(kv.x, sv.x, re);
+          re = fmaf(-kv.y, sv.y, re);
+          im = fmaf(kv.x, sv.y, im);
+          im = fmaf(kv.y, sv.x, im);
+        };
 #pragma unroll
         for (int ex = 0; ex < 3; ++ex)
 #pragma unroll
           for (int ey = 0; ey < 3; ++ey) {
             const int c = (tx + ex) * 4 + (ty + ey);
-            const float2 a = kk[ex * 9 + ey * 3], b = kk[ex * 9 + ey * 3 + 1], d = kk[ex * 9 + ey * 3 + 2];
-            re += a.x * zm[c].x - a.y * zm[c].y + b.x * z0[c].x - b.y * z0[c].y + d.x * zp[c].x - d.y * zp[c].y;
-            im += a.x * zm[c].y + a.y * zm[c].x + b.x * z0[c].y + b.y * z0[c].x + d.x * zp[c].y + d.y * zp[c].x;
+            cmac(kk[ex * 9 + ey * 3], zm[c]);
+            cmac(kk[ex * 9 + ey * 3 + 1], z0[c]);
+            cmac(kk[ex * 9 + ey * 3 + 2], zp[c]);
           }
         obase[(int64_t)(((bx0 + tx) * nb + by0 + ty) * nb + bz) * stride] = make_float2(re, im);
       }
@@ -565,53 +572,71 @@ int near_fft_kernels(const NearFft* f) {
   return n;
 }
 
+// Timer hooks that do nothing without a timer.
+inline hipError_t tbegin(KernelTimer* kt, hipStream_t st) { return kt ? kt->begin(st) : hipSuccess; }
+inline hipError_t tend(KernelTimer* kt, hipStream_t st, int part, hipError_t e) {
+  if (e != hipSuccess || !kt) return e;
+  return kt->end(st, part);
+}
+
 template <int S>
 hipError_t run_fused(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
-                     hipStream_t st) {
+                     hipStream_t st, KernelTimer* kt) {
   const unsigned leaves = (unsigned)f->nleaf;
+  hipError_t e = tbegin(kt, st);
+  if (e != hipSuccess) return e;
   k_leaf_fwd<S><<<leaves, leaf_threads<S>(), 0, st>>>(rho, f->N, f->lgnb, f->nleaf, f->rhat);
-  hipError_t e = hipGetLastError();
+  e = tend(kt, st, 0, hipGetLastError());
   const int nchunk = (int)(f->F / 64);
   const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * (f->nb / 2) * (f->nb / 2);
   for (int t = 0; t < nout && e == hipSuccess; ++t) {
+    e = tbegin(kt, st);
+    if (e != hipSuccess) break;
     k_near_mac<true><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
                                                       isolated, f->yhat);
-    e = hipGetLastError();
+    e = tend(kt, st, 1 + 2 * t, hipGetLastError());
+    if (e == hipSuccess) e = tbegin(kt, st);
     if (e == hipSuccess) {
       k_leaf_inv<S><<<leaves, leaf_threads<S>(), 0, st>>>(f->yhat, f->N, f->lgnb, f->nleaf, out[t]);
-      e = hipGetLastError();
+      e = tend(kt, st, 2 + 2 * t, hipGetLastError());
     }
   }
   return e;
 }
 
 hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
-                        hipStream_t st) {
+                        hipStream_t st, KernelTimer* kt) {
   if (nout < 1 || nout > near_fft_kernels(f)) return hipErrorInvalidValue;
   if (f->fused) {
     switch (f->s) {
-      case 4: return run_fused<4>(f, rho, out, nout, isolated, st);
-      case 8: return run_fused<8>(f, rho, out, nout, isolated, st);
-      default: return run_fused<16>(f, rho, out, nout, isolated, st);
+      case 4: return run_fused<4>(f, rho, out, nout, isolated, st, kt);
+      case 8: return run_fused<8>(f, rho, out, nout, isolated, st, kt);
+      default: return run_fused<16>(f, rho, out, nout, isolated, st, kt);
     }
   }
   const int64_t total = f->nleaf * f->R;
+  hipError_t e = tbegin(kt, st);
+  if (e != hipSuccess) return e;
   k_pack<<<nblk(total), kThreads, 0, st>>>(rho, f->N, f->s, f->nb, total, f->pad);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e == hipSuccess) e = fft_err(hipfftSetStream(f->fwd, st));
   if (e == hipSuccess) e = fft_err(hipfftSetStream(f->inv, st));
   if (e == hipSuccess) e = fft_err(hipfftExecR2C(f->fwd, f->pad, (hipfftComplex*)f->rhat));
+  e = tend(kt, st, 0, e);
   const int nchunk = (int)((f->F + kThreads - 1) / kThreads);
   const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * (f->nb / 2) * (f->nb / 2);
   const int64_t N3 = (int64_t)f->N * f->N * f->N;
   for (int t = 0; t < nout && e == hipSuccess; ++t) {
+    e = tbegin(kt, st);
+    if (e != hipSuccess) break;
     k_near_mac<false><<<(unsigned)blocks, kThreads, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F,
                                                             nchunk, isolated, f->yhat);
-    e = hipGetLastError();
+    e = tend(kt, st, 1 + 2 * t, hipGetLastError());
+    if (e == hipSuccess) e = tbegin(kt, st);
     if (e == hipSuccess) e = fft_err(hipfftExecC2R(f->inv, (hipfftComplex*)f->yhat, f->pad));
     if (e == hipSuccess) {
       k_unpack<<<nblk(N3), kThreads, 0, st>>>(f->pad, f->N, f->s, f->nb, 0, out[t]);
-      e = hipGetLastError();
+      e = tend(kt, st, 2 + 2 * t, hipGetLastError());
     }
   }
   return e;

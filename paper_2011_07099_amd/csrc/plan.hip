@@ -49,7 +49,9 @@ struct pfmm_plan_s {
   double* dT64 = nullptr;
   float* dAd = nullptr;   // [p][s] derivative of the L2P weights
   double* dAd64 = nullptr;
-  int fp64_levels = 2;            // levels 2 .. 1+fp64_levels kept in FP64
+  int fp64_levels = 2;            // levels 2 .. 1+fp64_levels kept in FP64 (default max(2, L-2))
+  int learned_kind = 0;           // created as PFMM_GREEN_LEARNED (G_S1 tables plus a network)
+  int batch_refs = 0;             // live batches bound to this plan (its buffers are in their graphs)
   std::vector<void*> M, P;        // gridlet masses / potentials per level
   std::vector<double*> tab64;     // per level, (8p-1)^3
   std::vector<float*> tab32;
@@ -113,11 +115,12 @@ struct pfmm_plan_s {
   int* doffs = nullptr;
   int dq = 0, dC = 0, dnoff = 0;
   std::vector<void*> owned;
-  // stage timing (PFMM_OPT_PROFILE): a ring of event sets, one per solve
-  int profile = 0;
-  std::vector<hipEvent_t> ev;  // [kSlots][kMaxEvents], created at plan time
-  std::vector<int> ev_tag;     // stage of the interval ending at event k+1
-  std::vector<int> ev_used;    // events recorded per slot
+  // stage timing (PFMM_OPT_PROFILE): a ring of event sets, one per solve;
+  // each timed launch (or group of launches) has a start and an end event
+  int profile = 0;             // 0 off, 1 serial stages, 2 live (near zone beside the tree)
+  std::vector<hipEvent_t> ev;  // [kSlots][2 kMaxIntervals], created when profiling is first on
+  std::vector<int> ev_tag;     // [kSlots][kMaxIntervals]: stage | level << 8 | part << 16
+  std::vector<int> ev_used;    // intervals recorded per slot
   int nprof = 0;               // profiled solves since profiling was enabled
 };
 
@@ -126,15 +129,13 @@ namespace {
 // masses cancel strongly) and near zone (cell masses)
 constexpr int kM2LTerms = 3;
 constexpr int kNearTerms = 2;
-constexpr int kMaxEvents = 64;  // per solve
-constexpr int kSlots = 16;      // most recent profiled solves kept
+constexpr int kMaxIntervals = 64;  // timed launch groups per solve
+constexpr int kSlots = 16;         // most recent profiled solves kept
 }
 
 namespace {
 
 thread_local std::string g_err;
-std::mutex g_mu;
-std::set<pfmm_plan_s*> g_live;
 
 pfmm_status fail(pfmm_status st, const std::string& msg) {
   g_err = msg;
@@ -145,9 +146,75 @@ pfmm_status hip_fail(hipError_t e, const char* where) {
   return fail(PFMM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-bool live(pfmm_plan_s* p) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  return p && g_live.count(p);
+// Handles are tokens, not addresses: a tag byte, a generation count and a
+// slot index.  Destroying an object bumps its slot's generation, so a stale
+// handle is refused even after the slot has been reused by a new object.
+template <class T, uintptr_t Tag>
+class Registry {
+ public:
+  void* add(T* obj) {
+    std::lock_guard<std::mutex> lk(mu_);
+    uint32_t slot;
+    if (!free_.empty()) {
+      slot = free_.back();
+      free_.pop_back();
+    } else {
+      slot = (uint32_t)obj_.size();
+      obj_.push_back(nullptr);
+      gen_.push_back(1);
+    }
+    obj_[slot] = obj;
+    return reinterpret_cast<void*>(Tag << 56 | (uintptr_t)gen_[slot] << 24 | slot);
+  }
+  T* get(const void* h) {
+    std::lock_guard<std::mutex> lk(mu_);
+    uint32_t slot;
+    return find(h, slot);
+  }
+  // Remove and return the object of a live handle (nullptr for any other).
+  T* remove(const void* h) {
+    std::lock_guard<std::mutex> lk(mu_);
+    uint32_t slot;
+    T* obj = find(h, slot);
+    if (!obj) return nullptr;
+    obj_[slot] = nullptr;
+    gen_[slot] = (gen_[slot] + 1) & 0xffffffffu;
+    if (!gen_[slot]) gen_[slot] = 1;
+    free_.push_back(slot);
+    return obj;
+  }
+
+ private:
+  T* find(const void* h, uint32_t& slot) {
+    const uintptr_t v = reinterpret_cast<uintptr_t>(h);
+    if ((v >> 56) != Tag) return nullptr;
+    slot = (uint32_t)(v & 0xffffff);
+    const uint32_t gen = (uint32_t)((v >> 24) & 0xffffffffu);
+    if (slot >= obj_.size() || gen_[slot] != gen) return nullptr;
+    return obj_[slot];
+  }
+  std::mutex mu_;
+  std::vector<T*> obj_;
+  std::vector<uint32_t> gen_;
+  std::vector<uint32_t> free_;
+};
+
+Registry<pfmm_plan_s, 0x70> g_plans;
+
+pfmm_plan_s* plan_of(pfmm_plan_t h) { return g_plans.get(h); }
+pfmm_status bad_plan() { return fail(PFMM_ERR_BAD_HANDLE, "not a live plan handle"); }
+
+// Is work on `st` being captured into a graph?  Calls that allocate or
+// synchronise must not run then.
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e == hipErrorStreamCaptureImplicit) return true;
+  return e == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+pfmm_status capture_fail(const char* what) {
+  return fail(PFMM_ERR_CAPTURE, std::string(what) + " allocates or synchronises: not while the "
+                                "plan's stream is being captured");
 }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -221,7 +288,8 @@ void release(pfmm_plan_s* pl) {
 // Is level l kept in FP64?  Levels 2 .. 1 + fp64_levels are, except a leaf
 // whose FP64 P2M / L2P staging would not fit in 64 KiB of LDS.
 bool level64(const pfmm_plan_s* pl, int l) {
-  if (l < 2 || l > 1 + pl->fp64_levels) return false;
+  const int top = pl->prec == PFMM_PREC_FP64 ? pl->L : 1 + pl->fp64_levels;
+  if (l < 2 || l > top) return false;
   if (l == pl->L) {
     const int p = pl->p, s = pl->s;
     const size_t w1 = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
@@ -574,13 +642,6 @@ pfmm_status build(pfmm_plan_s* pl) {
     e = hipMemcpy(pl->offs_near, nz.data(), nz.size() * sizeof(int), hipMemcpyHostToDevice);
   if ((st = chk("upload zone lists"))) return st;
   (void)N;
-  pl->ev.assign(kSlots * kMaxEvents, nullptr);
-  for (auto& ev : pl->ev) {
-    e = hipEventCreate(&ev);
-    if ((st = chk("event"))) return st;
-  }
-  pl->ev_tag.assign(kSlots * kMaxEvents, 0);
-  pl->ev_used.assign(kSlots, 0);
   // default priority (no priority streams anywhere in this library)
   e = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking);
   if ((st = chk("side stream"))) return st;
@@ -595,6 +656,7 @@ pfmm_status build(pfmm_plan_s* pl) {
 namespace {
 pfmm_status learned_apply(pfmm_plan_s* pl, int bf16);
 }
+void drop_cached_batches(pfmm_plan_s* pl);
 
 extern "C" {
 
@@ -606,44 +668,71 @@ pfmm_status pfmm_plan_create(int N, int L, int p, int green_kind, pfmm_plan_t* o
     return fail(PFMM_ERR_INVALID_ARG, "N must be a power of two in [8, 1024]");
   if (L < 2 || (1 << L) > N) return fail(PFMM_ERR_INVALID_ARG, "need 2 <= L and 2^L <= N");
   if (p < 1 || p > 10) return fail(PFMM_ERR_INVALID_ARG, "p must be in [1, 10]");
-  if (green_kind < PFMM_GREEN_X || green_kind > PFMM_GREEN_E)
+  if (green_kind < PFMM_GREEN_X || green_kind > PFMM_GREEN_LEARNED)
     return fail(PFMM_ERR_INVALID_ARG, "unknown green_kind");
   const int s = N >> L;
-  if (s > 16) return fail(PFMM_ERR_UNSUPPORTED, "leaf width N/2^L must be <= 16");
+  if (s > 16)
+    return fail(PFMM_ERR_UNSUPPORTED, "leaf width N/2^L must be <= 16 (one leaf is staged in 64 KiB "
+                                      "of LDS by the mesh transfers)");
   pfmm_plan_s* pl = new (std::nothrow) pfmm_plan_s;
   if (!pl) return fail(PFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
   pl->N = N;
   pl->L = L;
   pl->p = p;
   pl->s = s;
-  pl->green = green_kind;
+  // a learned G is G_S1's tables with the network's correction on top
+  pl->learned_kind = green_kind == PFMM_GREEN_LEARNED;
+  pl->green = pl->learned_kind ? PFMM_GREEN_S1 : green_kind;
+  // deeper trees keep every level down to L - 1 in FP64: the downward
+  // interpolation (Eq. 7) amplifies a coarse level's rounding on its way to
+  // the mesh, once per level it passes
+  pl->fp64_levels = std::max(2, L - 2);
   pfmm_status st = build(pl);
   if (st != PFMM_OK) {
     (void)hipDeviceSynchronize();
     release(pl);
     return st;
   }
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_live.insert(pl);
-  }
-  *out = pl;
+  *out = static_cast<pfmm_plan_t>(g_plans.add(pl));
   return PFMM_OK;
 }
 
-pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t bytes) {
+pfmm_status pfmm_plan_set(pfmm_plan_t h, int option, const void* value, size_t bytes) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
   if (!value) return fail(PFMM_ERR_INVALID_ARG, "value is NULL");
+  if (option != PFMM_OPT_STREAM && option != PFMM_OPT_PROFILE && capturing(pl->stream))
+    return capture_fail("pfmm_plan_set");
+  // a live batch holds this plan's buffers, zone lists and routes in its graph
+  if (pl->batch_refs > 0 &&
+      (option == PFMM_OPT_PRECISION || option == PFMM_OPT_ISOLATED || option == PFMM_OPT_FP64_LEVELS ||
+       option == PFMM_OPT_M2L || option == PFMM_OPT_NEAR))
+    return fail(PFMM_ERR_INVALID_ARG, "the plan is bound to a live batch: this option would change "
+                                      "what the batch's graph uses");
   switch (option) {
     case PFMM_OPT_PRECISION: {
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "precision is an int32");
       int32_t v;
       std::memcpy(&v, value, sizeof v);
-      if (v != PFMM_PREC_FP32 && v != PFMM_PREC_BF16X3)
+      if (v != PFMM_PREC_FP32 && v != PFMM_PREC_BF16X3 && v != PFMM_PREC_FP64)
         return fail(PFMM_ERR_INVALID_ARG, "unknown precision");
+      if (v == PFMM_PREC_FP64) {
+        const int keep = pl->fp64_levels;
+        pl->fp64_levels = 30;
+        const bool leaf = level64(pl, pl->L);
+        pl->fp64_levels = keep;
+        if (!leaf)
+          return fail(PFMM_ERR_UNSUPPORTED, "PFMM_PREC_FP64: the leaf's FP64 mesh transfers do not fit "
+                                            "in 64 KiB of LDS at this leaf width and p");
+      }
       pl->prec = v;
       return PFMM_OK;
+    }
+    case PFMM_OPT_LEARNED_WEIGHTS: {
+      if (bytes != (size_t)kMlpParams * sizeof(float))
+        return fail(PFMM_ERR_INVALID_ARG, "learned weights are PFMM_MLP_PARAMS floats");
+      return pfmm_learned_set(h, static_cast<const float*>(value), 1);
     }
     case PFMM_OPT_STREAM: {
       if (bytes != sizeof(hipStream_t)) return fail(PFMM_ERR_INVALID_ARG, "stream is a hipStream_t");
@@ -722,7 +811,6 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       if (v == PFMM_M2L_SPECTRAL) {
         if (pl->p != 4 && pl->p != 6 && pl->p != 8)
           return fail(PFMM_ERR_UNSUPPORTED, "the spectral interaction zones need p = 4, 6 or 8");
-        if (!pl->g0.empty()) return fail(PFMM_ERR_UNSUPPORTED, "plan has learned tables");
         if (!pl->mspec) {
           M2LSpectral* f = nullptr;
           hipError_t e = m2l_spectral_create(pl->L, pl->p, &f);
@@ -787,7 +875,17 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "profile is an int32");
       int32_t v;
       std::memcpy(&v, value, sizeof v);
-      pl->profile = v != 0;
+      if (v < 0 || v > 2) return fail(PFMM_ERR_INVALID_ARG, "profile must be 0, 1 or 2");
+      if (v && pl->ev.empty()) {  // the ring of timing events, on first use
+        pl->ev.assign((size_t)kSlots * 2 * kMaxIntervals, nullptr);
+        for (auto& ev : pl->ev) {
+          const hipError_t e = hipEventCreate(&ev);
+          if (e != hipSuccess) return hip_fail(e, "timing events");
+        }
+        pl->ev_tag.assign((size_t)kSlots * kMaxIntervals, 0);
+        pl->ev_used.assign(kSlots, 0);
+      }
+      pl->profile = v;
       pl->nprof = 0;
       return PFMM_OK;
     }
@@ -796,34 +894,76 @@ pfmm_status pfmm_plan_set(pfmm_plan_t pl, int option, const void* value, size_t 
   }
 }
 
-pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* accel) {
-  g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
-  if (!rho || !phi) return fail(PFMM_ERR_INVALID_ARG, "density and potential are required");
-  if ((const void*)rho == (const void*)phi || (const void*)rho == (const void*)accel ||
-      (accel && (void*)accel == (void*)phi))
+}  // extern "C"
+
+namespace {
+
+// Records a start and an end event around each timed launch group of one
+// solve, into the plan's ring slot; the tag holds the stage, the tree level
+// and the part (kernel) within the stage.
+struct SolveTimer final : KernelTimer {
+  bool on = false;
+  hipEvent_t* ev = nullptr;
+  int* tag = nullptr;
+  int n = 0, stage = 0, level = 0;
+  void at(int st, int lv) {
+    stage = st;
+    level = lv;
+  }
+  hipError_t begin(hipStream_t s) override {
+    if (!on || n >= kMaxIntervals) return hipSuccess;
+    return hipEventRecord(ev[2 * n], s);
+  }
+  hipError_t end(hipStream_t s, int part) override {
+    if (!on || n >= kMaxIntervals) return hipSuccess;
+    tag[n] = stage | level << 8 | part << 16;
+    const hipError_t e = hipEventRecord(ev[2 * n + 1], s);
+    ++n;
+    return e;
+  }
+};
+
+// The whole solve (see pfmm_solve).  io64: density, potential and accel are
+// doubles (pfmm_solve_f64, PFMM_PREC_FP64 plans only), else floats.
+pfmm_status solve_impl(pfmm_plan_s* pl, const void* rho_in, void* phi_out, void* accel_out,
+                       int io64 = 0) {
+  if (!rho_in || !phi_out) return fail(PFMM_ERR_INVALID_ARG, "density and potential are required");
+  if (rho_in == (const void*)phi_out || rho_in == (const void*)accel_out ||
+      (accel_out && accel_out == phi_out))
     return fail(PFMM_ERR_INVALID_ARG, "buffers must not alias");
-  if (pl->near_fft && (((uintptr_t)rho | (uintptr_t)phi | (uintptr_t)accel) & 15))
+  const bool f64 = pl->prec == PFMM_PREC_FP64;
+  if (io64 && !f64) return fail(PFMM_ERR_INVALID_ARG, "FP64 buffers need a PFMM_PREC_FP64 plan");
+  // FP64 precision sums the near zone directly in FP64, whatever PFMM_OPT_NEAR says
+  const bool near_fft = pl->near_fft && !f64;
+  if (near_fft && (((uintptr_t)rho_in | (uintptr_t)phi_out | (uintptr_t)accel_out) & 15))
     return fail(PFMM_ERR_INVALID_ARG, "the FFT near zone needs 16-byte aligned density and outputs");
+  const float* rho = static_cast<const float*>(rho_in);
+  float* phi = static_cast<float*>(phi_out);
+  float* accel = static_cast<float*>(accel_out);
   const int N = pl->N, L = pl->L, p = pl->p, s = pl->s;
+  const size_t n3 = (size_t)N * N * N;
+  // component c of the accelerations, in the caller's type
+  auto acc_c = [&](int c) -> void* {
+    return io64 ? (void*)(static_cast<double*>(accel_out) + c * n3) : (void*)(accel + c * n3);
+  };
   const double h3 = 1.0 / ((double)N * N * N);
   hipStream_t st = pl->stream;
   hipError_t e;
-  int nev = 0;
   const int slot = pl->nprof % kSlots;
-  hipEvent_t* ev = pl->ev.data() + slot * kMaxEvents;
-  int* tag = pl->ev_tag.data() + slot * kMaxEvents;
-  // record the end of a stage's launch (profiling only); the tag holds the
-  // stage and the tree level of per-level stages
-  auto mark = [&](int stage, int level = 0) -> hipError_t {
-    if (!pl->profile || nev + 1 >= kMaxEvents) return hipSuccess;
-    tag[nev] = stage | (level << 8);
-    return hipEventRecord(ev[++nev], st);
-  };
-  if (pl->profile) {
-    e = hipEventRecord(ev[0], st);
-    if (e != hipSuccess) return hip_fail(e, "event");
+  SolveTimer tm;
+  tm.on = pl->profile != 0;
+  if (tm.on) {
+    tm.ev = pl->ev.data() + (size_t)slot * 2 * kMaxIntervals;
+    tm.tag = pl->ev_tag.data() + (size_t)slot * kMaxIntervals;
   }
+  // one stage's launches as one timed interval (profiling only)
+  auto timed = [&](int stage, int level, hipStream_t s, auto&& launch) -> hipError_t {
+    tm.at(stage, level);
+    hipError_t r = tm.begin(s);
+    if (r == hipSuccess) r = launch();
+    if (r == hipSuccess) r = tm.end(s, 0);
+    return r;
+  };
 
   const Weights A = wts(pl->dA, pl->dA64), T = wts(pl->dT, pl->dT64);
   auto is64 = [&](int l) { return (int)level64(pl, l); };
@@ -833,9 +973,9 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     ToepArgs ta = ta0;
     if (pl->m2l_fft)  // the FFT-convolution comparator, in the level's precision
       return m2l_fft_level(pl->fft, l, ta.X, ta.Y, ta.fp64, ta.accumulate, st);
-    if (pl->m2l_spectral)  // spectral stencils, FP64 throughout
+    if (pl->m2l_spectral)  // spectral stencils, FP64 throughout; each kernel timed
       return m2l_spectral_level(pl->mspec, l, ta.X, ta.fp64, ta.Y, ta.fp64, ta.accumulate, ta.offs,
-                                ta.noff, ta.isolated, st);
+                                ta.noff, ta.isolated, st, tm.on ? &tm : nullptr);
     if (ta.fp64 && ta.q == 8 && ta.C >= 31) {  // FP64 coarse level on the matrix cores
       ToepF64Args fa{};
       fa.n = ta.n;
@@ -879,8 +1019,8 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   };
 
   // near zone (reads only the density): writes phi; on the side stream, so
-  // that it runs beside the tree, unless stages are being timed
-  const bool overlap = !pl->profile;
+  // that it runs beside the tree, unless stages are timed one after another
+  const bool overlap = pl->profile != 1;
   hipStream_t sn = overlap ? pl->side : st;
   if (overlap) {
     e = hipEventRecord(pl->ev_fork, st);
@@ -893,24 +1033,28 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   nb.n = N / pl->qn;
   nb.noff = (int)cube(3 * pl->mn);
   nb.offs = pl->offs_near;
-  nb.tab = pl->ntab32;
+  nb.fp64 = f64;
+  nb.mesh64 = io64;
+  nb.tab = f64 ? (const void*)pl->ntab64 : (const void*)pl->ntab32;
   nb.C = 2 * s - 1;
-  nb.X = rho;
-  nb.Y = phi;
+  nb.X = rho_in;
+  nb.Y = phi_out;
   nb.grid_in = 1;
   nb.grid_out = 1;
   nb.xscale = 1.0 / ((double)N * N * N);
   nb.accumulate = 0;
   nb.groups = 1;
   nb.isolated = pl->isolated;
-  if (pl->near_fft) {
+  tm.at(PFMM_STAGE_NEAR, 0);
+  if (near_fft) {  // each of its kernels timed
     float* outs[4] = {phi, nullptr, nullptr, nullptr};
     int nout = 1;
     if (accel && pl->accel_mode)
       for (int c = 0; c < 3; ++c) outs[nout++] = accel + (size_t)c * N * N * N;
-    e = near_fft_run(pl->nfft, rho, outs, nout, pl->isolated, sn);
+    e = near_fft_run(pl->nfft, rho, outs, nout, pl->isolated, sn, tm.on ? &tm : nullptr);
   } else if (mx && pl->nwin) {
-    e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xsn, sn);
+    e = tm.begin(sn);
+    if (e == hipSuccess) e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xsn, sn);
     if (e == hipSuccess) {
       ToepMfmaArgs ma{};
       ma.n = nb.n;
@@ -934,24 +1078,30 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
         e = launch_toep8_split(ma, kNearTerms, sn);
       }
     }
+    if (e == hipSuccess) e = tm.end(sn, 0);
   } else {
-    e = launch_toeplitz(nb, sn);
+    e = tm.begin(sn);
+    if (e == hipSuccess) e = launch_toeplitz(nb, sn);
     for (int c = 0; c < 3 && e == hipSuccess && accel && pl->accel_mode; ++c) {
-      nb.tab = pl->ndtab32[c];
-      nb.Y = accel + (size_t)c * N * N * N;
+      nb.tab = f64 ? (const void*)pl->ndtab64[c] : (const void*)pl->ndtab32[c];
+      nb.Y = acc_c(c);
       e = launch_toeplitz(nb, sn);
     }
+    if (e == hipSuccess) e = tm.end(sn, 0);
   }
-  if (e == hipSuccess) e = overlap ? hipEventRecord(pl->ev_join, pl->side) : mark(PFMM_STAGE_NEAR);
+  if (e == hipSuccess && overlap) e = hipEventRecord(pl->ev_join, pl->side);
   if (e != hipSuccess) return hip_fail(e, "near zone");
 
   // upward pass
-  e = launch_p2m(rho, pl->M[L], is64(L), A, N, s, p, (double)h3, st);
-  if (e == hipSuccess) e = mark(PFMM_STAGE_P2M);
+  e = timed(PFMM_STAGE_P2M, 0, st, [&] {
+    return io64 ? launch_p2m_f64in(static_cast<const double*>(rho_in), pl->M[L], A, N, s, p, h3, st)
+                : launch_p2m(rho, pl->M[L], is64(L), A, N, s, p, (double)h3, st);
+  });
   if (e != hipSuccess) return hip_fail(e, "P2M");
   for (int l = L - 1; l >= 2; --l) {
-    e = launch_m2m(pl->M[l + 1], is64(l + 1), pl->M[l], is64(l), T, 1 << l, p, st);
-    if (e == hipSuccess) e = mark(PFMM_STAGE_M2M, l);
+    e = timed(PFMM_STAGE_M2M, l, st, [&] {
+      return launch_m2m(pl->M[l + 1], is64(l + 1), pl->M[l], is64(l), T, 1 << l, p, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "M2M");
   }
 
@@ -970,12 +1120,20 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
   a.X = pl->M[2];
   a.Y = pl->P[2];
   a.accumulate = 0;
-  e = m2l(a, 2);
-  if (e == hipSuccess) e = mark(PFMM_STAGE_M2L, 2);
+  // the spectral zones time each of their kernels themselves
+  auto m2l_timed = [&](const ToepArgs& ta, int l) -> hipError_t {
+    if (pl->m2l_spectral && !pl->m2l_fft) {
+      tm.at(PFMM_STAGE_M2L, l);
+      return m2l(ta, l);
+    }
+    return timed(PFMM_STAGE_M2L, l, st, [&] { return m2l(ta, l); });
+  };
+  e = m2l_timed(a, 2);
   if (e != hipSuccess) return hip_fail(e, "M2L level 2");
   for (int l = 3; l <= L; ++l) {
-    e = launch_l2l(pl->P[l - 1], is64(l - 1), pl->P[l], is64(l), T, 1 << (l - 1), p, st);
-    if (e == hipSuccess) e = mark(PFMM_STAGE_L2L, l);
+    e = timed(PFMM_STAGE_L2L, l, st, [&] {
+      return launch_l2l(pl->P[l - 1], is64(l - 1), pl->P[l], is64(l), T, 1 << (l - 1), p, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "L2L");
     a.n = 1 << l;
     a.m = 2;
@@ -986,8 +1144,7 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     a.X = pl->M[l];
     a.Y = pl->P[l];
     a.accumulate = 1;
-    e = m2l(a, l);
-    if (e == hipSuccess) e = mark(PFMM_STAGE_M2L, l);
+    e = m2l_timed(a, l);
     if (e != hipSuccess) return hip_fail(e, "M2L");
   }
 
@@ -996,31 +1153,66 @@ pfmm_status pfmm_solve(pfmm_plan_t pl, const float* rho, float* phi, float* acce
     e = hipStreamWaitEvent(st, pl->ev_join, 0);
     if (e != hipSuccess) return hip_fail(e, "join");
   }
-  e = launch_l2p(pl->P[L], is64(L), phi, A, N, s, p, st, 1);
-  if (e == hipSuccess) e = mark(PFMM_STAGE_L2P);
+  e = timed(PFMM_STAGE_L2P, 0, st, [&] {
+    return io64 ? launch_l2p_f64out(pl->P[L], static_cast<double*>(phi_out), A, N, s, p, st, 1)
+                : launch_l2p(pl->P[L], is64(L), phi, A, N, s, p, st, 1);
+  });
   if (e != hipSuccess) return hip_fail(e, "L2P");
 
   if (accel && pl->accel_mode) {
     // far part: gradient of the leaf's local expansion, -d/dx = -(1/eta_L) d/dv
-    e = launch_l2p_grad(pl->P[L], is64(L), accel, A, wts(pl->dAd, pl->dAd64),
-                        -(double)(1 << L) * p, N, s, p, st);
-    if (e == hipSuccess) e = mark(PFMM_STAGE_FD4);
+    const Weights Ad = wts(pl->dAd, pl->dAd64);
+    const double sc = -(double)(1 << L) * p;
+    e = timed(PFMM_STAGE_FD4, 0, st, [&] {
+      return io64 ? launch_l2p_grad_f64out(pl->P[L], static_cast<double*>(accel_out), A, Ad, sc, N, s,
+                                           p, st)
+                  : launch_l2p_grad(pl->P[L], is64(L), accel, A, Ad, sc, N, s, p, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "expansion gradient");
   } else if (accel) {
-    e = launch_fd4(phi, accel, N, st);
-    if (e == hipSuccess) e = mark(PFMM_STAGE_FD4);
+    e = timed(PFMM_STAGE_FD4, 0, st, [&] {
+      return io64 ? launch_fd4_f64(static_cast<const double*>(phi_out), static_cast<double*>(accel_out),
+                                   N, st)
+                  : launch_fd4(phi, accel, N, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "FD4");
   }
   if (pl->profile) {
-    pl->ev_used[slot] = nev;
+    pl->ev_used[slot] = tm.n;
     ++pl->nprof;
   }
   return PFMM_OK;
 }
 
-pfmm_status pfmm_plan_read(pfmm_plan_t pl, int buffer, int level, void* dst) {
+// A learned-G plan without weights solves with its G_S1 tables: say so.
+pfmm_status note_fallback(const pfmm_plan_s* pl, pfmm_status st) {
+  if (st == PFMM_OK && pl->learned_kind && !pl->learned)
+    g_err = "PFMM_GREEN_LEARNED: no network weights set, solved with the G_S1 fallback";
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+pfmm_status pfmm_solve(pfmm_plan_t h, const float* rho, float* phi, float* accel) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  return note_fallback(pl, solve_impl(pl, rho, phi, accel, 0));
+}
+
+pfmm_status pfmm_solve_f64(pfmm_plan_t h, const double* rho, double* phi, double* accel) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  return note_fallback(pl, solve_impl(pl, rho, phi, accel, 1));
+}
+
+pfmm_status pfmm_plan_read(pfmm_plan_t h, int buffer, int level, void* dst) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
   if (!dst) return fail(PFMM_ERR_INVALID_ARG, "dst is NULL");
   const void* src = nullptr;
   size_t bytes = 0;
@@ -1055,75 +1247,109 @@ pfmm_status pfmm_plan_read(pfmm_plan_t pl, int buffer, int level, void* dst) {
   return PFMM_OK;
 }
 
-pfmm_status pfmm_plan_stage_times(pfmm_plan_t pl, double* ms, int* launches) {
-  g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
-  if (!ms) return fail(PFMM_ERR_INVALID_ARG, "ms is NULL");
+}  // extern "C"
+
+namespace {
+
+// Visit every timed interval of the recent profiled solves (newest first):
+// f(solve index, interval index within the solve, tag, ms).  Waits for them.
+template <class F>
+pfmm_status each_interval(pfmm_plan_s* pl, F f) {
   if (pl->nprof == 0) return fail(PFMM_ERR_INVALID_ARG, "no profiled solve");
+  const int nsol = pl->nprof < kSlots ? pl->nprof : kSlots;
+  for (int j = 0; j < nsol; ++j) {
+    const int slot = (pl->nprof - 1 - j) % kSlots;
+    const hipEvent_t* ev = pl->ev.data() + (size_t)slot * 2 * kMaxIntervals;
+    const int* tag = pl->ev_tag.data() + (size_t)slot * kMaxIntervals;
+    for (int k = 0; k < pl->ev_used[slot]; ++k) {
+      hipError_t e = hipEventSynchronize(ev[2 * k + 1]);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
+      if (e != hipSuccess) return hip_fail(e, "profile events");
+      f(j, k, tag[k], (double)t);
+    }
+  }
+  return PFMM_OK;
+}
+
+int solves_kept(const pfmm_plan_s* pl) { return pl->nprof < kSlots ? pl->nprof : kSlots; }
+
+}  // namespace
+
+extern "C" {
+
+pfmm_status pfmm_plan_stage_times(pfmm_plan_t h, double* ms, int* launches) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_plan_stage_times");
+  if (!ms) return fail(PFMM_ERR_INVALID_ARG, "ms is NULL");
   for (int k = 0; k < PFMM_STAGE_COUNT; ++k) {
     ms[k] = 0.0;
     if (launches) launches[k] = 0;
   }
-  const int nsol = pl->nprof < kSlots ? pl->nprof : kSlots;
-  for (int j = 0; j < nsol; ++j) {
-    const int slot = (pl->nprof - 1 - j) % kSlots;
-    hipEvent_t* ev = pl->ev.data() + slot * kMaxEvents;
-    const int* tag = pl->ev_tag.data() + slot * kMaxEvents;
-    hipError_t e = hipEventSynchronize(ev[pl->ev_used[slot]]);
-    if (e != hipSuccess) return hip_fail(e, "stage times");
-    for (int k = 0; k < pl->ev_used[slot]; ++k) {
-      float t = 0.f;
-      e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-      if (e != hipSuccess) return hip_fail(e, "stage times");
-      ms[tag[k] & 255] += t / nsol;
-      if (launches && j == 0) launches[tag[k] & 255] += 1;
-    }
-  }
-  return PFMM_OK;
+  const double w = pl->nprof ? 1.0 / solves_kept(pl) : 0.0;
+  return each_interval(pl, [&](int j, int, int tag, double t) {
+    const int stg = tag & 255;
+    if (stg >= PFMM_STAGE_COUNT) return;
+    ms[stg] += t * w;
+    if (launches && j == 0) launches[stg] += 1;
+  });
 }
 
-pfmm_status pfmm_plan_level_times(pfmm_plan_t pl, int stage, double* ms) {
+pfmm_status pfmm_plan_level_times(pfmm_plan_t h, int stage, double* ms) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_plan_level_times");
   if (!ms) return fail(PFMM_ERR_INVALID_ARG, "ms is NULL");
   if (stage != PFMM_STAGE_M2M && stage != PFMM_STAGE_M2L && stage != PFMM_STAGE_L2L)
     return fail(PFMM_ERR_INVALID_ARG, "stage has no per-level launches");
-  if (pl->nprof == 0) return fail(PFMM_ERR_INVALID_ARG, "no profiled solve");
   for (int l = 0; l <= pl->L; ++l) ms[l] = 0.0;
-  const int nsol = pl->nprof < kSlots ? pl->nprof : kSlots;
-  for (int j = 0; j < nsol; ++j) {
-    const int slot = (pl->nprof - 1 - j) % kSlots;
-    hipEvent_t* ev = pl->ev.data() + slot * kMaxEvents;
-    const int* tag = pl->ev_tag.data() + slot * kMaxEvents;
-    hipError_t e = hipEventSynchronize(ev[pl->ev_used[slot]]);
-    if (e != hipSuccess) return hip_fail(e, "level times");
-    for (int k = 0; k < pl->ev_used[slot]; ++k) {
-      if ((tag[k] & 255) != stage) continue;
-      float t = 0.f;
-      e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
-      if (e != hipSuccess) return hip_fail(e, "level times");
-      const int l = tag[k] >> 8;
-      if (l >= 0 && l <= pl->L) ms[l] += t / nsol;
-    }
-  }
-  return PFMM_OK;
+  const double w = pl->nprof ? 1.0 / solves_kept(pl) : 0.0;
+  return each_interval(pl, [&](int, int, int tag, double t) {
+    const int l = (tag >> 8) & 255;
+    if ((tag & 255) == stage && l <= pl->L) ms[l] += t * w;
+  });
 }
 
-pfmm_status pfmm_plan_info(pfmm_plan_t pl, int* s, int64_t* table_entries) {
+pfmm_status pfmm_plan_kernel_times(pfmm_plan_t h, int stage, int level, double* ms, int* count) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_plan_kernel_times");
+  if (!ms || !count) return fail(PFMM_ERR_INVALID_ARG, "ms and count are required");
+  if (stage < 0 || stage >= PFMM_STAGE_COUNT) return fail(PFMM_ERR_INVALID_ARG, "unknown stage");
+  for (int k = 0; k < 8; ++k) ms[k] = 0.0;
+  *count = 0;
+  const double w = pl->nprof ? 1.0 / solves_kept(pl) : 0.0;
+  return each_interval(pl, [&](int, int, int tag, double t) {
+    const int part = (tag >> 16) & 255;
+    if ((tag & 255) != stage || ((tag >> 8) & 255) != level || part >= 8) return;
+    ms[part] += t * w;
+    if (part + 1 > *count) *count = part + 1;
+  });
+}
+
+pfmm_status pfmm_plan_info(pfmm_plan_t h, int* s, int64_t* table_entries) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
   if (s) *s = pl->s;
   if (table_entries) *table_entries = cube(8 * pl->p - 1);
   return PFMM_OK;
 }
 
-pfmm_status pfmm_plan_destroy(pfmm_plan_t pl) {
+pfmm_status pfmm_plan_destroy(pfmm_plan_t h) {
   g_err.clear();
-  if (!pl) return PFMM_OK;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_live.erase(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
-  }
+  if (!h) return PFMM_OK;
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_plan_destroy");
+  drop_cached_batches(pl);
+  if (pl->batch_refs > 0)
+    return fail(PFMM_ERR_INVALID_ARG, "the plan is bound to a live batch: destroy the batch first");
+  if (!g_plans.remove(h)) return bad_plan();
   hipError_t e = hipStreamSynchronize(pl->stream);
   release(pl);
   if (e != hipSuccess) return hip_fail(e, "destroy");
@@ -1139,6 +1365,8 @@ const char* pfmm_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 struct pfmm_batch_s {
   std::vector<pfmm_plan_s*> plans;
+  std::vector<pfmm_plan_t> handles;  // the plans' handles (checked live before every launch)
+  bool cached = false;               // made by pfmm_solve_batch, owned by its cache
   std::vector<const float*> rho;
   std::vector<float*> phi;
   hipStream_t caller = nullptr;  // stream of plans[0]; solves are ordered with it
@@ -1148,6 +1376,12 @@ struct pfmm_batch_s {
   // outputs are disjoint): two more streams, forked and joined by events
   hipStream_t s_split = nullptr, s_f64 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_split = nullptr, ev_f64 = nullptr;
+  // fields whose every contraction is one of their plan's own transform
+  // kernels (FFT near zone, spectral zones) need no work list: each runs its
+  // whole solve as one chain, the chains spread over kChains forked streams
+  static constexpr int kChains = 4;
+  hipStream_t s_chain[kChains] = {};
+  hipEvent_t ev_chain[kChains] = {};
   BatchItem* items = nullptr;  // device work list (portable kernel)
   unsigned* counter = nullptr;  // [0] portable, [1] split, [2] FP64 matrix-core list
   int nitems = 0, grid = 0;
@@ -1172,15 +1406,24 @@ struct pfmm_batch_s {
 
 namespace {
 
-std::mutex g_bmu;
-std::set<pfmm_batch_s*> g_blive;
+Registry<pfmm_batch_s, 0x71> g_batches;
 
-bool blive(pfmm_batch_s* b) {
-  std::lock_guard<std::mutex> lk(g_bmu);
-  return b && g_blive.count(b);
-}
+pfmm_batch_s* batch_of(pfmm_batch_t h) { return g_batches.get(h); }
+pfmm_status bad_batch() { return fail(PFMM_ERR_BAD_HANDLE, "not a live batch handle"); }
+
+// Batches made by pfmm_solve_batch, one per set of (plan, density,
+// potential), reused while that set is solved again.
+struct CachedBatch {
+  std::vector<pfmm_plan_t> plans;
+  std::vector<const float*> rho;
+  std::vector<float*> phi;
+  pfmm_batch_t handle;
+};
+std::mutex g_cmu;
+std::vector<CachedBatch> g_cache;
 
 void brelease(pfmm_batch_s* b) {
+  for (pfmm_plan_s* pl : b->plans) --pl->batch_refs;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->items) (void)hipFree(b->items);
@@ -1198,6 +1441,13 @@ void brelease(pfmm_batch_s* b) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
+  for (int c = 0; c < pfmm_batch_s::kChains; ++c) {
+    if (b->ev_chain[c]) (void)hipEventDestroy(b->ev_chain[c]);
+    if (b->s_chain[c]) {
+      (void)hipStreamSynchronize(b->s_chain[c]);
+      (void)hipStreamDestroy(b->s_chain[c]);
+    }
+  }
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
@@ -1209,6 +1459,10 @@ bool batch_split_near(const pfmm_plan_s* pl) {
   return !pl->near_fft && pl->prec == PFMM_PREC_BF16X3 && pl->nwin;
 }
 bool batch_f64_level(const pfmm_plan_s* pl, int l) { return level64(pl, l) && pl->p == 8; }
+// A field solved as one chain of its own kernels (no work items).
+bool batch_chain(const pfmm_plan_s* pl) {
+  return pl->near_fft && pl->m2l_spectral && near_fft_fused(pl->nfft);
+}
 
 // Tuning group of a portable item: block edge, FP64 or FP32, near zone or
 // interaction zone (in the terms of the method: p or the leaf width s, and the
@@ -1369,12 +1623,55 @@ hipError_t batch_upload(pfmm_batch_s* b, const std::map<std::string, int>& width
 // The whole batch solve, enqueued on the batch stream.  `part`: 0 = all,
 // 1 = upward passes only, 2 = the persistent contractions only, 3 = downward,
 // 4 = the portable persistent kernel only.
+// One chain field's whole solve on stream `st`, in the order of a single
+// solve: near zone (writes the potential), upward pass, level 2, then per
+// level L2L and the zones, and L2P added to the potential.
+hipError_t batch_chain_solve(pfmm_batch_s* b, size_t f, hipStream_t st) {
+  pfmm_plan_s* pl = b->plans[f];
+  const Weights T = wts(pl->dT, pl->dT64);
+  float* out[1] = {b->phi[f]};
+  hipError_t e = near_fft_run(pl->nfft, b->rho[f], out, 1, 0, st);
+  if (e == hipSuccess)
+    e = launch_p2m(b->rho[f], pl->M[pl->L], level64(pl, pl->L), wts(pl->dA, pl->dA64), pl->N, pl->s,
+                   pl->p, 1.0 / ((double)pl->N * pl->N * pl->N), st);
+  for (int l = pl->L - 1; l >= 2 && e == hipSuccess; --l)
+    e = launch_m2m(pl->M[l + 1], level64(pl, l + 1), pl->M[l], level64(pl, l), T, 1 << l, pl->p, st);
+  for (int l = 2; l <= pl->L && e == hipSuccess; ++l) {
+    if (l > 2)
+      e = launch_l2l(pl->P[l - 1], level64(pl, l - 1), pl->P[l], level64(pl, l), T, 1 << (l - 1),
+                     pl->p, st);
+    if (e == hipSuccess)
+      e = m2l_spectral_level(pl->mspec, l, pl->M[l], level64(pl, l), pl->P[l], level64(pl, l), l > 2,
+                             l == 2 ? pl->offs_l2 : pl->offs_iz, l == 2 ? pl->nl2 : 189, 0, st);
+  }
+  if (e == hipSuccess)
+    e = launch_l2p(pl->P[pl->L], level64(pl, pl->L), b->phi[f], wts(pl->dA, pl->dA64), pl->N, pl->s,
+                   pl->p, st, 1);
+  return e;
+}
+
 hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
   hipStream_t st = b->stream;
   hipError_t e = hipSuccess;
-  if (part == 0 || part == 1) {
+  if (part == 0) {  // chain fields, spread over the forked chain streams
+    bool any = false;
+    for (pfmm_plan_s* pl : b->plans) any = any || batch_chain(pl);
+    if (any) {
+      e = hipEventRecord(b->ev_fork, st);
+      for (int c = 0; c < pfmm_batch_s::kChains && e == hipSuccess; ++c)
+        e = hipStreamWaitEvent(b->s_chain[c], b->ev_fork, 0);
+      int next = 0;
+      for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f)
+        if (batch_chain(b->plans[f])) {
+          e = batch_chain_solve(b, f, b->s_chain[next]);
+          next = (next + 1) % pfmm_batch_s::kChains;
+        }
+    }
+  }
+  if (e == hipSuccess && (part == 0 || part == 1)) {
     for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
       pfmm_plan_s* pl = b->plans[f];
+      if (batch_chain(pl)) continue;
       const Weights T = wts(pl->dT, pl->dT64);
       e = launch_p2m(b->rho[f], pl->M[pl->L], level64(pl, pl->L), wts(pl->dA, pl->dA64), pl->N,
                      pl->s, pl->p, 1.0 / ((double)pl->N * pl->N * pl->N), st);
@@ -1403,6 +1700,7 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
     // before the downward passes add to them
     for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
       pfmm_plan_s* pl = b->plans[f];
+      if (batch_chain(pl)) continue;
       if (pl->near_fft) {
         float* out[1] = {b->phi[f]};
         e = near_fft_run(pl->nfft, b->rho[f], out, 1, 0, st);
@@ -1422,6 +1720,7 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
   if (e == hipSuccess && (part == 0 || part == 3)) {
     for (size_t f = 0; f < b->plans.size() && e == hipSuccess; ++f) {
       pfmm_plan_s* pl = b->plans[f];
+      if (batch_chain(pl)) continue;
       const Weights T = wts(pl->dT, pl->dT64);
       for (int l = 3; l <= pl->L && e == hipSuccess; ++l)
         e = launch_l2l(pl->P[l - 1], level64(pl, l - 1), pl->P[l], level64(pl, l), T,
@@ -1429,6 +1728,14 @@ hipError_t batch_enqueue(pfmm_batch_s* b, int part) {
       if (e == hipSuccess)
         e = launch_l2p(pl->P[pl->L], level64(pl, pl->L), b->phi[f], wts(pl->dA, pl->dA64),
                        pl->N, pl->s, pl->p, st, 1);
+    }
+  }
+  if (e == hipSuccess && part == 0) {  // join the chains
+    bool any = false;
+    for (pfmm_plan_s* pl : b->plans) any = any || batch_chain(pl);
+    for (int c = 0; c < pfmm_batch_s::kChains && e == hipSuccess && any; ++c) {
+      e = hipEventRecord(b->ev_chain[c], b->s_chain[c]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_chain[c], 0);
     }
   }
   return e;
@@ -1476,19 +1783,30 @@ void cache_store(const char* path, const std::string& key, int tpt) {
 
 extern "C" {
 
-pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* const* density,
-                              float* const* potential, pfmm_batch_t* out) {
-  g_err.clear();
+}  // extern "C"
+
+namespace {
+
+pfmm_status batch_create_impl(int n, const pfmm_plan_t* handles, const float* const* density,
+                              float* const* potential, bool cached, pfmm_batch_t* out) {
   if (!out) return fail(PFMM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (n < 1 || n > 4096 || !plans || !density || !potential)
+  if (n < 1 || n > 4096 || !handles || !density || !potential)
     return fail(PFMM_ERR_INVALID_ARG, "need 1 <= n <= 4096 and non-NULL arrays");
+  std::vector<pfmm_plan_s*> plans(n);
+  for (int i = 0; i < n; ++i) {
+    plans[i] = plan_of(handles[i]);
+    if (!plans[i]) return bad_plan();
+    if (!density[i] || !potential[i]) return fail(PFMM_ERR_INVALID_ARG, "NULL buffer in batch");
+  }
+  if (capturing(plans[0]->stream)) return capture_fail("creating a batch");
   pfmm_batch_s* b = new (std::nothrow) pfmm_batch_s;
   if (!b) return fail(PFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->cached = cached;
   for (int i = 0; i < n; ++i) {
-    if (!live(plans[i]) || !density[i] || !potential[i]) {
+    if (plans[i]->prec == PFMM_PREC_FP64) {
       delete b;
-      return fail(PFMM_ERR_INVALID_ARG, "invalid plan or NULL buffer in batch");
+      return fail(PFMM_ERR_UNSUPPORTED, "batches of PFMM_PREC_FP64 plans");
     }
     if (plans[i]->p > 8) {
       delete b;
@@ -1517,9 +1835,12 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
         return fail(PFMM_ERR_INVALID_ARG, "a plan appears twice in a batch");
       }
     b->plans.push_back(plans[i]);
+    b->handles.push_back(handles[i]);
     b->rho.push_back(density[i]);
     b->phi.push_back(potential[i]);
   }
+  // from here on the plans know the batch holds them (brelease undoes this)
+  for (pfmm_plan_s* pl : b->plans) ++pl->batch_refs;
   b->caller = plans[0]->stream;
   // default priority (no priority streams anywhere in this library)
   hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
@@ -1529,6 +1850,10 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->s_f64, hipStreamNonBlocking);
   for (hipEvent_t* ev : {&b->ev_fork, &b->ev_split, &b->ev_f64})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  for (int c = 0; c < pfmm_batch_s::kChains && e == hipSuccess; ++c) {
+    e = hipStreamCreateWithFlags(&b->s_chain[c], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_chain[c], hipEventDisableTiming);
+  }
   // inputs written on the caller's stream must be visible to the tuning runs
   if (e == hipSuccess) e = hipStreamSynchronize(b->caller);
   if (e == hipSuccess) e = hipMalloc(&b->counter, 3 * sizeof(unsigned));
@@ -1609,17 +1934,13 @@ pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* cons
     brelease(b);
     return hip_fail(e, "batch graph");
   }
-  {
-    std::lock_guard<std::mutex> lk(g_bmu);
-    g_blive.insert(b);
-  }
-  *out = b;
+  *out = static_cast<pfmm_batch_t>(g_batches.add(b));
   return PFMM_OK;
 }
 
-pfmm_status pfmm_batch_solve(pfmm_batch_t b) {
-  g_err.clear();
-  if (!blive(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
+pfmm_status batch_launch(pfmm_batch_s* b) {
+  for (pfmm_plan_t ph : b->handles)
+    if (!plan_of(ph)) return fail(PFMM_ERR_BAD_HANDLE, "a plan of the batch is no longer live");
   hipError_t e = hipEventRecord(b->ev_in, b->caller);
   if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_in, 0);
   if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
@@ -1629,17 +1950,98 @@ pfmm_status pfmm_batch_solve(pfmm_batch_t b) {
   return PFMM_OK;
 }
 
-pfmm_status pfmm_batch_info(pfmm_batch_t b, int* items, int* groups) {
+pfmm_status batch_destroy_impl(pfmm_batch_t h) {
+  pfmm_batch_s* b = g_batches.remove(h);
+  if (!b) return bad_batch();
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  brelease(b);
+  if (e != hipSuccess) return hip_fail(e, "batch destroy");
+  return PFMM_OK;
+}
+
+}  // namespace
+
+// Release the batches pfmm_solve_batch made for sets that hold `pl`.
+void drop_cached_batches(pfmm_plan_s* pl) {
+  std::vector<pfmm_batch_t> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cmu);
+    for (size_t i = 0; i < g_cache.size();) {
+      bool uses = false;
+      for (pfmm_plan_t ph : g_cache[i].plans) uses = uses || plan_of(ph) == pl;
+      if (uses) {
+        drop.push_back(g_cache[i].handle);
+        g_cache.erase(g_cache.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  for (pfmm_batch_t bh : drop) (void)batch_destroy_impl(bh);
+}
+
+extern "C" {
+
+pfmm_status pfmm_batch_create(int n, const pfmm_plan_t* plans, const float* const* density,
+                              float* const* potential, pfmm_batch_t* out) {
   g_err.clear();
-  if (!blive(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
+  return batch_create_impl(n, plans, density, potential, false, out);
+}
+
+pfmm_status pfmm_batch_solve(pfmm_batch_t h) {
+  g_err.clear();
+  pfmm_batch_s* b = batch_of(h);
+  if (!b || b->cached) return bad_batch();
+  return batch_launch(b);
+}
+
+pfmm_status pfmm_solve_batch(int n, const pfmm_plan_t* plans, const float* const* density,
+                             float* const* potential) {
+  g_err.clear();
+  if (n < 1 || n > 4096 || !plans || !density || !potential)
+    return fail(PFMM_ERR_INVALID_ARG, "need 1 <= n <= 4096 and non-NULL arrays");
+  pfmm_batch_t hit = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_cmu);
+    for (const CachedBatch& c : g_cache) {
+      if ((int)c.plans.size() != n) continue;
+      bool same = true;
+      for (int i = 0; i < n && same; ++i)
+        same = c.plans[i] == plans[i] && c.rho[i] == density[i] && c.phi[i] == potential[i];
+      if (same) {
+        hit = c.handle;
+        break;
+      }
+    }
+  }
+  if (!hit) {  // first solve of this set: build and capture its batch (plan time)
+    pfmm_status st = batch_create_impl(n, plans, density, potential, true, &hit);
+    if (st != PFMM_OK) return st;
+    CachedBatch c;
+    c.plans.assign(plans, plans + n);
+    c.rho.assign(density, density + n);
+    c.phi.assign(potential, potential + n);
+    c.handle = hit;
+    std::lock_guard<std::mutex> lk(g_cmu);
+    g_cache.push_back(std::move(c));
+  }
+  pfmm_batch_s* b = batch_of(hit);
+  if (!b) return bad_batch();
+  return batch_launch(b);
+}
+pfmm_status pfmm_batch_info(pfmm_batch_t h, int* items, int* groups) {
+  g_err.clear();
+  pfmm_batch_s* b = batch_of(h);
+  if (!b) return bad_batch();
   if (items) *items = b->nitems + b->nsplit + b->nf64;
   if (groups) *groups = (int)b->groups.size();
   return PFMM_OK;
 }
 
-pfmm_status pfmm_batch_group(pfmm_batch_t b, int group, int* desc, double* ms) {
+pfmm_status pfmm_batch_group(pfmm_batch_t h, int group, int* desc, double* ms) {
   g_err.clear();
-  if (!blive(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
+  pfmm_batch_s* b = batch_of(h);
+  if (!b) return bad_batch();
   if (group < 0 || group >= (int)b->groups.size())
     return fail(PFMM_ERR_INVALID_ARG, "group out of range");
   const auto& g = b->groups[group];
@@ -1654,17 +2056,13 @@ pfmm_status pfmm_batch_group(pfmm_batch_t b, int group, int* desc, double* ms) {
   return PFMM_OK;
 }
 
-pfmm_status pfmm_batch_destroy(pfmm_batch_t b) {
+pfmm_status pfmm_batch_destroy(pfmm_batch_t h) {
   g_err.clear();
-  if (!b) return PFMM_OK;
-  {
-    std::lock_guard<std::mutex> lk(g_bmu);
-    if (!g_blive.erase(b)) return fail(PFMM_ERR_INVALID_ARG, "invalid batch handle");
-  }
-  const hipError_t e = hipStreamSynchronize(b->stream);
-  brelease(b);
-  if (e != hipSuccess) return hip_fail(e, "batch destroy");
-  return PFMM_OK;
+  if (!h) return PFMM_OK;
+  pfmm_batch_s* b = batch_of(h);
+  if (!b || b->cached) return bad_batch();
+  if (capturing(b->caller)) return capture_fail("pfmm_batch_destroy");
+  return batch_destroy_impl(h);
 }
 
 }  // extern "C"
@@ -1776,6 +2174,8 @@ pfmm_status learned_apply(pfmm_plan_s* pl, int bf16) {
     if (e == hipSuccess && pl->win[l])
       e = make_windows(pl->tab64[l], C, kM2LTerms, pl->win[l], st);
   }
+  // the spectral zones' transformed kernels follow the corrected tables
+  if (e == hipSuccess && pl->mspec) e = m2l_spectral_tables(pl->mspec, pl->tab64, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "apply learned correction");
   return PFMM_OK;
@@ -1845,12 +2245,32 @@ pfmm_status direct_prepare(pfmm_plan_s* pl) {
 
 extern "C" {
 
-pfmm_status pfmm_plan_direct(pfmm_plan_t pl, const float* rho, float* phi) {
+}  // extern "C"
+
+namespace pfmm {
+int plan_direct_spec(const void* h, DirectSpec* out) {
+  pfmm_plan_s* pl = plan_of(static_cast<pfmm_plan_t>(const_cast<void*>(h)));
+  if (!pl) return bad_plan();
+  out->N = pl->N;
+  out->isolated = pl->isolated;
+  out->green = green_spec(pl);
+  out->stream = pl->stream;
+  return PFMM_OK;
+}
+int set_error(int status, const std::string& msg) { return fail((pfmm_status)status, msg); }
+void clear_error() { g_err.clear(); }
+}  // namespace pfmm
+
+extern "C" {
+
+pfmm_status pfmm_plan_direct(pfmm_plan_t h, const float* rho, float* phi) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "direct solve of an isolated plan");
   if (!rho || !phi || (const void*)rho == (const void*)phi)
     return fail(PFMM_ERR_INVALID_ARG, "density and potential must be distinct device arrays");
+  if (!pl->dtab64 && capturing(pl->stream)) return capture_fail("the first pfmm_plan_direct");
   pfmm_status s0 = direct_prepare(pl);
   if (s0 != PFMM_OK) return s0;
   ToepArgs a{};
@@ -1873,12 +2293,13 @@ pfmm_status pfmm_plan_direct(pfmm_plan_t pl, const float* rho, float* phi) {
   return PFMM_OK;
 }
 
-pfmm_status pfmm_learned_set(pfmm_plan_t pl, const float* weights, int bf16) {
+pfmm_status pfmm_learned_set(pfmm_plan_t h, const float* weights, int bf16) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_learned_set");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
-  if (pl->m2l_fft || pl->m2l_spectral)
-    return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT or spectral interaction zones");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
   if (!weights) {
     if (pl->g0.empty()) return PFMM_OK;  // never corrected
     pl->learned = 0;
@@ -1892,12 +2313,13 @@ pfmm_status pfmm_learned_set(pfmm_plan_t pl, const float* weights, int bf16) {
   return learned_apply(pl, bf16 ? 1 : 0);
 }
 
-pfmm_status pfmm_learned_train_begin(pfmm_plan_t pl, const float* weights, double lr) {
+pfmm_status pfmm_learned_train_begin(pfmm_plan_t h, const float* weights, double lr) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_learned_train_begin");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
-  if (pl->m2l_fft || pl->m2l_spectral)
-    return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT or spectral interaction zones");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
   if (!weights || !(lr > 0.0)) return fail(PFMM_ERR_INVALID_ARG, "need weights and lr > 0");
   pfmm_status s0 = learned_prepare(pl);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
@@ -1914,17 +2336,19 @@ pfmm_status pfmm_learned_train_begin(pfmm_plan_t pl, const float* weights, doubl
   return learned_apply(pl, 0);
 }
 
-pfmm_status pfmm_learned_accumulate(pfmm_plan_t pl, const float* rho, const float* target,
+pfmm_status pfmm_learned_accumulate(pfmm_plan_t h, const float* rho, const float* target,
                                     double* loss) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_learned_accumulate");
   if (pl->learned != 2 && pl->learned != 3)
     return fail(PFMM_ERR_INVALID_ARG, "call pfmm_learned_train_begin or pfmm_table_train_begin first");
   if (!rho || !target) return fail(PFMM_ERR_INVALID_ARG, "density and target are required");
   const int N = pl->N, L = pl->L, p = pl->p;
   const int64_t n3 = (int64_t)N * N * N;
   hipStream_t st = pl->stream;
-  pfmm_status s0 = pfmm_solve(pl, rho, pl->tphi, nullptr);
+  pfmm_status s0 = solve_impl(pl, rho, pl->tphi, nullptr);
   if (s0 != PFMM_OK) return s0;
   hipError_t e = residual(pl->tphi, target, n3, pl->rpart, pl->rstats, pl->resid, st);
   // adjoint sweep: transposes of L2P and L2L
@@ -1960,17 +2384,18 @@ pfmm_status pfmm_learned_accumulate(pfmm_plan_t pl, const float* rho, const floa
   return PFMM_OK;
 }
 
-pfmm_status pfmm_learned_loss(pfmm_plan_t pl, const float* rho, const float* target,
+pfmm_status pfmm_learned_loss(pfmm_plan_t h, const float* rho, const float* target,
                               double* loss) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_learned_loss");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
-  if (pl->m2l_fft || pl->m2l_spectral)
-    return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT or spectral interaction zones");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
   if (!rho || !target || !loss) return fail(PFMM_ERR_INVALID_ARG, "NULL argument");
   pfmm_status s0 = learned_prepare(pl);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
-  if (s0 == PFMM_OK) s0 = pfmm_solve(pl, rho, pl->tphi, nullptr);
+  if (s0 == PFMM_OK) s0 = solve_impl(pl, rho, pl->tphi, nullptr);
   if (s0 != PFMM_OK) return s0;
   const int64_t n3 = (int64_t)pl->N * pl->N * pl->N;
   double stats[3] = {0, 0, 0};
@@ -1983,9 +2408,11 @@ pfmm_status pfmm_learned_loss(pfmm_plan_t pl, const float* rho, const float* tar
   return PFMM_OK;
 }
 
-pfmm_status pfmm_learned_step(pfmm_plan_t pl) {
+pfmm_status pfmm_learned_step(pfmm_plan_t h) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_learned_step");
   if ((pl->learned != 2 && pl->learned != 3) || pl->accumulated == 0)
     return fail(PFMM_ERR_INVALID_ARG, "no accumulated gradient");
   const hipError_t e =
@@ -1999,25 +2426,28 @@ pfmm_status pfmm_learned_step(pfmm_plan_t pl) {
   return learned_apply(pl, 0);
 }
 
-pfmm_status pfmm_table_params(pfmm_plan_t pl, int* count) {
+pfmm_status pfmm_table_params(pfmm_plan_t h, int* count) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_table_params");
   if (!count) return fail(PFMM_ERR_INVALID_ARG, "count is NULL");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
-  if (pl->m2l_fft || pl->m2l_spectral)
-    return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT or spectral interaction zones");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
   const pfmm_status s0 = learned_prepare(pl);
   if (s0 != PFMM_OK) return s0;
   *count = (pl->L - 1) * pl->nu;
   return PFMM_OK;
 }
 
-pfmm_status pfmm_table_set(pfmm_plan_t pl, const float* delta) {
+pfmm_status pfmm_table_set(pfmm_plan_t h, const float* delta) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
-  if (!delta) return pfmm_learned_set(pl, nullptr, 0);
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_table_set");
+  if (!delta) return pfmm_learned_set(h, nullptr, 0);
   int n = 0;
-  pfmm_status s0 = pfmm_table_params(pl, &n);
+  pfmm_status s0 = pfmm_table_params(h, &n);
   if (s0 != PFMM_OK) return s0;
   const hipError_t e = hipMemcpy(pl->delta, delta, (size_t)n * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "upload table parameters");
@@ -2026,9 +2456,11 @@ pfmm_status pfmm_table_set(pfmm_plan_t pl, const float* delta) {
   return learned_apply(pl, 0);
 }
 
-pfmm_status pfmm_table_get(pfmm_plan_t pl, float* delta) {
+pfmm_status pfmm_table_get(pfmm_plan_t h, float* delta) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_table_get");
   if (!delta) return fail(PFMM_ERR_INVALID_ARG, "delta is NULL");
   if (pl->learned != 3) return fail(PFMM_ERR_INVALID_ARG, "the plan has no grid-valued tables");
   const hipError_t e = hipMemcpy(delta, pl->delta, (size_t)(pl->L - 1) * pl->nu * sizeof(float),
@@ -2037,9 +2469,11 @@ pfmm_status pfmm_table_get(pfmm_plan_t pl, float* delta) {
   return PFMM_OK;
 }
 
-pfmm_status pfmm_table_grad(pfmm_plan_t pl, float* grad) {
+pfmm_status pfmm_table_grad(pfmm_plan_t h, float* grad) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_table_grad");
   if (!grad) return fail(PFMM_ERR_INVALID_ARG, "grad is NULL");
   if (pl->learned != 3 || !pl->ggrad)
     return fail(PFMM_ERR_INVALID_ARG, "call pfmm_table_train_begin first");
@@ -2051,12 +2485,14 @@ pfmm_status pfmm_table_grad(pfmm_plan_t pl, float* grad) {
   return PFMM_OK;
 }
 
-pfmm_status pfmm_table_train_begin(pfmm_plan_t pl, double lr) {
+pfmm_status pfmm_table_train_begin(pfmm_plan_t h, double lr) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_table_train_begin");
   if (!(lr > 0.0)) return fail(PFMM_ERR_INVALID_ARG, "need lr > 0");
   int n = 0;
-  pfmm_status s0 = pfmm_table_params(pl, &n);
+  pfmm_status s0 = pfmm_table_params(h, &n);
   if (s0 == PFMM_OK) s0 = learned_train_alloc(pl);
   if (s0 != PFMM_OK) return s0;
   hipError_t e = hipSuccess;
@@ -2075,9 +2511,11 @@ pfmm_status pfmm_table_train_begin(pfmm_plan_t pl, double lr) {
   return learned_apply(pl, 0);
 }
 
-pfmm_status pfmm_learned_get(pfmm_plan_t pl, float* weights) {
+pfmm_status pfmm_learned_get(pfmm_plan_t h, float* weights) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_learned_get");
   if (!weights || !pl->learned) return fail(PFMM_ERR_INVALID_ARG, "no network on this plan");
   const hipError_t e =
       hipMemcpy(weights, pl->theta, kMlpParams * sizeof(float), hipMemcpyDeviceToHost);
@@ -2085,10 +2523,12 @@ pfmm_status pfmm_learned_get(pfmm_plan_t pl, float* weights) {
   return PFMM_OK;
 }
 
-pfmm_status pfmm_learned_read_grad(pfmm_plan_t pl, int level, double* table_grad,
+pfmm_status pfmm_learned_read_grad(pfmm_plan_t h, int level, double* table_grad,
                                    float* weight_grad) {
   g_err.clear();
-  if (!live(pl)) return fail(PFMM_ERR_INVALID_ARG, "invalid plan handle");
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_learned_read_grad");
   if (pl->learned != 2) return fail(PFMM_ERR_INVALID_ARG, "not training");
   if (level < 2 || level > pl->L) return fail(PFMM_ERR_INVALID_ARG, "level out of range");
   hipError_t e = hipSuccess;

@@ -176,37 +176,65 @@ __global__ void k_accel_tab(const double* __restrict__ g, int C, double n12,
 
 }  // namespace
 
-hipError_t tabulate_green(const GreenSpec& g, int N, int C, int64_t den, double self_h,
-                          double* dst, hipStream_t st) {
+namespace {
+// The three partial sums of the Fourier kinds (doubles each).
+void fourier_sizes(int N, int C, int64_t& ncs, int64_t& nU, int64_t& nV) {
+  const int H = N / 2;
+  ncs = (int64_t)(H + 1) * (C + 1);
+  nU = (int64_t)(H + 1) * (H + 1) * (C + 1);
+  nV = (int64_t)(H + 1) * (C + 1) * (C + 1);
+}
+
+// Tabulation with the Fourier kinds' partial sums in `ws` (cs, U, V one
+// after another); enqueued on `st` only.
+hipError_t tabulate_into(const GreenSpec& g, int N, int C, int64_t den, double self_h, double* dst,
+                         double* ws, hipStream_t st) {
   const int E = 2 * C + 1;
   const int64_t total = (int64_t)E * E * E;
-  hipError_t e = hipSuccess;
   if (g.kind == GK_K || g.kind == GK_E) {  // Fourier sum (the whole G_K; G_E's long-range part)
     const int H = N / 2;
     const double damp = g.kind == GK_E ? kPi * kPi * g.rs * g.rs : 0.0;
-    double *cs = nullptr, *U = nullptr, *V = nullptr;
-    const int64_t ncs = (int64_t)(H + 1) * (C + 1);
-    const int64_t nU = (int64_t)(H + 1) * (H + 1) * (C + 1);
-    const int64_t nV = (int64_t)(H + 1) * (C + 1) * (C + 1);
-    e = hipMalloc(&cs, ncs * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&U, nU * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&V, nV * sizeof(double));
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(gk_cos, dim3(nblocks(ncs, 256)), dim3(256), 0, st, H, C, den, cs);
-      hipLaunchKernelGGL(gk_step1, dim3(nblocks(nU, 256)), dim3(256), 0, st, H, C, damp, cs, U);
-      hipLaunchKernelGGL(gk_step2, dim3(nblocks(nV, 256)), dim3(256), 0, st, H, C, cs, U, V);
-      hipLaunchKernelGGL(gk_step3, dim3(nblocks(total, 256)), dim3(256), 0, st, H, C, cs, V, dst);
-      e = hipGetLastError();
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-    }
-    if (cs) (void)hipFree(cs);
-    if (U) (void)hipFree(U);
-    if (V) (void)hipFree(V);
+    int64_t ncs, nU, nV;
+    fourier_sizes(N, C, ncs, nU, nV);
+    double* cs = ws;
+    double* U = cs + ncs;
+    double* V = U + nU;
+    hipLaunchKernelGGL(gk_cos, dim3(nblocks(ncs, 256)), dim3(256), 0, st, H, C, den, cs);
+    hipLaunchKernelGGL(gk_step1, dim3(nblocks(nU, 256)), dim3(256), 0, st, H, C, damp, cs, U);
+    hipLaunchKernelGGL(gk_step2, dim3(nblocks(nV, 256)), dim3(256), 0, st, H, C, cs, U, V);
+    hipLaunchKernelGGL(gk_step3, dim3(nblocks(total, 256)), dim3(256), 0, st, H, C, cs, V, dst);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess || g.kind == GK_K) return e;
   }
   hipLaunchKernelGGL(tab_real_space, dim3(nblocks(total, 256)), dim3(256), 0, st, g.kind, g.a1,
                      g.a2, g.rs, C, den, self_h, dst);
   return hipGetLastError();
+}
+}  // namespace
+
+size_t tabulate_workspace_doubles(int kind, int N, int C) {
+  if (kind != GK_K && kind != GK_E) return 0;
+  int64_t ncs, nU, nV;
+  fourier_sizes(N, C, ncs, nU, nV);
+  return (size_t)(ncs + nU + nV);
+}
+
+hipError_t tabulate_green_ws(const GreenSpec& g, int N, int C, int64_t den, double self_h,
+                             double* dst, double* ws, hipStream_t st) {
+  return tabulate_into(g, N, C, den, self_h, dst, ws, st);
+}
+
+hipError_t tabulate_green(const GreenSpec& g, int N, int C, int64_t den, double self_h,
+                          double* dst, hipStream_t st) {
+  const size_t nws = tabulate_workspace_doubles(g.kind, N, C);
+  double* ws = nullptr;
+  hipError_t e = nws ? hipMalloc(&ws, nws * sizeof(double)) : hipSuccess;
+  if (e == hipSuccess) e = tabulate_into(g, N, C, den, self_h, dst, ws, st);
+  if (ws) {
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(ws);
+  }
+  return e;
 }
 
 hipError_t tabulate_accel(const GreenSpec& gs, int N, int C, double* d[3], hipStream_t st) {

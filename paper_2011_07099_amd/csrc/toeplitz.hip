@@ -98,7 +98,11 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
         } else {
           src = (((size_t)ux * a.n + uy) * a.n + uz) * Q3 + e;
         }
-        v = static_cast<const T*>(a.X)[src] * xscale;
+        // a mesh source is FP32 unless the FP64 solve hands in an FP64 mesh
+        const T x = !a.grid_in ? static_cast<const T*>(a.X)[src]
+                    : a.mesh64 ? (T) static_cast<const double*>(a.X)[src]
+                               : (T) static_cast<const float*>(a.X)[src];
+        v = x * xscale;
       }
       xs[i] = v;
     }
@@ -147,11 +151,18 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz(ToepArgs a) {
     const int tx = cx + m * kx, ty = cy + m * ky, tz = cz + m * kz;
 #pragma unroll
     for (int az = 0; az < Q; ++az) {
-      size_t o;
-      if (a.grid_out)
-        o = ((size_t)(tx * Q + ax) * NN + (ty * Q + ay)) * NN + (tz * Q + az);
-      else
-        o = (((size_t)tx * a.n + ty) * a.n + tz) * Q3 + (ax * Q + ay) * Q + az;
+      if (a.grid_out) {  // the mesh: FP32, or FP64 for the FP64 solve with FP64 buffers
+        const size_t o = ((size_t)(tx * Q + ax) * NN + (ty * Q + ay)) * NN + (tz * Q + az);
+        if (a.mesh64) {
+          double* Yd = static_cast<double*>(a.Y);
+          Yd[o] = a.accumulate ? Yd[o] + tot[i][az] : tot[i][az];
+        } else {
+          float* Yf = static_cast<float*>(a.Y);
+          Yf[o] = a.accumulate ? (float)((double)Yf[o] + tot[i][az]) : (float)tot[i][az];
+        }
+        continue;
+      }
+      const size_t o = (((size_t)tx * a.n + ty) * a.n + tz) * Q3 + (ax * Q + ay) * Q + az;
       Y[o] = (a.accumulate && !to_part) ? (T)((double)Y[o] + tot[i][az]) : (T)tot[i][az];
     }
   }
@@ -229,7 +240,7 @@ int toeplitz_workgroups(int q, int fp64, int n, int m) {
 }
 
 hipError_t launch_toeplitz(const ToepArgs& a, hipStream_t st) {
-  if (a.grid_in && a.fp64) return hipErrorInvalidValue;  // the mesh is FP32
+  if (a.mesh64 && !a.fp64) return hipErrorInvalidValue;  // an FP64 mesh needs FP64 arithmetic
   if (a.groups < 1 || (a.groups > 1 && (a.grid_out || !a.partial))) return hipErrorInvalidValue;
   switch (a.q) {
     case 1: return launch_q2<1>(a, st);

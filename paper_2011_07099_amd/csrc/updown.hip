@@ -30,8 +30,8 @@ template <> __device__ inline const double* wsel<double>(Weights w) { return w.d
 
 // S, P: leaf width and gridlet size fixed at compile time (0: the arguments),
 // so that the index arithmetic folds and the contraction loops unroll.
-template <class TO, class W, int S = 0, int P = 0>
-__global__ __launch_bounds__(kThreads) void k_p2m(const float* __restrict__ rho,
+template <class TO, class W, int S = 0, int P = 0, class TR = float>
+__global__ __launch_bounds__(kThreads) void k_p2m(const TR* __restrict__ rho,
                                                    TO* __restrict__ M, Weights Aw, int N, int s_,
                                                    int p_, W h3) {
   const int s = S ? S : s_, p = P ? P : p_;
@@ -179,9 +179,9 @@ __global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
 // out[b s + c] (+)= scale sum_a Wx[ax][cx] Wy[ay][cy] Wz[az][cz] P[b][a]: L2P
 // with Wx = Wy = Wz = A and scale 1, or one component of the gradient of the
 // leaf's local expansion with the derivative weights on that axis
-template <class TI, class W, int S = 0, int PP = 0>
+template <class TI, class W, int S = 0, int PP = 0, class TP = float>
 __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
-                                                   float* __restrict__ phi, Weights Wxw,
+                                                   TP* __restrict__ phi, Weights Wxw,
                                                    Weights Wyw, Weights Wzw, W scale, int N,
                                                    int s_, int p_, int accumulate) {
   const int s = S ? S : s_, p = PP ? PP : p_;
@@ -228,25 +228,26 @@ __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
     for (int k = 0; k < p; ++k) v += sAx[k * s + cx] * w2[k * s * s + cyz];
     v *= scale;
     const int cy = cyz / s, cz = cyz % s;
-    float* o = phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz);
-    *o = accumulate ? (float)((W)*o + v) : (float)v;
+    TP* o = phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz);
+    *o = accumulate ? (TP)((W)*o + v) : (TP)v;
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_fd4(const float* __restrict__ phi,
-                                                   float* __restrict__ acc, int N) {
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_fd4(const T* __restrict__ phi,
+                                                   T* __restrict__ acc, int N) {
   const size_t n3 = (size_t)N * N * N;
   const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n3) return;
   const int z = (int)(i % N), y = (int)((i / N) % N), x = (int)(i / ((size_t)N * N));
   const int mk = N - 1;
-  const float inv12h = (float)N / 12.0f;
+  const T inv12h = (T)N / (T)12;
   auto at = [&](int xx, int yy, int zz) {
     return phi[((size_t)(xx & mk) * N + (yy & mk)) * N + (zz & mk)];
   };
-  const float gx = -at(x + 2, y, z) + 8.f * at(x + 1, y, z) - 8.f * at(x - 1, y, z) + at(x - 2, y, z);
-  const float gy = -at(x, y + 2, z) + 8.f * at(x, y + 1, z) - 8.f * at(x, y - 1, z) + at(x, y - 2, z);
-  const float gz = -at(x, y, z + 2) + 8.f * at(x, y, z + 1) - 8.f * at(x, y, z - 1) + at(x, y, z - 2);
+  const T gx = -at(x + 2, y, z) + (T)8 * at(x + 1, y, z) - (T)8 * at(x - 1, y, z) + at(x - 2, y, z);
+  const T gy = -at(x, y + 2, z) + (T)8 * at(x, y + 1, z) - (T)8 * at(x, y - 1, z) + at(x, y - 2, z);
+  const T gz = -at(x, y, z + 2) + (T)8 * at(x, y, z + 1) - (T)8 * at(x, y, z - 1) + at(x, y, z - 2);
   acc[i] = -gx * inv12h;
   acc[n3 + i] = -gy * inv12h;
   acc[2 * n3 + i] = -gz * inv12h;
@@ -378,9 +379,53 @@ hipError_t launch_l2p_grad(const void* P, int p64, float* acc, Weights A, Weight
 
 hipError_t launch_fd4(const float* phi, float* acc, int N, hipStream_t st) {
   const size_t n3 = (size_t)N * N * N;
-  hipLaunchKernelGGL(k_fd4, dim3((unsigned)((n3 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+  hipLaunchKernelGGL(k_fd4<float>, dim3((unsigned)((n3 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                      st, phi, acc, N);
   return hipGetLastError();
+}
+
+hipError_t launch_fd4_f64(const double* phi, double* acc, int N, hipStream_t st) {
+  const size_t n3 = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_fd4<double>, dim3((unsigned)((n3 + kThreads - 1) / kThreads)), dim3(kThreads),
+                     0, st, phi, acc, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_p2m_f64in(const double* rho, void* M, Weights A, int N, int s, int p, double h3,
+                            hipStream_t st) {
+  const int nL = N / s;
+  const size_t words = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
+  hipLaunchKernelGGL((k_p2m<double, double, 0, 0, double>), dim3(nL * nL * nL), dim3(kThreads),
+                     words * sizeof(double), st, rho, (double*)M, A, N, s, p, h3);
+  return hipGetLastError();
+}
+
+namespace {
+hipError_t l2p_axes_f64out(const void* P, double* out, Weights Wx, Weights Wy, Weights Wz,
+                           double scale, int N, int s, int p, hipStream_t st, int accumulate) {
+  const int nL = N / s;
+  const size_t words = (size_t)(3 * p * s + p * p * p + p * p * s + p * s * s);
+  hipLaunchKernelGGL((k_l2p<double, double, 0, 0, double>), dim3(nL * nL * nL), dim3(kThreads),
+                     words * sizeof(double), st, (const double*)P, out, Wx, Wy, Wz, scale, N, s, p,
+                     accumulate);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_l2p_f64out(const void* P, double* phi, Weights A, int N, int s, int p,
+                             hipStream_t st, int accumulate) {
+  return l2p_axes_f64out(P, phi, A, A, A, 1.0, N, s, p, st, accumulate);
+}
+
+hipError_t launch_l2p_grad_f64out(const void* P, double* acc, Weights A, Weights Ad, double scale,
+                                  int N, int s, int p, hipStream_t st) {
+  const size_t n3 = (size_t)N * N * N;
+  for (int c = 0; c < 3; ++c) {
+    const hipError_t e = l2p_axes_f64out(P, acc + c * n3, c == 0 ? Ad : A, c == 1 ? Ad : A,
+                                         c == 2 ? Ad : A, scale, N, s, p, st, 1);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_cast_d2f(const double* src, float* dst, int64_t n, hipStream_t st) {

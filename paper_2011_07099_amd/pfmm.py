@@ -11,11 +11,12 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpfmm.so")
 
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP = range(5)
-GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3, "E": 4}
-PREC = {"fp32": 0, "bf16x3": 1}
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_CAPTURE, ERR_BAD_HANDLE = \
+    range(7)
+GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3, "E": 4, "LEARNED": 5}
+PREC = {"fp32": 0, "bf16x3": 1, "fp64": 2}
 OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED, OPT_GS_A2, \
-    OPT_ACCEL, OPT_EWALD_RS, OPT_M2L, OPT_NEAR = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+    OPT_ACCEL, OPT_EWALD_RS, OPT_M2L, OPT_NEAR, OPT_LEARNED_WEIGHTS = range(1, 13)
 M2L = {"gemm": 0, "fft": 1, "spectral": 2}
 NEAR = {"direct": 0, "fft": 1}
 ACCEL = {"fd4": 0, "expansion": 1}
@@ -23,11 +24,13 @@ STAGES = ("p2m", "m2m", "m2l", "l2l", "l2p", "near", "fd4")
 BUF_MULTIPOLE, BUF_LOCAL, BUF_TABLE_LEVEL, BUF_TABLE_NEAR = 0, 1, 2, 3
 
 # every symbol include/pfmm.h declares
-EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_plan_read",
-           "pfmm_plan_stage_times", "pfmm_plan_level_times", "pfmm_plan_info", "pfmm_plan_destroy",
+EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_solve_f64", "pfmm_plan_read",
+           "pfmm_plan_stage_times", "pfmm_plan_level_times", "pfmm_plan_kernel_times",
+           "pfmm_plan_info", "pfmm_plan_destroy",
            "pfmm_batch_create", "pfmm_batch_solve", "pfmm_batch_info", "pfmm_batch_group",
-           "pfmm_batch_destroy",
-           "pfmm_plan_direct", "pfmm_learned_set", "pfmm_learned_train_begin",
+           "pfmm_batch_destroy", "pfmm_solve_batch",
+           "pfmm_plan_direct", "pfmm_learned_set",
+           "pfmm_learned_train_begin",
            "pfmm_learned_accumulate", "pfmm_learned_loss", "pfmm_learned_step", "pfmm_learned_get",
            "pfmm_learned_read_grad", "pfmm_table_params", "pfmm_table_set", "pfmm_table_get",
            "pfmm_table_train_begin", "pfmm_table_grad", "pfmm_last_error")
@@ -54,10 +57,13 @@ def load():
     lib.pfmm_plan_create.argtypes = [i32, i32, i32, i32, ctypes.POINTER(vp)]
     lib.pfmm_plan_set.argtypes = [vp, i32, vp, sz]
     lib.pfmm_solve.argtypes = [vp, vp, vp, vp]
+    lib.pfmm_solve_f64.argtypes = [vp, vp, vp, vp]
     lib.pfmm_plan_read.argtypes = [vp, i32, i32, vp]
     lib.pfmm_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(i32)]
     lib.pfmm_plan_level_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+    lib.pfmm_plan_kernel_times.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(i32)]
     lib.pfmm_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
     lib.pfmm_plan_destroy.argtypes = [vp]
     lib.pfmm_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -66,6 +72,8 @@ def load():
     lib.pfmm_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pfmm_batch_group.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.pfmm_batch_destroy.argtypes = [vp]
+    lib.pfmm_solve_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp)]
     fp = ctypes.POINTER(ctypes.c_float)
     dp = ctypes.POINTER(ctypes.c_double)
     lib.pfmm_plan_direct.argtypes = [vp, vp, vp]
@@ -196,7 +204,10 @@ class Plan:
         _check(load().pfmm_plan_set(self._h, OPT_GS_A2, ctypes.byref(v), 8))
 
     def set_profile(self, on):
-        v = ctypes.c_int32(1 if on else 0)
+        """Stage timing: False (off), True or "serial" (stages one after another
+        on the plan's stream), "live" (near zone beside the tree, as unprofiled)."""
+        mode = {False: 0, True: 1, "serial": 1, "live": 2}[on]
+        v = ctypes.c_int32(mode)
         _check(load().pfmm_plan_set(self._h, OPT_PROFILE, ctypes.byref(v), 4))
 
     def stage_times(self):
@@ -213,13 +224,34 @@ class Plan:
         _check(load().pfmm_plan_level_times(self._h, STAGES.index(stage), ms))
         return {l: ms[l] for l in range(self.L + 1) if ms[l] > 0.0}
 
+    def kernel_times(self, stage, level=0):
+        """[ms per kernel] of a stage at a tree level (see pfmm_plan_kernel_times),
+        averaged over the recent profiled solves (synchronises)."""
+        ms = (ctypes.c_double * 8)()
+        n = ctypes.c_int()
+        _check(load().pfmm_plan_kernel_times(self._h, STAGES.index(stage), int(level), ms,
+                                             ctypes.byref(n)))
+        return [ms[i] for i in range(n.value)]
+
     def solve(self, rho, phi, accel=None):
+        """FP32 density -> FP32 potential (and accelerations); float64 tensors
+        go to the FP64 entry point (plans in precision "fp64" only)."""
         import torch
         n3 = self.N ** 3
+        dt = rho.dtype
+        if dt not in (torch.float32, torch.float64):
+            raise ValueError("expected float32 or float64 tensors")
         for t, n in ((rho, n3), (phi, n3)) + (((accel, 3 * n3),) if accel is not None else ()):
-            if t.dtype != torch.float32 or t.numel() != n:
-                raise ValueError("expected float32 tensors of N^3 (accel 3 N^3) elements")
-        _check(load().pfmm_solve(self._h, _ptr(rho), _ptr(phi), _ptr(accel)))
+            if t.dtype != dt or t.numel() != n:
+                raise ValueError("expected tensors of one dtype with N^3 (accel 3 N^3) elements")
+        f = load().pfmm_solve_f64 if dt == torch.float64 else load().pfmm_solve
+        _check(f(self._h, _ptr(rho), _ptr(phi), _ptr(accel)))
+
+    def set_learned_weights(self, weights):
+        """The network's weights through PFMM_OPT_LEARNED_WEIGHTS (BF16 inference)."""
+        w, _ = self._f32(weights)
+        _check(load().pfmm_plan_set(self._h, OPT_LEARNED_WEIGHTS, w.ctypes.data_as(ctypes.c_void_p),
+                                    w.nbytes))
 
     def direct(self, rho, phi):
         """Exact periodic convolution with the plan's G on the device (O(N^6))."""
@@ -352,6 +384,28 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def last_error():
+    """The calling thread's last message from the library ("" if none)."""
+    return load().pfmm_last_error().decode()
+
+
+def solve_batch(plans, rhos, phis):
+    """pfmm_solve_batch: solve independent fields as one batch.  The first
+    call with a given set of (plan, density, potential) builds and keeps its
+    graph; later calls with the same set only launch it."""
+    n = len(plans)
+    if not (n == len(rhos) == len(phis)) or n == 0:
+        raise ValueError("plans, rhos and phis must have the same non-zero length")
+    for pl, r, f in zip(plans, rhos, phis):
+        _ptr(r), _ptr(f)
+        if r.numel() != pl.N ** 3 or f.numel() != pl.N ** 3:
+            raise ValueError("tensor sizes must match the plans")
+    P = (ctypes.c_void_p * n)(*[pl._h.value for pl in plans])
+    R = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+    F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in phis])
+    _check(load().pfmm_solve_batch(n, P, R, F))
 
 
 class Batch:

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "pfmm.h")).read()
-    return sorted(set(re.findall(r"\b(pfmm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(pfmm_[a-z_0-9]+)\s*\(", src)))
 
 
 def _lib():
@@ -42,6 +42,7 @@ def test_library_exports_every_declared_symbol():
     (16, 3, 0, 2),     # p < 1
     (16, 3, 11, 2),    # p > 10
     (16, 3, 4, 9),     # unknown Green's function
+    (16, 3, 4, 6),     # one past PFMM_GREEN_LEARNED
 ])
 def test_invalid_plan_arguments(N, L, p, g):
     lib = _lib()
@@ -57,11 +58,44 @@ def test_unsupported_leaf_width():
     assert lib.pfmm_plan_create(1024, 4, 4, 2, ctypes.byref(h)) == 2  # s = 64
 
 
+def _header_enums():
+    src = open(os.path.join(ROOT, "include", "pfmm.h")).read()
+    return {k: int(v) for k, v in re.findall(r"\b(PFMM_[A-Z0-9_]+)\s*=\s*(\d+)", src)}
+
+
+def test_binding_constants_match_the_header():
+    from paper_2011_07099_amd import pfmm
+    e = _header_enums()
+    assert (e["PFMM_OK"], e["PFMM_ERR_INVALID_ARG"], e["PFMM_ERR_UNSUPPORTED"],
+            e["PFMM_ERR_OUT_OF_MEMORY"], e["PFMM_ERR_HIP"], e["PFMM_ERR_CAPTURE"],
+            e["PFMM_ERR_BAD_HANDLE"]) == (pfmm.OK, pfmm.ERR_INVALID_ARG, pfmm.ERR_UNSUPPORTED,
+                                          pfmm.ERR_OUT_OF_MEMORY, pfmm.ERR_HIP, pfmm.ERR_CAPTURE,
+                                          pfmm.ERR_BAD_HANDLE) == tuple(range(7))
+    for name, v in pfmm.GREEN.items():
+        assert e["PFMM_GREEN_" + name] == v
+    for name, v in pfmm.PREC.items():
+        assert e["PFMM_PREC_" + name.upper()] == v
+    for name, v in pfmm.M2L.items():
+        assert e["PFMM_M2L_" + name.upper()] == v
+    for name, v in pfmm.NEAR.items():
+        assert e["PFMM_NEAR_" + name.upper()] == v
+    for name in ("PRECISION", "STREAM", "GS_A1", "PROFILE", "FP64_LEVELS", "ISOLATED", "GS_A2",
+                 "ACCEL", "EWALD_RS", "M2L", "NEAR", "LEARNED_WEIGHTS"):
+        assert e["PFMM_OPT_" + name] == getattr(pfmm, "OPT_" + name)
+
+
 def test_bad_handles():
     lib = _lib()
-    bogus = ctypes.c_void_p(0x1234)
-    assert lib.pfmm_solve(bogus, None, None, None) == 1
-    assert lib.pfmm_plan_destroy(bogus) == 1
+    for bogus in (0x1234,                  # an arbitrary address
+                  (0x70 << 56) | (7 << 24),  # a plan token whose generation never existed
+                  (0x71 << 56) | (1 << 24)):  # a batch token where a plan is expected
+        h = ctypes.c_void_p(bogus)
+        assert lib.pfmm_solve(h, None, None, None) == 6
+        assert lib.pfmm_solve_f64(h, None, None, None) == 6
+        assert lib.pfmm_plan_destroy(h) == 6
+        assert lib.pfmm_plan_set(h, 1, ctypes.byref(ctypes.c_int32(0)), 4) == 6
+        assert lib.pfmm_plan_info(h, None, None) == 6
+        assert "handle" in lib.pfmm_last_error().decode()
     assert lib.pfmm_plan_destroy(None) == 0
     assert lib.pfmm_plan_create(16, 3, 4, 2, None) == 1
 
@@ -71,10 +105,13 @@ def test_invalid_batch_arguments():
     h = ctypes.c_void_p(1)
     assert lib.pfmm_batch_create(0, None, None, None, ctypes.byref(h)) == 1 and h.value is None
     arr = (ctypes.c_void_p * 1)(0x1234)
-    assert lib.pfmm_batch_create(1, arr, arr, arr, ctypes.byref(h)) == 1
+    assert lib.pfmm_batch_create(1, arr, arr, arr, ctypes.byref(h)) == 6
     assert lib.pfmm_batch_create(1, arr, arr, arr, None) == 1
-    assert lib.pfmm_batch_solve(ctypes.c_void_p(0x1234)) == 1
+    assert lib.pfmm_batch_solve(ctypes.c_void_p(0x1234)) == 6
+    assert lib.pfmm_batch_solve(ctypes.c_void_p((0x70 << 56) | (1 << 24))) == 6  # a plan token
     assert lib.pfmm_batch_destroy(None) == 0
+    assert lib.pfmm_solve_batch(0, None, None, None) == 1
+    assert lib.pfmm_solve_batch(1, arr, arr, arr) == 6
 
 
 def test_header_is_plain_c_and_links():

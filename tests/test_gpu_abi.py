@@ -1,0 +1,221 @@
+"""The C ABI's handle, capture, batch-binding, learned-kind, FP64 and
+solve_batch rules, on the GPU, through the library.
+
+* Handles: a destroyed plan's handle is refused (PFMM_ERR_BAD_HANDLE), also
+  after a new plan has taken its slot; the new plan's handle works.
+* Capture: calls that allocate or synchronise return PFMM_ERR_CAPTURE while
+  the plan's stream is being captured, and do nothing.
+* Batch binding: while a batch lives, its plans refuse pfmm_plan_destroy and
+  the options that change what the batch's graph uses.
+* PFMM_GREEN_LEARNED: without weights a solve is G_S1's bit for bit and the
+  fallback is recorded in pfmm_last_error; with weights it equals a G_S1
+  plan corrected by the same network.
+* PFMM_PREC_FP64: with L = 2 and s = p the FMM is the exact periodic
+  convolution (Sec. 3: the two are identical by construction); through the
+  FP64 entry point it matches the oracle's direct sum (Eq. 4) to 1e-12 of
+  max|phi| for G_S1, G_K and G_X, and a three-level tree matches the oracle's
+  reference FMM to 1e-11 (FP64 rounding amplified by the downward
+  interpolation).  Through the FP32 entry point only the final roundings
+  remain.
+* pfmm_solve_batch equals the per-field solves and keeps its graph between
+  calls; destroying one of its plans releases it.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import conv, fmm as ofmm
+from paper_2011_07099_amd import fields
+
+from gpu_util import f32, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2011_07099_amd import pfmm
+    return pfmm.load()
+
+
+def test_stale_handles_are_refused_after_slot_reuse():
+    import torch
+    from paper_2011_07099_amd import pfmm
+    lib = _lib()
+    a = pfmm.Plan(16, 2, 4, "S1")
+    old = ctypes.c_void_p(a._h.value)
+    a.close()
+    b = pfmm.Plan(16, 2, 4, "S1")   # takes the freed slot
+    assert b._h.value != old.value
+    rho = torch.zeros((16, 16, 16), dtype=torch.float32, device="cuda")
+    phi = torch.empty_like(rho)
+    assert lib.pfmm_solve(old, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                          None) == pfmm.ERR_BAD_HANDLE
+    assert lib.pfmm_plan_destroy(old) == pfmm.ERR_BAD_HANDLE
+    b.solve(rho, phi)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(phi).item() == 0
+    b.close()
+
+
+def test_capture_refuses_allocating_calls():
+    import torch
+    from paper_2011_07099_amd import pfmm
+    lib = _lib()
+    s = torch.cuda.Stream()
+    x = torch.zeros(16, device="cuda")
+    with pfmm.Plan(32, 3, 4, "S1", stream=s) as pl:
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        codes = []
+        with torch.cuda.graph(g, stream=s):
+            x.add_(1.0)
+            v = ctypes.c_int32(1)
+            codes.append(lib.pfmm_plan_set(pl._h, pfmm.OPT_PRECISION, ctypes.byref(v), 4))
+            codes.append(lib.pfmm_plan_destroy(pl._h))
+            v2 = ctypes.c_int32(pfmm.M2L["spectral"])
+            codes.append(lib.pfmm_plan_set(pl._h, pfmm.OPT_M2L, ctypes.byref(v2), 4))
+        torch.cuda.synchronize()
+        print("codes under capture:", codes)
+        assert codes == [pfmm.ERR_CAPTURE] * 3
+        # nothing changed: the plan still solves, in FP32 with GEMM zones
+        rho = torch.from_numpy(fields.lognormal(32, 2.0, 1.0, seed=3).astype(np.float32)).cuda()
+        phi = torch.empty_like(rho)
+        pl.solve(rho, phi)
+        torch.cuda.synchronize()
+    ref = ofmm.fmm(f32(rho.cpu().numpy()), 3, 4, "S1")
+    assert rel_max(phi.cpu().numpy().astype(np.float64), ref) < 2e-5
+
+
+def test_batch_binding_refuses_destroy_and_structural_options():
+    import torch
+    from paper_2011_07099_amd import pfmm
+    lib = _lib()
+    pl = pfmm.Plan(32, 3, 4, "S1")
+    rho = torch.from_numpy(fields.lognormal(32, 2.0, 1.0, seed=4).astype(np.float32)).cuda()
+    phi = torch.empty_like(rho)
+    b = pfmm.Batch([pl], [rho], [phi])
+    assert lib.pfmm_plan_destroy(pl._h) == pfmm.ERR_INVALID_ARG
+    for opt, val in ((pfmm.OPT_PRECISION, 1), (pfmm.OPT_NEAR, 1), (pfmm.OPT_M2L, 2),
+                     (pfmm.OPT_FP64_LEVELS, 1), (pfmm.OPT_ISOLATED, 0)):
+        v = ctypes.c_int32(val)
+        assert lib.pfmm_plan_set(pl._h, opt, ctypes.byref(v), 4) == pfmm.ERR_INVALID_ARG, opt
+    b.solve()
+    torch.cuda.synchronize()
+    ref = ofmm.fmm(f32(rho.cpu().numpy()), 3, 4, "S1")
+    assert rel_max(phi.cpu().numpy().astype(np.float64), ref) < 2e-5
+    b.close()
+    v = ctypes.c_int32(1)
+    assert lib.pfmm_plan_set(pl._h, pfmm.OPT_NEAR, ctypes.byref(v), 4) == pfmm.OK
+    pl.close()
+
+
+def test_learned_kind_falls_back_to_gs1_and_follows_its_network():
+    import torch
+    from paper_2011_07099_amd import pfmm
+    N, L, p = 64, 3, 6
+    rho = torch.from_numpy(fields.lognormal(N, 2.0, 1.0, seed=21).astype(np.float32)).cuda()
+    a, b = torch.empty_like(rho), torch.empty_like(rho)
+    rng = np.random.default_rng(5)
+    w = (rng.standard_normal(pfmm.MLP_PARAMS) * 0.3).astype(np.float32)
+    with pfmm.Plan(N, L, p, "LEARNED") as pl, pfmm.Plan(N, L, p, "S1") as ref:
+        pl.solve(rho, a)
+        msg = pfmm.last_error()
+        ref.solve(rho, b)
+        torch.cuda.synchronize()
+        print("fallback message:", msg)
+        assert "fallback" in msg and torch.equal(a, b)
+        pl.set_learned_weights(w)
+        ref.set_learned(w, bf16=True)
+        pl.solve(rho, a)
+        assert pfmm.last_error() == ""
+        ref.solve(rho, b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        base = torch.empty_like(rho)
+        with pfmm.Plan(N, L, p, "S1") as plain:
+            plain.solve(rho, base)
+            torch.cuda.synchronize()
+        assert not torch.equal(a, base)   # the network did change the tables
+
+
+@pytest.mark.parametrize("N,p,green", [(16, 4, "S1"), (16, 4, "K"), (32, 8, "S1"), (32, 8, "X")])
+def test_fp64_two_level_tree_equals_the_direct_sum(N, p, green):
+    import torch
+    from paper_2011_07099_amd import pfmm
+    rho = fields.lognormal(N, 2.0, 1.0, seed=31)
+    ref = conv.direct(rho, conv.lattice_table(green, N))
+    r = torch.from_numpy(rho).cuda()
+    phi = torch.empty_like(r)
+    acc = torch.empty((3, N, N, N), dtype=torch.float64, device="cuda")
+    with pfmm.Plan(N, 2, p, green, precision="fp64") as pl:
+        assert pl.s == p
+        pl.solve(r, phi, acc)
+        torch.cuda.synchronize()
+        got = phi.cpu().numpy()
+        err = rel_max(got, ref)
+        print("FP64 N=%d L=2 s=p=%d G_%s: max |phi - direct| / max|phi| = %.2e" % (N, p, green, err))
+        assert err < 1e-12
+        # FD4 accelerations in FP64 on the FP64 potential
+        from oracle import fd
+        ga = fd.accel_fd4(ref)
+        assert rel_max(acc.cpu().numpy(), ga) < 1e-11
+        # the FP32 entry point of the same plan: FP64 arithmetic, so only the
+        # FP32 roundings of the near-zone part and of the sum remain
+        r32 = r.float()
+        phi32 = torch.empty_like(r32)
+        pl.solve(r32, phi32)
+        torch.cuda.synchronize()
+        ref32 = conv.direct(f32(rho), conv.lattice_table(green, N))
+        err32 = rel_max(phi32.cpu().numpy().astype(np.float64), ref32)
+        print("  FP32 buffers: %.2e" % err32)
+        assert err32 < 3e-7
+
+
+def test_fp64_three_level_tree_equals_the_reference_fmm():
+    import torch
+    from paper_2011_07099_amd import pfmm
+    N, L, p = 64, 3, 8
+    rho = fields.lognormal(N, 2.0, 1.0, seed=32)
+    ref = ofmm.fmm(rho, L, p, "S1")
+    r = torch.from_numpy(rho).cuda()
+    phi = torch.empty_like(r)
+    with pfmm.Plan(N, L, p, "S1", precision="fp64") as pl:
+        pl.solve(r, phi)
+        torch.cuda.synchronize()
+    err = rel_max(phi.cpu().numpy(), ref)
+    print("FP64 64^3 L=3 p=8: max |phi - reference FMM| / max|phi| = %.2e" % err)
+    # FP64 rounding (1.1e-16) of the coarse fields, amplified on the way down:
+    # each interpolation of Eq. 7 extrapolates past the parent's outer gridlet
+    # nodes (Lebesgue constant about 20 per axis at p = 8, 8e3 in 3D), and
+    # both sides round differently; measured 1.05e-12
+    assert err < 1e-11
+
+
+def test_solve_batch_matches_single_solves_and_keeps_its_graph():
+    import torch
+    from paper_2011_07099_amd import pfmm
+    specs = [(32, 3, 4, "S1", 41), (64, 3, 8, "K", 42)]
+    plans, rhos, phis, refs = [], [], [], []
+    for N, L, p, g, seed in specs:
+        pl = pfmm.Plan(N, L, p, g)
+        r = torch.from_numpy(fields.lognormal(N, 2.0, 1.0, seed=seed).astype(np.float32)).cuda()
+        out = torch.empty_like(r)
+        pl.solve(r, out)
+        plans.append(pl)
+        rhos.append(r)
+        phis.append(torch.full_like(r, float("nan")))
+        refs.append(out)
+    for rep in range(3):
+        for f in phis:
+            f.fill_(float("nan"))
+        pfmm.solve_batch(plans, rhos, phis)
+        torch.cuda.synchronize()
+        for f, ref in zip(phis, refs):
+            assert rel_max(f.cpu().numpy().astype(np.float64),
+                           ref.cpu().numpy().astype(np.float64)) < 1e-6
+    # the kept batch goes with its first plan; the other plan is free again
+    plans[0].close()
+    v = ctypes.c_int32(1)
+    assert _lib().pfmm_plan_set(plans[1]._h, pfmm.OPT_NEAR, ctypes.byref(v), 4) == pfmm.OK
+    plans[1].close()
