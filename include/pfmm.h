@@ -474,6 +474,20 @@ pfmm_status pfmm_solve_batch(int n, const pfmm_plan_t* plans, const float* const
 pfmm_status pfmm_plan_direct(pfmm_plan_t plan, const float* density, float* potential);
 
 /*
+ * pfmm_plan_direct for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and result as pfmm_plan_direct, bit for bit,
+ * without its first-call allocation: the lattice table of G is tabulated on
+ * every call into a static device array of the library (8 MiB, one per
+ * device, held until the process ends), which limits it to N <= 64
+ * (PFMM_ERR_UNSUPPORTED above; isolated plans too).  Allocates and
+ * synchronises nothing; enqueued on the plan's stream.  Every call on a
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, or two threads) race.
+ */
+pfmm_status pfmm_plan_direct_noalloc(pfmm_plan_t plan, const float* density, float* potential);
+
+/*
  * Learned correction of the interaction-zone tables (Sec. 3 defines the
  * optimal G_* as the G with which FMM and PM agree; Sec. 4 proposes
  * parameterising it with many values).  A network f(|j| sorted / (4p),

@@ -29,7 +29,7 @@ EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_solve_f64", 
            "pfmm_plan_info", "pfmm_plan_destroy",
            "pfmm_batch_create", "pfmm_batch_solve", "pfmm_batch_info", "pfmm_batch_group",
            "pfmm_batch_destroy", "pfmm_solve_batch",
-           "pfmm_plan_direct", "pfmm_learned_set",
+           "pfmm_plan_direct", "pfmm_plan_direct_noalloc", "pfmm_learned_set",
            "pfmm_learned_train_begin",
            "pfmm_learned_accumulate", "pfmm_learned_loss", "pfmm_learned_step", "pfmm_learned_get",
            "pfmm_learned_read_grad", "pfmm_table_params", "pfmm_table_set", "pfmm_table_get",
@@ -77,6 +77,7 @@ def load():
     fp = ctypes.POINTER(ctypes.c_float)
     dp = ctypes.POINTER(ctypes.c_double)
     lib.pfmm_plan_direct.argtypes = [vp, vp, vp]
+    lib.pfmm_plan_direct_noalloc.argtypes = [vp, vp, vp]
     lib.pfmm_learned_set.argtypes = [vp, fp, i32]
     lib.pfmm_learned_train_begin.argtypes = [vp, fp, ctypes.c_double]
     lib.pfmm_learned_accumulate.argtypes = [vp, vp, vp, dp]
@@ -256,6 +257,11 @@ class Plan:
     def direct(self, rho, phi):
         """Exact periodic convolution with the plan's G on the device (O(N^6))."""
         _check(load().pfmm_plan_direct(self._h, _ptr(rho), _ptr(phi)))
+
+    def direct_noalloc(self, rho, phi):
+        """The same without allocating (the library's static device array;
+        N <= 64)."""
+        _check(load().pfmm_plan_direct_noalloc(self._h, _ptr(rho), _ptr(phi)))
 
     # --- learned correction of the interaction-zone tables ---------------
     @staticmethod
