@@ -9,10 +9,13 @@ the interaction zones of levels 2..4, L2L, L2P and the near zone) with the
 density already resident in HBM.
 
 Prints one JSON line:
-  - cells/s (N^3 / time per solve) over the timed steps;
-  - the roofline of the dominant single kernel of those same steps: the plan
-    records HIP events around each kernel on the stream it runs on while the
-    steps are timed (the near zone beside the tree, as in any solve);
+  - cells/s (N^3 / time per solve) over the timed steps, run as any solve
+    runs (the near zone on a second stream beside the tree);
+  - per-kernel durations from HIP events the plan records around each
+    kernel on its stream: in those timed steps ("live"), and in a second
+    timed run of the same number of steps with every stage alone on the
+    device ("serial"); the roofline of the dominant single kernel uses its
+    serial duration, with its live one beside it;
   - m2l_mfma: the interaction zones as block-Toeplitz GEMMs on the matrix
     cores, timed in the same run on the same density, per level against the
     peak of the matrix-core instruction it uses;
@@ -548,45 +551,60 @@ def headline(args):
     for _ in range(args.warmup):
         plan.solve(rho, phi, acc)
     torch.cuda.synchronize()
-    # the timed steps record HIP events around every kernel group on the
-    # stream it runs on (the near zone stays beside the tree): the per-kernel
-    # durations below come from these same solves
-    plan.set_profile("live")
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record(stream)
-    for _ in range(args.steps):
-        plan.solve(rho, phi, acc)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ms = t_start.elapsed_time(t_end) / args.steps
+    # Two timed runs of K steps each, HIP events around every kernel group on
+    # the stream it runs on.  The first, as any solve runs (the near zone
+    # beside the tree), gives the throughput and each kernel's live duration;
+    # the second runs every stage alone on the device, one after another,
+    # which gives each kernel's own duration for its roofline.
     spectral, near_fft = args.m2l == "spectral", args.near == "fft"
-    kern = kernel_table(plan, L, near_fft, spectral)
-    stages = plan.stage_times()
-    m2l_levels = plan.level_times("m2l")
+    runs = {}
+    for mode in ("live", "serial"):
+        plan.set_profile(mode)
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record(stream)
+        for _ in range(args.steps):
+            plan.solve(rho, phi, acc)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        runs[mode] = {"ms": t_start.elapsed_time(t_end) / args.steps,
+                      "kern": kernel_table(plan, L, near_fft, spectral),
+                      "stages": plan.stage_times(), "m2l_levels": plan.level_times("m2l")}
     plan.close()
+    ms = runs["live"]["ms"]
+    kern = runs["serial"]["kern"]
+    stages = runs["serial"]["stages"]
+    m2l_levels = runs["serial"]["m2l_levels"]
 
-    # the dominant single kernel of the timed solves and its roofline
+    def roof(name, dms):
+        fl, unit, kbytes = kernel_work(name, N, L, P) if (spectral and near_fft) else (None, "hbm", None)
+        if fl is not None:
+            peak = PEAK_UNIT[unit]
+            tf = fl / (dms * 1e-3) / 1e12
+            return {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                    "frac": tf / peak, "unit_used": unit, "flops_per_launch": fl}, kbytes
+        gbs = (kbytes or 0.0) / (dms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                "frac": gbs / 8000.0}, kbytes
+
+    # the dominant single kernel (longest on its own) and its roofline
     dom = max(kern, key=lambda k: kern[k][0])
     dms = kern[dom][0]
-    fl, unit, kbytes = kernel_work(dom, N, L, P) if (spectral and near_fft) else (None, "hbm", None)
-    if fl is not None:
-        peak = PEAK_UNIT[unit]
-        tf = fl / (dms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
-                    "frac": tf / peak, "unit_used": unit, "flops_per_launch": fl}
-    else:
-        gbs = (kbytes or 0.0) / (dms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
-                    "frac": gbs / 8000.0}
+    roofline, kbytes = roof(dom, dms)
     roofline.update({
-        "kernel": "%s (%.4f ms average over the last %d timed solves, HIP events on its stream)"
-                  % (dom, dms, min(args.steps, 16)),
+        "kernel": "%s (%.4f ms: average over the last %d solves of the serial timed run, HIP "
+                  "events on its stream)" % (dom, dms, min(args.steps, 16)),
         "traffic": traffic_bytes(dom, args.precision),
         "kernel_compulsory_bytes": kbytes,
         "solve_compulsory_bytes": 4.0 * N ** 3 * 2 + sum(
             (8.0 if lv in FP64_LEVELS else 4.0) * 2 * P ** 3 * 8 ** lv for lv in range(2, L + 1)),
     })
+    live = runs["live"]["kern"]
+    if dom in live:
+        rl, _ = roof(dom, live[dom][0])
+        roofline["live"] = {"ms": live[dom][0], "achieved": rl["achieved"], "frac": rl["frac"],
+                            "note": "the same kernel in the live timed run, sharing the device "
+                                    "with the other stream's kernels"}
     out = {
         "metric": METRIC,
         "value": N ** 3 / (ms * 1e-3),
@@ -611,7 +629,9 @@ def headline(args):
                    **({"accel": args.accel} if args.accel != "none" else {}),
                    "near": args.near, "m2l": args.m2l},
         "roofline": roofline,
+        "serial_ms_per_step": runs["serial"]["ms"],
         "kernels_ms": {k: v[0] for k, v in sorted(kern.items(), key=lambda kv: -kv[1][0])},
+        "kernels_live_ms": {k: v[0] for k, v in sorted(live.items(), key=lambda kv: -kv[1][0])},
         "stages_ms": {k: v[0] for k, v in stages.items()},
         "m2l_levels_ms": {str(k): v for k, v in m2l_levels.items()},
     }

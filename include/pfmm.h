@@ -107,8 +107,8 @@ typedef enum {
    * transfers and the near zone (direct summation in FP64, whatever
    * PFMM_OPT_NEAR says).  pfmm_solve then rounds only its FP32 result;
    * pfmm_solve_f64 takes and returns FP64 arrays.  Needs the leaf's FP64
-   * transfers to fit in 64 KiB of LDS (p s + s^3 + s^2 p + s p^2 <= 8192
-   * doubles, and the same for L2P; every s <= 16 with p <= 9): else
+   * transfers to fit in 64 KiB of LDS (p (s + 1) + s^2 (s + 1) + s^2 p + s p^2
+   * <= 8192 doubles, and the same for L2P; every s <= 16 with p <= 9): else
    * PFMM_ERR_UNSUPPORTED.  Not accepted by batches. */
   PFMM_PREC_FP64 = 2
 } pfmm_precision;

@@ -471,8 +471,101 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
   o[16] = make_double2(r2, i2);  // node tz + 2
 }
 
-// Whole-level stencil for the periodic levels with n = 2H = 8 or 16 nodes per
-// axis: one workgroup per frequency holds the level's whole spectrum at that
+// Whole-level stencil, targets in runs along y (used for the 16^3 level, n =
+// 2H = 16): one workgroup per frequency holds the level's whole spectrum at that
+// frequency in LDS (n^3 values: periodic wrap, no halo) and sums every
+// target's zone.  Stored split by parity, [px][py][pz][hx][hy][hz] (node
+// coordinate 2h + p), hz fastest.  One (H = 4) or two (H = 8) waves per
+// parity class: the class, the zone's offsets and so every kernel value are
+// uniform across a wave, and the kernel values come from the frequency's
+// contiguous row of khatT by scalar loads, leaving LDS to the sources.  The
+// 64 lanes of a wave span (hx, hz), so that one load instruction reads H
+// consecutive entries per row (no bank conflicts without a swizzle); a lane
+// owns TY targets of its class consecutive in hy (2 apart in y).  Walking
+// the zone by (dx, dz) columns, each parity plane of a column is one run of
+// TY + 2 source rows along hy shared by the TY targets (three offsets per
+// target and plane); with TY = H / 2 the run's rows are the same for the
+// whole wave, so their offsets fold into the load instructions.  Columns
+// next to the target (|dx|, |dz| <= 1) skip the three dy of the near zone.
+// Blocks are dealt to the 8 XCDs so that the 8 frequencies of a chunk, which
+// share every 128-byte line of the spectra, run on one XCD back to back.
+template <int H, int TY>
+__global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
+    const double2* __restrict__ spec, const double2* __restrict__ khatT, int64_t F, int nchunk,
+    double2* __restrict__ out) {
+  constexpr int n = 2 * H, nn = n * n * n, H3 = H * H * H;
+  constexpr int LPC = H3 / TY;   // lanes per class
+  constexpr int NT = 8 * LPC;
+  static_assert(LPC % 64 == 0, "a class fills whole waves");
+  static_assert(H % TY == 0, "whole target runs");
+  __shared__ double2 box[nn];
+  const int g = blockIdx.x;
+  const int chunk = ((g >> 3) >> 3) * 8 + (g & 7);
+  if (chunk >= nchunk) return;
+  const int k = chunk * 8 + ((g >> 3) & 7);
+  const double2* sk = spec + (int64_t)(k >> 3) * nn * 8 + (k & 7);  // node v at sk[8 v]
+  // stage: LDS slot i = ((p * H + hx) * H + hy) * H + hz, consecutive threads
+  // writing consecutive slots
+  for (int i = threadIdx.x; i < nn; i += NT) {
+    const int hz = i % H, hy = (i / H) % H, hx = (i / (H * H)) % H, p = i / H3;
+    const int x = 2 * hx + (p >> 2), y = 2 * hy + ((p >> 1) & 1), z = 2 * hz + (p & 1);
+    box[i] = sk[(int64_t)((x * n + y) * n + z) * 8];
+  }
+  __syncthreads();
+  const int cls = __builtin_amdgcn_readfirstlane(threadIdx.x / LPC);
+  const int cx = cls >> 2, cy = (cls >> 1) & 1, cz = cls & 1;
+  const int lane = threadIdx.x % LPC;
+  const int hz = lane % H, hx = (lane / H) % H, hy0 = (lane / (H * H)) * TY;
+  const double2* kf = khatT + (int64_t)k * kKT;
+  double re[TY], im[TY];
+#pragma unroll
+  for (int t = 0; t < TY; ++t) re[t] = im[t] = 0.0;
+  // one parity plane (py) of a column: rows hy0 - 1 + j (j < TY + 2) of the
+  // column's (px, pz, hx', hz'); target t reads j = t + m with the kernel of
+  // offset dy = 2 m - 2 + py - cy
+  auto plane = [&](const double2* col, int kbase, int py, bool m0, bool m1, bool m2) {
+    const double2* pl = col + py * 2 * H3;
+    double2 src[TY + 2];
+#pragma unroll
+    for (int j = 0; j < TY + 2; ++j) src[j] = pl[((hy0 - 1 + j) & (H - 1)) * H];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      if ((m == 0 && !m0) || (m == 1 && !m1) || (m == 2 && !m2)) continue;
+      const double2 kd = kf[kbase + 7 * (2 * m - 2 + py - cy + 3)];
+#pragma unroll
+      for (int t = 0; t < TY; ++t) cmac(re[t], im[t], kd, src[t + m]);
+    }
+  };
+  for (int sx = -2; sx <= 3; ++sx) {      // source x = 2 hx + cx + dx, sx = cx + dx
+    const int dx = sx - cx;
+    const int cxo = (sx & 1) * 4 * H3 + ((hx + (sx >> 1)) & (H - 1)) * H * H;
+    for (int sz = -2; sz <= 3; ++sz) {
+      const int dz = sz - cz;
+      const double2* col = box + cxo + (sz & 1) * H3 + ((hz + (sz >> 1)) & (H - 1));
+      const int kbase = (dx + 3) * 49 + (dz + 3);
+      if (abs(dx) > 1 || abs(dz) > 1) {
+        plane(col, kbase, 0, true, true, true);
+        plane(col, kbase, 1, true, true, true);
+      } else if (cy == 0) {  // keep sy = -2, 2 (even) and 3 (odd)
+        plane(col, kbase, 0, true, false, true);
+        plane(col, kbase, 1, false, false, true);
+      } else {               // keep sy = -2 (even), -1 and 3 (odd)
+        plane(col, kbase, 0, true, false, false);
+        plane(col, kbase, 1, true, false, true);
+      }
+    }
+  }
+  double2* o = out + (int64_t)(k >> 3) * nn * 8 + (k & 7);
+#pragma unroll
+  for (int t = 0; t < TY; ++t) {
+    const int y = 2 * (hy0 + t) + cy;
+    const int v = ((2 * hx + cx) * n + y) * n + (2 * hz + cz);
+    o[(int64_t)v * 8] = make_double2(re[t], im[t]);
+  }
+}
+
+// Whole-level stencil, targets in runs along z (used for the 8^3 level, n =
+// 2H = 8): one workgroup per frequency holds the level's whole spectrum at that
 // frequency in LDS (n^3 values: periodic wrap, no halo) and sums every
 // target's zone.  Stored split by parity ([px][py][pz][hx][hy][hz], node
 // coordinate 2h + p), rows of H values (hz) XOR-swizzled by the row index so
@@ -488,7 +581,7 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
 // Blocks are dealt to the 8 XCDs so that the 8 frequencies of a chunk, which
 // share every 128-byte line of the spectra, run on one XCD back to back.
 template <int H, int TZ>
-__global__ void __launch_bounds__(8 * (H * H * H / TZ), 8) k_zone_level(
+__global__ void __launch_bounds__(8 * (H * H * H / TZ), 8) k_zone_level_z(
     const double2* __restrict__ spec, const double2* __restrict__ khatT, int64_t F, int nchunk,
     double2* __restrict__ out) {
   constexpr int n = 2 * H, nn = n * n * n;
@@ -531,13 +624,7 @@ __global__ void __launch_bounds__(8 * (H * H * H / TZ), 8) k_zone_level(
       if ((m == 0 && !m0) || (m == 1 && !m1) || (m == 2 && !m2)) continue;
       const double2 kd = kf[kbase + (2 * m - 2 + pz - cz + 3)];
 #pragma unroll
-      for (int t = 0; t < TZ; ++t) {  // one complex multiply-add as four FMAs
-        const double2 sv = src[t + m];
-        re[t] = fma(kd.x, sv.x, re[t]);
-        re[t] = fma(-kd.y, sv.y, re[t]);
-        im[t] = fma(kd.x, sv.y, im[t]);
-        im[t] = fma(kd.y, sv.x, im[t]);
-      }
+      for (int t = 0; t < TZ; ++t) cmac(re[t], im[t], kd, src[t + m]);
     }
   };
   for (int sx = -2; sx <= 3; ++sx) {      // source x = 2 hx + cx + dx, sx = cx + dx
@@ -710,9 +797,9 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
   const int nchunk = (int)(f->F / 8);
   const unsigned cgrid = (unsigned)((nchunk + 7) / 8 * 64);  // chunks rounded up to 8, times 8
   if (n == 16 && !isolated) {  // the whole level per frequency, four targets per lane
-    k_zone_level<8, 4><<<cgrid, 1024, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
+    k_zone_level_y<8, 8><<<cgrid, 512, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
   } else if (n == 8 && !isolated) {
-    k_zone_level<4, 1><<<cgrid, 512, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
+    k_zone_level_z<4, 1><<<cgrid, 512, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
   } else if (n == 4) {
     k_zone_l2<<<(unsigned)nchunk, 512, 0, st>>>(f->spec, f->khatT[l], offs, noff, isolated, nchunk,
                                                  f->out);

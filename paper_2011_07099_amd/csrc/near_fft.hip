@@ -404,15 +404,22 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
 // yhat_b(k) = sum_e khat_e(k) rhat_{b+e}(k).  A thread owns one frequency
 // and a 2 x 2 block of pencils of leaves (bx, by), swept along z: the 4 x 4
 // source columns around the block are each read once per z and serve all
-// four targets (4 reads per output instead of 9), three z-neighbours held in
-// registers and the next one loaded ahead.  The pencil blocks of one
-// frequency chunk go to one XCD (blocks are dealt to the 8 XCDs round
-// robin), so its L2 serves the column re-reads between neighbouring blocks.
-template <bool CHUNKED>
-__global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
+// four targets (4 reads per output instead of 9), three z-planes of them in
+// registers.  Each step first adds the lowest plane's terms, then reloads
+// that plane's registers with the plane two above (in flight while the other
+// two planes' terms are added), so three register sets rotate.  The
+// thread's 27 kernel values sit in its own slots of LDS (no barrier: only
+// the writing thread reads them), which keeps the register count for three
+// waves per SIMD.  The pencil blocks of one frequency chunk go to one XCD
+// (blocks are dealt to the 8 XCDs round robin), so its L2 serves the column
+// re-reads between neighbouring blocks.
+template <bool CHUNKED, bool ISO>
+__global__ void __launch_bounds__(CHUNKED ? 64 : kThreads, 3) k_near_mac(
     const float2* __restrict__ rhat, const float2* __restrict__ khat, int nb, int64_t F,
-    int nchunk, int isolated, float2* __restrict__ yhat) {
+    int nchunk, float2* __restrict__ yhat) {
+  constexpr bool isolated = ISO;  // sources outside the box are absent
   constexpr int W = CHUNKED ? 64 : kThreads;  // frequencies per block
+  __shared__ float2 kks[27 * W];
   const int g = blockIdx.x;
   const int hb = nb >> 1;
   const int np = hb * hb;  // 2 x 2 pencil blocks
@@ -431,65 +438,74 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
   const int msk = nb - 1;
   const int blk = j % np;
   const int bx0 = 2 * (blk / hb), by0 = 2 * (blk % hb);
-  float2 kk[27];
+  float2* kk = kks + threadIdx.x;  // kernel e at kk[e * W]
 #pragma unroll
-  for (int e = 0; e < 27; ++e) kk[e] = khat[(int64_t)e * F + k];
-  // columns (bx0 - 1 + ix, by0 - 1 + iy), ix, iy in [0, 4)
-  int col[16];
-  bool ok[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const int sx = bx0 - 1 + c / 4, sy = by0 - 1 + c % 4;
-    ok[c] = !isolated || (sx >= 0 && sx < nb && sy >= 0 && sy < nb);
-    col[c] = ((sx & msk) * nb + (sy & msk)) * nb;
-  }
+  for (int e = 0; e < 27; ++e) kk[e * W] = khat[(int64_t)e * F + k];
+  // columns (bx0 - 1 + ix, by0 - 1 + iy), ix, iy in [0, 4), c = 4 ix + iy
   auto load = [&](int c, int z) -> float2 {
-    if (isolated && (z < 0 || z >= nb || !ok[c])) return make_float2(0.0f, 0.0f);
-    return base[(int64_t)(col[c] + (z & msk)) * stride];
+    const int sx = bx0 - 1 + c / 4, sy = by0 - 1 + c % 4;
+    if (isolated && (z < 0 || z >= nb || sx < 0 || sx >= nb || sy < 0 || sy >= nb))
+      return make_float2(0.0f, 0.0f);
+    return base[(int64_t)((((sx & msk) * nb + (sy & msk)) * nb) + (z & msk)) * stride];
   };
-  // z - 1, z, z + 1 of every column in three register sets, z + 2 loaded
-  // into the fourth one step ahead; the sweep is unrolled by four (nb is a
-  // power of two >= 4) and rotates the roles of the sets instead of copying
-  float2 r0[16], r1[16], r2[16], r3[16];
+  float2 r0[16], r1[16], r2[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     r0[c] = load(c, -1);
     r1[c] = load(c, 0);
     r2[c] = load(c, 1);
   }
-  auto step = [&](int bz, float2 (&zm)[16], float2 (&z0)[16], float2 (&zp)[16], float2 (&next)[16]) {
+  // one complex multiply-add as four FMAs
+  auto cmac = [](float& re, float& im, float2 kv, float2 sv) {
+    re = fmaf(kv.x, sv.x, re);
+    re = fmaf(-kv.y, sv.y, re);
+    im = fmaf(kv.x, sv.y, im);
+    im = fmaf(kv.y, sv.x, im);
+  };
+  // plane `ez` (0: z - 1, 1: z, 2: z + 1) of the four targets' sums
+  auto plane = [&](float (&re)[4], float (&im)[4], const float2 (&zz)[16], int ez) {
+    // the kernel values are read from LDS here, every time: an empty asm
+    // statement with a memory clobber keeps the compiler from hoisting them
+    // into registers for the whole sweep (it emits no instruction)
+    asm volatile("" ::: "memory");
 #pragma unroll
-    for (int c = 0; c < 16; ++c) next[c] = load(c, bz + 2);
+    for (int ex = 0; ex < 3; ++ex)
+#pragma unroll
+      for (int ey = 0; ey < 3; ++ey) {
+        const float2 kv = kk[(ex * 9 + ey * 3 + ez) * W];
+#pragma unroll
+        for (int tx = 0; tx < 2; ++tx)
+#pragma unroll
+          for (int ty = 0; ty < 2; ++ty)
+            cmac(re[tx * 2 + ty], im[tx * 2 + ty], kv, zz[(tx + ex) * 4 + (ty + ey)]);
+      }
+  };
+  // targets at z = bz: planes zm (bz - 1), z0 (bz), zp (bz + 1); zm is
+  // reloaded with bz + 2 once its terms are in
+  auto step = [&](int bz, float2 (&zm)[16], float2 (&z0)[16], float2 (&zp)[16]) {
+    float re[4] = {0.0f, 0.0f, 0.0f, 0.0f}, im[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    plane(re, im, zm, 0);
+    if (bz + 1 < nb) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) zm[c] = load(c, bz + 2);
+    }
+    plane(re, im, z0, 1);
+    plane(re, im, zp, 2);
 #pragma unroll
     for (int tx = 0; tx < 2; ++tx)
 #pragma unroll
-      for (int ty = 0; ty < 2; ++ty) {
-        float re = 0.0f, im = 0.0f;
-        // one complex multiply-add as four FMAs
-        auto cmac = [&](float2 kv, float2 sv) {
-          re = fmaf(kv.x, sv.x, re);
-          re = fmaf(-kv.y, sv.y, re);
-          im = fmaf(kv.x, sv.y, im);
-          im = fmaf(kv.y, sv.x, im);
-        };
-#pragma unroll
-        for (int ex = 0; ex < 3; ++ex)
-#pragma unroll
-          for (int ey = 0; ey < 3; ++ey) {
-            const int c = (tx + ex) * 4 + (ty + ey);
-            cmac(kk[ex * 9 + ey * 3], zm[c]);
-            cmac(kk[ex * 9 + ey * 3 + 1], z0[c]);
-            cmac(kk[ex * 9 + ey * 3 + 2], zp[c]);
-          }
-        obase[(int64_t)(((bx0 + tx) * nb + by0 + ty) * nb + bz) * stride] = make_float2(re, im);
-      }
+      for (int ty = 0; ty < 2; ++ty)
+        obase[(int64_t)(((bx0 + tx) * nb + by0 + ty) * nb + bz) * stride] =
+            make_float2(re[tx * 2 + ty], im[tx * 2 + ty]);
   };
-  for (int bz = 0; bz < nb; bz += 4) {
-    step(bz, r0, r1, r2, r3);
-    step(bz + 1, r1, r2, r3, r0);
-    step(bz + 2, r2, r3, r0, r1);
-    step(bz + 3, r3, r0, r1, r2);
+  int bz = 0;
+  for (; bz + 3 <= nb; bz += 3) {
+    step(bz, r0, r1, r2);
+    step(bz + 1, r1, r2, r0);
+    step(bz + 2, r2, r0, r1);
   }
+  if (bz < nb) step(bz, r0, r1, r2);
+  if (bz + 1 < nb) step(bz + 1, r1, r2, r0);
 }
 
 }  // namespace
@@ -592,8 +608,12 @@ hipError_t run_fused(NearFft* f, const float* rho, float* const* out, int nout, 
   for (int t = 0; t < nout && e == hipSuccess; ++t) {
     e = tbegin(kt, st);
     if (e != hipSuccess) break;
-    k_near_mac<true><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
-                                                      isolated, f->yhat);
+    if (isolated)
+      k_near_mac<true, true><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
+                                                              f->yhat);
+    else
+      k_near_mac<true, false><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
+                                                               f->yhat);
     e = tend(kt, st, 1 + 2 * t, hipGetLastError());
     if (e == hipSuccess) e = tbegin(kt, st);
     if (e == hipSuccess) {
@@ -629,8 +649,12 @@ hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nou
   for (int t = 0; t < nout && e == hipSuccess; ++t) {
     e = tbegin(kt, st);
     if (e != hipSuccess) break;
-    k_near_mac<false><<<(unsigned)blocks, kThreads, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F,
-                                                            nchunk, isolated, f->yhat);
+    if (isolated)
+      k_near_mac<false, true><<<(unsigned)blocks, kThreads, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F,
+                                                                     nchunk, f->yhat);
+    else
+      k_near_mac<false, false><<<(unsigned)blocks, kThreads, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F,
+                                                                      nchunk, f->yhat);
     e = tend(kt, st, 1 + 2 * t, hipGetLastError());
     if (e == hipSuccess) e = tbegin(kt, st);
     if (e == hipSuccess) e = fft_err(hipfftExecC2R(f->inv, (hipfftComplex*)f->yhat, f->pad));

@@ -292,7 +292,7 @@ bool level64(const pfmm_plan_s* pl, int l) {
   if (l < 2 || l > top) return false;
   if (l == pl->L) {
     const int p = pl->p, s = pl->s;
-    const size_t w1 = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
+    const size_t w1 = (size_t)(p * (s + 1) + s * s * (s + 1) + s * s * p + s * p * p);
     const size_t w2 = (size_t)(3 * p * s + p * p * p + p * p * s + p * s * s);
     if ((w1 > w2 ? w1 : w2) * sizeof(double) > 65536) return false;
   }

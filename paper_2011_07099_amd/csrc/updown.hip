@@ -35,34 +35,55 @@ __global__ __launch_bounds__(kThreads) void k_p2m(const TR* __restrict__ rho,
                                                    TO* __restrict__ M, Weights Aw, int N, int s_,
                                                    int p_, W h3) {
   const int s = S ? S : s_, p = P ? P : p_;
+  // LDS rows of the weights and of the cell block padded by one word, so
+  // that lanes reading different rows at one column hit different banks
+  const int sp = s + 1;
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
-  W* sA = sm;              // [p][s]
-  W* sr = sA + p * s;      // [s][s][s]
-  W* t1 = sr + s * s * s;  // [cx][cy][az]
-  W* t2 = t1 + s * s * p;  // [cx][ay][az]
+  W* sA = sm;               // [p][s + 1]
+  W* sr = sA + p * sp;      // [s][s][s + 1]
+  W* t1 = sr + s * s * sp;  // [cx][cy][az]
+  W* t2 = t1 + s * s * p;   // [cx][ay][az]
   const W* A = wsel<W>(Aw);
   const int nL = N / s;
   const int b = blockIdx.x;
   const int bx = b / (nL * nL), by = (b / nL) % nL, bz = b % nL;
   const int tid = threadIdx.x;
-  for (int i = tid; i < p * s; i += kThreads) sA[i] = A[i];
-  for (int i = tid; i < s * s * s; i += kThreads) {
-    const int cx = i / (s * s), cy = (i / s) % s, cz = i % s;
-    sr[i] = (W)rho[((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz)];
+  for (int i = tid; i < p * s; i += kThreads) sA[(i / s) * sp + i % s] = A[i];
+  if constexpr (S % 4 == 0 && S > 0) {  // rows of s cells as float4 (16-byte aligned: s | N)
+    for (int i = tid; i < s * s * (s / 4); i += kThreads) {
+      const int row = i / (s / 4), q = i % (s / 4);
+      const int cx = row / s, cy = row % s;
+      const TR* src = rho + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (size_t)bz * s + 4 * q;
+      W* dst = sr + row * sp + 4 * q;
+      if constexpr (sizeof(TR) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(src);
+        dst[0] = (W)v.x;
+        dst[1] = (W)v.y;
+        dst[2] = (W)v.z;
+        dst[3] = (W)v.w;
+      } else {
+        for (int c = 0; c < 4; ++c) dst[c] = (W)src[c];
+      }
+    }
+  } else {
+    for (int i = tid; i < s * s * s; i += kThreads) {
+      const int cx = i / (s * s), cy = (i / s) % s, cz = i % s;
+      sr[(cx * s + cy) * sp + cz] = (W)rho[((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz)];
+    }
   }
   __syncthreads();
   for (int i = tid; i < s * s * p; i += kThreads) {
     const int cxy = i / p, az = i % p;
     W acc = 0;
-    for (int cz = 0; cz < s; ++cz) acc += sA[az * s + cz] * sr[cxy * s + cz];
+    for (int cz = 0; cz < s; ++cz) acc += sA[az * sp + cz] * sr[cxy * sp + cz];
     t1[i] = acc;
   }
   __syncthreads();
   for (int i = tid; i < s * p * p; i += kThreads) {
     const int cx = i / (p * p), ay = (i / p) % p, az = i % p;
     W acc = 0;
-    for (int cy = 0; cy < s; ++cy) acc += sA[ay * s + cy] * t1[(cx * s + cy) * p + az];
+    for (int cy = 0; cy < s; ++cy) acc += sA[ay * sp + cy] * t1[(cx * s + cy) * p + az];
     t2[i] = acc;
   }
   __syncthreads();
@@ -70,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_p2m(const TR* __restrict__ rho,
   for (int i = tid; i < p3; i += kThreads) {
     const int ax = i / (p * p), ayz = i % (p * p);
     W acc = 0;
-    for (int cx = 0; cx < s; ++cx) acc += sA[ax * s + cx] * t2[cx * p * p + ayz];
+    for (int cx = 0; cx < s; ++cx) acc += sA[ax * sp + cx] * t2[cx * p * p + ayz];
     M[(size_t)b * p3 + i] = (TO)(h3 * acc);
   }
 }
@@ -222,14 +243,39 @@ __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
     w2[i] = v;
   }
   __syncthreads();
-  for (int i = tid; i < s * s * s; i += kThreads) {
-    const int cx = i / (s * s), cyz = i % (s * s);
-    W v = 0;
-    for (int k = 0; k < p; ++k) v += sAx[k * s + cx] * w2[k * s * s + cyz];
-    v *= scale;
-    const int cy = cyz / s, cz = cyz % s;
-    TP* o = phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz);
-    *o = accumulate ? (TP)((W)*o + v) : (TP)v;
+  if constexpr (S % 4 == 0 && S > 0 && sizeof(TP) == 4) {
+    // four consecutive cells of a row per thread, read and written as float4
+    // (16-byte aligned: the launcher checks the mesh pointer)
+    for (int i = tid; i < s * s * (s / 4); i += kThreads) {
+      const int cx = i / (s * (s / 4)), cy = (i / (s / 4)) % s, cz0 = 4 * (i % (s / 4));
+      W v[4] = {0, 0, 0, 0};
+      for (int k = 0; k < p; ++k) {
+        const W a = sAx[k * s + cx];
+        const W* w = w2 + k * s * s + cy * s + cz0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] += a * w[c];
+      }
+      float4* o = reinterpret_cast<float4*>(phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N +
+                                            (bz * s + cz0));
+      float4 r = make_float4((float)(v[0] * scale), (float)(v[1] * scale), (float)(v[2] * scale),
+                             (float)(v[3] * scale));
+      if (accumulate) {
+        const float4 q = *o;
+        r = make_float4((float)((W)q.x + v[0] * scale), (float)((W)q.y + v[1] * scale),
+                        (float)((W)q.z + v[2] * scale), (float)((W)q.w + v[3] * scale));
+      }
+      *o = r;
+    }
+  } else {
+    for (int i = tid; i < s * s * s; i += kThreads) {
+      const int cx = i / (s * s), cyz = i % (s * s);
+      W v = 0;
+      for (int k = 0; k < p; ++k) v += sAx[k * s + cx] * w2[k * s * s + cyz];
+      v *= scale;
+      const int cy = cyz / s, cz = cyz % s;
+      TP* o = phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz);
+      *o = accumulate ? (TP)((W)*o + v) : (TP)v;
+    }
   }
 }
 
@@ -260,10 +306,16 @@ __global__ void k_d2f(const double* __restrict__ s, float* __restrict__ d, int64
 
 }  // namespace
 
+// LDS words of P2M: the padded weights and cell block, and the two partial
+// contractions.
+inline size_t p2m_words(int s, int p) {
+  return (size_t)(p * (s + 1) + s * s * (s + 1) + s * s * p + s * p * p);
+}
+
 hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int s, int p,
                       double h3, hipStream_t st) {
   const int nL = N / s;
-  const size_t words = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
+  const size_t words = p2m_words(s, p);
   if (m64)
     hipLaunchKernelGGL((k_p2m<double, double>), dim3(nL * nL * nL), dim3(kThreads),
                        words * sizeof(double), st, rho, (double*)M, A, N, s, p, h3);
@@ -271,7 +323,11 @@ hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int 
     const dim3 g(nL * nL * nL), b(kThreads);
     const size_t sh = words * sizeof(float);
     const float hf = (float)h3;
-    if (s == 16 && p == 8)
+    // the compile-time instances read rows of cells as float4
+    const bool aligned = ((uintptr_t)rho & 15) == 0;
+    if (!aligned)
+      hipLaunchKernelGGL((k_p2m<float, float>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
+    else if (s == 16 && p == 8)
       hipLaunchKernelGGL((k_p2m<float, float, 16, 8>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
     else if (s == 8 && p == 8)
       hipLaunchKernelGGL((k_p2m<float, float, 8, 8>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
@@ -346,7 +402,9 @@ hipError_t l2p_axes(const void* P, int p64, float* out, Weights Wx, Weights Wy, 
     const size_t sh = words * sizeof(float);
     const float sc = (float)scale;
     const float* Pf = (const float*)P;
-    if (s == 16 && p == 8)
+    if (((uintptr_t)out & 15) != 0)  // the compile-time instances write float4
+      hipLaunchKernelGGL((k_l2p<float, float>), g, b, sh, st, Pf, out, Wx, Wy, Wz, sc, N, s, p, accumulate);
+    else if (s == 16 && p == 8)
       hipLaunchKernelGGL((k_l2p<float, float, 16, 8>), g, b, sh, st, Pf, out, Wx, Wy, Wz, sc, N, s, p, accumulate);
     else if (s == 8 && p == 8)
       hipLaunchKernelGGL((k_l2p<float, float, 8, 8>), g, b, sh, st, Pf, out, Wx, Wy, Wz, sc, N, s, p, accumulate);
@@ -394,7 +452,7 @@ hipError_t launch_fd4_f64(const double* phi, double* acc, int N, hipStream_t st)
 hipError_t launch_p2m_f64in(const double* rho, void* M, Weights A, int N, int s, int p, double h3,
                             hipStream_t st) {
   const int nL = N / s;
-  const size_t words = (size_t)(p * s + s * s * s + s * s * p + s * p * p);
+  const size_t words = p2m_words(s, p);
   hipLaunchKernelGGL((k_p2m<double, double, 0, 0, double>), dim3(nL * nL * nL), dim3(kThreads),
                      words * sizeof(double), st, rho, (double*)M, A, N, s, p, h3);
   return hipGetLastError();
