@@ -504,10 +504,12 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
   if (chunk >= nchunk) return;
   const int k = chunk * 8 + ((g >> 3) & 7);
   const double2* sk = spec + (int64_t)(k >> 3) * nn * 8 + (k & 7);  // node v at sk[8 v]
-  // stage: LDS slot i = ((p * H + hx) * H + hy) * H + hz, consecutive threads
-  // writing consecutive slots
+  // stage: LDS slot i = ((p * H + hx) * H + (hy ^ (hx & 1))) * H + hz,
+  // consecutive threads writing consecutive slots.  Flipping the low bit of
+  // hy on odd hx puts the two hx of a 16-lane group on different halves of
+  // the 64 banks when all lanes read one hy.
   for (int i = threadIdx.x; i < nn; i += NT) {
-    const int hz = i % H, hy = (i / H) % H, hx = (i / (H * H)) % H, p = i / H3;
+    const int hz = i % H, hx = (i / (H * H)) % H, hy = ((i / H) % H) ^ (hx & 1), p = i / H3;
     const int x = 2 * hx + (p >> 2), y = 2 * hy + ((p >> 1) & 1), z = 2 * hz + (p & 1);
     box[i] = sk[(int64_t)((x * n + y) * n + z) * 8];
   }
@@ -520,14 +522,22 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
   double re[TY], im[TY];
 #pragma unroll
   for (int t = 0; t < TY; ++t) re[t] = im[t] = 0.0;
+  int fl = 0;  // 1 when the current source column's hx' is odd
   // one parity plane (py) of a column: rows hy0 - 1 + j (j < TY + 2) of the
   // column's (px, pz, hx', hz'); target t reads j = t + m with the kernel of
   // offset dy = 2 m - 2 + py - cy
-  auto plane = [&](const double2* col, int kbase, int py, bool m0, bool m1, bool m2) {
-    const double2* pl = col + py * 2 * H3;
+  auto plane = [&](int col, int kbase, int py, bool m0, bool m1, bool m2) {
+    // row hy sits at slot row hy ^ (hx' & 1): one base per parity of hy
+    // (32-bit LDS slot offsets, no pointer arithmetic)
+    const int pl = col + py * 2 * H3;
+    const int pe = pl + fl * H;   // even hy: +H on odd hx'
+    const int po = pl - fl * H;   // odd hy: -H on odd hx'
     double2 src[TY + 2];
 #pragma unroll
-    for (int j = 0; j < TY + 2; ++j) src[j] = pl[((hy0 - 1 + j) & (H - 1)) * H];
+    for (int j = 0; j < TY + 2; ++j) {
+      const int hy = (hy0 - 1 + j) & (H - 1);
+      src[j] = box[((hy & 1) ? po : pe) + hy * H];
+    }
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if ((m == 0 && !m0) || (m == 1 && !m1) || (m == 2 && !m2)) continue;
@@ -538,10 +548,12 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
   };
   for (int sx = -2; sx <= 3; ++sx) {      // source x = 2 hx + cx + dx, sx = cx + dx
     const int dx = sx - cx;
-    const int cxo = (sx & 1) * 4 * H3 + ((hx + (sx >> 1)) & (H - 1)) * H * H;
+    const int hxs = (hx + (sx >> 1)) & (H - 1);
+    fl = hxs & 1;
+    const int cxo = (sx & 1) * 4 * H3 + hxs * H * H;
     for (int sz = -2; sz <= 3; ++sz) {
       const int dz = sz - cz;
-      const double2* col = box + cxo + (sz & 1) * H3 + ((hz + (sz >> 1)) & (H - 1));
+      const int col = cxo + (sz & 1) * H3 + ((hz + (sz >> 1)) & (H - 1));
       const int kbase = (dx + 3) * 49 + (dz + 3);
       if (abs(dx) > 1 || abs(dz) > 1) {
         plane(col, kbase, 0, true, true, true);

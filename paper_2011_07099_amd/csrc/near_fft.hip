@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
 // (blocks are dealt to the 8 XCDs round robin), so its L2 serves the column
 // re-reads between neighbouring blocks.
 template <bool CHUNKED, bool ISO>
-__global__ void __launch_bounds__(CHUNKED ? 64 : kThreads, 3) k_near_mac(
+__global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
     const float2* __restrict__ rhat, const float2* __restrict__ khat, int nb, int64_t F,
     int nchunk, float2* __restrict__ yhat) {
   constexpr bool isolated = ISO;  // sources outside the box are absent
