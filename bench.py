@@ -51,7 +51,25 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default at L = 4)
 # plain 1 GiB copy (read x2.0, write x1.0), keyed by the kernel's name in the
 # bench line and the SHA-1 prefix of the sources it was taken on (its file and
 # plan.hip); a changed source reports null.
-TRAFFIC = {}
+# HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE x 1, KiB scaled to bytes
+# by a plain 1 GiB copy) of the default route at 256^3, L = 4, p = 8, taken
+# with rocprofv3 --pmc on the sources whose SHA-1 prefix keys each entry; a
+# change to those sources (or another route) reports null until the counters
+# are taken again.
+TRAFFIC = {
+    ("near leaf transforms", "865237993b4c"): 134438052 + 570425344,
+    ("near stencil", "865237993b4c"): 840296160 + 570425344,
+    ("near inverse transforms", "865237993b4c"): 570662335 + 67108992,
+    ("p2m", "dd1c6fa857cd"): 134264877 + 8388608,
+    ("l2p", "dd1c6fa857cd"): 142635249 + 67108864,
+    ("m2l L4 node transforms", "3df04596f28c"): 8520380 + 150994944,
+    ("m2l L4 stencil", "3df04596f28c"): 176560106 + 151036800,
+    ("m2l L4 inverse transforms", "3df04596f28c"): 159527921 + 8648448,
+    ("m2l L3 stencil", "3df04596f28c"): 44314321 + 18875456,
+    ("m2l L2 stencil", "3df04596f28c"): 6827670 + 2359296,
+}
+TRAFFIC_ROUTE = {"precision": "bf16x3", "near": "fft", "m2l": "spectral", "accel": "none",
+                 "N": 256, "L": 4, "p": 8}
 KERNEL_SRC = {"m2l": ("m2l_spectral.hip", "plan.hip"), "near": ("near_fft.hip", "plan.hip"),
               "p2m": ("updown.hip", "plan.hip"), "l2p": ("updown.hip", "plan.hip")}
 
@@ -68,9 +86,11 @@ def source_key():
     return out
 
 
-def traffic_bytes(kernel, precision=None):
+def traffic_bytes(kernel, route):
+    """Counted HBM bytes of one launch of `kernel`, or None when the route or
+    the kernel's sources differ from those the counters were taken on."""
     fam = kernel.split()[0]
-    if fam not in KERNEL_SRC:
+    if fam not in KERNEL_SRC or route != TRAFFIC_ROUTE:
         return None
     return TRAFFIC.get((kernel, source_key()[fam]))
 
@@ -594,7 +614,9 @@ def headline(args):
     roofline.update({
         "kernel": "%s (%.4f ms: average over the last %d solves of the serial timed run, HIP "
                   "events on its stream)" % (dom, dms, min(args.steps, 16)),
-        "traffic": traffic_bytes(dom, args.precision),
+        "traffic": traffic_bytes(dom, {"precision": args.precision, "near": args.near,
+                                            "m2l": args.m2l, "accel": args.accel,
+                                            "N": N, "L": L, "p": P}),
         "kernel_compulsory_bytes": kbytes,
         "solve_compulsory_bytes": 4.0 * N ** 3 * 2 + sum(
             (8.0 if lv in FP64_LEVELS else 4.0) * 2 * P ** 3 * 8 ** lv for lv in range(2, L + 1)),
