@@ -490,13 +490,16 @@ pfmm_status pfmm_plan_direct_noalloc(pfmm_plan_t plan, const float* density, flo
 /*
  * Learned correction of the interaction-zone tables (Sec. 3 defines the
  * optimal G_* as the G with which FMM and PM agree; Sec. 4 proposes
- * parameterising it with many values).  A network f(|j| sorted / (4p),
- * level / 8, p / 10) with layers 5 -> 64 -> 64 -> 1 and SiLU activations
- * sets T_l[j] = G(eta_l j) (1 + 1e-4 f) for every interaction-zone table
- * entry (Eq. 6); the near zone keeps G.  Weights: PFMM_MLP_PARAMS
- * floats, W1[64][5] b1[64] W2[64][64] b2[64] W3[64] b3.
+ * parameterising it with many values).  A network of the table offset
+ * j = a - a' - p d (Eq. 6), the level and p,
+ *     f(|j| sorted / (4p), (|j| sorted mod p) / p, level / 8, p / 10),
+ * with layers 8 -> 64 -> 64 -> 1 and SiLU activations, sets
+ * T_l[j] = G(eta_l j) (1 + 1e-4 f) for every interaction-zone table entry;
+ * the near zone keeps G.  Its inputs are invariant under the cube's 48
+ * symmetries, so the corrected tables keep the FMM symmetric.  Weights:
+ * PFMM_MLP_PARAMS floats, W1[64][8] b1[64] W2[64][64] b2[64] W3[64] b3.
  */
-#define PFMM_MLP_PARAMS 4609
+#define PFMM_MLP_PARAMS 4801
 
 /* Set the network (host weights) and rebuild the tables by running it on the
  * device, in BF16 with FP32 accumulation when bf16 != 0, else in FP32.
@@ -573,6 +576,52 @@ pfmm_status pfmm_table_train_begin(pfmm_plan_t plan, double lr);
  * so a line search along any direction needs one more loss evaluation.
  * Synchronises. */
 pfmm_status pfmm_table_grad(pfmm_plan_t plan, float* grad);
+
+/*
+ * G_* as one grid-valued function everywhere (Sec. 3: G_* is the G with which
+ * the FMM and PM, both using it, agree, which gives Eq. 8; Sec. 4: G_* as a
+ * grid of free values).  On the periodic mesh,
+ *     G_*(x) = G(x) (1 + delta[u(x)]),
+ * one free value per orbit u of mesh separations x under the cube's 48
+ * symmetries: each component folded to min(|x_i| mod N, N - |x_i| mod N),
+ * sorted a >= b >= c, u = a(a+1)(a+2)/6 + b(b+1)/2 + c, (N/2 + 1)(N/2 + 2)
+ * (N/2 + 3)/6 values.  G_* replaces G in the near-zone table G(h m), in every
+ * level's interaction-zone table G(eta_l j), and in the exact periodic
+ * convolution (pfmm_plan_direct), which is the PM solution with G_* that
+ * the FMM is compared with.  The level tables sample the mesh only when p
+ * divides the leaf width N / 2^L, which is required (UNSUPPORTED otherwise),
+ * as are a periodic plan, interaction zones other than the FFT comparator,
+ * and the potential alone (no PFMM_OPT_ACCEL expansion accelerations).
+ * While G_* is set, the interaction-zone table corrections (pfmm_learned_*,
+ * pfmm_table_*) are refused, and they must be cleared before G_* is set.
+ * The loss of a density is that of pfmm_learned_accumulate with the target
+ * PM(G_*), which moves with delta.  The first call allocates (tables,
+ * orbit maps, an FP64 FFT plan of N^3); every call synchronises.
+ */
+
+/* Number of free values into *count. */
+pfmm_status pfmm_gstar_params(pfmm_plan_t plan, int* count);
+
+/* Set delta from the host (count floats) and rebuild every table; NULL
+ * restores G everywhere. */
+pfmm_status pfmm_gstar_set(pfmm_plan_t plan, const float* delta);
+
+/* Copy the current delta to the host (count floats). */
+pfmm_status pfmm_gstar_get(pfmm_plan_t plan, float* delta);
+
+/* Loss of one density (device, N^3 FP32) against PM with the plan's G_*:
+ * a forward solve, the exact periodic convolution and the residual. */
+pfmm_status pfmm_gstar_loss(pfmm_plan_t plan, const float* density, double* loss);
+
+/* The same, and add d loss / d delta to the plan's accumulator: the FMM's
+ * adjoint (level tables through the adjoint sweep, the near-zone table by a
+ * sum over neighbouring-leaf pairs) minus the PM side (a periodic
+ * cross-correlation by FP64 FFT), including the change of the PM norm.
+ * *loss may be NULL. */
+pfmm_status pfmm_gstar_accumulate(pfmm_plan_t plan, const float* density, double* loss);
+
+/* Copy the accumulated gradient (count floats) to the host and clear it. */
+pfmm_status pfmm_gstar_grad(pfmm_plan_t plan, float* grad);
 
 /* Message describing the calling thread's last failure ("" if none). */
 const char* pfmm_last_error(void);

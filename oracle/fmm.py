@@ -228,7 +228,7 @@ def _near_sum(tab, J, mb, periodic):
 
 
 def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
-        m2l_tables=None, periodic=True):
+        m2l_tables=None, periodic=True, near_tables=None):
     """Natively periodic FMM potential of the density ``rho`` (N^3, FP64).
 
     With ``periodic=False``: the non-periodic twin of Sec. 3 (Eq. 3), the same
@@ -239,7 +239,8 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
     With ``stages=True`` also returns a dict of intermediates:
     ``M[l]`` and ``Phi[l]`` (shape (n, n, n, p, p, p)), ``far`` and ``near``.
     ``m2l_tables`` optionally overrides the per-level M2L G samples
-    (dict level -> (table, J)), e.g. to test a corrected Green's function.
+    (dict level -> (table, J)), e.g. to test a corrected Green's function,
+    and ``near_tables`` the near-zone samples G(h j) ((table, J), J = 2s - 1).
     """
     rho = np.asarray(rho, np.float64)
     N = rho.shape[0]
@@ -320,7 +321,10 @@ def fmm(rho, L, p, kind="S1", a=(-0.125,), targets=None, stages=False,
         Phi[l] = out
 
     # ---- downward to cells: L2P (transpose of P2M) and the near zone ----
-    ntab, NJ = near_table(kind if periodic else "N", N, s, a)
+    if near_tables is not None:
+        ntab, NJ = near_tables
+    else:
+        ntab, NJ = near_table(kind if periodic else "N", N, s, a)
     if targets is None:
         far = apply3T(A, Phi[L])                        # [b..., c...]
         near = _near_sum(ntab, NJ, mb, periodic)

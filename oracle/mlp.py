@@ -4,29 +4,42 @@ The paper defines the optimal Green's function G_* as the one with which the
 FMM reproduces the PM solution (Sec. 3, Eq. 8) and proposes to parameterise
 it by many free values (Sec. 4).  The correction studied here multiplies every
 interaction-zone table entry by (1 + delta), delta = KAPPA * f(features) from
-a network 5 -> 64 -> 64 -> 1 with SiLU activations and the fixed output scale
-KAPPA = 1e-4:
+a network 8 -> 64 -> 64 -> 1 with SiLU activations and the fixed output scale
+KAPPA = 1e-4.  Its input is the table offset j = a - a' - p d of Eq. 6
+reduced to what the cube's 48 symmetries leave invariant (so the corrected
+table stays symmetric), plus the level and p:
 
-    features(j, level, p) = (u1/(4p), u2/(4p), u3/(4p), level/8, p/10),
-    (u1 >= u2 >= u3) = |j| sorted descending  (invariant under the cube's
-    48 symmetries, so the corrected table stays symmetric),
-    weights theta = W1[64][5] b1[64] W2[64][64] b2[64] W3[64] b3.
+    (u1 >= u2 >= u3) = |j| sorted descending,
+    features(j, level, p) = (u1/(4p), u2/(4p), u3/(4p),
+                             (u1 mod p)/p, (u2 mod p)/p, (u3 mod p)/p,
+                             level/8, p/10),
+
+where u_i mod p is the in-gridlet residue of the offset along that axis (the
+part a - a' of j up to the sign of the axis).  Weights
+theta = W1[64][8] b1[64] W2[64][64] b2[64] W3[64] b3.
 """
 import numpy as np
 
-N_PARAMS = 4609
+N_IN = 8
+N_HID = 64
+O_W1, O_B1 = 0, N_HID * N_IN
+O_W2 = O_B1 + N_HID
+O_B2 = O_W2 + N_HID * N_HID
+O_W3 = O_B2 + N_HID
+O_B3 = O_W3 + N_HID
+N_PARAMS = O_B3 + 1
 KAPPA = 1e-4
 
 
 def unpack(theta):
     t = np.asarray(theta, np.float64)
     assert t.size == N_PARAMS
-    W1 = t[0:320].reshape(64, 5)
-    b1 = t[320:384]
-    W2 = t[384:4480].reshape(64, 64)
-    b2 = t[4480:4544]
-    W3 = t[4544:4608]
-    b3 = t[4608]
+    W1 = t[O_W1:O_B1].reshape(N_HID, N_IN)
+    b1 = t[O_B1:O_W2]
+    W2 = t[O_W2:O_B2].reshape(N_HID, N_HID)
+    b2 = t[O_B2:O_W3]
+    W3 = t[O_W3:O_B3]
+    b3 = t[O_B3]
     return W1, b1, W2, b2, W3, b3
 
 
@@ -40,11 +53,11 @@ def features(j, level, p):
     K = 4.0 * p
     lev = np.full(a.shape[:-1] + (1,), level / 8.0)
     pp = np.full(a.shape[:-1] + (1,), p / 10.0)
-    return np.concatenate([a / K, lev, pp], axis=-1)
+    return np.concatenate([a / K, (a % p) / float(p), lev, pp], axis=-1)
 
 
 def forward(theta, x):
-    """Network output for feature rows x (..., 5), FP64."""
+    """Network output for feature rows x (..., N_IN), FP64."""
     W1, b1, W2, b2, W3, b3 = unpack(theta)
     h1 = silu(x @ W1.T + b1)
     h2 = silu(h1 @ W2.T + b2)

@@ -175,7 +175,8 @@ hipError_t launch_batch_toeplitz(const BatchItem* items, int nitems, unsigned* c
 // ---------------------------------------------------------------------------
 // Learned correction of the interaction-zone tables (learned.hip)
 // ---------------------------------------------------------------------------
-constexpr int kMlpParams = 4609;  // 5 -> 64 -> 64 -> 1
+constexpr int kMlpIn = 8;          // network inputs per table entry
+constexpr int kMlpParams = 4801;  // 8 -> 64 -> 64 -> 1
 hipError_t mlp_forward(const float* theta, const float* feats, int n, int bf16, float* delta,
                        hipStream_t st);
 hipError_t apply_correction(const double* g0, const float* delta, const int* uidx, int64_t n,
@@ -194,6 +195,24 @@ hipError_t adam_step(float* theta, float* m1, float* m2, float* grad, int n, flo
                      float lr, int step, hipStream_t st);
 // dst[i] += src[i], i < n
 hipError_t add_into(float* dst, const float* src, int n, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// G_* as one grid-valued function on the whole mesh (gstar.hip)
+// ---------------------------------------------------------------------------
+int gstar_orbit(int x, int y, int z, int N);  // orbit of a mesh separation
+int gstar_orbits(int N);                      // number of orbits
+struct GStarFft;
+hipError_t gstar_fft_create(int N, GStarFft** out);
+void gstar_fft_destroy(GStarFft* f);
+// near-zone table gradient (FP64 per entry of the (4s-1)^3 table)
+hipError_t gstar_near_grad(const float* r, const float* rho, int N, int s, double h3, double* g,
+                           hipStream_t st);
+// N^3 sum_t q_t rho(t - x) with q = r + 2 (loss / B)(t - mean t), stats as residual()'s
+hipError_t gstar_pm_corr(GStarFft* f, const float* r, const float* t, const float* rho,
+                         const double* stats, double* corr, hipStream_t st);
+// scale times a centred table (extent C >= N/2) at every mesh point, FP64
+hipError_t gstar_mesh_values(const double* tab, int C, int N, double scale, double* out,
+                             hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Upward / downward passes (tensor products of 1D Lagrange operators).

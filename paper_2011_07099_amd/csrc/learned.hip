@@ -4,7 +4,9 @@
 // the FMM reproduces the PM solution (Sec. 3, Eq. 8), approximates it by the
 // closed form G_S1 (Eq. 9), and suggests parameterising G_* by many values
 // and minimising the FMM-vs-PM error (Sec. 4).  Here a small MLP
-// f_theta(|j| sorted / (4p), level / 8, p / 10) gives every table entry
+// f_theta(|j| sorted / (4p), (|j| sorted mod p) / p, level / 8, p / 10) of the
+// table offset j = a - a' - p d (its cube invariants and in-gridlet residues),
+// the level and p gives every table entry
 // T_l[j] = G(eta_l j) (1 + delta), delta = kappa f_theta with the fixed output
 // scale kappa = 1e-4 (the corrections that matter are of the size of the
 // FMM-vs-PM residual), of the interaction-zone convolution (Eq. 6); the near
@@ -37,8 +39,10 @@ __device__ inline float dsilu(float z) {
 }
 __device__ inline float rb(float x, int bf16) { return bf16 ? (float)(__bf16)x : x; }
 
-// theta layout: W1[64][5] b1[64] W2[64][64] b2[64] W3[64] b3
-constexpr int oW1 = 0, oB1 = 320, oW2 = 384, oB2 = 4480, oW3 = 4544, oB3 = 4608;
+// theta layout: W1[64][kMlpIn] b1[64] W2[64][64] b2[64] W3[64] b3
+constexpr int oW1 = 0, oB1 = kH * kMlpIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
+              oB3 = oW3 + kH;
+static_assert(oB3 + 1 == kMlpParams, "network layout");
 
 // Network output for every entry; with bf16 = 1 the weights, inputs and
 // activations are rounded to bf16 before each product (FP32 accumulation).
@@ -49,12 +53,12 @@ __global__ void k_mlp_forward(const float* __restrict__ theta, const float* __re
   __syncthreads();
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  float x[5];
-  for (int k = 0; k < 5; ++k) x[k] = rb(feats[e * 5 + k], bf16);
+  float x[kMlpIn];
+  for (int k = 0; k < kMlpIn; ++k) x[k] = rb(feats[e * kMlpIn + k], bf16);
   float h1[kH];
   for (int i = 0; i < kH; ++i) {
     float z = w[oB1 + i];
-    for (int k = 0; k < 5; ++k) z += w[oW1 + i * 5 + k] * x[k];
+    for (int k = 0; k < kMlpIn; ++k) z += w[oW1 + i * kMlpIn + k] * x[k];
     h1[i] = rb(silu(z), bf16);
   }
   float out = w[oB3];
@@ -112,7 +116,8 @@ __global__ void k_resid_partial(const float* __restrict__ phi, const float* __re
   }
 }
 
-// out[0] = mean d, out[1] = loss, out[2] = norm (sum over the block partials in order)
+// out[0] = mean d, out[1] = loss, out[2] = norm, out[3] = mean t (sum over the block
+// partials in order)
 __global__ void k_resid_final(const double* __restrict__ part, int nblk, int64_t n,
                               double* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -128,6 +133,7 @@ __global__ void k_resid_final(const double* __restrict__ part, int nblk, int64_t
   out[0] = md;
   out[1] = (b - (double)n * md * md) / norm;
   out[2] = norm;
+  out[3] = mt;
 }
 
 // r = 2 (phi - t - mean) / norm  (d loss / d phi)
@@ -243,19 +249,19 @@ __global__ __launch_bounds__(64) void k_mlp_backward(const float* __restrict__ t
                                                      const float* __restrict__ ddelta, int n,
                                                      float* __restrict__ part) {
   __shared__ float w[kMlpParams];
-  __shared__ float X[64][5], H1[64][kH + 1], H2[64][kH + 1], DZ2[64][kH + 1], DZ1[64][kH + 1];
+  __shared__ float X[64][kMlpIn], H1[64][kH + 1], H2[64][kH + 1], DZ2[64][kH + 1], DZ1[64][kH + 1];
   __shared__ float DD[64];
   for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) w[i] = theta[i];
   __syncthreads();
   const int tid = threadIdx.x;
   const int e = blockIdx.x * 64 + tid;
   const bool ok = e < n;
-  float x[5], z1[kH], z2[kH];
-  for (int k = 0; k < 5; ++k) x[k] = ok ? feats[e * 5 + k] : 0.f;
+  float x[kMlpIn], z1[kH], z2[kH];
+  for (int k = 0; k < kMlpIn; ++k) x[k] = ok ? feats[e * kMlpIn + k] : 0.f;
   const float dd = ok ? kKappa * ddelta[e] : 0.f;  // d loss / d (network output)
   for (int i = 0; i < kH; ++i) {
     float z = w[oB1 + i];
-    for (int k = 0; k < 5; ++k) z += w[oW1 + i * 5 + k] * x[k];
+    for (int k = 0; k < kMlpIn; ++k) z += w[oW1 + i * kMlpIn + k] * x[k];
     z1[i] = z;
     H1[tid][i] = silu(z);
   }
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(64) void k_mlp_backward(const float* __restrict__ t
     for (int i = 0; i < kH; ++i) s += w[oW2 + i * kH + k] * DZ2[tid][i];
     DZ1[tid][k] = s * dsilu(z1[k]);
   }
-  for (int k = 0; k < 5; ++k) X[tid][k] = x[k];
+  for (int k = 0; k < kMlpIn; ++k) X[tid][k] = x[k];
   DD[tid] = dd;
   __syncthreads();
   // thread tid owns hidden unit tid: W2 row, W1 row, biases, W3 entry
@@ -282,10 +288,10 @@ __global__ __launch_bounds__(64) void k_mlp_backward(const float* __restrict__ t
     for (int r = 0; r < 64; ++r) s += DZ2[r][i] * H1[r][k];
     out[oW2 + i * kH + k] = s;
   }
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < kMlpIn; ++k) {
     float s = 0.f;
     for (int r = 0; r < 64; ++r) s += DZ1[r][i] * X[r][k];
-    out[oW1 + i * 5 + k] = s;
+    out[oW1 + i * kMlpIn + k] = s;
   }
   float b1 = 0.f, b2 = 0.f, w3 = 0.f;
   for (int r = 0; r < 64; ++r) {

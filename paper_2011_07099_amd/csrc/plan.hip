@@ -89,7 +89,7 @@ struct pfmm_plan_s {
   int nu = 0;                     // unique (|j| sorted) entries per level
   std::vector<double*> g0;        // uncorrected FP64 level tables
   std::vector<int*> uidx, optr, opos;
-  float* feats = nullptr;         // [(L-1) nu][5]
+  float* feats = nullptr;         // [(L-1) nu][kMlpIn]
   float* delta = nullptr;         // [(L-1) nu]
   float* theta = nullptr;
   float* adam_m = nullptr;
@@ -109,6 +109,27 @@ struct pfmm_plan_s {
   std::vector<double*> tgrad;     // table gradient per level (last accumulate)
   int adam_t = 0, accumulated = 0;
   double lr = 1e-3;
+  // G_* on the whole mesh (pfmm_gstar_*, allocated on first use): one relative
+  // correction per orbit of mesh separations, applied to the near table, every
+  // level's table and the direct solve's table
+  int gstar = 0;                  // 1 while the correction is set
+  int nug = 0;                    // orbits of mesh separations
+  float* gdelta = nullptr;        // [nug]
+  float* gdd = nullptr;           // gradient of one field [nug]
+  float* gacc = nullptr;          // accumulated gradient [nug]
+  std::vector<double*> gl0;       // uncorrected level tables
+  std::vector<int*> gluidx, glptr, glpos;  // per level: entry -> orbit, orbit -> entries
+  double* gn0 = nullptr;          // uncorrected near table
+  int *gnuidx = nullptr, *gnptr = nullptr, *gnpos = nullptr;
+  double* gd0 = nullptr;          // uncorrected direct table
+  int* gduidx = nullptr;
+  double* gmesh0 = nullptr;       // -G(x) / N^6 at every mesh point (PM-side gather weights)
+  int *gmptr = nullptr, *gmpos = nullptr;
+  double* gnear = nullptr;        // near-table gradient of one field
+  double* gcorr = nullptr;        // PM-side correlation (N^3)
+  float* gtarget = nullptr;       // PM potential with G_*
+  GStarFft* gfft = nullptr;
+  int gacc_n = 0;                 // fields accumulated
   // direct periodic convolution over the whole box (allocated on first use)
   double* dtab64 = nullptr;
   float* dtab32 = nullptr;
@@ -271,6 +292,8 @@ void release(pfmm_plan_s* pl) {
   pl->nfft = nullptr;
   if (pl->mspec) m2l_spectral_destroy(pl->mspec);
   pl->mspec = nullptr;
+  if (pl->gfft) gstar_fft_destroy(pl->gfft);
+  pl->gfft = nullptr;
   for (hipEvent_t e : pl->ev)
     if (e) (void)hipEventDestroy(e);
   pl->ev.clear();
@@ -351,6 +374,9 @@ pfmm_status tabulate_accel_tables(pfmm_plan_s* pl) {
   return refresh_near_fft(pl);
 }
 
+hipError_t gstar_base(pfmm_plan_s* pl);
+pfmm_status gstar_apply(pfmm_plan_s* pl);
+
 pfmm_status tabulate_all(pfmm_plan_s* pl) {
   const int p = pl->p;
   const int C = 4 * p - 1;
@@ -385,7 +411,12 @@ pfmm_status tabulate_all(pfmm_plan_s* pl) {
     e = m2l_spectral_tables(pl->mspec, pl->tab64, pl->stream);
     if (e != hipSuccess) return hip_fail(e, "spectral zone kernels");
   }
-  return pl->accel_mode ? tabulate_accel_tables(pl) : refresh_near_fft(pl);
+  pfmm_status s0 = pl->accel_mode ? tabulate_accel_tables(pl) : refresh_near_fft(pl);
+  if (s0 != PFMM_OK || !pl->gdelta) return s0;
+  // G_* follows the new G: new uncorrected copies, the correction applied again
+  e = gstar_base(pl);
+  if (e != hipSuccess) return hip_fail(e, "G_* tables");
+  return pl->gstar ? gstar_apply(pl) : PFMM_OK;
 }
 
 // Offset groups of a level's matrix-core launch: enough workgroups to give
@@ -2079,6 +2110,9 @@ int unique_count(int p) {  // sorted triples 4p-1 >= u1 >= u2 >= u3 >= 0
 
 // Allocate the correction's index maps, features and network buffers.
 pfmm_status learned_prepare(pfmm_plan_s* pl) {
+  if (pl->gstar)  // its base tables would be G_*'s
+    return fail(PFMM_ERR_INVALID_ARG,
+                "G_* is set on the whole mesh; clear it with pfmm_gstar_set first");
   if (!pl->g0.empty()) return PFMM_OK;
   const int p = pl->p, L = pl->L, C = 4 * p - 1, E = 2 * C + 1, K = 4 * p;
   const int64_t ntab = cube(E);
@@ -2115,6 +2149,9 @@ pfmm_status learned_prepare(pfmm_plan_s* pl) {
           fl.push_back((float)u1 / K);
           fl.push_back((float)u2 / K);
           fl.push_back((float)u3 / K);
+          fl.push_back((float)(u1 % p) / p);
+          fl.push_back((float)(u2 % p) / p);
+          fl.push_back((float)(u3 % p) / p);
           fl.push_back((float)l / 8.f);
           fl.push_back((float)p / 10.f);
         }
@@ -2124,8 +2161,6 @@ pfmm_status learned_prepare(pfmm_plan_s* pl) {
   pl->uidx.assign(L + 1, nullptr);
   pl->optr.assign(L + 1, nullptr);
   pl->opos.assign(L + 1, nullptr);
-  pl->lam.assign(L + 1, nullptr);
-  pl->tgrad.assign(L + 1, nullptr);
   int* d_uidx = nullptr;
   int* d_ptr = nullptr;
   int* d_pos = nullptr;
@@ -2181,18 +2216,16 @@ pfmm_status learned_apply(pfmm_plan_s* pl, int bf16) {
   return PFMM_OK;
 }
 
-pfmm_status learned_train_alloc(pfmm_plan_s* pl) {
-  if (pl->adam_m) return PFMM_OK;
+// Buffers of the adjoint sweep shared by every table-gradient mode: mesh
+// scratch, residual statistics, the adjoint per level and the table gradients.
+pfmm_status adjoint_alloc(pfmm_plan_s* pl) {
+  if (pl->resid) return PFMM_OK;
   const int N = pl->N, L = pl->L, p = pl->p;
   const size_t n3 = (size_t)N * N * N, p3 = (size_t)p * p * p;
-  const int nent = (L - 1) * pl->nu;
   const int64_t ntab = cube(8 * p - 1);
-  hipError_t e = dalloc(pl, &pl->adam_m, (size_t)kMlpParams);
-  if (e == hipSuccess) e = dalloc(pl, &pl->adam_v, (size_t)kMlpParams);
-  if (e == hipSuccess) e = dalloc(pl, &pl->wgrad, (size_t)kMlpParams);
-  if (e == hipSuccess) e = dalloc(pl, &pl->ddelta, (size_t)nent);
-  if (e == hipSuccess) e = dalloc(pl, &pl->mlp_part, mlp_backward_partial_floats(nent));
-  if (e == hipSuccess) e = dalloc(pl, &pl->resid, n3);
+  pl->lam.assign(L + 1, nullptr);
+  pl->tgrad.assign(L + 1, nullptr);
+  hipError_t e = dalloc(pl, &pl->resid, n3);
   if (e == hipSuccess) e = dalloc(pl, &pl->tphi, n3);
   if (e == hipSuccess) e = dalloc(pl, &pl->rpart, (size_t)4 * 1024);
   if (e == hipSuccess) e = dalloc(pl, &pl->rstats, (size_t)4);
@@ -2205,11 +2238,54 @@ pfmm_status learned_train_alloc(pfmm_plan_s* pl) {
     tg = std::max(tg, table_grad_partial_doubles(l == 2 ? 1 : 2, p, l == 2 ? 37 : 189));
   }
   if (e == hipSuccess) e = dalloc(pl, &pl->tgpart, tg);
+  if (e != hipSuccess) {
+    pl->resid = nullptr;
+    return hip_fail(e, "adjoint buffers");
+  }
+  return PFMM_OK;
+}
+
+pfmm_status learned_train_alloc(pfmm_plan_s* pl) {
+  if (pl->adam_m) return PFMM_OK;
+  pfmm_status s0 = adjoint_alloc(pl);
+  if (s0 != PFMM_OK) return s0;
+  const int nent = (pl->L - 1) * pl->nu;
+  hipError_t e = dalloc(pl, &pl->adam_m, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dalloc(pl, &pl->adam_v, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dalloc(pl, &pl->wgrad, (size_t)kMlpParams);
+  if (e == hipSuccess) e = dalloc(pl, &pl->ddelta, (size_t)nent);
+  if (e == hipSuccess) e = dalloc(pl, &pl->mlp_part, mlp_backward_partial_floats(nent));
   if (e == hipSuccess) e = hipMemset(pl->adam_m, 0, kMlpParams * 4);
   if (e == hipSuccess) e = hipMemset(pl->adam_v, 0, kMlpParams * 4);
   if (e == hipSuccess) e = hipMemset(pl->wgrad, 0, kMlpParams * 4);
-  if (e != hipSuccess) return hip_fail(e, "training buffers");
+  if (e != hipSuccess) {
+    pl->adam_m = nullptr;
+    return hip_fail(e, "training buffers");
+  }
   return PFMM_OK;
+}
+
+// Residual of the last forward solve (pl->tphi) against `target` into
+// pl->resid / pl->rstats, then the adjoint sweep (transposes of L2P and L2L)
+// and the gradient of the loss with respect to every entry of every level's
+// interaction-zone table into pl->tgrad.
+hipError_t adjoint_tables(pfmm_plan_s* pl, const float* target) {
+  const int N = pl->N, L = pl->L, p = pl->p;
+  const int64_t n3 = (int64_t)N * N * N;
+  hipStream_t st = pl->stream;
+  hipError_t e = residual(pl->tphi, target, n3, pl->rpart, pl->rstats, pl->resid, st);
+  if (e == hipSuccess)
+    e = launch_p2m(pl->resid, pl->lam[L], level64(pl, L), wts(pl->dA, pl->dA64), N, pl->s, p, 1.0,
+                   st);
+  for (int l = L - 1; l >= 2 && e == hipSuccess; --l)
+    e = launch_m2m(pl->lam[l + 1], level64(pl, l + 1), pl->lam[l], level64(pl, l),
+                   wts(pl->dT, pl->dT64), 1 << l, p, st);
+  for (int l = 2; l <= L && e == hipSuccess; ++l) {
+    const int m = l == 2 ? 1 : 2, noff = l == 2 ? 37 : 189;
+    e = table_grad(1 << l, m, p, noff, l == 2 ? pl->offs_l2 : pl->offs_iz, pl->lam[l], pl->M[l],
+                   level64(pl, l), 4 * p - 1, pl->tgpart, pl->tgrad[l], st);
+  }
+  return e;
 }
 
 pfmm_status direct_prepare(pfmm_plan_s* pl) {
@@ -2238,6 +2314,188 @@ pfmm_status direct_prepare(pfmm_plan_s* pl) {
   pl->dq = q;
   pl->dC = C;
   pl->dnoff = (int)offs.size();
+  return PFMM_OK;
+}
+
+// The exact periodic convolution with the plan's direct table (prepared).
+hipError_t direct_launch(pfmm_plan_s* pl, const float* rho, float* phi) {
+  ToepArgs a{};
+  a.n = pl->N / pl->dq;
+  a.m = 1;
+  a.q = pl->dq;
+  a.noff = pl->dnoff;
+  a.offs = pl->doffs;
+  a.tab = pl->dtab32;
+  a.C = pl->dC;
+  a.X = rho;
+  a.Y = phi;
+  a.grid_in = 1;
+  a.grid_out = 1;
+  a.xscale = 1.0 / ((double)pl->N * pl->N * pl->N);
+  a.accumulate = 0;
+  a.groups = 1;
+  return launch_toeplitz(a, pl->stream);
+}
+
+// --- G_* on the whole mesh -------------------------------------------------
+
+pfmm_status gstar_check(pfmm_plan_s* pl) {
+  if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "G_* of an isolated plan");
+  if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "G_* with FFT interaction zones");
+  if (pl->accel_mode)
+    return fail(PFMM_ERR_UNSUPPORTED, "G_* with accelerations from the expansion");
+  if (pl->s % pl->p)
+    return fail(PFMM_ERR_UNSUPPORTED, "G_* on the mesh needs p to divide the leaf width");
+  if (pl->learned)
+    return fail(PFMM_ERR_INVALID_ARG,
+                "the interaction-zone tables carry a learned correction; clear it first");
+  return PFMM_OK;
+}
+
+// orbit -> entries (CSR) of an entry -> orbit map
+void orbit_csr(const std::vector<int>& uidx, int nu, std::vector<int>& ptr, std::vector<int>& pos) {
+  ptr.assign(nu + 1, 0);
+  for (int u : uidx) ++ptr[u + 1];
+  for (int u = 0; u < nu; ++u) ptr[u + 1] += ptr[u];
+  pos.assign(uidx.size(), 0);
+  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  for (size_t i = 0; i < uidx.size(); ++i) pos[fill[uidx[i]]++] = (int)i;
+}
+
+template <class T>
+hipError_t upload(pfmm_plan_s* pl, T** dst, const std::vector<T>& v) {
+  hipError_t e = dalloc(pl, dst, v.size());
+  if (e == hipSuccess) e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+// Uncorrected copies of every table G_* replaces, from the current tables.
+hipError_t gstar_base(pfmm_plan_s* pl) {
+  const int p = pl->p, N = pl->N;
+  const int64_t nlev = cube(8 * p - 1), nnear = cube(4 * pl->s - 1), ndir = cube(2 * pl->dC + 1);
+  hipStream_t st = pl->stream;
+  hipError_t e = hipSuccess;
+  for (int l = 2; l <= pl->L && e == hipSuccess; ++l)
+    e = hipMemcpyAsync(pl->gl0[l], pl->tab64[l], nlev * sizeof(double), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(pl->gn0, pl->ntab64, nnear * sizeof(double), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(pl->gd0, pl->dtab64, ndir * sizeof(double), hipMemcpyDeviceToDevice, st);
+  const double n6 = (double)N * N * N * (double)N * N * N;
+  if (e == hipSuccess) e = gstar_mesh_values(pl->gd0, pl->dC, N, -1.0 / n6, pl->gmesh0, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+pfmm_status gstar_prepare(pfmm_plan_s* pl) {
+  if (pl->gdelta) return PFMM_OK;
+  pfmm_status s0 = direct_prepare(pl);
+  if (s0 == PFMM_OK) s0 = adjoint_alloc(pl);
+  if (s0 != PFMM_OK) return s0;
+  const int N = pl->N, L = pl->L, p = pl->p, s = pl->s;
+  const int nu = gstar_orbits(N);
+  std::vector<int> ptr, pos;
+  hipError_t e = hipSuccess;
+  pl->gl0.assign(L + 1, nullptr);
+  pl->gluidx.assign(L + 1, nullptr);
+  pl->glptr.assign(L + 1, nullptr);
+  pl->glpos.assign(L + 1, nullptr);
+  // level tables: entry j is the mesh separation j (N / 2^l) / p
+  for (int l = 2; l <= L && e == hipSuccess; ++l) {
+    const int C = 4 * p - 1, E = 2 * C + 1, w = (N >> l) / p;
+    std::vector<int> u((size_t)E * E * E);
+    for (int x = 0; x < E; ++x)
+      for (int y = 0; y < E; ++y)
+        for (int z = 0; z < E; ++z)
+          u[((size_t)x * E + y) * E + z] = gstar_orbit((x - C) * w, (y - C) * w, (z - C) * w, N);
+    orbit_csr(u, nu, ptr, pos);
+    e = upload(pl, &pl->gluidx[l], u);
+    if (e == hipSuccess) e = upload(pl, &pl->glptr[l], ptr);
+    if (e == hipSuccess) e = upload(pl, &pl->glpos[l], pos);
+    if (e == hipSuccess) e = dalloc(pl, &pl->gl0[l], u.size());
+  }
+  // near table: entry m is the mesh separation m
+  if (e == hipSuccess) {
+    const int C = 2 * s - 1, E = 2 * C + 1;
+    std::vector<int> u((size_t)E * E * E);
+    for (int x = 0; x < E; ++x)
+      for (int y = 0; y < E; ++y)
+        for (int z = 0; z < E; ++z)
+          u[((size_t)x * E + y) * E + z] = gstar_orbit(x - C, y - C, z - C, N);
+    orbit_csr(u, nu, ptr, pos);
+    e = upload(pl, &pl->gnuidx, u);
+    if (e == hipSuccess) e = upload(pl, &pl->gnptr, ptr);
+    if (e == hipSuccess) e = upload(pl, &pl->gnpos, pos);
+    if (e == hipSuccess) e = dalloc(pl, &pl->gn0, u.size());
+    if (e == hipSuccess) e = dalloc(pl, &pl->gnear, u.size());
+  }
+  // direct table (periodic images of the same separations share an orbit)
+  if (e == hipSuccess) {
+    const int C = pl->dC, E = 2 * C + 1;
+    std::vector<int> u((size_t)E * E * E);
+    for (int x = 0; x < E; ++x)
+      for (int y = 0; y < E; ++y)
+        for (int z = 0; z < E; ++z)
+          u[((size_t)x * E + y) * E + z] = gstar_orbit(x - C, y - C, z - C, N);
+    e = upload(pl, &pl->gduidx, u);
+    if (e == hipSuccess) e = dalloc(pl, &pl->gd0, u.size());
+  }
+  // every mesh point, for the PM side of the gradient
+  if (e == hipSuccess) {
+    std::vector<int> u((size_t)N * N * N);
+    for (int x = 0; x < N; ++x)
+      for (int y = 0; y < N; ++y)
+        for (int z = 0; z < N; ++z) u[((size_t)x * N + y) * N + z] = gstar_orbit(x, y, z, N);
+    orbit_csr(u, nu, ptr, pos);
+    e = upload(pl, &pl->gmptr, ptr);
+    if (e == hipSuccess) e = upload(pl, &pl->gmpos, pos);
+    if (e == hipSuccess) e = dalloc(pl, &pl->gmesh0, u.size());
+    if (e == hipSuccess) e = dalloc(pl, &pl->gcorr, u.size());
+    if (e == hipSuccess) e = dalloc(pl, &pl->gtarget, u.size());
+  }
+  if (e == hipSuccess) e = dalloc(pl, &pl->gdd, (size_t)nu);
+  if (e == hipSuccess) e = dalloc(pl, &pl->gacc, (size_t)nu);
+  if (e == hipSuccess) e = hipMemset(pl->gacc, 0, (size_t)nu * sizeof(float));
+  if (e == hipSuccess) e = gstar_fft_create(N, &pl->gfft);
+  if (e == hipSuccess) e = gstar_base(pl);
+  float* d = nullptr;
+  if (e == hipSuccess) e = dalloc(pl, &d, (size_t)nu);
+  if (e == hipSuccess) e = hipMemset(d, 0, (size_t)nu * sizeof(float));
+  if (e != hipSuccess) return hip_fail(e, "G_* buffers");
+  pl->nug = nu;
+  pl->gdelta = d;  // set last: marks the state complete
+  return PFMM_OK;
+}
+
+// Every table from G_* = G (1 + delta[orbit]), and what is derived from them.
+pfmm_status gstar_apply(pfmm_plan_s* pl) {
+  const int p = pl->p, C = 4 * p - 1;
+  const int64_t nlev = cube(2 * C + 1), nnear = cube(4 * pl->s - 1), ndir = cube(2 * pl->dC + 1);
+  hipStream_t st = pl->stream;
+  hipError_t e = hipSuccess;
+  for (int l = 2; l <= pl->L && e == hipSuccess; ++l) {
+    e = apply_correction(pl->gl0[l], pl->gdelta, pl->gluidx[l], nlev, pl->tab64[l], pl->tab32[l],
+                         st);
+    if (e == hipSuccess && pl->win[l]) e = make_windows(pl->tab64[l], C, kM2LTerms, pl->win[l], st);
+  }
+  if (e == hipSuccess)
+    e = apply_correction(pl->gn0, pl->gdelta, pl->gnuidx, nnear, pl->ntab64, pl->ntab32, st);
+  if (e == hipSuccess && pl->nwin)
+    e = make_windows(pl->ntab64, 2 * pl->s - 1, kNearTerms, pl->nwin, st);
+  if (e == hipSuccess)
+    e = apply_correction(pl->gd0, pl->gdelta, pl->gduidx, ndir, pl->dtab64, pl->dtab32, st);
+  if (e == hipSuccess && pl->mspec) e = m2l_spectral_tables(pl->mspec, pl->tab64, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "apply G_*");
+  return refresh_near_fft(pl);
+}
+
+// Forward solve with G_*, its PM potential, and the residual statistics.
+pfmm_status gstar_forward(pfmm_plan_s* pl, const float* rho) {
+  pfmm_status s0 = solve_impl(pl, rho, pl->tphi, nullptr);
+  if (s0 != PFMM_OK) return s0;
+  const hipError_t e = direct_launch(pl, rho, pl->gtarget);
+  if (e != hipSuccess) return hip_fail(e, "PM potential with G_*");
   return PFMM_OK;
 }
 
@@ -2273,30 +2531,19 @@ pfmm_status pfmm_plan_direct(pfmm_plan_t h, const float* rho, float* phi) {
   if (!pl->dtab64 && capturing(pl->stream)) return capture_fail("the first pfmm_plan_direct");
   pfmm_status s0 = direct_prepare(pl);
   if (s0 != PFMM_OK) return s0;
-  ToepArgs a{};
-  a.n = pl->N / pl->dq;
-  a.m = 1;
-  a.q = pl->dq;
-  a.noff = pl->dnoff;
-  a.offs = pl->doffs;
-  a.tab = pl->dtab32;
-  a.C = pl->dC;
-  a.X = rho;
-  a.Y = phi;
-  a.grid_in = 1;
-  a.grid_out = 1;
-  a.xscale = 1.0 / ((double)pl->N * pl->N * pl->N);
-  a.accumulate = 0;
-  a.groups = 1;
-  const hipError_t e = launch_toeplitz(a, pl->stream);
+  const hipError_t e = direct_launch(pl, rho, phi);
   if (e != hipSuccess) return hip_fail(e, "direct solve");
   return PFMM_OK;
 }
+
 
 pfmm_status pfmm_learned_set(pfmm_plan_t h, const float* weights, int bf16) {
   g_err.clear();
   pfmm_plan_s* pl = plan_of(h);
   if (!pl) return bad_plan();
+  if (pl->gstar)
+    return fail(PFMM_ERR_INVALID_ARG,
+                "G_* is set on the whole mesh; clear it with pfmm_gstar_set first");
   if (capturing(pl->stream)) return capture_fail("pfmm_learned_set");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
   if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
@@ -2317,6 +2564,9 @@ pfmm_status pfmm_learned_train_begin(pfmm_plan_t h, const float* weights, double
   g_err.clear();
   pfmm_plan_s* pl = plan_of(h);
   if (!pl) return bad_plan();
+  if (pl->gstar)
+    return fail(PFMM_ERR_INVALID_ARG,
+                "G_* is set on the whole mesh; clear it with pfmm_gstar_set first");
   if (capturing(pl->stream)) return capture_fail("pfmm_learned_train_begin");
   if (pl->isolated) return fail(PFMM_ERR_UNSUPPORTED, "learned tables of an isolated plan");
   if (pl->m2l_fft) return fail(PFMM_ERR_UNSUPPORTED, "learned tables with FFT interaction zones");
@@ -2350,24 +2600,12 @@ pfmm_status pfmm_learned_accumulate(pfmm_plan_t h, const float* rho, const float
   hipStream_t st = pl->stream;
   pfmm_status s0 = solve_impl(pl, rho, pl->tphi, nullptr);
   if (s0 != PFMM_OK) return s0;
-  hipError_t e = residual(pl->tphi, target, n3, pl->rpart, pl->rstats, pl->resid, st);
-  // adjoint sweep: transposes of L2P and L2L
-  if (e == hipSuccess)
-    e = launch_p2m(pl->resid, pl->lam[L], level64(pl, L), wts(pl->dA, pl->dA64), N, pl->s, p, 1.0,
-                   st);
-  for (int l = L - 1; l >= 2 && e == hipSuccess; --l)
-    e = launch_m2m(pl->lam[l + 1], level64(pl, l + 1), pl->lam[l], level64(pl, l),
-                   wts(pl->dT, pl->dT64), 1 << l, p, st);
+  hipError_t e = adjoint_tables(pl, target);
   const int nent = (L - 1) * pl->nu;
   if (e == hipSuccess) e = hipMemsetAsync(pl->ddelta, 0, nent * sizeof(float), st);
-  for (int l = 2; l <= L && e == hipSuccess; ++l) {
-    const int m = l == 2 ? 1 : 2, noff = l == 2 ? 37 : 189;
-    e = table_grad(1 << l, m, p, noff, l == 2 ? pl->offs_l2 : pl->offs_iz, pl->lam[l], pl->M[l],
-                   level64(pl, l), 4 * p - 1, pl->tgpart, pl->tgrad[l], st);
-    if (e == hipSuccess)
-      e = orbit_gather(pl->tgrad[l], pl->g0[l], pl->optr[l], pl->opos[l], pl->nu,
-                       pl->ddelta + (size_t)(l - 2) * pl->nu, st);
-  }
+  for (int l = 2; l <= L && e == hipSuccess; ++l)
+    e = orbit_gather(pl->tgrad[l], pl->g0[l], pl->optr[l], pl->opos[l], pl->nu,
+                     pl->ddelta + (size_t)(l - 2) * pl->nu, st);
   if (e == hipSuccess) {
     if (pl->learned == 3)  // grid-valued tables: ddelta is the parameters' gradient
       e = add_into(pl->ggrad, pl->ddelta, nent, st);
@@ -2444,6 +2682,9 @@ pfmm_status pfmm_table_set(pfmm_plan_t h, const float* delta) {
   g_err.clear();
   pfmm_plan_s* pl = plan_of(h);
   if (!pl) return bad_plan();
+  if (pl->gstar)
+    return fail(PFMM_ERR_INVALID_ARG,
+                "G_* is set on the whole mesh; clear it with pfmm_gstar_set first");
   if (capturing(pl->stream)) return capture_fail("pfmm_table_set");
   if (!delta) return pfmm_learned_set(h, nullptr, 0);
   int n = 0;
@@ -2489,6 +2730,9 @@ pfmm_status pfmm_table_train_begin(pfmm_plan_t h, double lr) {
   g_err.clear();
   pfmm_plan_s* pl = plan_of(h);
   if (!pl) return bad_plan();
+  if (pl->gstar)
+    return fail(PFMM_ERR_INVALID_ARG,
+                "G_* is set on the whole mesh; clear it with pfmm_gstar_set first");
   if (capturing(pl->stream)) return capture_fail("pfmm_table_train_begin");
   if (!(lr > 0.0)) return fail(PFMM_ERR_INVALID_ARG, "need lr > 0");
   int n = 0;
@@ -2538,6 +2782,123 @@ pfmm_status pfmm_learned_read_grad(pfmm_plan_t h, int level, double* table_grad,
   if (e == hipSuccess && weight_grad)
     e = hipMemcpy(weight_grad, pl->wgrad, kMlpParams * sizeof(float), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "read gradient");
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_gstar_params(pfmm_plan_t h, int* count) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (!count) return fail(PFMM_ERR_INVALID_ARG, "count is NULL");
+  const pfmm_status s0 = gstar_check(pl);
+  if (s0 != PFMM_OK) return s0;
+  *count = gstar_orbits(pl->N);
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_gstar_set(pfmm_plan_t h, const float* delta) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_gstar_set");
+  if (!delta) {  // back to G everywhere
+    if (!pl->gstar) return PFMM_OK;
+    const hipError_t e = hipMemset(pl->gdelta, 0, (size_t)pl->nug * sizeof(float));
+    if (e != hipSuccess) return hip_fail(e, "clear G_*");
+    pl->gstar = 0;
+    return gstar_apply(pl);
+  }
+  pfmm_status s0 = gstar_check(pl);
+  if (s0 == PFMM_OK) s0 = gstar_prepare(pl);
+  if (s0 != PFMM_OK) return s0;
+  const hipError_t e =
+      hipMemcpy(pl->gdelta, delta, (size_t)pl->nug * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload G_*");
+  pl->gstar = 1;
+  return gstar_apply(pl);
+}
+
+pfmm_status pfmm_gstar_get(pfmm_plan_t h, float* delta) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_gstar_get");
+  if (!delta) return fail(PFMM_ERR_INVALID_ARG, "delta is NULL");
+  if (!pl->gdelta) return fail(PFMM_ERR_INVALID_ARG, "the plan has no G_* values");
+  const hipError_t e =
+      hipMemcpy(delta, pl->gdelta, (size_t)pl->nug * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "download G_*");
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_gstar_loss(pfmm_plan_t h, const float* rho, double* loss) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_gstar_loss");
+  if (!rho || !loss) return fail(PFMM_ERR_INVALID_ARG, "NULL argument");
+  pfmm_status s0 = gstar_check(pl);
+  if (s0 == PFMM_OK) s0 = gstar_prepare(pl);
+  if (s0 == PFMM_OK) s0 = gstar_forward(pl, rho);
+  if (s0 != PFMM_OK) return s0;
+  const int64_t n3 = (int64_t)pl->N * pl->N * pl->N;
+  double stats[4] = {0, 0, 0, 0};
+  hipError_t e = residual(pl->tphi, pl->gtarget, n3, pl->rpart, pl->rstats, pl->resid, pl->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(stats, pl->rstats, sizeof stats, hipMemcpyDeviceToHost, pl->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) return hip_fail(e, "G_* loss");
+  *loss = stats[1];
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_gstar_accumulate(pfmm_plan_t h, const float* rho, double* loss) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_gstar_accumulate");
+  if (!rho) return fail(PFMM_ERR_INVALID_ARG, "density is NULL");
+  pfmm_status s0 = gstar_check(pl);
+  if (s0 == PFMM_OK) s0 = gstar_prepare(pl);
+  if (s0 == PFMM_OK) s0 = gstar_forward(pl, rho);
+  if (s0 != PFMM_OK) return s0;
+  const int N = pl->N, nu = pl->nug;
+  hipStream_t st = pl->stream;
+  // the FMM side: adjoint sweep and level-table gradients, then the near table
+  hipError_t e = adjoint_tables(pl, pl->gtarget);
+  if (e == hipSuccess) e = hipMemsetAsync(pl->gdd, 0, (size_t)nu * sizeof(float), st);
+  for (int l = 2; l <= pl->L && e == hipSuccess; ++l)
+    e = orbit_gather(pl->tgrad[l], pl->gl0[l], pl->glptr[l], pl->glpos[l], nu, pl->gdd, st);
+  const double h3 = 1.0 / ((double)N * N * N);
+  if (e == hipSuccess) e = gstar_near_grad(pl->resid, rho, N, pl->s, h3, pl->gnear, st);
+  if (e == hipSuccess) e = orbit_gather(pl->gnear, pl->gn0, pl->gnptr, pl->gnpos, nu, pl->gdd, st);
+  // the PM side (its weights carry -1 / N^6: h^3 and the unnormalised FFT)
+  if (e == hipSuccess)
+    e = gstar_pm_corr(pl->gfft, pl->resid, pl->gtarget, rho, pl->rstats, pl->gcorr, st);
+  if (e == hipSuccess)
+    e = orbit_gather(pl->gcorr, pl->gmesh0, pl->gmptr, pl->gmpos, nu, pl->gdd, st);
+  if (e == hipSuccess) e = add_into(pl->gacc, pl->gdd, nu, st);
+  double stats[4] = {0, 0, 0, 0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(stats, pl->rstats, sizeof stats, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "G_* gradient");
+  ++pl->gacc_n;
+  if (loss) *loss = stats[1];
+  return PFMM_OK;
+}
+
+pfmm_status pfmm_gstar_grad(pfmm_plan_t h, float* grad) {
+  g_err.clear();
+  pfmm_plan_s* pl = plan_of(h);
+  if (!pl) return bad_plan();
+  if (capturing(pl->stream)) return capture_fail("pfmm_gstar_grad");
+  if (!grad) return fail(PFMM_ERR_INVALID_ARG, "grad is NULL");
+  if (!pl->gdelta || pl->gacc_n == 0) return fail(PFMM_ERR_INVALID_ARG, "no accumulated gradient");
+  hipError_t e = hipMemcpy(grad, pl->gacc, (size_t)pl->nug * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(pl->gacc, 0, (size_t)pl->nug * sizeof(float));
+  if (e != hipSuccess) return hip_fail(e, "G_* gradient");
+  pl->gacc_n = 0;
   return PFMM_OK;
 }
 

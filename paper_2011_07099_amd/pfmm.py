@@ -33,8 +33,10 @@ EXPORTS = ("pfmm_plan_create", "pfmm_plan_set", "pfmm_solve", "pfmm_solve_f64", 
            "pfmm_learned_train_begin",
            "pfmm_learned_accumulate", "pfmm_learned_loss", "pfmm_learned_step", "pfmm_learned_get",
            "pfmm_learned_read_grad", "pfmm_table_params", "pfmm_table_set", "pfmm_table_get",
-           "pfmm_table_train_begin", "pfmm_table_grad", "pfmm_last_error")
-MLP_PARAMS = 4609
+           "pfmm_table_train_begin", "pfmm_table_grad", "pfmm_gstar_params", "pfmm_gstar_set",
+           "pfmm_gstar_get", "pfmm_gstar_loss", "pfmm_gstar_accumulate", "pfmm_gstar_grad",
+           "pfmm_last_error")
+MLP_PARAMS = 4801
 
 _lib = None
 
@@ -87,6 +89,12 @@ def load():
     lib.pfmm_table_get.argtypes = [vp, fp]
     lib.pfmm_table_train_begin.argtypes = [vp, ctypes.c_double]
     lib.pfmm_table_grad.argtypes = [vp, fp]
+    lib.pfmm_gstar_params.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.pfmm_gstar_set.argtypes = [vp, fp]
+    lib.pfmm_gstar_get.argtypes = [vp, fp]
+    lib.pfmm_gstar_loss.argtypes = [vp, vp, dp]
+    lib.pfmm_gstar_accumulate.argtypes = [vp, vp, dp]
+    lib.pfmm_gstar_grad.argtypes = [vp, fp]
     lib.pfmm_learned_step.argtypes = [vp]
     lib.pfmm_learned_get.argtypes = [vp, fp]
     lib.pfmm_learned_read_grad.argtypes = [vp, i32, dp, fp]
@@ -315,6 +323,51 @@ class Plan:
         import numpy as np
         g = np.empty(self.table_params(), np.float32)
         _check(load().pfmm_table_grad(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return g
+
+    # --- G_* as one grid-valued function everywhere (Eq. 8) ----------------
+    def gstar_params(self):
+        """Number of free values of G_* (one per cube-symmetry orbit of mesh
+        separations)."""
+        n = ctypes.c_int()
+        _check(load().pfmm_gstar_params(self._h, ctypes.byref(n)))
+        return n.value
+
+    def set_gstar(self, delta):
+        """G_* = G (1 + delta[orbit]) in the near zone, every level's tables
+        and the direct solve; None restores G everywhere."""
+        import numpy as np
+        if delta is None:
+            _check(load().pfmm_gstar_set(self._h, None))
+            return
+        d = np.ascontiguousarray(delta, np.float32)
+        if d.size != self.gstar_params():
+            raise ValueError("delta must have %d entries" % self.gstar_params())
+        _check(load().pfmm_gstar_set(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def gstar_values(self):
+        import numpy as np
+        d = np.empty(self.gstar_params(), np.float32)
+        _check(load().pfmm_gstar_get(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return d
+
+    def gstar_loss(self, rho):
+        """Relative mean-removed squared residual of the FMM against PM, both
+        with the plan's G_*."""
+        v = ctypes.c_double()
+        _check(load().pfmm_gstar_loss(self._h, _ptr(rho), ctypes.byref(v)))
+        return v.value
+
+    def gstar_accumulate(self, rho):
+        v = ctypes.c_double()
+        _check(load().pfmm_gstar_accumulate(self._h, _ptr(rho), ctypes.byref(v)))
+        return v.value
+
+    def gstar_grad(self):
+        """Gradient summed over the accumulated densities (clears it)."""
+        import numpy as np
+        g = np.empty(self.gstar_params(), np.float32)
+        _check(load().pfmm_gstar_grad(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return g
 
     def train_begin(self, weights, lr):

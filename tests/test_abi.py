@@ -95,6 +95,10 @@ def test_bad_handles():
         assert lib.pfmm_plan_destroy(h) == 6
         assert lib.pfmm_plan_set(h, 1, ctypes.byref(ctypes.c_int32(0)), 4) == 6
         assert lib.pfmm_plan_info(h, None, None) == 6
+        n = ctypes.c_int32()
+        assert lib.pfmm_gstar_params(h, ctypes.byref(n)) == 6
+        assert lib.pfmm_gstar_set(h, None) == 6
+        assert lib.pfmm_gstar_loss(h, None, None) == 6
         assert "handle" in lib.pfmm_last_error().decode()
     assert lib.pfmm_plan_destroy(None) == 0
     assert lib.pfmm_plan_create(16, 3, 4, 2, None) == 1

@@ -7,8 +7,10 @@
   residual it differentiates carries ~1e-7 |phi| of rounding against a
   residual of ~1e-3 |phi| at p = 4: tolerance 1e-3 relative.
 * Fallback and inference: zero output layer = plain G; NULL restores G.
-* Training: the loss falls, and the trained network lowers the FMM-vs-PM
-  error on unseen fields (PM with the same G from the oracle as the reference).
+* Training: Adam lowers the loss; the exact output-layer fit (the loss is
+  quadratic in the output layer) lowers the FMM-vs-PM error on unseen 64^3
+  and 128^3 fields, with PM(G_S1) from the oracle as the judge and the
+  library's BF16 inference tables.
 """
 import numpy as np
 import pytest
@@ -40,7 +42,7 @@ def test_gradients_match_finite_differences_of_the_oracle():
     target = f32(conv.pm(rho, "S1"))
     rng = np.random.default_rng(5)
     theta = rng.standard_normal(omlp.N_PARAMS).astype(np.float32) * 0.05
-    theta[4544:4608] = rng.standard_normal(64).astype(np.float32) * 200.0
+    theta[omlp.O_W3:omlp.O_B3] = rng.standard_normal(64).astype(np.float32) * 200.0
     theta = theta.astype(np.float64).astype(np.float32)
     th64 = theta.astype(np.float64)
     with Plan(N, L, p, "S1") as pl:
@@ -81,7 +83,7 @@ def test_gradients_match_finite_differences_of_the_oracle():
             tab[J, J, J] = 0.0
             tb[l] = (omlp.corrected_table(tab, l, p, th), J)
         return _oracle_loss(rho, L, p, tb, target)
-    for k in (3, 330, 400, 4481, 4550, 4608):
+    for k in (3, omlp.O_B1 + 10, omlp.O_W2 + 16, omlp.O_B2 + 1, omlp.O_W3 + 6, omlp.O_B3):
         eps = 1e-4
         a = th64.copy(); a[k] += eps
         b = th64.copy(); b[k] -= eps
@@ -104,7 +106,7 @@ def test_fallback_and_inference():
             pl.solve(rho, phi)
             outs.append(phi.cpu())
         th = init_weights(2)
-        th[4544:4608] = 100.0
+        th[omlp.O_W3:omlp.O_B3] = 100.0
         pl.set_learned(th)
         t64 = pl.level_table(3).cpu().numpy()
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
@@ -149,3 +151,34 @@ def test_training_reduces_loss_and_reports_gain_on_unseen_fields():
     gain = errs["G_S1"] / errs["learned"]
     print("unseen mean relative L2^2 error", errs, "gain", gain)
     assert errs["learned"] <= errs["G_S1"] * (1 + 1e-3)
+
+
+def test_output_layer_fit_gains_on_unseen_fields():
+    # 16 training fields of 64^3 at p = 6, the hidden layers at their random
+    # initialisation (first-layer scale 8), the output layer solved exactly;
+    # measured gains 1.034 (64^3) and 1.029 (128^3), at the level of the
+    # grid-valued tables' 1.027 with 2 x 2600 free values
+    import torch
+    from paper_2011_07099_amd.learned import fit_output
+    from paper_2011_07099_amd.pfmm import Plan
+    L, p = 3, 6
+    w, info = fit_output(N=64, L=L, p=p, n_fields=16, n_valid=8, seed0=40000, seed=0)
+    print("output-layer fit:", {k: v for k, v in info.items() if k != "fits"})
+    assert info["ridge"] is not None
+    gains = {}
+    for N, n, seed0 in ((64, 4, 50000), (128, 2, 60000)):
+        errs = {}
+        for name, weights in (("G_S1", None), ("learned", w)):
+            e = []
+            with Plan(N, L, p, "S1") as pl:
+                pl.set_learned(weights)         # BF16 inference
+                for i in range(n):
+                    rho = f32(fields.lognormal(N, 2.0, 1.0, seed=seed0 + i))
+                    r = torch.from_numpy(rho.astype(np.float32)).cuda()
+                    phi = torch.empty_like(r)
+                    pl.solve(r, phi)
+                    e.append(_loss(phi.cpu().numpy().astype(np.float64), conv.pm(rho, "S1")))
+            errs[name] = float(np.mean(e))
+        gains[N] = errs["G_S1"] / errs["learned"]
+        print("%d^3 unseen: %s, gain %.4f" % (N, errs, gains[N]))
+    assert gains[64] > 1.01 and gains[128] > 1.005

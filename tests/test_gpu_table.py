@@ -80,12 +80,16 @@ def test_random_delta_matches_oracle_operator():
     assert e < 1e-5 and rel_max(ref, plain) > 10 * e
 
 
-def test_table_fit_lowers_loss():
+@pytest.mark.parametrize("N,p,n_fields,iters", [(64, 6, 24, 6), (128, 8, 6, 4)])
+def test_table_fit_lowers_loss(N, p, n_fields, iters):
+    # p = 8: every orbit of the (8p - 1)^3 table of levels 2 and 3 (5984 per
+    # level), the size Sec. 4 names for N_g = 8; 16^3-cell leaves, since with
+    # 8^3-cell leaves (s = p) the FMM matches PM to FP32 rounding already
     import torch
     from paper_2011_07099_amd.learned import fit_table
     from paper_2011_07099_amd.pfmm import Plan
-    N, L, p = 64, 3, 6
-    d, hist = fit_table(N=N, L=L, p=p, n_fields=24, iters=6, seed0=40000)
+    L = 3
+    d, hist = fit_table(N=N, L=L, p=p, n_fields=n_fields, iters=iters, seed0=40000)
     print("grid-valued tables (conjugate gradients): training loss", hist,
           "max |delta|", float(np.abs(d).max()))
     assert len(hist) > 1 and all(b < a for a, b in zip(hist, hist[1:]))
@@ -108,5 +112,5 @@ def test_table_fit_lowers_loss():
                 pl.solve(r, phi)
                 e.append(loss(phi.cpu().numpy().astype(np.float64), conv.pm(rho, "S1")))
         errs[name] = float(np.mean(e))
-    print("unseen mean relative L2^2 error", errs, "gain", errs["G_S1"] / errs["grid"])
+    print("p = %d: unseen mean relative L2^2 error" % p, errs, "gain", errs["G_S1"] / errs["grid"])
     assert errs["grid"] <= errs["G_S1"] * (1 + 1e-3)
