@@ -184,6 +184,11 @@ __device__ __forceinline__ float2 tw(int j) {
   return make_float2(cos32(j * r), sin32(j * r));
 }
 
+// Fourth word of a raw buffer resource (32-bit data format, no swizzle) and
+// the two-dword vector the 64-bit buffer builtins move.
+constexpr int kBufferDword3 = 0x00020000;
+typedef unsigned v2u32 __attribute__((ext_vector_type(2)));
+
 // Address of frequency f of leaf `leaf` in the chunked spectrum layout:
 // [F / 64][leaves][64].
 __device__ __forceinline__ int64_t chunk_addr(int f, int64_t leaf, int64_t nleaf) {
@@ -256,57 +261,60 @@ constexpr int leaf_threads() { return (S * (S + 1) + 63) / 64 * 64; }
 // X[kx][ky][kz], kz <= s, written in the chunked layout.  z: direct real DFT
 // of the s inputs to s + 1 outputs.  y and x: s inputs to 2s outputs, split
 // by output parity, X[2m] = DFT_s(u)[m] and X[2m + 1] = DFT_s(u_n w^n)[m]
-// with w = exp(-2 pi i / 2s); the y pass runs once per parity of ky so that
-// LDS holds one half of its output at a time.
+// with w = exp(-2 pi i / 2s).  The work runs once per parity of ky in one
+// LDS buffer of s^2 (s + 1) values: the z pass fills it, the y pass of that
+// parity transforms every (x, kz) column in place (one thread per column),
+// the x pass reads it out.  The second parity redoes the z pass from the
+// mesh (its rows are still in L2) instead of keeping a second buffer, so
+// four leaves fit in a CU's LDS at s = 16.
 template <int S>
 __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __restrict__ rho, int N, int lgnb,
                                                         int64_t nleaf, float2* __restrict__ rhat) {
   constexpr int M = 2 * S, H = S + 1;
-  __shared__ float2 A1[S * S * H];  // [x][y][kz]
-  __shared__ float2 A2[S * S * H];  // [x][m][kz], ky = 2m + parity
+  __shared__ float2 A[S * S * H];  // [x][y][kz], then [x][m][kz] with ky = 2m + parity
   const int64_t leaf = blockIdx.x;
   const int msk = (1 << lgnb) - 1;
   const int bz = (int)(leaf & msk), by = (int)((leaf >> lgnb) & msk), bx = (int)(leaf >> (2 * lgnb));
-  for (int r = threadIdx.x; r < S * S; r += leaf_threads<S>()) {
-    const int x = r / S, y = r % S;
-    const float4* src = reinterpret_cast<const float4*>(
-        rho + ((int64_t)(bx * S + x) * N + (by * S + y)) * N + (int64_t)bz * S);
-    // kz = 2m: DFT_s of the row; kz = 2m + 1: DFT_s of the row times w^z
-    float2 e[S], o[S];
-#pragma unroll
-    for (int q = 0; q < S / 4; ++q) {
-      const float4 a = src[q];
-      e[4 * q] = make_float2(a.x, 0.0f);
-      e[4 * q + 1] = make_float2(a.y, 0.0f);
-      e[4 * q + 2] = make_float2(a.z, 0.0f);
-      e[4 * q + 3] = make_float2(a.w, 0.0f);
-    }
-#pragma unroll
-    for (int z = 0; z < S; ++z) o[z] = twiddle<M, false>(e[z], z);
-    dft<S, false>(e);
-    dft<S, false>(o);
-    float2* row = A1 + (x * S + y) * H;
-#pragma unroll
-    for (int m = 0; m < S / 2; ++m) {
-      row[2 * m] = e[m];
-      row[2 * m + 1] = o[m];
-    }
-    row[S] = e[S / 2];
-  }
-  __syncthreads();
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
+    for (int r = threadIdx.x; r < S * S; r += leaf_threads<S>()) {
+      const int x = r / S, y = r % S;
+      const float4* src = reinterpret_cast<const float4*>(
+          rho + ((int64_t)(bx * S + x) * N + (by * S + y)) * N + (int64_t)bz * S);
+      // kz = 2m: DFT_s of the row; kz = 2m + 1: DFT_s of the row times w^z
+      float2 e[S], o[S];
+#pragma unroll
+      for (int q = 0; q < S / 4; ++q) {
+        const float4 a = src[q];
+        e[4 * q] = make_float2(a.x, 0.0f);
+        e[4 * q + 1] = make_float2(a.y, 0.0f);
+        e[4 * q + 2] = make_float2(a.z, 0.0f);
+        e[4 * q + 3] = make_float2(a.w, 0.0f);
+      }
+#pragma unroll
+      for (int z = 0; z < S; ++z) o[z] = twiddle<M, false>(e[z], z);
+      dft<S, false>(e);
+      dft<S, false>(o);
+      float2* row = A + (x * S + y) * H;
+#pragma unroll
+      for (int m = 0; m < S / 2; ++m) {
+        row[2 * m] = e[m];
+        row[2 * m + 1] = o[m];
+      }
+      row[S] = e[S / 2];
+    }
+    __syncthreads();
     for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
       const int x = r / H, kz = r % H;
       float2 u[S];
 #pragma unroll
       for (int y = 0; y < S; ++y) {
-        u[y] = A1[(x * S + y) * H + kz];
+        u[y] = A[(x * S + y) * H + kz];
         if (h) u[y] = twiddle<M, false>(u[y], y);
       }
       dft<S, false>(u);
 #pragma unroll
-      for (int m = 0; m < S; ++m) A2[(x * S + m) * H + kz] = u[m];
+      for (int m = 0; m < S; ++m) A[(x * S + m) * H + kz] = u[m];
     }
     __syncthreads();
     for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
@@ -314,7 +322,7 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __r
       float2 e[S], o[S];
 #pragma unroll
       for (int x = 0; x < S; ++x) {
-        e[x] = A2[(x * S + m) * H + kz];
+        e[x] = A[(x * S + m) * H + kz];
         o[x] = twiddle<M, false>(e[x], x);
       }
       dft<S, false>(e);
@@ -333,23 +341,29 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __r
 
 // Inverse transform of one leaf's half spectrum (chunked layout), kept only
 // at the s^3 target cells and written into the mesh: x and y passes keep s
-// of the 2s outputs, v[x] = IDFT_s(Y_even)[x] + exp(2 pi i x / 2s) IDFT_s(Y_odd)[x]
-// (the y pass accumulated over the two parities of ky, one in LDS at a time);
+// of the 2s outputs, v[x] = IDFT_s(Y_even)[x] + exp(2 pi i x / 2s) IDFT_s(Y_odd)[x];
 // the z pass is the real inverse of the half spectrum,
 //   v[z] = Re Y[0] + (-1)^z Re Y[s] + 2 sum_{0 < k < s} Re(Y[k] exp(2 pi i k z / 2s)),
-// unnormalised (the kernels carry 1 / (2s)^3).
+// unnormalised (the kernels carry 1 / (2s)^3).  One LDS buffer of s^2 (s + 1)
+// values: per parity of ky the x pass fills it, then the thread of each
+// (x, kz) column does that column's y pass; the first parity's result waits
+// in the thread's registers, and the second parity's sum is written back over
+// the column in place for the z pass.  Every pass has at most one task per
+// thread (leaf_threads >= s (s + 1)).
 template <int S>
 __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __restrict__ yhat, int N, int lgnb,
                                                         int64_t nleaf, float* __restrict__ out) {
   constexpr int M = 2 * S, H = S + 1;
-  __shared__ float2 B1[S * S * H];  // [x][m][kz], ky = 2m + parity
-  __shared__ float2 B2[S * S * H];  // [x][y][kz]
+  static_assert(leaf_threads<S>() >= S * H, "one column per thread");
+  __shared__ float2 B[S * S * H];  // [x][m][kz], then [x][y][kz]
   const int64_t leaf = blockIdx.x;
   const int msk = (1 << lgnb) - 1;
   const int bz = (int)(leaf & msk), by = (int)((leaf >> lgnb) & msk), bx = (int)(leaf >> (2 * lgnb));
+  const int r = threadIdx.x;
+  float2 acc[S];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
+    if (r < S * H) {
       const int m = r / H, kz = r % H;
       float2 e[S], o[S];
 #pragma unroll
@@ -360,28 +374,30 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
       dft<S, true>(e);
       dft<S, true>(o);
 #pragma unroll
-      for (int x = 0; x < S; ++x) B1[(x * S + m) * H + kz] = cadd(e[x], twiddle<M, true>(o[x], x));
+      for (int x = 0; x < S; ++x) B[(x * S + m) * H + kz] = cadd(e[x], twiddle<M, true>(o[x], x));
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < S * H; r += leaf_threads<S>()) {
+    if (r < S * H) {
       const int x = r / H, kz = r % H;
       float2 v[S];
 #pragma unroll
-      for (int m = 0; m < S; ++m) v[m] = B1[(x * S + m) * H + kz];
+      for (int m = 0; m < S; ++m) v[m] = B[(x * S + m) * H + kz];
       dft<S, true>(v);
+      if (h == 0) {
 #pragma unroll
-      for (int y = 0; y < S; ++y) {
-        float2& d = B2[(x * S + y) * H + kz];
-        d = h ? cadd(d, twiddle<M, true>(v[y], y)) : v[y];
+        for (int y = 0; y < S; ++y) acc[y] = v[y];
+      } else {
+#pragma unroll
+        for (int y = 0; y < S; ++y) B[(x * S + y) * H + kz] = cadd(acc[y], twiddle<M, true>(v[y], y));
       }
     }
     __syncthreads();
   }
-  for (int r = threadIdx.x; r < S * S; r += leaf_threads<S>()) {
+  if (r < S * S) {
     const int x = r / S, y = r % S;
     float2 u[H];
 #pragma unroll
-    for (int k = 0; k < H; ++k) u[k] = B2[r * H + k];
+    for (int k = 0; k < H; ++k) u[k] = B[r * H + k];
     float v[S];
 #pragma unroll
     for (int z = 0; z < S; ++z) {
@@ -428,13 +444,24 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
   if (chunk >= nchunk) return;
   const int64_t k = (int64_t)chunk * W + threadIdx.x;
   if (k >= F) return;
-  // this frequency of leaf l is at base[l * stride] (leaves per axis are a
-  // power of two, so wrapping is a mask)
+  // this frequency of leaf l is at base[l * stride + lane] (leaves per axis
+  // are a power of two, so wrapping is a mask).  base and the leaf offset are
+  // the same for the whole wave.  In the chunked layout a chunk's spectra of
+  // all leaves span nleaf * 512 bytes, so every access goes through a buffer
+  // resource on the chunk: the leaf's byte offset in a scalar register, the
+  // lane's in one vector register shared by all loads, and no per-lane 64-bit
+  // address arithmetic or registers holding the 16 columns' addresses.
   const int64_t nleaf = (int64_t)nb * nb * nb;
-  const int64_t off = CHUNKED ? (int64_t)chunk * nleaf * 64 + threadIdx.x : k;
+  const int64_t off = CHUNKED ? (int64_t)chunk * nleaf * 64 : (int64_t)chunk * W;
   const float2* __restrict__ base = rhat + off;
   float2* __restrict__ obase = yhat + off;
+  const unsigned lane = threadIdx.x;
   const int stride = CHUNKED ? 64 : (int)F;
+  const unsigned chunk_bytes = (unsigned)(nleaf * 64 * sizeof(float2));
+  __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2*>(base), (short)0, (int)chunk_bytes, kBufferDword3);
+  __amdgpu_buffer_rsrc_t rout =
+      __builtin_amdgcn_make_buffer_rsrc(obase, (short)0, (int)chunk_bytes, kBufferDword3);
   const int msk = nb - 1;
   const int blk = j % np;
   const int bx0 = 2 * (blk / hb), by0 = 2 * (blk % hb);
@@ -446,7 +473,13 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
     const int sx = bx0 - 1 + c / 4, sy = by0 - 1 + c % 4;
     if (isolated && (z < 0 || z >= nb || sx < 0 || sx >= nb || sy < 0 || sy >= nb))
       return make_float2(0.0f, 0.0f);
-    return base[(int64_t)((((sx & msk) * nb + (sy & msk)) * nb) + (z & msk)) * stride];
+    const int leaf = (((sx & msk) * nb + (sy & msk)) * nb) + (z & msk);
+    if constexpr (CHUNKED) {
+      return __builtin_bit_cast(
+          float2, __builtin_amdgcn_raw_buffer_load_b64(rin, lane * 8, leaf * 512, 0));
+    } else {
+      return base[(int64_t)leaf * stride + lane];
+    }
   };
   float2 r0[16], r1[16], r2[16];
 #pragma unroll
@@ -494,9 +527,15 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
 #pragma unroll
     for (int tx = 0; tx < 2; ++tx)
 #pragma unroll
-      for (int ty = 0; ty < 2; ++ty)
-        obase[(int64_t)(((bx0 + tx) * nb + by0 + ty) * nb + bz) * stride] =
-            make_float2(re[tx * 2 + ty], im[tx * 2 + ty]);
+      for (int ty = 0; ty < 2; ++ty) {
+        const int leaf = ((bx0 + tx) * nb + by0 + ty) * nb + bz;
+        const float2 v = make_float2(re[tx * 2 + ty], im[tx * 2 + ty]);
+        if constexpr (CHUNKED)
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, v), rout, lane * 8,
+                                                leaf * 512, 0);
+        else
+          obase[(int64_t)leaf * stride + lane] = v;
+      }
   };
   int bz = 0;
   for (; bz + 3 <= nb; bz += 3) {

@@ -222,6 +222,25 @@ __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
   const int b = blockIdx.x;
   const int bx = b / (nL * nL), by = (b / nL) % nL, bz = b % nL;
   const int tid = threadIdx.x;
+  // with rows of float4 and accumulation, the mesh values this thread will
+  // update are read first, so their latency overlaps the two LDS passes
+  constexpr int kRows = (S % 4 == 0 && S > 0 && sizeof(TP) == 4)
+                            ? (S * S * (S / 4) + kThreads - 1) / kThreads : 1;
+  float4 prior[kRows];
+  auto row_ptr = [&](int i) {
+    const int cx = i / (s * (s / 4)), cy = (i / (s / 4)) % s, cz0 = 4 * (i % (s / 4));
+    return reinterpret_cast<float4*>(phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N +
+                                     (bz * s + cz0));
+  };
+  if constexpr (S % 4 == 0 && S > 0 && sizeof(TP) == 4) {
+    if (accumulate) {
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        const int i = tid + k * kThreads;
+        if (i < s * s * (s / 4)) prior[k] = *row_ptr(i);
+      }
+    }
+  }
   for (int i = tid; i < p * s; i += kThreads) {
     sAx[i] = Ax[i];
     sAy[i] = Ay[i];
@@ -246,7 +265,10 @@ __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
   if constexpr (S % 4 == 0 && S > 0 && sizeof(TP) == 4) {
     // four consecutive cells of a row per thread, read and written as float4
     // (16-byte aligned: the launcher checks the mesh pointer)
-    for (int i = tid; i < s * s * (s / 4); i += kThreads) {
+#pragma unroll
+    for (int kr = 0; kr < kRows; ++kr) {
+      const int i = tid + kr * kThreads;
+      if (i >= s * s * (s / 4)) break;
       const int cx = i / (s * (s / 4)), cy = (i / (s / 4)) % s, cz0 = 4 * (i % (s / 4));
       W v[4] = {0, 0, 0, 0};
       for (int k = 0; k < p; ++k) {
@@ -255,16 +277,14 @@ __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[c] += a * w[c];
       }
-      float4* o = reinterpret_cast<float4*>(phi + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N +
-                                            (bz * s + cz0));
       float4 r = make_float4((float)(v[0] * scale), (float)(v[1] * scale), (float)(v[2] * scale),
                              (float)(v[3] * scale));
       if (accumulate) {
-        const float4 q = *o;
+        const float4 q = prior[kr];
         r = make_float4((float)((W)q.x + v[0] * scale), (float)((W)q.y + v[1] * scale),
                         (float)((W)q.z + v[2] * scale), (float)((W)q.w + v[3] * scale));
       }
-      *o = r;
+      *row_ptr(i) = r;
     }
   } else {
     for (int i = tid; i < s * s * s; i += kThreads) {
