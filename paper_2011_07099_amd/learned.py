@@ -244,6 +244,8 @@ def fit_output(N=64, L=3, p=6, n_fields=64, n_valid=8, seed0=10000, alpha=2.0, s
     plan = Plan(N, L, p, green)
     rhos, targets = _fields_and_targets(plan, N, n_fields, alpha, sigma, seed0)
     vr, vt = _fields_and_targets(plan, N, n_valid, alpha, sigma, seed0 + n_fields)
+    if log:
+        log("%d training and %d validation fields with their targets" % (n_fields, n_valid))
     th0 = init_weights(seed, scale)
     nout = N_HID + 1
 
@@ -266,6 +268,8 @@ def fit_output(N=64, L=3, p=6, n_fields=64, n_valid=8, seed0=10000, alpha=2.0, s
         th = th0.copy()
         th[O_W3 + k] = h
         H[:, k] = (grad_out(th) - g0) / h
+        if log and (k % 8 == 7 or k == nout - 1):
+            log("Hessian columns %d / %d" % (k + 1, nout))
     H = 0.5 * (H + H.T)
     ev = np.linalg.eigvalsh(H)
     base_train = mean_loss(th0, rhos, targets, False)
