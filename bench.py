@@ -39,11 +39,15 @@ ALPHA, SIGMA, SEED = 1.5, 2.0, 5
 METRIC = "cells/s at 256^3 p=8 periodic FMM, L2 err<=1e-4 vs PM; M2L MFMA util"
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
-# MI355X peaks (TFLOP/s) of the units each kernel runs on.  The vector FP32
-# figure is the non-packed rate (256 CUs x 64 lanes x 2 flops x 2.4 GHz): this
-# library compiles every kernel with packed FP32 instructions disabled, so
-# the packed 157.3 is out of reach; it equals the FP64 vector rate.
-PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 78.6, "f64 valu": 78.6}
+# MI355X peaks (TFLOP/s) of the units each kernel runs on.  The library
+# compiles every kernel with packed FP32 instructions disabled, yet the FP32
+# vector peak of 157.3 stays reachable: gfx950 issues the two-operand FP32
+# multiply-add (v_fmac_f32 e32, all operands in vector registers) at twice
+# the rate of the three-operand form.  The FP32 direct near zone's counters
+# show it: 3.70e10 VALU instructions in 9.6e7 cycles on 1024 SIMDs, 1.5 per
+# four cycles, which one instruction per four cycles could not give.  FP64
+# has no such doubling: 78.6.
+PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 157.3, "f64 valu": 78.6}
 FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default at L = 4)
 
 # HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE
@@ -523,14 +527,37 @@ def kernel_table(plan, L, near_fft, spectral):
     return out
 
 
-def kernel_work(name, N, L, p):
-    """Algorithmic work of one launch of a kernel of the default route:
-    (flops, unit, bytes).  Flops count 8 per complex multiply-add; bytes are
-    the kernel's compulsory HBM traffic (operands read once, results written
-    once).  Spectra are complex FP64 at the interaction zones ((2p)^2 (p + 1)
-    frequencies per node), complex FP32 at the near zone ((2s)^2 (s + 1) per
-    leaf)."""
+def kernel_work(name, N, L, p, route=None):
+    """Algorithmic work of one launch of a kernel: (flops, unit, bytes,
+    products).  Default route (spectral zones, FFT near zone): flops count 8
+    per complex multiply-add; bytes are the kernel's compulsory HBM traffic
+    (operands read once, results written once); spectra are complex FP64 at
+    the interaction zones ((2p)^2 (p + 1) frequencies per node), complex FP32
+    at the near zone ((2s)^2 (s + 1) per leaf).  GEMM zones and the direct
+    near zone: 2 p^6 flops per offset and target node, 2 s^6 per neighbour
+    leaf and target leaf, on the unit the precision puts them on; `products`
+    is the number of bf16 products the split issues per algorithmic product
+    (the matrix cores' peak applies to issued flops)."""
     s = N >> L
+    route = route or {"m2l": "spectral", "near": "fft", "precision": "bf16x3"}
+    if name.startswith("m2l L") and len(name.split()) == 2 and route["m2l"] == "gemm":
+        lv = int(name.split()[1][1:])
+        fl = (37 if lv == 2 else 189) * 2.0 * p ** 6 * 8 ** lv
+        if lv in FP64_LEVELS:
+            return fl, ("f64 mfma" if p == 8 else "f64 valu"), None, 1
+        if route["precision"] == "bf16x3" and p == 8:
+            return fl, "bf16 mfma", None, 6
+        return fl, "f32 valu", None, 1
+    if name == "near" and route["near"] == "direct":
+        fl = 27 * 2.0 * s ** 6 * 8 ** L
+        if route["precision"] == "bf16x3" and s in (8, 16):
+            return fl, "bf16 mfma", None, 3
+        return fl, "f32 valu", None, 1
+    r = _default_work(name, N, L, p, s)
+    return r + (1,)
+
+
+def _default_work(name, N, L, p, s):
     if name.startswith("m2l L"):
         lv = int(name.split()[1][1:])
         F = (2 * p) ** 2 * (p + 1)
@@ -650,13 +677,20 @@ def headline(args):
     stages = runs["serial"]["stages"]
     m2l_levels = runs["serial"]["m2l_levels"]
 
+    route = {"m2l": args.m2l, "near": args.near, "precision": args.precision}
+
     def roof(name, dms):
-        fl, unit, kbytes = kernel_work(name, N, L, P) if (spectral and near_fft) else (None, "hbm", None)
+        fl, unit, kbytes, products = kernel_work(name, N, L, P, route)
         if fl is not None:
             peak = PEAK_UNIT[unit]
-            tf = fl / (dms * 1e-3) / 1e12
-            return {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
-                    "frac": tf / peak, "unit_used": unit, "flops_per_launch": fl}, kbytes
+            tf = fl * products / (dms * 1e-3) / 1e12
+            r = {"bound": "mfma" if "mfma" in unit else "alu", "achieved": tf, "peak": peak,
+                 "unit": "TFLOP/s", "frac": tf / peak, "unit_used": unit,
+                 "flops_per_launch": fl * products}
+            if products > 1:
+                r.update({"products": products, "algorithmic_flops_per_launch": fl,
+                          "algorithmic_tflops": tf / products})
+            return r, kbytes
         gbs = (kbytes or 0.0) / (dms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
                 "frac": gbs / 8000.0}, kbytes

@@ -97,7 +97,13 @@ typedef enum {
 /* Arithmetic of the two contraction-heavy steps (interaction-zone
  * convolution and near zone).  Tabulation of G always runs in FP64. */
 typedef enum {
-  /* FP32 products and FP32 accumulation. */
+  /* FP32 products and FP32 accumulation.  The spectral interaction zones
+   * (PFMM_OPT_M2L) are FP64 in every precision.  With GEMM zones the leaf
+   * level's FP32 sums, which cancel 10^2-10^3 fold, are amplified toward the
+   * leaf corners by L2P's extrapolation beyond the outer gridlet nodes: at
+   * 256^3, p = 8 that leaves 8e-5 of max|phi| against the FP64 reference
+   * FMM (2e-5 relative L2 against PM), against 3e-6 for the spectral zones;
+   * PFMM_OPT_FP64_LEVELS = L - 1 removes it. */
   PFMM_PREC_FP32 = 0,
   /* Split precision: each FP32 operand x is held as hi = bf16(x) and
    * lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi on the BF16 matrix
