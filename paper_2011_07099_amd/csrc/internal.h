@@ -10,6 +10,15 @@
 
 namespace pfmm {
 
+// Workgroup index -> leaf, for kernels with one workgroup per leaf of the
+// mesh.  Dispatch deals workgroups to the 8 XCDs in turn; this gives each XCD
+// a contiguous range of leaves, so the leaves it runs one after another are
+// neighbours along z, whose mesh rows (s floats each) share 128-byte lines:
+// the second half of a line then comes from that XCD's L2 instead of HBM.
+__device__ __forceinline__ int64_t xcd_leaf(int64_t i, int64_t n) {
+  return (n & 7) ? i : (i & 7) * (n >> 3) + (i >> 3);
+}
+
 // Optional timing of a routine's kernels: begin() before and end(part) after
 // its part-th kernel (or group of kernels), on the stream it launches on.
 // A null timer times nothing.

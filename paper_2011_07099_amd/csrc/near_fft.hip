@@ -265,27 +265,35 @@ constexpr int leaf_threads() { return (S * (S + 1) + 63) / 64 * 64; }
 // LDS buffer of s^2 (s + 1) values: the z pass fills it, the y pass of that
 // parity transforms every (x, kz) column in place (one thread per column),
 // the x pass reads it out.  The second parity redoes the z pass from the
-// mesh (its rows are still in L2) instead of keeping a second buffer, so
-// four leaves fit in a CU's LDS at s = 16.
+// row each thread keeps in registers instead of keeping a second buffer, so
+// four leaves fit in a CU's LDS at s = 16 and the mesh is read once.
 template <int S>
 __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __restrict__ rho, int N, int lgnb,
                                                         int64_t nleaf, float2* __restrict__ rhat) {
   constexpr int M = 2 * S, H = S + 1;
   __shared__ float2 A[S * S * H];  // [x][y][kz], then [x][m][kz] with ky = 2m + parity
-  const int64_t leaf = blockIdx.x;
+  const int64_t leaf = xcd_leaf(blockIdx.x, nleaf);
   const int msk = (1 << lgnb) - 1;
   const int bz = (int)(leaf & msk), by = (int)((leaf >> lgnb) & msk), bx = (int)(leaf >> (2 * lgnb));
+  static_assert(leaf_threads<S>() >= S * S, "one row per thread");
+  const int tr = threadIdx.x;
+  float4 rowv[S / 4];
+  if (tr < S * S) {
+    const int x = tr / S, y = tr % S;
+    const float4* src = reinterpret_cast<const float4*>(
+        rho + ((int64_t)(bx * S + x) * N + (by * S + y)) * N + (int64_t)bz * S);
+#pragma unroll
+    for (int q = 0; q < S / 4; ++q) rowv[q] = src[q];
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    for (int r = threadIdx.x; r < S * S; r += leaf_threads<S>()) {
-      const int x = r / S, y = r % S;
-      const float4* src = reinterpret_cast<const float4*>(
-          rho + ((int64_t)(bx * S + x) * N + (by * S + y)) * N + (int64_t)bz * S);
+    if (tr < S * S) {
+      const int x = tr / S, y = tr % S;
       // kz = 2m: DFT_s of the row; kz = 2m + 1: DFT_s of the row times w^z
       float2 e[S], o[S];
 #pragma unroll
       for (int q = 0; q < S / 4; ++q) {
-        const float4 a = src[q];
+        const float4 a = rowv[q];
         e[4 * q] = make_float2(a.x, 0.0f);
         e[4 * q + 1] = make_float2(a.y, 0.0f);
         e[4 * q + 2] = make_float2(a.z, 0.0f);
@@ -356,7 +364,7 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
   constexpr int M = 2 * S, H = S + 1;
   static_assert(leaf_threads<S>() >= S * H, "one column per thread");
   __shared__ float2 B[S * S * H];  // [x][m][kz], then [x][y][kz]
-  const int64_t leaf = blockIdx.x;
+  const int64_t leaf = xcd_leaf(blockIdx.x, nleaf);
   const int msk = (1 << lgnb) - 1;
   const int bz = (int)(leaf & msk), by = (int)((leaf >> lgnb) & msk), bx = (int)(leaf >> (2 * lgnb));
   const int r = threadIdx.x;

@@ -38,48 +38,79 @@ __global__ __launch_bounds__(kThreads) void k_p2m(const TR* __restrict__ rho,
   // LDS rows of the weights and of the cell block padded by one word, so
   // that lanes reading different rows at one column hit different banks
   const int sp = s + 1;
+  // compile-time rows of FP32 cells, one per thread: each thread contracts
+  // its own row along z from registers, and the cell block never goes
+  // through LDS (a third of the LDS, so more leaves per CU)
+  constexpr bool kRowRegs = S % 4 == 0 && S > 0 && P > 0 && S * S <= kThreads &&
+                            sizeof(TR) == 4;
   extern __shared__ __align__(8) unsigned char smraw[];
   W* sm = reinterpret_cast<W*>(smraw);
   W* sA = sm;               // [p][s + 1]
-  W* sr = sA + p * sp;      // [s][s][s + 1]
-  W* t1 = sr + s * s * sp;  // [cx][cy][az]
+  W* sr = sA + p * sp;      // [s][s][s + 1] (not with rows in registers)
+  W* t1 = kRowRegs ? sr : sr + s * s * sp;  // [cx][cy][az]
   W* t2 = t1 + s * s * p;   // [cx][ay][az]
   const W* A = wsel<W>(Aw);
   const int nL = N / s;
-  const int b = blockIdx.x;
+  const int b = (int)xcd_leaf(blockIdx.x, (int64_t)nL * nL * nL);
   const int bx = b / (nL * nL), by = (b / nL) % nL, bz = b % nL;
   const int tid = threadIdx.x;
-  for (int i = tid; i < p * s; i += kThreads) sA[(i / s) * sp + i % s] = A[i];
-  if constexpr (S % 4 == 0 && S > 0) {  // rows of s cells as float4 (16-byte aligned: s | N)
-    for (int i = tid; i < s * s * (s / 4); i += kThreads) {
-      const int row = i / (s / 4), q = i % (s / 4);
-      const int cx = row / s, cy = row % s;
-      const TR* src = rho + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (size_t)bz * s + 4 * q;
-      W* dst = sr + row * sp + 4 * q;
-      if constexpr (sizeof(TR) == 4) {
-        const float4 v = *reinterpret_cast<const float4*>(src);
-        dst[0] = (W)v.x;
-        dst[1] = (W)v.y;
-        dst[2] = (W)v.z;
-        dst[3] = (W)v.w;
-      } else {
-        for (int c = 0; c < 4; ++c) dst[c] = (W)src[c];
+  if constexpr (kRowRegs) {
+    float4 rowv[S / 4];
+    if (tid < S * S) {
+      const int cx = tid / S, cy = tid % S;
+      const float4* src = reinterpret_cast<const float4*>(
+          rho + ((size_t)(bx * S + cx) * N + (by * S + cy)) * N + (size_t)bz * S);
+#pragma unroll
+      for (int q = 0; q < S / 4; ++q) rowv[q] = src[q];
+    }
+    for (int i = tid; i < P * S; i += kThreads) sA[(i / S) * sp + i % S] = A[i];
+    __syncthreads();
+    if (tid < S * S) {
+#pragma unroll
+      for (int az = 0; az < P; ++az) {
+        const W* w = sA + az * sp;
+        W acc = 0;
+#pragma unroll
+        for (int q = 0; q < S / 4; ++q)
+          acc += w[4 * q] * (W)rowv[q].x + w[4 * q + 1] * (W)rowv[q].y +
+                 w[4 * q + 2] * (W)rowv[q].z + w[4 * q + 3] * (W)rowv[q].w;
+        t1[tid * P + az] = acc;
       }
     }
+    __syncthreads();
   } else {
-    for (int i = tid; i < s * s * s; i += kThreads) {
-      const int cx = i / (s * s), cy = (i / s) % s, cz = i % s;
-      sr[(cx * s + cy) * sp + cz] = (W)rho[((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz)];
+    for (int i = tid; i < p * s; i += kThreads) sA[(i / s) * sp + i % s] = A[i];
+    if constexpr (S % 4 == 0 && S > 0) {  // rows of s cells as float4 (16-byte aligned: s | N)
+      for (int i = tid; i < s * s * (s / 4); i += kThreads) {
+        const int row = i / (s / 4), q = i % (s / 4);
+        const int cx = row / s, cy = row % s;
+        const TR* src = rho + ((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (size_t)bz * s + 4 * q;
+        W* dst = sr + row * sp + 4 * q;
+        if constexpr (sizeof(TR) == 4) {
+          const float4 v = *reinterpret_cast<const float4*>(src);
+          dst[0] = (W)v.x;
+          dst[1] = (W)v.y;
+          dst[2] = (W)v.z;
+          dst[3] = (W)v.w;
+        } else {
+          for (int c = 0; c < 4; ++c) dst[c] = (W)src[c];
+        }
+      }
+    } else {
+      for (int i = tid; i < s * s * s; i += kThreads) {
+        const int cx = i / (s * s), cy = (i / s) % s, cz = i % s;
+        sr[(cx * s + cy) * sp + cz] = (W)rho[((size_t)(bx * s + cx) * N + (by * s + cy)) * N + (bz * s + cz)];
+      }
     }
+    __syncthreads();
+    for (int i = tid; i < s * s * p; i += kThreads) {
+      const int cxy = i / p, az = i % p;
+      W acc = 0;
+      for (int cz = 0; cz < s; ++cz) acc += sA[az * sp + cz] * sr[cxy * sp + cz];
+      t1[i] = acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int i = tid; i < s * s * p; i += kThreads) {
-    const int cxy = i / p, az = i % p;
-    W acc = 0;
-    for (int cz = 0; cz < s; ++cz) acc += sA[az * sp + cz] * sr[cxy * sp + cz];
-    t1[i] = acc;
-  }
-  __syncthreads();
   for (int i = tid; i < s * p * p; i += kThreads) {
     const int cx = i / (p * p), ay = (i / p) % p, az = i % p;
     W acc = 0;
@@ -219,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_l2p(const TI* __restrict__ P,
   const W* Ay = wsel<W>(Wyw);
   const W* Az = wsel<W>(Wzw);
   const int nL = N / s;
-  const int b = blockIdx.x;
+  const int b = (int)xcd_leaf(blockIdx.x, (int64_t)nL * nL * nL);
   const int bx = b / (nL * nL), by = (b / nL) % nL, bz = b % nL;
   const int tid = threadIdx.x;
   // with rows of float4 and accumulation, the mesh values this thread will
@@ -327,9 +358,13 @@ __global__ void k_d2f(const double* __restrict__ s, float* __restrict__ d, int64
 }  // namespace
 
 // LDS words of P2M: the padded weights and cell block, and the two partial
-// contractions.
+// contractions; without the cell block for the instances that keep the
+// rows in registers.
 inline size_t p2m_words(int s, int p) {
   return (size_t)(p * (s + 1) + s * s * (s + 1) + s * s * p + s * p * p);
+}
+inline size_t p2m_words_rows(int s, int p) {
+  return (size_t)(p * (s + 1) + s * s * p + s * p * p);
 }
 
 hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int s, int p,
@@ -341,10 +376,12 @@ hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int 
                        words * sizeof(double), st, rho, (double*)M, A, N, s, p, h3);
   else {
     const dim3 g(nL * nL * nL), b(kThreads);
-    const size_t sh = words * sizeof(float);
+    size_t sh = words * sizeof(float);
     const float hf = (float)h3;
     // the compile-time instances read rows of cells as float4
     const bool aligned = ((uintptr_t)rho & 15) == 0;
+    if (aligned && (s == 16 || s == 8) && (p == 8 || p == 4))
+      sh = p2m_words_rows(s, p) * sizeof(float);
     if (!aligned)
       hipLaunchKernelGGL((k_p2m<float, float>), g, b, sh, st, rho, (float*)M, A, N, s, p, hf);
     else if (s == 16 && p == 8)
