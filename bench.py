@@ -442,8 +442,8 @@ def m2l_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mfma", action="store_true",
@@ -553,11 +553,11 @@ def kernel_work(name, N, L, p, route=None):
         if route["precision"] == "bf16x3" and s in (8, 16):
             return fl, "bf16 mfma", None, 3
         return fl, "f32 valu", None, 1
-    r = _default_work(name, N, L, p, s)
+    r = _default_work(name, N, L, p, s, route.get("fold", False))
     return r + (1,)
 
 
-def _default_work(name, N, L, p, s):
+def _default_work(name, N, L, p, s, fold=False):
     if name.startswith("m2l L"):
         lv = int(name.split()[1][1:])
         F = (2 * p) ** 2 * (p + 1)
@@ -574,11 +574,12 @@ def _default_work(name, N, L, p, s):
         F = (2 * s) ** 2 * (s + 1)
         leaves = 8 ** L
         spec = 8.0 * F * leaves
+        # P2M and L2P folded into the transforms: the leaf gridlets written
+        # by the forward one and read by the inverse one (FP32)
+        gl = 4.0 * p ** 3 * leaves if fold else 0.0
         if "stencil" in name:
             return 27 * 8.0 * F * leaves, "f32 valu", 2 * spec + 27 * 8.0 * F
-        if "inverse" in name:
-            return None, "hbm", spec + 4.0 * N ** 3
-        return None, "hbm", spec + 4.0 * N ** 3
+        return None, "hbm", spec + 4.0 * N ** 3 + gl
     if name in ("p2m",):
         return None, "hbm", 4.0 * N ** 3 + 4.0 * p ** 3 * 8 ** L
     if name in ("l2p",):
@@ -652,13 +653,24 @@ def headline(args):
     for _ in range(args.warmup):
         plan.solve(rho, phi, acc)
     torch.cuda.synchronize()
-    # Two timed runs of K steps each, HIP events around every kernel group on
-    # the stream it runs on.  The first, as any solve runs (the near zone
-    # beside the tree), gives the throughput and each kernel's live duration;
-    # the second runs every stage alone on the device, one after another,
-    # which gives each kernel's own duration for its roofline.
+    # Three timed runs of K steps each.  The first, with no timing inside the
+    # solve, gives the throughput (HIP events between the kernels would cost
+    # 5% of it: every recorded event is one more packet between two kernels
+    # on each stream).  The second, as any solve runs (the near zone beside
+    # the tree) with HIP events around every kernel group on the stream it
+    # runs on, gives each kernel's live duration; the third runs every stage
+    # alone on the device, one after another, which gives each kernel's own
+    # duration for its roofline.
     spectral, near_fft = args.m2l == "spectral", args.near == "fft"
     runs = {}
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record(stream)
+    for _ in range(args.steps):
+        plan.solve(rho, phi, acc)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = t_start.elapsed_time(t_end) / args.steps
     for mode in ("live", "serial"):
         plan.set_profile(mode)
         t_start = torch.cuda.Event(enable_timing=True)
@@ -672,12 +684,15 @@ def headline(args):
                       "kern": kernel_table(plan, L, near_fft, spectral),
                       "stages": plan.stage_times(), "m2l_levels": plan.level_times("m2l")}
     plan.close()
-    ms = runs["live"]["ms"]
+    ms = plain_ms
     kern = runs["serial"]["kern"]
     stages = runs["serial"]["stages"]
     m2l_levels = runs["serial"]["m2l_levels"]
 
-    route = {"m2l": args.m2l, "near": args.near, "precision": args.precision}
+    # P2M and L2P run inside the near zone's leaf transforms when they have
+    # no stage of their own
+    route = {"m2l": args.m2l, "near": args.near, "precision": args.precision,
+             "fold": near_fft and stages["p2m"][1] == 0}
 
     def roof(name, dms):
         fl, unit, kbytes, products = kernel_work(name, N, L, P, route)
@@ -739,6 +754,7 @@ def headline(args):
                    **({"accel": args.accel} if args.accel != "none" else {}),
                    "near": args.near, "m2l": args.m2l},
         "roofline": roofline,
+        "live_profiled_ms_per_step": runs["live"]["ms"],
         "serial_ms_per_step": runs["serial"]["ms"],
         "kernels_ms": {k: v[0] for k, v in sorted(kern.items(), key=lambda kv: -kv[1][0])},
         "kernels_live_ms": {k: v[0] for k, v in sorted(live.items(), key=lambda kv: -kv[1][0])},

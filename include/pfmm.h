@@ -187,7 +187,18 @@ typedef enum {
   /* value: PFMM_MLP_PARAMS floats, the weights of the table-correction
    * network (same as pfmm_learned_set with BF16 inference), meant for
    * PFMM_GREEN_LEARNED plans.  Synchronises. */
-  PFMM_OPT_LEARNED_WEIGHTS = 12
+  PFMM_OPT_LEARNED_WEIGHTS = 12,
+  /* value: int32 0 or 1.  1 folds P2M into the FFT near zone's forward leaf
+   * transforms and L2P into the potential's inverse ones (Sec. 2: the leaf
+   * steps read and write the same cells), when the library's own transforms
+   * run (leaf edge 8 or 16, p = 4 or 8) and the leaf level is FP32: the
+   * density is read once and the potential written once, two launches fewer.
+   * The tree then starts only after the forward transforms and the inverse
+   * waits for the whole tree, so the near zone no longer runs beside the
+   * coarse levels' small kernels: at 256^3, L = 4, p = 8 a solve takes about
+   * 1.22 ms folded against 1.16 ms unfolded, and 1.19 ms folded with
+   * everything on one stream.  Default 0. */
+  PFMM_OPT_FOLD = 13
 } pfmm_option;
 
 /* Leaf near-zone algorithm (the 27 neighbour leaves, Sec. 2). */

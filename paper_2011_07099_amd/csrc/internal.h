@@ -281,6 +281,17 @@ hipError_t m2l_fft_level(M2LFft* f, int l, const void* Ml, void* Pl, int fp64, i
 // Leaf near zone by FFT convolution on the doubled grid (Sec. 2-3)
 // ---------------------------------------------------------------------------
 struct NearFft;
+// P2M and L2P folded into the leaf transforms of the potential (library
+// kernels, FP32 leaf gridlets of p^3 values in leaf order, p = 4 or 8): the
+// forward transform writes M = P2M(rho), the inverse adds L2P(Pl).  A null
+// M or Pl leaves that step out.
+struct LeafTree {
+  float* M = nullptr;         // leaf gridlet masses out (P2M, times h3)
+  const float* Pl = nullptr;  // leaf locals in (L2P)
+  const float* A = nullptr;   // weights A[a][c], p x s (gridlet node a, cell c)
+  float h3 = 0.0f;            // cell volume
+  int p = 0;                  // gridlet size
+};
 // Plans and buffers for N^3 cells in leaves of s^3 (about 100 bytes per cell);
 // allocates.
 hipError_t near_fft_create(int N, int s, NearFft** out);
@@ -301,6 +312,19 @@ int near_fft_fused(const NearFft* f);
 // stencil (1 + 2t) and the inverse transform (2 + 2t).
 hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
                         hipStream_t st, KernelTimer* kt = nullptr);
+// 1 when the transforms can fold the P2M and L2P of gridlet size p.
+int near_fft_folds(const NearFft* f, int p);
+// near_fft_run in two halves around the tree, P2M and L2P folded in (see
+// LeafTree): near_fft_begin runs the forward transforms with P2M into
+// tree.M (then records `after_fwd` when given: the leaf masses are ready),
+// the stencils and inverses of outputs 1 .. nout - 1, and the stencil of
+// output 0; near_fft_end, once tree.Pl holds the leaf locals, the inverse
+// transform of output 0 with L2P added.  Timer parts as near_fft_run.
+hipError_t near_fft_begin(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
+                          const LeafTree& tree, hipEvent_t after_fwd, hipStream_t st,
+                          KernelTimer* kt = nullptr);
+hipError_t near_fft_end(NearFft* f, float* out0, const LeafTree& tree, hipStream_t st,
+                        KernelTimer* kt = nullptr);
 
 // ---------------------------------------------------------------------------
 // Interaction zones as spectral stencils (per-node transforms, FP64)

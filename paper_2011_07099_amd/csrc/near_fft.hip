@@ -267,15 +267,22 @@ constexpr int leaf_threads() { return (S * (S + 1) + 63) / 64 * 64; }
 // the x pass reads it out.  The second parity redoes the z pass from the
 // row each thread keeps in registers instead of keeping a second buffer, so
 // four leaves fit in a CU's LDS at s = 16 and the mesh is read once.
-template <int S>
+//
+// With P > 0 the kernel first does the leaf's P2M from the same rows (the
+// gridlet masses h^3 sum_c A[ax][cx] A[ay][cy] A[az][cz] rho[c], A[a][c] the
+// Lagrange basis of gridlet node a at cell centre c): z is contracted from
+// each thread's row in registers, y and x through the LDS buffer before the
+// transform takes it over, so the density is read from HBM once for both.
+template <int S, int P = 0>
 __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __restrict__ rho, int N, int lgnb,
-                                                        int64_t nleaf, float2* __restrict__ rhat) {
-  constexpr int M = 2 * S, H = S + 1;
+                                                        int64_t nleaf, float2* __restrict__ rhat,
+                                                        LeafTree tree) {
+  constexpr int M = 2 * S, H = S + 1, NT = leaf_threads<S>();
   __shared__ float2 A[S * S * H];  // [x][y][kz], then [x][m][kz] with ky = 2m + parity
   const int64_t leaf = xcd_leaf(blockIdx.x, nleaf);
   const int msk = (1 << lgnb) - 1;
   const int bz = (int)(leaf & msk), by = (int)((leaf >> lgnb) & msk), bx = (int)(leaf >> (2 * lgnb));
-  static_assert(leaf_threads<S>() >= S * S, "one row per thread");
+  static_assert(NT >= S * S, "one row per thread");
   const int tr = threadIdx.x;
   float4 rowv[S / 4];
   if (tr < S * S) {
@@ -284,6 +291,44 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __r
         rho + ((int64_t)(bx * S + x) * N + (by * S + y)) * N + (int64_t)bz * S);
 #pragma unroll
     for (int q = 0; q < S / 4; ++q) rowv[q] = src[q];
+  }
+  if constexpr (P > 0) {
+    constexpr int SP = S + 1;  // weight rows padded by one word
+    static_assert((P * SP + S * S * P + S * P * P) * sizeof(float) <= sizeof(A), "P2M fits in the buffer");
+    float* sw = reinterpret_cast<float*>(A);  // [a][c]
+    float* t1 = sw + P * SP;                  // [cx][cy][az]
+    float* t2 = t1 + S * S * P;               // [cx][ay][az]
+    for (int i = tr; i < P * S; i += NT) sw[(i / S) * SP + i % S] = tree.A[i];
+    __syncthreads();
+    if (tr < S * S) {
+#pragma unroll
+      for (int az = 0; az < P; ++az) {
+        const float* w = sw + az * SP;
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < S / 4; ++q)
+          acc += w[4 * q] * rowv[q].x + w[4 * q + 1] * rowv[q].y + w[4 * q + 2] * rowv[q].z +
+                 w[4 * q + 3] * rowv[q].w;
+        t1[tr * P + az] = acc;
+      }
+    }
+    __syncthreads();
+    for (int i = tr; i < S * P * P; i += NT) {
+      const int cx = i / (P * P), ay = (i / P) % P, az = i % P;
+      float acc = 0.0f;
+#pragma unroll
+      for (int cy = 0; cy < S; ++cy) acc += sw[ay * SP + cy] * t1[(cx * S + cy) * P + az];
+      t2[i] = acc;
+    }
+    __syncthreads();
+    for (int i = tr; i < P * P * P; i += NT) {
+      const int ax = i / (P * P), ayz = i % (P * P);
+      float acc = 0.0f;
+#pragma unroll
+      for (int cx = 0; cx < S; ++cx) acc += sw[ax * SP + cx] * t2[cx * P * P + ayz];
+      tree.M[leaf * (P * P * P) + i] = tree.h3 * acc;
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -358,16 +403,30 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __r
 // in the thread's registers, and the second parity's sum is written back over
 // the column in place for the z pass.  Every pass has at most one task per
 // thread (leaf_threads >= s (s + 1)).
-template <int S>
+//
+// With P > 0 the leaf's L2P is added before the write (the far field
+// sum_a A[ax][x] A[ay][y] A[az][z] P[a] of the leaf locals P, A as in the
+// forward kernel): the locals are read at the start, and once the z pass
+// has its spectra in registers the buffer holds the weights, the locals and
+// their x contraction; each thread then contracts y and z for its row.
+template <int S, int P = 0>
 __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __restrict__ yhat, int N, int lgnb,
-                                                        int64_t nleaf, float* __restrict__ out) {
-  constexpr int M = 2 * S, H = S + 1;
-  static_assert(leaf_threads<S>() >= S * H, "one column per thread");
+                                                        int64_t nleaf, float* __restrict__ out,
+                                                        LeafTree tree) {
+  constexpr int M = 2 * S, H = S + 1, NT = leaf_threads<S>();
+  static_assert(NT >= S * H, "one column per thread");
   __shared__ float2 B[S * S * H];  // [x][m][kz], then [x][y][kz]
   const int64_t leaf = xcd_leaf(blockIdx.x, nleaf);
   const int msk = (1 << lgnb) - 1;
   const int bz = (int)(leaf & msk), by = (int)((leaf >> lgnb) & msk), bx = (int)(leaf >> (2 * lgnb));
   const int r = threadIdx.x;
+  constexpr int P3 = P * P * P, NPL = P > 0 ? (P3 + NT - 1) / NT : 1;
+  float loc[NPL];
+  if constexpr (P > 0) {
+#pragma unroll
+    for (int j = 0; j < NPL; ++j)
+      if (r + j * NT < P3) loc[j] = tree.Pl[leaf * P3 + r + j * NT];
+  }
   float2 acc[S];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -401,12 +460,11 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
     }
     __syncthreads();
   }
+  float v[S];
   if (r < S * S) {
-    const int x = r / S, y = r % S;
     float2 u[H];
 #pragma unroll
     for (int k = 0; k < H; ++k) u[k] = B[r * H + k];
-    float v[S];
 #pragma unroll
     for (int z = 0; z < S; ++z) {
       const float a = u[0].x + ((z & 1) ? -u[S].x : u[S].x);
@@ -418,6 +476,47 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
       }
       v[z] = a + 2.0f * b;
     }
+  }
+  if constexpr (P > 0) {
+    static_assert((P * S + P3 + S * P * P) * sizeof(float) <= sizeof(B), "L2P fits in the buffer");
+    float* sw = reinterpret_cast<float*>(B);  // [a][c]
+    float* sl = sw + P * S;                   // locals [ax][ay][az]
+    float* su = sl + P3;                      // [x][ay][az]
+    __syncthreads();  // every row of the buffer is in registers
+    for (int i = r; i < P * S; i += NT) sw[i] = tree.A[i];
+#pragma unroll
+    for (int j = 0; j < NPL; ++j)
+      if (r + j * NT < P3) sl[r + j * NT] = loc[j];
+    __syncthreads();
+    for (int i = r; i < S * P * P; i += NT) {
+      const int x = i / (P * P), yz = i % (P * P);
+      float a = 0.0f;
+#pragma unroll
+      for (int ax = 0; ax < P; ++ax) a += sw[ax * S + x] * sl[ax * P * P + yz];
+      su[i] = a;
+    }
+    __syncthreads();
+    if (r < S * S) {
+      const int x = r / S, y = r % S;
+      float t[P];
+#pragma unroll
+      for (int az = 0; az < P; ++az) {
+        float a = 0.0f;
+#pragma unroll
+        for (int ay = 0; ay < P; ++ay) a += sw[ay * S + y] * su[(x * P + ay) * P + az];
+        t[az] = a;
+      }
+#pragma unroll
+      for (int z = 0; z < S; ++z) {
+        float a = 0.0f;
+#pragma unroll
+        for (int az = 0; az < P; ++az) a += sw[az * S + z] * t[az];
+        v[z] += a;
+      }
+    }
+  }
+  if (r < S * S) {
+    const int x = r / S, y = r % S;
     float4* dst = reinterpret_cast<float4*>(
         out + ((int64_t)(bx * S + x) * N + (by * S + y)) * N + (int64_t)bz * S);
 #pragma unroll
@@ -642,45 +741,110 @@ inline hipError_t tend(KernelTimer* kt, hipStream_t st, int part, hipError_t e) 
   return kt->end(st, part);
 }
 
-template <int S>
-hipError_t run_fused(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
-                     hipStream_t st, KernelTimer* kt) {
-  const unsigned leaves = (unsigned)f->nleaf;
-  hipError_t e = tbegin(kt, st);
-  if (e != hipSuccess) return e;
-  k_leaf_fwd<S><<<leaves, leaf_threads<S>(), 0, st>>>(rho, f->N, f->lgnb, f->nleaf, f->rhat);
-  e = tend(kt, st, 0, hipGetLastError());
+template <int S, int P>
+hipError_t leaf_fwd(NearFft* f, const float* rho, const LeafTree& tree, hipStream_t st) {
+  k_leaf_fwd<S, P><<<(unsigned)f->nleaf, leaf_threads<S>(), 0, st>>>(rho, f->N, f->lgnb, f->nleaf,
+                                                                     f->rhat, tree);
+  return hipGetLastError();
+}
+
+template <int S, int P>
+hipError_t leaf_inv(NearFft* f, float* out, const LeafTree& tree, hipStream_t st) {
+  k_leaf_inv<S, P><<<(unsigned)f->nleaf, leaf_threads<S>(), 0, st>>>(f->yhat, f->N, f->lgnb, f->nleaf,
+                                                                     out, tree);
+  return hipGetLastError();
+}
+
+// The fused leaf transforms at the plan's leaf edge, with the P2M or L2P of
+// gridlet size p folded in (p = 0: none; p = 4 or 8 at s = 8, 16).
+hipError_t fwd_any(NearFft* f, const float* rho, const LeafTree& tree, int p, hipStream_t st) {
+  switch (f->s * 16 + p) {
+    case 4 * 16: return leaf_fwd<4, 0>(f, rho, tree, st);
+    case 8 * 16: return leaf_fwd<8, 0>(f, rho, tree, st);
+    case 8 * 16 + 4: return leaf_fwd<8, 4>(f, rho, tree, st);
+    case 8 * 16 + 8: return leaf_fwd<8, 8>(f, rho, tree, st);
+    case 16 * 16: return leaf_fwd<16, 0>(f, rho, tree, st);
+    case 16 * 16 + 4: return leaf_fwd<16, 4>(f, rho, tree, st);
+    case 16 * 16 + 8: return leaf_fwd<16, 8>(f, rho, tree, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t inv_any(NearFft* f, float* out, const LeafTree& tree, int p, hipStream_t st) {
+  switch (f->s * 16 + p) {
+    case 4 * 16: return leaf_inv<4, 0>(f, out, tree, st);
+    case 8 * 16: return leaf_inv<8, 0>(f, out, tree, st);
+    case 8 * 16 + 4: return leaf_inv<8, 4>(f, out, tree, st);
+    case 8 * 16 + 8: return leaf_inv<8, 8>(f, out, tree, st);
+    case 16 * 16: return leaf_inv<16, 0>(f, out, tree, st);
+    case 16 * 16 + 4: return leaf_inv<16, 4>(f, out, tree, st);
+    case 16 * 16 + 8: return leaf_inv<16, 8>(f, out, tree, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t near_mac(NearFft* f, int t, int isolated, hipStream_t st) {
   const int nchunk = (int)(f->F / 64);
   const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * (f->nb / 2) * (f->nb / 2);
+  if (isolated)
+    k_near_mac<true, true><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
+                                                            f->yhat);
+  else
+    k_near_mac<true, false><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
+                                                             f->yhat);
+  return hipGetLastError();
+}
+
+hipError_t run_fused(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
+                     hipStream_t st, KernelTimer* kt) {
+  const LeafTree none{};
+  hipError_t e = tbegin(kt, st);
+  if (e == hipSuccess) e = tend(kt, st, 0, fwd_any(f, rho, none, 0, st));
   for (int t = 0; t < nout && e == hipSuccess; ++t) {
     e = tbegin(kt, st);
-    if (e != hipSuccess) break;
-    if (isolated)
-      k_near_mac<true, true><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
-                                                              f->yhat);
-    else
-      k_near_mac<true, false><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
-                                                               f->yhat);
-    e = tend(kt, st, 1 + 2 * t, hipGetLastError());
+    if (e == hipSuccess) e = tend(kt, st, 1 + 2 * t, near_mac(f, t, isolated, st));
     if (e == hipSuccess) e = tbegin(kt, st);
-    if (e == hipSuccess) {
-      k_leaf_inv<S><<<leaves, leaf_threads<S>(), 0, st>>>(f->yhat, f->N, f->lgnb, f->nleaf, out[t]);
-      e = tend(kt, st, 2 + 2 * t, hipGetLastError());
-    }
+    if (e == hipSuccess) e = tend(kt, st, 2 + 2 * t, inv_any(f, out[t], none, 0, st));
   }
+  return e;
+}
+
+int near_fft_folds(const NearFft* f, int p) {
+  return f->fused && (f->s == 8 || f->s == 16) && (p == 4 || p == 8);
+}
+
+hipError_t near_fft_begin(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
+                          const LeafTree& tree, hipEvent_t after_fwd, hipStream_t st,
+                          KernelTimer* kt) {
+  if (nout < 1 || nout > near_fft_kernels(f) || !near_fft_folds(f, tree.p) || !tree.A)
+    return hipErrorInvalidValue;
+  const LeafTree none{};
+  hipError_t e = tbegin(kt, st);
+  if (e == hipSuccess) e = tend(kt, st, 0, fwd_any(f, rho, tree, tree.M ? tree.p : 0, st));
+  if (e == hipSuccess && after_fwd) e = hipEventRecord(after_fwd, st);
+  for (int t = 1; t < nout && e == hipSuccess; ++t) {
+    e = tbegin(kt, st);
+    if (e == hipSuccess) e = tend(kt, st, 1 + 2 * t, near_mac(f, t, isolated, st));
+    if (e == hipSuccess) e = tbegin(kt, st);
+    if (e == hipSuccess) e = tend(kt, st, 2 + 2 * t, inv_any(f, out[t], none, 0, st));
+  }
+  if (e == hipSuccess) e = tbegin(kt, st);
+  if (e == hipSuccess) e = tend(kt, st, 1, near_mac(f, 0, isolated, st));
+  return e;
+}
+
+hipError_t near_fft_end(NearFft* f, float* out0, const LeafTree& tree, hipStream_t st,
+                        KernelTimer* kt) {
+  if (!near_fft_folds(f, tree.p) || !tree.A) return hipErrorInvalidValue;
+  hipError_t e = tbegin(kt, st);
+  if (e == hipSuccess) e = tend(kt, st, 2, inv_any(f, out0, tree, tree.Pl ? tree.p : 0, st));
   return e;
 }
 
 hipError_t near_fft_run(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
                         hipStream_t st, KernelTimer* kt) {
   if (nout < 1 || nout > near_fft_kernels(f)) return hipErrorInvalidValue;
-  if (f->fused) {
-    switch (f->s) {
-      case 4: return run_fused<4>(f, rho, out, nout, isolated, st, kt);
-      case 8: return run_fused<8>(f, rho, out, nout, isolated, st, kt);
-      default: return run_fused<16>(f, rho, out, nout, isolated, st, kt);
-    }
-  }
+  if (f->fused) return run_fused(f, rho, out, nout, isolated, st, kt);
   const int64_t total = f->nleaf * f->R;
   hipError_t e = tbegin(kt, st);
   if (e != hipSuccess) return e;

@@ -42,6 +42,9 @@ struct pfmm_plan_s {
   // join by events), except when profiling
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // with P2M and L2P folded into the near zone's leaf transforms: the leaf
+  // masses are ready (side -> stream), the leaf locals are ready (stream -> side)
+  hipEvent_t ev_mass = nullptr, ev_local = nullptr;
   int qn = 0, mn = 0;  // near-zone block edge and classes per axis
   float* dA = nullptr;  // [p][s] P2M / L2P weights
   float* dT = nullptr;  // [2][p][p] M2M / L2L weights
@@ -65,6 +68,7 @@ struct pfmm_plan_s {
   int m2l_spectral = 0;           // interaction zones as spectral stencils (PFMM_OPT_M2L)
   M2LSpectral* mspec = nullptr;   // its spectra and transformed kernels
   int near_fft = 0;               // leaf near zone by FFT convolution (PFMM_OPT_NEAR)
+  int fold = 0;                   // P2M and L2P inside its leaf transforms (PFMM_OPT_FOLD)
   NearFft* nfft = nullptr;        // its plans, buffers and transformed kernels
   uint16_t* zero = nullptr;       // 512 zero bf16 values: the source outside an isolated box
   // accelerations from the expansion (PFMM_OPT_ACCEL; tables on first use)
@@ -303,6 +307,8 @@ void release(pfmm_plan_s* pl) {
   }
   if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
   if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  if (pl->ev_mass) (void)hipEventDestroy(pl->ev_mass);
+  if (pl->ev_local) (void)hipEventDestroy(pl->ev_local);
   for (void* q : pl->owned) (void)hipFree(q);
   pl->owned.clear();
   delete pl;
@@ -678,6 +684,8 @@ pfmm_status build(pfmm_plan_s* pl) {
   if ((st = chk("side stream"))) return st;
   e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_mass, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_local, hipEventDisableTiming);
   if ((st = chk("fork events"))) return st;
   return tabulate_all(pl);
 }
@@ -758,6 +766,14 @@ pfmm_status pfmm_plan_set(pfmm_plan_t h, int option, const void* value, size_t b
                                             "in 64 KiB of LDS at this leaf width and p");
       }
       pl->prec = v;
+      return PFMM_OK;
+    }
+    case PFMM_OPT_FOLD: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fold is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      if (v != 0 && v != 1) return fail(PFMM_ERR_INVALID_ARG, "fold is 0 or 1");
+      pl->fold = v;
       return PFMM_OK;
     }
     case PFMM_OPT_LEARNED_WEIGHTS: {
@@ -1076,13 +1092,28 @@ pfmm_status solve_impl(pfmm_plan_s* pl, const void* rho_in, void* phi_out, void*
   nb.accumulate = 0;
   nb.groups = 1;
   nb.isolated = pl->isolated;
+  // P2M and L2P folded into the FFT near zone's leaf transforms of the
+  // potential (FP32 leaf gridlets): the tree waits for the forward
+  // transforms, the potential's inverse transform for the leaf locals
+  const bool fold = pl->fold && near_fft && !io64 && !is64(L) && near_fft_folds(pl->nfft, p);
+  const bool fold_p2m = fold, fold_l2p = fold;
+  LeafTree lt{};
+  if (fold) {
+    lt.M = fold_p2m ? static_cast<float*>(pl->M[L]) : nullptr;
+    lt.Pl = fold_l2p ? static_cast<const float*>(pl->P[L]) : nullptr;
+    lt.A = pl->dA;
+    lt.h3 = (float)h3;
+    lt.p = p;
+  }
   tm.at(PFMM_STAGE_NEAR, 0);
   if (near_fft) {  // each of its kernels timed
     float* outs[4] = {phi, nullptr, nullptr, nullptr};
     int nout = 1;
     if (accel && pl->accel_mode)
       for (int c = 0; c < 3; ++c) outs[nout++] = accel + (size_t)c * N * N * N;
-    e = near_fft_run(pl->nfft, rho, outs, nout, pl->isolated, sn, tm.on ? &tm : nullptr);
+    e = fold ? near_fft_begin(pl->nfft, rho, outs, nout, pl->isolated, lt,
+                              overlap ? pl->ev_mass : nullptr, sn, tm.on ? &tm : nullptr)
+             : near_fft_run(pl->nfft, rho, outs, nout, pl->isolated, sn, tm.on ? &tm : nullptr);
   } else if (mx && pl->nwin) {
     e = tm.begin(sn);
     if (e == hipSuccess) e = split_mesh(rho, (float)h3, N, kNearTerms, pl->xsn, sn);
@@ -1120,15 +1151,22 @@ pfmm_status solve_impl(pfmm_plan_s* pl, const void* rho_in, void* phi_out, void*
     }
     if (e == hipSuccess) e = tm.end(sn, 0);
   }
-  if (e == hipSuccess && overlap) e = hipEventRecord(pl->ev_join, pl->side);
+  if (e == hipSuccess && overlap && !fold) e = hipEventRecord(pl->ev_join, pl->side);
   if (e != hipSuccess) return hip_fail(e, "near zone");
 
   // upward pass
-  e = timed(PFMM_STAGE_P2M, 0, st, [&] {
-    return io64 ? launch_p2m_f64in(static_cast<const double*>(rho_in), pl->M[L], A, N, s, p, h3, st)
-                : launch_p2m(rho, pl->M[L], is64(L), A, N, s, p, (double)h3, st);
-  });
-  if (e != hipSuccess) return hip_fail(e, "P2M");
+  if (fold_p2m) {
+    if (overlap) {
+      e = hipStreamWaitEvent(st, pl->ev_mass, 0);
+      if (e != hipSuccess) return hip_fail(e, "leaf masses");
+    }
+  } else {
+    e = timed(PFMM_STAGE_P2M, 0, st, [&] {
+      return io64 ? launch_p2m_f64in(static_cast<const double*>(rho_in), pl->M[L], A, N, s, p, h3, st)
+                  : launch_p2m(rho, pl->M[L], is64(L), A, N, s, p, (double)h3, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "P2M");
+  }
   for (int l = L - 1; l >= 2; --l) {
     e = timed(PFMM_STAGE_M2M, l, st, [&] {
       return launch_m2m(pl->M[l + 1], is64(l + 1), pl->M[l], is64(l), T, 1 << l, p, st);
@@ -1180,15 +1218,27 @@ pfmm_status solve_impl(pfmm_plan_s* pl, const void* rho_in, void* phi_out, void*
   }
 
   // downward to the mesh, added to the near zone
+  if (fold) {
+    if (overlap && fold_l2p) {
+      e = hipEventRecord(pl->ev_local, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(sn, pl->ev_local, 0);
+    }
+    tm.at(PFMM_STAGE_NEAR, 0);
+    if (e == hipSuccess) e = near_fft_end(pl->nfft, phi, lt, sn, tm.on ? &tm : nullptr);
+    if (e == hipSuccess && overlap) e = hipEventRecord(pl->ev_join, sn);
+    if (e != hipSuccess) return hip_fail(e, "near zone");
+  }
   if (overlap) {
     e = hipStreamWaitEvent(st, pl->ev_join, 0);
     if (e != hipSuccess) return hip_fail(e, "join");
   }
-  e = timed(PFMM_STAGE_L2P, 0, st, [&] {
-    return io64 ? launch_l2p_f64out(pl->P[L], static_cast<double*>(phi_out), A, N, s, p, st, 1)
-                : launch_l2p(pl->P[L], is64(L), phi, A, N, s, p, st, 1);
-  });
-  if (e != hipSuccess) return hip_fail(e, "L2P");
+  if (!fold_l2p) {
+    e = timed(PFMM_STAGE_L2P, 0, st, [&] {
+      return io64 ? launch_l2p_f64out(pl->P[L], static_cast<double*>(phi_out), A, N, s, p, st, 1)
+                  : launch_l2p(pl->P[L], is64(L), phi, A, N, s, p, st, 1);
+    });
+    if (e != hipSuccess) return hip_fail(e, "L2P");
+  }
 
   if (accel && pl->accel_mode) {
     // far part: gradient of the leaf's local expansion, -d/dx = -(1/eta_L) d/dv

@@ -228,6 +228,123 @@ __global__ __launch_bounds__(kThreads) void k_l2l(const TI* __restrict__ Pp,
   }
 }
 
+// M2M and L2L with the gridlet size fixed at compile time, the eight
+// children in one pass per axis instead of one child after another.  The
+// child operators are T_o = T_ox (x) T_oy (x) T_oz with two 1D matrices
+// T_0, T_1, so along each axis the two children of a pair share the pass:
+// M2M contracts x over (ox, kx) for the four (oy, oz), then y over (oy, ky)
+// for the two oz, then z over (oz, kz) (14 p^4 multiply-adds against
+// 24 p^4 child by child, three barriers against 32); L2L expands x into the
+// two ox, y into four (ox, oy), z into the eight children.
+template <class TI, class TO, class W, int P>
+__global__ __launch_bounds__(kThreads) void k_m2m_pairs(const TI* __restrict__ Mc,
+                                                         TO* __restrict__ Mp, Weights Tw, int np) {
+  constexpr int P2 = P * P, P3 = P2 * P;
+  extern __shared__ __align__(8) unsigned char smraw[];
+  W* sT = reinterpret_cast<W*>(smraw);  // [o][a][k]
+  W* sTt = sT + 2 * P2;                 // [o][k][a]
+  W* c = sTt + 2 * P2;                  // children [ox][oy][oz][kx][ky][kz]
+  W* w = c + 8 * P3;                    // [oy][oz][ax][ky][kz]
+  W* v = c;                             // [oz][ax][ay][kz], over the children
+  const W* T = wsel<W>(Tw);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * P2; i += kThreads) {
+    const int o = i / P2, a = (i / P) % P, k = i % P;
+    sT[i] = T[i];
+    sTt[(o * P + k) * P + a] = T[i];
+  }
+  const int B = blockIdx.x;
+  const int Bx = B / (np * np), By = (B / np) % np, Bz = B % np;
+  const int nc = 2 * np;
+  for (int i = tid; i < 8 * P3; i += kThreads) {
+    const int o = i / P3;
+    const size_t child = ((size_t)(2 * Bx + (o >> 2)) * nc + (2 * By + ((o >> 1) & 1))) * nc +
+                         (2 * Bz + (o & 1));
+    c[i] = (W)Mc[child * P3 + i % P3];
+  }
+  __syncthreads();
+  for (int i = tid; i < 4 * P3; i += kThreads) {
+    const int q = i / P3, ax = (i / P2) % P, kyz = i % P2;
+    W acc = 0;
+#pragma unroll
+    for (int ox = 0; ox < 2; ++ox)
+#pragma unroll
+      for (int kx = 0; kx < P; ++kx)
+        acc += sT[(ox * P + ax) * P + kx] * c[((ox * 4 + q) * P + kx) * P2 + kyz];
+    w[i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < 2 * P3; i += kThreads) {
+    const int oz = i / P3, ax = (i / P2) % P, ay = (i / P) % P, kz = i % P;
+    W acc = 0;
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ky = 0; ky < P; ++ky)
+        acc += sT[(oy * P + ay) * P + ky] * w[(oy * 2 + oz) * P3 + (ax * P + ky) * P + kz];
+    v[i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < P3; i += kThreads) {
+    const int axy = i / P, az = i % P;
+    W acc = 0;
+#pragma unroll
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+      for (int kz = 0; kz < P; ++kz) acc += sTt[(oz * P + kz) * P + az] * v[oz * P3 + axy * P + kz];
+    Mp[(size_t)B * P3 + i] = (TO)acc;
+  }
+}
+
+template <class TI, class TO, class W, int P>
+__global__ __launch_bounds__(kThreads) void k_l2l_pairs(const TI* __restrict__ Pp,
+                                                         TO* __restrict__ Pc, Weights Tw, int np,
+                                                         int accumulate) {
+  constexpr int P2 = P * P, P3 = P2 * P;
+  extern __shared__ __align__(8) unsigned char smraw[];
+  W* sT = reinterpret_cast<W*>(smraw);  // [o][a][b]: child node b from parent node a
+  W* par = sT + 2 * P2;                 // [ax][ay][az]
+  W* w = par + P3;                      // [ox][bx][ay][az]
+  W* v = w + 2 * P3;                    // [ox][oy][bx][by][az]
+  const W* T = wsel<W>(Tw);
+  const int tid = threadIdx.x;
+  const int B = blockIdx.x;
+  const int Bx = B / (np * np), By = (B / np) % np, Bz = B % np;
+  const int nc = 2 * np;
+  for (int i = tid; i < 2 * P2; i += kThreads) sT[i] = T[i];
+  for (int i = tid; i < P3; i += kThreads) par[i] = (W)Pp[(size_t)B * P3 + i];
+  __syncthreads();
+  for (int i = tid; i < 2 * P3; i += kThreads) {
+    const int ox = i / P3, bx = (i / P2) % P, ayz = i % P2;
+    W acc = 0;
+#pragma unroll
+    for (int ax = 0; ax < P; ++ax) acc += sT[(ox * P + ax) * P + bx] * par[ax * P2 + ayz];
+    w[i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < 4 * P3; i += kThreads) {
+    const int q = i / P3, bx = (i / P2) % P, by = (i / P) % P, az = i % P;
+    const int ox = q >> 1, oy = q & 1;
+    W acc = 0;
+#pragma unroll
+    for (int ay = 0; ay < P; ++ay)
+      acc += sT[(oy * P + ay) * P + by] * w[ox * P3 + (bx * P + ay) * P + az];
+    v[i] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < 8 * P3; i += kThreads) {
+    const int o = i / P3, bxy = (i / P) % P2, bz = i % P;
+    const int oz = o & 1;
+    W acc = 0;
+#pragma unroll
+    for (int az = 0; az < P; ++az) acc += sT[(oz * P + az) * P + bz] * v[(o >> 1) * P3 + bxy * P + az];
+    const size_t child = ((size_t)(2 * Bx + (o >> 2)) * nc + (2 * By + ((o >> 1) & 1))) * nc +
+                         (2 * Bz + oz);
+    TO* dst = Pc + child * P3 + i % P3;
+    *dst = accumulate ? (TO)((W)*dst + acc) : (TO)acc;
+  }
+}
+
 // out[b s + c] (+)= scale sum_a Wx[ax][cx] Wy[ay][cy] Wz[az][cz] P[b][a]: L2P
 // with Wx = Wy = Wz = A and scale 1, or one component of the gradient of the
 // leaf's local expansion with the derivative weights on that axis
@@ -410,10 +527,33 @@ hipError_t launch_p2m(const float* rho, void* M, int m64, Weights A, int N, int 
       hipLaunchKernelGGL((KERNEL<TI, TO, W>), __VA_ARGS__);       \
   } while (0)
 
+// The pairwise kernels at p = 4, 8 (LDS words: the weights twice, eight
+// children and the four x-contracted pairs).
+#define PFMM_PAIRS(KERNEL, TI, TO, W, ...)                        \
+  do {                                                            \
+    if (p == 8)                                                   \
+      hipLaunchKernelGGL((KERNEL<TI, TO, W, 8>), __VA_ARGS__);    \
+    else                                                          \
+      hipLaunchKernelGGL((KERNEL<TI, TO, W, 4>), __VA_ARGS__);    \
+  } while (0)
+
 hipError_t launch_m2m(const void* Mc, int c64, void* Mp, int p64, Weights T, int np, int p,
                       hipStream_t st) {
-  const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
   const dim3 g(np * np * np), b(kThreads);
+  if (p == 4 || p == 8) {
+    const size_t pw = (size_t)(4 * p * p + 12 * p * p * p);
+    if (!c64 && !p64)
+      PFMM_PAIRS(k_m2m_pairs, float, float, float, g, b, pw * 4, st, (const float*)Mc, (float*)Mp, T, np);
+    else if (!c64 && p64)
+      PFMM_PAIRS(k_m2m_pairs, float, double, double, g, b, pw * 8, st, (const float*)Mc, (double*)Mp, T, np);
+    else if (c64 && p64)
+      PFMM_PAIRS(k_m2m_pairs, double, double, double, g, b, pw * 8, st, (const double*)Mc, (double*)Mp, T,
+                 np);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
   if (!c64 && !p64)
     PFMM_BY_P(k_m2m, float, float, float, g, b, words * 4, st, (const float*)Mc, (float*)Mp, T, np, p);
   else if (!c64 && p64)
@@ -428,8 +568,23 @@ hipError_t launch_m2m(const void* Mc, int c64, void* Mp, int p64, Weights T, int
 
 hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int np, int p,
                       hipStream_t st, int accumulate) {
-  const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
   const dim3 g(np * np * np), b(kThreads);
+  if (p == 4 || p == 8) {
+    const size_t pw = (size_t)(2 * p * p + 7 * p * p * p);
+    if (!p64 && !c64)
+      PFMM_PAIRS(k_l2l_pairs, float, float, float, g, b, pw * 4, st, (const float*)Pp, (float*)Pc, T, np,
+                 accumulate);
+    else if (p64 && !c64)
+      PFMM_PAIRS(k_l2l_pairs, double, float, double, g, b, pw * 8, st, (const double*)Pp, (float*)Pc, T,
+                 np, accumulate);
+    else if (p64 && c64)
+      PFMM_PAIRS(k_l2l_pairs, double, double, double, g, b, pw * 8, st, (const double*)Pp, (double*)Pc,
+                 T, np, accumulate);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  const size_t words = (size_t)(2 * p * p + 3 * p * p * p);
   if (!p64 && !c64)
     PFMM_BY_P(k_l2l, float, float, float, g, b, words * 4, st, (const float*)Pp, (float*)Pc, T, np, p,
               accumulate);
@@ -444,6 +599,7 @@ hipError_t launch_l2l(const void* Pp, int p64, void* Pc, int c64, Weights T, int
   return hipGetLastError();
 }
 #undef PFMM_BY_P
+#undef PFMM_PAIRS
 
 namespace {
 hipError_t l2p_axes(const void* P, int p64, float* out, Weights Wx, Weights Wy, Weights Wz,

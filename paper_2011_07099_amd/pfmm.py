@@ -16,7 +16,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_CAPTURE, E
 GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3, "E": 4, "LEARNED": 5}
 PREC = {"fp32": 0, "bf16x3": 1, "fp64": 2}
 OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED, OPT_GS_A2, \
-    OPT_ACCEL, OPT_EWALD_RS, OPT_M2L, OPT_NEAR, OPT_LEARNED_WEIGHTS = range(1, 13)
+    OPT_ACCEL, OPT_EWALD_RS, OPT_M2L, OPT_NEAR, OPT_LEARNED_WEIGHTS, OPT_FOLD = range(1, 14)
 M2L = {"gemm": 0, "fft": 1, "spectral": 2}
 NEAR = {"direct": 0, "fft": 1}
 ACCEL = {"fd4": 0, "expansion": 1}
@@ -127,7 +127,7 @@ class Plan:
 
     def __init__(self, N, L, p, green="S1", precision="fp32", a1=None, stream=None,
                  fp64_levels=None, isolated=False, a2=None, accel="fd4", rs=None, m2l="gemm",
-                 near="direct"):
+                 near="direct", fold=False):
         import torch
         lib = load()
         h = ctypes.c_void_p()
@@ -158,6 +158,14 @@ class Plan:
             self.set_m2l(m2l)
         if near != "direct":
             self.set_near(near)
+        if fold:
+            self.set_fold(True)
+
+    def set_fold(self, on):
+        """P2M and L2P inside the FFT near zone's leaf transforms (leaf edge 8
+        or 16, p = 4 or 8, FP32 leaf level); see PFMM_OPT_FOLD."""
+        v = ctypes.c_int32(1 if on else 0)
+        _check(load().pfmm_plan_set(self._h, OPT_FOLD, ctypes.byref(v), 4))
 
     def set_near(self, mode):
         """Leaf near zone by "direct" summation (block Toeplitz) or "fft"

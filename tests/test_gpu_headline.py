@@ -24,7 +24,8 @@ error is the split near zone's (~1.3e-6; tolerance 1e-5) or FP32 rounding
 the split path's tolerances.  With the interaction zones as FP64 spectral
 stencils (the benchmark's default) every level's zones are FP64 whatever the
 level's storage, and the error left is FP32 storage and the near zone's,
-measured 2.5e-6: tolerance 1e-5.
+measured 2.5e-6: tolerance 1e-5, also with P2M and L2P folded into the
+near zone's leaf transforms (PFMM_OPT_FOLD).
 """
 import numpy as np
 import pytest
@@ -49,10 +50,10 @@ def _targets():
 
 # (precision, FP64 levels, near zone) -> sampled-cell tolerance against the
 # FP64 reference FMM
-CASES = {("fp32", 2, "direct", "gemm"): 2e-4, ("bf16x3", 2, "direct", "gemm"): 1e-4,
-         ("fp32", 3, "direct", "gemm"): 1e-6, ("bf16x3", 3, "direct", "gemm"): 1e-5,
-         ("bf16x3", 2, "fft", "gemm"): 1e-4, ("bf16x3", 3, "fft", "gemm"): 1e-5,
-         ("bf16x3", 2, "fft", "spectral"): 1e-5}
+CASES = {("fp32", 2, "direct", "gemm", 0): 2e-4, ("bf16x3", 2, "direct", "gemm", 0): 1e-4,
+         ("fp32", 3, "direct", "gemm", 0): 1e-6, ("bf16x3", 3, "direct", "gemm", 0): 1e-5,
+         ("bf16x3", 2, "fft", "gemm", 0): 1e-4, ("bf16x3", 3, "fft", "gemm", 0): 1e-5,
+         ("bf16x3", 2, "fft", "spectral", 0): 1e-5, ("bf16x3", 2, "fft", "spectral", 1): 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -66,11 +67,12 @@ def reference(rho):
     return tg, ofmm.fmm(rho, L, P, "S1", targets=tg), conv.pm(rho, "S1")
 
 
-@pytest.fixture(scope="module", params=sorted(CASES), ids=lambda c: "%s-fp64levels%d-near-%s-m2l-%s" % c)
+@pytest.fixture(scope="module", params=sorted(CASES),
+                ids=lambda c: "%s-fp64levels%d-near-%s-m2l-%s-fold%d" % c)
 def headline(request, rho):
-    prec, f64, near, m2l = request.param
+    prec, f64, near, m2l, fold = request.param
     return request.param, solve(rho, L, P, "S1", precision=prec, fp64_levels=f64, near=near,
-                                m2l=m2l)["phi"]
+                                m2l=m2l, fold=bool(fold))["phi"]
 
 
 def test_headline_sampled_vs_reference_fmm(headline, reference):

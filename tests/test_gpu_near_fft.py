@@ -6,6 +6,12 @@ paper takes for a leaf's near zone, Sec. 2-3), through the C ABI.
   leaf edges s = 1 .. 16, several G, FP32 and split precision for the rest of
   the tree.  Tolerance 2e-5 of max|phi|: FP32 rounding of (2s)^3 transforms
   (grows like log s) on top of the FP32 tree.
+* PFMM_OPT_FOLD (P2M inside the forward transform, L2P inside the
+  potential's inverse transform; library transforms at s = 8, 16 with
+  p = 4, 8 and an FP32 leaf level): periodic and isolated cases at s = 8
+  with p = 4 and 8, with and without expansion accelerations, and s = 16
+  with p = 4 at sampled cells that run through every position inside a leaf
+  (s = 16 with p = 8 is the headline test's).
 * Accelerations from the expansion, whose three near-zone kernels reuse the
   forward transforms, against the oracle's ``fmm_accel``.
 * Leaf and near-zone corner cases: one cell per leaf (s = 1, a 2^3 cyclic
@@ -28,43 +34,65 @@ from gpu_util import f32, rel_max, solve
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("N,L,p,green,prec,iso", [
-    (32, 3, 4, "S1", "fp32", False),   # s = 4
-    (64, 3, 8, "S1", "bf16x3", False),  # s = 8, split tree
-    (64, 2, 8, "K", "fp32", False),     # s = 16, the smallest periodic tree
-    (16, 4, 2, "X", "fp32", False),     # s = 1
-    (32, 3, 4, "X", "fp32", True),      # isolated twin
-    (64, 3, 6, "X", "fp32", True),
-    (32, 4, 3, "S1", "fp32", False),    # s = 2, odd p
+@pytest.mark.parametrize("N,L,p,green,prec,iso,fold", [
+    (32, 3, 4, "S1", "fp32", False, False),   # s = 4
+    (64, 3, 8, "S1", "bf16x3", False, False),  # s = 8, split tree
+    (64, 3, 8, "S1", "bf16x3", False, True),   # the same, P2M and L2P folded
+    (64, 2, 8, "K", "fp32", False, False),     # s = 16, the smallest periodic tree
+    (16, 4, 2, "X", "fp32", False, False),     # s = 1
+    (32, 3, 4, "X", "fp32", True, False),      # isolated twin
+    (64, 3, 6, "X", "fp32", True, False),
+    (32, 4, 3, "S1", "fp32", False, False),    # s = 2, odd p
+    (64, 3, 4, "S1", "fp32", False, True),     # s = 8, p = 4, folded
+    (64, 3, 4, "X", "fp32", True, True),       # the same, isolated
 ])
-def test_fft_near_zone_matches_reference_and_direct(N, L, p, green, prec, iso):
+def test_fft_near_zone_matches_reference_and_direct(N, L, p, green, prec, iso, fold):
     rho = f32(fields.lognormal(N, 1.5, 1.0, seed=171 + N + p))
-    got = solve(rho, L, p, green, precision=prec, isolated=iso, near="fft")["phi"]
+    got = solve(rho, L, p, green, precision=prec, isolated=iso, near="fft", fold=fold)["phi"]
     ref = ofmm.fmm(rho, L, p, green, periodic=not iso)
     direct = solve(rho, L, p, green, precision=prec, isolated=iso)["phi"]
     e, ed = rel_max(got, ref), rel_max(got, direct)
-    print("FFT near zone", (N, L, p, green, prec, "isolated" if iso else "periodic"),
+    print("FFT near zone", (N, L, p, green, prec, "isolated" if iso else "periodic",
+                            "folded" if fold else "separate P2M and L2P"),
           "vs reference %.3e, vs direct near zone %.3e" % (e, ed))
     tol = 2e-5 if prec == "fp32" else 1e-4
     assert e < tol and ed < tol
 
 
-@pytest.mark.parametrize("N,L,p,prec,iso", [
-    (32, 3, 4, "fp32", False),
-    (64, 3, 8, "bf16x3", False),
-    (32, 2, 6, "fp32", True),
+@pytest.mark.parametrize("N,L,p,prec,iso,fold", [
+    (32, 3, 4, "fp32", False, False),
+    (64, 3, 8, "bf16x3", False, False),
+    (64, 3, 8, "bf16x3", False, True),
+    (32, 2, 6, "fp32", True, False),
 ])
-def test_fft_near_zone_expansion_accel(N, L, p, prec, iso):
+def test_fft_near_zone_expansion_accel(N, L, p, prec, iso, fold):
     rho = f32(fields.lognormal(N, 1.5, 1.0, seed=181 + N + p))
     green = "X" if iso else "S1"
     out = solve(rho, L, p, green, accel=True, precision=prec, isolated=iso,
-                accel_mode="expansion", near="fft")
+                accel_mode="expansion", near="fft", fold=fold)
     ref, ref_phi = ofmm.fmm_accel(rho, L, p, green, periodic=not iso)
     e, ep = rel_max(out["accel"], ref), rel_max(out["phi"], ref_phi)
-    print("FFT near zone, expansion accel", (N, L, p, prec, iso),
+    print("FFT near zone, expansion accel", (N, L, p, prec, iso, fold),
           "max err / max|g| = %.3e, potential %.3e" % (e, ep))
     tol = 2e-5 if prec == "fp32" else 2e-4
     assert e < tol and ep < tol
+
+
+def test_folded_p2m_l2p_at_16_cell_leaves_p4():
+    N, L, p = 128, 3, 4
+    s = N >> L
+    rho = f32(fields.lognormal(N, 1.5, 1.0, seed=175))
+    k = np.arange(N // s)
+    # two cells per leaf and axis, together every position 0 .. 15
+    c = np.concatenate([s * k + (7 * k + 15) % s, s * k + (7 * k + 15 + s // 2) % s])
+    tg = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    assert len(np.unique(c % s)) == s
+    got = solve(rho, L, p, "S1", near="fft", m2l="spectral", fold=True)["phi"]
+    ref = ofmm.fmm(rho, L, p, "S1", targets=tg)
+    e = np.max(np.abs(got[tg[:, 0], tg[:, 1], tg[:, 2]] - ref)) / np.max(np.abs(got))
+    print("FFT near zone with P2M and L2P folded, s = 16, p = 4: sampled max err / max|phi| "
+          "= %.3e" % e)
+    assert e < 2e-5
 
 
 def test_fft_near_zone_point_mass_and_zero():
