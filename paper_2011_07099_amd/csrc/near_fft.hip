@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace pfmm {
 
@@ -49,6 +50,7 @@ struct NearFft {
   double2* dft[2] = {nullptr, nullptr};                    // [F] FP64 DFT passes
   int fused = 0;             // s in {4, 8, 16}: fused LDS transforms, chunked spectra
   int lgnb = 0;              // log2 of leaves per axis
+  int sym[4] = {0, 0, 0, 0};  // per kernel: +1 even, -1 odd, 0 neither (k_near_mac)
 };
 
 namespace {
@@ -531,18 +533,24 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
 // registers.  Each step first adds the lowest plane's terms, then reloads
 // that plane's registers with the plane two above (in flight while the other
 // two planes' terms are added), so three register sets rotate.  The
-// thread's 27 kernel values sit in its own slots of LDS (no barrier: only
-// the writing thread reads them), which keeps the register count for three
+// thread's kernel values sit in its own slots of LDS (no barrier: only the
+// writing thread reads them), which keeps the register count for three
 // waves per SIMD.  The pencil blocks of one frequency chunk go to one XCD
 // (blocks are dealt to the 8 XCDs round robin), so its L2 serves the column
 // re-reads between neighbouring blocks.
-template <bool CHUNKED, bool ISO>
+//
+// SYM = +1 (-1): the kernel is even (odd) in the cell separation, so the
+// transform of neighbour -e is the conjugate (minus the conjugate) of that of
+// e, and only the 14 kernels from the centre up in index order are kept in
+// LDS (half the LDS per thread).  SYM = 0: all 27.
+template <bool CHUNKED, bool ISO, int SYM = 0>
 __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
     const float2* __restrict__ rhat, const float2* __restrict__ khat, int nb, int64_t F,
     int nchunk, float2* __restrict__ yhat) {
   constexpr bool isolated = ISO;  // sources outside the box are absent
   constexpr int W = CHUNKED ? 64 : kThreads;  // frequencies per block
-  __shared__ float2 kks[27 * W];
+  constexpr int NK = SYM ? 14 : 27;           // kernels kept
+  __shared__ float2 kks[NK * W];
   const int g = blockIdx.x;
   const int hb = nb >> 1;
   const int np = hb * hb;  // 2 x 2 pencil blocks
@@ -572,9 +580,12 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
   const int msk = nb - 1;
   const int blk = j % np;
   const int bx0 = 2 * (blk / hb), by0 = 2 * (blk % hb);
-  float2* kk = kks + threadIdx.x;  // kernel e at kk[e * W]
+  float2* kk = kks + threadIdx.x;  // kernel e at kk[slot(e) * W]
+  // e = (ex, ey, ez) in {0, 1, 2}^3 (offset e - 1), index 9 ex + 3 ey + ez;
+  // its opposite is 26 - e.  With SYM the kernels e >= 13 sit at slot
+  // e - 13 and e < 13 reads slot 13 - e (its opposite's) conjugated.
 #pragma unroll
-  for (int e = 0; e < 27; ++e) kk[e * W] = khat[(int64_t)e * F + k];
+  for (int e = SYM ? 13 : 0; e < 27; ++e) kk[(SYM ? e - 13 : e) * W] = khat[(int64_t)e * F + k];
   // columns (bx0 - 1 + ix, by0 - 1 + iy), ix, iy in [0, 4), c = 4 ix + iy
   auto load = [&](int c, int z) -> float2 {
     const int sx = bx0 - 1 + c / 4, sy = by0 - 1 + c % 4;
@@ -612,7 +623,10 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
     for (int ex = 0; ex < 3; ++ex)
 #pragma unroll
       for (int ey = 0; ey < 3; ++ey) {
-        const float2 kv = kk[(ex * 9 + ey * 3 + ez) * W];
+        const int e = ex * 9 + ey * 3 + ez;
+        const bool kept = !SYM || e >= 13;
+        float2 kv = kk[(SYM ? (kept ? e - 13 : 13 - e) : e) * W];
+        if (!kept) kv = SYM > 0 ? make_float2(kv.x, -kv.y) : make_float2(-kv.x, kv.y);
 #pragma unroll
         for (int tx = 0; tx < 2; ++tx)
 #pragma unroll
@@ -723,6 +737,23 @@ hipError_t near_fft_tables(NearFft* f, const double* const* tabs, int ntabs, dou
       e = hipGetLastError();
     }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  // parity of each kernel: its neighbour -e is the conjugate (even kernel)
+  // or minus the conjugate (odd) of neighbour e at every frequency, to FP32
+  // rounding of the largest value
+  std::vector<float2> h((size_t)27 * f->F);
+  for (int t = 0; t < ntabs && e == hipSuccess; ++t) {
+    e = hipMemcpy(h.data(), f->khat[t], h.size() * sizeof(float2), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) break;
+    double big = 0.0, de = 0.0, dodd = 0.0;
+    for (int ei = 0; ei < 27; ++ei)
+      for (int64_t k = 0; k < f->F; ++k) {
+        const float2 a = h[(size_t)ei * f->F + k], b = h[(size_t)(26 - ei) * f->F + k];
+        big = std::max(big, (double)std::hypot(a.x, a.y));
+        de = std::max(de, std::hypot((double)a.x - b.x, (double)a.y + b.y));
+        dodd = std::max(dodd, std::hypot((double)a.x + b.x, (double)a.y - b.y));
+      }
+    f->sym[t] = de <= 1e-6 * big ? 1 : dodd <= 1e-6 * big ? -1 : 0;
+  }
   return e;
 }
 
@@ -783,16 +814,21 @@ hipError_t inv_any(NearFft* f, float* out, const LeafTree& tree, int p, hipStrea
   }
 }
 
-hipError_t near_mac(NearFft* f, int t, int isolated, hipStream_t st) {
+template <bool ISO>
+hipError_t near_mac_iso(NearFft* f, int t, hipStream_t st) {
   const int nchunk = (int)(f->F / 64);
-  const int64_t blocks = (int64_t)((nchunk + 7) / 8) * 8 * (f->nb / 2) * (f->nb / 2);
-  if (isolated)
-    k_near_mac<true, true><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
-                                                            f->yhat);
+  const unsigned blocks = (unsigned)((int64_t)((nchunk + 7) / 8) * 8 * (f->nb / 2) * (f->nb / 2));
+  if (f->sym[t] > 0)
+    k_near_mac<true, ISO, 1><<<blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk, f->yhat);
+  else if (f->sym[t] < 0)
+    k_near_mac<true, ISO, -1><<<blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk, f->yhat);
   else
-    k_near_mac<true, false><<<(unsigned)blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk,
-                                                             f->yhat);
+    k_near_mac<true, ISO, 0><<<blocks, 64, 0, st>>>(f->rhat, f->khat[t], f->nb, f->F, nchunk, f->yhat);
   return hipGetLastError();
+}
+
+hipError_t near_mac(NearFft* f, int t, int isolated, hipStream_t st) {
+  return isolated ? near_mac_iso<true>(f, t, st) : near_mac_iso<false>(f, t, st);
 }
 
 hipError_t run_fused(NearFft* f, const float* rho, float* const* out, int nout, int isolated,
