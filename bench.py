@@ -461,6 +461,9 @@ def main():
     ap.add_argument("--near", default="fft", choices=["direct", "fft"],
                     help="leaf near zone by direct summation or by FFT convolution "
                          "(headline and batch workloads)")
+    ap.add_argument("--zones", default="fp32", choices=["fp32", "fp64"],
+                    help="arithmetic of the 16^3 leaf level's spectral zone stencil: FP32 "
+                         "columns with FP64 totals (PFMM_OPT_ZONES_FP32) or FP64")
     ap.add_argument("--m2l", default="spectral", choices=["gemm", "spectral"],
                     help="interaction zones by block-Toeplitz GEMM or spectral stencils "
                          "(headline and batch workloads)")
@@ -553,11 +556,11 @@ def kernel_work(name, N, L, p, route=None):
         if route["precision"] == "bf16x3" and s in (8, 16):
             return fl, "bf16 mfma", None, 3
         return fl, "f32 valu", None, 1
-    r = _default_work(name, N, L, p, s, route.get("fold", False))
+    r = _default_work(name, N, L, p, s, route.get("fold", False), route.get("zones_fp32_level"))
     return r + (1,)
 
 
-def _default_work(name, N, L, p, s, fold=False):
+def _default_work(name, N, L, p, s, fold=False, zones_fp32_level=None):
     if name.startswith("m2l L"):
         lv = int(name.split()[1][1:])
         F = (2 * p) ** 2 * (p + 1)
@@ -566,7 +569,8 @@ def _default_work(name, N, L, p, s, fold=False):
         gl = (8.0 if lv in FP64_LEVELS else 4.0) * p ** 3 * nodes  # gridlet buffer
         if name.endswith("stencil"):
             offs = 37 if lv == 2 else 189
-            return offs * 8.0 * F * nodes, "f64 valu", 2 * spec + 343 * 16.0 * F
+            unit = "f32 valu" if lv == zones_fp32_level else "f64 valu"
+            return offs * 8.0 * F * nodes, unit, 2 * spec + 343 * 16.0 * F
         if name.endswith("inverse transforms"):
             return None, "hbm", spec + 2 * gl
         return None, "hbm", spec + gl
@@ -645,9 +649,10 @@ def headline(args):
     rho = torch.from_numpy(rho32).to(dev)
     phi = torch.empty_like(rho)
     stream = torch.cuda.current_stream(dev)
+    zones32 = args.zones == "fp32" and args.m2l == "spectral" and L == 4
     plan = Plan(N, L, P, GREEN, precision=args.precision, stream=stream,
                 accel="expansion" if args.accel == "expansion" else "fd4", near=args.near,
-                m2l=args.m2l)
+                m2l=args.m2l, zones_fp32=zones32)
     acc = (torch.empty((3, N, N, N), dtype=torch.float32, device=dev)
            if args.accel != "none" else None)
     for _ in range(args.warmup):
@@ -692,7 +697,7 @@ def headline(args):
     # P2M and L2P run inside the near zone's leaf transforms when they have
     # no stage of their own
     route = {"m2l": args.m2l, "near": args.near, "precision": args.precision,
-             "fold": near_fft and stages["p2m"][1] == 0}
+             "fold": near_fft and stages["p2m"][1] == 0, "zones_fp32_level": L if zones32 else None}
 
     def roof(name, dms):
         fl, unit, kbytes, products = kernel_work(name, N, L, P, route)
@@ -748,11 +753,15 @@ def headline(args):
         "config": {"workload": "periodic FMM, 256^3 lognormal density (P(k)~k^-1.5, "
                                "sigma_delta=2, seed 5), L=4 (16^3-cell leaves), p=8, G_S1",
                    "N": N, "L": L, "p": P, "green": GREEN,
-                   "arithmetic": ("FP32 near zone (FFT on the doubled grid) and mesh transfers, "
-                                  "FP64 interaction zones (spectral stencils) and levels 2-3"
+                   "arithmetic": (("FP32 near zone (FFT on the doubled grid) and mesh transfers, "
+                                   + ("leaf-level zone stencil in FP32 columns with FP64 totals, "
+                                      "FP64 zone transforms, level 2-3 zones and levels 2-3"
+                                      if zones32 else
+                                      "FP64 interaction zones (spectral stencils) and levels 2-3"))
                                   if (near_fft and spectral) else args.precision),
                    **({"accel": args.accel} if args.accel != "none" else {}),
-                   "near": args.near, "m2l": args.m2l},
+                   "near": args.near, "m2l": args.m2l,
+                   **({"zones": args.zones} if spectral else {})},
         "roofline": roofline,
         "live_profiled_ms_per_step": runs["live"]["ms"],
         "serial_ms_per_step": runs["serial"]["ms"],

@@ -336,6 +336,9 @@ void m2l_spectral_destroy(M2LSpectral* f);
 // Transform the kernels of every offset in [-3, 3]^3 from the FP64 level
 // tables; synchronises `st`.
 hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64, hipStream_t st);
+// on = 1: the 16^3 leaf level's stencil (L = 4) sums each zone column in
+// FP32 (FP32 sources and kernel values) and the column sums in FP64.
+void m2l_spectral_set_f32(M2LSpectral* f, int on);
 // Pl (+)= the level-l zone sums of Ml over `offs` (noff per class: 8 classes
 // at levels >= 3, one at level 2); m64 / p64: the buffers hold doubles.
 // Parts for a timer: 0 the node transforms, 1 the stencil, 2 the inverse.

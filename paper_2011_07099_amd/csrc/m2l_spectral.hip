@@ -37,6 +37,8 @@ struct M2LSpectral {
   double2* out = nullptr;        // [F][nodes]
   std::vector<double2*> khat;    // per level: [343][F], offsets of [-3, 3]^3
   std::vector<double2*> khatT;   // per level: [F][kKT], the same values frequency by frequency
+  float2* khatT32 = nullptr;     // the leaf level's khatT in FP32 (the FP32 16^3 stencil)
+  int f32 = 0;                   // the 16^3 level's stencil in FP32 with FP64 column totals
   double2* dft[2] = {nullptr, nullptr};  // [343][F] DFT passes of the kernels
 };
 
@@ -291,6 +293,26 @@ __device__ __forceinline__ void cmac(double& re, double& im, double2 k, double2 
   im = fma(k.x, s.y, im);
   im = fma(k.y, s.x, im);
 }
+__device__ __forceinline__ void cmac(float& re, float& im, float2 k, float2 s) {
+  re = fmaf(k.x, s.x, re);
+  re = fmaf(-k.y, s.y, re);
+  im = fmaf(k.x, s.y, im);
+  im = fmaf(k.y, s.x, im);
+}
+
+// A wave-uniform FP32 value copied into a vector register, so that the
+// multiply-adds that use it take the two-operand form with all operands in
+// vector registers, which gfx950 issues at twice the rate of the forms with
+// a scalar operand or a negation modifier.
+__device__ __forceinline__ float vreg(float x) {
+  float r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+
+template <class T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
 
 // out_t(k) = sum_{d in zone(class of t)} khat_d(k) spec_{t+d}(k) for one
 // frequency k and one tile of T^3 targets; T = 8, or T = n = 4 on the 4^3
@@ -489,16 +511,22 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
 // next to the target (|dx|, |dz| <= 1) skip the three dy of the near zone.
 // Blocks are dealt to the 8 XCDs so that the 8 frequencies of a chunk, which
 // share every 128-byte line of the spectra, run on one XCD back to back.
-template <int H, int TY>
-__global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
-    const double2* __restrict__ spec, const double2* __restrict__ khatT, int64_t F, int nchunk,
-    double2* __restrict__ out) {
+//
+// T = float: the sources and kernel values in FP32 (the transforms and the
+// level's spectra stay FP64), the terms of each (dx, dz) column summed in
+// FP32 and the 36 column sums of a target added in FP64.
+template <int H, int TY, class T = double>
+__global__ void __launch_bounds__(8 * (H * H * H / TY), sizeof(T) == 4 ? 4 : 8) k_zone_level_y(
+    const double2* __restrict__ spec, const typename Vec2<T>::type* __restrict__ khatT, int64_t F,
+    int nchunk, double2* __restrict__ out) {
+  using T2 = typename Vec2<T>::type;
+  constexpr bool kSplit = sizeof(T) == 4;  // FP32 column sums into FP64 totals
   constexpr int n = 2 * H, nn = n * n * n, H3 = H * H * H;
   constexpr int LPC = H3 / TY;   // lanes per class
   constexpr int NT = 8 * LPC;
   static_assert(LPC % 64 == 0, "a class fills whole waves");
   static_assert(H % TY == 0, "whole target runs");
-  __shared__ double2 box[nn];
+  __shared__ T2 box[nn];
   const int g = blockIdx.x;
   const int chunk = ((g >> 3) >> 3) * 8 + (g & 7);
   if (chunk >= nchunk) return;
@@ -511,17 +539,22 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
   for (int i = threadIdx.x; i < nn; i += NT) {
     const int hz = i % H, hx = (i / (H * H)) % H, hy = ((i / H) % H) ^ (hx & 1), p = i / H3;
     const int x = 2 * hx + (p >> 2), y = 2 * hy + ((p >> 1) & 1), z = 2 * hz + (p & 1);
-    box[i] = sk[(int64_t)((x * n + y) * n + z) * 8];
+    const double2 v = sk[(int64_t)((x * n + y) * n + z) * 8];
+    box[i] = T2{(T)v.x, (T)v.y};
   }
   __syncthreads();
   const int cls = __builtin_amdgcn_readfirstlane(threadIdx.x / LPC);
   const int cx = cls >> 2, cy = (cls >> 1) & 1, cz = cls & 1;
   const int lane = threadIdx.x % LPC;
   const int hz = lane % H, hx = (lane / H) % H, hy0 = (lane / (H * H)) * TY;
-  const double2* kf = khatT + (int64_t)k * kKT;
+  const T2* kf = khatT + (int64_t)k * kKT;
   double re[TY], im[TY];
+  T cr[TY], ci[TY];  // the current column's sums (FP32 with kSplit)
 #pragma unroll
-  for (int t = 0; t < TY; ++t) re[t] = im[t] = 0.0;
+  for (int t = 0; t < TY; ++t) {
+    re[t] = im[t] = 0.0;
+    cr[t] = ci[t] = (T)0;
+  }
   int fl = 0;  // 1 when the current source column's hx' is odd
   // one parity plane (py) of a column: rows hy0 - 1 + j (j < TY + 2) of the
   // column's (px, pz, hx', hz'); target t reads j = t + m with the kernel of
@@ -532,7 +565,7 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
     const int pl = col + py * 2 * H3;
     const int pe = pl + fl * H;   // even hy: +H on odd hx'
     const int po = pl - fl * H;   // odd hy: -H on odd hx'
-    double2 src[TY + 2];
+    T2 src[TY + 2];
 #pragma unroll
     for (int j = 0; j < TY + 2; ++j) {
       const int hy = (hy0 - 1 + j) & (H - 1);
@@ -541,9 +574,32 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if ((m == 0 && !m0) || (m == 1 && !m1) || (m == 2 && !m2)) continue;
-      const double2 kd = kf[kbase + 7 * (2 * m - 2 + py - cy + 3)];
+      const T2 kd = kf[kbase + 7 * (2 * m - 2 + py - cy + 3)];
+      if constexpr (kSplit) {
+        // k s = (kx sx - ky sy, kx sy + ky sx) with -ky kept as its own value
+        const float kx = vreg(kd.x), ky = vreg(kd.y), nky = vreg(-kd.y);
 #pragma unroll
-      for (int t = 0; t < TY; ++t) cmac(re[t], im[t], kd, src[t + m]);
+        for (int t = 0; t < TY; ++t) {
+          cr[t] = fmaf(kx, src[t + m].x, cr[t]);
+          cr[t] = fmaf(nky, src[t + m].y, cr[t]);
+          ci[t] = fmaf(kx, src[t + m].y, ci[t]);
+          ci[t] = fmaf(ky, src[t + m].x, ci[t]);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < TY; ++t) cmac(re[t], im[t], kd, src[t + m]);
+      }
+    }
+  };
+  // with kSplit, a finished column's sums go into the FP64 totals
+  auto flush = [&]() {
+    if constexpr (kSplit) {
+#pragma unroll
+      for (int t = 0; t < TY; ++t) {
+        re[t] += (double)cr[t];
+        im[t] += (double)ci[t];
+        cr[t] = ci[t] = (T)0;
+      }
     }
   };
   for (int sx = -2; sx <= 3; ++sx) {      // source x = 2 hx + cx + dx, sx = cx + dx
@@ -565,6 +621,7 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), 8) k_zone_level_y(
         plane(col, kbase, 0, true, false, false);
         plane(col, kbase, 1, true, false, true);
       }
+      flush();
     }
   }
   double2* o = out + (int64_t)(k >> 3) * nn * 8 + (k & 7);
@@ -709,6 +766,12 @@ __global__ void __launch_bounds__(512) k_zone_l2(const double2* __restrict__ spe
   out[(int64_t)chunk * 64 * 8 + t * 8 + f] = make_double2(re, im);
 }
 
+// khatT in FP32.
+__global__ void k_khat_f32(const double2* __restrict__ in, int64_t n, float2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
 // khatT[f][d] = khat[d][f] (d < 343; the pad entry is zero).
 __global__ void k_khat_transpose(const double2* __restrict__ khat, int64_t F,
                                  double2* __restrict__ khatT) {
@@ -808,7 +871,9 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
   const int64_t per_tile = (f->F / 8 + 7) / 8 * 64;
   const int nchunk = (int)(f->F / 8);
   const unsigned cgrid = (unsigned)((nchunk + 7) / 8 * 64);  // chunks rounded up to 8, times 8
-  if (n == 16 && !isolated) {  // the whole level per frequency, four targets per lane
+  if (n == 16 && !isolated && f->f32 && l == f->L && f->khatT32) {  // FP32 columns
+    k_zone_level_y<8, 8, float><<<cgrid, 512, 0, st>>>(f->spec, f->khatT32, f->F, nchunk, f->out);
+  } else if (n == 16 && !isolated) {  // the whole level per frequency, eight targets per lane
     k_zone_level_y<8, 8><<<cgrid, 512, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
   } else if (n == 8 && !isolated) {
     k_zone_level_z<4, 1><<<cgrid, 512, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
@@ -844,6 +909,7 @@ void m2l_spectral_destroy(M2LSpectral* f) {
   (void)hipFree(f->out);
   for (double2* k : f->khat) (void)hipFree(k);
   for (double2* k : f->khatT) (void)hipFree(k);
+  (void)hipFree(f->khatT32);
   for (double2* d : f->dft) (void)hipFree(d);
   delete f;
 }
@@ -865,6 +931,7 @@ hipError_t m2l_spectral_create(int L, int p, M2LSpectral** out) {
     e = hipMalloc(&f->khat[l], (size_t)(343 * f->F) * sizeof(double2));
   for (int l = 2; l <= L && e == hipSuccess; ++l)
     e = hipMalloc(&f->khatT[l], (size_t)(kKT * f->F) * sizeof(double2));
+  if (e == hipSuccess && L == 4) e = hipMalloc(&f->khatT32, (size_t)(kKT * f->F) * sizeof(float2));
   if (e != hipSuccess) {
     m2l_spectral_destroy(f);
     return e;
@@ -872,6 +939,8 @@ hipError_t m2l_spectral_create(int L, int p, M2LSpectral** out) {
   *out = f;
   return hipSuccess;
 }
+
+void m2l_spectral_set_f32(M2LSpectral* f, int on) { f->f32 = on; }
 
 hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64, hipStream_t st) {
   const int p = f->p, C = 4 * p - 1;
@@ -884,6 +953,8 @@ hipError_t m2l_spectral_tables(M2LSpectral* f, const std::vector<double*>& tab64
     k_sdft_axis<<<grid, kThreads, 0, st>>>(f->dft[1], p, 0, f->dft[0]);
     k_sdft_store<<<grid, kThreads, 0, st>>>(f->dft[0], p, scale, f->khat[l]);
     k_khat_transpose<<<nblk(f->F * kKT), kThreads, 0, st>>>(f->khat[l], f->F, f->khatT[l]);
+    if (l == f->L && f->khatT32)
+      k_khat_f32<<<nblk(f->F * kKT), kThreads, 0, st>>>(f->khatT[l], f->F * kKT, f->khatT32);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -69,6 +69,7 @@ struct pfmm_plan_s {
   M2LSpectral* mspec = nullptr;   // its spectra and transformed kernels
   int near_fft = 0;               // leaf near zone by FFT convolution (PFMM_OPT_NEAR)
   int fold = 0;                   // P2M and L2P inside its leaf transforms (PFMM_OPT_FOLD)
+  int zones_f32 = 0;              // FP32 columns in the 16^3 spectral stencil (PFMM_OPT_ZONES_FP32)
   NearFft* nfft = nullptr;        // its plans, buffers and transformed kernels
   uint16_t* zero = nullptr;       // 512 zero bf16 values: the source outside an isolated box
   // accelerations from the expansion (PFMM_OPT_ACCEL; tables on first use)
@@ -768,6 +769,15 @@ pfmm_status pfmm_plan_set(pfmm_plan_t h, int option, const void* value, size_t b
       pl->prec = v;
       return PFMM_OK;
     }
+    case PFMM_OPT_ZONES_FP32: {
+      if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "zones_fp32 is an int32");
+      int32_t v;
+      std::memcpy(&v, value, sizeof v);
+      if (v != 0 && v != 1) return fail(PFMM_ERR_INVALID_ARG, "zones_fp32 is 0 or 1");
+      pl->zones_f32 = v;
+      if (pl->mspec) m2l_spectral_set_f32(pl->mspec, v);
+      return PFMM_OK;
+    }
     case PFMM_OPT_FOLD: {
       if (bytes != sizeof(int32_t)) return fail(PFMM_ERR_INVALID_ARG, "fold is an int32");
       int32_t v;
@@ -863,6 +873,7 @@ pfmm_status pfmm_plan_set(pfmm_plan_t h, int option, const void* value, size_t b
           hipError_t e = m2l_spectral_create(pl->L, pl->p, &f);
           if (e == hipErrorOutOfMemory) return fail(PFMM_ERR_OUT_OF_MEMORY, "spectral zone buffers");
           if (e != hipSuccess) return hip_fail(e, "spectral zone buffers");
+          m2l_spectral_set_f32(f, pl->zones_f32);
           pl->mspec = f;
           e = m2l_spectral_tables(pl->mspec, pl->tab64, pl->stream);
           if (e != hipSuccess) return hip_fail(e, "spectral zone kernels");

@@ -16,7 +16,8 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_CAPTURE, E
 GREEN = {"X": 0, "K": 1, "S1": 2, "S": 3, "E": 4, "LEARNED": 5}
 PREC = {"fp32": 0, "bf16x3": 1, "fp64": 2}
 OPT_PRECISION, OPT_STREAM, OPT_GS_A1, OPT_PROFILE, OPT_FP64_LEVELS, OPT_ISOLATED, OPT_GS_A2, \
-    OPT_ACCEL, OPT_EWALD_RS, OPT_M2L, OPT_NEAR, OPT_LEARNED_WEIGHTS, OPT_FOLD = range(1, 14)
+    OPT_ACCEL, OPT_EWALD_RS, OPT_M2L, OPT_NEAR, OPT_LEARNED_WEIGHTS, OPT_FOLD, \
+    OPT_ZONES_FP32 = range(1, 15)
 M2L = {"gemm": 0, "fft": 1, "spectral": 2}
 NEAR = {"direct": 0, "fft": 1}
 ACCEL = {"fd4": 0, "expansion": 1}
@@ -127,7 +128,7 @@ class Plan:
 
     def __init__(self, N, L, p, green="S1", precision="fp32", a1=None, stream=None,
                  fp64_levels=None, isolated=False, a2=None, accel="fd4", rs=None, m2l="gemm",
-                 near="direct", fold=False):
+                 near="direct", fold=False, zones_fp32=False):
         import torch
         lib = load()
         h = ctypes.c_void_p()
@@ -160,6 +161,14 @@ class Plan:
             self.set_near(near)
         if fold:
             self.set_fold(True)
+        if zones_fp32:
+            self.set_zones_fp32(True)
+
+    def set_zones_fp32(self, on):
+        """Spectral zones of a 16^3 leaf level (L = 4) summed in FP32 columns
+        with FP64 totals; see PFMM_OPT_ZONES_FP32."""
+        v = ctypes.c_int32(1 if on else 0)
+        _check(load().pfmm_plan_set(self._h, OPT_ZONES_FP32, ctypes.byref(v), 4))
 
     def set_fold(self, on):
         """P2M and L2P inside the FFT near zone's leaf transforms (leaf edge 8

@@ -10,7 +10,7 @@ def f32(rho):
 
 def solve(rho, L, p, green, accel=False, precision="fp32", a1=None, stages=False,
           fp64_levels=None, isolated=False, accel_mode="fd4", a2=None, near="direct",
-          m2l="gemm", fold=False):
+          m2l="gemm", fold=False, zones_fp32=False):
     import torch
     from paper_2011_07099_amd.pfmm import Plan
     N = rho.shape[0]
@@ -19,7 +19,8 @@ def solve(rho, L, p, green, accel=False, precision="fp32", a1=None, stages=False
     acc = torch.empty((3, N, N, N), dtype=torch.float32, device="cuda") if accel else None
     out = {}
     with Plan(N, L, p, green, precision=precision, a1=a1, fp64_levels=fp64_levels,
-              isolated=isolated, accel=accel_mode, a2=a2, near=near, m2l=m2l, fold=fold) as pl:
+              isolated=isolated, accel=accel_mode, a2=a2, near=near, m2l=m2l, fold=fold,
+              zones_fp32=zones_fp32) as pl:
         pl.solve(r, phi, acc)
         if stages:
             n = lambda l: 2 ** l

@@ -25,7 +25,11 @@ the split path's tolerances.  With the interaction zones as FP64 spectral
 stencils (the benchmark's default) every level's zones are FP64 whatever the
 level's storage, and the error left is FP32 storage and the near zone's,
 measured 2.5e-6: tolerance 1e-5, also with P2M and L2P folded into the
-near zone's leaf transforms (PFMM_OPT_FOLD).
+near zone's leaf transforms (PFMM_OPT_FOLD).  With the leaf level's zones
+summed in FP32 columns (PFMM_OPT_ZONES_FP32, the benchmark's setting) the
+sources and kernel values carry 2^-24 each over 189 offsets, a few 1e-7 of
+the leaf locals, which L2P's extrapolation to the leaf corners amplifies as
+above: measured 1.4e-5 from the FP64-zone potential; tolerance 5e-5.
 """
 import numpy as np
 import pytest
@@ -50,10 +54,11 @@ def _targets():
 
 # (precision, FP64 levels, near zone) -> sampled-cell tolerance against the
 # FP64 reference FMM
-CASES = {("fp32", 2, "direct", "gemm", 0): 2e-4, ("bf16x3", 2, "direct", "gemm", 0): 1e-4,
-         ("fp32", 3, "direct", "gemm", 0): 1e-6, ("bf16x3", 3, "direct", "gemm", 0): 1e-5,
-         ("bf16x3", 2, "fft", "gemm", 0): 1e-4, ("bf16x3", 3, "fft", "gemm", 0): 1e-5,
-         ("bf16x3", 2, "fft", "spectral", 0): 1e-5, ("bf16x3", 2, "fft", "spectral", 1): 1e-5}
+CASES = {("fp32", 2, "direct", "gemm", 0, 0): 2e-4, ("bf16x3", 2, "direct", "gemm", 0, 0): 1e-4,
+         ("fp32", 3, "direct", "gemm", 0, 0): 1e-6, ("bf16x3", 3, "direct", "gemm", 0, 0): 1e-5,
+         ("bf16x3", 2, "fft", "gemm", 0, 0): 1e-4, ("bf16x3", 3, "fft", "gemm", 0, 0): 1e-5,
+         ("bf16x3", 2, "fft", "spectral", 0, 0): 1e-5, ("bf16x3", 2, "fft", "spectral", 1, 0): 1e-5,
+         ("bf16x3", 2, "fft", "spectral", 0, 1): 5e-5}
 
 
 @pytest.fixture(scope="module")
@@ -68,11 +73,11 @@ def reference(rho):
 
 
 @pytest.fixture(scope="module", params=sorted(CASES),
-                ids=lambda c: "%s-fp64levels%d-near-%s-m2l-%s-fold%d" % c)
+                ids=lambda c: "%s-fp64levels%d-near-%s-m2l-%s-fold%d-zonesfp32%d" % c)
 def headline(request, rho):
-    prec, f64, near, m2l, fold = request.param
+    prec, f64, near, m2l, fold, zf = request.param
     return request.param, solve(rho, L, P, "S1", precision=prec, fp64_levels=f64, near=near,
-                                m2l=m2l, fold=bool(fold))["phi"]
+                                m2l=m2l, fold=bool(fold), zones_fp32=bool(zf))["phi"]
 
 
 def test_headline_sampled_vs_reference_fmm(headline, reference):

@@ -7,8 +7,13 @@ ABI, against the oracle's step-by-step FMM and the block-Toeplitz GEMM path.
   The FP32 levels' rounding sets the tolerance, 2e-5, as for the other M2L
   routes.  With every level kept in FP64 the spectral and GEMM locals differ
   by FP64 rounding only: their FP32 read-backs agree to 2e-7 of max.
-* The split-precision plan with spectral zones at the 256^3 headline size is
-  covered by the headline parity test.
+* PFMM_OPT_ZONES_FP32 (the 16^3 leaf level's zones summed in FP32 columns
+  with FP64 totals) at 128^3, L = 4, p = 4 and 6, under the same FP32
+  tolerance: the FP32 roundings of the sources and kernel values
+  (2^-24 each) over 189 offsets leave a few 1e-7 of the locals.
+* The split-precision plan with spectral zones at the 256^3 headline size,
+  with FP64 and with FP32 leaf columns, is covered by the headline parity
+  test.
 * Both transform routes together (FFT near zone and spectral zones) with
   accelerations from the expansion, periodic and isolated, against the
   oracle's fmm_accel (measured 1-6e-7; tolerance 2e-5).
@@ -26,7 +31,8 @@ from gpu_util import f32, rel_max
 pytestmark = pytest.mark.gpu
 
 
-def _solve_stages(rho, L, p, green, m2l, fp64_levels=None, isolated=False, precision="fp32"):
+def _solve_stages(rho, L, p, green, m2l, fp64_levels=None, isolated=False, precision="fp32",
+                  zones_fp32=False):
     import torch
     from paper_2011_07099_amd.pfmm import Plan
     N = rho.shape[0]
@@ -34,7 +40,7 @@ def _solve_stages(rho, L, p, green, m2l, fp64_levels=None, isolated=False, preci
     phi = torch.empty_like(r)
     n = lambda l: 2 ** l
     with Plan(N, L, p, green, fp64_levels=fp64_levels, isolated=isolated, m2l=m2l,
-              precision=precision) as pl:
+              precision=precision, zones_fp32=zones_fp32) as pl:
         pl.solve(r, phi)
         Phi = {l: pl.locals(l).cpu().numpy().astype(np.float64).reshape((n(l),) * 3 + (p,) * 3)
                for l in range(2, L + 1)}
@@ -42,20 +48,22 @@ def _solve_stages(rho, L, p, green, m2l, fp64_levels=None, isolated=False, preci
     return phi.cpu().numpy().astype(np.float64), Phi
 
 
-@pytest.mark.parametrize("N,L,p,green,f64,iso,prec", [
-    (32, 3, 4, "S1", 0, False, "fp32"),       # every level in FP32
-    (64, 3, 8, "S1", None, False, "fp32"),    # default FP64 levels 2-3
-    (64, 3, 8, "S1", None, False, "bf16x3"),  # split near zone beside spectral zones
-    (128, 4, 4, "K", None, False, "fp32"),
-    (64, 2, 8, "S1", None, False, "fp32"),    # the smallest periodic tree
-    (32, 3, 4, "X", None, True, "fp32"),      # isolated twin (316-offset level 2)
-    (64, 3, 8, "X", None, True, "fp32"),
-    (64, 3, 6, "S1", None, False, "fp32"),    # p = 6: 12-point transforms, 1008 frequencies
-    (128, 4, 6, "X", None, True, "fp32"),     # p = 6 isolated, a 16^3 leaf level
+@pytest.mark.parametrize("N,L,p,green,f64,iso,prec,zf", [
+    (32, 3, 4, "S1", 0, False, "fp32", False),       # every level in FP32
+    (64, 3, 8, "S1", None, False, "fp32", False),    # default FP64 levels 2-3
+    (64, 3, 8, "S1", None, False, "bf16x3", False),  # split near zone beside spectral zones
+    (128, 4, 4, "K", None, False, "fp32", False),
+    (128, 4, 4, "K", None, False, "fp32", True),     # the 16^3 leaf level in FP32 columns
+    (128, 4, 6, "S1", None, False, "fp32", True),    # the same at p = 6
+    (64, 2, 8, "S1", None, False, "fp32", False),    # the smallest periodic tree
+    (32, 3, 4, "X", None, True, "fp32", False),      # isolated twin (316-offset level 2)
+    (64, 3, 8, "X", None, True, "fp32", False),
+    (64, 3, 6, "S1", None, False, "fp32", False),    # p = 6: 12-point transforms, 1008 frequencies
+    (128, 4, 6, "X", None, True, "fp32", False),     # p = 6 isolated, a 16^3 leaf level
 ])
-def test_spectral_zones_match_reference_and_gemm(N, L, p, green, f64, iso, prec):
+def test_spectral_zones_match_reference_and_gemm(N, L, p, green, f64, iso, prec, zf):
     rho = f32(fields.lognormal(N, 2.0, 1.0, seed=281 + N + p))
-    phi, Phi = _solve_stages(rho, L, p, green, "spectral", f64, iso, prec)
+    phi, Phi = _solve_stages(rho, L, p, green, "spectral", f64, iso, prec, zf)
     ref, st = ofmm.fmm(rho, L, p, green, stages=True, periodic=not iso)
     for l in range(2, L + 1):
         e = rel_max(Phi[l], st["Phi"][l])
@@ -64,7 +72,7 @@ def test_spectral_zones_match_reference_and_gemm(N, L, p, green, f64, iso, prec)
     e = rel_max(phi, ref)
     g, _ = _solve_stages(rho, L, p, green, "gemm", f64, iso, prec)
     eg = rel_max(phi, g)
-    print("spectral zones", (N, L, p, green, iso, prec),
+    print("spectral zones", (N, L, p, green, iso, prec, "FP32 leaf columns" if zf else "FP64"),
           "potential vs reference %.3e, vs GEMM path %.3e" % (e, eg))
     tol = 2e-5 if prec == "fp32" else 1e-4
     assert e < tol and eg < tol
