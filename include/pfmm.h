@@ -200,14 +200,15 @@ typedef enum {
    * everything on one stream.  Default 0. */
   PFMM_OPT_FOLD = 13,
   /* value: int32 0 or 1.  1 sums the spectral interaction zones (PFMM_M2L_SPECTRAL,
-   * Eq. 6 per frequency) of a 16^3 leaf level (L = 4) in FP32: the sources
-   * and kernel values rounded to FP32, each of a target's 36 zone columns
-   * (six or three offsets along a line, both parities) summed in FP32 and the
-   * column sums added in FP64; the transforms stay FP64.  Every other level
-   * and tree keeps FP64 stencils.  At 256^3, p = 8 the stencil takes 0.235
-   * instead of 0.326 ms and the potential moves by up to 1.4e-5 of
-   * max|phi| (at leaf corners, where L2P extrapolates), relative L2 against
-   * PM with the same G 1.3e-6 instead of 1.0e-6.  Default 0. */
+   * Eq. 6 per frequency) of a 16^3 leaf level (L = 4) in FP32: the level's
+   * spectra stored in FP32 (the node transforms compute in FP64), each of a
+   * target's 36 zone columns (six or three offsets along a line, both
+   * parities) summed in FP32 and the column sums added in FP64.  Every
+   * other level and tree keeps FP64 stencils.  At 256^3, p = 8 the level's
+   * transforms and stencil take 0.29 instead of 0.40 ms and the potential
+   * moves by up to 1.5e-5 of max|phi| (at leaf corners, where L2P
+   * extrapolates), relative L2 against PM with the same G 1.3e-6 instead of
+   * 1.0e-6.  Default 0. */
   PFMM_OPT_ZONES_FP32 = 14
 } pfmm_option;
 

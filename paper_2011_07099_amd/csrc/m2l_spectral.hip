@@ -166,9 +166,20 @@ __device__ __forceinline__ bool zone_block(int g, int tiles, int nchunk, int& k,
 // Forward transform of one node's p^3 gridlet (on the 2p cyclic grid, zero
 // beyond p) to its half spectrum; frequency order
 // ((kx * 2 + ky % 2) * p + ky / 2) * (p + 1) + kz.
-template <int P, class TIN>
+// Spectra are stored as TS: double2, or float2 for the 16^3 leaf level
+// summed in FP32 columns (half the bytes; its stencil rounds them to FP32
+// anyway).
+__device__ __forceinline__ double2 as_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 as_d2(float2 v) { return make_double2(v.x, v.y); }
+template <class TS> __device__ __forceinline__ TS from_d2(double2 v);
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) {
+  return make_float2((float)v.x, (float)v.y);
+}
+
+template <int P, class TIN, class TS = double2>
 __global__ void __launch_bounds__(node_threads<P>()) k_node_fwd(const TIN* __restrict__ Ml, int64_t nn,
-                                                                double2* __restrict__ spec) {
+                                                                TS* __restrict__ spec) {
   constexpr int M = 2 * P, H = P + 1, NT = node_threads<P>();
   __shared__ double2 A1[P * P * H];
   __shared__ double2 A2[P * P * H];
@@ -219,8 +230,8 @@ __global__ void __launch_bounds__(node_threads<P>()) k_node_fwd(const TIN* __res
       ddft<P, false>(o);
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        spec[sidx((4 * j + h) * P * H + r, node, nn)] = e[j];
-        spec[sidx((4 * j + 2 + h) * P * H + r, node, nn)] = o[j];
+        spec[sidx((4 * j + h) * P * H + r, node, nn)] = from_d2<TS>(e[j]);
+        spec[sidx((4 * j + 2 + h) * P * H + r, node, nn)] = from_d2<TS>(o[j]);
       }
     }
     __syncthreads();
@@ -229,8 +240,8 @@ __global__ void __launch_bounds__(node_threads<P>()) k_node_fwd(const TIN* __res
 
 // Inverse of k_node_fwd at the p^3 gridlet points, added to (or written into)
 // the node's potentials; unnormalised (the kernel spectra carry 1 / (2p)^3).
-template <int P, class TOUT>
-__global__ void __launch_bounds__(node_threads<P>()) k_node_inv(const double2* __restrict__ spec,
+template <int P, class TOUT, class TS = double2>
+__global__ void __launch_bounds__(node_threads<P>()) k_node_inv(const TS* __restrict__ spec,
                                                                 int64_t nn, int accumulate,
                                                                 TOUT* __restrict__ Pl) {
   constexpr int M = 2 * P, H = P + 1, NT = node_threads<P>();
@@ -244,8 +255,8 @@ __global__ void __launch_bounds__(node_threads<P>()) k_node_inv(const double2* _
       double2 e[P], o[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        e[j] = spec[sidx((4 * j + h) * P * H + r, node, nn)];
-        o[j] = spec[sidx((4 * j + 2 + h) * P * H + r, node, nn)];
+        e[j] = as_d2(spec[sidx((4 * j + h) * P * H + r, node, nn)]);
+        o[j] = as_d2(spec[sidx((4 * j + 2 + h) * P * H + r, node, nn)]);
       }
       ddft<P, true>(e);
       ddft<P, true>(o);
@@ -515,10 +526,10 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
 // T = float: the sources and kernel values in FP32 (the transforms and the
 // level's spectra stay FP64), the terms of each (dx, dz) column summed in
 // FP32 and the 36 column sums of a target added in FP64.
-template <int H, int TY, class T = double>
+template <int H, int TY, class T = double, class TS = double2>
 __global__ void __launch_bounds__(8 * (H * H * H / TY), sizeof(T) == 4 ? 4 : 8) k_zone_level_y(
-    const double2* __restrict__ spec, const typename Vec2<T>::type* __restrict__ khatT, int64_t F,
-    int nchunk, double2* __restrict__ out) {
+    const TS* __restrict__ spec, const typename Vec2<T>::type* __restrict__ khatT, int64_t F,
+    int nchunk, TS* __restrict__ out) {
   using T2 = typename Vec2<T>::type;
   constexpr bool kSplit = sizeof(T) == 4;  // FP32 column sums into FP64 totals
   constexpr int n = 2 * H, nn = n * n * n, H3 = H * H * H;
@@ -531,7 +542,7 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), sizeof(T) == 4 ? 4 : 8) 
   const int chunk = ((g >> 3) >> 3) * 8 + (g & 7);
   if (chunk >= nchunk) return;
   const int k = chunk * 8 + ((g >> 3) & 7);
-  const double2* sk = spec + (int64_t)(k >> 3) * nn * 8 + (k & 7);  // node v at sk[8 v]
+  const TS* sk = spec + (int64_t)(k >> 3) * nn * 8 + (k & 7);  // node v at sk[8 v]
   // stage: LDS slot i = ((p * H + hx) * H + (hy ^ (hx & 1))) * H + hz,
   // consecutive threads writing consecutive slots.  Flipping the low bit of
   // hy on odd hx puts the two hx of a 16-lane group on different halves of
@@ -539,7 +550,7 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), sizeof(T) == 4 ? 4 : 8) 
   for (int i = threadIdx.x; i < nn; i += NT) {
     const int hz = i % H, hx = (i / (H * H)) % H, hy = ((i / H) % H) ^ (hx & 1), p = i / H3;
     const int x = 2 * hx + (p >> 2), y = 2 * hy + ((p >> 1) & 1), z = 2 * hz + (p & 1);
-    const double2 v = sk[(int64_t)((x * n + y) * n + z) * 8];
+    const TS v = sk[(int64_t)((x * n + y) * n + z) * 8];
     box[i] = T2{(T)v.x, (T)v.y};
   }
   __syncthreads();
@@ -624,12 +635,12 @@ __global__ void __launch_bounds__(8 * (H * H * H / TY), sizeof(T) == 4 ? 4 : 8) 
       flush();
     }
   }
-  double2* o = out + (int64_t)(k >> 3) * nn * 8 + (k & 7);
+  TS* o = out + (int64_t)(k >> 3) * nn * 8 + (k & 7);
 #pragma unroll
   for (int t = 0; t < TY; ++t) {
     const int y = 2 * (hy0 + t) + cy;
     const int v = ((2 * hx + cx) * n + y) * n + (2 * hz + cz);
-    o[(int64_t)v * 8] = make_double2(re[t], im[t]);
+    o[(int64_t)v * 8] = from_d2<TS>(make_double2(re[t], im[t]));
   }
 }
 
@@ -857,9 +868,17 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
   const int n = 1 << l;
   const int64_t nn = (int64_t)n * n * n;
   constexpr int NT = node_threads<P>();
+  // the 16^3 leaf level in FP32 columns: its spectra stored as float2
+  const bool f32 = n == 16 && !isolated && f->f32 && l == f->L && f->khatT32;
+  float2* spec32 = reinterpret_cast<float2*>(f->spec);
+  float2* out32 = reinterpret_cast<float2*>(f->out);
   hipError_t e = tbegin(kt, st);
   if (e != hipSuccess) return e;
-  if (m64)
+  if (m64 && f32)
+    k_node_fwd<P, double, float2><<<(unsigned)nn, NT, 0, st>>>((const double*)Ml, nn, spec32);
+  else if (f32)
+    k_node_fwd<P, float, float2><<<(unsigned)nn, NT, 0, st>>>((const float*)Ml, nn, spec32);
+  else if (m64)
     k_node_fwd<P, double><<<(unsigned)nn, NT, 0, st>>>((const double*)Ml, nn, f->spec);
   else
     k_node_fwd<P, float><<<(unsigned)nn, NT, 0, st>>>((const float*)Ml, nn, f->spec);
@@ -871,8 +890,8 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
   const int64_t per_tile = (f->F / 8 + 7) / 8 * 64;
   const int nchunk = (int)(f->F / 8);
   const unsigned cgrid = (unsigned)((nchunk + 7) / 8 * 64);  // chunks rounded up to 8, times 8
-  if (n == 16 && !isolated && f->f32 && l == f->L && f->khatT32) {  // FP32 columns
-    k_zone_level_y<8, 8, float><<<cgrid, 512, 0, st>>>(f->spec, f->khatT32, f->F, nchunk, f->out);
+  if (f32) {  // FP32 columns
+    k_zone_level_y<8, 8, float, float2><<<cgrid, 512, 0, st>>>(spec32, f->khatT32, f->F, nchunk, out32);
   } else if (n == 16 && !isolated) {  // the whole level per frequency, eight targets per lane
     k_zone_level_y<8, 8><<<cgrid, 512, 0, st>>>(f->spec, f->khatT[l], f->F, nchunk, f->out);
   } else if (n == 8 && !isolated) {
@@ -894,7 +913,11 @@ hipError_t run_level(M2LSpectral* f, int l, const void* Ml, int m64, void* Pl, i
   e = tend(kt, st, 1, hipGetLastError());
   if (e == hipSuccess) e = tbegin(kt, st);
   if (e != hipSuccess) return e;
-  if (p64)
+  if (p64 && f32)
+    k_node_inv<P, double, float2><<<(unsigned)nn, NT, 0, st>>>(out32, nn, accumulate, (double*)Pl);
+  else if (f32)
+    k_node_inv<P, float, float2><<<(unsigned)nn, NT, 0, st>>>(out32, nn, accumulate, (float*)Pl);
+  else if (p64)
     k_node_inv<P, double><<<(unsigned)nn, NT, 0, st>>>(f->out, nn, accumulate, (double*)Pl);
   else
     k_node_inv<P, float><<<(unsigned)nn, NT, 0, st>>>(f->out, nn, accumulate, (float*)Pl);
