@@ -50,30 +50,26 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}
 PEAK_UNIT = {"bf16 mfma": 2516.6, "f64 mfma": 78.6, "f32 valu": 157.3, "f64 valu": 78.6}
 FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default at L = 4)
 
-# HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# (KiB per dispatch, the mean over the profiled run's launches), scaled by a
-# plain 1 GiB copy (read x2.0, write x1.0), keyed by the kernel's name in the
-# bench line and the SHA-1 prefix of the sources it was taken on (its file and
-# plan.hip); a changed source reports null.
-# HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE x 1, KiB scaled to bytes
-# by a plain 1 GiB copy) of the default route at 256^3, L = 4, p = 8, taken
-# with rocprofv3 --pmc on the sources whose SHA-1 prefix keys each entry; a
-# change to those sources (or another route) reports null until the counters
-# are taken again.
+# HBM bytes per launch of a kernel (rocprofv3 --pmc FETCH_SIZE x 2 + WRITE_SIZE
+# x 1, KiB per dispatch scaled to bytes by a plain 1 GiB copy) in the serial
+# solve of the bench route at 256^3, L = 4, p = 8, keyed by the kernel's name
+# in the bench line and the SHA-1 prefix of the sources it was taken on (its
+# file and plan.hip); another route or a changed source reports null until the
+# counters are taken again.
 TRAFFIC = {
-    ("near leaf transforms", "865237993b4c"): 134438052 + 570425344,
-    ("near stencil", "865237993b4c"): 840296160 + 570425344,
-    ("near inverse transforms", "865237993b4c"): 570662335 + 67108992,
-    ("p2m", "dd1c6fa857cd"): 134264877 + 8388608,
-    ("l2p", "dd1c6fa857cd"): 142635249 + 67108864,
-    ("m2l L4 node transforms", "3df04596f28c"): 8520380 + 150994944,
-    ("m2l L4 stencil", "3df04596f28c"): 176560106 + 151036800,
-    ("m2l L4 inverse transforms", "3df04596f28c"): 159527921 + 8648448,
-    ("m2l L3 stencil", "3df04596f28c"): 44314321 + 18875456,
-    ("m2l L2 stencil", "3df04596f28c"): 6827670 + 2359296,
+    ("near leaf transforms", "96a874038546"): 637905948,
+    ("near stencil", "96a874038546"): 1245835644,
+    ("near inverse transforms", "96a874038546"): 644468204,
+    ("p2m", "6c4695704e03"): 75558445,
+    ("l2p", "6c4695704e03"): 143365298,
+    ("m2l L4 node transforms", "16a17836a65b"): 84229631,
+    ("m2l L4 stencil", "16a17836a65b"): 163756054,
+    ("m2l L4 inverse transforms", "16a17836a65b"): 92448436,
+    ("m2l L3 stencil", "16a17836a65b"): 63199169,
+    ("m2l L2 stencil", "16a17836a65b"): 9186968,
 }
 TRAFFIC_ROUTE = {"precision": "bf16x3", "near": "fft", "m2l": "spectral", "accel": "none",
-                 "N": 256, "L": 4, "p": 8}
+                 "zones": "fp32", "N": 256, "L": 4, "p": 8}
 KERNEL_SRC = {"m2l": ("m2l_spectral.hip", "plan.hip"), "near": ("near_fft.hip", "plan.hip"),
               "p2m": ("updown.hip", "plan.hip"), "l2p": ("updown.hip", "plan.hip")}
 
@@ -724,7 +720,7 @@ def headline(args):
                   "events on its stream)" % (dom, dms, min(args.steps, 16)),
         "traffic": traffic_bytes(dom, {"precision": args.precision, "near": args.near,
                                             "m2l": args.m2l, "accel": args.accel,
-                                            "N": N, "L": L, "p": P}),
+                                            "zones": args.zones, "N": N, "L": L, "p": P}),
         "kernel_compulsory_bytes": kbytes,
         "solve_compulsory_bytes": 4.0 * N ** 3 * 2 + sum(
             (8.0 if lv in FP64_LEVELS else 4.0) * 2 * P ** 3 * 8 ** lv for lv in range(2, L + 1)),
