@@ -747,7 +747,7 @@ pfmm_status pfmm_plan_set(pfmm_plan_t h, int option, const void* value, size_t b
   // a live batch holds this plan's buffers, zone lists and routes in its graph
   if (pl->batch_refs > 0 &&
       (option == PFMM_OPT_PRECISION || option == PFMM_OPT_ISOLATED || option == PFMM_OPT_FP64_LEVELS ||
-       option == PFMM_OPT_M2L || option == PFMM_OPT_NEAR))
+       option == PFMM_OPT_M2L || option == PFMM_OPT_NEAR || option == PFMM_OPT_ZONES_FP32))
     return fail(PFMM_ERR_INVALID_ARG, "the plan is bound to a live batch: this option would change "
                                       "what the batch's graph uses");
   switch (option) {

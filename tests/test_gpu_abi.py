@@ -7,6 +7,8 @@ solve_batch rules, on the GPU, through the library.
   the plan's stream is being captured, and do nothing.
 * Batch binding: while a batch lives, its plans refuse pfmm_plan_destroy and
   the options that change what the batch's graph uses.
+* PFMM_OPT_FOLD and PFMM_OPT_ZONES_FP32 refuse values other than an int32 0
+  or 1, and change nothing where they do not apply.
 * PFMM_GREEN_LEARNED: without weights a solve is G_S1's bit for bit and the
   fallback is recorded in pfmm_last_error; with weights it equals a G_S1
   plan corrected by the same network.
@@ -97,7 +99,7 @@ def test_batch_binding_refuses_destroy_and_structural_options():
     b = pfmm.Batch([pl], [rho], [phi])
     assert lib.pfmm_plan_destroy(pl._h) == pfmm.ERR_INVALID_ARG
     for opt, val in ((pfmm.OPT_PRECISION, 1), (pfmm.OPT_NEAR, 1), (pfmm.OPT_M2L, 2),
-                     (pfmm.OPT_FP64_LEVELS, 1), (pfmm.OPT_ISOLATED, 0)):
+                     (pfmm.OPT_FP64_LEVELS, 1), (pfmm.OPT_ISOLATED, 0), (pfmm.OPT_ZONES_FP32, 1)):
         v = ctypes.c_int32(val)
         assert lib.pfmm_plan_set(pl._h, opt, ctypes.byref(v), 4) == pfmm.ERR_INVALID_ARG, opt
     b.solve()
@@ -108,6 +110,33 @@ def test_batch_binding_refuses_destroy_and_structural_options():
     v = ctypes.c_int32(1)
     assert lib.pfmm_plan_set(pl._h, pfmm.OPT_NEAR, ctypes.byref(v), 4) == pfmm.OK
     pl.close()
+
+
+def test_fold_and_zones_fp32_options_are_checked():
+    """PFMM_OPT_FOLD and PFMM_OPT_ZONES_FP32 take an int32 0 or 1; anything
+    else is refused and changes nothing (the solve stays bit for bit)."""
+    import torch
+    from paper_2011_07099_amd import pfmm
+    lib = _lib()
+    rho = torch.from_numpy(fields.lognormal(32, 2.0, 1.0, seed=5).astype(np.float32)).cuda()
+    with pfmm.Plan(32, 3, 4, "S1", near="fft", m2l="spectral") as pl:
+        ref = torch.empty_like(rho)
+        pl.solve(rho, ref)
+        for opt in (pfmm.OPT_FOLD, pfmm.OPT_ZONES_FP32):
+            v = ctypes.c_int32(2)
+            assert lib.pfmm_plan_set(pl._h, opt, ctypes.byref(v), 4) == pfmm.ERR_INVALID_ARG
+            w = ctypes.c_int64(1)
+            assert lib.pfmm_plan_set(pl._h, opt, ctypes.byref(w), 8) == pfmm.ERR_INVALID_ARG
+        phi = torch.empty_like(rho)
+        pl.solve(rho, phi)
+        torch.cuda.synchronize()
+        assert torch.equal(phi, ref)
+        # where they do not apply (s = 4 leaves, an 8^3 leaf level) they change nothing
+        pl.set_fold(True)
+        pl.set_zones_fp32(True)
+        pl.solve(rho, phi)
+        torch.cuda.synchronize()
+        assert torch.equal(phi, ref)
 
 
 def test_learned_kind_falls_back_to_gs1_and_follows_its_network():
