@@ -696,7 +696,15 @@ def headline(args):
              "fold": near_fft and stages["p2m"][1] == 0, "zones_fp32_level": L if zones32 else None}
 
     def roof(name, dms):
+        # the kernel's roofline is the larger of its two floors, flops at the
+        # unit's peak and compulsory bytes at the HBM peak; the other is
+        # reported beside it
         fl, unit, kbytes, products = kernel_work(name, N, L, P, route)
+        mem = None
+        if kbytes:
+            gbs = kbytes / (dms * 1e-3) / 1e9
+            mem = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                   "frac": gbs / 8000.0}
         if fl is not None:
             peak = PEAK_UNIT[unit]
             tf = fl * products / (dms * 1e-3) / 1e12
@@ -706,10 +714,14 @@ def headline(args):
             if products > 1:
                 r.update({"products": products, "algorithmic_flops_per_launch": fl,
                           "algorithmic_tflops": tf / products})
+            if mem is not None and mem["frac"] > r["frac"]:
+                mem["compute"] = r  # the HBM floor is the higher one
+                return mem, kbytes
+            if mem is not None:
+                r["memory"] = mem
             return r, kbytes
-        gbs = (kbytes or 0.0) / (dms * 1e-3) / 1e9
-        return {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
-                "frac": gbs / 8000.0}, kbytes
+        return (mem or {"bound": "hbm", "achieved": 0.0, "peak": 8000.0, "unit": "GB/s",
+                        "frac": 0.0}), kbytes
 
     # the dominant single kernel (longest on its own) and its roofline
     dom = max(kern, key=lambda k: kern[k][0])
