@@ -57,16 +57,16 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default at L = 4)
 # file and plan.hip); another route or a changed source reports null until the
 # counters are taken again.
 TRAFFIC = {
-    ("near leaf transforms", "96a874038546"): 637905948,
-    ("near stencil", "96a874038546"): 1245835644,
-    ("near inverse transforms", "96a874038546"): 644468204,
-    ("p2m", "6c4695704e03"): 75558445,
-    ("l2p", "6c4695704e03"): 143365298,
-    ("m2l L4 node transforms", "16a17836a65b"): 84229631,
-    ("m2l L4 stencil", "16a17836a65b"): 163756054,
-    ("m2l L4 inverse transforms", "16a17836a65b"): 92448436,
-    ("m2l L3 stencil", "16a17836a65b"): 63199169,
-    ("m2l L2 stencil", "16a17836a65b"): 9186968,
+    ("near leaf transforms", "33428628d11d"): 637957234,
+    ("near stencil", "33428628d11d"): 1247994755,
+    ("near inverse transforms", "33428628d11d"): 644026232,
+    ("p2m", "e6fe4316e767"): 75558533,
+    ("l2p", "e6fe4316e767"): 143439510,
+    ("m2l L4 node transforms", "c22bfefc6d9b"): 84127946,
+    ("m2l L4 stencil", "c22bfefc6d9b"): 163756201,
+    ("m2l L4 inverse transforms", "c22bfefc6d9b"): 92444834,
+    ("m2l L3 stencil", "c22bfefc6d9b"): 63193595,
+    ("m2l L2 stencil", "c22bfefc6d9b"): 9186977,
 }
 TRAFFIC_ROUTE = {"precision": "bf16x3", "near": "fft", "m2l": "spectral", "accel": "none",
                  "zones": "fp32", "N": 256, "L": 4, "p": 8}
