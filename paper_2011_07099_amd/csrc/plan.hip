@@ -1107,11 +1107,10 @@ pfmm_status solve_impl(pfmm_plan_s* pl, const void* rho_in, void* phi_out, void*
   // potential (FP32 leaf gridlets): the tree waits for the forward
   // transforms, the potential's inverse transform for the leaf locals
   const bool fold = pl->fold && near_fft && !io64 && !is64(L) && near_fft_folds(pl->nfft, p);
-  const bool fold_p2m = fold, fold_l2p = fold;
   LeafTree lt{};
   if (fold) {
-    lt.M = fold_p2m ? static_cast<float*>(pl->M[L]) : nullptr;
-    lt.Pl = fold_l2p ? static_cast<const float*>(pl->P[L]) : nullptr;
+    lt.M = static_cast<float*>(pl->M[L]);
+    lt.Pl = static_cast<const float*>(pl->P[L]);
     lt.A = pl->dA;
     lt.h3 = (float)h3;
     lt.p = p;
@@ -1166,7 +1165,7 @@ pfmm_status solve_impl(pfmm_plan_s* pl, const void* rho_in, void* phi_out, void*
   if (e != hipSuccess) return hip_fail(e, "near zone");
 
   // upward pass
-  if (fold_p2m) {
+  if (fold) {
     if (overlap) {
       e = hipStreamWaitEvent(st, pl->ev_mass, 0);
       if (e != hipSuccess) return hip_fail(e, "leaf masses");
@@ -1230,7 +1229,7 @@ pfmm_status solve_impl(pfmm_plan_s* pl, const void* rho_in, void* phi_out, void*
 
   // downward to the mesh, added to the near zone
   if (fold) {
-    if (overlap && fold_l2p) {
+    if (overlap) {
       e = hipEventRecord(pl->ev_local, st);
       if (e == hipSuccess) e = hipStreamWaitEvent(sn, pl->ev_local, 0);
     }
@@ -1243,7 +1242,7 @@ pfmm_status solve_impl(pfmm_plan_s* pl, const void* rho_in, void* phi_out, void*
     e = hipStreamWaitEvent(st, pl->ev_join, 0);
     if (e != hipSuccess) return hip_fail(e, "join");
   }
-  if (!fold_l2p) {
+  if (!fold) {
     e = timed(PFMM_STAGE_L2P, 0, st, [&] {
       return io64 ? launch_l2p_f64out(pl->P[L], static_cast<double*>(phi_out), A, N, s, p, st, 1)
                   : launch_l2p(pl->P[L], is64(L), phi, A, N, s, p, st, 1);
