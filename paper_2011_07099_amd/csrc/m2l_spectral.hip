@@ -508,24 +508,25 @@ __global__ void __launch_bounds__(TZ * 32) k_zone_spec2(const double2* __restric
 // 2H = 16): one workgroup per frequency holds the level's whole spectrum at that
 // frequency in LDS (n^3 values: periodic wrap, no halo) and sums every
 // target's zone.  Stored split by parity, [px][py][pz][hx][hy][hz] (node
-// coordinate 2h + p), hz fastest.  One (H = 4) or two (H = 8) waves per
+// coordinate 2h + p), hz fastest.  With H = 8 and TY = 8 one wave per
 // parity class: the class, the zone's offsets and so every kernel value are
 // uniform across a wave, and the kernel values come from the frequency's
 // contiguous row of khatT by scalar loads, leaving LDS to the sources.  The
 // 64 lanes of a wave span (hx, hz), so that one load instruction reads H
-// consecutive entries per row (no bank conflicts without a swizzle); a lane
-// owns TY targets of its class consecutive in hy (2 apart in y).  Walking
-// the zone by (dx, dz) columns, each parity plane of a column is one run of
-// TY + 2 source rows along hy shared by the TY targets (three offsets per
-// target and plane); with TY = H / 2 the run's rows are the same for the
-// whole wave, so their offsets fold into the load instructions.  Columns
+// consecutive entries per row; a lane owns TY targets of its class
+// consecutive in hy (2 apart in y).  Walking the zone by (dx, dz) columns,
+// each parity plane of a column is one run of TY + 2 source rows along hy
+// shared by the TY targets (three offsets per target and plane); with
+// TY = H the run's rows are the same for the whole wave, so their offsets
+// fold into the load instructions.  Columns
 // next to the target (|dx|, |dz| <= 1) skip the three dy of the near zone.
 // Blocks are dealt to the 8 XCDs so that the 8 frequencies of a chunk, which
 // share every 128-byte line of the spectra, run on one XCD back to back.
 //
-// T = float: the sources and kernel values in FP32 (the transforms and the
-// level's spectra stay FP64), the terms of each (dx, dz) column summed in
-// FP32 and the 36 column sums of a target added in FP64.
+// T = float: the sources and kernel values in FP32 (with TS = float2 the
+// level's spectra are stored in FP32 too; the transforms compute in FP64),
+// the terms of each (dx, dz) column summed in FP32 and the 36 column sums
+// of a target added in FP64.
 template <int H, int TY, class T = double, class TS = double2>
 __global__ void __launch_bounds__(8 * (H * H * H / TY), sizeof(T) == 4 ? 4 : 8) k_zone_level_y(
     const TS* __restrict__ spec, const typename Vec2<T>::type* __restrict__ khatT, int64_t F,
