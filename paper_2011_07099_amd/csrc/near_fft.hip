@@ -399,7 +399,9 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __r
 // of the 2s outputs, v[x] = IDFT_s(Y_even)[x] + exp(2 pi i x / 2s) IDFT_s(Y_odd)[x];
 // the z pass is the real inverse of the half spectrum,
 //   v[z] = Re Y[0] + (-1)^z Re Y[s] + 2 sum_{0 < k < s} Re(Y[k] exp(2 pi i k z / 2s)),
-// unnormalised (the kernels carry 1 / (2s)^3).  One LDS buffer of s^2 (s + 1)
+// unnormalised (the kernels carry 1 / (2s)^3), done as one complex inverse
+// DFT of length s whose real and imaginary parts are the even and odd z
+// (the Hermitian half spectrum packed into s values).  One LDS buffer of s^2 (s + 1)
 // values: per parity of ky the x pass fills it, then the thread of each
 // (x, kz) column does that column's y pass; the first parity's result waits
 // in the thread's registers, and the second parity's sum is written back over
@@ -467,16 +469,22 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
     float2 u[H];
 #pragma unroll
     for (int k = 0; k < H; ++k) u[k] = B[r * H + k];
+    // with X[k + s] = conj Y[s - k] and w = exp(2 pi i / 2s),
+    // Z[k] = (Y[k] + X[k + s]) + i w^k (Y[k] - X[k + s]) has
+    // IDFT_s(Z)[n] = v[2n] + i v[2n + 1]; n < s / 2 are the target cells
+    float2 zz[S];
 #pragma unroll
-    for (int z = 0; z < S; ++z) {
-      const float a = u[0].x + ((z & 1) ? -u[S].x : u[S].x);
-      float b = 0.0f;
+    for (int k = 0; k < S; ++k) {
+      const float2 ys = make_float2(u[S - k].x, -u[S - k].y);
+      const float2 e = cadd(u[k], ys);
+      const float2 o = twiddle<M, true>(csub(u[k], ys), k);
+      zz[k] = make_float2(e.x - o.y, e.y + o.x);
+    }
+    dft<S, true>(zz);
 #pragma unroll
-      for (int k = 1; k < S; ++k) {
-        const float2 w = tw<M>(k * z);
-        b += u[k].x * w.x - u[k].y * w.y;
-      }
-      v[z] = a + 2.0f * b;
+    for (int n = 0; n < S / 2; ++n) {
+      v[2 * n] = zz[n].x;
+      v[2 * n + 1] = zz[n].y;
     }
   }
   if constexpr (P > 0) {
