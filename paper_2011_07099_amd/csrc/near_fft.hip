@@ -406,7 +406,9 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __r
 // (x, kz) column does that column's y pass; the first parity's result waits
 // in the thread's registers, and the second parity's sum is written back over
 // the column in place for the z pass.  Every pass has at most one task per
-// thread (leaf_threads >= s (s + 1)).
+// thread (leaf_threads >= s (s + 1)).  The second parity's spectra are
+// loaded as soon as the first parity's x pass has consumed its registers,
+// so they arrive while the first parity's y pass runs.
 //
 // With P > 0 the leaf's L2P is added before the write (the far field
 // sum_a A[ax][x] A[ay][y] A[az][z] P[a] of the leaf locals P, A as in the
@@ -432,20 +434,29 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
       if (r + j * NT < P3) loc[j] = tree.Pl[leaf * P3 + r + j * NT];
   }
   float2 acc[S];
+  float2 e[S], o[S];
+  if (r < S * H) {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      e[j] = yhat[chunk_addr((4 * j) * S * H + r, leaf, nleaf)];
+      o[j] = yhat[chunk_addr((4 * j + 2) * S * H + r, leaf, nleaf)];
+    }
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     if (r < S * H) {
       const int m = r / H, kz = r % H;
-      float2 e[S], o[S];
-#pragma unroll
-      for (int j = 0; j < S; ++j) {
-        e[j] = yhat[chunk_addr((4 * j + h) * S * H + r, leaf, nleaf)];
-        o[j] = yhat[chunk_addr((4 * j + 2 + h) * S * H + r, leaf, nleaf)];
-      }
       dft<S, true>(e);
       dft<S, true>(o);
 #pragma unroll
       for (int x = 0; x < S; ++x) B[(x * S + m) * H + kz] = cadd(e[x], twiddle<M, true>(o[x], x));
+      if (h == 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          e[j] = yhat[chunk_addr((4 * j + 1) * S * H + r, leaf, nleaf)];
+          o[j] = yhat[chunk_addr((4 * j + 3) * S * H + r, leaf, nleaf)];
+        }
+      }
     }
     __syncthreads();
     if (r < S * H) {

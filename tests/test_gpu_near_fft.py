@@ -64,6 +64,7 @@ def test_fft_near_zone_matches_reference_and_direct(N, L, p, green, prec, iso, f
     (64, 3, 8, "bf16x3", False, False),
     (64, 3, 8, "bf16x3", False, True),
     (32, 2, 6, "fp32", True, False),
+    (64, 3, 4, "fp32", True, False),   # isolated, 8^3 leaves
 ])
 def test_fft_near_zone_expansion_accel(N, L, p, prec, iso, fold):
     rho = f32(fields.lognormal(N, 1.5, 1.0, seed=181 + N + p))
