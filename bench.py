@@ -57,16 +57,16 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default at L = 4)
 # file and plan.hip); another route or a changed source reports null until the
 # counters are taken again.
 TRAFFIC = {
-    ("near leaf transforms", "33428628d11d"): 637957234,
-    ("near stencil", "33428628d11d"): 1247994755,
-    ("near inverse transforms", "33428628d11d"): 644026232,
-    ("p2m", "e6fe4316e767"): 75558533,
-    ("l2p", "e6fe4316e767"): 143439510,
-    ("m2l L4 node transforms", "c22bfefc6d9b"): 84127946,
-    ("m2l L4 stencil", "c22bfefc6d9b"): 163756201,
-    ("m2l L4 inverse transforms", "c22bfefc6d9b"): 92444834,
-    ("m2l L3 stencil", "c22bfefc6d9b"): 63193595,
-    ("m2l L2 stencil", "c22bfefc6d9b"): 9186977,
+    ("near leaf transforms", "8ce45f63a4b8"): 637867709,
+    ("near stencil", "8ce45f63a4b8"): 1246267414,
+    ("near inverse transforms", "8ce45f63a4b8"): 646180766,
+    ("p2m", "a91f476d7c39"): 75558221,
+    ("l2p", "a91f476d7c39"): 143454197,
+    ("m2l L4 node transforms", "b9145110233e"): 84124386,
+    ("m2l L4 stencil", "b9145110233e"): 163758063,
+    ("m2l L4 inverse transforms", "b9145110233e"): 92443675,
+    ("m2l L3 stencil", "b9145110233e"): 63203309,
+    ("m2l L2 stencil", "b9145110233e"): 9186945,
 }
 TRAFFIC_ROUTE = {"precision": "bf16x3", "near": "fft", "m2l": "spectral", "accel": "none",
                  "zones": "fp32", "N": 256, "L": 4, "p": 8}
