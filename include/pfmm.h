@@ -195,9 +195,9 @@ typedef enum {
    * density is read once and the potential written once, two launches fewer.
    * The tree then starts only after the forward transforms and the inverse
    * waits for the whole tree, so the near zone no longer runs beside the
-   * coarse levels' small kernels: at 256^3, L = 4, p = 8 a solve takes about
-   * 1.22 ms folded against 1.16 ms unfolded, and 1.19 ms folded with
-   * everything on one stream.  Default 0. */
+   * coarse levels' small kernels: at 256^3, L = 4, p = 8 (FP32 leaf-level
+   * zones) a solve takes about 1.09 ms folded against 1.00 ms unfolded.
+   * Default 0. */
   PFMM_OPT_FOLD = 13,
   /* value: int32 0 or 1.  1 sums the spectral interaction zones (PFMM_M2L_SPECTRAL,
    * Eq. 6 per frequency) of a 16^3 leaf level (L = 4) in FP32: the level's
