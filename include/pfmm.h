@@ -205,7 +205,7 @@ typedef enum {
    * target's 36 zone columns (six or three offsets along a line, both
    * parities) summed in FP32 and the column sums added in FP64.  Every
    * other level and tree keeps FP64 stencils.  At 256^3, p = 8 the level's
-   * transforms and stencil take 0.29 instead of 0.40 ms and the potential
+   * transforms and stencil take 0.25 instead of 0.37 ms and the potential
    * moves by up to 1.5e-5 of max|phi| (at leaf corners, where L2P
    * extrapolates), relative L2 against PM with the same G 1.3e-6 instead of
    * 1.0e-6.  Default 0. */
