@@ -190,6 +190,7 @@ __device__ __forceinline__ float2 tw(int j) {
 // the two-dword vector the 64-bit buffer builtins move.
 constexpr int kBufferDword3 = 0x00020000;
 typedef unsigned v2u32 __attribute__((ext_vector_type(2)));
+typedef unsigned v4u32 __attribute__((ext_vector_type(4)));
 
 // Address of frequency f of leaf `leaf` in the chunked spectrum layout:
 // [F / 64][leaves][64].
@@ -553,10 +554,17 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
 // that plane's registers with the plane two above (in flight while the other
 // two planes' terms are added), so three register sets rotate.  The
 // thread's kernel values sit in its own slots of LDS (no barrier: only the
-// writing thread reads them), which keeps the register count for three
-// waves per SIMD.  The pencil blocks of one frequency chunk go to one XCD
-// (blocks are dealt to the 8 XCDs round robin), so its L2 serves the column
-// re-reads between neighbouring blocks.
+// writing thread reads them).  The pencil blocks of one frequency chunk go
+// to one XCD (blocks are dealt to the 8 XCDs round robin), so its L2 serves
+// the column re-reads between neighbouring blocks.
+//
+// The stencil is bound by its vector memory instructions (the texture
+// units' address and data paths, not the bytes), so in the chunked layout
+// every load and store moves 16 bytes per lane: lane l takes frequency
+// 2 (l mod 32) + l / 32 of its chunk, a half-wave reads or writes one
+// leaf's 64 frequencies, and a swap of values between the half-waves
+// (v_permlane32_swap) gives each lane its frequency of two columns, or
+// gathers two targets' outputs, per instruction.
 //
 // SYM = +1 (-1): the kernel is even (odd) in the cell separation, so the
 // transform of neighbour -e is the conjugate (minus the conjugate) of that of
@@ -576,7 +584,11 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
   const int j = g >> 3;
   const int chunk = (j / np) * 8 + (g & 7);
   if (chunk >= nchunk) return;
-  const int64_t k = (int64_t)chunk * W + threadIdx.x;
+  // chunked: lane l takes frequency 2 (l mod 32) + l / 32 of the chunk (the
+  // even ones in the lower half-wave, the odd ones in the upper), which lets
+  // one 16-byte load per lane serve two columns (see load_plane)
+  const int phi = CHUNKED ? (int)(((threadIdx.x & 31) << 1) | (threadIdx.x >> 5)) : (int)threadIdx.x;
+  const int64_t k = (int64_t)chunk * W + phi;
   if (k >= F) return;
   // this frequency of leaf l is at base[l * stride + lane] (leaves per axis
   // are a power of two, so wrapping is a mask).  base and the leaf offset are
@@ -613,18 +625,44 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
     const int leaf = (((sx & msk) * nb + (sy & msk)) * nb) + (z & msk);
     if constexpr (CHUNKED) {
       return __builtin_bit_cast(
-          float2, __builtin_amdgcn_raw_buffer_load_b64(rin, lane * 8, leaf * 512, 0));
+          float2, __builtin_amdgcn_raw_buffer_load_b64(rin, phi * 8, leaf * 512, 0));
     } else {
       return base[(int64_t)leaf * stride + lane];
     }
   };
-  float2 r0[16], r1[16], r2[16];
+  // a z-plane of the 16 columns.  Chunked: the lower half-wave loads column
+  // c with 16 bytes per lane (frequencies 2j and 2j + 1 in lane j), the
+  // upper half column c + 1; swapping the lower half's odd values with the
+  // upper half's even ones leaves every lane its own frequency of both
+  // columns, with half the load instructions of one 8-byte load per column.
+  const unsigned hi = lane >> 5, lo16 = (lane & 31) * 16;
+  auto load_plane = [&](float2 (&dst)[16], int z) {
+    if constexpr (CHUNKED) {
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    r0[c] = load(c, -1);
-    r1[c] = load(c, 0);
-    r2[c] = load(c, 1);
-  }
+      for (int c = 0; c < 16; c += 2) {
+        const int sxa = bx0 - 1 + c / 4, sya = by0 - 1 + c % 4, syb = sya + 1;
+        const int la = (((sxa & msk) * nb + (sya & msk)) * nb) + (z & msk);
+        const int lb = (((sxa & msk) * nb + (syb & msk)) * nb) + (z & msk);
+        v4u32 q = __builtin_amdgcn_raw_buffer_load_b128(rin, (unsigned)((hi ? lb : la) * 512) + lo16, 0, 0);
+        if (isolated) {
+          const bool zin = z >= 0 && z < nb && sxa >= 0 && sxa < nb;
+          const bool ok = zin && (hi ? (syb >= 0 && syb < nb) : (sya >= 0 && sya < nb));
+          if (!ok) q = v4u32{0u, 0u, 0u, 0u};
+        }
+        const auto sre = __builtin_amdgcn_permlane32_swap(q[0], q[2], false, false);
+        const auto sim = __builtin_amdgcn_permlane32_swap(q[1], q[3], false, false);
+        dst[c] = make_float2(__uint_as_float(sre[0]), __uint_as_float(sim[0]));
+        dst[c + 1] = make_float2(__uint_as_float(sre[1]), __uint_as_float(sim[1]));
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) dst[c] = load(c, z);
+    }
+  };
+  float2 r0[16], r1[16], r2[16];
+  load_plane(r0, -1);
+  load_plane(r1, 0);
+  load_plane(r2, 1);
   // one complex multiply-add as four FMAs
   auto cmac = [](float& re, float& im, float2 kv, float2 sv) {
     re = fmaf(kv.x, sv.x, re);
@@ -658,24 +696,30 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
   auto step = [&](int bz, float2 (&zm)[16], float2 (&z0)[16], float2 (&zp)[16]) {
     float re[4] = {0.0f, 0.0f, 0.0f, 0.0f}, im[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     plane(re, im, zm, 0);
-    if (bz + 1 < nb) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) zm[c] = load(c, bz + 2);
-    }
+    if (bz + 1 < nb) load_plane(zm, bz + 2);
     plane(re, im, z0, 1);
     plane(re, im, zp, 2);
 #pragma unroll
-    for (int tx = 0; tx < 2; ++tx)
+    for (int tx = 0; tx < 2; ++tx) {
+      if constexpr (CHUNKED) {
+        // the two targets (tx, 0), (tx, 1) with one 16-byte store per lane:
+        // after the swap the lower half-wave holds frequencies 2j, 2j + 1 of
+        // the first, the upper half those of the second
+        const int l0 = ((bx0 + tx) * nb + by0) * nb + bz, l1 = l0 + nb;
+        const auto sre = __builtin_amdgcn_permlane32_swap(__float_as_uint(re[tx * 2]),
+                                                          __float_as_uint(re[tx * 2 + 1]), false, false);
+        const auto sim = __builtin_amdgcn_permlane32_swap(__float_as_uint(im[tx * 2]),
+                                                          __float_as_uint(im[tx * 2 + 1]), false, false);
+        const v4u32 q = {sre[0], sim[0], sre[1], sim[1]};
+        __builtin_amdgcn_raw_buffer_store_b128(q, rout, (unsigned)((hi ? l1 : l0) * 512) + lo16, 0, 0);
+      } else {
 #pragma unroll
-      for (int ty = 0; ty < 2; ++ty) {
-        const int leaf = ((bx0 + tx) * nb + by0 + ty) * nb + bz;
-        const float2 v = make_float2(re[tx * 2 + ty], im[tx * 2 + ty]);
-        if constexpr (CHUNKED)
-          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, v), rout, lane * 8,
-                                                leaf * 512, 0);
-        else
-          obase[(int64_t)leaf * stride + lane] = v;
+        for (int ty = 0; ty < 2; ++ty) {
+          const int leaf = ((bx0 + tx) * nb + by0 + ty) * nb + bz;
+          obase[(int64_t)leaf * stride + lane] = make_float2(re[tx * 2 + ty], im[tx * 2 + ty]);
+        }
       }
+    }
   };
   int bz = 0;
   for (; bz + 3 <= nb; bz += 3) {
