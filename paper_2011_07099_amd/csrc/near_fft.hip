@@ -118,8 +118,9 @@ __global__ void k_kdft_axis(const double2* __restrict__ in, int s, int axis, dou
 }
 
 // Scaled FP32 copy of a transformed kernel.  With `fused` the frequencies
-// go to the order of the fused transforms, ky split into parity and half:
-// (kx, ky, kz) -> ((kx * 2 + ky % 2) * s + ky / 2) * (s + 1) + kz.
+// go to the order of the fused transforms, ky split into parity and half
+// and the parity of kx innermost (kx = 2j and 2j + 1 side by side):
+// (kx, ky, kz) -> (((kx / 2 * 2 + ky % 2) * s + ky / 2) * (s + 1) + kz) * 2 + kx % 2.
 __global__ void k_kdft_store(const double2* __restrict__ in, int s, int fused, double scale,
                              float2* __restrict__ out) {
   const int M = 2 * s, H = s + 1;
@@ -129,7 +130,7 @@ __global__ void k_kdft_store(const double2* __restrict__ in, int s, int fused, d
   int64_t d = i;
   if (fused) {
     const int kz = (int)(i % H), ky = (int)((i / H) % M), kx = (int)(i / ((int64_t)H * M));
-    d = ((int64_t)(kx * 2 + (ky & 1)) * s + (ky >> 1)) * H + kz;
+    d = ((((int64_t)(kx >> 1) * 2 + (ky & 1)) * s + (ky >> 1)) * H + kz) * 2 + (kx & 1);
   }
   out[d] = make_float2((float)(in[i].x * scale), (float)(in[i].y * scale));
 }
@@ -383,13 +384,12 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_fwd(const float* __r
       }
       dft<S, false>(e);
       dft<S, false>(o);
-      // frequency order ((kx * 2 + parity) * s + m) * (s + 1) + kz, ky = 2m + parity:
-      // one parity's s (s + 1) frequencies of a kx plane are contiguous
+      // frequency order (((j * 2 + parity) * s + m) * (s + 1) + kz) * 2 + kx % 2
+      // (kx = 2j, 2j + 1; ky = 2m + parity): one 16-byte store writes both kx
 #pragma unroll
-      for (int j = 0; j < S; ++j) {
-        rhat[chunk_addr((4 * j + h) * S * H + r, leaf, nleaf)] = e[j];
-        rhat[chunk_addr((4 * j + 2 + h) * S * H + r, leaf, nleaf)] = o[j];
-      }
+      for (int j = 0; j < S; ++j)
+        *reinterpret_cast<float4*>(rhat + chunk_addr(((2 * j + h) * S * H + r) * 2, leaf, nleaf)) =
+            make_float4(e[j].x, e[j].y, o[j].x, o[j].y);
     }
     __syncthreads();
   }
@@ -438,9 +438,10 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
   float2 e[S], o[S];
   if (r < S * H) {
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-      e[j] = yhat[chunk_addr((4 * j) * S * H + r, leaf, nleaf)];
-      o[j] = yhat[chunk_addr((4 * j + 2) * S * H + r, leaf, nleaf)];
+    for (int j = 0; j < S; ++j) {  // kx = 2j and 2j + 1 side by side: one 16-byte load
+      const float4 q = *reinterpret_cast<const float4*>(yhat + chunk_addr((2 * j * S * H + r) * 2, leaf, nleaf));
+      e[j] = make_float2(q.x, q.y);
+      o[j] = make_float2(q.z, q.w);
     }
   }
 #pragma unroll
@@ -454,8 +455,10 @@ __global__ void __launch_bounds__(leaf_threads<S>()) k_leaf_inv(const float2* __
       if (h == 0) {
 #pragma unroll
         for (int j = 0; j < S; ++j) {
-          e[j] = yhat[chunk_addr((4 * j + 1) * S * H + r, leaf, nleaf)];
-          o[j] = yhat[chunk_addr((4 * j + 3) * S * H + r, leaf, nleaf)];
+          const float4 q =
+              *reinterpret_cast<const float4*>(yhat + chunk_addr(((2 * j + 1) * S * H + r) * 2, leaf, nleaf));
+          e[j] = make_float2(q.x, q.y);
+          o[j] = make_float2(q.z, q.w);
         }
       }
     }
