@@ -57,16 +57,16 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default at L = 4)
 # file and plan.hip); another route or a changed source reports null until the
 # counters are taken again.
 TRAFFIC = {
-    ("near leaf transforms", "e050cc19e7fe"): 637929171,
-    ("near stencil", "e050cc19e7fe"): 1215456393,
-    ("near inverse transforms", "e050cc19e7fe"): 646928778,
-    ("p2m", "a91f476d7c39"): 75558373,
-    ("l2p", "a91f476d7c39"): 143570337,
-    ("m2l L4 node transforms", "b9145110233e"): 84144694,
-    ("m2l L4 stencil", "b9145110233e"): 163755703,
-    ("m2l L4 inverse transforms", "b9145110233e"): 92440154,
-    ("m2l L3 stencil", "b9145110233e"): 63192914,
-    ("m2l L2 stencil", "b9145110233e"): 9186961,
+    ("near leaf transforms", "8ad8cbf45848"): 637840080,
+    ("near stencil", "8ad8cbf45848"): 1215762554,
+    ("near inverse transforms", "8ad8cbf45848"): 655559559,
+    ("p2m", "a91f476d7c39"): 75561437,
+    ("l2p", "a91f476d7c39"): 143449256,
+    ("m2l L4 node transforms", "b9145110233e"): 84136325,
+    ("m2l L4 stencil", "b9145110233e"): 163756213,
+    ("m2l L4 inverse transforms", "b9145110233e"): 92446448,
+    ("m2l L3 stencil", "b9145110233e"): 63194849,
+    ("m2l L2 stencil", "b9145110233e"): 9186973,
 }
 TRAFFIC_ROUTE = {"precision": "bf16x3", "near": "fft", "m2l": "spectral", "accel": "none",
                  "zones": "fp32", "N": 256, "L": 4, "p": 8}
