@@ -196,7 +196,7 @@ typedef enum {
    * The tree then starts only after the forward transforms and the inverse
    * waits for the whole tree, so the near zone no longer runs beside the
    * coarse levels' small kernels: at 256^3, L = 4, p = 8 (FP32 leaf-level
-   * zones) a solve takes about 1.09 ms folded against 1.00 ms unfolded.
+   * zones) a solve takes about 1.00 ms folded against 0.96 ms unfolded.
    * Default 0. */
   PFMM_OPT_FOLD = 13,
   /* value: int32 0 or 1.  1 sums the spectral interaction zones (PFMM_M2L_SPECTRAL,
