@@ -57,9 +57,9 @@ FP64_LEVELS = (2, 3)  # coarse levels kept in FP64 (the plan's default at L = 4)
 # file and plan.hip); another route or a changed source reports null until the
 # counters are taken again.
 TRAFFIC = {
-    ("near leaf transforms", "8ad8cbf45848"): 637840080,
-    ("near stencil", "8ad8cbf45848"): 1215762554,
-    ("near inverse transforms", "8ad8cbf45848"): 655559559,
+    ("near leaf transforms", "82ec6b7cc7ad"): 637840080,
+    ("near stencil", "82ec6b7cc7ad"): 1215762554,
+    ("near inverse transforms", "82ec6b7cc7ad"): 655559559,
     ("p2m", "a91f476d7c39"): 75561437,
     ("l2p", "a91f476d7c39"): 143449256,
     ("m2l L4 node transforms", "b9145110233e"): 84136325,

@@ -594,12 +594,11 @@ __global__ void __launch_bounds__(CHUNKED ? 64 : kThreads) k_near_mac(
   const int64_t k = (int64_t)chunk * W + phi;
   if (k >= F) return;
   // this frequency of leaf l is at base[l * stride + lane] (leaves per axis
-  // are a power of two, so wrapping is a mask).  base and the leaf offset are
-  // the same for the whole wave.  In the chunked layout a chunk's spectra of
-  // all leaves span nleaf * 512 bytes, so every access goes through a buffer
-  // resource on the chunk: the leaf's byte offset in a scalar register, the
-  // lane's in one vector register shared by all loads, and no per-lane 64-bit
-  // address arithmetic or registers holding the 16 columns' addresses.
+  // are a power of two, so wrapping is a mask).  In the chunked layout a
+  // chunk's spectra of all leaves span nleaf * 512 bytes, so every access
+  // goes through a buffer resource on the chunk with 32-bit offsets: no
+  // per-lane 64-bit address arithmetic or registers holding the columns'
+  // addresses.
   const int64_t nleaf = (int64_t)nb * nb * nb;
   const int64_t off = CHUNKED ? (int64_t)chunk * nleaf * 64 : (int64_t)chunk * W;
   const float2* __restrict__ base = rhat + off;
